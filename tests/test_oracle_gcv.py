@@ -1,0 +1,135 @@
+"""Pins for GCV (Sec. 3, eqs. (xgamma), (GCV)) and its minimiser."""
+import math
+
+import numpy as np
+import pytest
+from scipy.fft import dctn
+from scipy.optimize import minimize_scalar
+
+from oracle import operators as ops
+from oracle import gcv
+from oracle.hierarchy import Hierarchy
+import synth
+
+
+def brute_terms(A, D, b, c, gamma):
+    """Dense route: solve the normal equations and form A A_gamma^# explicitly."""
+    Ag = A.T @ A + gamma * D.T @ D
+    x = np.linalg.solve(Ag, A.T @ b + gamma * D.T @ c)
+    H = A @ np.linalg.solve(Ag, A.T)
+    return float(np.sum((A @ x - b) ** 2)), float(np.trace(H)), x
+
+
+def reflexive_blur(X, P):
+    r0, r1 = P.shape[0] // 2, P.shape[1] // 2
+    m0, m1 = X.shape
+    Xp = np.pad(X, ((r0, r0), (r1, r1)), mode="symmetric")
+    Y = np.zeros_like(X)
+    for a in range(-r0, r0 + 1):
+        for b in range(-r1, r1 + 1):
+            Y += P[a + r0, b + r1] * Xp[r0 - a:r0 - a + m0, r1 - b:r1 - b + m1]
+    return Y
+
+
+def dense_of(fn, m):
+    n = m * m
+    return np.stack([ops.vec(fn(ops.unvec(np.eye(n)[:, k], m))) for k in range(n)], axis=1)
+
+
+@pytest.mark.parametrize("kind", ["irls", "shift"])
+def test_exact_tier_matches_brute_force(kind):
+    rng = np.random.default_rng(1)
+    m = 6
+    H = Hierarchy(synth.gaussian_psf(1.3, 2), m, 1, "haar")
+    A = H.dense(0)
+    L = ops.grad_dense(m)
+    b = rng.standard_normal(m * m)
+    if kind == "irls":
+        D, c = rng.uniform(0.3, 3.0, L.shape[0])[:, None] * L, np.zeros(L.shape[0])
+    else:
+        D, c = L, rng.standard_normal(L.shape[0])
+    data = gcv.exact_data(A, D, b, c)
+    for gamma in (1e-4, 1e-2, 0.5, 20.0):
+        r_b, t_b, x = brute_terms(A, D, b, c, gamma)
+        r_e, t_e = gcv.exact_terms(gamma, data)
+        assert abs(r_e - r_b) < 1e-10 * max(r_b, 1e-3)
+        assert abs(t_e - t_b) < 1e-10 * m * m
+        # n - tr(A A#) = gamma tr(A_gamma^{-1} D^T D)
+        alt = gamma * np.trace(np.linalg.solve(A.T @ A + gamma * D.T @ D, D.T @ D))
+        assert abs((m * m - t_b) - alt) < 1e-9 * m * m
+
+
+def test_dct_helpers_match_scipy():
+    rng = np.random.default_rng(2)
+    X = rng.standard_normal((12, 12))
+    assert np.max(np.abs(gcv.dct2(X) - dctn(X, type=2, norm="ortho"))) < 1e-13
+    K = synth.gaussian_psf(1.7, 4)
+    m = 16
+    E = np.zeros((m, m))
+    E[0, 0] = 1.0
+    sym = dctn(reflexive_blur(E, K), norm="ortho") / dctn(E, norm="ortho")
+    assert np.max(np.abs(gcv.cosine_symbol(K, m) - sym)) < 1e-13
+    L = ops.grad_dense(m)
+    C = np.kron(gcv.dct_matrix(m), gcv.dct_matrix(m))
+    lam = np.diag(C @ (L.T @ L) @ C.T)
+    assert np.max(np.abs(lam - ops.vec(gcv.neumann_symbol(m)))) < 1e-12
+
+
+@pytest.mark.parametrize("mode", ["mm", "irls_const"])
+def test_spectral_tier_exact_for_reflexive_blur(mode):
+    """The surrogate is exact when A is the reflexive-boundary blur of an
+    axis-symmetric kernel and D = L (or w L with constant w)."""
+    rng = np.random.default_rng(3)
+    m = 8
+    K = synth.gaussian_psf(1.1, 3)
+    A = dense_of(lambda X: reflexive_blur(X, K), m)
+    L = ops.grad_dense(m)
+    B = rng.standard_normal((m, m))
+    if mode == "mm":
+        wbar, D, c = 1.0, L, rng.standard_normal(L.shape[0])
+        dtc = ops.grad_adjoint(c, m)
+    else:
+        wbar, D, c, dtc = 1.7, 1.7 * L, np.zeros(L.shape[0]), None
+    de = gcv.exact_data(A, D, ops.vec(B), c)
+    ds = gcv.spectral_data(K, B, wbar, dtc)
+    for gamma in (1e-3, 0.1, 3.0):
+        r1, t1 = gcv.exact_terms(gamma, de)
+        r2, t2 = gcv.spectral_terms(gamma, ds)
+        assert abs(r1 - r2) < 1e-9 * r1 and abs(t1 - t2) < 1e-9 * m * m
+
+
+@pytest.mark.parametrize("fn,a,b", [
+    (lambda t: (t - 0.3) ** 2 + 1.0, -2.0, 3.0),
+    (lambda t: math.cosh(t - 1.234567), 0.0, 2.0),
+    (lambda t: abs(t + 0.5) + 0.1 * t * t, -3.0, 1.0),
+    (lambda t: t * t * t * t - 2 * t, -1.0, 2.0),
+])
+def test_brent_matches_scipy_bounded(fn, a, b):
+    x, fx, nev = gcv.brent_minimize(fn, a, b, xtol=1e-8)
+    res = minimize_scalar(fn, bounds=(a, b), method="bounded", options={"xatol": 1e-8})
+    assert abs(x - res.x) < 1e-6
+    assert fx <= res.fun + 1e-12
+    assert nev <= 101
+
+
+def test_grid_tie_rule_and_bracket():
+    # A data set whose GCV is constant in gamma: zero residual, zero trace.
+    data = {"kind": "spectral", "s": np.zeros(4), "lp": np.ones(4), "e": np.zeros(4), "n": 4}
+    data["s"][0] = 1e-3
+    g, f, info = gcv.choose_gamma(data)
+    assert info["j"] == 0
+    assert info["bracket"][0] == info["t_lo"]
+
+
+def test_choose_gamma_matches_exhaustive_search():
+    rng = np.random.default_rng(4)
+    m = 16
+    H = Hierarchy(synth.gaussian_psf(1.5, 4), m, 1, "haar")
+    X = synth.piecewise_constant_image(m, 6, rng)
+    B = ops.blur(X, H.P) + 0.01 * rng.standard_normal((m, m))
+    data = gcv.spectral_data(H.interior_stencil(0), B)
+    g, f, info = gcv.choose_gamma(data)
+    ts = np.linspace(info["bracket"][0], info["bracket"][1], 20001)
+    vals = [gcv.gcv_value(10 ** t, data) for t in ts]
+    assert f <= min(vals) * (1 + 1e-9)
+    assert abs(math.log10(g) - ts[int(np.argmin(vals))]) < 1e-3
