@@ -1,0 +1,239 @@
+/*
+ * deblur.h -- C ABI of the MI355X (gfx950) wavelet multilevel l1 deblurring
+ * library.
+ *
+ * The library solves, for an m x m image (m a power of two),
+ *
+ *     min_x ||A x - b||_2^2 + mu ||L x||_1                  (paper eq. (l1b))
+ *
+ * with A a zero-boundary blur and L the discrete gradient, by a wavelet
+ * V-cycle (Alg. 4) whose levels run IRLS (Alg. 1), MM (Alg. 2) or Split
+ * Bregman (Alg. 3).  Each outer iteration solves the l2 subproblem of eq.
+ * (generic_sub) by CGLS on the augmented system of eq. (augmented), with the
+ * parameter chosen by GCV (eqs. (xgamma), (GCV)).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Images: device pointers to m x m arrays stored column-major (x = vec(X),
+ *   Sec. 4.1 and Sec. 5), contiguous, element type given by the precision
+ *   (DBL_F32: float, DBL_F64: double).
+ * Gradient-space vectors (length n_L = 2 m (m-1)): [vec(D X); vec(X D^T)],
+ *   i.e. the (m-1) x m block of row differences followed by the m x (m-1)
+ *   block of column differences, both column-major (Sec. 4.2).
+ * Kernels (PSFs): host float64 arrays of odd shape ph x pw, column-major,
+ *   centred: entry (a + ph/2) + (b + pw/2) * ph weighs offset (a, b), a along
+ *   the row index.  (A X)[i,j] = sum_{a,b} P[a,b] X[i-a, j-b], X = 0 outside.
+ * Ownership: the caller owns every buffer it passes; the library keeps no
+ *   pointer to them after a call returns.  The library owns dbl_ctx, dbl_op
+ *   and dbl_server objects and their device workspaces.
+ * Streams: all device work of a context is issued on the stream given to
+ *   dbl_create (NULL = the null stream).  Entry points that return results
+ *   to host memory (reports, gamma) synchronise that stream; the others are
+ *   asynchronous with respect to the host -- call dbl_sync before reading.
+ * Errors: every function returns 0 (DBL_OK) or a negative dbl_status.
+ *   Argument validation happens before any device work is issued, so a
+ *   rejected call has no side effects.  dbl_last_error(ctx) describes the
+ *   last failure on that context.
+ * Threads: a context must not be used by two host threads at once.
+ */
+#ifndef DEBLUR_H
+#define DEBLUR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DBL_MAX_LEVELS 8
+#define DBL_MAX_KOUT 64
+#define DBL_MAX_PSF_RADIUS 16   /* largest supported kernel half-width   */
+#define DBL_GCV_GRID_MAX 64
+
+typedef enum {
+  DBL_OK = 0,
+  DBL_EINVAL = -1,    /* bad argument (null pointer, size, enum, range)     */
+  DBL_ENOMEM = -2,    /* workspace budget or device allocation exhausted    */
+  DBL_EDEVICE = -3,   /* HIP runtime error                                  */
+  DBL_ENOTSUP = -4,   /* valid request this build does not support          */
+  DBL_ENUMERIC = -5,  /* NaN or Inf detected in a result                    */
+  DBL_ENOTFOUND = -6  /* unknown server ticket                              */
+} dbl_status;
+
+typedef enum { DBL_IRLS = 0, DBL_MM = 1, DBL_SB = 2 } dbl_solver;
+/* Low-pass filters of Sec. 4: the two-tap Haar filter and the four-tap
+ * Daubechies filter (1+sqrt3, 3+sqrt3, 3-sqrt3, 1-sqrt3) / (4 sqrt2). */
+typedef enum { DBL_HAAR = 0, DBL_DB4 = 1 } dbl_wavelet;
+/* Information transfer of Sec. 4.1: X = coarse solution, D = auxiliaries.
+ * With levels == 1 the transfer is unused (Approach I). */
+typedef enum { DBL_XFER_X = 0, DBL_XFER_D = 1 } dbl_transfer;
+typedef enum { DBL_F32 = 0, DBL_F64 = 1 } dbl_precision;
+/* GCV tiers: SPECTRAL evaluates the GCV function of eq. (GCV) on the DCT
+ * surrogate (reflexive-boundary blur, exact Neumann gradient); EXACT uses the
+ * generalised eigendecomposition of the pair {A, D} (the paper's GSVD route,
+ * Sec. 3) and is limited to n <= 4096; AUTO picks EXACT when n <= 4096. */
+typedef enum { DBL_GCV_AUTO = 0, DBL_GCV_EXACT = 1, DBL_GCV_SPECTRAL = 2 } dbl_gcv_mode;
+
+typedef struct dbl_ctx dbl_ctx;
+typedef struct dbl_op dbl_op;
+typedef struct dbl_server dbl_server;
+
+/* Solver options.  dbl_opts_default() fills the paper's values: eps = 0.03,
+ * tau = 0.005 (Sec. 5), 50 GCV grid points (Sec. 3), 10 outer x 30 CGLS
+ * iterations, GCV on, AUTO tier, FP32. */
+typedef struct dbl_opts {
+  double eps;            /* IRLS / MM stabilisation (Algs. 1, 2)              */
+  double tau;            /* SB shrink threshold (Alg. 3)                      */
+  int k_out;             /* outer iterations per level, 1..DBL_MAX_KOUT      */
+  int k_in;              /* CGLS iterations per subproblem, >= 1              */
+  double mu_fixed;       /* > 0: use this parameter everywhere (no GCV)       */
+  const double* mu_schedule; /* optional host array levels*k_out, finest level
+                                first; overrides mu_fixed and GCV             */
+  int gcv_mode;          /* dbl_gcv_mode                                      */
+  int gcv_grid;          /* grid points, 3..DBL_GCV_GRID_MAX                  */
+  int precision;         /* dbl_precision for vectors on the device           */
+} dbl_opts;
+
+/* Per-solve report.  Level 0 is the finest grid.  Arrays are filled for
+ * levels < levels and k < k_out.  rc[l][0] is NaN when the level starts
+ * from x = 0 (Approaches I and D). */
+typedef struct dbl_report {
+  int levels;
+  int k_out;
+  int sizes[DBL_MAX_LEVELS];
+  double gamma[DBL_MAX_LEVELS][DBL_MAX_KOUT];     /* mu (IRLS, MM) or lambda (SB) */
+  double rc[DBL_MAX_LEVELS][DBL_MAX_KOUT];        /* eq. (stop)                    */
+  double objective[DBL_MAX_LEVELS][DBL_MAX_KOUT]; /* solver objective, FP64        */
+  double seconds;        /* device time of the solve (plain path), or latency */
+  int status;            /* dbl_status of this solve                          */
+} dbl_report;
+
+/* A deblurring request for the batched and serving entry points.  b and x
+ * are device pointers (m x m, element type per opts->precision); psf is a
+ * host array that is copied during the call that takes the request. */
+typedef struct dbl_request {
+  const void* b;
+  void* x;
+  const double* psf;
+  int ph, pw;
+  int m;
+  int solver, wavelet, levels, transfer;
+  dbl_opts opts;
+} dbl_request;
+
+/* CGLS subproblem description (eq. (generic_sub)).  d_kind 0: D = L;
+ * 1: D = diag(w) L.  w (n_L, device, same element type) is required for
+ * d_kind 1; c (n_L, device) may be NULL for c = 0. */
+typedef struct dbl_sub {
+  int d_kind;
+  const void* w;
+  double gamma;
+  const void* c;
+} dbl_sub;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on HIP device `device`, issuing work on `hip_stream`
+ * (a hipStream_t, or NULL for the null stream).  hbm_budget_bytes caps the
+ * device workspace the context may allocate (0 = no cap).  device = -1
+ * creates an argument-checking context with no device: every entry point
+ * validates its arguments as usual and then returns DBL_EDEVICE. */
+int dbl_create(dbl_ctx** out, int device, void* hip_stream, size_t hbm_budget_bytes);
+int dbl_destroy(dbl_ctx* ctx);
+/* Message describing the last error on ctx (never NULL). */
+const char* dbl_last_error(const dbl_ctx* ctx);
+/* Wait for all work issued by ctx. */
+int dbl_sync(dbl_ctx* ctx);
+/* Bytes of device workspace currently held by ctx. */
+size_t dbl_workspace_bytes(const dbl_ctx* ctx);
+void dbl_opts_default(dbl_opts* opts);
+
+/* -------------------------------------------------------------- operators */
+
+/* Build the level hierarchy A^(i+1) = W^T A^(i) W, b^(i+1) = W^T b^(i)
+ * (Sec. 4, Alg. 4) for kernel psf on an m x m grid with `levels` grids.
+ * The coarse operators are exact (Galerkin, periodic wavelet seam included)
+ * and are stored as small per-level stencil tables.  Requires m a power of
+ * two, odd ph, pw with half-widths <= DBL_MAX_PSF_RADIUS, and a coarsest
+ * grid of at least 8 pixels per side. */
+int dbl_op_create(dbl_ctx* ctx, const double* psf, int ph, int pw, int m, int levels,
+                  int wavelet, int precision, dbl_op** out);
+int dbl_op_destroy(dbl_op* op);
+
+/* out = A^(level) in (transpose = 0) or A^(level)^T in (transpose = 1).
+ * in and out are (m/2^level)^2 device arrays of the op's precision. */
+int dbl_apply_A(dbl_ctx* ctx, const dbl_op* op, int level, int transpose,
+                const void* in, void* out);
+
+/* Gradient L of Sec. 4.2 on an m x m grid: transpose = 0 maps n -> n_L,
+ * transpose = 1 maps n_L -> n (the negative divergence). */
+int dbl_apply_L(dbl_ctx* ctx, int m, int precision, int transpose, const void* in, void* out);
+
+/* One level of the periodic DWT with the filters of Sec. 4.
+ * inverse = 0: in m x m -> out; lowpass_only = 1 writes only the (m/2)^2
+ * low-pass band (restriction W^T), else the four bands [LL, LH, HL, HH]
+ * (first letter: filter along rows) as 4 consecutive (m/2)^2 blocks; the
+ * high-pass filter is g_k = (-1)^k h_{kappa-1-k}.
+ * inverse = 1: lowpass_only = 1 maps (m/2)^2 -> m x m by the adjoint of the
+ * restriction (prolongation W, Approach X); else the four bands back to the
+ * image (perfect reconstruction).  m is the fine size. */
+int dbl_dwt(dbl_ctx* ctx, int wavelet, int m, int precision, int inverse, int lowpass_only,
+            const void* in, void* out);
+
+/* Approach D block transfer (Sec. 4.2): a coarse gradient-space vector
+ * (m_coarse) -> the fine one (2 m_coarse):  Q_x <- W~1 Q_x W1^T,
+ * Q_y <- W1 Q_y W~1^T, W~1 = first m_f - 1 rows and m_c - 1 columns of W1. */
+int dbl_dtransfer(dbl_ctx* ctx, int wavelet, int m_coarse, int precision,
+                  const void* in, void* out);
+
+/* Run exactly `iters` CGLS iterations on min ||A^ x - b^|| with
+ * A^ = [A^(level); sqrt(gamma) D] and b^ = [b; sqrt(gamma) c] (eq.
+ * (augmented)), from x0 (NULL = 0).  resid_hist (host, may be NULL) receives
+ * ||b^ - A^ x_k||^2 after each iteration, in FP64.  CGLS replaces the
+ * paper's LSQR: both produce the same iterates in exact arithmetic. */
+int dbl_cgls(dbl_ctx* ctx, const dbl_op* op, int level, const dbl_sub* sub, const void* b,
+             const void* x0, int iters, void* x, double* resid_hist);
+
+/* GCV choice of gamma for the subproblem {A^(level), D, c} and data b
+ * (Sec. 3): a grid of opts.gcv_grid log-spaced values followed by Brent's
+ * minimisation on the neighbouring interval.  Writes gamma and GCV(gamma)
+ * to host doubles.  sub->gamma is ignored.  mode: dbl_gcv_mode. */
+int dbl_gcv(dbl_ctx* ctx, const dbl_op* op, int level, const dbl_sub* sub, const void* b,
+            int mode, int grid, double* gamma_out, double* gcv_out);
+
+/* ------------------------------------------------------------------ solve */
+
+/* Full V-cycle solve (Alg. 4).  b, x: device m x m arrays of
+ * opts->precision.  levels = 1 runs Approach I.  rep may be NULL. */
+int dbl_deblur(dbl_ctx* ctx, const void* b, const double* psf, int ph, int pw, int m,
+               int solver, int wavelet, int levels, int transfer, const dbl_opts* opts,
+               void* x, dbl_report* rep);
+
+/* Solve `count` independent requests together: their V-cycles advance in
+ * lock step, one fused launch per CGLS phase covering every image.  Each
+ * result equals the plain dbl_deblur result of the same request.  reps may
+ * be NULL, else `count` reports. */
+int dbl_deblur_batch(dbl_ctx* ctx, int count, const dbl_request* reqs, dbl_report* reps);
+
+/* ---------------------------------------------------------------- serving */
+
+/* Continuous-batching server on ctx: up to max_slots solves are resident at
+ * once and share every launch; new requests are admitted at outer-iteration
+ * boundaries while slots and the HBM budget allow. */
+int dbl_server_create(dbl_ctx* ctx, int max_slots, size_t hbm_budget_bytes, dbl_server** out);
+int dbl_server_destroy(dbl_server* srv);
+/* Queue a request; returns a ticket.  The psf is copied; b and x must stay
+ * valid until the ticket completes. */
+int dbl_server_submit(dbl_server* srv, const dbl_request* req, int64_t* ticket);
+/* Advance the server by one outer-iteration step (admits, computes,
+ * retires).  *active receives the number of resident solves afterwards. */
+int dbl_server_step(dbl_server* srv, int* active);
+/* *done = 1 when the ticket has completed; then rep (may be NULL) receives
+ * its report and the ticket is released. */
+int dbl_server_poll(dbl_server* srv, int64_t ticket, int* done, dbl_report* rep);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DEBLUR_H */

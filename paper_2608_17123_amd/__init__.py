@@ -1,0 +1,376 @@
+"""Python binding of libdeblur (include/deblur.h) -- argument marshalling only.
+
+Every function here has the name of the C entry point it calls and does no
+arithmetic of its own: device buffers are torch tensors (for memory and
+streams only) whose data pointers are handed to the library, host arrays are
+numpy float64 arrays.  Images are vectors of length m*m in column-major order
+(x = vec(X)); gradient-space vectors have length 2 m (m - 1).
+
+The library is built in-tree by ``python -m paper_2608_17123_amd.build``.
+Importing this package does not load it; the first call does, and raises
+``RuntimeError`` when the library is missing -- there is no fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdeblur.so")
+
+DBL_OK, DBL_EINVAL, DBL_ENOMEM, DBL_EDEVICE, DBL_ENOTSUP, DBL_ENUMERIC, DBL_ENOTFOUND = (
+    0, -1, -2, -3, -4, -5, -6)
+DBL_IRLS, DBL_MM, DBL_SB = 0, 1, 2
+DBL_HAAR, DBL_DB4 = 0, 1
+DBL_XFER_X, DBL_XFER_D = 0, 1
+DBL_F32, DBL_F64 = 0, 1
+DBL_GCV_AUTO, DBL_GCV_EXACT, DBL_GCV_SPECTRAL = 0, 1, 2
+DBL_MAX_LEVELS, DBL_MAX_KOUT, DBL_GCV_GRID_MAX = 8, 64, 64
+
+SOLVERS = {"irls": DBL_IRLS, "mm": DBL_MM, "sb": DBL_SB}
+WAVELETS = {"haar": DBL_HAAR, "db4": DBL_DB4}
+TRANSFERS = {"X": DBL_XFER_X, "D": DBL_XFER_D, "I": DBL_XFER_X}
+GCV_MODES = {"auto": DBL_GCV_AUTO, "exact": DBL_GCV_EXACT, "spectral": DBL_GCV_SPECTRAL}
+
+EXPORTS = [
+    "dbl_create", "dbl_destroy", "dbl_last_error", "dbl_sync", "dbl_workspace_bytes",
+    "dbl_opts_default", "dbl_op_create", "dbl_op_destroy", "dbl_apply_A", "dbl_apply_L",
+    "dbl_dwt", "dbl_dtransfer", "dbl_cgls", "dbl_gcv", "dbl_deblur", "dbl_deblur_batch",
+    "dbl_server_create", "dbl_server_destroy", "dbl_server_submit", "dbl_server_step",
+    "dbl_server_poll",
+]
+
+
+class dbl_opts(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_double), ("tau", ctypes.c_double), ("k_out", ctypes.c_int),
+                ("k_in", ctypes.c_int), ("mu_fixed", ctypes.c_double),
+                ("mu_schedule", ctypes.POINTER(ctypes.c_double)), ("gcv_mode", ctypes.c_int),
+                ("gcv_grid", ctypes.c_int), ("precision", ctypes.c_int)]
+
+
+class dbl_report(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int), ("k_out", ctypes.c_int),
+                ("sizes", ctypes.c_int * DBL_MAX_LEVELS),
+                ("gamma", (ctypes.c_double * DBL_MAX_KOUT) * DBL_MAX_LEVELS),
+                ("rc", (ctypes.c_double * DBL_MAX_KOUT) * DBL_MAX_LEVELS),
+                ("objective", (ctypes.c_double * DBL_MAX_KOUT) * DBL_MAX_LEVELS),
+                ("seconds", ctypes.c_double), ("status", ctypes.c_int)]
+
+    def to_dict(self):
+        L, K = self.levels, self.k_out
+        return {
+            "sizes": [self.sizes[i] for i in range(L)],
+            "gamma": [[self.gamma[i][k] for k in range(K)] for i in range(L)],
+            "rc": [[self.rc[i][k] for k in range(K)] for i in range(L)],
+            "objective": [[self.objective[i][k] for k in range(K)] for i in range(L)],
+            "seconds": self.seconds, "status": self.status,
+        }
+
+
+class dbl_request(ctypes.Structure):
+    _fields_ = [("b", ctypes.c_void_p), ("x", ctypes.c_void_p),
+                ("psf", ctypes.POINTER(ctypes.c_double)), ("ph", ctypes.c_int),
+                ("pw", ctypes.c_int), ("m", ctypes.c_int), ("solver", ctypes.c_int),
+                ("wavelet", ctypes.c_int), ("levels", ctypes.c_int), ("transfer", ctypes.c_int),
+                ("opts", dbl_opts)]
+
+
+class dbl_sub(ctypes.Structure):
+    _fields_ = [("d_kind", ctypes.c_int), ("w", ctypes.c_void_p), ("gamma", ctypes.c_double),
+                ("c", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libdeblur.so (raises RuntimeError when it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_2608_17123_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i, d, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+    dp = ctypes.POINTER(ctypes.c_double)
+    sig = {
+        "dbl_create": (i, [ctypes.POINTER(vp), i, vp, sz]),
+        "dbl_destroy": (i, [vp]),
+        "dbl_last_error": (ctypes.c_char_p, [vp]),
+        "dbl_sync": (i, [vp]),
+        "dbl_workspace_bytes": (sz, [vp]),
+        "dbl_opts_default": (None, [ctypes.POINTER(dbl_opts)]),
+        "dbl_op_create": (i, [vp, dp, i, i, i, i, i, i, ctypes.POINTER(vp)]),
+        "dbl_op_destroy": (i, [vp]),
+        "dbl_apply_A": (i, [vp, vp, i, i, vp, vp]),
+        "dbl_apply_L": (i, [vp, i, i, i, vp, vp]),
+        "dbl_dwt": (i, [vp, i, i, i, i, i, vp, vp]),
+        "dbl_dtransfer": (i, [vp, i, i, i, vp, vp]),
+        "dbl_cgls": (i, [vp, vp, i, ctypes.POINTER(dbl_sub), vp, vp, i, vp, dp]),
+        "dbl_gcv": (i, [vp, vp, i, ctypes.POINTER(dbl_sub), vp, i, i, dp, dp]),
+        "dbl_deblur": (i, [vp, vp, dp, i, i, i, i, i, i, i, ctypes.POINTER(dbl_opts), vp,
+                           ctypes.POINTER(dbl_report)]),
+        "dbl_deblur_batch": (i, [vp, i, ctypes.POINTER(dbl_request), ctypes.POINTER(dbl_report)]),
+        "dbl_server_create": (i, [vp, i, sz, ctypes.POINTER(vp)]),
+        "dbl_server_destroy": (i, [vp]),
+        "dbl_server_submit": (i, [vp, ctypes.POINTER(dbl_request), ctypes.POINTER(ctypes.c_int64)]),
+        "dbl_server_step": (i, [vp, ctypes.POINTER(i)]),
+        "dbl_server_poll": (i, [vp, ctypes.c_int64, ctypes.POINTER(i), ctypes.POINTER(dbl_report)]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+class DeblurError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (status {code})")
+        self.code = code
+
+
+def _check(ctx, code):
+    if code != DBL_OK:
+        msg = lib().dbl_last_error(ctx.handle if ctx is not None else None)
+        raise DeblurError(code, msg.decode() if msg else "error")
+    return code
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("device tensors must be contiguous cuda tensors")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _psf_arg(psf):
+    """Host kernel as a column-major float64 array (PSF[a, b] -> a + b*ph)."""
+    P = np.asfortranarray(np.asarray(psf, dtype=np.float64))
+    flat = np.ascontiguousarray(P.ravel(order="F"))
+    return flat, flat.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), P.shape[0], P.shape[1]
+
+
+class Context:
+    """Owns a dbl_ctx bound to a torch stream on one device."""
+
+    def __init__(self, device=0, stream=None, budget=0):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        self.device = device
+        h = ctypes.c_void_p()
+        code = lib().dbl_create(ctypes.byref(h), device, ctypes.c_void_p(stream.cuda_stream),
+                                budget)
+        if code != DBL_OK:
+            raise DeblurError(code, "dbl_create failed")
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            lib().dbl_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def dbl_create(device=0, stream=None, budget=0):
+    return Context(device, stream, budget)
+
+
+def dbl_destroy(ctx):
+    ctx.close()
+
+
+def dbl_sync(ctx):
+    _check(ctx, lib().dbl_sync(ctx.handle))
+
+
+def dbl_workspace_bytes(ctx):
+    return int(lib().dbl_workspace_bytes(ctx.handle))
+
+
+def dbl_opts_default(**kw):
+    o = dbl_opts()
+    lib().dbl_opts_default(ctypes.byref(o))
+    sched = kw.pop("mu_schedule", None)
+    for k, v in kw.items():
+        if k == "gcv_mode" and isinstance(v, str):
+            v = GCV_MODES[v]
+        setattr(o, k, v)
+    if sched is not None:
+        arr = np.ascontiguousarray(np.asarray(sched, dtype=np.float64).ravel())
+        o._sched = arr  # keep alive
+        o.mu_schedule = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    return o
+
+
+class Op:
+    def __init__(self, ctx, handle, m, levels, precision):
+        self.ctx, self.handle, self.m, self.levels, self.precision = ctx, handle, m, levels, precision
+
+    def close(self):
+        if self.handle:
+            lib().dbl_op_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def dbl_op_create(ctx, psf, m, levels, wavelet, precision=DBL_F32):
+    keep, p, ph, pw = _psf_arg(psf)
+    h = ctypes.c_void_p()
+    wavelet = WAVELETS.get(wavelet, wavelet)
+    _check(ctx, lib().dbl_op_create(ctx.handle, p, ph, pw, m, levels, wavelet, precision,
+                                    ctypes.byref(h)))
+    return Op(ctx, h, m, levels, precision)
+
+
+def dbl_op_destroy(op):
+    op.close()
+
+
+def dbl_apply_A(ctx, op, level, transpose, x_in, x_out):
+    _check(ctx, lib().dbl_apply_A(ctx.handle, op.handle, level, int(transpose), _ptr(x_in),
+                                  _ptr(x_out)))
+
+
+def dbl_apply_L(ctx, m, precision, transpose, x_in, x_out):
+    _check(ctx, lib().dbl_apply_L(ctx.handle, m, precision, int(transpose), _ptr(x_in),
+                                  _ptr(x_out)))
+
+
+def dbl_dwt(ctx, wavelet, m, precision, inverse, lowpass_only, x_in, x_out):
+    wavelet = WAVELETS.get(wavelet, wavelet)
+    _check(ctx, lib().dbl_dwt(ctx.handle, wavelet, m, precision, int(inverse),
+                              int(lowpass_only), _ptr(x_in), _ptr(x_out)))
+
+
+def dbl_dtransfer(ctx, wavelet, m_coarse, precision, q_in, q_out):
+    wavelet = WAVELETS.get(wavelet, wavelet)
+    _check(ctx, lib().dbl_dtransfer(ctx.handle, wavelet, m_coarse, precision, _ptr(q_in),
+                                    _ptr(q_out)))
+
+
+def _sub(d_kind, w, gamma, c):
+    s = dbl_sub()
+    s.d_kind = d_kind
+    s.w = _ptr(w)
+    s.gamma = float(gamma)
+    s.c = _ptr(c)
+    return s
+
+
+def dbl_cgls(ctx, op, level, b, iters, x, gamma, w=None, c=None, x0=None, d_kind=None):
+    """Run `iters` CGLS steps; returns the FP64 residual history."""
+    if d_kind is None:
+        d_kind = 1 if w is not None else 0
+    s = _sub(d_kind, w, gamma, c)
+    hist = np.zeros(max(iters, 1), dtype=np.float64)
+    _check(ctx, lib().dbl_cgls(ctx.handle, op.handle, level, ctypes.byref(s), _ptr(b), _ptr(x0),
+                               iters, _ptr(x),
+                               hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return hist[:iters]
+
+
+def dbl_gcv(ctx, op, level, b, w=None, c=None, mode=DBL_GCV_SPECTRAL, grid=50):
+    """GCV choice of gamma; returns (gamma, GCV(gamma))."""
+    mode = GCV_MODES.get(mode, mode)
+    s = _sub(1 if w is not None else 0, w, 0.0, c)
+    g, f = ctypes.c_double(), ctypes.c_double()
+    _check(ctx, lib().dbl_gcv(ctx.handle, op.handle, level, ctypes.byref(s), _ptr(b), mode, grid,
+                              ctypes.byref(g), ctypes.byref(f)))
+    return g.value, f.value
+
+
+def dbl_deblur(ctx, b, psf, m, solver, wavelet, levels, transfer, x, opts=None):
+    """Full V-cycle solve; returns the report as a dict."""
+    keep, p, ph, pw = _psf_arg(psf)
+    opts = opts if opts is not None else dbl_opts_default()
+    rep = dbl_report()
+    _check(ctx, lib().dbl_deblur(ctx.handle, _ptr(b), p, ph, pw, m, SOLVERS.get(solver, solver),
+                                 WAVELETS.get(wavelet, wavelet), levels,
+                                 TRANSFERS.get(transfer, transfer), ctypes.byref(opts), _ptr(x),
+                                 ctypes.byref(rep)))
+    return rep.to_dict()
+
+
+def make_request(b, x, psf, m, solver, wavelet, levels, transfer, opts):
+    keep, p, ph, pw = _psf_arg(psf)
+    r = dbl_request()
+    r.b, r.x = _ptr(b), _ptr(x)
+    r.psf, r.ph, r.pw, r.m = p, ph, pw, m
+    r.solver = SOLVERS.get(solver, solver)
+    r.wavelet = WAVELETS.get(wavelet, wavelet)
+    r.levels = levels
+    r.transfer = TRANSFERS.get(transfer, transfer)
+    r.opts = opts
+    r._keep = (keep, opts)
+    return r
+
+
+def dbl_deblur_batch(ctx, requests):
+    """Solve a list of requests (from make_request) together; returns reports."""
+    n = len(requests)
+    arr = (dbl_request * n)(*requests)
+    reps = (dbl_report * n)()
+    _check(ctx, lib().dbl_deblur_batch(ctx.handle, n, arr, reps))
+    return [reps[i].to_dict() for i in range(n)]
+
+
+class Server:
+    def __init__(self, ctx, max_slots, budget=0):
+        self.ctx = ctx
+        h = ctypes.c_void_p()
+        _check(ctx, lib().dbl_server_create(ctx.handle, max_slots, budget, ctypes.byref(h)))
+        self.handle = h
+        self._keep = {}
+
+    def close(self):
+        if self.handle:
+            lib().dbl_server_destroy(self.handle)
+            self.handle = None
+
+
+def dbl_server_create(ctx, max_slots, budget=0):
+    return Server(ctx, max_slots, budget)
+
+
+def dbl_server_destroy(srv):
+    srv.close()
+
+
+def dbl_server_submit(srv, request):
+    t = ctypes.c_int64()
+    _check(srv.ctx, lib().dbl_server_submit(srv.handle, ctypes.byref(request), ctypes.byref(t)))
+    srv._keep[t.value] = request
+    return t.value
+
+
+def dbl_server_step(srv):
+    a = ctypes.c_int()
+    _check(srv.ctx, lib().dbl_server_step(srv.handle, ctypes.byref(a)))
+    return a.value
+
+
+def dbl_server_poll(srv, ticket):
+    done = ctypes.c_int()
+    rep = dbl_report()
+    _check(srv.ctx, lib().dbl_server_poll(srv.handle, ticket, ctypes.byref(done),
+                                          ctypes.byref(rep)))
+    if done.value:
+        srv._keep.pop(ticket, None)
+        return rep.to_dict()
+    return None

@@ -1,0 +1,515 @@
+// extern "C" entry points (include/deblur.h): argument validation first, then
+// the runtime.
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <new>
+
+#include "runtime.h"
+
+using namespace dbl;
+
+namespace {
+
+bool pow2(int m) { return m > 0 && (m & (m - 1)) == 0; }
+
+int check_prec(dbl_ctx* ctx, int p) {
+  if (p != DBL_F32 && p != DBL_F64) return set_err(ctx, DBL_EINVAL, "precision must be F32 or F64");
+  return DBL_OK;
+}
+
+int check_psf(dbl_ctx* ctx, const double* psf, int ph, int pw) {
+  if (!psf) return set_err(ctx, DBL_EINVAL, "psf is NULL");
+  if (ph <= 0 || pw <= 0 || ph % 2 == 0 || pw % 2 == 0)
+    return set_err(ctx, DBL_EINVAL, "psf dimensions must be odd and positive");
+  if (ph / 2 > DBL_MAX_PSF_RADIUS || pw / 2 > DBL_MAX_PSF_RADIUS)
+    return set_err(ctx, DBL_ENOTSUP, "psf half-width exceeds DBL_MAX_PSF_RADIUS");
+  double s = 0.0;
+  for (int k = 0; k < ph * pw; ++k) {
+    if (!std::isfinite(psf[k])) return set_err(ctx, DBL_EINVAL, "psf has non-finite entries");
+    s += std::fabs(psf[k]);
+  }
+  if (s == 0.0) return set_err(ctx, DBL_EINVAL, "psf is zero");
+  return DBL_OK;
+}
+
+int check_grid(dbl_ctx* ctx, int m, int levels, int wavelet) {
+  if (!pow2(m) || m < 8 || m > 8192) return set_err(ctx, DBL_EINVAL, "m must be a power of two in [8, 8192]");
+  if (wavelet != DBL_HAAR && wavelet != DBL_DB4) return set_err(ctx, DBL_EINVAL, "bad wavelet");
+  if (levels < 1 || levels > DBL_MAX_LEVELS) return set_err(ctx, DBL_EINVAL, "bad level count");
+  if ((m >> (levels - 1)) < 8) return set_err(ctx, DBL_EINVAL, "coarsest grid smaller than 8");
+  return DBL_OK;
+}
+
+int check_opts(dbl_ctx* ctx, const dbl_opts& o) {
+  if (!(o.eps > 0.0) || !(o.tau >= 0.0)) return set_err(ctx, DBL_EINVAL, "eps must be > 0, tau >= 0");
+  if (o.k_out < 1 || o.k_out > DBL_MAX_KOUT) return set_err(ctx, DBL_EINVAL, "k_out out of range");
+  if (o.k_in < 1 || o.k_in > 100000) return set_err(ctx, DBL_EINVAL, "k_in out of range");
+  if (o.gcv_mode < 0 || o.gcv_mode > 2) return set_err(ctx, DBL_EINVAL, "bad gcv_mode");
+  if (o.gcv_grid < 3 || o.gcv_grid > DBL_GCV_GRID_MAX) return set_err(ctx, DBL_EINVAL, "bad gcv_grid");
+  return check_prec(ctx, o.precision);
+}
+
+int check_request(dbl_ctx* ctx, const dbl_request& r) {
+  if (!r.b || !r.x) return set_err(ctx, DBL_EINVAL, "b or x is NULL");
+  int rc = check_psf(ctx, r.psf, r.ph, r.pw);
+  if (!rc) rc = check_grid(ctx, r.m, r.levels, r.wavelet);
+  if (!rc && (r.solver < 0 || r.solver > 2)) rc = set_err(ctx, DBL_EINVAL, "bad solver");
+  if (!rc && (r.transfer < 0 || r.transfer > 1)) rc = set_err(ctx, DBL_EINVAL, "bad transfer");
+  if (!rc) rc = check_opts(ctx, r.opts);
+  if (!rc && r.opts.mu_schedule) {
+    for (int k = 0; k < r.levels * r.opts.k_out; ++k)
+      if (!(r.opts.mu_schedule[k] > 0.0) || !std::isfinite(r.opts.mu_schedule[k]))
+        return set_err(ctx, DBL_EINVAL, "mu_schedule entries must be positive and finite");
+  }
+  return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+void dbl_opts_default(dbl_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->eps = 0.03;
+  o->tau = 0.005;
+  o->k_out = 10;
+  o->k_in = 30;
+  o->mu_fixed = 0.0;
+  o->mu_schedule = nullptr;
+  o->gcv_mode = DBL_GCV_AUTO;
+  o->gcv_grid = 50;
+  o->precision = DBL_F32;
+}
+
+int dbl_create(dbl_ctx** out, int device, void* hip_stream, size_t budget) {
+  if (!out) return DBL_EINVAL;
+  *out = nullptr;
+  if (device == -1) {  // argument-checking context: no device, no work
+    dbl_ctx* ctx = new (std::nothrow) dbl_ctx();
+    if (!ctx) return DBL_ENOMEM;
+    ctx->device = -1;
+    *out = ctx;
+    return DBL_OK;
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+    (void)hipGetLastError();
+    return DBL_EDEVICE;
+  }
+  if (device < 0 || device >= ndev) return DBL_EINVAL;
+  if (hipSetDevice(device) != hipSuccess) return DBL_EDEVICE;
+  dbl_ctx* ctx = new (std::nothrow) dbl_ctx();
+  if (!ctx) return DBL_ENOMEM;
+  ctx->device = device;
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  ctx->budget = budget;
+  if (hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess) {
+    delete ctx;
+    return DBL_EDEVICE;
+  }
+  *out = ctx;
+  return DBL_OK;
+}
+
+int dbl_destroy(dbl_ctx* ctx) {
+  if (!ctx) return DBL_EINVAL;
+  if (ctx->device < 0) {
+    delete ctx;
+    return DBL_OK;
+  }
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  for (auto& kv : ctx->dct) (void)hipFree(kv.second);
+  for (auto& kv : ctx->allocs) (void)hipFree(kv.first);
+  if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
+  if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+  if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+  delete ctx;
+  return DBL_OK;
+}
+
+const char* dbl_last_error(const dbl_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : "null context";
+}
+
+int dbl_sync(dbl_ctx* ctx) {
+  if (!ctx) return DBL_EINVAL;
+  if (ctx->device < 0) return DBL_OK;
+  return hip_check(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+}
+
+size_t dbl_workspace_bytes(const dbl_ctx* ctx) { return ctx ? ctx->used : 0; }
+
+int dbl_op_create(dbl_ctx* ctx, const double* psf, int ph, int pw, int m, int levels,
+                  int wavelet, int precision, dbl_op** out) {
+  if (!ctx || !out) return DBL_EINVAL;
+  *out = nullptr;
+  int rc = check_psf(ctx, psf, ph, pw);
+  if (!rc) rc = check_grid(ctx, m, levels, wavelet);
+  if (!rc) rc = check_prec(ctx, precision);
+  if (rc) return rc;
+  if (ctx->device < 0) return set_err(ctx, DBL_EDEVICE, "context has no device");
+  (void)hipSetDevice(ctx->device);
+  return op_build(ctx, psf, ph, pw, m, levels, wavelet, precision, out);
+}
+
+int dbl_op_destroy(dbl_op* op) {
+  if (!op) return DBL_EINVAL;
+  (void)hipStreamSynchronize(op->ctx->stream);
+  op_free(op);
+  return DBL_OK;
+}
+
+int dbl_apply_A(dbl_ctx* ctx, const dbl_op* op, int level, int transpose, const void* in,
+                void* out) {
+  if (!ctx || !op) return DBL_EINVAL;
+  if (!in || !out) return set_err(ctx, DBL_EINVAL, "in or out is NULL");
+  if (level < 0 || level >= op->levels) return set_err(ctx, DBL_EINVAL, "level out of range");
+  if (transpose != 0 && transpose != 1) return set_err(ctx, DBL_EINVAL, "bad transpose flag");
+  if (ctx->device < 0) return set_err(ctx, DBL_EDEVICE, "context has no device");
+  (void)hipSetDevice(ctx->device);
+  const LevelHost& L = op->host.levels[level];
+  Job j;
+  std::memset(&j, 0, sizeof(j));
+  j.m = L.m;
+  j.op = op->d_ops + level;
+  j.flags = transpose ? F_ADJ : 0;
+  j.v[0] = const_cast<void*>(in);
+  j.v[1] = out;
+  Launch Lc;
+  const int esz = op->precision == DBL_F64 ? 8 : 4;
+  Lc.add(j, j.m, esz);
+  LaunchArgs la;
+  int rc = Lc.upload(ctx, la);
+  if (rc) return rc;
+  return hip_check(ctx, launch_apply_A(la, op->precision, L.sep ? 1 : 0, L.rb, L.sep ? L.rb : L.R),
+                   "apply A");
+}
+
+int dbl_apply_L(dbl_ctx* ctx, int m, int precision, int transpose, const void* in, void* out) {
+  if (!ctx) return DBL_EINVAL;
+  if (!in || !out) return set_err(ctx, DBL_EINVAL, "in or out is NULL");
+  if (!pow2(m) || m < 2) return set_err(ctx, DBL_EINVAL, "m must be a power of two >= 2");
+  if (transpose != 0 && transpose != 1) return set_err(ctx, DBL_EINVAL, "bad transpose flag");
+  int rc = check_prec(ctx, precision);
+  if (rc) return rc;
+  if (ctx->device < 0) return set_err(ctx, DBL_EDEVICE, "context has no device");
+  (void)hipSetDevice(ctx->device);
+  Job j;
+  std::memset(&j, 0, sizeof(j));
+  j.m = m;
+  j.v[0] = const_cast<void*>(in);
+  j.v[1] = out;
+  Launch Lc;
+  Lc.add(j, m, precision == DBL_F64 ? 8 : 4);
+  LaunchArgs la;
+  if ((rc = Lc.upload(ctx, la))) return rc;
+  return hip_check(ctx, transpose ? launch_gradT(la, precision) : launch_grad(la, precision),
+                   "apply L");
+}
+
+int dbl_dwt(dbl_ctx* ctx, int wavelet, int m, int precision, int inverse, int lowpass_only,
+            const void* in, void* out) {
+  if (!ctx) return DBL_EINVAL;
+  if (!in || !out) return set_err(ctx, DBL_EINVAL, "in or out is NULL");
+  if (!pow2(m) || m < 4) return set_err(ctx, DBL_EINVAL, "m must be a power of two >= 4");
+  if (wavelet != DBL_HAAR && wavelet != DBL_DB4) return set_err(ctx, DBL_EINVAL, "bad wavelet");
+  if ((inverse != 0 && inverse != 1) || (lowpass_only != 0 && lowpass_only != 1))
+    return set_err(ctx, DBL_EINVAL, "bad flag");
+  int rc = check_prec(ctx, precision);
+  if (rc) return rc;
+  if (ctx->device < 0) return set_err(ctx, DBL_EDEVICE, "context has no device");
+  (void)hipSetDevice(ctx->device);
+  Job j;
+  std::memset(&j, 0, sizeof(j));
+  j.m = m;
+  j.flags = wavelet;
+  j.p0 = lowpass_only ? 0.0 : 1.0;
+  j.v[0] = const_cast<void*>(in);
+  j.v[1] = out;
+  Launch Lc;
+  Lc.add(j, inverse ? m : m / 2, precision == DBL_F64 ? 8 : 4);
+  LaunchArgs la;
+  if ((rc = Lc.upload(ctx, la))) return rc;
+  return hip_check(ctx, inverse ? launch_dwt_inv(la, precision) : launch_dwt_fwd(la, precision),
+                   "dwt");
+}
+
+int dbl_dtransfer(dbl_ctx* ctx, int wavelet, int m_coarse, int precision, const void* in,
+                  void* out) {
+  if (!ctx) return DBL_EINVAL;
+  if (!in || !out) return set_err(ctx, DBL_EINVAL, "in or out is NULL");
+  if (!pow2(m_coarse) || m_coarse < 2) return set_err(ctx, DBL_EINVAL, "m_coarse must be a power of two >= 2");
+  if (wavelet != DBL_HAAR && wavelet != DBL_DB4) return set_err(ctx, DBL_EINVAL, "bad wavelet");
+  int rc = check_prec(ctx, precision);
+  if (rc) return rc;
+  if (ctx->device < 0) return set_err(ctx, DBL_EDEVICE, "context has no device");
+  (void)hipSetDevice(ctx->device);
+  Job j;
+  std::memset(&j, 0, sizeof(j));
+  j.m = 2 * m_coarse;
+  j.flags = wavelet;
+  j.v[0] = const_cast<void*>(in);
+  j.v[1] = out;
+  Launch Lc;
+  Lc.add(j, j.m, precision == DBL_F64 ? 8 : 4);
+  LaunchArgs la;
+  if ((rc = Lc.upload(ctx, la))) return rc;
+  return hip_check(ctx, launch_dtransfer(la, precision), "dtransfer");
+}
+
+int dbl_cgls(dbl_ctx* ctx, const dbl_op* op, int level, const dbl_sub* sub, const void* b,
+             const void* x0, int iters, void* x, double* resid_hist) {
+  if (!ctx || !op) return DBL_EINVAL;
+  if (!sub || !b || !x) return set_err(ctx, DBL_EINVAL, "sub, b or x is NULL");
+  if (level < 0 || level >= op->levels) return set_err(ctx, DBL_EINVAL, "level out of range");
+  if (iters < 0 || iters > NSCAL - S_HIST) return set_err(ctx, DBL_EINVAL, "iters out of range [0, 128]");
+  if (sub->d_kind != 0 && sub->d_kind != 1) return set_err(ctx, DBL_EINVAL, "bad d_kind");
+  if (sub->d_kind == 1 && !sub->w) return set_err(ctx, DBL_EINVAL, "weights required for d_kind 1");
+  if (!(sub->gamma >= 0.0) || !std::isfinite(sub->gamma)) return set_err(ctx, DBL_EINVAL, "gamma must be finite and >= 0");
+  if (ctx->device < 0) return set_err(ctx, DBL_EDEVICE, "context has no device");
+  (void)hipSetDevice(ctx->device);
+  const LevelHost& L = op->host.levels[level];
+  const int m = L.m, prec = op->precision;
+  const size_t esz = prec == DBL_F64 ? 8 : 4;
+  const size_t n = (size_t)m * m, nl = 2 * (size_t)m * (m - 1);
+  const int nt = tiles_per_axis(m, (int)esz);
+  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  const size_t need = 6 * al(n * esz) + 3 * al(nl * esz) + al(NSCAL * 8) +
+                      al((size_t)nt * nt * 32 * 8) + 256;
+  int rc = DBL_OK;
+  if (ctx->scratch_bytes < need) {
+    if ((rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "sync"))) return rc;
+    dfree(ctx, ctx->scratch);
+    ctx->scratch = nullptr;
+    ctx->scratch_bytes = 0;
+    if ((rc = dmalloc(ctx, need, &ctx->scratch))) return rc;
+    ctx->scratch_bytes = need;
+  }
+  char* p = static_cast<char*>(ctx->scratch);
+  auto take = [&](size_t b) { void* r = p; p += al(b); return r; };
+  void* P[2] = {take(n * esz), take(n * esz)};
+  void* S = take(n * esz);
+  void* R1[2] = {take(n * esz), take(n * esz)};
+  void* Q1 = take(n * esz);
+  void* R2[2] = {take(nl * esz), take(nl * esz)};
+  void* Q2 = take(nl * esz);
+  double* scal = static_cast<double*>(take(NSCAL * 8));
+  double* part = static_cast<double*>(take((size_t)nt * nt * 32 * 8));
+  unsigned* cnt = static_cast<unsigned*>(take(256));
+  if ((rc = hip_check(ctx, hipMemsetAsync(cnt, 0, 256, ctx->stream), "clear"))) return rc;
+  const double gv[2] = {sub->gamma, std::sqrt(sub->gamma)};
+  void* dg = nullptr;
+  if ((rc = stage(ctx, gv, sizeof(gv), &dg))) return rc;
+  if ((rc = hip_check(ctx, hipMemcpyAsync(scal + S_GAMMA, dg, sizeof(gv), hipMemcpyDeviceToDevice,
+                                          ctx->stream), "set gamma")))
+    return rc;
+  Job j;
+  std::memset(&j, 0, sizeof(j));
+  j.m = m;
+  j.op = op->d_ops + level;
+  j.scal = scal;
+  j.part = part;
+  j.cnt = cnt;
+  j.flags = (sub->d_kind == 1 ? F_IRLS : 0) | (sub->c ? F_SHIFT : 0) | F_HIST;
+  j.v[V_X] = x;
+  j.v[V_S] = S;
+  j.v[V_Q1] = Q1;
+  j.v[V_Q2] = Q2;
+  j.v[V_W] = const_cast<void*>(sub->w);
+  j.v[V_B] = const_cast<void*>(b);
+  j.v[V_C1] = const_cast<void*>(sub->c);
+  const int sep = L.sep ? 1 : 0, rb = L.rb, H = L.sep ? L.rb : L.R;
+  if (x0) {
+    Job ja = j;
+    ja.v[0] = const_cast<void*>(x0);
+    ja.v[1] = R1[0];
+    ja.flags = 0;
+    Launch La;
+    La.add(ja, m, (int)esz);
+    LaunchArgs la;
+    if ((rc = La.upload(ctx, la))) return rc;
+    if ((rc = hip_check(ctx, launch_apply_A(la, prec, sep, rb, H), "A x0"))) return rc;
+  }
+  Job ji = j;
+  ji.v[V_PA] = P[0];
+  ji.v[V_R1A] = R1[0];
+  ji.v[V_R2A] = R2[0];
+  ji.v[V_X0] = const_cast<void*>(x0);
+  Launch Li;
+  Li.add(ji, m, (int)esz);
+  LaunchArgs la;
+  if ((rc = Li.upload(ctx, la))) return rc;
+  if ((rc = hip_check(ctx, launch_cgls_init(la, prec), "cgls init"))) return rc;
+  Job jf = j;
+  jf.flags |= F_FIRST;
+  jf.v[V_R1A] = R1[0];
+  jf.v[V_R1B] = R1[1];
+  jf.v[V_R2A] = R2[0];
+  jf.v[V_R2B] = R2[1];
+  Launch Lf;
+  Lf.add(jf, m, (int)esz);
+  if ((rc = Lf.upload(ctx, la))) return rc;
+  if ((rc = hip_check(ctx, launch_cgls_p2(la, prec, sep, rb, H), "cgls p2"))) return rc;
+  LaunchArgs a1[2], a2[2];
+  for (int par = 0; par < 2; ++par) {
+    Job a = j;
+    a.v[V_PA] = P[par];
+    a.v[V_PB] = P[1 - par];
+    Launch L1;
+    L1.add(a, m, (int)esz);
+    if ((rc = L1.upload(ctx, a1[par]))) return rc;
+    Job bb = j;
+    bb.v[V_PB] = P[1 - par];
+    bb.v[V_R1A] = R1[1 - par];
+    bb.v[V_R1B] = R1[par];
+    bb.v[V_R2A] = R2[1 - par];
+    bb.v[V_R2B] = R2[par];
+    Launch L2;
+    L2.add(bb, m, (int)esz);
+    if ((rc = L2.upload(ctx, a2[par]))) return rc;
+  }
+  for (int it = 0; it < iters; ++it) {
+    const int par = it & 1;
+    if ((rc = hip_check(ctx, launch_cgls_p1(a1[par], prec, sep, rb, H), "cgls p1"))) return rc;
+    if ((rc = hip_check(ctx, launch_cgls_p2(a2[par], prec, sep, rb, H), "cgls p2"))) return rc;
+  }
+  if (resid_hist && iters > 0) {
+    if ((rc = hip_check(ctx, hipMemcpyAsync(resid_hist, scal + S_HIST, iters * sizeof(double),
+                                            hipMemcpyDeviceToHost, ctx->stream), "read history")))
+      return rc;
+    if ((rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "sync"))) return rc;
+  }
+  return DBL_OK;
+}
+
+int dbl_gcv(dbl_ctx* ctx, const dbl_op* op, int level, const dbl_sub* sub, const void* b,
+            int mode, int grid, double* gamma_out, double* gcv_out) {
+  if (!ctx || !op) return DBL_EINVAL;
+  if (!sub || !b || !gamma_out) return set_err(ctx, DBL_EINVAL, "sub, b or gamma_out is NULL");
+  if (level < 0 || level >= op->levels) return set_err(ctx, DBL_EINVAL, "level out of range");
+  if (sub->d_kind != 0 && sub->d_kind != 1) return set_err(ctx, DBL_EINVAL, "bad d_kind");
+  if (sub->d_kind == 1 && !sub->w) return set_err(ctx, DBL_EINVAL, "weights required for d_kind 1");
+  if (sub->d_kind == 1 && sub->c) return set_err(ctx, DBL_EINVAL, "weighted pair takes no shift");
+  if (mode < 0 || mode > 2) return set_err(ctx, DBL_EINVAL, "bad mode");
+  if (grid < 3 || grid > DBL_GCV_GRID_MAX) return set_err(ctx, DBL_EINVAL, "bad grid size");
+  const int m = op->host.levels[level].m;
+  const size_t n = (size_t)m * m;
+  if (mode == DBL_GCV_AUTO) mode = n <= 4096 ? DBL_GCV_EXACT : DBL_GCV_SPECTRAL;
+  if (mode == DBL_GCV_EXACT && n > 4096)
+    return set_err(ctx, DBL_ENOTSUP, "EXACT GCV is limited to n <= 4096");
+  if (ctx->device < 0) return set_err(ctx, DBL_EDEVICE, "context has no device");
+  (void)hipSetDevice(ctx->device);
+  const int nt = tiles_per_axis(m, op->precision == DBL_F64 ? 8 : 4);
+  void* blk = nullptr;
+  const size_t bytes = 4 * ((n * 8 + 255) & ~size_t(255)) + NSCAL * 8 + 256 +
+                       (size_t)std::max(nt * nt, 64) * 64 * 8 * 4;
+  int rc = dmalloc(ctx, bytes, &blk);
+  if (rc) return rc;
+  char* p = static_cast<char*>(blk);
+  auto take = [&](size_t b) { void* r = p; p += (b + 255) & ~size_t(255); return r; };
+  GcvReq g{};
+  g.op = op;
+  g.level = level;
+  g.prec = op->precision;
+  g.b = b;
+  g.w = sub->d_kind == 1 ? sub->w : nullptr;
+  g.c1 = sub->c;
+  g.c2 = nullptr;
+  g.bh = static_cast<double*>(take(n * 8));
+  g.e = static_cast<double*>(take(n * 8));
+  g.tmp = static_cast<double*>(take(n * 8));
+  g.in = static_cast<double*>(take(n * 8));
+  g.scal = static_cast<double*>(take(NSCAL * 8));
+  g.cnt = static_cast<unsigned*>(take(256));
+  g.part = static_cast<double*>(take((size_t)std::max(nt * nt, 64) * 64 * 8 * 4));
+  g.bh_valid = false;
+  g.grid = grid;
+  g.mode = mode;
+  rc = hip_check(ctx, hipMemsetAsync(g.cnt, 0, 256, ctx->stream), "clear");
+  if (!rc) rc = hip_check(ctx, hipMemsetAsync(g.scal, 0, NSCAL * 8, ctx->stream), "clear");
+  std::vector<GcvReq> v{g};
+  if (!rc) rc = gcv_run(ctx, v);
+  double out[2] = {0, 0};
+  if (!rc)
+    rc = hip_check(ctx, hipMemcpyAsync(out, g.scal + S_GAMMA, sizeof(double), hipMemcpyDeviceToHost,
+                                       ctx->stream), "read gamma");
+  if (!rc)
+    rc = hip_check(ctx, hipMemcpyAsync(out + 1, g.scal + S_G_FBEST, sizeof(double),
+                                       hipMemcpyDeviceToHost, ctx->stream), "read gcv");
+  if (!rc) rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "sync");
+  dfree(ctx, blk);
+  if (rc) return rc;
+  *gamma_out = out[0];
+  if (gcv_out) *gcv_out = out[1];
+  return DBL_OK;
+}
+
+int dbl_deblur(dbl_ctx* ctx, const void* b, const double* psf, int ph, int pw, int m, int solver,
+               int wavelet, int levels, int transfer, const dbl_opts* opts, void* x,
+               dbl_report* rep) {
+  if (!ctx) return DBL_EINVAL;
+  dbl_request r;
+  std::memset(&r, 0, sizeof(r));
+  r.b = b;
+  r.x = x;
+  r.psf = psf;
+  r.ph = ph;
+  r.pw = pw;
+  r.m = m;
+  r.solver = solver;
+  r.wavelet = wavelet;
+  r.levels = levels;
+  r.transfer = transfer;
+  if (opts) r.opts = *opts; else dbl_opts_default(&r.opts);
+  return dbl_deblur_batch(ctx, 1, &r, rep);
+}
+
+int dbl_deblur_batch(dbl_ctx* ctx, int count, const dbl_request* reqs, dbl_report* reps) {
+  if (!ctx) return DBL_EINVAL;
+  if (count < 0 || (count > 0 && !reqs)) return set_err(ctx, DBL_EINVAL, "bad request list");
+  if (count > 60000) return set_err(ctx, DBL_EINVAL, "too many requests");
+  for (int i = 0; i < count; ++i) {
+    int rc = check_request(ctx, reqs[i]);
+    if (rc) return rc;
+  }
+  if (count == 0) return DBL_OK;
+  if (ctx->device < 0) return set_err(ctx, DBL_EDEVICE, "context has no device");
+  (void)hipSetDevice(ctx->device);
+  std::vector<Slot> slots(count);
+  std::vector<Slot*> ptrs;
+  int rc = DBL_OK;
+  for (int i = 0; i < count && !rc; ++i) {
+    rc = slot_init(ctx, reqs[i], &slots[i]);
+    ptrs.push_back(&slots[i]);
+  }
+  if (!rc) rc = hip_check(ctx, hipEventRecord(ctx->ev0, ctx->stream), "event");
+  while (!rc) {
+    bool all = true;
+    for (Slot* s : ptrs) all = all && s->done;
+    if (all) break;
+    rc = engine_step(ctx, ptrs);
+  }
+  if (!rc) rc = hip_check(ctx, hipEventRecord(ctx->ev1, ctx->stream), "event");
+  if (!rc) rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "sync");
+  float ms = 0.f;
+  if (!rc) (void)hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
+  for (int i = 0; i < count; ++i) {
+    if (!rc && reps) {
+      rc = slot_report(ctx, &slots[i], &reps[i]);
+      reps[i].seconds = ms * 1e-3;
+      bool bad = false;
+      for (int l = 0; l < slots[i].levels; ++l)
+        for (int k = 0; k < slots[i].opts.k_out; ++k)
+          if (!std::isfinite(reps[i].objective[l][k])) bad = true;
+      if (bad) reps[i].status = DBL_ENUMERIC;
+    }
+  }
+  (void)hipStreamSynchronize(ctx->stream);
+  for (auto& s : slots) slot_free(ctx, &s);
+  return rc;
+}
+
+}  // extern "C"

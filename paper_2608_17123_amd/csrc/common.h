@@ -1,0 +1,191 @@
+// Shared host/device definitions of the deblurring library (gfx950).
+//
+// Device data model
+// -----------------
+// * Every kernel launch covers a list of jobs (one job = one image at one
+//   level) cut into TILE x TILE output tiles.  Block b of a launch handles tile
+//   table entry b: job index in the upper 16 bits, tile index within the job in
+//   the lower 16 bits.  A single solve is a launch with one job; a batch or a
+//   server step is the same launch with many jobs.
+// * Each job owns an FP64 scalar block (CGLS alpha/beta, gamma, norms, GCV
+//   state) and a partials array indexed by tile.  Reductions are
+//   deterministic: a block writes its FP64 partial to its own slot; the last
+//   block of the job to finish (atomic counter) sums the partials in tile
+//   order, so results do not depend on which other jobs share the launch.
+// * Coarse operators are stored as "class tables": along one axis, rows near
+//   the periodic wavelet seam (top St rows, bottom Sb rows) have their own tap
+//   rows, every other row uses the interior Toeplitz row; taps are indexed by
+//   circular offset e in [-R, R] and applied with periodic indexing.  The
+//   finest level (zero boundary) is the same structure with truncated rows.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dbl {
+
+constexpr int TILE = 64;
+constexpr int NTHREADS = 256;
+constexpr int MAX_R = 16;
+constexpr int NSCAL = 256;  // doubles per job scalar block
+
+// Scalar block layout (FP64, device).
+enum Scal : int {
+  S_GAMMA = 0, S_SQRTG, S_GS, S_ALPHA, S_BETA, S_QQ, S_RR, S_GS0,
+  S_RCNUM, S_RCDEN, S_RES2, S_PEN, S_EPS, S_TAU, S_WSQ, S_ITER,
+  // GCV state
+  S_G_TLO = 32, S_G_THI, S_G_A, S_G_B, S_G_X, S_G_W, S_G_V, S_G_FX, S_G_FW,
+  S_G_FV, S_G_D, S_G_E, S_G_U, S_G_DONE, S_G_NEV, S_G_XTOL, S_G_IT, S_G_RMIN,
+  S_G_RMAX, S_G_NPTS, S_G_WBAR, S_G_RES, S_G_TR, S_G_FBEST,
+  S_GRID = 64,   // up to 64 grid values
+  S_HIST = 128   // CGLS residual history (up to 128 iterations)
+};
+
+struct Table1D {
+  int R;            // radius (taps per row = 2R + 1)
+  int St, Sb;       // seam rows at top / bottom
+  int rows;         // St + 1 + Sb
+  const float* tf;  // rows * (2R+1), row-major
+  const double* td;
+};
+
+struct Table2D {
+  int R0, R1;
+  int St0, Sb0, St1, Sb1;
+  int rows0, rows1;
+  const int* off;     // rows0 * rows1 + 1 offsets into taps
+  const short2* e;    // (e0, e1) per tap
+  const float* vf;
+  const double* vd;
+};
+
+struct LevelOp {
+  int m;
+  int sep;   // 1: separable (two 1-D passes), 0: general 2-D tap lists
+  int rb;    // radius bucket used by the separable kernels (tables padded to rb)
+  int R;     // halo radius (max over both axes)
+  Table1D f0, f1, a0, a1;  // forward / adjoint tables, axis 0 (rows) and 1 (cols)
+  Table2D f2, a2;
+};
+
+__host__ __device__ inline int class_of(int i, int m, int St, int Sb) {
+  if (i < St) return i;
+  if (i >= m - Sb) return St + 1 + (i - (m - Sb));
+  return St;
+}
+
+struct Job {
+  int m;
+  int nti, ntj;     // tiles along axis 0 and axis 1
+  int flags;        // kernel specific
+  const LevelOp* op;
+  void* v[16];      // vectors (meaning set by each kernel)
+  double* scal;     // FP64 scalar block
+  double* part;     // FP64 partials, >= 4 per tile
+  unsigned* cnt;    // completion counter (reset by the last block)
+  double p0, p1;    // extra scalars passed by value
+  int i0, i1;       // extra integers passed by value
+  double* hist;     // per-solve history (gamma, rc, objective) for stats kernels
+};
+
+// Job flags
+enum : int {
+  F_IRLS = 1,       // D = diag(w) L
+  F_SHIFT = 2,      // c != 0 (MM, SB)
+  F_SB = 4,
+  F_MM = 8,
+  F_ADJ = 16,       // transpose
+  F_HIST = 32,      // record CGLS residual history
+  F_FIRST = 64,     // first phase after init (alpha = 0)
+};
+
+__device__ __forceinline__ void decode_tile(const Job* __restrict__ jobs,
+                                            const uint32_t* __restrict__ tiles,
+                                            const Job*& job, int& ti, int& tj, int& tix) {
+  uint32_t t = tiles[blockIdx.x];
+  job = jobs + (t >> 16);
+  tix = int(t & 0xffffu);
+  ti = tix % job->nti;
+  tj = tix / job->nti;
+}
+
+// ---------------------------------------------------------------- reduce --
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum over the block (NTHREADS threads), result valid in thread 0.  `red`
+// must hold NTHREADS/64 doubles per value.  Order is fixed.
+template <int K>
+__device__ __forceinline__ void block_sum(double (&v)[K], double* red) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) red[k * (NTHREADS / 64) + wid] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      double s = 0.0;
+      for (int w = 0; w < NTHREADS / 64; ++w) s += red[k * (NTHREADS / 64) + w];
+      v[k] = s;
+    }
+  }
+}
+
+// Write this tile's K partials; returns true in thread 0 of the last block of
+// the job to finish, after which `tot` holds the job-wide sums.  The last
+// block sums the partials with a fixed assignment (thread t takes tiles t,
+// t + NTHREADS, ... in order) and a fixed tree, so the result depends only on
+// the job's own tiles.  Partials go through device-scope atomics and fences
+// so that blocks on different XCDs (separate L2s) see each other's values.
+template <int K>
+__device__ __forceinline__ bool job_reduce(const Job* job, int tix, double (&v)[K],
+                                           double* red, double (&tot)[K]) {
+  block_sum<K>(v, red);
+  __shared__ int s_last;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      __hip_atomic_store(job->part + tix * K + k, v[k], __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    __threadfence();
+    unsigned ntile = unsigned(job->nti * job->ntj);
+    unsigned prev = atomicAdd(job->cnt, 1u);
+    s_last = (prev == ntile - 1) ? 1 : 0;
+  }
+  __syncthreads();
+  if (!s_last) return false;
+  __threadfence();
+  const int nt = job->nti * job->ntj;
+  double acc[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) acc[k] = 0.0;
+  for (int t = threadIdx.x; t < nt; t += NTHREADS) {
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      acc[k] += __hip_atomic_load(job->part + t * K + k, __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT);
+  }
+  block_sum<K>(acc, red);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) tot[k] = acc[k];
+    __hip_atomic_store(job->cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  return threadIdx.x == 0;
+}
+
+// Publish a scalar written by the finalising thread so later kernels and
+// other XCDs read it from memory.
+__device__ __forceinline__ void put_scal(double* s, int k, double v) {
+  __hip_atomic_store(s + k, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+}  // namespace dbl

@@ -1,0 +1,45 @@
+// Host-side structures of the deblurring library.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/deblur.h"
+#include "common.h"
+#include "launch.h"
+
+namespace dbl {
+
+struct Table1DHost {
+  int R = 0, St = 0, Sb = 0, rows = 1;
+  std::vector<double> taps;  // rows * (2R+1)
+};
+
+struct Table2DHost {
+  int R0 = 0, R1 = 0, St0 = 0, Sb0 = 0, St1 = 0, Sb1 = 0, rows0 = 1, rows1 = 1;
+  std::vector<int> off;
+  std::vector<short> e0, e1;
+  std::vector<double> val;
+};
+
+struct LevelHost {
+  int m = 0;
+  bool sep = true;
+  int R = 0, rb = 0;
+  Table1DHost f0, f1, a0, a1;
+  Table2DHost f2, a2;
+  int kint_r0 = 0, kint_r1 = 0;
+  std::vector<double> kint;  // interior kernel, convolution orientation, column-major
+};
+
+struct HierHost {
+  bool sep = true;
+  std::vector<LevelHost> levels;
+};
+
+void build_hierarchy(const double* P, int ph, int pw, int m, int levels, int wavelet,
+                     HierHost& out);
+
+}  // namespace dbl

@@ -1,0 +1,467 @@
+// Solver kernels: the two fused CGLS phases on the augmented system of eq.
+// (augmented), their start, the per-outer-iteration auxiliary updates of
+// Algs. 1-3 (IRLS weights, MM shift, SB shrink and Bregman update) and the
+// per-outer-iteration statistics (relative change of eq. (stop), objective).
+//
+// CGLS on [A; sqrt(g) D] x ~ [b; sqrt(g) c], x0 = 0, FP64 scalars:
+//   init : x = 0, p = 0, r1 = b, r2 = sqrt(g) c
+//   p2(first): s = A^T r1 + sqrt(g) D^T r2,  gs = |s|^2,  beta = 0
+//   repeat:
+//   p1   : p = s + beta p;  q1 = A p;  q2 = sqrt(g) D p;  alpha = gs / |q|^2
+//   p2   : x += alpha p;  r -= alpha q;  s = A^T r1 + sqrt(g) D^T r2;
+//          beta = |s|^2 / gs
+// p, r1 and r2 are double-buffered (read one copy, write the other) because
+// the stencils read neighbours that other blocks update in the same launch.
+#include "launch.h"
+#include "stencil.h"
+
+namespace dbl {
+
+template <bool SEP>
+__device__ __forceinline__ int xs_at(int i, int j, int H, int TI, int TJ) {
+  return SEP ? (i + H) * sep_lx(TJ, H) + (j + H) : (j + H) * col_lx(TI, H) + (i + H);
+}
+
+template <bool SEP>
+__device__ __forceinline__ int xs_ld(int H, int TI, int TJ) {
+  return SEP ? sep_lx(TJ, H) : col_lx(TI, H);
+}
+
+template <bool SEP>
+__device__ __forceinline__ int xs_elems(int H, int TI, int TJ) {
+  return SEP ? (TI + 2 * H) * sep_lx(TJ, H) : col_lds_elems(TI, TJ, H);
+}
+
+template <typename T, int RB, bool SEP, class Epi>
+__device__ __forceinline__ void conv_tile(const T* Xs, int H, void* scratch, const LevelOp& op,
+                                          bool adj, int i0, int j0, int TI, int TJ, int m,
+                                          Epi epi) {
+  if constexpr (SEP) {
+    sep_tile<T, RB>(Xs, H, static_cast<T*>(scratch), adj ? op.a0 : op.f0, adj ? op.a1 : op.f1,
+                    i0, j0, TI, TJ, m, epi);
+  } else {
+    T* s_v = static_cast<T*>(scratch);
+    short2* s_e = reinterpret_cast<short2*>(s_v + (2 * H + 1) * (2 * H + 1));
+    gen_tile<T>(Xs, H, adj ? op.a2 : op.f2, s_e, s_v, i0, j0, TI, TJ, m, epi);
+  }
+}
+
+template <typename T> __device__ __forceinline__ T* vp(const Job* j, int k) {
+  return static_cast<T*>(j->v[k]);
+}
+
+// ------------------------------------------------------------------ init --
+template <typename T>
+__global__ void __launch_bounds__(NTHREADS) k_cgls_init(const Job* __restrict__ jobs,
+                                                        const uint32_t* __restrict__ tiles) {
+  const Job* job; int ti, tj, tix;
+  decode_tile(jobs, tiles, job, ti, tj, tix);
+  const int m = job->m;
+  int i0, j0, TI, TJ;
+  tile_geom<T>(m, ti, tj, i0, j0, TI, TJ);
+  const double sg = job->scal[S_SQRTG];
+  const bool shift = job->flags & F_SHIFT, sb = job->flags & F_SB, irls = job->flags & F_IRLS;
+  T* x = vp<T>(job, V_X);
+  T* p = vp<T>(job, V_PA);
+  T* r1 = vp<T>(job, V_R1A);
+  T* r2 = vp<T>(job, V_R2A);
+  const T* b = vp<T>(job, V_B);
+  const T* c1 = vp<T>(job, V_C1);
+  const T* c2 = vp<T>(job, V_C2);
+  const T* w = vp<T>(job, V_W);
+  const T* x0 = vp<T>(job, V_X0);   // optional start; r1 then already holds A x0
+  const size_t nx = (size_t)(m - 1) * m;
+  for (int o = threadIdx.x; o < TI * TJ; o += NTHREADS) {
+    const int gi = i0 + o % TI, gj = j0 + o / TI;
+    const size_t g = gi + (size_t)gj * m;
+    double xv = 0.0;
+    if (x0) {
+      xv = (double)x0[g];
+      r1[g] = (T)((double)b[g] - (double)r1[g]);
+    } else {
+      r1[g] = b[g];
+    }
+    x[g] = (T)xv;
+    p[g] = T(0);
+    for (int dir = 0; dir < 2; ++dir) {
+      if ((dir == 0 && gi >= m - 1) || (dir == 1 && gj >= m - 1)) continue;
+      const size_t k = dir == 0 ? gi + (size_t)gj * (m - 1) : nx + g;
+      double c = 0.0;
+      if (shift) c = (double)c1[k] - (sb ? (double)c2[k] : 0.0);
+      if (x0) {
+        const double nb = dir == 0 ? (double)x0[g + 1] : (double)x0[g + m];
+        double d = nb - xv;
+        if (irls) d *= (double)w[k];
+        c -= d;
+      }
+      r2[k] = (T)(sg * c);
+    }
+  }
+}
+
+// --------------------------------------------------------------- phase 1 --
+template <typename T, int RB, bool SEP>
+__global__ void __launch_bounds__(NTHREADS) k_cgls_p1(const Job* __restrict__ jobs,
+                                                      const uint32_t* __restrict__ tiles) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double red[8];
+  const Job* job; int ti, tj, tix;
+  decode_tile(jobs, tiles, job, ti, tj, tix);
+  const int m = job->m;
+  int i0, j0, TI, TJ;
+  tile_geom<T>(m, ti, tj, i0, j0, TI, TJ);
+  const LevelOp& op = *job->op;
+  const int H = SEP ? RB : op.R;
+  T* Xs = reinterpret_cast<T*>(smem);
+  void* scratch = Xs + xs_elems<SEP>(H, TI, TJ);
+  const T tb = (T)job->scal[S_BETA];
+  const double sg = job->scal[S_SQRTG];
+  const bool irls = job->flags & F_IRLS;
+  const T* __restrict__ s = vp<T>(job, V_S);
+  const T* __restrict__ pa = vp<T>(job, V_PA);
+  T* __restrict__ pb = vp<T>(job, V_PB);
+  T* __restrict__ q1 = vp<T>(job, V_Q1);
+  T* __restrict__ q2 = vp<T>(job, V_Q2);
+  const T* __restrict__ w = vp<T>(job, V_W);
+  load_tile<T, SEP>(Xs, xs_ld<SEP>(H, TI, TJ), i0, j0, TI, TJ, H, m,
+                    [&](int g) { return s[g] + tb * pa[g]; });
+  __syncthreads();
+  double acc = 0.0;
+  const size_t nx = (size_t)(m - 1) * m;
+  for (int o = threadIdx.x; o < TI * TJ; o += NTHREADS) {
+    const int i = o % TI, j = o / TI, gi = i0 + i, gj = j0 + j;
+    const size_t g = gi + (size_t)gj * m;
+    const T pc = Xs[xs_at<SEP>(i, j, H, TI, TJ)];
+    pb[g] = pc;
+    if (gi < m - 1) {
+      const size_t k = gi + (size_t)gj * (m - 1);
+      double d = (double)Xs[xs_at<SEP>(i + 1, j, H, TI, TJ)] - (double)pc;
+      if (irls) d *= (double)w[k];
+      const T qv = (T)(sg * d);
+      q2[k] = qv;
+      acc += (double)qv * (double)qv;
+    }
+    if (gj < m - 1) {
+      const size_t k = nx + g;
+      double d = (double)Xs[xs_at<SEP>(i, j + 1, H, TI, TJ)] - (double)pc;
+      if (irls) d *= (double)w[k];
+      const T qv = (T)(sg * d);
+      q2[k] = qv;
+      acc += (double)qv * (double)qv;
+    }
+  }
+  conv_tile<T, RB, SEP>(Xs, H, scratch, op, false, i0, j0, TI, TJ, m, [&](int i, int j, T v) {
+    q1[(i0 + i) + (size_t)(j0 + j) * m] = v;
+    acc += (double)v * (double)v;
+  });
+  double vv[1] = {acc}, tot[1];
+  if (job_reduce<1>(job, tix, vv, red, tot)) {
+    const double gs = job->scal[S_GS];
+    const double qq = tot[0];
+    put_scal(job->scal, S_QQ, qq);
+    put_scal(job->scal, S_ALPHA, qq > 0.0 ? gs / qq : 0.0);
+  }
+}
+
+// --------------------------------------------------------------- phase 2 --
+template <typename T, int RB, bool SEP>
+__global__ void __launch_bounds__(NTHREADS) k_cgls_p2(const Job* __restrict__ jobs,
+                                                      const uint32_t* __restrict__ tiles) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double red[8];
+  const Job* job; int ti, tj, tix;
+  decode_tile(jobs, tiles, job, ti, tj, tix);
+  const int m = job->m;
+  int i0, j0, TI, TJ;
+  tile_geom<T>(m, ti, tj, i0, j0, TI, TJ);
+  const LevelOp& op = *job->op;
+  const int H = SEP ? RB : op.R;
+  T* Xs = reinterpret_cast<T*>(smem);
+  void* scratch = Xs + xs_elems<SEP>(H, TI, TJ);
+  const bool first = job->flags & F_FIRST;
+  const bool irls = job->flags & F_IRLS;
+  const double alpha = first ? 0.0 : job->scal[S_ALPHA];
+  const T ta = (T)alpha;
+  const double sg = job->scal[S_SQRTG];
+  T* __restrict__ x = vp<T>(job, V_X);
+  const T* __restrict__ p = vp<T>(job, V_PB);
+  const T* __restrict__ r1a = vp<T>(job, V_R1A);
+  T* __restrict__ r1b = vp<T>(job, V_R1B);
+  const T* __restrict__ q1 = vp<T>(job, V_Q1);
+  const T* __restrict__ r2a = vp<T>(job, V_R2A);
+  T* __restrict__ r2b = vp<T>(job, V_R2B);
+  const T* __restrict__ q2 = vp<T>(job, V_Q2);
+  const T* __restrict__ w = vp<T>(job, V_W);
+  T* __restrict__ s = vp<T>(job, V_S);
+  if (first) {
+    load_tile<T, SEP>(Xs, xs_ld<SEP>(H, TI, TJ), i0, j0, TI, TJ, H, m,
+                      [&](int g) { return r1a[g]; });
+  } else {
+    load_tile<T, SEP>(Xs, xs_ld<SEP>(H, TI, TJ), i0, j0, TI, TJ, H, m,
+                      [&](int g) { return r1a[g] - ta * q1[g]; });
+  }
+  __syncthreads();
+  double accr = 0.0, accs = 0.0;
+  for (int o = threadIdx.x; o < TI * TJ; o += NTHREADS) {
+    const int i = o % TI, j = o / TI;
+    const size_t g = (i0 + i) + (size_t)(j0 + j) * m;
+    const T rv = Xs[xs_at<SEP>(i, j, H, TI, TJ)];
+    r1b[g] = rv;
+    accr += (double)rv * (double)rv;
+    if (!first) x[g] = x[g] + ta * p[g];
+  }
+  const size_t nx = (size_t)(m - 1) * m;
+  auto r2n = [&](size_t k) -> T { return first ? r2a[k] : (T)(r2a[k] - ta * q2[k]); };
+  auto wk = [&](size_t k) -> double { return irls ? (double)w[k] : 1.0; };
+  conv_tile<T, RB, SEP>(Xs, H, scratch, op, true, i0, j0, TI, TJ, m, [&](int i, int j, T v) {
+    const int gi = i0 + i, gj = j0 + j;
+    const size_t g = gi + (size_t)gj * m;
+    double lt = 0.0;
+    if (gi >= 1) {
+      const size_t k = gi - 1 + (size_t)gj * (m - 1);
+      lt += wk(k) * (double)r2n(k);
+    }
+    if (gi < m - 1) {
+      const size_t k = gi + (size_t)gj * (m - 1);
+      const T rn = r2n(k);
+      r2b[k] = rn;
+      accr += (double)rn * (double)rn;
+      lt -= wk(k) * (double)rn;
+    }
+    if (gj >= 1) {
+      const size_t k = nx + g - m;
+      lt += wk(k) * (double)r2n(k);
+    }
+    if (gj < m - 1) {
+      const size_t k = nx + g;
+      const T rn = r2n(k);
+      r2b[k] = rn;
+      accr += (double)rn * (double)rn;
+      lt -= wk(k) * (double)rn;
+    }
+    const T sv = (T)((double)v + sg * lt);
+    s[g] = sv;
+    accs += (double)sv * (double)sv;
+  });
+  double vv[2] = {accs, accr}, tot[2];
+  if (job_reduce<2>(job, tix, vv, red, tot)) {
+    double* sc = job->scal;
+    const double gs_new = tot[0];
+    const double gs_old = sc[S_GS];
+    put_scal(sc, S_BETA, (first || gs_old <= 0.0) ? 0.0 : gs_new / gs_old);
+    put_scal(sc, S_GS, gs_new);
+    put_scal(sc, S_RR, tot[1]);
+    if (first) {
+      put_scal(sc, S_GS0, gs_new);
+      put_scal(sc, S_ITER, 0.0);
+    } else if (job->flags & F_HIST) {
+      const int it = (int)sc[S_ITER];
+      if (it < NSCAL - S_HIST) put_scal(sc, S_HIST + it, tot[1]);
+      put_scal(sc, S_ITER, (double)(it + 1));
+    }
+  }
+}
+
+// ------------------------------------------------------------------- aux --
+// Job::i0 = AuxMode; p0 = eps, p1 = tau.  Reads x = v[V_X] with neighbours.
+template <typename T>
+__global__ void __launch_bounds__(NTHREADS) k_aux(const Job* __restrict__ jobs,
+                                                  const uint32_t* __restrict__ tiles) {
+  __shared__ double red[8];
+  const Job* job; int ti, tj, tix;
+  decode_tile(jobs, tiles, job, ti, tj, tix);
+  const int m = job->m;
+  int i0, j0, TI, TJ;
+  tile_geom<T>(m, ti, tj, i0, j0, TI, TJ);
+  const int mode = job->i0;
+  const double eps = job->p0, tau = job->p1;
+  const T* __restrict__ x = vp<T>(job, V_X);
+  T* __restrict__ w = vp<T>(job, V_W);
+  T* __restrict__ c1 = vp<T>(job, V_C1);
+  T* __restrict__ c2 = vp<T>(job, V_C2);
+  const size_t nx = (size_t)(m - 1) * m;
+  double wsq = 0.0;
+  for (int o = threadIdx.x; o < TI * TJ; o += NTHREADS) {
+    const int gi = i0 + o % TI, gj = j0 + o / TI;
+    const size_t g = gi + (size_t)gj * m;
+    const double xc = (double)x[g];
+    for (int dir = 0; dir < 2; ++dir) {
+      if ((dir == 0 && gi >= m - 1) || (dir == 1 && gj >= m - 1)) continue;
+      const size_t k = dir == 0 ? gi + (size_t)gj * (m - 1) : nx + g;
+      const double u = (dir == 0 ? (double)x[g + 1] : (double)x[g + m]) - xc;
+      if (mode == AUX_IRLS_W) {
+        const double a = fabs(u) > eps ? fabs(u) : eps;
+        const T wv = (T)(1.0 / sqrt(a));
+        w[k] = wv;
+        wsq += (double)wv * (double)wv;
+      } else if (mode == AUX_MM_W) {
+        c1[k] = (T)(u * (1.0 - sqrt(eps * eps / (u * u + eps * eps))));
+      } else {
+        const double v = mode == AUX_SB_UPDATE ? u + (double)c2[k] : u;
+        const double av = fabs(v) - tau;
+        const double d = av > 0.0 ? (v > 0.0 ? av : -av) : 0.0;
+        const T dt = (T)d;
+        c1[k] = dt;
+        c2[k] = (T)(v - (double)dt);
+      }
+    }
+  }
+  double vv[1] = {wsq}, tot[1];
+  if (job_reduce<1>(job, tix, vv, red, tot)) put_scal(job->scal, S_WSQ, tot[0]);
+}
+
+// ----------------------------------------------------------------- stats --
+// Per outer iteration: partials of |x - x_old|^2, |x_old|^2, |A x - b|^2 and
+// the solver penalty; the last block writes (gamma, RC, objective) to
+// job->hist[3 * i0 ...].  flags: F_IRLS / F_MM / F_SB select the penalty.
+template <typename T, int RB, bool SEP>
+__global__ void __launch_bounds__(NTHREADS) k_stats(const Job* __restrict__ jobs,
+                                                    const uint32_t* __restrict__ tiles) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double red[16];
+  const Job* job; int ti, tj, tix;
+  decode_tile(jobs, tiles, job, ti, tj, tix);
+  const int m = job->m;
+  int i0, j0, TI, TJ;
+  tile_geom<T>(m, ti, tj, i0, j0, TI, TJ);
+  const LevelOp& op = *job->op;
+  const int H = SEP ? RB : op.R;
+  T* Xs = reinterpret_cast<T*>(smem);
+  void* scratch = Xs + xs_elems<SEP>(H, TI, TJ);
+  const T* __restrict__ x = vp<T>(job, V_X);
+  const T* __restrict__ xo = vp<T>(job, V_XOLD);
+  const T* __restrict__ b = vp<T>(job, V_B);
+  const double eps = job->p0;
+  const int fl = job->flags;
+  load_tile<T, SEP>(Xs, xs_ld<SEP>(H, TI, TJ), i0, j0, TI, TJ, H, m,
+                    [&](int g) { return x[g]; });
+  __syncthreads();
+  double num = 0.0, den = 0.0, res = 0.0, pen = 0.0;
+  for (int o = threadIdx.x; o < TI * TJ; o += NTHREADS) {
+    const int i = o % TI, j = o / TI, gi = i0 + i, gj = j0 + j;
+    const size_t g = gi + (size_t)gj * m;
+    const double xc = (double)Xs[xs_at<SEP>(i, j, H, TI, TJ)];
+    const double xv = (double)xo[g];
+    num += (xc - xv) * (xc - xv);
+    den += xv * xv;
+    for (int dir = 0; dir < 2; ++dir) {
+      if ((dir == 0 && gi >= m - 1) || (dir == 1 && gj >= m - 1)) continue;
+      const double t = (double)Xs[dir == 0 ? xs_at<SEP>(i + 1, j, H, TI, TJ)
+                                           : xs_at<SEP>(i, j + 1, H, TI, TJ)] - xc;
+      const double at = fabs(t);
+      if (fl & F_IRLS) pen += at <= eps ? t * t / (2.0 * eps) : at - 0.5 * eps;
+      else if (fl & F_MM) pen += sqrt(t * t + eps * eps);
+      else pen += at;
+    }
+  }
+  conv_tile<T, RB, SEP>(Xs, H, scratch, op, false, i0, j0, TI, TJ, m, [&](int i, int j, T v) {
+    const double r = (double)v - (double)b[(i0 + i) + (size_t)(j0 + j) * m];
+    res += r * r;
+  });
+  double vv[4] = {num, den, res, pen}, tot[4];
+  if (job_reduce<4>(job, tix, vv, red, tot)) {
+    const double gam = job->scal[S_GAMMA];
+    double coef;
+    if (fl & F_IRLS) coef = 2.0 * gam;
+    else if (fl & F_MM) coef = 2.0 * eps * gam;
+    else coef = 2.0 * job->p1 * gam;
+    const double rc = tot[1] > 0.0 ? sqrt(tot[0] / tot[1]) : __builtin_nan("");
+    double* h = job->hist + 3 * job->i0;
+    __hip_atomic_store(h + 0, gam, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(h + 1, rc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(h + 2, tot[2] + coef * tot[3], __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// ------------------------------------------------------------------ fill --
+// v[0] (image space, may be null) and v[1] (gradient space, may be null) <- p0.
+template <typename T>
+__global__ void __launch_bounds__(NTHREADS) k_fill(const Job* __restrict__ jobs,
+                                                   const uint32_t* __restrict__ tiles) {
+  const Job* job; int ti, tj, tix;
+  decode_tile(jobs, tiles, job, ti, tj, tix);
+  const int m = job->m;
+  int i0, j0, TI, TJ;
+  tile_geom<T>(m, ti, tj, i0, j0, TI, TJ);
+  T* a = vp<T>(job, 0);
+  T* q = vp<T>(job, 1);
+  const T val = (T)job->p0;
+  const size_t nx = (size_t)(m - 1) * m;
+  for (int o = threadIdx.x; o < TI * TJ; o += NTHREADS) {
+    const int gi = i0 + o % TI, gj = j0 + o / TI;
+    const size_t g = gi + (size_t)gj * m;
+    if (a) a[g] = val;
+    if (q) {
+      if (gi < m - 1) q[gi + (size_t)gj * (m - 1)] = val;
+      if (gj < m - 1) q[nx + g] = val;
+    }
+  }
+}
+
+// -------------------------------------------------------------- launchers --
+
+template <typename T, template <typename, int, bool> class K>
+struct Dummy {};
+
+#define DISPATCH_STENCIL(KERNEL, T, la, sep, rb, H, extra_lds)                           \
+  do {                                                                                 \
+    const int TS_ = TileCfg<T>::TS;                                                    \
+    const int ts_ = (la).m_max < TS_ ? (la).m_max : TS_;                               \
+    if (sep) {                                                                         \
+      const size_t lds_ = sizeof(T) * sep_lds_elems(ts_, ts_, rb);                     \
+      switch (rb) {                                                                    \
+        case 2: hipLaunchKernelGGL((KERNEL<T, 2, true>), dim3((la).ntiles),           \
+                    dim3(NTHREADS), lds_, (la).stream, (la).jobs, (la).tiles); break;  \
+        case 4: hipLaunchKernelGGL((KERNEL<T, 4, true>), dim3((la).ntiles),           \
+                    dim3(NTHREADS), lds_, (la).stream, (la).jobs, (la).tiles); break;  \
+        case 8: hipLaunchKernelGGL((KERNEL<T, 8, true>), dim3((la).ntiles),           \
+                    dim3(NTHREADS), lds_, (la).stream, (la).jobs, (la).tiles); break;  \
+        case 12: hipLaunchKernelGGL((KERNEL<T, 12, true>), dim3((la).ntiles),         \
+                    dim3(NTHREADS), lds_, (la).stream, (la).jobs, (la).tiles); break;  \
+        case 16: hipLaunchKernelGGL((KERNEL<T, 16, true>), dim3((la).ntiles),         \
+                    dim3(NTHREADS), lds_, (la).stream, (la).jobs, (la).tiles); break;  \
+        default: return hipErrorInvalidValue;                                          \
+      }                                                                                \
+    } else {                                                                           \
+      const size_t lds_ = sizeof(T) * col_lds_elems(ts_, ts_, H) +                     \
+                          (sizeof(T) + sizeof(short2)) * (2 * (H) + 1) * (2 * (H) + 1);\
+      hipLaunchKernelGGL((KERNEL<T, 0, false>), dim3((la).ntiles), dim3(NTHREADS),    \
+                         lds_, (la).stream, (la).jobs, (la).tiles);                    \
+    }                                                                                  \
+  } while (0)
+
+hipError_t launch_cgls_p1(const LaunchArgs& la, int precision, int sep, int rb, int H) {
+  if (precision == 1) DISPATCH_STENCIL(k_cgls_p1, double, la, sep, rb, H, 0);
+  else DISPATCH_STENCIL(k_cgls_p1, float, la, sep, rb, H, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_cgls_p2(const LaunchArgs& la, int precision, int sep, int rb, int H) {
+  if (precision == 1) DISPATCH_STENCIL(k_cgls_p2, double, la, sep, rb, H, 0);
+  else DISPATCH_STENCIL(k_cgls_p2, float, la, sep, rb, H, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_stats(const LaunchArgs& la, int precision, int sep, int rb, int H) {
+  if (precision == 1) DISPATCH_STENCIL(k_stats, double, la, sep, rb, H, 0);
+  else DISPATCH_STENCIL(k_stats, float, la, sep, rb, H, 0);
+  return hipGetLastError();
+}
+
+#define SIMPLE_LAUNCHER(NAME, KERNEL)                                                   \
+  hipError_t NAME(const LaunchArgs& la, int precision) {                               \
+    if (precision == 1)                                                                \
+      hipLaunchKernelGGL((KERNEL<double>), dim3(la.ntiles), dim3(NTHREADS), 0,         \
+                         la.stream, la.jobs, la.tiles);                                \
+    else                                                                               \
+      hipLaunchKernelGGL((KERNEL<float>), dim3(la.ntiles), dim3(NTHREADS), 0,          \
+                         la.stream, la.jobs, la.tiles);                                \
+    return hipGetLastError();                                                          \
+  }
+
+SIMPLE_LAUNCHER(launch_cgls_init, k_cgls_init)
+SIMPLE_LAUNCHER(launch_aux, k_aux)
+SIMPLE_LAUNCHER(launch_fill, k_fill)
+
+}  // namespace dbl

@@ -1,0 +1,64 @@
+// Host-side launch interface of the device kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include "common.h"
+
+namespace dbl {
+
+struct LaunchArgs {
+  const Job* jobs;       // device array of jobs
+  const uint32_t* tiles; // device tile table
+  int ntiles;            // blocks in the launch
+  int m_max;             // largest grid among the jobs (sizes LDS)
+  hipStream_t stream;
+};
+
+// Vector slots of CGLS / solver jobs (Job::v indices).
+enum VSlot : int {
+  V_X = 0,   // CGLS iterate
+  V_PA,      // search direction, read buffer
+  V_PB,      // search direction, write buffer
+  V_S,       // A^ T r
+  V_R1A, V_R1B,  // image-space residual, read / write buffers
+  V_Q1,      // A p
+  V_R2A, V_R2B,  // gradient-space residual, read / write buffers
+  V_Q2,      // sqrt(gamma) D p
+  V_W,       // IRLS weights (n_L)
+  V_B,       // right-hand side b (n)
+  V_C1, V_C2,// shift c = C1 - C2 (SB: d - g), c = C1 (MM)
+  V_XOLD,    // previous outer iterate
+  V_X0       // optional CGLS start
+};
+
+hipError_t launch_apply_A(const LaunchArgs& la, int precision, int sep, int rb, int H);
+hipError_t launch_grad(const LaunchArgs& la, int precision);
+hipError_t launch_gradT(const LaunchArgs& la, int precision);
+hipError_t launch_dwt_fwd(const LaunchArgs& la, int precision);
+hipError_t launch_dwt_inv(const LaunchArgs& la, int precision);
+hipError_t launch_dtransfer(const LaunchArgs& la, int precision);
+
+// CGLS phases (kernels_solve.hip)
+hipError_t launch_cgls_init(const LaunchArgs& la, int precision);
+hipError_t launch_cgls_p1(const LaunchArgs& la, int precision, int sep, int rb, int H);
+hipError_t launch_cgls_p2(const LaunchArgs& la, int precision, int sep, int rb, int H);
+hipError_t launch_aux(const LaunchArgs& la, int precision);
+hipError_t launch_stats(const LaunchArgs& la, int precision, int sep, int rb, int H);
+hipError_t launch_fill(const LaunchArgs& la, int precision);
+
+// aux modes (Job::i0)
+enum AuxMode : int {
+  AUX_IRLS_W = 0,   // v[V_W] = max(|Lx|, eps)^(-1/2)      from v[V_X]
+  AUX_MM_W = 1,     // v[V_C1] = u (1 - (eps^2/(u^2+eps^2))^(1/2)), u = L x
+  AUX_SB_INIT = 2,  // d = shrink(Lx, tau), g = Lx - d      (v[V_C1] = d, v[V_C2] = g)
+  AUX_SB_UPDATE = 3 // d = shrink(Lx + g, tau), g += Lx - d
+};
+
+// GCV (kernels_gcv.hip)
+hipError_t launch_gcv_prep(const LaunchArgs& la, int precision);
+hipError_t launch_gemm64(const LaunchArgs& la);
+hipError_t launch_gcv_symbol(const LaunchArgs& la);
+hipError_t launch_gcv_data(const LaunchArgs& la);
+hipError_t launch_gcv_grid(const LaunchArgs& la, int ngroups);
+hipError_t launch_gcv_brent(const LaunchArgs& la);
+
+}  // namespace dbl

@@ -1,0 +1,723 @@
+// Runtime: device memory, job staging, operator upload and the V-cycle
+// engine (Alg. 4 with the outer solvers of Algs. 1-3).
+#include "runtime.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <stdexcept>
+
+namespace dbl {
+
+int set_err(dbl_ctx* ctx, int code, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  return code;
+}
+
+int hip_check(dbl_ctx* ctx, hipError_t e, const char* what) {
+  if (e == hipSuccess) return DBL_OK;
+  return set_err(ctx, DBL_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int dmalloc(dbl_ctx* ctx, size_t bytes, void** p) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 256;
+  if (ctx->budget && ctx->used + bytes > ctx->budget)
+    return set_err(ctx, DBL_ENOMEM, "device workspace budget exceeded");
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return set_err(ctx, DBL_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  }
+  ctx->allocs[*p] = bytes;
+  ctx->used += bytes;
+  return DBL_OK;
+}
+
+void dfree(dbl_ctx* ctx, void* p) {
+  if (!p) return;
+  auto it = ctx->allocs.find(p);
+  if (it != ctx->allocs.end()) {
+    ctx->used -= it->second;
+    ctx->allocs.erase(it);
+  }
+  (void)hipFree(p);
+}
+
+// Copy `bytes` to the device through the staging ring; the copy is queued on
+// the context stream.  A region is only reused after a full stream sync.
+int stage(dbl_ctx* ctx, const void* src, size_t bytes, void** dptr) {
+  const size_t need = (bytes + 255) & ~size_t(255);
+  if (ctx->stage_off + need > ctx->stage_cap) {
+    int rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "stage sync");
+    if (rc) return rc;
+    ctx->stage_off = 0;
+    if (need > ctx->stage_cap) {
+      size_t cap = std::max(need, ctx->stage_cap * 2);
+      if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
+      if (ctx->d_stage) dfree(ctx, ctx->d_stage);
+      ctx->h_stage = nullptr;
+      ctx->d_stage = nullptr;
+      ctx->stage_cap = 0;
+      rc = hip_check(ctx, hipHostMalloc((void**)&ctx->h_stage, cap, hipHostMallocDefault),
+                     "hipHostMalloc");
+      if (rc) return rc;
+      rc = dmalloc(ctx, cap, (void**)&ctx->d_stage);
+      if (rc) return rc;
+      ctx->stage_cap = cap;
+    }
+  }
+  std::memcpy(ctx->h_stage + ctx->stage_off, src, bytes);
+  int rc = hip_check(ctx,
+                     hipMemcpyAsync(ctx->d_stage + ctx->stage_off, ctx->h_stage + ctx->stage_off,
+                                    bytes, hipMemcpyHostToDevice, ctx->stream),
+                     "stage copy");
+  if (rc) return rc;
+  *dptr = ctx->d_stage + ctx->stage_off;
+  ctx->stage_off += need;
+  return DBL_OK;
+}
+
+int tiles_per_axis(int grid_m, int esz) {
+  const int ts = esz == 8 ? 32 : 64;
+  return grid_m < ts ? 1 : grid_m / ts;
+}
+
+void Launch::add(const Job& j0, int grid_m, int esz) {
+  Job j = j0;
+  j.nti = j.ntj = tiles_per_axis(grid_m, esz);
+  const uint32_t idx = (uint32_t)jobs.size();
+  jobs.push_back(j);
+  for (int t = 0; t < j.nti * j.ntj; ++t) tiles.push_back((idx << 16) | (uint32_t)t);
+  tiles_upto.push_back((int)tiles.size());
+  m_max = std::max(m_max, j.m);
+}
+
+int Launch::upload(dbl_ctx* ctx, LaunchArgs& la) {
+  void *dj = nullptr, *dt = nullptr;
+  int rc = stage(ctx, jobs.data(), jobs.size() * sizeof(Job), &dj);
+  if (rc) return rc;
+  rc = stage(ctx, tiles.data(), tiles.size() * sizeof(uint32_t), &dt);
+  if (rc) return rc;
+  la.jobs = static_cast<const Job*>(dj);
+  la.tiles = static_cast<const uint32_t*>(dt);
+  la.ntiles = (int)tiles.size();
+  la.m_max = m_max;
+  la.stream = ctx->stream;
+  return DBL_OK;
+}
+
+// ----------------------------------------------------------- operators ----
+
+static int upload_vec(dbl_ctx* ctx, dbl_op* op, const void* src, size_t bytes, void** d) {
+  int rc = dmalloc(ctx, bytes, d);
+  if (rc) return rc;
+  op->bufs.push_back(*d);
+  return hip_check(ctx, hipMemcpy(*d, src, bytes, hipMemcpyHostToDevice), "upload table");
+}
+
+static int upload_t1(dbl_ctx* ctx, dbl_op* op, const Table1DHost& h, Table1D& d) {
+  d.R = h.R;
+  d.St = h.St;
+  d.Sb = h.Sb;
+  d.rows = h.rows;
+  std::vector<float> f(h.taps.begin(), h.taps.end());
+  void *pf, *pd;
+  int rc = upload_vec(ctx, op, f.data(), f.size() * 4, &pf);
+  if (rc) return rc;
+  rc = upload_vec(ctx, op, h.taps.data(), h.taps.size() * 8, &pd);
+  d.tf = static_cast<const float*>(pf);
+  d.td = static_cast<const double*>(pd);
+  return rc;
+}
+
+static int upload_t2(dbl_ctx* ctx, dbl_op* op, const Table2DHost& h, Table2D& d) {
+  d.R0 = h.R0;
+  d.R1 = h.R1;
+  d.St0 = h.St0;
+  d.Sb0 = h.Sb0;
+  d.St1 = h.St1;
+  d.Sb1 = h.Sb1;
+  d.rows0 = h.rows0;
+  d.rows1 = h.rows1;
+  std::vector<short2> e(h.val.size());
+  for (size_t k = 0; k < e.size(); ++k) e[k] = make_short2(h.e0[k], h.e1[k]);
+  std::vector<float> f(h.val.begin(), h.val.end());
+  void *po, *pe, *pf, *pd;
+  int rc = upload_vec(ctx, op, h.off.data(), h.off.size() * 4, &po);
+  if (!rc) rc = upload_vec(ctx, op, e.data(), std::max<size_t>(1, e.size()) * 4, &pe);
+  if (!rc) rc = upload_vec(ctx, op, f.data(), std::max<size_t>(1, f.size()) * 4, &pf);
+  if (!rc) rc = upload_vec(ctx, op, h.val.data(), std::max<size_t>(1, h.val.size()) * 8, &pd);
+  if (rc) return rc;
+  d.off = static_cast<const int*>(po);
+  d.e = static_cast<const short2*>(pe);
+  d.vf = static_cast<const float*>(pf);
+  d.vd = static_cast<const double*>(pd);
+  return DBL_OK;
+}
+
+void op_free(dbl_op* op) {
+  if (!op) return;
+  for (void* p : op->bufs) dfree(op->ctx, p);
+  for (double* p : op->sym) dfree(op->ctx, p);
+  if (op->d_ops) dfree(op->ctx, op->d_ops);
+  delete op;
+}
+
+int op_build(dbl_ctx* ctx, const double* psf, int ph, int pw, int m, int levels, int wavelet,
+             int precision, dbl_op** out) {
+  *out = nullptr;
+  dbl_op* op = new dbl_op();
+  op->ctx = ctx;
+  op->m = m;
+  op->levels = levels;
+  op->wavelet = wavelet;
+  op->precision = precision;
+  try {
+    build_hierarchy(psf, ph, pw, m, levels, wavelet, op->host);
+  } catch (const std::exception& ex) {
+    delete op;
+    return set_err(ctx, DBL_ENOTSUP, std::string("hierarchy: ") + ex.what());
+  }
+  op->sep = op->host.sep;
+  std::vector<LevelOp> lv(levels);
+  int rc = DBL_OK;
+  for (int i = 0; i < levels && !rc; ++i) {
+    const LevelHost& L = op->host.levels[i];
+    LevelOp& d = lv[i];
+    std::memset(&d, 0, sizeof(d));
+    d.m = L.m;
+    d.sep = L.sep ? 1 : 0;
+    d.rb = L.rb;
+    d.R = L.sep ? L.rb : L.R;
+    if (L.sep) {
+      rc = upload_t1(ctx, op, L.f0, d.f0);
+      if (!rc) rc = upload_t1(ctx, op, L.f1, d.f1);
+      if (!rc) rc = upload_t1(ctx, op, L.a0, d.a0);
+      if (!rc) rc = upload_t1(ctx, op, L.a1, d.a1);
+    } else {
+      rc = upload_t2(ctx, op, L.f2, d.f2);
+      if (!rc) rc = upload_t2(ctx, op, L.a2, d.a2);
+    }
+  }
+  if (!rc) rc = dmalloc(ctx, sizeof(LevelOp) * levels, (void**)&op->d_ops);
+  if (!rc)
+    rc = hip_check(ctx, hipMemcpy(op->d_ops, lv.data(), sizeof(LevelOp) * levels,
+                                  hipMemcpyHostToDevice),
+                   "upload level ops");
+  op->sym.assign(levels, nullptr);
+  if (rc) {
+    op_free(op);
+    return rc;
+  }
+  *out = op;
+  return DBL_OK;
+}
+
+// --------------------------------------------------------------- slots ----
+
+static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+static bool wants_gcv(const dbl_opts& o) { return !o.mu_schedule && !(o.mu_fixed > 0.0); }
+
+size_t slot_bytes(const dbl_request& req) {
+  const size_t esz = req.opts.precision == DBL_F64 ? 8 : 4;
+  const size_t n = (size_t)req.m * req.m, nl = 2 * (size_t)req.m * (req.m - 1);
+  size_t b = 0;
+  b += 8 * align256(n * esz);
+  b += 6 * align256(nl * esz);
+  for (int i = 1; i < req.levels; ++i) b += align256(((size_t)req.m >> i) * (req.m >> i) * esz);
+  const int nt = tiles_per_axis(req.m, (int)esz);
+  b += align256(NSCAL * 8) + align256((size_t)nt * nt * 32 * 8) + 256;
+  b += align256((size_t)req.levels * DBL_MAX_KOUT * 3 * 8);
+  if (wants_gcv(req.opts)) b += 4 * align256(n * 8);
+  return b;
+}
+
+int slot_init(dbl_ctx* ctx, const dbl_request& req, Slot* s) {
+  s->req = req;
+  s->opts = req.opts;
+  s->prec = req.opts.precision;
+  s->esz = s->prec == DBL_F64 ? 8 : 4;
+  s->m = req.m;
+  s->levels = req.levels;
+  s->solver = req.solver;
+  s->wavelet = req.wavelet;
+  s->transfer = req.transfer;
+  s->n0 = req.m * req.m;
+  s->nl0 = 2 * req.m * (req.m - 1);
+  s->gcv = wants_gcv(req.opts);
+  const int K = req.opts.k_out;
+  if (!s->gcv) {
+    s->mu.assign((size_t)req.levels * K, req.opts.mu_fixed);
+    if (req.opts.mu_schedule)
+      for (size_t i = 0; i < s->mu.size(); ++i) s->mu[i] = req.opts.mu_schedule[i];
+  }
+  int rc = op_build(ctx, req.psf, req.ph, req.pw, req.m, req.levels, req.wavelet, s->prec, &s->op);
+  if (rc) return rc;
+  const size_t bytes = slot_bytes(req);
+  rc = dmalloc(ctx, bytes, &s->block);
+  if (rc) {
+    op_free(s->op);
+    s->op = nullptr;
+    return rc;
+  }
+  char* p = static_cast<char*>(s->block);
+  auto take = [&](size_t b) {
+    void* r = p;
+    p += align256(b);
+    return r;
+  };
+  const size_t n = s->n0, nl = s->nl0, e = s->esz;
+  s->X[0] = take(n * e);
+  s->X[1] = take(n * e);
+  s->P[0] = take(n * e);
+  s->P[1] = take(n * e);
+  s->S = take(n * e);
+  s->R1[0] = take(n * e);
+  s->R1[1] = take(n * e);
+  s->Q1 = take(n * e);
+  s->R2[0] = take(nl * e);
+  s->R2[1] = take(nl * e);
+  s->Q2 = take(nl * e);
+  s->W = take(nl * e);
+  s->C1 = take(nl * e);
+  s->C2 = take(nl * e);
+  s->B.assign(req.levels, nullptr);
+  s->B[0] = req.b;
+  for (int i = 1; i < req.levels; ++i) s->B[i] = take(((size_t)req.m >> i) * (req.m >> i) * e);
+  const int nt = tiles_per_axis(req.m, (int)e);
+  s->scal = static_cast<double*>(take(NSCAL * 8));
+  s->part = static_cast<double*>(take((size_t)nt * nt * 32 * 8));
+  s->cnt = static_cast<unsigned*>(take(256));
+  s->hist = static_cast<double*>(take((size_t)req.levels * DBL_MAX_KOUT * 3 * 8));
+  if (s->gcv) {
+    s->g_bh = static_cast<double*>(take(n * 8));
+    s->g_e = static_cast<double*>(take(n * 8));
+    s->g_tmp = static_cast<double*>(take(n * 8));
+    s->g_in = static_cast<double*>(take(n * 8));
+  }
+  rc = hip_check(ctx, hipMemsetAsync(s->cnt, 0, 256, ctx->stream), "clear counters");
+  if (!rc) rc = hip_check(ctx, hipMemsetAsync(s->scal, 0, NSCAL * 8, ctx->stream), "clear scalars");
+  if (!rc)
+    rc = hip_check(ctx, hipMemsetAsync(s->hist, 0xff, (size_t)req.levels * DBL_MAX_KOUT * 3 * 8,
+                                       ctx->stream),
+                   "clear history");
+  s->level = req.levels - 1;
+  s->k = 0;
+  s->cur = 0;
+  s->started = false;
+  s->done = false;
+  return rc;
+}
+
+void slot_free(dbl_ctx* ctx, Slot* s) {
+  if (s->block) dfree(ctx, s->block);
+  s->block = nullptr;
+  if (s->op) op_free(s->op);
+  s->op = nullptr;
+}
+
+int slot_report(dbl_ctx* ctx, Slot* s, dbl_report* rep) {
+  if (!rep) return DBL_OK;
+  std::vector<double> h((size_t)s->levels * DBL_MAX_KOUT * 3);
+  int rc = hip_check(ctx, hipMemcpyAsync(h.data(), s->hist, h.size() * 8, hipMemcpyDeviceToHost,
+                                         ctx->stream),
+                     "read history");
+  if (!rc) rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "sync");
+  if (rc) return rc;
+  rep->levels = s->levels;
+  rep->k_out = s->opts.k_out;
+  for (int i = 0; i < DBL_MAX_LEVELS; ++i) rep->sizes[i] = i < s->levels ? (s->m >> i) : 0;
+  for (int i = 0; i < s->levels; ++i)
+    for (int k = 0; k < s->opts.k_out; ++k) {
+      const double* e = &h[((size_t)i * DBL_MAX_KOUT + k) * 3];
+      rep->gamma[i][k] = e[0];
+      rep->rc[i][k] = e[1];
+      rep->objective[i][k] = e[2];
+    }
+  rep->status = s->status;
+  return DBL_OK;
+}
+
+// -------------------------------------------------------------- engine ----
+
+namespace {
+
+struct GroupKey {
+  int prec, sep, rb, H;
+  bool operator<(const GroupKey& o) const {
+    if (prec != o.prec) return prec < o.prec;
+    if (sep != o.sep) return sep < o.sep;
+    if (rb != o.rb) return rb < o.rb;
+    return H < o.H;
+  }
+};
+
+Job base_job(const Slot* s, int level) {
+  Job j;
+  std::memset(&j, 0, sizeof(j));
+  j.m = s->m >> level;
+  j.op = s->op->d_ops + level;
+  j.scal = s->scal;
+  j.part = s->part;
+  j.cnt = s->cnt;
+  j.hist = s->hist;
+  return j;
+}
+
+GroupKey key_of(const Slot* s, int level) {
+  const LevelHost& L = s->op->host.levels[level];
+  return GroupKey{s->prec, L.sep ? 1 : 0, L.sep ? L.rb : 0, L.sep ? L.rb : L.R};
+}
+
+int solver_flags(const Slot* s) {
+  if (s->solver == DBL_IRLS) return F_IRLS;
+  if (s->solver == DBL_MM) return F_SHIFT | F_MM;
+  return F_SHIFT | F_SB;
+}
+
+// Launch helpers: one launch per precision for simple kernels.
+using SimpleFn = hipError_t (*)(const LaunchArgs&, int);
+
+int run_simple(dbl_ctx* ctx, SimpleFn fn, std::map<int, Launch>& byprec, const char* what) {
+  for (auto& kv : byprec) {
+    if (kv.second.empty()) continue;
+    LaunchArgs la;
+    int rc = kv.second.upload(ctx, la);
+    if (rc) return rc;
+    rc = hip_check(ctx, fn(la, kv.first), what);
+    if (rc) return rc;
+  }
+  return DBL_OK;
+}
+
+void add_fill(std::map<int, Launch>& L, const Slot* s, int level, void* img, void* grad,
+              double val) {
+  Job j = base_job(s, level);
+  j.v[0] = img;
+  j.v[1] = grad;
+  j.p0 = val;
+  L[s->prec].add(j, j.m, (int)s->esz);
+}
+
+void add_aux(std::map<int, Launch>& L, const Slot* s, int level, int mode, const void* x,
+             void* w, void* c1, void* c2) {
+  Job j = base_job(s, level);
+  j.i0 = mode;
+  j.p0 = s->opts.eps;
+  j.p1 = s->opts.tau;
+  j.v[V_X] = const_cast<void*>(x);
+  j.v[V_W] = w;
+  j.v[V_C1] = c1;
+  j.v[V_C2] = c2;
+  L[s->prec].add(j, j.m, (int)s->esz);
+}
+
+}  // namespace
+
+int engine_step(dbl_ctx* ctx, std::vector<Slot*>& slots) {
+  int rc = DBL_OK;
+  std::vector<Slot*> act;
+  for (Slot* s : slots)
+    if (!s->done && !s->status) act.push_back(s);
+  if (act.empty()) return DBL_OK;
+
+  // ---- A. entering a level ------------------------------------------------
+  {
+    // restriction of b down the hierarchy (first step only), by depth
+    int maxdepth = 0;
+    for (Slot* s : act)
+      if (!s->started) maxdepth = std::max(maxdepth, s->levels - 1);
+    for (int d = 1; d <= maxdepth; ++d) {
+      std::map<int, Launch> L;
+      for (Slot* s : act) {
+        if (s->started || d > s->levels - 1) continue;
+        Job j = base_job(s, d - 1);
+        j.m = s->m >> (d - 1);  // fine size
+        j.flags = s->wavelet;
+        j.v[0] = const_cast<void*>(s->B[d - 1]);
+        j.v[1] = const_cast<void*>(s->B[d]);
+        j.p0 = 0.0;
+        L[s->prec].add(j, j.m >> 1, (int)s->esz);
+      }
+      if ((rc = run_simple(ctx, launch_dwt_fwd, L, "restrict b"))) return rc;
+    }
+    std::map<int, Launch> fillL, prolL, auxL, finL, xferL;
+    std::vector<Slot*> dslots;
+    for (Slot* s : act) {
+      if (s->k != 0) continue;
+      const int lv = s->level;
+      if (!s->started) {
+        // Approach I start at the coarsest grid (Sec. 4.1)
+        add_fill(fillL, s, lv, s->X[s->cur], nullptr, 0.0);
+        if (s->solver == DBL_IRLS) add_fill(fillL, s, lv, nullptr, s->W, 1.0);
+        if (s->solver == DBL_MM) add_fill(fillL, s, lv, nullptr, s->C1, 0.0);
+        if (s->solver == DBL_SB) {
+          add_fill(fillL, s, lv, nullptr, s->C1, 0.0);
+          add_fill(fillL, s, lv, nullptr, s->C2, 0.0);
+        }
+      } else if (s->transfer == DBL_XFER_X) {
+        // X^(i) = W1 X^(i+1) W1^T, then auxiliaries from it
+        Job j = base_job(s, lv);
+        j.flags = s->wavelet;
+        j.v[0] = s->X[s->cur];
+        j.v[1] = s->X[1 - s->cur];
+        j.p0 = 0.0;
+        prolL[s->prec].add(j, j.m, (int)s->esz);
+      } else {
+        // coarse auxiliary state from the completed coarse solve
+        if (s->solver == DBL_IRLS)
+          add_aux(finL, s, lv + 1, AUX_IRLS_W, s->X[s->cur], s->W, nullptr, nullptr);
+        if (s->solver == DBL_MM)
+          add_aux(finL, s, lv + 1, AUX_MM_W, s->X[s->cur], nullptr, s->C1, nullptr);
+        dslots.push_back(s);
+      }
+    }
+    if ((rc = run_simple(ctx, launch_fill, fillL, "approach I start"))) return rc;
+    if ((rc = run_simple(ctx, launch_dwt_inv, prolL, "prolong"))) return rc;
+    if ((rc = run_simple(ctx, launch_aux, finL, "coarse aux"))) return rc;
+    for (Slot* s : act) {
+      if (s->k != 0 || !s->started || s->transfer != DBL_XFER_X) continue;
+      s->cur = 1 - s->cur;
+      const int lv = s->level;
+      if (s->solver == DBL_IRLS) add_aux(auxL, s, lv, AUX_IRLS_W, s->X[s->cur], s->W, nullptr, nullptr);
+      if (s->solver == DBL_MM) add_aux(auxL, s, lv, AUX_MM_W, s->X[s->cur], nullptr, s->C1, nullptr);
+      if (s->solver == DBL_SB) add_aux(auxL, s, lv, AUX_SB_INIT, s->X[s->cur], nullptr, s->C1, s->C2);
+    }
+    // Approach D: block transfer of the auxiliaries, then start from x = 0
+    std::map<int, Launch> fillD;
+    for (Slot* s : dslots) {
+      const int lv = s->level;
+      auto add_x = [&](void* src, void* dst) {
+        Job j = base_job(s, lv);
+        j.flags = s->wavelet;
+        j.v[0] = src;
+        j.v[1] = dst;
+        xferL[s->prec].add(j, j.m, (int)s->esz);
+      };
+      if (s->solver == DBL_IRLS) add_x(s->W, s->R2[0]);
+      if (s->solver == DBL_MM) add_x(s->C1, s->R2[0]);
+      if (s->solver == DBL_SB) {
+        add_x(s->C1, s->R2[0]);
+        add_x(s->C2, s->R2[1]);
+      }
+      add_fill(fillD, s, lv, s->X[s->cur], nullptr, 0.0);
+    }
+    if ((rc = run_simple(ctx, launch_dtransfer, xferL, "approach D transfer"))) return rc;
+    for (Slot* s : dslots) {
+      if (s->solver == DBL_IRLS) std::swap(s->W, s->R2[0]);
+      if (s->solver == DBL_MM) std::swap(s->C1, s->R2[0]);
+      if (s->solver == DBL_SB) {
+        std::swap(s->C1, s->R2[0]);
+        std::swap(s->C2, s->R2[1]);
+      }
+    }
+    if ((rc = run_simple(ctx, launch_fill, fillD, "approach D start"))) return rc;
+    if ((rc = run_simple(ctx, launch_aux, auxL, "approach X auxiliaries"))) return rc;
+    for (Slot* s : act) s->started = true;
+  }
+
+  // ---- B. auxiliaries from the current iterate (Algs. 1, 2) --------------
+  {
+    std::map<int, Launch> L;
+    for (Slot* s : act) {
+      if (s->k == 0) continue;
+      if (s->solver == DBL_IRLS) add_aux(L, s, s->level, AUX_IRLS_W, s->X[s->cur], s->W, nullptr, nullptr);
+      if (s->solver == DBL_MM) add_aux(L, s, s->level, AUX_MM_W, s->X[s->cur], nullptr, s->C1, nullptr);
+    }
+    if ((rc = run_simple(ctx, launch_aux, L, "outer auxiliaries"))) return rc;
+  }
+
+  // ---- C. the parameter gamma ----------------------------------------------
+  {
+    std::vector<GcvReq> greqs;
+    for (Slot* s : act) {
+      if (!s->gcv) {
+        const double g = s->mu[(size_t)s->level * s->opts.k_out + s->k];
+        const double gv[2] = {g, std::sqrt(g)};
+        void* d = nullptr;
+        if ((rc = stage(ctx, gv, sizeof(gv), &d))) return rc;
+        if ((rc = hip_check(ctx, hipMemcpyAsync(s->scal + S_GAMMA, d, sizeof(gv),
+                                                 hipMemcpyDeviceToDevice, ctx->stream),
+                            "set gamma")))
+          return rc;
+        continue;
+      }
+      // GCV schedule (Sec. 3): MM / SB at k = 0, 1, 2; IRLS every k with at
+      // most two grids, else two passes (unweighted at k = 0, weighted at k = 3).
+      int which = 0;  // 0 none, 1 current pair, 2 unweighted pair
+      if (s->solver != DBL_IRLS) which = s->k <= 2 ? 1 : 0;
+      else if (s->levels <= 2) which = 1;
+      else which = s->k == 0 ? 2 : (s->k == 3 ? 1 : 0);
+      if (!which) continue;
+      GcvReq g{};
+      g.op = s->op;
+      g.level = s->level;
+      g.prec = s->prec;
+      g.b = s->B[s->level];
+      g.w = (s->solver == DBL_IRLS && which == 1) ? s->W : nullptr;
+      g.c1 = s->solver != DBL_IRLS ? s->C1 : nullptr;
+      g.c2 = s->solver == DBL_SB ? s->C2 : nullptr;
+      g.scal = s->scal;
+      g.part = s->part;
+      g.cnt = s->cnt;
+      g.bh = s->g_bh;
+      g.e = s->g_e;
+      g.tmp = s->g_tmp;
+      g.in = s->g_in;
+      g.bh_valid = s->bh_valid;
+      g.grid = s->opts.gcv_grid;
+      const int n = (s->m >> s->level) * (s->m >> s->level);
+      g.mode = s->opts.gcv_mode == DBL_GCV_AUTO ? (n <= 4096 ? DBL_GCV_EXACT : DBL_GCV_SPECTRAL)
+                                                : s->opts.gcv_mode;
+      greqs.push_back(g);
+      s->bh_valid = true;
+    }
+    if (!greqs.empty() && (rc = gcv_run(ctx, greqs))) return rc;
+  }
+
+  // ---- D. CGLS on the augmented system -------------------------------------
+  {
+    // order slots by decreasing k_in so every iteration launches a prefix
+    std::vector<Slot*> ord = act;
+    std::stable_sort(ord.begin(), ord.end(),
+                     [](const Slot* a, const Slot* b) { return a->opts.k_in > b->opts.k_in; });
+    std::map<int, Launch> initL;
+    std::map<GroupKey, Launch> first, p1[2], p2[2];
+    std::map<GroupKey, std::vector<int>> kin;
+    for (Slot* s : ord) {
+      const int lv = s->level;
+      const int nw = 1 - s->cur;
+      Job j = base_job(s, lv);
+      j.flags = solver_flags(s);
+      j.v[V_X] = s->X[nw];
+      j.v[V_S] = s->S;
+      j.v[V_Q1] = s->Q1;
+      j.v[V_Q2] = s->Q2;
+      j.v[V_W] = s->W;
+      j.v[V_B] = const_cast<void*>(s->B[lv]);
+      j.v[V_C1] = s->C1;
+      j.v[V_C2] = s->C2;
+      Job ji = j;
+      ji.v[V_PA] = s->P[0];
+      ji.v[V_R1A] = s->R1[0];
+      ji.v[V_R2A] = s->R2[0];
+      initL[s->prec].add(ji, ji.m, (int)s->esz);
+      const GroupKey gk = key_of(s, lv);
+      Job jf = j;
+      jf.flags |= F_FIRST;
+      jf.v[V_R1A] = s->R1[0];
+      jf.v[V_R1B] = s->R1[1];
+      jf.v[V_R2A] = s->R2[0];
+      jf.v[V_R2B] = s->R2[1];
+      first[gk].add(jf, jf.m, (int)s->esz);
+      for (int par = 0; par < 2; ++par) {
+        Job a = j;
+        a.v[V_PA] = s->P[par];
+        a.v[V_PB] = s->P[1 - par];
+        p1[par][gk].add(a, a.m, (int)s->esz);
+        Job b = j;
+        b.v[V_PB] = s->P[1 - par];
+        b.v[V_R1A] = s->R1[1 - par];
+        b.v[V_R1B] = s->R1[par];
+        b.v[V_R2A] = s->R2[1 - par];
+        b.v[V_R2B] = s->R2[par];
+        p2[par][gk].add(b, b.m, (int)s->esz);
+      }
+      kin[gk].push_back(s->opts.k_in);
+    }
+    if ((rc = run_simple(ctx, launch_cgls_init, initL, "cgls init"))) return rc;
+    std::map<GroupKey, LaunchArgs> aF, a1[2], a2[2];
+    for (auto& kv : first) {
+      const GroupKey& g = kv.first;
+      if ((rc = kv.second.upload(ctx, aF[g]))) return rc;
+      for (int par = 0; par < 2; ++par) {
+        if ((rc = p1[par][g].upload(ctx, a1[par][g]))) return rc;
+        if ((rc = p2[par][g].upload(ctx, a2[par][g]))) return rc;
+      }
+    }
+    for (auto& kv : aF) {
+      const GroupKey& g = kv.first;
+      if ((rc = hip_check(ctx, launch_cgls_p2(kv.second, g.prec, g.sep, g.rb, g.H), "cgls p2")))
+        return rc;
+    }
+    int kmax = 0;
+    for (Slot* s : ord) kmax = std::max(kmax, s->opts.k_in);
+    for (int it = 0; it < kmax; ++it) {
+      const int par = it & 1;
+      for (auto& kv : kin) {
+        const GroupKey& g = kv.first;
+        const std::vector<int>& ks = kv.second;
+        int q = 0;
+        while (q < (int)ks.size() && ks[q] > it) ++q;
+        if (!q) continue;
+        LaunchArgs la = a1[par][g];
+        la.ntiles = p1[par][g].tiles_upto[q - 1];
+        if ((rc = hip_check(ctx, launch_cgls_p1(la, g.prec, g.sep, g.rb, g.H), "cgls p1")))
+          return rc;
+      }
+      for (auto& kv : kin) {
+        const GroupKey& g = kv.first;
+        const std::vector<int>& ks = kv.second;
+        int q = 0;
+        while (q < (int)ks.size() && ks[q] > it) ++q;
+        if (!q) continue;
+        LaunchArgs la = a2[par][g];
+        la.ntiles = p2[par][g].tiles_upto[q - 1];
+        if ((rc = hip_check(ctx, launch_cgls_p2(la, g.prec, g.sep, g.rb, g.H), "cgls p2")))
+          return rc;
+      }
+    }
+  }
+
+  // ---- E. Split Bregman update (Alg. 3) and statistics ----------------------
+  {
+    std::map<int, Launch> L;
+    for (Slot* s : act)
+      if (s->solver == DBL_SB)
+        add_aux(L, s, s->level, AUX_SB_UPDATE, s->X[1 - s->cur], nullptr, s->C1, s->C2);
+    if ((rc = run_simple(ctx, launch_aux, L, "split Bregman update"))) return rc;
+    std::map<GroupKey, Launch> S;
+    for (Slot* s : act) {
+      Job j = base_job(s, s->level);
+      j.flags = solver_flags(s);
+      j.v[V_X] = s->X[1 - s->cur];
+      j.v[V_XOLD] = s->X[s->cur];
+      j.v[V_B] = const_cast<void*>(s->B[s->level]);
+      j.p0 = s->opts.eps;
+      j.p1 = s->opts.tau;
+      j.i0 = s->level * DBL_MAX_KOUT + s->k;
+      S[key_of(s, s->level)].add(j, j.m, (int)s->esz);
+    }
+    for (auto& kv : S) {
+      LaunchArgs la;
+      if ((rc = kv.second.upload(ctx, la))) return rc;
+      const GroupKey& g = kv.first;
+      if ((rc = hip_check(ctx, launch_stats(la, g.prec, g.sep, g.rb, g.H), "stats"))) return rc;
+    }
+  }
+
+  // ---- F. advance ------------------------------------------------------------
+  for (Slot* s : act) {
+    s->cur = 1 - s->cur;
+    s->k += 1;
+    if (s->k == s->opts.k_out) {
+      s->k = 0;
+      if (s->level == 0) {
+        s->done = true;
+        rc = hip_check(ctx, hipMemcpyAsync(s->req.x, s->X[s->cur], (size_t)s->n0 * s->esz,
+                                           hipMemcpyDeviceToDevice, ctx->stream),
+                       "copy result");
+        if (rc) return rc;
+      } else {
+        s->level -= 1;
+        s->bh_valid = false;
+      }
+    }
+  }
+  return DBL_OK;
+}
+
+}  // namespace dbl

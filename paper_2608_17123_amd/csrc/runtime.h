@@ -1,0 +1,139 @@
+// Runtime objects behind the C ABI: context, operator hierarchy, solve slots.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <deque>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "host.h"
+
+struct dbl_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  size_t budget = 0;
+  size_t used = 0;
+  std::string err = "no error";
+  std::map<void*, size_t> allocs;
+  // job-table staging ring: pinned host memory mirrored to device memory
+  char* h_stage = nullptr;
+  char* d_stage = nullptr;
+  size_t stage_cap = 0;
+  size_t stage_off = 0;
+  // cached orthonormal DCT-II matrices (FP64, column-major) per grid size
+  std::map<int, double*> dct;
+  // scratch block for single-operator entry points
+  void* scratch = nullptr;
+  size_t scratch_bytes = 0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+struct dbl_op {
+  dbl_ctx* ctx = nullptr;
+  int m = 0, levels = 0, wavelet = 0, precision = 0;
+  bool sep = true;
+  dbl::HierHost host;
+  dbl::LevelOp* d_ops = nullptr;     // device array [levels]
+  std::vector<void*> bufs;           // device table storage
+  std::vector<double*> sym;          // per level GCV symbol a_k (FP64, n_i), lazily built
+};
+
+namespace dbl {
+
+int set_err(dbl_ctx* ctx, int code, const std::string& msg);
+int hip_check(dbl_ctx* ctx, hipError_t e, const char* what);
+int dmalloc(dbl_ctx* ctx, size_t bytes, void** p);
+void dfree(dbl_ctx* ctx, void* p);
+int stage(dbl_ctx* ctx, const void* src, size_t bytes, void** dptr);
+
+// Jobs of one launch plus its tile table.
+struct Launch {
+  std::vector<Job> jobs;
+  std::vector<uint32_t> tiles;
+  std::vector<int> tiles_upto;  // tiles after each job (prefix launches)
+  int m_max = 0;
+  void add(const Job& j, int grid_m, int esz);
+  int upload(dbl_ctx* ctx, LaunchArgs& la);
+  bool empty() const { return jobs.empty(); }
+};
+
+int tiles_per_axis(int grid_m, int esz);
+
+// Build the hierarchy and upload its tables.
+int op_build(dbl_ctx* ctx, const double* psf, int ph, int pw, int m, int levels, int wavelet,
+             int precision, dbl_op** out);
+void op_free(dbl_op* op);
+
+// One V-cycle solve in flight.
+struct Slot {
+  dbl_request req{};
+  dbl_opts opts{};
+  dbl_op* op = nullptr;
+  int prec = 0;
+  size_t esz = 4;
+  int m = 0, levels = 1, solver = 0, wavelet = 0, transfer = 0;
+  int n0 = 0, nl0 = 0;
+  void* block = nullptr;  // single device allocation carved below
+  void* X[2]{};
+  void* P[2]{};
+  void* S = nullptr;
+  void* R1[2]{};
+  void* Q1 = nullptr;
+  void* R2[2]{};
+  void* Q2 = nullptr;
+  void* W = nullptr;
+  void* C1 = nullptr;
+  void* C2 = nullptr;
+  std::vector<const void*> B;  // b per level (B[0] = caller's b)
+  double* scal = nullptr;
+  double* part = nullptr;
+  unsigned* cnt = nullptr;
+  double* hist = nullptr;  // levels * k_out * 3 (gamma, rc, objective)
+  double* g_bh = nullptr;  // GCV: DCT of b (per level, recomputed on entry)
+  double* g_e = nullptr;   // GCV: per-frequency residual numerator
+  double* g_tmp = nullptr; // GCV: GEMM / input staging
+  double* g_in = nullptr;  // GCV: FP64 input staging
+  bool gcv = false;
+  std::vector<double> mu;  // levels * k_out fixed parameters (when !gcv)
+  // progress
+  int level = 0, k = 0, cur = 0;
+  bool started = false, done = false, bh_valid = false;
+  int status = 0;
+  double t_submit = 0.0, t_done = 0.0;
+  int64_t ticket = -1;
+};
+
+int slot_init(dbl_ctx* ctx, const dbl_request& req, Slot* s);
+void slot_free(dbl_ctx* ctx, Slot* s);
+size_t slot_bytes(const dbl_request& req);
+// Advance every slot by one outer iteration (level entry, aux, gamma, CGLS,
+// post-update, statistics).  Slots that finish copy their result out.
+int engine_step(dbl_ctx* ctx, std::vector<Slot*>& slots);
+int slot_report(dbl_ctx* ctx, Slot* s, dbl_report* rep);
+
+// GCV for a set of (slot-like) requests, writes S_GAMMA / S_SQRTG in scal.
+struct GcvReq {
+  const dbl_op* op;
+  int level;
+  int prec;
+  const void* b;     // level data (device, prec)
+  const void* w;     // IRLS weights or null
+  const void* c1;    // shift part 1 or null
+  const void* c2;    // shift part 2 (SB: c = c1 - c2) or null
+  double* scal;
+  double* part;
+  unsigned* cnt;
+  double* bh;        // FP64 n: DCT(b) (computed when !bh_valid)
+  double* e;         // FP64 n
+  double* tmp;       // FP64 n
+  double* in;        // FP64 n
+  bool bh_valid;
+  int grid;
+  int mode;          // resolved: DBL_GCV_SPECTRAL / DBL_GCV_EXACT
+};
+int gcv_run(dbl_ctx* ctx, std::vector<GcvReq>& reqs);
+
+}  // namespace dbl

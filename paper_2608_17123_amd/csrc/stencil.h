@@ -1,0 +1,217 @@
+// Tile-level stencil building blocks for the blur operators A^(i), A^(i)^T.
+//
+// A tile of TI x TJ outputs is computed from an LDS copy of the input with a
+// halo of H pixels on every side, loaded with periodic indexing (the class
+// tables hold zeros wherever a level has no coupling, so wrapped halo values
+// only matter where the periodic wavelet seam really couples the two ends).
+//
+// Separable operators (A^(i) = C1 (x) C0) run two register-blocked passes:
+//   pass A: Z = C0 X along axis 0 for every column of the tile plus halo; a
+//           thread owns one column and V consecutive rows, so each LDS value
+//           is read once per V outputs and the interior taps sit in registers;
+//   pass B: Y = Z C1^T along axis 1; a thread owns one row and V columns.
+// Rows near the seam use their own tap row (wave-uniform address).
+//
+// General (non-separable) operators use per class-pair tap lists; tiles that
+// lie entirely in the interior read the interior list from LDS.
+#pragma once
+#include "common.h"
+
+namespace dbl {
+
+template <typename T> __device__ __forceinline__ const T* taps1(const Table1D& t);
+template <> __device__ __forceinline__ const float* taps1<float>(const Table1D& t) { return t.tf; }
+template <> __device__ __forceinline__ const double* taps1<double>(const Table1D& t) { return t.td; }
+template <typename T> __device__ __forceinline__ const T* taps2(const Table2D& t);
+template <> __device__ __forceinline__ const float* taps2<float>(const Table2D& t) { return t.vf; }
+template <> __device__ __forceinline__ const double* taps2<double>(const Table2D& t) { return t.vd; }
+
+template <typename T> struct TileCfg;
+template <> struct TileCfg<float> { static constexpr int TS = 64; static constexpr int V = 16; };
+template <> struct TileCfg<double> { static constexpr int TS = 32; static constexpr int V = 8; };
+
+// Row-major LDS tile (separable kernels): Xs[r * LX + c], r indexes axis 0
+// (rows, i) and c axis 1 (columns, j), both offset by the halo H.
+__host__ __device__ inline int sep_lx(int TJ, int H) { return TJ + 2 * H + 1; }
+__host__ __device__ inline int sep_lz(int TI) { return TI + 1; }
+// LDS elements needed by the separable path.
+__host__ __device__ inline int sep_lds_elems(int TI, int TJ, int H) {
+  return (TI + 2 * H) * sep_lx(TJ, H) + (TJ + 2 * H) * sep_lz(TI);
+}
+// Column-major LDS tile (general 2-D kernels): Xs[c * LXC + r].
+__host__ __device__ inline int col_lx(int TI, int H) { return TI + 2 * H + 1; }
+__host__ __device__ inline int col_lds_elems(int TI, int TJ, int H) {
+  return (TJ + 2 * H) * col_lx(TI, H);
+}
+
+// Load the (TI+2H) x (TJ+2H) region starting at global (i0-H, j0-H) with
+// periodic wrap.  f(gi) returns the value at flat global index gi.
+template <typename T, bool ROWMAJOR, class F>
+__device__ __forceinline__ void load_tile(T* Xs, int ld, int i0, int j0, int TI, int TJ, int H,
+                                          int m, F f) {
+  const int NR = TI + 2 * H, NC = TJ + 2 * H, tot = NR * NC;
+  const int msk = m - 1;
+  for (int idx = threadIdx.x; idx < tot; idx += NTHREADS) {
+    const int r = idx % NR, c = idx / NR;
+    const int gi = (i0 - H + r) & msk, gj = (j0 - H + c) & msk;
+    const T v = f(gi + gj * m);
+    if (ROWMAJOR) Xs[r * ld + c] = v; else Xs[c * ld + r] = v;
+  }
+}
+
+// Separable two-pass tile convolution.  Tables padded to radius RB (2RB+1
+// taps per row), RB <= H.  epi(i_local, j_local, value) consumes outputs;
+// every thread calls it for the outputs it owns (rows i, columns j..j+V-1).
+template <typename T, int RB, class Epi>
+__device__ __forceinline__ void sep_tile(const T* __restrict__ Xs, int H, T* __restrict__ Zs,
+                                         const Table1D& t0, const Table1D& t1, int i0, int j0,
+                                         int TI, int TJ, int m, Epi epi) {
+  constexpr int V = TileCfg<T>::V;
+  constexpr int NT = 2 * RB + 1;
+  constexpr int NW = V + 2 * RB;
+  const int LX = sep_lx(TJ, H), LZ = sep_lz(TI);
+  const T* __restrict__ T0 = taps1<T>(t0);
+  const T* __restrict__ T1 = taps1<T>(t1);
+  const int NRX = TI + 2 * H;
+
+  // ---- pass A: along axis 0, for the TJ + 2RB columns pass B needs
+  {
+    T tp[NT];
+#pragma unroll
+    for (int e = 0; e < NT; ++e) tp[e] = T0[t0.St * NT + e];
+    const int NC = TJ + 2 * RB;
+    const int nch = (TI + V - 1) / V;
+    for (int item = threadIdx.x; item < NC * nch; item += NTHREADS) {
+      const int c = item % NC, ch = item / NC;
+      const int r0 = ch * V;
+      const int xc = c + (H - RB);
+      T win[NW];
+#pragma unroll
+      for (int k = 0; k < NW; ++k) {
+        const int rr = r0 + k + (H - RB);
+        win[k] = (rr < NRX) ? Xs[rr * LX + xc] : T(0);
+      }
+      const int ia = i0 + r0;
+      const bool inter = (ia >= t0.St) && (ia + V - 1 < m - t0.Sb);
+      T out[V];
+      if (inter) {
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          T a = T(0);
+#pragma unroll
+          for (int e = 0; e < NT; ++e) a = fma(tp[e], win[v + e], a);
+          out[v] = a;
+        }
+      } else {
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          const int i = ia + v;
+          const int cls = (i < m) ? class_of(i, m, t0.St, t0.Sb) : t0.St;
+          const T* __restrict__ row = T0 + cls * NT;
+          T a = T(0);
+#pragma unroll
+          for (int e = 0; e < NT; ++e) a = fma(row[e], win[v + e], a);
+          out[v] = a;
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < V; ++v)
+        if (r0 + v < TI) Zs[c * LZ + r0 + v] = out[v];
+    }
+  }
+  __syncthreads();
+  // ---- pass B: along axis 1
+  {
+    T tp[NT];
+#pragma unroll
+    for (int e = 0; e < NT; ++e) tp[e] = T1[t1.St * NT + e];
+    const int NC = TJ + 2 * RB;
+    const int nch = (TJ + V - 1) / V;
+    for (int item = threadIdx.x; item < TI * nch; item += NTHREADS) {
+      const int r = item % TI, ch = item / TI;
+      const int c0 = ch * V;
+      T win[NW];
+#pragma unroll
+      for (int k = 0; k < NW; ++k) win[k] = (c0 + k < NC) ? Zs[(c0 + k) * LZ + r] : T(0);
+      const int ja = j0 + c0;
+      const bool inter = (ja >= t1.St) && (ja + V - 1 < m - t1.Sb);
+      if (inter) {
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          T a = T(0);
+#pragma unroll
+          for (int e = 0; e < NT; ++e) a = fma(tp[e], win[v + e], a);
+          if (c0 + v < TJ) epi(r, c0 + v, a);
+        }
+      } else {
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          const int j = ja + v;
+          const int cls = (j < m) ? class_of(j, m, t1.St, t1.Sb) : t1.St;
+          const T* __restrict__ row = T1 + cls * NT;
+          T a = T(0);
+#pragma unroll
+          for (int e = 0; e < NT; ++e) a = fma(row[e], win[v + e], a);
+          if (c0 + v < TJ) epi(r, c0 + v, a);
+        }
+      }
+    }
+  }
+}
+
+// General 2-D tile convolution over class-pair tap lists.  Xs is the
+// column-major tile (halo H >= max(R0, R1)); `itaps` is LDS scratch for up
+// to (2H+1)^2 interior taps.  epi(i_local, j_local, value).
+template <typename T, class Epi>
+__device__ __forceinline__ void gen_tile(const T* __restrict__ Xs, int H, const Table2D& tb,
+                                         short2* s_e, T* s_v, int i0, int j0, int TI, int TJ,
+                                         int m, Epi epi) {
+  const int LXC = col_lx(TI, H);
+  const T* __restrict__ vals = taps2<T>(tb);
+  const bool inter = (i0 >= tb.St0) && (i0 + TI - 1 < m - tb.Sb0) && (j0 >= tb.St1) &&
+                     (j0 + TJ - 1 < m - tb.Sb1);
+  if (inter) {
+    const int cls = tb.St0 + tb.St1 * tb.rows0;
+    const int b = tb.off[cls], n = tb.off[cls + 1] - b;
+    for (int k = threadIdx.x; k < n; k += NTHREADS) {
+      s_e[k] = tb.e[b + k];
+      s_v[k] = vals[b + k];
+    }
+    __syncthreads();
+    for (int o = threadIdx.x; o < TI * TJ; o += NTHREADS) {
+      const int i = o % TI, j = o / TI;
+      T a = T(0);
+      for (int k = 0; k < n; ++k) {
+        const short2 e = s_e[k];
+        a = fma(s_v[k], Xs[(j + H + e.y) * LXC + (i + H + e.x)], a);
+      }
+      epi(i, j, a);
+    }
+  } else {
+    for (int o = threadIdx.x; o < TI * TJ; o += NTHREADS) {
+      const int i = o % TI, j = o / TI;
+      const int c0 = class_of(i0 + i, m, tb.St0, tb.Sb0);
+      const int c1 = class_of(j0 + j, m, tb.St1, tb.Sb1);
+      const int cls = c0 + c1 * tb.rows0;
+      const int b = tb.off[cls], e_ = tb.off[cls + 1];
+      T a = T(0);
+      for (int k = b; k < e_; ++k) {
+        const short2 e = tb.e[k];
+        a = fma(vals[k], Xs[(j + H + e.y) * LXC + (i + H + e.x)], a);
+      }
+      epi(i, j, a);
+    }
+  }
+}
+
+// Tile geometry of a job: tile (ti, tj) covers rows [i0, i0+TI), cols [j0, j0+TJ).
+template <typename T>
+__device__ __forceinline__ void tile_geom(int m, int ti, int tj, int& i0, int& j0, int& TI,
+                                          int& TJ) {
+  constexpr int TS = TileCfg<T>::TS;
+  TI = TJ = (m < TS) ? m : TS;
+  i0 = ti * TI;
+  j0 = tj * TJ;
+}
+
+}  // namespace dbl
