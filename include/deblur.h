@@ -159,6 +159,8 @@ void dbl_opts_default(dbl_opts* opts);
  * grid of at least 8 pixels per side. */
 int dbl_op_create(dbl_ctx* ctx, const double* psf, int ph, int pw, int m, int levels,
                   int wavelet, int precision, dbl_op** out);
+/* Release an operator.  Operators (and servers) must be destroyed before the
+ * context they were made on; dbl_destroy releases their device memory. */
 int dbl_op_destroy(dbl_op* op);
 
 /* out = A^(level) in (transpose = 0) or A^(level)^T in (transpose = 1).

@@ -12,6 +12,7 @@ Importing this package does not load it; the first call does, and raises
 """
 import ctypes
 import os
+import weakref
 
 import numpy as np
 
@@ -169,9 +170,13 @@ class Context:
         if code != DBL_OK:
             raise DeblurError(code, "dbl_create failed")
         self.handle = h
+        self._children = weakref.WeakSet()
 
     def close(self):
+        """Destroy the context; operators and servers made from it go first."""
         if self.handle:
+            for ch in list(self._children):
+                ch.close()
             lib().dbl_destroy(self.handle)
             self.handle = None
 
@@ -216,6 +221,7 @@ def dbl_opts_default(**kw):
 class Op:
     def __init__(self, ctx, handle, m, levels, precision):
         self.ctx, self.handle, self.m, self.levels, self.precision = ctx, handle, m, levels, precision
+        ctx._children.add(self)
 
     def close(self):
         if self.handle:
@@ -337,6 +343,7 @@ class Server:
         _check(ctx, lib().dbl_server_create(ctx.handle, max_slots, budget, ctypes.byref(h)))
         self.handle = h
         self._keep = {}
+        ctx._children.add(self)
 
     def close(self):
         if self.handle:

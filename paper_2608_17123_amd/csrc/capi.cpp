@@ -124,6 +124,7 @@ int dbl_destroy(dbl_ctx* ctx) {
   for (auto& kv : ctx->dct) (void)hipFree(kv.second);
   for (auto& kv : ctx->allocs) (void)hipFree(kv.first);
   if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
+  for (auto& b : ctx->retired) (void)hipHostFree(b.first);
   if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
   if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
   delete ctx;
@@ -152,6 +153,7 @@ int dbl_op_create(dbl_ctx* ctx, const double* psf, int ph, int pw, int m, int le
   if (rc) return rc;
   if (ctx->device < 0) return set_err(ctx, DBL_EDEVICE, "context has no device");
   (void)hipSetDevice(ctx->device);
+  if (int rc0 = stage_checkpoint(ctx)) return rc0;
   return op_build(ctx, psf, ph, pw, m, levels, wavelet, precision, out);
 }
 
@@ -170,6 +172,7 @@ int dbl_apply_A(dbl_ctx* ctx, const dbl_op* op, int level, int transpose, const 
   if (transpose != 0 && transpose != 1) return set_err(ctx, DBL_EINVAL, "bad transpose flag");
   if (ctx->device < 0) return set_err(ctx, DBL_EDEVICE, "context has no device");
   (void)hipSetDevice(ctx->device);
+  if (int rc0 = stage_checkpoint(ctx)) return rc0;
   const LevelHost& L = op->host.levels[level];
   Job j;
   std::memset(&j, 0, sizeof(j));
@@ -197,6 +200,7 @@ int dbl_apply_L(dbl_ctx* ctx, int m, int precision, int transpose, const void* i
   if (rc) return rc;
   if (ctx->device < 0) return set_err(ctx, DBL_EDEVICE, "context has no device");
   (void)hipSetDevice(ctx->device);
+  if (int rc0 = stage_checkpoint(ctx)) return rc0;
   Job j;
   std::memset(&j, 0, sizeof(j));
   j.m = m;
@@ -222,6 +226,7 @@ int dbl_dwt(dbl_ctx* ctx, int wavelet, int m, int precision, int inverse, int lo
   if (rc) return rc;
   if (ctx->device < 0) return set_err(ctx, DBL_EDEVICE, "context has no device");
   (void)hipSetDevice(ctx->device);
+  if (int rc0 = stage_checkpoint(ctx)) return rc0;
   Job j;
   std::memset(&j, 0, sizeof(j));
   j.m = m;
@@ -247,6 +252,7 @@ int dbl_dtransfer(dbl_ctx* ctx, int wavelet, int m_coarse, int precision, const 
   if (rc) return rc;
   if (ctx->device < 0) return set_err(ctx, DBL_EDEVICE, "context has no device");
   (void)hipSetDevice(ctx->device);
+  if (int rc0 = stage_checkpoint(ctx)) return rc0;
   Job j;
   std::memset(&j, 0, sizeof(j));
   j.m = 2 * m_coarse;
@@ -271,14 +277,14 @@ int dbl_cgls(dbl_ctx* ctx, const dbl_op* op, int level, const dbl_sub* sub, cons
   if (!(sub->gamma >= 0.0) || !std::isfinite(sub->gamma)) return set_err(ctx, DBL_EINVAL, "gamma must be finite and >= 0");
   if (ctx->device < 0) return set_err(ctx, DBL_EDEVICE, "context has no device");
   (void)hipSetDevice(ctx->device);
+  if (int rc0 = stage_checkpoint(ctx)) return rc0;
   const LevelHost& L = op->host.levels[level];
   const int m = L.m, prec = op->precision;
   const size_t esz = prec == DBL_F64 ? 8 : 4;
   const size_t n = (size_t)m * m, nl = 2 * (size_t)m * (m - 1);
-  const int nt = tiles_per_axis(m, (int)esz);
   auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
   const size_t need = 6 * al(n * esz) + 3 * al(nl * esz) + al(NSCAL * 8) +
-                      al((size_t)nt * nt * 32 * 8) + 256;
+                      al(part_doubles(m) * 8) + 256;
   int rc = DBL_OK;
   if (ctx->scratch_bytes < need) {
     if ((rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "sync"))) return rc;
@@ -297,7 +303,7 @@ int dbl_cgls(dbl_ctx* ctx, const dbl_op* op, int level, const dbl_sub* sub, cons
   void* R2[2] = {take(nl * esz), take(nl * esz)};
   void* Q2 = take(nl * esz);
   double* scal = static_cast<double*>(take(NSCAL * 8));
-  double* part = static_cast<double*>(take((size_t)nt * nt * 32 * 8));
+  double* part = static_cast<double*>(take(part_doubles(m) * 8));
   unsigned* cnt = static_cast<unsigned*>(take(256));
   if ((rc = hip_check(ctx, hipMemsetAsync(cnt, 0, 256, ctx->stream), "clear"))) return rc;
   const double gv[2] = {sub->gamma, std::sqrt(sub->gamma)};
@@ -402,10 +408,10 @@ int dbl_gcv(dbl_ctx* ctx, const dbl_op* op, int level, const dbl_sub* sub, const
     return set_err(ctx, DBL_ENOTSUP, "EXACT GCV is limited to n <= 4096");
   if (ctx->device < 0) return set_err(ctx, DBL_EDEVICE, "context has no device");
   (void)hipSetDevice(ctx->device);
-  const int nt = tiles_per_axis(m, op->precision == DBL_F64 ? 8 : 4);
+  if (int rc0 = stage_checkpoint(ctx)) return rc0;
   void* blk = nullptr;
-  const size_t bytes = 4 * ((n * 8 + 255) & ~size_t(255)) + NSCAL * 8 + 256 +
-                       (size_t)std::max(nt * nt, 64) * 64 * 8 * 4;
+  const size_t bytes = 4 * ((n * 8 + 255) & ~size_t(255)) + NSCAL * 8 + 256 + 256 +
+                       part_doubles(m) * 8;
   int rc = dmalloc(ctx, bytes, &blk);
   if (rc) return rc;
   char* p = static_cast<char*>(blk);
@@ -424,7 +430,7 @@ int dbl_gcv(dbl_ctx* ctx, const dbl_op* op, int level, const dbl_sub* sub, const
   g.in = static_cast<double*>(take(n * 8));
   g.scal = static_cast<double*>(take(NSCAL * 8));
   g.cnt = static_cast<unsigned*>(take(256));
-  g.part = static_cast<double*>(take((size_t)std::max(nt * nt, 64) * 64 * 8 * 4));
+  g.part = static_cast<double*>(take(part_doubles(m) * 8));
   g.bh_valid = false;
   g.grid = grid;
   g.mode = mode;
@@ -478,6 +484,7 @@ int dbl_deblur_batch(dbl_ctx* ctx, int count, const dbl_request* reqs, dbl_repor
   if (count == 0) return DBL_OK;
   if (ctx->device < 0) return set_err(ctx, DBL_EDEVICE, "context has no device");
   (void)hipSetDevice(ctx->device);
+  if (int rc0 = stage_checkpoint(ctx)) return rc0;
   std::vector<Slot> slots(count);
   std::vector<Slot*> ptrs;
   int rc = DBL_OK;

@@ -1,8 +1,206 @@
-// GCV driver (placeholder until the GCV kernels land).
+// GCV driver (Sec. 3): spectral data, grid search and Brent refinement for a
+// batch of subproblems; writes gamma and sqrt(gamma) into each scalar block.
+#include <cmath>
+#include <cstring>
+
 #include "runtime.h"
 
 namespace dbl {
-int gcv_run(dbl_ctx* ctx, std::vector<GcvReq>&) {
-  return set_err(ctx, DBL_ENOTSUP, "GCV not built yet");
+
+namespace {
+
+enum : int { G_B = 0, G_W, G_C1, G_C2, G_IN, G_TMP, G_BH, G_E, G_SYM, G_LAM, G_KINT, G_DCT };
+
+const int BRENT_MAXIT = 100;
+const double BRENT_XTOL = 1e-8;
+
+int ensure_dct(dbl_ctx* ctx, int m, double** out) {
+  auto it = ctx->dct.find(m);
+  if (it != ctx->dct.end()) {
+    *out = it->second;
+    return DBL_OK;
+  }
+  // orthonormal DCT-II, column-major: C[k + i m] = c_k cos(pi k (2i + 1) / (2m))
+  std::vector<double> C((size_t)m * m);
+  for (int i = 0; i < m; ++i)
+    for (int k = 0; k < m; ++k)
+      C[k + (size_t)i * m] = (k == 0 ? std::sqrt(1.0 / m) : std::sqrt(2.0 / m)) *
+                             std::cos(M_PI * k * (2.0 * i + 1.0) / (2.0 * m));
+  double* d = nullptr;
+  int rc = hip_check(ctx, hipMalloc((void**)&d, C.size() * 8), "hipMalloc dct");
+  if (rc) return rc;
+  rc = hip_check(ctx, hipMemcpy(d, C.data(), C.size() * 8, hipMemcpyHostToDevice), "upload dct");
+  if (rc) return rc;
+  ctx->dct[m] = d;
+  *out = d;
+  return DBL_OK;
 }
+
+// Symbol block per op level: [a_k (n) | l(k) (m) | interior kernel].
+int ensure_symbol(dbl_ctx* ctx, const dbl_op* cop, int level, double** sym) {
+  dbl_op* op = const_cast<dbl_op*>(cop);
+  if (op->sym[level]) {
+    *sym = op->sym[level];
+    return DBL_OK;
+  }
+  const LevelHost& L = op->host.levels[level];
+  const int m = L.m;
+  const size_t n = (size_t)m * m;
+  const size_t nk = L.kint.size();
+  double* blk = nullptr;
+  int rc = dmalloc(ctx, (n + m + nk) * 8, (void**)&blk);
+  if (rc) return rc;
+  std::vector<double> host(m + nk);
+  for (int k = 0; k < m; ++k) {
+    const double s = std::sin(M_PI * k / (2.0 * m));
+    host[k] = 4.0 * s * s;
+  }
+  std::memcpy(host.data() + m, L.kint.data(), nk * 8);
+  rc = hip_check(ctx, hipMemcpy(blk + n, host.data(), host.size() * 8, hipMemcpyHostToDevice),
+                 "upload symbol inputs");
+  if (rc) {
+    dfree(ctx, blk);
+    return rc;
+  }
+  Job j;
+  std::memset(&j, 0, sizeof(j));
+  j.m = m;
+  j.i0 = L.kint_r0;
+  j.i1 = L.kint_r1;
+  j.v[G_KINT] = blk + n + m;
+  j.v[G_SYM] = blk;
+  Launch La;
+  La.add(j, m, 4);
+  LaunchArgs la;
+  if ((rc = La.upload(ctx, la))) return rc;
+  if ((rc = hip_check(ctx, launch_gcv_symbol(la), "gcv symbol"))) return rc;
+  op->sym[level] = blk;
+  *sym = blk;
+  return DBL_OK;
+}
+
+}  // namespace
+
+int gcv_run(dbl_ctx* ctx, std::vector<GcvReq>& reqs) {
+  int rc = DBL_OK;
+  for (auto& r : reqs)
+    if (r.mode == DBL_GCV_EXACT)
+      return set_err(ctx, DBL_ENOTSUP, "EXACT GCV is not available in this build; use SPECTRAL");
+  std::vector<Job> base(reqs.size());
+  for (size_t q = 0; q < reqs.size(); ++q) {
+    GcvReq& r = reqs[q];
+    const int m = r.op->host.levels[r.level].m;
+    double *sym = nullptr, *dct = nullptr;
+    if ((rc = ensure_symbol(ctx, r.op, r.level, &sym))) return rc;
+    if ((rc = ensure_dct(ctx, m, &dct))) return rc;
+    Job& j = base[q];
+    std::memset(&j, 0, sizeof(j));
+    j.m = m;
+    j.scal = r.scal;
+    j.part = r.part;
+    j.cnt = r.cnt;
+    j.v[G_B] = const_cast<void*>(r.b);
+    j.v[G_W] = const_cast<void*>(r.w);
+    j.v[G_C1] = const_cast<void*>(r.c1);
+    j.v[G_C2] = const_cast<void*>(r.c2);
+    j.v[G_IN] = r.in;
+    j.v[G_TMP] = r.tmp;
+    j.v[G_BH] = r.bh;
+    j.v[G_E] = r.e;
+    j.v[G_SYM] = sym;
+    j.v[G_LAM] = sym + (size_t)m * m;
+    j.v[G_DCT] = dct;
+  }
+  auto run = [&](hipError_t (*fn)(const LaunchArgs&), Launch& L, const char* what) -> int {
+    if (L.empty()) return DBL_OK;
+    LaunchArgs la;
+    int r2 = L.upload(ctx, la);
+    if (r2) return r2;
+    return hip_check(ctx, fn(la), what);
+  };
+  auto run_prec = [&](std::map<int, Launch>& M, const char* what) -> int {
+    for (auto& kv : M) {
+      if (kv.second.empty()) continue;
+      LaunchArgs la;
+      int r2 = kv.second.upload(ctx, la);
+      if (r2) return r2;
+      if ((r2 = hip_check(ctx, launch_gcv_prep(la, kv.first), what))) return r2;
+    }
+    return DBL_OK;
+  };
+  // DCT(X) = C X C^T as two GEMMs: tmp = C in, out = tmp C^T.
+  auto dct2 = [&](const std::vector<size_t>& sel, int out_slot) -> int {
+    Launch g1, g2;
+    for (size_t q : sel) {
+      Job a = base[q];
+      a.v[0] = base[q].v[G_DCT];
+      a.v[1] = base[q].v[G_IN];
+      a.v[2] = base[q].v[G_TMP];
+      a.i0 = 0;
+      g1.add(a, a.m, 4);
+      Job b = base[q];
+      b.v[0] = base[q].v[G_TMP];
+      b.v[1] = base[q].v[G_DCT];
+      b.v[2] = base[q].v[out_slot];
+      b.i0 = 1;
+      g2.add(b, b.m, 4);
+    }
+    int r2 = run(launch_gemm64, g1, "dct gemm 1");
+    if (!r2) r2 = run(launch_gemm64, g2, "dct gemm 2");
+    return r2;
+  };
+  // 1. DCT of the data b (once per level)
+  {
+    std::map<int, Launch> P;
+    std::vector<size_t> sel;
+    for (size_t q = 0; q < reqs.size(); ++q) {
+      if (reqs[q].bh_valid) continue;
+      Job j = base[q];
+      j.i0 = 0;
+      P[reqs[q].prec].add(j, j.m, 4);
+      sel.push_back(q);
+    }
+    if ((rc = run_prec(P, "gcv prep b"))) return rc;
+    if (!sel.empty() && (rc = dct2(sel, G_BH))) return rc;
+  }
+  // 2. L^T c (shift) and the IRLS weight scale, then DCT(L^T c)
+  {
+    std::map<int, Launch> P;
+    std::vector<size_t> sel;
+    for (size_t q = 0; q < reqs.size(); ++q) {
+      Job j = base[q];
+      j.i0 = 1;
+      P[reqs[q].prec].add(j, j.m, 4);
+      if (reqs[q].c1) sel.push_back(q);
+    }
+    if ((rc = run_prec(P, "gcv prep c"))) return rc;
+    if (!sel.empty() && (rc = dct2(sel, G_E))) return rc;
+  }
+  // 3. per-frequency data and grid bounds; 4. grid; 5. Brent
+  {
+    Launch Ld, Lg, Lb;
+    for (size_t q = 0; q < reqs.size(); ++q) {
+      Job j = base[q];
+      j.i0 = reqs[q].c1 ? 1 : 0;
+      Ld.add(j, j.m, 4);
+      Job g = base[q];
+      g.i1 = reqs[q].grid;
+      Lg.add(g, g.m, 4);
+      Job b = base[q];
+      b.i1 = BRENT_MAXIT;
+      b.p0 = BRENT_XTOL;
+      Lb.add(b, b.m, 4);
+    }
+    if ((rc = run(launch_gcv_data, Ld, "gcv data"))) return rc;
+    LaunchArgs lg;
+    if ((rc = Lg.upload(ctx, lg))) return rc;
+    if ((rc = hip_check(ctx, launch_gcv_grid(lg, 0), "gcv grid"))) return rc;
+    LaunchArgs lb;
+    if ((rc = Lb.upload(ctx, lb))) return rc;
+    for (int it = 0; it <= BRENT_MAXIT; ++it)
+      if ((rc = hip_check(ctx, launch_gcv_brent(lb), "gcv brent"))) return rc;
+  }
+  return DBL_OK;
+}
+
 }  // namespace dbl

@@ -335,7 +335,7 @@ void build_hierarchy(const double* P, int ph, int pw, int m, int levels, int wav
           tb.off.push_back((int)tb.val.size());
         }
     }
-    L.R = std::max(L.f2.R0, L.a2.R0);
+    L.R = std::max(1, std::max(L.f2.R0, L.a2.R0));  // the gradient needs a halo of 1
     L.rb = 0;
     if (L.R > 16) throw std::runtime_error("coarse operator radius exceeds 16");
     // interior kernel for the GCV surrogate: K[a, b] = tap at offset (-a, -b)

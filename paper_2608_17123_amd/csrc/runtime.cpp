@@ -45,28 +45,30 @@ void dfree(dbl_ctx* ctx, void* p) {
   (void)hipFree(p);
 }
 
-// Copy `bytes` to the device through the staging ring; the copy is queued on
-// the context stream.  A region is only reused after a full stream sync.
+// Copy `bytes` to the device through the staging buffer; the copy is queued
+// on the context stream.  Staged data stays valid until the next checkpoint:
+// when the buffer is full a larger one replaces it and the old one is only
+// released at a checkpoint, after a stream synchronisation, so arrays staged
+// for launches that have not been issued yet are never overwritten.
 int stage(dbl_ctx* ctx, const void* src, size_t bytes, void** dptr) {
   const size_t need = (bytes + 255) & ~size_t(255);
   if (ctx->stage_off + need > ctx->stage_cap) {
-    int rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "stage sync");
-    if (rc) return rc;
+    if (ctx->h_stage) ctx->retired.push_back({ctx->h_stage, ctx->d_stage});
+    ctx->h_stage = nullptr;
+    ctx->d_stage = nullptr;
+    const size_t cap = std::max<size_t>(std::max(need, 2 * ctx->stage_cap), size_t(4) << 20);
+    ctx->stage_cap = 0;
     ctx->stage_off = 0;
-    if (need > ctx->stage_cap) {
-      size_t cap = std::max(need, ctx->stage_cap * 2);
-      if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
-      if (ctx->d_stage) dfree(ctx, ctx->d_stage);
+    int rc = hip_check(ctx, hipHostMalloc((void**)&ctx->h_stage, cap, hipHostMallocDefault),
+                       "hipHostMalloc");
+    if (rc) return rc;
+    rc = dmalloc(ctx, cap, (void**)&ctx->d_stage);
+    if (rc) {
+      (void)hipHostFree(ctx->h_stage);
       ctx->h_stage = nullptr;
-      ctx->d_stage = nullptr;
-      ctx->stage_cap = 0;
-      rc = hip_check(ctx, hipHostMalloc((void**)&ctx->h_stage, cap, hipHostMallocDefault),
-                     "hipHostMalloc");
-      if (rc) return rc;
-      rc = dmalloc(ctx, cap, (void**)&ctx->d_stage);
-      if (rc) return rc;
-      ctx->stage_cap = cap;
+      return rc;
     }
+    ctx->stage_cap = cap;
   }
   std::memcpy(ctx->h_stage + ctx->stage_off, src, bytes);
   int rc = hip_check(ctx,
@@ -79,9 +81,30 @@ int stage(dbl_ctx* ctx, const void* src, size_t bytes, void** dptr) {
   return DBL_OK;
 }
 
+// Called only where no staged array is waiting for its launch: when the
+// buffer is more than half used (or old buffers are retired), wait for the
+// stream, free retired buffers and restart at offset 0.
+int stage_checkpoint(dbl_ctx* ctx) {
+  if (ctx->retired.empty() && ctx->stage_off <= ctx->stage_cap / 2) return DBL_OK;
+  int rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "stage checkpoint");
+  if (rc) return rc;
+  for (auto& b : ctx->retired) {
+    (void)hipHostFree(b.first);
+    dfree(ctx, b.second);
+  }
+  ctx->retired.clear();
+  ctx->stage_off = 0;
+  return DBL_OK;
+}
+
 int tiles_per_axis(int grid_m, int esz) {
   const int ts = esz == 8 ? 32 : 64;
   return grid_m < ts ? 1 : grid_m / ts;
+}
+
+size_t part_doubles(int m) {
+  const size_t t4 = (size_t)tiles_per_axis(m, 4), t8 = (size_t)tiles_per_axis(m, 8);
+  return t4 * t4 * 2 * DBL_GCV_GRID_MAX + t8 * t8 * 8;
 }
 
 void Launch::add(const Job& j0, int grid_m, int esz) {
@@ -228,8 +251,7 @@ size_t slot_bytes(const dbl_request& req) {
   b += 8 * align256(n * esz);
   b += 6 * align256(nl * esz);
   for (int i = 1; i < req.levels; ++i) b += align256(((size_t)req.m >> i) * (req.m >> i) * esz);
-  const int nt = tiles_per_axis(req.m, (int)esz);
-  b += align256(NSCAL * 8) + align256((size_t)nt * nt * 32 * 8) + 256;
+  b += align256(NSCAL * 8) + align256(part_doubles(req.m) * 8) + 256;
   b += align256((size_t)req.levels * DBL_MAX_KOUT * 3 * 8);
   if (wants_gcv(req.opts)) b += 4 * align256(n * 8);
   return b;
@@ -287,9 +309,8 @@ int slot_init(dbl_ctx* ctx, const dbl_request& req, Slot* s) {
   s->B.assign(req.levels, nullptr);
   s->B[0] = req.b;
   for (int i = 1; i < req.levels; ++i) s->B[i] = take(((size_t)req.m >> i) * (req.m >> i) * e);
-  const int nt = tiles_per_axis(req.m, (int)e);
   s->scal = static_cast<double*>(take(NSCAL * 8));
-  s->part = static_cast<double*>(take((size_t)nt * nt * 32 * 8));
+  s->part = static_cast<double*>(take(part_doubles(req.m) * 8));
   s->cnt = static_cast<unsigned*>(take(256));
   s->hist = static_cast<double*>(take((size_t)req.levels * DBL_MAX_KOUT * 3 * 8));
   if (s->gcv) {
@@ -418,7 +439,8 @@ void add_aux(std::map<int, Launch>& L, const Slot* s, int level, int mode, const
 }  // namespace
 
 int engine_step(dbl_ctx* ctx, std::vector<Slot*>& slots) {
-  int rc = DBL_OK;
+  int rc = stage_checkpoint(ctx);
+  if (rc) return rc;
   std::vector<Slot*> act;
   for (Slot* s : slots)
     if (!s->done && !s->status) act.push_back(s);

