@@ -149,6 +149,17 @@ int dbl_sync(dbl_ctx* ctx);
 size_t dbl_workspace_bytes(const dbl_ctx* ctx);
 void dbl_opts_default(dbl_opts* opts);
 
+/* Per-kernel timing.  dbl_profile(ctx, 1) clears the counters and starts
+ * bracketing every kernel launch of ctx with HIP events on its stream;
+ * dbl_profile(ctx, 0) stops.  dbl_profile_read returns, for kernel family
+ * `index` (0, 1, ...; DBL_ENOTFOUND past the last), its name, the number of
+ * launches, their summed device time in milliseconds and the algorithmic
+ * bytes they moved (each operand read or written once; 0 where not
+ * counted).  Reading synchronises the stream. */
+int dbl_profile(dbl_ctx* ctx, int enable);
+int dbl_profile_read(dbl_ctx* ctx, int index, char* name, size_t name_cap, int64_t* launches,
+                     double* ms, double* bytes);
+
 /* -------------------------------------------------------------- operators */
 
 /* Build the level hierarchy A^(i+1) = W^T A^(i) W, b^(i+1) = W^T b^(i)

@@ -35,7 +35,7 @@ GCV_MODES = {"auto": DBL_GCV_AUTO, "exact": DBL_GCV_EXACT, "spectral": DBL_GCV_S
 
 EXPORTS = [
     "dbl_create", "dbl_destroy", "dbl_last_error", "dbl_sync", "dbl_workspace_bytes",
-    "dbl_opts_default", "dbl_op_create", "dbl_op_destroy", "dbl_apply_A", "dbl_apply_L",
+    "dbl_opts_default", "dbl_profile", "dbl_profile_read", "dbl_op_create", "dbl_op_destroy", "dbl_apply_A", "dbl_apply_L",
     "dbl_dwt", "dbl_dtransfer", "dbl_cgls", "dbl_gcv", "dbl_deblur", "dbl_deblur_batch",
     "dbl_server_create", "dbl_server_destroy", "dbl_server_submit", "dbl_server_step",
     "dbl_server_poll",
@@ -102,6 +102,9 @@ def lib():
         "dbl_sync": (i, [vp]),
         "dbl_workspace_bytes": (sz, [vp]),
         "dbl_opts_default": (None, [ctypes.POINTER(dbl_opts)]),
+        "dbl_profile": (i, [vp, i]),
+        "dbl_profile_read": (i, [vp, i, ctypes.c_char_p, sz, ctypes.POINTER(ctypes.c_int64),
+                                 dp, dp]),
         "dbl_op_create": (i, [vp, dp, i, i, i, i, i, i, ctypes.POINTER(vp)]),
         "dbl_op_destroy": (i, [vp]),
         "dbl_apply_A": (i, [vp, vp, i, i, vp, vp]),
@@ -201,6 +204,27 @@ def dbl_sync(ctx):
 
 def dbl_workspace_bytes(ctx):
     return int(lib().dbl_workspace_bytes(ctx.handle))
+
+
+def dbl_profile(ctx, enable):
+    _check(ctx, lib().dbl_profile(ctx.handle, int(enable)))
+
+
+def dbl_profile_read(ctx):
+    """All kernel families recorded since profiling was enabled:
+    {name: (launches, milliseconds, algorithmic bytes)}."""
+    out = {}
+    idx = 0
+    buf = ctypes.create_string_buffer(64)
+    n, ms, by = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+    while True:
+        code = lib().dbl_profile_read(ctx.handle, idx, buf, 64, ctypes.byref(n), ctypes.byref(ms),
+                                      ctypes.byref(by))
+        if code == DBL_ENOTFOUND:
+            return out
+        _check(ctx, code)
+        out[buf.value.decode()] = (n.value, ms.value, by.value)
+        idx += 1
 
 
 def dbl_opts_default(**kw):

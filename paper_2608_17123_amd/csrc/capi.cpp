@@ -125,6 +125,9 @@ int dbl_destroy(dbl_ctx* ctx) {
   for (auto& kv : ctx->allocs) (void)hipFree(kv.first);
   if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
   for (auto& b : ctx->retired) (void)hipHostFree(b.first);
+  (void)prof_collect(ctx);
+  op_cache_clear(ctx);
+  for (hipEvent_t e : ctx->prof_pool) (void)hipEventDestroy(e);
   if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
   if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
   delete ctx;
@@ -142,6 +145,37 @@ int dbl_sync(dbl_ctx* ctx) {
 }
 
 size_t dbl_workspace_bytes(const dbl_ctx* ctx) { return ctx ? ctx->used : 0; }
+
+int dbl_profile(dbl_ctx* ctx, int enable) {
+  if (!ctx) return DBL_EINVAL;
+  if (enable != 0 && enable != 1) return set_err(ctx, DBL_EINVAL, "enable must be 0 or 1");
+  if (ctx->device < 0) return set_err(ctx, DBL_EDEVICE, "context has no device");
+  int rc = prof_collect(ctx);
+  if (rc) return rc;
+  if (enable) {
+    ctx->prof_names.clear();
+    ctx->prof_launches.clear();
+    ctx->prof_ms.clear();
+    ctx->prof_bytes.clear();
+  }
+  ctx->prof_on = enable != 0;
+  return DBL_OK;
+}
+
+int dbl_profile_read(dbl_ctx* ctx, int index, char* name, size_t name_cap, int64_t* launches,
+                     double* ms, double* bytes) {
+  if (!ctx || !name || name_cap == 0 || !launches || !ms || !bytes) return DBL_EINVAL;
+  if (ctx->device < 0) return set_err(ctx, DBL_EDEVICE, "context has no device");
+  int rc = prof_collect(ctx);
+  if (rc) return rc;
+  if (index < 0 || index >= (int)ctx->prof_names.size()) return DBL_ENOTFOUND;
+  std::strncpy(name, ctx->prof_names[index].c_str(), name_cap - 1);
+  name[name_cap - 1] = 0;
+  *launches = ctx->prof_launches[index];
+  *ms = ctx->prof_ms[index];
+  *bytes = ctx->prof_bytes[index];
+  return DBL_OK;
+}
 
 int dbl_op_create(dbl_ctx* ctx, const double* psf, int ph, int pw, int m, int levels,
                   int wavelet, int precision, dbl_op** out) {
@@ -187,7 +221,10 @@ int dbl_apply_A(dbl_ctx* ctx, const dbl_op* op, int level, int transpose, const 
   LaunchArgs la;
   int rc = Lc.upload(ctx, la);
   if (rc) return rc;
-  return hip_check(ctx, launch_apply_A(la, op->precision, L.sep ? 1 : 0, L.rb, L.sep ? L.rb : L.R),
+  return hip_check(ctx, timed(ctx, "apply_A", job_bytes("apply_A", Lc.jobs[0], esz), [&] {
+                     return launch_apply_A(la, op->precision, L.sep ? 1 : 0, L.rb,
+                                           L.sep ? L.rb : L.R);
+                   }),
                    "apply A");
 }
 
@@ -349,38 +386,61 @@ int dbl_cgls(dbl_ctx* ctx, const dbl_op* op, int level, const dbl_sub* sub, cons
   LaunchArgs la;
   if ((rc = Li.upload(ctx, la))) return rc;
   if ((rc = hip_check(ctx, launch_cgls_init(la, prec), "cgls init"))) return rc;
+  const PartLayout PL = part_layout(part, m);
   Job jf = j;
   jf.flags |= F_FIRST;
   jf.v[V_R1A] = R1[0];
   jf.v[V_R1B] = R1[1];
   jf.v[V_R2A] = R2[0];
   jf.v[V_R2B] = R2[1];
+  jf.pw = PL.s[0];
   Launch Lf;
   Lf.add(jf, m, (int)esz);
   if ((rc = Lf.upload(ctx, la))) return rc;
   if ((rc = hip_check(ctx, launch_cgls_p2(la, prec, sep, rb, H), "cgls p2"))) return rc;
-  LaunchArgs a1[2], a2[2];
+  LaunchArgs a2[2];
   for (int par = 0; par < 2; ++par) {
-    Job a = j;
-    a.v[V_PA] = P[par];
-    a.v[V_PB] = P[1 - par];
-    Launch L1;
-    L1.add(a, m, (int)esz);
-    if ((rc = L1.upload(ctx, a1[par]))) return rc;
     Job bb = j;
     bb.v[V_PB] = P[1 - par];
     bb.v[V_R1A] = R1[1 - par];
     bb.v[V_R1B] = R1[par];
     bb.v[V_R2A] = R2[1 - par];
     bb.v[V_R2B] = R2[par];
+    bb.pr[0] = PL.q;
+    bb.pr[1] = PL.s[par];
+    bb.pw = PL.s[1 - par];
     Launch L2;
     L2.add(bb, m, (int)esz);
     if ((rc = L2.upload(ctx, a2[par]))) return rc;
   }
   for (int it = 0; it < iters; ++it) {
     const int par = it & 1;
-    if ((rc = hip_check(ctx, launch_cgls_p1(a1[par], prec, sep, rb, H), "cgls p1"))) return rc;
+    Job a = j;
+    a.v[V_PA] = P[par];
+    a.v[V_PB] = P[1 - par];
+    a.pw = PL.q;
+    a.pr[0] = PL.s[par];
+    a.pr[1] = PL.s[1 - par];
+    a.i0 = it;
+    if (it == 0) a.flags |= F_FIRST;
+    Launch L1;
+    L1.add(a, m, (int)esz);
+    LaunchArgs a1;
+    if ((rc = L1.upload(ctx, a1))) return rc;
+    if ((rc = hip_check(ctx, launch_cgls_p1(a1, prec, sep, rb, H), "cgls p1"))) return rc;
     if ((rc = hip_check(ctx, launch_cgls_p2(a2[par], prec, sep, rb, H), "cgls p2"))) return rc;
+  }
+  if (iters > 0) {
+    Job h = j;
+    h.pr[0] = PL.s[iters & 1];
+    h.i0 = iters - 1;
+    const int t = tiles_per_axis(m, (int)esz);
+    h.i1 = t * t;
+    Launch Lh;
+    Lh.add(h, 1, 4);
+    LaunchArgs lh;
+    if ((rc = Lh.upload(ctx, lh))) return rc;
+    if ((rc = hip_check(ctx, launch_cgls_hist(lh), "cgls history"))) return rc;
   }
   if (resid_hist && iters > 0) {
     if ((rc = hip_check(ctx, hipMemcpyAsync(resid_hist, scal + S_HIST, iters * sizeof(double),

@@ -7,11 +7,13 @@
 //   table entry b: job index in the upper 16 bits, tile index within the job in
 //   the lower 16 bits.  A single solve is a launch with one job; a batch or a
 //   server step is the same launch with many jobs.
-// * Each job owns an FP64 scalar block (CGLS alpha/beta, gamma, norms, GCV
-//   state) and a partials array indexed by tile.  Reductions are
-//   deterministic: a block writes its FP64 partial to its own slot; the last
-//   block of the job to finish (atomic counter) sums the partials in tile
-//   order, so results do not depend on which other jobs share the launch.
+// * Each job owns an FP64 scalar block (gamma, GCV state, histories) and
+//   partial-sum arrays indexed by tile.  Reductions never synchronise blocks
+//   inside a launch: a producer launch stores one FP64 partial per tile, and
+//   the consumer launch that needs the total has every block sum the job's
+//   partials in the same fixed order (no atomics, no fences).  Every block
+//   therefore sees bit-identical scalars, and a job's results do not depend
+//   on which other jobs share the launch.
 // * Coarse operators are stored as "class tables": along one axis, rows near
 //   the periodic wavelet seam (top St rows, bottom Sb rows) have their own tap
 //   rows, every other row uses the interior Toeplitz row; taps are indexed by
@@ -26,7 +28,7 @@ namespace dbl {
 constexpr int TILE = 64;
 constexpr int NTHREADS = 256;
 constexpr int MAX_R = 16;
-constexpr int NSCAL = 256;  // doubles per job scalar block
+constexpr int NSCAL = 512;  // doubles per job scalar block
 
 // Scalar block layout (FP64, device).
 enum Scal : int {
@@ -37,7 +39,15 @@ enum Scal : int {
   S_G_FV, S_G_D, S_G_E, S_G_U, S_G_DONE, S_G_NEV, S_G_XTOL, S_G_IT, S_G_RMIN,
   S_G_RMAX, S_G_NPTS, S_G_WBAR, S_G_RES, S_G_TR, S_G_FBEST,
   S_GRID = 64,   // up to 64 grid values
-  S_HIST = 128   // CGLS residual history (up to 128 iterations)
+  S_HIST = 128,  // CGLS residual history (up to 128 iterations)
+  S_BR = 256     // Brent state, two copies of BR_SIZE (read one, write the other)
+};
+constexpr int HIST_MAX = 128;
+
+// Brent state layout (offsets inside one copy)
+enum Brent : int {
+  BR_A = 0, BR_B, BR_X, BR_W, BR_V, BR_FX, BR_FW, BR_FV, BR_D, BR_E, BR_U, BR_IT, BR_PHASE,
+  BR_DONE, BR_SIZE = 16
 };
 
 struct Table1D {
@@ -85,6 +95,8 @@ struct Job {
   double p0, p1;    // extra scalars passed by value
   int i0, i1;       // extra integers passed by value
   double* hist;     // per-solve history (gamma, rc, objective) for stats kernels
+  double* pw;       // partials written by this launch: pw[tile * K + k]
+  const double* pr[3];  // partials of earlier launches summed by this launch
 };
 
 // Job flags
@@ -139,47 +151,31 @@ __device__ __forceinline__ void block_sum(double (&v)[K], double* red) {
   }
 }
 
-// Write this tile's K partials; returns true in thread 0 of the last block of
-// the job to finish, after which `tot` holds the job-wide sums.  The last
-// block sums the partials with a fixed assignment (thread t takes tiles t,
-// t + NTHREADS, ... in order) and a fixed tree, so the result depends only on
-// the job's own tiles.  Partials go through device-scope atomics and fences
-// so that blocks on different XCDs (separate L2s) see each other's values.
+// Store this block's K partial sums at p[tix * K + k] (fixed-order block sum).
 template <int K>
-__device__ __forceinline__ bool job_reduce(const Job* job, int tix, double (&v)[K],
-                                           double* red, double (&tot)[K]) {
+__device__ __forceinline__ void put_partials(double* p, int tix, double (&v)[K], double* red) {
   block_sum<K>(v, red);
-  __shared__ int s_last;
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int k = 0; k < K; ++k)
-      __hip_atomic_store(job->part + tix * K + k, v[k], __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
-    __threadfence();
-    unsigned ntile = unsigned(job->nti * job->ntj);
-    unsigned prev = atomicAdd(job->cnt, 1u);
-    s_last = (prev == ntile - 1) ? 1 : 0;
+    for (int k = 0; k < K; ++k) p[tix * K + k] = v[k];
   }
+}
+
+// Sum component `comp` of K-component partials over the nt tiles of a job in
+// a fixed order (thread t takes tiles t, t + NTHREADS, ...; then the block
+// tree); the total is returned in every thread.  `red` holds 4 doubles.
+template <int K>
+__device__ __forceinline__ double sum_partials(const double* p, int nt, int comp, double* red,
+                                               double* bcast) {
+  double a = 0.0;
+  for (int t = threadIdx.x; t < nt; t += NTHREADS) a += p[t * K + comp];
+  double v[1] = {a};
+  block_sum<1>(v, red);
+  if (threadIdx.x == 0) *bcast = v[0];
   __syncthreads();
-  if (!s_last) return false;
-  __threadfence();
-  const int nt = job->nti * job->ntj;
-  double acc[K];
-#pragma unroll
-  for (int k = 0; k < K; ++k) acc[k] = 0.0;
-  for (int t = threadIdx.x; t < nt; t += NTHREADS) {
-#pragma unroll
-    for (int k = 0; k < K; ++k)
-      acc[k] += __hip_atomic_load(job->part + t * K + k, __ATOMIC_RELAXED,
-                                  __HIP_MEMORY_SCOPE_AGENT);
-  }
-  block_sum<K>(acc, red);
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int k = 0; k < K; ++k) tot[k] = acc[k];
-    __hip_atomic_store(job->cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-  return threadIdx.x == 0;
+  const double r = *bcast;
+  __syncthreads();
+  return r;
 }
 
 // Publish a scalar written by the finalising thread so later kernels and

@@ -87,9 +87,11 @@ int gcv_run(dbl_ctx* ctx, std::vector<GcvReq>& reqs) {
     if (r.mode == DBL_GCV_EXACT)
       return set_err(ctx, DBL_ENOTSUP, "EXACT GCV is not available in this build; use SPECTRAL");
   std::vector<Job> base(reqs.size());
+  std::vector<PartLayout> PLs(reqs.size());
   for (size_t q = 0; q < reqs.size(); ++q) {
     GcvReq& r = reqs[q];
     const int m = r.op->host.levels[r.level].m;
+    PLs[q] = part_layout(r.part, m);
     double *sym = nullptr, *dct = nullptr;
     if ((rc = ensure_symbol(ctx, r.op, r.level, &sym))) return rc;
     if ((rc = ensure_dct(ctx, m, &dct))) return rc;
@@ -116,7 +118,7 @@ int gcv_run(dbl_ctx* ctx, std::vector<GcvReq>& reqs) {
     LaunchArgs la;
     int r2 = L.upload(ctx, la);
     if (r2) return r2;
-    return hip_check(ctx, fn(la), what);
+    return hip_check(ctx, timed(ctx, what, 0.0, [&] { return fn(la); }), what);
   };
   auto run_prec = [&](std::map<int, Launch>& M, const char* what) -> int {
     for (auto& kv : M) {
@@ -124,7 +126,9 @@ int gcv_run(dbl_ctx* ctx, std::vector<GcvReq>& reqs) {
       LaunchArgs la;
       int r2 = kv.second.upload(ctx, la);
       if (r2) return r2;
-      if ((r2 = hip_check(ctx, launch_gcv_prep(la, kv.first), what))) return r2;
+      if ((r2 = hip_check(ctx, timed(ctx, what, 0.0, [&] { return launch_gcv_prep(la, kv.first); }),
+                          what)))
+        return r2;
     }
     return DBL_OK;
   };
@@ -145,8 +149,8 @@ int gcv_run(dbl_ctx* ctx, std::vector<GcvReq>& reqs) {
       b.i0 = 1;
       g2.add(b, b.m, 4);
     }
-    int r2 = run(launch_gemm64, g1, "dct gemm 1");
-    if (!r2) r2 = run(launch_gemm64, g2, "dct gemm 2");
+    int r2 = run(launch_gemm64, g1, "gcv_dct_gemm");
+    if (!r2) r2 = run(launch_gemm64, g2, "gcv_dct_gemm");
     return r2;
   };
   // 1. DCT of the data b (once per level)
@@ -160,7 +164,7 @@ int gcv_run(dbl_ctx* ctx, std::vector<GcvReq>& reqs) {
       P[reqs[q].prec].add(j, j.m, 4);
       sel.push_back(q);
     }
-    if ((rc = run_prec(P, "gcv prep b"))) return rc;
+    if ((rc = run_prec(P, "gcv_prep"))) return rc;
     if (!sel.empty() && (rc = dct2(sel, G_BH))) return rc;
   }
   // 2. L^T c (shift) and the IRLS weight scale, then DCT(L^T c)
@@ -170,35 +174,60 @@ int gcv_run(dbl_ctx* ctx, std::vector<GcvReq>& reqs) {
     for (size_t q = 0; q < reqs.size(); ++q) {
       Job j = base[q];
       j.i0 = 1;
+      j.pw = PLs[q].gw;
       P[reqs[q].prec].add(j, j.m, 4);
       if (reqs[q].c1) sel.push_back(q);
     }
-    if ((rc = run_prec(P, "gcv prep c"))) return rc;
+    if ((rc = run_prec(P, "gcv_prep"))) return rc;
     if (!sel.empty() && (rc = dct2(sel, G_E))) return rc;
   }
   // 3. per-frequency data and grid bounds; 4. grid; 5. Brent
   {
-    Launch Ld, Lg, Lb;
+    Launch Ld, Lg, Lf, Lb[2];
     for (size_t q = 0; q < reqs.size(); ++q) {
+      const PartLayout& PL = PLs[q];
       Job j = base[q];
       j.i0 = reqs[q].c1 ? 1 : 0;
+      j.pr[0] = reqs[q].w ? PL.gw : nullptr;
+      j.pw = PL.gmm;
       Ld.add(j, j.m, 4);
       Job g = base[q];
       g.i1 = reqs[q].grid;
+      g.pr[0] = PL.gmm;
+      g.pw = PL.ggrid;
       Lg.add(g, g.m, 4);
-      Job b = base[q];
-      b.i1 = BRENT_MAXIT;
-      b.p0 = BRENT_XTOL;
-      Lb.add(b, b.m, 4);
+      Job f = base[q];
+      f.i0 = reqs[q].grid;
+      const int t = tiles_per_axis(f.m, 4);
+      f.i1 = t * t;
+      f.pr[0] = PL.ggrid;
+      Lf.add(f, 1, 4);
+      for (int par = 0; par < 2; ++par) {
+        Job b = base[q];
+        b.i0 = par;
+        b.i1 = BRENT_MAXIT;
+        b.p0 = BRENT_XTOL;
+        b.pr[0] = PL.gb[par];
+        b.pw = PL.gb[1 - par];
+        Lb[par].add(b, b.m, 4);
+      }
     }
-    if ((rc = run(launch_gcv_data, Ld, "gcv data"))) return rc;
+    if ((rc = run(launch_gcv_data, Ld, "gcv_data"))) return rc;
     LaunchArgs lg;
     if ((rc = Lg.upload(ctx, lg))) return rc;
-    if ((rc = hip_check(ctx, launch_gcv_grid(lg, 0), "gcv grid"))) return rc;
-    LaunchArgs lb;
-    if ((rc = Lb.upload(ctx, lb))) return rc;
-    for (int it = 0; it <= BRENT_MAXIT; ++it)
-      if ((rc = hip_check(ctx, launch_gcv_brent(lb), "gcv brent"))) return rc;
+    if ((rc = hip_check(ctx, timed(ctx, "gcv_grid", 0.0, [&] { return launch_gcv_grid(lg, 0); }),
+                        "gcv grid")))
+      return rc;
+    if ((rc = run(launch_gcv_gridfin, Lf, "gcv_gridfin"))) return rc;
+    LaunchArgs lb[2];
+    for (int par = 0; par < 2; ++par)
+      if ((rc = Lb[par].upload(ctx, lb[par]))) return rc;
+    // one start evaluation, up to BRENT_MAXIT steps, one final reduction
+    for (int it = 0; it < BRENT_MAXIT + 2; ++it)
+      if ((rc = hip_check(ctx, timed(ctx, "gcv_brent", 0.0,
+                                     [&] { return launch_gcv_brent(lb[it & 1]); }),
+                          "gcv brent")))
+        return rc;
   }
   return DBL_OK;
 }

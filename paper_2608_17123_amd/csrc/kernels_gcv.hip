@@ -13,8 +13,12 @@
 // the smallest and largest s/lp, lower bound clamped to 14 decades below the
 // upper), then Brent's method (golden section with parabolic steps) on the
 // interval around the grid minimum, xtol 1e-8 in log10(g), at most 100 steps.
-// Brent runs as a device state machine: each launch evaluates GCV at the
-// current point (all blocks), the job's last block advances the state.
+// Brent runs as a device state machine over a fixed number of launches: each
+// launch sums the previous evaluation's per-tile partials (every block, same
+// order), advances the state identically in every block, persists it (tile 0
+// of the job) in the copy the next launch reads, and evaluates GCV at the new
+// point.  State copies and partial arrays alternate between launches, so no
+// block ever reads what another block of the same launch writes.
 #include "launch.h"
 #include "stencil.h"
 
@@ -36,6 +40,8 @@ enum : int {
   G_DCT = 11   // FP64 m x m DCT-II matrix, column-major
 };
 
+constexpr int DBL_GCV_GRID_MAX_DEV = 64;
+
 __device__ __forceinline__ double gcv_from(double gam, double res, double tr, int n) {
   const double d = (double)n - tr;
   return gam * gam * res / (d * d);
@@ -46,24 +52,31 @@ __device__ __forceinline__ double gcv_from(double gam, double res, double tr, in
 // Job: m, i0 = r0, i1 = r1.
 __global__ void __launch_bounds__(NTHREADS) k_gcv_symbol(const Job* __restrict__ jobs,
                                                          const uint32_t* __restrict__ tiles) {
+  __shared__ double c0[64 * 33], c1[64 * 33];
   const Job* job; int ti, tj, tix;
   decode_tile(jobs, tiles, job, ti, tj, tix);
   const int m = job->m;
   int i0, j0, TI, TJ;
   tile_geom<float>(m, ti, tj, i0, j0, TI, TJ);
-  const int r0 = job->i0, r1 = job->i1, n0 = 2 * r0 + 1;
+  const int r0 = job->i0, r1 = job->i1, n0 = 2 * r0 + 1, n1 = 2 * r1 + 1;
   const double* __restrict__ K = static_cast<const double*>(job->v[G_KINT]);
   double* __restrict__ sym = static_cast<double*>(job->v[G_SYM]);
   const double w = 3.14159265358979323846 / m;
+  // cos(pi k a / m) for the tile's frequencies and every kernel offset
+  for (int q = threadIdx.x; q < TI * n0; q += NTHREADS)
+    c0[q] = cos(w * (double)(i0 + q % TI) * (double)(q / TI - r0));
+  for (int q = threadIdx.x; q < TJ * n1; q += NTHREADS)
+    c1[q] = cos(w * (double)(j0 + q % TJ) * (double)(q / TJ - r1));
+  __syncthreads();
   for (int o = threadIdx.x; o < TI * TJ; o += NTHREADS) {
-    const int k0 = i0 + o % TI, k1 = j0 + o / TI;
+    const int u = o % TI, v = o / TI;
     double acc = 0.0;
-    for (int b = -r1; b <= r1; ++b) {
+    for (int b = 0; b < n1; ++b) {
       double inner = 0.0;
-      for (int a = -r0; a <= r0; ++a) inner += K[(a + r0) + (size_t)(b + r1) * n0] * cos(w * k0 * a);
-      acc += inner * cos(w * k1 * b);
+      for (int a = 0; a < n0; ++a) inner += K[a + (size_t)b * n0] * c0[u + a * TI];
+      acc += inner * c1[v + b * TJ];
     }
-    sym[k0 + (size_t)k1 * m] = acc;
+    sym[(i0 + u) + (size_t)(j0 + v) * m] = acc;
   }
 }
 
@@ -112,9 +125,10 @@ __global__ void __launch_bounds__(NTHREADS) k_gcv_prep(const Job* __restrict__ j
       if (gj < m - 1) { const double v = w[nx + g]; wsq += v * v; }
     }
   }
-  double vv[1] = {wsq}, tot[1];
-  if (job_reduce<1>(job, tix, vv, red, tot))
-    put_scal(job->scal, S_G_WBAR, w ? tot[0] / (2.0 * (double)m * (m - 1)) : 1.0);
+  if (w) {
+    double vv[1] = {wsq};
+    put_partials<1>(job->pw, tix, vv, red);
+  }
 }
 
 // ---------------------------------------------------------------- GEMM ----
@@ -177,6 +191,7 @@ __global__ void __launch_bounds__(NTHREADS) k_gemm64(const Job* __restrict__ job
 __global__ void __launch_bounds__(NTHREADS) k_gcv_data(const Job* __restrict__ jobs,
                                                        const uint32_t* __restrict__ tiles) {
   __shared__ double red[8];
+  __shared__ double bc;
   const Job* job; int ti, tj, tix;
   decode_tile(jobs, tiles, job, ti, tj, tix);
   const int m = job->m;
@@ -187,7 +202,12 @@ __global__ void __launch_bounds__(NTHREADS) k_gcv_data(const Job* __restrict__ j
   const double* __restrict__ bh = static_cast<const double*>(job->v[G_BH]);
   double* __restrict__ e = static_cast<double*>(job->v[G_E]);
   const bool shift = job->i0 != 0;
-  const double wb2 = job->scal[S_G_WBAR];
+  // IRLS weight scale wbar^2 = mean(w^2) from the prep partials, else 1
+  double wb2 = 1.0;
+  if (job->pr[0])
+    wb2 = sum_partials<1>(job->pr[0], job->nti * job->ntj, 0, red, &bc) /
+          (2.0 * (double)m * (m - 1));
+  if (tix == 0 && threadIdx.x == 0) job->scal[S_G_WBAR] = wb2;
   double lo = 1e300, hi = -1e300;
   for (int o = threadIdx.x; o < TI * TJ; o += NTHREADS) {
     const int k0 = i0 + o % TI, k1 = j0 + o / TI;
@@ -204,38 +224,20 @@ __global__ void __launch_bounds__(NTHREADS) k_gcv_data(const Job* __restrict__ j
       hi = fmax(hi, t);
     }
   }
-  // min / max through the sum reduction: reduce (-lo, hi) with max below.
+  // block min / max, stored as this tile's partials (min, max)
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     lo = fmin(lo, __shfl_xor(lo, off, 64));
     hi = fmax(hi, __shfl_xor(hi, off, 64));
   }
-  __shared__ double sl[4], sh[4];
-  __shared__ int s_last;
-  if (lane == 0) { sl[wid] = lo; sh[wid] = hi; }
+  if (lane == 0) { red[wid] = lo; red[4 + wid] = hi; }
   __syncthreads();
   if (threadIdx.x == 0) {
-    for (int w = 1; w < 4; ++w) { lo = fmin(lo, sl[w]); hi = fmax(hi, sh[w]); }
-    __hip_atomic_store(job->part + 2 * tix, lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(job->part + 2 * tix + 1, hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __threadfence();
-    const unsigned prev = atomicAdd(job->cnt, 1u);
-    s_last = prev == unsigned(job->nti * job->ntj - 1);
+    for (int w = 1; w < 4; ++w) { lo = fmin(lo, red[w]); hi = fmax(hi, red[4 + w]); }
+    job->pw[2 * tix] = lo;
+    job->pw[2 * tix + 1] = hi;
   }
-  __syncthreads();
-  if (!s_last || threadIdx.x != 0) return;
-  __threadfence();
-  const int nt = job->nti * job->ntj;
-  double L = 1e300, Hh = -1e300;
-  for (int t = 0; t < nt; ++t) {
-    L = fmin(L, __hip_atomic_load(job->part + 2 * t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-    Hh = fmax(Hh, __hip_atomic_load(job->part + 2 * t + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-  }
-  (void)red;
-  put_scal(job->scal, S_G_THI, Hh);
-  put_scal(job->scal, S_G_TLO, fmax(L, Hh - 14.0));
-  __hip_atomic_store(job->cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Per-thread view of the frequencies of one tile (at most 16 per thread).
@@ -280,185 +282,218 @@ __device__ __forceinline__ void eval_freqs(const FreqRegs& f, double gam, double
 }
 
 // ---------------------------------------------------------------- grid ----
-// Job::i1 = number of grid points.  Partials: 2 per point per tile.
+// Job::i1 = number of grid points; pr[0] = (min, max) partials of k_gcv_data.
+// Writes 2 partials (residual sum, trace) per grid point per tile.
 __global__ void __launch_bounds__(NTHREADS) k_gcv_grid(const Job* __restrict__ jobs,
                                                        const uint32_t* __restrict__ tiles) {
   __shared__ double red[2 * 4];
-  __shared__ int s_last;
+  __shared__ double bl, bh_;
   const Job* job; int ti, tj, tix;
   decode_tile(jobs, tiles, job, ti, tj, tix);
-  const int m = job->m, npts = job->i1;
+  const int m = job->m, npts = job->i1, nt = job->nti * job->ntj;
   int i0, j0, TI, TJ;
   tile_geom<float>(m, ti, tj, i0, j0, TI, TJ);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  // bounds: min / max of log10(s / lp) over the job (order-free)
+  double lo = 1e300, hi = -1e300;
+  for (int t = threadIdx.x; t < nt; t += NTHREADS) {
+    lo = fmin(lo, job->pr[0][2 * t]);
+    hi = fmax(hi, job->pr[0][2 * t + 1]);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, off, 64));
+    hi = fmax(hi, __shfl_xor(hi, off, 64));
+  }
+  if (lane == 0) { red[wid] = lo; red[4 + wid] = hi; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < 4; ++w) { lo = fmin(lo, red[w]); hi = fmax(hi, red[4 + w]); }
+    bl = fmax(lo, hi - 14.0);
+    bh_ = hi;
+  }
+  __syncthreads();
+  const double tlo = bl, thi = bh_;
+  if (tix == 0 && threadIdx.x == 0) {
+    job->scal[S_G_TLO] = tlo;
+    job->scal[S_G_THI] = thi;
+  }
   FreqRegs f;
   load_freqs(job, i0, j0, TI, TJ, f);
-  const double tlo = job->scal[S_G_TLO], thi = job->scal[S_G_THI];
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   for (int p = 0; p < npts; ++p) {
     const double t = tlo + (thi - tlo) * p / (npts - 1);
     double res, tr;
     eval_freqs(f, pow(10.0, t), res, tr);
     res = wave_sum(res);
     tr = wave_sum(tr);
+    __syncthreads();
     if (lane == 0) { red[wid] = res; red[4 + wid] = tr; }
     __syncthreads();
     if (threadIdx.x == 0) {
       double a = 0.0, b = 0.0;
       for (int w = 0; w < 4; ++w) { a += red[w]; b += red[4 + w]; }
-      __hip_atomic_store(job->part + (size_t)tix * 2 * npts + 2 * p, a, __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(job->part + (size_t)tix * 2 * npts + 2 * p + 1, b, __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
+      job->pw[(size_t)tix * 2 * npts + 2 * p] = a;
+      job->pw[(size_t)tix * 2 * npts + 2 * p + 1] = b;
     }
-    __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const unsigned prev = atomicAdd(job->cnt, 1u);
-    s_last = prev == unsigned(job->nti * job->ntj - 1);
-  }
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
-  // last block: one thread per grid point sums the tiles in order
-  const int nt = job->nti * job->ntj;
+}
+
+// One block per job: grid GCV values from the partials (pr[0], i1 tiles,
+// i0 points), lowest-index minimum, Brent's bracket and start state.
+__global__ void __launch_bounds__(NTHREADS) k_gcv_gridfin(const Job* __restrict__ jobs,
+                                                          const uint32_t* __restrict__ tiles) {
+  const Job* job = jobs + (tiles[blockIdx.x] >> 16);
+  const int npts = job->i0, nt = job->i1, n = job->m * job->m;
   double* sc = job->scal;
-  const int n = m * m;
+  const double tlo = sc[S_G_TLO], thi = sc[S_G_THI];
+  __shared__ double vals[DBL_GCV_GRID_MAX_DEV];
   if (threadIdx.x < npts) {
     const int p = threadIdx.x;
     double a = 0.0, b = 0.0;
     for (int t = 0; t < nt; ++t) {
-      a += __hip_atomic_load(job->part + (size_t)t * 2 * npts + 2 * p, __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
-      b += __hip_atomic_load(job->part + (size_t)t * 2 * npts + 2 * p + 1, __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
+      a += job->pr[0][(size_t)t * 2 * npts + 2 * p];
+      b += job->pr[0][(size_t)t * 2 * npts + 2 * p + 1];
     }
     const double t = tlo + (thi - tlo) * p / (npts - 1);
-    sc[S_GRID + p] = gcv_from(pow(10.0, t), a, b, n);
+    vals[p] = gcv_from(pow(10.0, t), a, b, n);
+    sc[S_GRID + p] = vals[p];
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int jb = 0;
-    double best = sc[S_GRID];
-    for (int p = 1; p < npts; ++p)
-      if (sc[S_GRID + p] < best) { best = sc[S_GRID + p]; jb = p; }
-    const double step = (thi - tlo) / (npts - 1);
-    const double a = tlo + step * (jb > 0 ? jb - 1 : 0);
-    const double b = tlo + step * (jb < npts - 1 ? jb + 1 : npts - 1);
-    const double golden = 0.5 * (3.0 - sqrt(5.0));
-    const double x = a + golden * (b - a);
-    put_scal(sc, S_G_A, a);
-    put_scal(sc, S_G_B, b);
-    put_scal(sc, S_G_X, x);
-    put_scal(sc, S_G_W, x);
-    put_scal(sc, S_G_V, x);
-    put_scal(sc, S_G_D, 0.0);
-    put_scal(sc, S_G_E, 0.0);
-    put_scal(sc, S_G_U, x);
-    put_scal(sc, S_G_IT, -1.0);  // -1: the next evaluation is the start point
-    put_scal(sc, S_G_DONE, 0.0);
-    put_scal(sc, S_G_NEV, 0.0);
-    __hip_atomic_store(job->cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
+  if (threadIdx.x != 0) return;
+  int jb = 0;
+  double best = vals[0];
+  for (int p = 1; p < npts; ++p)
+    if (vals[p] < best) { best = vals[p]; jb = p; }
+  const double step = (thi - tlo) / (npts - 1);
+  const double a = tlo + step * (jb > 0 ? jb - 1 : 0);
+  const double b = tlo + step * (jb < npts - 1 ? jb + 1 : npts - 1);
+  const double golden = 0.5 * (3.0 - sqrt(5.0));
+  const double x = a + golden * (b - a);
+  double* st = sc + S_BR;  // copy 0: read by the first Brent launch
+  for (int q = 0; q < BR_SIZE; ++q) st[q] = 0.0;
+  st[BR_A] = a;
+  st[BR_B] = b;
+  st[BR_X] = x;
+  st[BR_W] = x;
+  st[BR_V] = x;
+  st[BR_U] = x;
+  st[BR_IT] = -1.0;    // the first evaluation is the start point
+  st[BR_PHASE] = 0.0;  // nothing evaluated yet
+  st[BR_DONE] = 0.0;
 }
 
 // --------------------------------------------------------------- Brent ----
-// One evaluation per launch.  Job::i1 = max Brent steps; p0 = xtol.
+// Launch parity is Job::i0 (0 / 1): read state copy i0 and partials pr[0]
+// (previous evaluation), write state copy 1 - i0 and partials pw.
+// Job::i1 = max Brent steps; p0 = xtol.
 __global__ void __launch_bounds__(NTHREADS) k_gcv_brent(const Job* __restrict__ jobs,
                                                         const uint32_t* __restrict__ tiles) {
   __shared__ double red[8];
+  __shared__ double bc;
   const Job* job; int ti, tj, tix;
   decode_tile(jobs, tiles, job, ti, tj, tix);
   double* sc = job->scal;
-  if (sc[S_G_DONE] != 0.0) return;
-  const int m = job->m;
+  const int par = job->i0;
+  const double* in = sc + S_BR + par * BR_SIZE;
+  double* out = sc + S_BR + (1 - par) * BR_SIZE;
+  const bool owner = (tix == 0 && threadIdx.x == 0);
+  double st[BR_SIZE];
+#pragma unroll
+  for (int q = 0; q < BR_SIZE; ++q) st[q] = in[q];
+  if (st[BR_DONE] != 0.0) {
+    if (owner)
+      for (int q = 0; q < BR_SIZE; ++q) out[q] = st[q];
+    return;
+  }
+  const int m = job->m, n = m * m, nt = job->nti * job->ntj;
+  bool done = false;
+  if (st[BR_PHASE] == 0.0) {
+    st[BR_PHASE] = 1.0;  // evaluate at U (= the start point) below
+  } else {
+    // the previous launch evaluated GCV at U: total its partials
+    const double res = sum_partials<2>(job->pr[0], nt, 0, red, &bc);
+    const double tr = sum_partials<2>(job->pr[0], nt, 1, red, &bc);
+    const double u = st[BR_U];
+    const double fu = gcv_from(pow(10.0, u), res, tr, n);
+    const double golden = 0.5 * (3.0 - sqrt(5.0));
+    const double sqeps = sqrt(2.220446049250313e-16);
+    const double xtol = job->p0;
+    const int maxit = job->i1;
+    double a = st[BR_A], b = st[BR_B], x = st[BR_X], w = st[BR_W], v = st[BR_V];
+    double fx = st[BR_FX], fw = st[BR_FW], fv = st[BR_FV], d = st[BR_D], e = st[BR_E];
+    int it = (int)st[BR_IT];
+    if (it < 0) {
+      fx = fw = fv = fu;
+      it = 0;
+    } else {
+      if (fu <= fx) {
+        if (u >= x) a = x; else b = x;
+        v = w; fv = fw; w = x; fw = fx; x = u; fx = fu;
+      } else {
+        if (u < x) a = u; else b = u;
+        if (fu <= fw || w == x) { v = w; fv = fw; w = u; fw = fu; }
+        else if (fu <= fv || v == x || v == w) { v = u; fv = fu; }
+      }
+      it += 1;
+    }
+    done = it >= maxit;
+    double unext = x;
+    if (!done) {
+      const double xm = 0.5 * (a + b);
+      const double tol = sqeps * fabs(x) + xtol / 3.0;
+      const double tol2 = 2.0 * tol;
+      if (fabs(x - xm) <= tol2 - 0.5 * (b - a)) {
+        done = true;
+      } else {
+        bool use_golden = true;
+        if (fabs(e) > tol) {
+          double r = (x - w) * (fx - fv);
+          double q = (x - v) * (fx - fw);
+          double p = (x - v) * q - (x - w) * r;
+          q = 2.0 * (q - r);
+          if (q > 0.0) p = -p;
+          q = fabs(q);
+          const double e_prev = e;
+          e = d;
+          if (fabs(p) < fabs(0.5 * q * e_prev) && p > q * (a - x) && p < q * (b - x)) {
+            d = p / q;
+            const double uu = x + d;
+            if ((uu - a) < tol2 || (b - uu) < tol2) d = xm >= x ? tol : -tol;
+            use_golden = false;
+          }
+        }
+        if (use_golden) {
+          e = x >= xm ? (a - x) : (b - x);
+          d = golden * e;
+        }
+        unext = fabs(d) >= tol ? x + d : (d > 0.0 ? x + tol : x - tol);
+      }
+    }
+    st[BR_A] = a; st[BR_B] = b; st[BR_X] = x; st[BR_W] = w; st[BR_V] = v;
+    st[BR_FX] = fx; st[BR_FW] = fw; st[BR_FV] = fv; st[BR_D] = d; st[BR_E] = e;
+    st[BR_IT] = (double)it;
+    st[BR_U] = unext;
+    st[BR_DONE] = done ? 1.0 : 0.0;
+  }
+  if (owner) {
+    for (int q = 0; q < BR_SIZE; ++q) out[q] = st[q];
+    if (done) {
+      const double g = pow(10.0, st[BR_X]);
+      sc[S_GAMMA] = g;
+      sc[S_SQRTG] = sqrt(g);
+      sc[S_G_FBEST] = st[BR_FX];
+    }
+  }
+  if (done) return;
+  // evaluate GCV at U: per-tile partials (residual sum, trace)
   int i0, j0, TI, TJ;
   tile_geom<float>(m, ti, tj, i0, j0, TI, TJ);
   FreqRegs f;
   load_freqs(job, i0, j0, TI, TJ, f);
-  const double u = sc[S_G_U];
   double res, tr;
-  eval_freqs(f, pow(10.0, u), res, tr);
-  double vv[2] = {res, tr}, tot[2];
-  if (!job_reduce<2>(job, tix, vv, red, tot)) return;
-  // ---- state machine (thread 0 of the job's last block) ----
-  const int n = m * m;
-  const double fu = gcv_from(pow(10.0, u), tot[0], tot[1], n);
-  const double golden = 0.5 * (3.0 - sqrt(5.0));
-  const double sqeps = sqrt(2.220446049250313e-16);
-  const double xtol = job->p0;
-  const int maxit = job->i1;
-  double a = sc[S_G_A], b = sc[S_G_B], x = sc[S_G_X], w = sc[S_G_W], v = sc[S_G_V];
-  double fx = sc[S_G_FX], fw = sc[S_G_FW], fv = sc[S_G_FV], d = sc[S_G_D], e = sc[S_G_E];
-  int it = (int)sc[S_G_IT];
-  if (it < 0) {
-    fx = fw = fv = fu;
-    it = 0;
-  } else {
-    if (fu <= fx) {
-      if (u >= x) a = x; else b = x;
-      v = w; fv = fw; w = x; fw = fx; x = u; fx = fu;
-    } else {
-      if (u < x) a = u; else b = u;
-      if (fu <= fw || w == x) { v = w; fv = fw; w = u; fw = fu; }
-      else if (fu <= fv || v == x || v == w) { v = u; fv = fu; }
-    }
-    it += 1;
-  }
-  bool done = it >= maxit;
-  double unext = x;
-  if (!done) {
-    const double xm = 0.5 * (a + b);
-    const double tol = sqeps * fabs(x) + xtol / 3.0;
-    const double tol2 = 2.0 * tol;
-    if (fabs(x - xm) <= tol2 - 0.5 * (b - a)) {
-      done = true;
-    } else {
-      bool use_golden = true;
-      if (fabs(e) > tol) {
-        double r = (x - w) * (fx - fv);
-        double q = (x - v) * (fx - fw);
-        double p = (x - v) * q - (x - w) * r;
-        q = 2.0 * (q - r);
-        if (q > 0.0) p = -p;
-        q = fabs(q);
-        const double e_prev = e;
-        e = d;
-        if (fabs(p) < fabs(0.5 * q * e_prev) && p > q * (a - x) && p < q * (b - x)) {
-          d = p / q;
-          const double uu = x + d;
-          if ((uu - a) < tol2 || (b - uu) < tol2) d = xm >= x ? tol : -tol;
-          use_golden = false;
-        }
-      }
-      if (use_golden) {
-        e = x >= xm ? (a - x) : (b - x);
-        d = golden * e;
-      }
-      unext = fabs(d) >= tol ? x + d : (d > 0.0 ? x + tol : x - tol);
-    }
-  }
-  put_scal(sc, S_G_A, a);
-  put_scal(sc, S_G_B, b);
-  put_scal(sc, S_G_X, x);
-  put_scal(sc, S_G_W, w);
-  put_scal(sc, S_G_V, v);
-  put_scal(sc, S_G_FX, fx);
-  put_scal(sc, S_G_FW, fw);
-  put_scal(sc, S_G_FV, fv);
-  put_scal(sc, S_G_D, d);
-  put_scal(sc, S_G_E, e);
-  put_scal(sc, S_G_IT, (double)it);
-  put_scal(sc, S_G_NEV, sc[S_G_NEV] + 1.0);
-  if (done) {
-    const double g = pow(10.0, x);
-    put_scal(sc, S_GAMMA, g);
-    put_scal(sc, S_SQRTG, sqrt(g));
-    put_scal(sc, S_G_FBEST, fx);
-    put_scal(sc, S_G_DONE, 1.0);
-  } else {
-    put_scal(sc, S_G_U, unext);
-  }
+  eval_freqs(f, pow(10.0, st[BR_U]), res, tr);
+  double vv[2] = {res, tr};
+  put_partials<2>(job->pw, tix, vv, red);
 }
 
 // -------------------------------------------------------------- launchers --
@@ -480,5 +515,9 @@ hipError_t launch_gcv_symbol(const LaunchArgs& la) {
 hipError_t launch_gcv_data(const LaunchArgs& la) { GLAUNCH(k_gcv_data, la); return hipGetLastError(); }
 hipError_t launch_gcv_grid(const LaunchArgs& la, int) { GLAUNCH(k_gcv_grid, la); return hipGetLastError(); }
 hipError_t launch_gcv_brent(const LaunchArgs& la) { GLAUNCH(k_gcv_brent, la); return hipGetLastError(); }
+hipError_t launch_gcv_gridfin(const LaunchArgs& la) {
+  GLAUNCH(k_gcv_gridfin, la);
+  return hipGetLastError();
+}
 
 }  // namespace dbl

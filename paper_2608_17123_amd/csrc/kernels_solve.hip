@@ -12,6 +12,9 @@
 //          beta = |s|^2 / gs
 // p, r1 and r2 are double-buffered (read one copy, write the other) because
 // the stencils read neighbours that other blocks update in the same launch.
+// The norms are per-tile FP64 partials: p1 writes |q|^2 partials and sums the
+// |s|^2 partials of the previous p2 (beta); p2 sums both (alpha) and writes
+// new |s|^2 and |r|^2 partials, which the next p1 reads.
 #include "launch.h"
 #include "stencil.h"
 
@@ -32,13 +35,17 @@ __device__ __forceinline__ int xs_elems(int H, int TI, int TJ) {
   return SEP ? (TI + 2 * H) * sep_lx(TJ, H) : col_lds_elems(TI, TJ, H);
 }
 
-template <typename T, int RB, bool SEP, class Epi>
+// Tile convolution.  `hook` runs once all threads are done reading the input
+// tile Xs (separable: between the two passes; general: after an extra sync,
+// which requires a copy of the input -- the general path instead runs the
+// hook before the convolution, so it must not overwrite Xs there).
+template <typename T, int RB, bool SEP, class Epi, class Hook = NoHook>
 __device__ __forceinline__ void conv_tile(const T* Xs, int H, void* scratch, const LevelOp& op,
                                           bool adj, int i0, int j0, int TI, int TJ, int m,
-                                          Epi epi) {
+                                          Epi epi, Hook hook = Hook()) {
   if constexpr (SEP) {
     sep_tile<T, RB>(Xs, H, static_cast<T*>(scratch), adj ? op.a0 : op.f0, adj ? op.a1 : op.f1,
-                    i0, j0, TI, TJ, m, epi);
+                    i0, j0, TI, TJ, m, epi, hook);
   } else {
     T* s_v = static_cast<T*>(scratch);
     short2* s_e = reinterpret_cast<short2*>(s_v + (2 * H + 1) * (2 * H + 1));
@@ -105,6 +112,7 @@ __global__ void __launch_bounds__(NTHREADS) k_cgls_p1(const Job* __restrict__ jo
                                                       const uint32_t* __restrict__ tiles) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red[8];
+  __shared__ double bc;
   const Job* job; int ti, tj, tix;
   decode_tile(jobs, tiles, job, ti, tj, tix);
   const int m = job->m;
@@ -114,7 +122,19 @@ __global__ void __launch_bounds__(NTHREADS) k_cgls_p1(const Job* __restrict__ jo
   const int H = SEP ? RB : op.R;
   T* Xs = reinterpret_cast<T*>(smem);
   void* scratch = Xs + xs_elems<SEP>(H, TI, TJ);
-  const T tb = (T)job->scal[S_BETA];
+  const int nt = job->nti * job->ntj;
+  double beta = 0.0;
+  if (!(job->flags & F_FIRST)) {  // iteration > 0: beta = |s_k|^2 / |s_{k-1}|^2
+    const double gcur = sum_partials<2>(job->pr[0], nt, 0, red, &bc);
+    const double gprev = sum_partials<2>(job->pr[1], nt, 0, red, &bc);
+    beta = gprev > 0.0 ? gcur / gprev : 0.0;
+    if ((job->flags & F_HIST) && tix == 0) {
+      const double rr = sum_partials<2>(job->pr[0], nt, 1, red, &bc);
+      if (threadIdx.x == 0 && job->i0 >= 1 && job->i0 <= HIST_MAX)
+        job->scal[S_HIST + job->i0 - 1] = rr;
+    }
+  }
+  const T tb = (T)beta;
   const double sg = job->scal[S_SQRTG];
   const bool irls = job->flags & F_IRLS;
   const T* __restrict__ s = vp<T>(job, V_S);
@@ -128,39 +148,38 @@ __global__ void __launch_bounds__(NTHREADS) k_cgls_p1(const Job* __restrict__ jo
   __syncthreads();
   double acc = 0.0;
   const size_t nx = (size_t)(m - 1) * m;
-  for (int o = threadIdx.x; o < TI * TJ; o += NTHREADS) {
-    const int i = o % TI, j = o / TI, gi = i0 + i, gj = j0 + j;
-    const size_t g = gi + (size_t)gj * m;
-    const T pc = Xs[xs_at<SEP>(i, j, H, TI, TJ)];
-    pb[g] = pc;
-    if (gi < m - 1) {
-      const size_t k = gi + (size_t)gj * (m - 1);
-      double d = (double)Xs[xs_at<SEP>(i + 1, j, H, TI, TJ)] - (double)pc;
-      if (irls) d *= (double)w[k];
-      const T qv = (T)(sg * d);
-      q2[k] = qv;
-      acc += (double)qv * (double)qv;
-    }
-    if (gj < m - 1) {
-      const size_t k = nx + g;
-      double d = (double)Xs[xs_at<SEP>(i, j + 1, H, TI, TJ)] - (double)pc;
-      if (irls) d *= (double)w[k];
-      const T qv = (T)(sg * d);
-      q2[k] = qv;
-      acc += (double)qv * (double)qv;
-    }
-  }
+  batched_pixels<8, 2, T>(
+      TI * TJ,
+      [&](int o, T* v) {
+        const int gi = i0 + o % TI, gj = j0 + o / TI;
+        const size_t g = gi + (size_t)gj * m;
+        v[0] = (irls && gi < m - 1) ? w[gi + (size_t)gj * (m - 1)] : T(1);
+        v[1] = (irls && gj < m - 1) ? w[nx + g] : T(1);
+      },
+      [&](int o, T* v) {
+        const int i = o % TI, j = o / TI, gi = i0 + i, gj = j0 + j;
+        const size_t g = gi + (size_t)gj * m;
+        const T pc = Xs[xs_at<SEP>(i, j, H, TI, TJ)];
+        pb[g] = pc;
+        if (gi < m - 1) {
+          const double d = ((double)Xs[xs_at<SEP>(i + 1, j, H, TI, TJ)] - (double)pc) * (double)v[0];
+          const T qv = (T)(sg * d);
+          q2[gi + (size_t)gj * (m - 1)] = qv;
+          acc += (double)qv * (double)qv;
+        }
+        if (gj < m - 1) {
+          const double d = ((double)Xs[xs_at<SEP>(i, j + 1, H, TI, TJ)] - (double)pc) * (double)v[1];
+          const T qv = (T)(sg * d);
+          q2[nx + g] = qv;
+          acc += (double)qv * (double)qv;
+        }
+      });
   conv_tile<T, RB, SEP>(Xs, H, scratch, op, false, i0, j0, TI, TJ, m, [&](int i, int j, T v) {
     q1[(i0 + i) + (size_t)(j0 + j) * m] = v;
     acc += (double)v * (double)v;
   });
-  double vv[1] = {acc}, tot[1];
-  if (job_reduce<1>(job, tix, vv, red, tot)) {
-    const double gs = job->scal[S_GS];
-    const double qq = tot[0];
-    put_scal(job->scal, S_QQ, qq);
-    put_scal(job->scal, S_ALPHA, qq > 0.0 ? gs / qq : 0.0);
-  }
+  double vv[1] = {acc};
+  put_partials<1>(job->pw, tix, vv, red);
 }
 
 // --------------------------------------------------------------- phase 2 --
@@ -169,6 +188,7 @@ __global__ void __launch_bounds__(NTHREADS) k_cgls_p2(const Job* __restrict__ jo
                                                       const uint32_t* __restrict__ tiles) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red[8];
+  __shared__ double bc;
   const Job* job; int ti, tj, tix;
   decode_tile(jobs, tiles, job, ti, tj, tix);
   const int m = job->m;
@@ -180,7 +200,13 @@ __global__ void __launch_bounds__(NTHREADS) k_cgls_p2(const Job* __restrict__ jo
   void* scratch = Xs + xs_elems<SEP>(H, TI, TJ);
   const bool first = job->flags & F_FIRST;
   const bool irls = job->flags & F_IRLS;
-  const double alpha = first ? 0.0 : job->scal[S_ALPHA];
+  const int nt = job->nti * job->ntj;
+  double alpha = 0.0;
+  if (!first) {  // alpha = |s|^2 / |q|^2
+    const double qq = sum_partials<1>(job->pr[0], nt, 0, red, &bc);
+    const double gs = sum_partials<2>(job->pr[1], nt, 0, red, &bc);
+    alpha = qq > 0.0 ? gs / qq : 0.0;
+  }
   const T ta = (T)alpha;
   const double sg = job->scal[S_SQRTG];
   T* __restrict__ x = vp<T>(job, V_X);
@@ -202,64 +228,104 @@ __global__ void __launch_bounds__(NTHREADS) k_cgls_p2(const Job* __restrict__ jo
   }
   __syncthreads();
   double accr = 0.0, accs = 0.0;
-  for (int o = threadIdx.x; o < TI * TJ; o += NTHREADS) {
-    const int i = o % TI, j = o / TI;
-    const size_t g = (i0 + i) + (size_t)(j0 + j) * m;
-    const T rv = Xs[xs_at<SEP>(i, j, H, TI, TJ)];
-    r1b[g] = rv;
-    accr += (double)rv * (double)rv;
-    if (!first) x[g] = x[g] + ta * p[g];
-  }
+  batched_pixels<8, 2, T>(
+      TI * TJ,
+      [&](int o, T* v) {
+        const size_t g = (i0 + o % TI) + (size_t)(j0 + o / TI) * m;
+        if (!first) {
+          v[0] = x[g];
+          v[1] = p[g];
+        }
+      },
+      [&](int o, T* v) {
+        const int i = o % TI, j = o / TI;
+        const size_t g = (i0 + i) + (size_t)(j0 + j) * m;
+        const T rv = Xs[xs_at<SEP>(i, j, H, TI, TJ)];
+        r1b[g] = rv;
+        accr += (double)rv * (double)rv;
+        if (!first) x[g] = v[0] + ta * v[1];
+      });
   const size_t nx = (size_t)(m - 1) * m;
-  auto r2n = [&](size_t k) -> T { return first ? r2a[k] : (T)(r2a[k] - ta * q2[k]); };
-  auto wk = [&](size_t k) -> double { return irls ? (double)w[k] : 1.0; };
-  conv_tile<T, RB, SEP>(Xs, H, scratch, op, true, i0, j0, TI, TJ, m, [&](int i, int j, T v) {
-    const int gi = i0 + i, gj = j0 + j;
-    const size_t g = gi + (size_t)gj * m;
-    double lt = 0.0;
-    if (gi >= 1) {
-      const size_t k = gi - 1 + (size_t)gj * (m - 1);
-      lt += wk(k) * (double)r2n(k);
-    }
-    if (gi < m - 1) {
-      const size_t k = gi + (size_t)gj * (m - 1);
-      const T rn = r2n(k);
-      r2b[k] = rn;
-      accr += (double)rn * (double)rn;
-      lt -= wk(k) * (double)rn;
-    }
-    if (gj >= 1) {
-      const size_t k = nx + g - m;
-      lt += wk(k) * (double)r2n(k);
-    }
-    if (gj < m - 1) {
-      const size_t k = nx + g;
-      const T rn = r2n(k);
-      r2b[k] = rn;
-      accr += (double)rn * (double)rn;
-      lt -= wk(k) * (double)rn;
-    }
-    const T sv = (T)((double)v + sg * lt);
-    s[g] = sv;
-    accs += (double)sv * (double)sv;
-  });
-  double vv[2] = {accs, accr}, tot[2];
-  if (job_reduce<2>(job, tix, vv, red, tot)) {
-    double* sc = job->scal;
-    const double gs_new = tot[0];
-    const double gs_old = sc[S_GS];
-    put_scal(sc, S_BETA, (first || gs_old <= 0.0) ? 0.0 : gs_new / gs_old);
-    put_scal(sc, S_GS, gs_new);
-    put_scal(sc, S_RR, tot[1]);
-    if (first) {
-      put_scal(sc, S_GS0, gs_new);
-      put_scal(sc, S_ITER, 0.0);
-    } else if (job->flags & F_HIST) {
-      const int it = (int)sc[S_ITER];
-      if (it < NSCAL - S_HIST) put_scal(sc, S_HIST + it, tot[1]);
-      put_scal(sc, S_ITER, (double)(it + 1));
-    }
+  // Gradient part: LT[i, j] = sqrt(g) (L^T (w r2_new))[i, j] for the tile,
+  // computed cooperatively (coalesced loads, all threads) into LDS, and
+  // r2_new written for the tile's own gradient entries.
+  T* LT = nullptr;
+  auto grad_part = [&](T* buf) {
+    LT = buf;
+    // per pixel: entries qx(i-1,j), qx(i,j), qy(i,j-1), qy(i,j) -> (r2a, q2, w)
+    batched_pixels<4, 12, T>(
+        TI * TJ,
+        [&](int o, T* v) {
+          const int gi = i0 + o % TI, gj = j0 + o / TI;
+          const size_t g = gi + (size_t)gj * m;
+          size_t ks[4];
+          bool ok[4];
+          ok[0] = gi >= 1;      ks[0] = gi - 1 + (size_t)gj * (m - 1);
+          ok[1] = gi < m - 1;   ks[1] = gi + (size_t)gj * (m - 1);
+          ok[2] = gj >= 1;      ks[2] = nx + g - m;
+          ok[3] = gj < m - 1;   ks[3] = nx + g;
+#pragma unroll
+          for (int d = 0; d < 4; ++d) {
+            v[3 * d] = ok[d] ? r2a[ks[d]] : T(0);
+            v[3 * d + 1] = (ok[d] && !first) ? q2[ks[d]] : T(0);
+            v[3 * d + 2] = (ok[d] && irls) ? w[ks[d]] : T(1);
+          }
+        },
+        [&](int o, T* v) {
+          const int i = o % TI, j = o / TI, gi = i0 + i, gj = j0 + j;
+          const size_t g = gi + (size_t)gj * m;
+          T rn[4];
+#pragma unroll
+          for (int d = 0; d < 4; ++d) rn[d] = first ? v[3 * d] : (T)(v[3 * d] - ta * v[3 * d + 1]);
+          double lt = 0.0;
+          if (gi >= 1) lt += (double)v[2] * (double)rn[0];
+          if (gi < m - 1) {
+            r2b[gi + (size_t)gj * (m - 1)] = rn[1];
+            accr += (double)rn[1] * (double)rn[1];
+            lt -= (double)v[5] * (double)rn[1];
+          }
+          if (gj >= 1) lt += (double)v[8] * (double)rn[2];
+          if (gj < m - 1) {
+            r2b[nx + g] = rn[3];
+            accr += (double)rn[3] * (double)rn[3];
+            lt -= (double)v[11] * (double)rn[3];
+          }
+          buf[i + j * TI] = (T)(sg * lt);
+        });
+    __syncthreads();
+  };
+  if constexpr (SEP) {
+    conv_tile<T, RB, SEP>(
+        Xs, H, scratch, op, true, i0, j0, TI, TJ, m,
+        [&](int i, int j, T v) {
+          const size_t g = (i0 + i) + (size_t)(j0 + j) * m;
+          const T sv = v + LT[i + j * TI];
+          s[g] = sv;
+          accs += (double)sv * (double)sv;
+        },
+        [&] { grad_part(Xs); });
+  } else {
+    grad_part(reinterpret_cast<T*>(scratch) + (2 * H + 1) * (2 * H + 1) * 2);
+    conv_tile<T, RB, SEP>(Xs, H, scratch, op, true, i0, j0, TI, TJ, m, [&](int i, int j, T v) {
+      const size_t g = (i0 + i) + (size_t)(j0 + j) * m;
+      const T sv = v + LT[i + j * TI];
+      s[g] = sv;
+      accs += (double)sv * (double)sv;
+    });
   }
+  double vv[2] = {accs, accr};
+  put_partials<2>(job->pw, tix, vv, red);
+}
+
+// Residual norm after the last CGLS iteration (one block per job): sums the
+// |r|^2 partials of the final p2 into scal[S_HIST + i0].
+__global__ void __launch_bounds__(NTHREADS) k_cgls_hist(const Job* __restrict__ jobs,
+                                                        const uint32_t* __restrict__ tiles) {
+  __shared__ double red[8];
+  __shared__ double bc;
+  const Job* job = jobs + (tiles[blockIdx.x] >> 16);
+  const double rr = sum_partials<2>(job->pr[0], job->i1, 1, red, &bc);
+  if (threadIdx.x == 0 && job->i0 >= 0 && job->i0 < HIST_MAX) job->scal[S_HIST + job->i0] = rr;
 }
 
 // ------------------------------------------------------------------- aux --
@@ -267,7 +333,6 @@ __global__ void __launch_bounds__(NTHREADS) k_cgls_p2(const Job* __restrict__ jo
 template <typename T>
 __global__ void __launch_bounds__(NTHREADS) k_aux(const Job* __restrict__ jobs,
                                                   const uint32_t* __restrict__ tiles) {
-  __shared__ double red[8];
   const Job* job; int ti, tj, tix;
   decode_tile(jobs, tiles, job, ti, tj, tix);
   const int m = job->m;
@@ -280,7 +345,6 @@ __global__ void __launch_bounds__(NTHREADS) k_aux(const Job* __restrict__ jobs,
   T* __restrict__ c1 = vp<T>(job, V_C1);
   T* __restrict__ c2 = vp<T>(job, V_C2);
   const size_t nx = (size_t)(m - 1) * m;
-  double wsq = 0.0;
   for (int o = threadIdx.x; o < TI * TJ; o += NTHREADS) {
     const int gi = i0 + o % TI, gj = j0 + o / TI;
     const size_t g = gi + (size_t)gj * m;
@@ -291,9 +355,7 @@ __global__ void __launch_bounds__(NTHREADS) k_aux(const Job* __restrict__ jobs,
       const double u = (dir == 0 ? (double)x[g + 1] : (double)x[g + m]) - xc;
       if (mode == AUX_IRLS_W) {
         const double a = fabs(u) > eps ? fabs(u) : eps;
-        const T wv = (T)(1.0 / sqrt(a));
-        w[k] = wv;
-        wsq += (double)wv * (double)wv;
+        w[k] = (T)(1.0 / sqrt(a));
       } else if (mode == AUX_MM_W) {
         c1[k] = (T)(u * (1.0 - sqrt(eps * eps / (u * u + eps * eps))));
       } else {
@@ -306,8 +368,6 @@ __global__ void __launch_bounds__(NTHREADS) k_aux(const Job* __restrict__ jobs,
       }
     }
   }
-  double vv[1] = {wsq}, tot[1];
-  if (job_reduce<1>(job, tix, vv, red, tot)) put_scal(job->scal, S_WSQ, tot[0]);
 }
 
 // ----------------------------------------------------------------- stats --
@@ -358,20 +418,32 @@ __global__ void __launch_bounds__(NTHREADS) k_stats(const Job* __restrict__ jobs
     const double r = (double)v - (double)b[(i0 + i) + (size_t)(j0 + j) * m];
     res += r * r;
   });
-  double vv[4] = {num, den, res, pen}, tot[4];
-  if (job_reduce<4>(job, tix, vv, red, tot)) {
-    const double gam = job->scal[S_GAMMA];
-    double coef;
-    if (fl & F_IRLS) coef = 2.0 * gam;
-    else if (fl & F_MM) coef = 2.0 * eps * gam;
-    else coef = 2.0 * job->p1 * gam;
-    const double rc = tot[1] > 0.0 ? sqrt(tot[0] / tot[1]) : __builtin_nan("");
-    double* h = job->hist + 3 * job->i0;
-    __hip_atomic_store(h + 0, gam, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(h + 1, rc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(h + 2, tot[2] + coef * tot[3], __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
-  }
+  double vv[4] = {num, den, res, pen};
+  put_partials<4>(job->pw, tix, vv, red);
+}
+
+// One block per job: total the stats partials (pr[0], i1 tiles) and write
+// (gamma, RC, objective) to hist[3 * i0 ...].
+__global__ void __launch_bounds__(NTHREADS) k_stats_fin(const Job* __restrict__ jobs,
+                                                        const uint32_t* __restrict__ tiles) {
+  __shared__ double red[8];
+  __shared__ double bc;
+  const Job* job = jobs + (tiles[blockIdx.x] >> 16);
+  const int nt = job->i1;
+  double tot[4];
+  for (int c = 0; c < 4; ++c) tot[c] = sum_partials<4>(job->pr[0], nt, c, red, &bc);
+  if (threadIdx.x != 0) return;
+  const int fl = job->flags;
+  const double gam = job->scal[S_GAMMA], eps = job->p0;
+  double coef;
+  if (fl & F_IRLS) coef = 2.0 * gam;
+  else if (fl & F_MM) coef = 2.0 * eps * gam;
+  else coef = 2.0 * job->p1 * gam;
+  const double rc = tot[1] > 0.0 ? sqrt(tot[0] / tot[1]) : __builtin_nan("");
+  double* h = job->hist + 3 * job->i0;
+  h[0] = gam;
+  h[1] = rc;
+  h[2] = tot[2] + coef * tot[3];
 }
 
 // ------------------------------------------------------------------ fill --
@@ -425,7 +497,8 @@ struct Dummy {};
       }                                                                                \
     } else {                                                                           \
       const size_t lds_ = sizeof(T) * col_lds_elems(ts_, ts_, H) +                     \
-                          (sizeof(T) + sizeof(short2)) * (2 * (H) + 1) * (2 * (H) + 1);\
+                          (2 * sizeof(T) + sizeof(short2)) * (2 * (H) + 1) * (2 * (H) + 1) + \
+                          sizeof(T) * ts_ * ts_;                                      \
       hipLaunchKernelGGL((KERNEL<T, 0, false>), dim3((la).ntiles), dim3(NTHREADS),    \
                          lds_, (la).stream, (la).jobs, (la).tiles);                    \
     }                                                                                  \
@@ -461,6 +534,18 @@ hipError_t launch_stats(const LaunchArgs& la, int precision, int sep, int rb, in
   }
 
 SIMPLE_LAUNCHER(launch_cgls_init, k_cgls_init)
+
+hipError_t launch_stats_fin(const LaunchArgs& la) {
+  hipLaunchKernelGGL(k_stats_fin, dim3(la.ntiles), dim3(NTHREADS), 0, la.stream, la.jobs,
+                     la.tiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_cgls_hist(const LaunchArgs& la) {
+  hipLaunchKernelGGL(k_cgls_hist, dim3(la.ntiles), dim3(NTHREADS), 0, la.stream, la.jobs,
+                     la.tiles);
+  return hipGetLastError();
+}
 SIMPLE_LAUNCHER(launch_aux, k_aux)
 SIMPLE_LAUNCHER(launch_fill, k_fill)
 

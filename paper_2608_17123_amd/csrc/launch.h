@@ -44,6 +44,8 @@ hipError_t launch_cgls_p2(const LaunchArgs& la, int precision, int sep, int rb, 
 hipError_t launch_aux(const LaunchArgs& la, int precision);
 hipError_t launch_stats(const LaunchArgs& la, int precision, int sep, int rb, int H);
 hipError_t launch_fill(const LaunchArgs& la, int precision);
+hipError_t launch_stats_fin(const LaunchArgs& la);
+hipError_t launch_cgls_hist(const LaunchArgs& la);
 
 // aux modes (Job::i0)
 enum AuxMode : int {
@@ -60,5 +62,6 @@ hipError_t launch_gcv_symbol(const LaunchArgs& la);
 hipError_t launch_gcv_data(const LaunchArgs& la);
 hipError_t launch_gcv_grid(const LaunchArgs& la, int ngroups);
 hipError_t launch_gcv_brent(const LaunchArgs& la);
+hipError_t launch_gcv_gridfin(const LaunchArgs& la);
 
 }  // namespace dbl

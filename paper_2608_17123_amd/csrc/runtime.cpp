@@ -97,6 +97,60 @@ int stage_checkpoint(dbl_ctx* ctx) {
   return DBL_OK;
 }
 
+// ------------------------------------------------------------ profiling ----
+
+hipEvent_t prof_event(dbl_ctx* ctx) {
+  if (ctx->prof_pool.empty()) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  hipEvent_t e = ctx->prof_pool.back();
+  ctx->prof_pool.pop_back();
+  return e;
+}
+
+int prof_id(dbl_ctx* ctx, const char* name) {
+  for (size_t i = 0; i < ctx->prof_names.size(); ++i)
+    if (ctx->prof_names[i] == name) return (int)i;
+  ctx->prof_names.push_back(name);
+  ctx->prof_launches.push_back(0);
+  ctx->prof_ms.push_back(0.0);
+  ctx->prof_bytes.push_back(0.0);
+  return (int)ctx->prof_names.size() - 1;
+}
+
+int prof_collect(dbl_ctx* ctx) {
+  if (ctx->prof_pending.empty()) return DBL_OK;
+  int rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "profile sync");
+  if (rc) return rc;
+  for (auto& p : ctx->prof_pending) {
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, p.a, p.b);
+    ctx->prof_launches[p.id] += 1;
+    ctx->prof_ms[p.id] += ms;
+    ctx->prof_bytes[p.id] += p.bytes;
+    ctx->prof_pool.push_back(p.a);
+    ctx->prof_pool.push_back(p.b);
+  }
+  ctx->prof_pending.clear();
+  return DBL_OK;
+}
+
+double job_bytes(const char* k, const Job& j, size_t esz) {
+  const double n = (double)j.m * j.m, nl = 2.0 * j.m * (j.m - 1);
+  const bool irls = j.flags & F_IRLS;
+  const std::string s(k);
+  double e = 0.0;  // elements moved
+  if (s == "cgls_p1") e = 2 * n + 2 * n + nl + (irls ? nl : 0);            // s, p in; p, q1, q2 out
+  else if (s == "cgls_p2") e = 7 * n + 3 * nl + (irls ? nl : 0);           // r1,q1,x,p in; r1,x,s out; r2,q2 in; r2 out
+  else if (s == "apply_A") e = 2 * n;
+  else if (s == "stats") e = 3 * n;
+  else if (s == "aux") e = n + 2 * nl;
+  else if (s == "cgls_init") e = 3 * n + 2 * nl;
+  return e * (double)esz;
+}
+
 int tiles_per_axis(int grid_m, int esz) {
   const int ts = esz == 8 ? 32 : 64;
   return grid_m < ts ? 1 : grid_m / ts;
@@ -104,7 +158,24 @@ int tiles_per_axis(int grid_m, int esz) {
 
 size_t part_doubles(int m) {
   const size_t t4 = (size_t)tiles_per_axis(m, 4), t8 = (size_t)tiles_per_axis(m, 8);
-  return t4 * t4 * 2 * DBL_GCV_GRID_MAX + t8 * t8 * 8;
+  return 9 * t8 * t8 + (5 + 2 * DBL_GCV_GRID_MAX + 2) * t4 * t4 + 64;
+}
+
+PartLayout part_layout(double* base, int m) {
+  const size_t t4 = (size_t)tiles_per_axis(m, 4), t8 = (size_t)tiles_per_axis(m, 8);
+  const size_t nt = t8 * t8, ng = t4 * t4;  // nt bounds the tile count of either precision
+  PartLayout L;
+  double* p = base;
+  L.q = p; p += nt;
+  L.s[0] = p; p += 2 * nt;
+  L.s[1] = p; p += 2 * nt;
+  L.st = p; p += 4 * nt;
+  L.gw = p; p += ng;
+  L.gmm = p; p += 2 * ng;
+  L.ggrid = p; p += 2 * DBL_GCV_GRID_MAX * ng;
+  L.gb[0] = p; p += 2 * ng;
+  L.gb[1] = p; p += 2 * ng;
+  return L;
 }
 
 void Launch::add(const Job& j0, int grid_m, int esz) {
@@ -238,6 +309,59 @@ int op_build(dbl_ctx* ctx, const double* psf, int ph, int pw, int m, int levels,
   return DBL_OK;
 }
 
+static std::string op_key(const double* psf, int ph, int pw, int m, int levels, int wavelet,
+                          int precision) {
+  std::string k;
+  const int hdr[6] = {ph, pw, m, levels, wavelet, precision};
+  k.append(reinterpret_cast<const char*>(hdr), sizeof(hdr));
+  k.append(reinterpret_cast<const char*>(psf), sizeof(double) * (size_t)ph * pw);
+  return k;
+}
+
+int op_acquire(dbl_ctx* ctx, const double* psf, int ph, int pw, int m, int levels, int wavelet,
+               int precision, dbl_op** out) {
+  const std::string key = op_key(psf, ph, pw, m, levels, wavelet, precision);
+  auto it = ctx->op_cache.find(key);
+  if (it != ctx->op_cache.end()) {
+    it->second.refs += 1;
+    it->second.last = ++ctx->op_clock;
+    *out = it->second.op;
+    return DBL_OK;
+  }
+  const size_t kMaxIdle = 64;
+  if (ctx->op_cache.size() >= kMaxIdle) {
+    // evict idle entries, oldest first, down to half the bound
+    std::vector<std::pair<unsigned long long, std::string>> idle;
+    for (auto& kv : ctx->op_cache)
+      if (kv.second.refs == 0) idle.push_back({kv.second.last, kv.first});
+    std::sort(idle.begin(), idle.end());
+    for (size_t q = 0; q < idle.size() && ctx->op_cache.size() >= kMaxIdle / 2; ++q) {
+      (void)hipStreamSynchronize(ctx->stream);
+      op_free(ctx->op_cache[idle[q].second].op);
+      ctx->op_cache.erase(idle[q].second);
+    }
+  }
+  dbl_op* op = nullptr;
+  int rc = op_build(ctx, psf, ph, pw, m, levels, wavelet, precision, &op);
+  if (rc) return rc;
+  ctx->op_cache[key] = {op, 1, ++ctx->op_clock};
+  *out = op;
+  return DBL_OK;
+}
+
+void op_release(dbl_ctx* ctx, dbl_op* op) {
+  for (auto& kv : ctx->op_cache)
+    if (kv.second.op == op) {
+      kv.second.refs -= 1;
+      return;
+    }
+}
+
+void op_cache_clear(dbl_ctx* ctx) {
+  for (auto& kv : ctx->op_cache) op_free(kv.second.op);
+  ctx->op_cache.clear();
+}
+
 // --------------------------------------------------------------- slots ----
 
 static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
@@ -276,12 +400,13 @@ int slot_init(dbl_ctx* ctx, const dbl_request& req, Slot* s) {
     if (req.opts.mu_schedule)
       for (size_t i = 0; i < s->mu.size(); ++i) s->mu[i] = req.opts.mu_schedule[i];
   }
-  int rc = op_build(ctx, req.psf, req.ph, req.pw, req.m, req.levels, req.wavelet, s->prec, &s->op);
+  int rc = op_acquire(ctx, req.psf, req.ph, req.pw, req.m, req.levels, req.wavelet, s->prec,
+                      &s->op);
   if (rc) return rc;
   const size_t bytes = slot_bytes(req);
   rc = dmalloc(ctx, bytes, &s->block);
   if (rc) {
-    op_free(s->op);
+    op_release(ctx, s->op);
     s->op = nullptr;
     return rc;
   }
@@ -336,7 +461,7 @@ int slot_init(dbl_ctx* ctx, const dbl_request& req, Slot* s) {
 void slot_free(dbl_ctx* ctx, Slot* s) {
   if (s->block) dfree(ctx, s->block);
   s->block = nullptr;
-  if (s->op) op_free(s->op);
+  if (s->op) op_release(ctx, s->op);
   s->op = nullptr;
 }
 
@@ -408,7 +533,9 @@ int run_simple(dbl_ctx* ctx, SimpleFn fn, std::map<int, Launch>& byprec, const c
     LaunchArgs la;
     int rc = kv.second.upload(ctx, la);
     if (rc) return rc;
-    rc = hip_check(ctx, fn(la, kv.first), what);
+    double b = 0.0;
+    for (const Job& jj : kv.second.jobs) b += job_bytes(what, jj, kv.first == 1 ? 8 : 4);
+    rc = hip_check(ctx, timed(ctx, what, b, [&] { return fn(la, kv.first); }), what);
     if (rc) return rc;
   }
   return DBL_OK;
@@ -464,7 +591,7 @@ int engine_step(dbl_ctx* ctx, std::vector<Slot*>& slots) {
         j.p0 = 0.0;
         L[s->prec].add(j, j.m >> 1, (int)s->esz);
       }
-      if ((rc = run_simple(ctx, launch_dwt_fwd, L, "restrict b"))) return rc;
+      if ((rc = run_simple(ctx, launch_dwt_fwd, L, "dwt_fwd"))) return rc;
     }
     std::map<int, Launch> fillL, prolL, auxL, finL, xferL;
     std::vector<Slot*> dslots;
@@ -497,9 +624,9 @@ int engine_step(dbl_ctx* ctx, std::vector<Slot*>& slots) {
         dslots.push_back(s);
       }
     }
-    if ((rc = run_simple(ctx, launch_fill, fillL, "approach I start"))) return rc;
-    if ((rc = run_simple(ctx, launch_dwt_inv, prolL, "prolong"))) return rc;
-    if ((rc = run_simple(ctx, launch_aux, finL, "coarse aux"))) return rc;
+    if ((rc = run_simple(ctx, launch_fill, fillL, "fill"))) return rc;
+    if ((rc = run_simple(ctx, launch_dwt_inv, prolL, "dwt_inv"))) return rc;
+    if ((rc = run_simple(ctx, launch_aux, finL, "aux"))) return rc;
     for (Slot* s : act) {
       if (s->k != 0 || !s->started || s->transfer != DBL_XFER_X) continue;
       s->cur = 1 - s->cur;
@@ -527,7 +654,7 @@ int engine_step(dbl_ctx* ctx, std::vector<Slot*>& slots) {
       }
       add_fill(fillD, s, lv, s->X[s->cur], nullptr, 0.0);
     }
-    if ((rc = run_simple(ctx, launch_dtransfer, xferL, "approach D transfer"))) return rc;
+    if ((rc = run_simple(ctx, launch_dtransfer, xferL, "dtransfer"))) return rc;
     for (Slot* s : dslots) {
       if (s->solver == DBL_IRLS) std::swap(s->W, s->R2[0]);
       if (s->solver == DBL_MM) std::swap(s->C1, s->R2[0]);
@@ -536,8 +663,8 @@ int engine_step(dbl_ctx* ctx, std::vector<Slot*>& slots) {
         std::swap(s->C2, s->R2[1]);
       }
     }
-    if ((rc = run_simple(ctx, launch_fill, fillD, "approach D start"))) return rc;
-    if ((rc = run_simple(ctx, launch_aux, auxL, "approach X auxiliaries"))) return rc;
+    if ((rc = run_simple(ctx, launch_fill, fillD, "fill"))) return rc;
+    if ((rc = run_simple(ctx, launch_aux, auxL, "aux"))) return rc;
     for (Slot* s : act) s->started = true;
   }
 
@@ -549,7 +676,7 @@ int engine_step(dbl_ctx* ctx, std::vector<Slot*>& slots) {
       if (s->solver == DBL_IRLS) add_aux(L, s, s->level, AUX_IRLS_W, s->X[s->cur], s->W, nullptr, nullptr);
       if (s->solver == DBL_MM) add_aux(L, s, s->level, AUX_MM_W, s->X[s->cur], nullptr, s->C1, nullptr);
     }
-    if ((rc = run_simple(ctx, launch_aux, L, "outer auxiliaries"))) return rc;
+    if ((rc = run_simple(ctx, launch_aux, L, "aux"))) return rc;
   }
 
   // ---- C. the parameter gamma ----------------------------------------------
@@ -607,11 +734,12 @@ int engine_step(dbl_ctx* ctx, std::vector<Slot*>& slots) {
     std::stable_sort(ord.begin(), ord.end(),
                      [](const Slot* a, const Slot* b) { return a->opts.k_in > b->opts.k_in; });
     std::map<int, Launch> initL;
-    std::map<GroupKey, Launch> first, p1[2], p2[2];
+    std::map<GroupKey, Launch> first, p1f, p1[2], p2[2];
     std::map<GroupKey, std::vector<int>> kin;
     for (Slot* s : ord) {
       const int lv = s->level;
       const int nw = 1 - s->cur;
+      const PartLayout PL = part_layout(s->part, s->m >> lv);
       Job j = base_job(s, lv);
       j.flags = solver_flags(s);
       j.v[V_X] = s->X[nw];
@@ -634,27 +762,40 @@ int engine_step(dbl_ctx* ctx, std::vector<Slot*>& slots) {
       jf.v[V_R1B] = s->R1[1];
       jf.v[V_R2A] = s->R2[0];
       jf.v[V_R2B] = s->R2[1];
+      jf.pw = PL.s[0];
       first[gk].add(jf, jf.m, (int)s->esz);
       for (int par = 0; par < 2; ++par) {
         Job a = j;
         a.v[V_PA] = s->P[par];
         a.v[V_PB] = s->P[1 - par];
+        a.pw = PL.q;
+        a.pr[0] = PL.s[par];
+        a.pr[1] = PL.s[1 - par];
         p1[par][gk].add(a, a.m, (int)s->esz);
+        if (par == 0) {
+          Job a0 = a;
+          a0.flags |= F_FIRST;  // iteration 0: beta = 0
+          p1f[gk].add(a0, a0.m, (int)s->esz);
+        }
         Job b = j;
         b.v[V_PB] = s->P[1 - par];
         b.v[V_R1A] = s->R1[1 - par];
         b.v[V_R1B] = s->R1[par];
         b.v[V_R2A] = s->R2[1 - par];
         b.v[V_R2B] = s->R2[par];
+        b.pr[0] = PL.q;
+        b.pr[1] = PL.s[par];
+        b.pw = PL.s[1 - par];
         p2[par][gk].add(b, b.m, (int)s->esz);
       }
       kin[gk].push_back(s->opts.k_in);
     }
-    if ((rc = run_simple(ctx, launch_cgls_init, initL, "cgls init"))) return rc;
-    std::map<GroupKey, LaunchArgs> aF, a1[2], a2[2];
+    if ((rc = run_simple(ctx, launch_cgls_init, initL, "cgls_init"))) return rc;
+    std::map<GroupKey, LaunchArgs> aF, a1f, a1[2], a2[2];
     for (auto& kv : first) {
       const GroupKey& g = kv.first;
       if ((rc = kv.second.upload(ctx, aF[g]))) return rc;
+      if ((rc = p1f[g].upload(ctx, a1f[g]))) return rc;
       for (int par = 0; par < 2; ++par) {
         if ((rc = p1[par][g].upload(ctx, a1[par][g]))) return rc;
         if ((rc = p2[par][g].upload(ctx, a2[par][g]))) return rc;
@@ -662,7 +803,12 @@ int engine_step(dbl_ctx* ctx, std::vector<Slot*>& slots) {
     }
     for (auto& kv : aF) {
       const GroupKey& g = kv.first;
-      if ((rc = hip_check(ctx, launch_cgls_p2(kv.second, g.prec, g.sep, g.rb, g.H), "cgls p2")))
+      double b = 0.0;
+      for (const Job& jj : first[g].jobs) b += job_bytes("cgls_p2", jj, g.prec == 1 ? 8 : 4);
+      if ((rc = hip_check(ctx, timed(ctx, "cgls_p2", b, [&] {
+                            return launch_cgls_p2(kv.second, g.prec, g.sep, g.rb, g.H);
+                          }),
+                          "cgls p2")))
         return rc;
     }
     int kmax = 0;
@@ -675,9 +821,15 @@ int engine_step(dbl_ctx* ctx, std::vector<Slot*>& slots) {
         int q = 0;
         while (q < (int)ks.size() && ks[q] > it) ++q;
         if (!q) continue;
-        LaunchArgs la = a1[par][g];
+        LaunchArgs la = it == 0 ? a1f[g] : a1[par][g];
         la.ntiles = p1[par][g].tiles_upto[q - 1];
-        if ((rc = hip_check(ctx, launch_cgls_p1(la, g.prec, g.sep, g.rb, g.H), "cgls p1")))
+        double b = 0.0;
+        for (int jq = 0; jq < q; ++jq)
+          b += job_bytes("cgls_p1", p1[par][g].jobs[jq], g.prec == 1 ? 8 : 4);
+        if ((rc = hip_check(ctx, timed(ctx, "cgls_p1", b, [&] {
+                              return launch_cgls_p1(la, g.prec, g.sep, g.rb, g.H);
+                            }),
+                            "cgls p1")))
           return rc;
       }
       for (auto& kv : kin) {
@@ -688,7 +840,13 @@ int engine_step(dbl_ctx* ctx, std::vector<Slot*>& slots) {
         if (!q) continue;
         LaunchArgs la = a2[par][g];
         la.ntiles = p2[par][g].tiles_upto[q - 1];
-        if ((rc = hip_check(ctx, launch_cgls_p2(la, g.prec, g.sep, g.rb, g.H), "cgls p2")))
+        double b = 0.0;
+        for (int jq = 0; jq < q; ++jq)
+          b += job_bytes("cgls_p2", p2[par][g].jobs[jq], g.prec == 1 ? 8 : 4);
+        if ((rc = hip_check(ctx, timed(ctx, "cgls_p2", b, [&] {
+                              return launch_cgls_p2(la, g.prec, g.sep, g.rb, g.H);
+                            }),
+                            "cgls p2")))
           return rc;
       }
     }
@@ -700,9 +858,11 @@ int engine_step(dbl_ctx* ctx, std::vector<Slot*>& slots) {
     for (Slot* s : act)
       if (s->solver == DBL_SB)
         add_aux(L, s, s->level, AUX_SB_UPDATE, s->X[1 - s->cur], nullptr, s->C1, s->C2);
-    if ((rc = run_simple(ctx, launch_aux, L, "split Bregman update"))) return rc;
+    if ((rc = run_simple(ctx, launch_aux, L, "aux"))) return rc;
     std::map<GroupKey, Launch> S;
+    Launch F;
     for (Slot* s : act) {
+      const PartLayout PL = part_layout(s->part, s->m >> s->level);
       Job j = base_job(s, s->level);
       j.flags = solver_flags(s);
       j.v[V_X] = s->X[1 - s->cur];
@@ -711,13 +871,32 @@ int engine_step(dbl_ctx* ctx, std::vector<Slot*>& slots) {
       j.p0 = s->opts.eps;
       j.p1 = s->opts.tau;
       j.i0 = s->level * DBL_MAX_KOUT + s->k;
+      j.pw = PL.st;
       S[key_of(s, s->level)].add(j, j.m, (int)s->esz);
+      Job jf = j;
+      jf.pr[0] = PL.st;
+      const int t = tiles_per_axis(j.m, (int)s->esz);
+      jf.i1 = t * t;
+      F.add(jf, 1, 4);
     }
     for (auto& kv : S) {
       LaunchArgs la;
       if ((rc = kv.second.upload(ctx, la))) return rc;
       const GroupKey& g = kv.first;
-      if ((rc = hip_check(ctx, launch_stats(la, g.prec, g.sep, g.rb, g.H), "stats"))) return rc;
+      double b = 0.0;
+      for (const Job& jj : kv.second.jobs) b += job_bytes("stats", jj, g.prec == 1 ? 8 : 4);
+      if ((rc = hip_check(ctx, timed(ctx, "stats", b, [&] {
+                            return launch_stats(la, g.prec, g.sep, g.rb, g.H);
+                          }),
+                          "stats")))
+        return rc;
+    }
+    {
+      LaunchArgs la;
+      if ((rc = F.upload(ctx, la))) return rc;
+      if ((rc = hip_check(ctx, timed(ctx, "stats_fin", 0.0, [&] { return launch_stats_fin(la); }),
+                          "stats fin")))
+        return rc;
     }
   }
 

@@ -30,6 +30,19 @@ struct dbl_ctx {
   void* scratch = nullptr;
   size_t scratch_bytes = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // optional per-kernel timing (dbl_profile): event pairs around launches
+  bool prof_on = false;
+  struct ProfPending { int id; hipEvent_t a, b; double bytes; };
+  std::vector<ProfPending> prof_pending;
+  std::vector<hipEvent_t> prof_pool;
+  std::vector<std::string> prof_names;
+  std::vector<long long> prof_launches;
+  std::vector<double> prof_ms, prof_bytes;
+  // operator hierarchies shared by solves with identical (kernel, m, levels,
+  // wavelet, precision); entries without users are evicted beyond a bound
+  struct OpEntry { dbl_op* op; int refs; unsigned long long last; };
+  std::map<std::string, OpEntry> op_cache;
+  unsigned long long op_clock = 0;
 };
 
 struct dbl_op {
@@ -51,6 +64,34 @@ void dfree(dbl_ctx* ctx, void* p);
 int stage(dbl_ctx* ctx, const void* src, size_t bytes, void** dptr);
 int stage_checkpoint(dbl_ctx* ctx);
 
+// Per-kernel timing: when profiling is on, `launch` runs between two events on
+// the context stream and the launch is charged `bytes` algorithmic bytes.
+template <class F>
+hipError_t timed(dbl_ctx* ctx, const char* name, double bytes, F&& launch);
+int prof_collect(dbl_ctx* ctx);
+hipEvent_t prof_event(dbl_ctx* ctx);
+int prof_id(dbl_ctx* ctx, const char* name);
+
+template <class F>
+hipError_t timed(dbl_ctx* ctx, const char* name, double bytes, F&& launch) {
+  if (!ctx->prof_on) return launch();
+  dbl_ctx::ProfPending p;
+  p.id = prof_id(ctx, name);
+  p.a = prof_event(ctx);
+  p.b = prof_event(ctx);
+  p.bytes = bytes;
+  hipError_t e = hipEventRecord(p.a, ctx->stream);
+  if (e != hipSuccess) return e;
+  e = launch();
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(p.b, ctx->stream);
+  ctx->prof_pending.push_back(p);
+  return e;
+}
+
+// Algorithmic bytes of one job (each operand read or written once).
+double job_bytes(const char* kernel, const Job& j, size_t esz);
+
 // Jobs of one launch plus its tile table.
 struct Launch {
   std::vector<Job> jobs;
@@ -66,10 +107,22 @@ int tiles_per_axis(int grid_m, int esz);
 // FP64 partial-sum slots a job on an m x m grid may need (CGLS, GCV grid).
 size_t part_doubles(int m);
 
+// Partial-sum regions carved from one FP64 block for a grid of size m.
+struct PartLayout {
+  double *q, *s[2], *st;                  // CGLS |q|^2, |s|^2 & |r|^2 (x2), stats
+  double *gw, *gmm, *ggrid, *gb[2];       // GCV weights, bounds, grid, Brent (x2)
+};
+PartLayout part_layout(double* base, int m);
+
 // Build the hierarchy and upload its tables.
 int op_build(dbl_ctx* ctx, const double* psf, int ph, int pw, int m, int levels, int wavelet,
              int precision, dbl_op** out);
 void op_free(dbl_op* op);
+// Shared hierarchy from the context cache (reference counted).
+int op_acquire(dbl_ctx* ctx, const double* psf, int ph, int pw, int m, int levels, int wavelet,
+               int precision, dbl_op** out);
+void op_release(dbl_ctx* ctx, dbl_op* op);
+void op_cache_clear(dbl_ctx* ctx);
 
 // One V-cycle solve in flight.
 struct Slot {

@@ -45,27 +45,48 @@ __host__ __device__ inline int col_lds_elems(int TI, int TJ, int H) {
 }
 
 // Load the (TI+2H) x (TJ+2H) region starting at global (i0-H, j0-H) with
-// periodic wrap.  f(gi) returns the value at flat global index gi.
+// periodic wrap.  f(gi) returns the value at flat global index gi.  Loads are
+// issued in groups of U per thread before the LDS stores, so the whole tile
+// is requested in one or two memory round trips.
 template <typename T, bool ROWMAJOR, class F>
 __device__ __forceinline__ void load_tile(T* Xs, int ld, int i0, int j0, int TI, int TJ, int H,
                                           int m, F f) {
+  constexpr int U = sizeof(T) == 4 ? 16 : 8;
   const int NR = TI + 2 * H, NC = TJ + 2 * H, tot = NR * NC;
   const int msk = m - 1;
-  for (int idx = threadIdx.x; idx < tot; idx += NTHREADS) {
-    const int r = idx % NR, c = idx / NR;
-    const int gi = (i0 - H + r) & msk, gj = (j0 - H + c) & msk;
-    const T v = f(gi + gj * m);
-    if (ROWMAJOR) Xs[r * ld + c] = v; else Xs[c * ld + r] = v;
+  for (int base = threadIdx.x; base < tot; base += NTHREADS * U) {
+    T v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int idx = base + u * NTHREADS;
+      if (idx < tot) {
+        const int r = idx % NR, c = idx / NR;
+        const int gi = (i0 - H + r) & msk, gj = (j0 - H + c) & msk;
+        v[u] = f(gi + gj * m);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int idx = base + u * NTHREADS;
+      if (idx < tot) {
+        const int r = idx % NR, c = idx / NR;
+        if (ROWMAJOR) Xs[r * ld + c] = v[u]; else Xs[c * ld + r] = v[u];
+      }
+    }
   }
 }
 
 // Separable two-pass tile convolution.  Tables padded to radius RB (2RB+1
 // taps per row), RB <= H.  epi(i_local, j_local, value) consumes outputs;
 // every thread calls it for the outputs it owns (rows i, columns j..j+V-1).
-template <typename T, int RB, class Epi>
+struct NoHook {
+  __device__ __forceinline__ void operator()() const {}
+};
+
+template <typename T, int RB, class Epi, class Hook = NoHook>
 __device__ __forceinline__ void sep_tile(const T* __restrict__ Xs, int H, T* __restrict__ Zs,
                                          const Table1D& t0, const Table1D& t1, int i0, int j0,
-                                         int TI, int TJ, int m, Epi epi) {
+                                         int TI, int TJ, int m, Epi epi, Hook hook = Hook()) {
   constexpr int V = TileCfg<T>::V;
   constexpr int NT = 2 * RB + 1;
   constexpr int NW = V + 2 * RB;
@@ -120,6 +141,7 @@ __device__ __forceinline__ void sep_tile(const T* __restrict__ Xs, int H, T* __r
     }
   }
   __syncthreads();
+  hook();  // Xs is no longer read: the hook may reuse it (and must sync)
   // ---- pass B: along axis 1
   {
     T tp[NT];
@@ -200,6 +222,26 @@ __device__ __forceinline__ void gen_tile(const T* __restrict__ Xs, int H, const 
         a = fma(vals[k], Xs[(j + H + e.y) * LXC + (i + H + e.x)], a);
       }
       epi(i, j, a);
+    }
+  }
+}
+
+// Apply `body(o, vals)` to the thread's pixels o = tid, tid + NTHREADS, ...
+// of a tile with N pixels, U pixels at a time: `ld(o, vals)` first issues
+// every load of the group (into registers), then `body` consumes them.
+template <int U, int NV, typename T, class LD, class BODY>
+__device__ __forceinline__ void batched_pixels(int N, LD ld, BODY body) {
+  for (int base = threadIdx.x; base < N; base += NTHREADS * U) {
+    T vals[U][NV];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int o = base + u * NTHREADS;
+      if (o < N) ld(o, vals[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int o = base + u * NTHREADS;
+      if (o < N) body(o, vals[u]);
     }
   }
 }
