@@ -141,13 +141,13 @@ int gcv_run(dbl_ctx* ctx, std::vector<GcvReq>& reqs) {
       a.v[1] = base[q].v[G_IN];
       a.v[2] = base[q].v[G_TMP];
       a.i0 = 0;
-      g1.add(a, a.m, 4);
+      g1.add(a, a.m, 0);
       Job b = base[q];
       b.v[0] = base[q].v[G_TMP];
       b.v[1] = base[q].v[G_DCT];
       b.v[2] = base[q].v[out_slot];
       b.i0 = 1;
-      g2.add(b, b.m, 4);
+      g2.add(b, b.m, 0);
     }
     int r2 = run(launch_gemm64, g1, "gcv_dct_gemm");
     if (!r2) r2 = run(launch_gemm64, g2, "gcv_dct_gemm");

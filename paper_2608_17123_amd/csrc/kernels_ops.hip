@@ -28,7 +28,7 @@ __device__ __forceinline__ double wl_g(int wav, int k) {
 // ---------------------------------------------------------------- blur ----
 // v[0] = input, v[1] = output; flags & F_ADJ selects A^T.
 template <typename T, int RB>
-__global__ void __launch_bounds__(NTHREADS) k_apply_sep(const Job* __restrict__ jobs,
+__global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 3 : 2) k_apply_sep(const Job* __restrict__ jobs,
                                                         const uint32_t* __restrict__ tiles) {
   extern __shared__ __align__(16) unsigned char smem[];
   const Job* job; int ti, tj, tix;

@@ -108,7 +108,7 @@ __global__ void __launch_bounds__(NTHREADS) k_cgls_init(const Job* __restrict__ 
 
 // --------------------------------------------------------------- phase 1 --
 template <typename T, int RB, bool SEP>
-__global__ void __launch_bounds__(NTHREADS) k_cgls_p1(const Job* __restrict__ jobs,
+__global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 3 : 2) k_cgls_p1(const Job* __restrict__ jobs,
                                                       const uint32_t* __restrict__ tiles) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red[8];
@@ -184,7 +184,7 @@ __global__ void __launch_bounds__(NTHREADS) k_cgls_p1(const Job* __restrict__ jo
 
 // --------------------------------------------------------------- phase 2 --
 template <typename T, int RB, bool SEP>
-__global__ void __launch_bounds__(NTHREADS) k_cgls_p2(const Job* __restrict__ jobs,
+__global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 3 : 2) k_cgls_p2(const Job* __restrict__ jobs,
                                                       const uint32_t* __restrict__ tiles) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red[8];
@@ -375,7 +375,7 @@ __global__ void __launch_bounds__(NTHREADS) k_aux(const Job* __restrict__ jobs,
 // the solver penalty; the last block writes (gamma, RC, objective) to
 // job->hist[3 * i0 ...].  flags: F_IRLS / F_MM / F_SB select the penalty.
 template <typename T, int RB, bool SEP>
-__global__ void __launch_bounds__(NTHREADS) k_stats(const Job* __restrict__ jobs,
+__global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 3 : 2) k_stats(const Job* __restrict__ jobs,
                                                     const uint32_t* __restrict__ tiles) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red[16];

@@ -27,7 +27,7 @@ template <> __device__ __forceinline__ const float* taps2<float>(const Table2D& 
 template <> __device__ __forceinline__ const double* taps2<double>(const Table2D& t) { return t.vd; }
 
 template <typename T> struct TileCfg;
-template <> struct TileCfg<float> { static constexpr int TS = 64; static constexpr int V = 16; };
+template <> struct TileCfg<float> { static constexpr int TS = 32; static constexpr int V = 8; };
 template <> struct TileCfg<double> { static constexpr int TS = 32; static constexpr int V = 8; };
 
 // Row-major LDS tile (separable kernels): Xs[r * LX + c], r indexes axis 0
@@ -54,6 +54,7 @@ __device__ __forceinline__ void load_tile(T* Xs, int ld, int i0, int j0, int TI,
   constexpr int U = sizeof(T) == 4 ? 16 : 8;
   const int NR = TI + 2 * H, NC = TJ + 2 * H, tot = NR * NC;
   const int msk = m - 1;
+#pragma unroll 1
   for (int base = threadIdx.x; base < tot; base += NTHREADS * U) {
     T v[U];
 #pragma unroll
@@ -102,6 +103,7 @@ __device__ __forceinline__ void sep_tile(const T* __restrict__ Xs, int H, T* __r
     for (int e = 0; e < NT; ++e) tp[e] = T0[t0.St * NT + e];
     const int NC = TJ + 2 * RB;
     const int nch = (TI + V - 1) / V;
+#pragma unroll 1
     for (int item = threadIdx.x; item < NC * nch; item += NTHREADS) {
       const int c = item % NC, ch = item / NC;
       const int r0 = ch * V;
@@ -149,6 +151,7 @@ __device__ __forceinline__ void sep_tile(const T* __restrict__ Xs, int H, T* __r
     for (int e = 0; e < NT; ++e) tp[e] = T1[t1.St * NT + e];
     const int NC = TJ + 2 * RB;
     const int nch = (TJ + V - 1) / V;
+#pragma unroll 1
     for (int item = threadIdx.x; item < TI * nch; item += NTHREADS) {
       const int r = item % TI, ch = item / TI;
       const int c0 = ch * V;
@@ -231,6 +234,7 @@ __device__ __forceinline__ void gen_tile(const T* __restrict__ Xs, int H, const 
 // every load of the group (into registers), then `body` consumes them.
 template <int U, int NV, typename T, class LD, class BODY>
 __device__ __forceinline__ void batched_pixels(int N, LD ld, BODY body) {
+#pragma unroll 1
   for (int base = threadIdx.x; base < N; base += NTHREADS * U) {
     T vals[U][NV];
 #pragma unroll
