@@ -236,6 +236,9 @@ int dbl_deblur_batch(dbl_ctx* ctx, int count, const dbl_request* reqs, dbl_repor
  * boundaries while slots and the HBM budget allow. */
 int dbl_server_create(dbl_ctx* ctx, int max_slots, size_t hbm_budget_bytes, dbl_server** out);
 int dbl_server_destroy(dbl_server* srv);
+/* Device workspace bytes one resident solve of `req` needs (what admission
+ * by budget charges); 0 for an invalid request. */
+size_t dbl_request_bytes(const dbl_request* req);
 /* Queue a request; returns a ticket.  The psf is copied; b and x must stay
  * valid until the ticket completes. */
 int dbl_server_submit(dbl_server* srv, const dbl_request* req, int64_t* ticket);

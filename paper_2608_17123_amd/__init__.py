@@ -37,8 +37,8 @@ EXPORTS = [
     "dbl_create", "dbl_destroy", "dbl_last_error", "dbl_sync", "dbl_workspace_bytes",
     "dbl_opts_default", "dbl_profile", "dbl_profile_read", "dbl_op_create", "dbl_op_destroy", "dbl_apply_A", "dbl_apply_L",
     "dbl_dwt", "dbl_dtransfer", "dbl_cgls", "dbl_gcv", "dbl_deblur", "dbl_deblur_batch",
-    "dbl_server_create", "dbl_server_destroy", "dbl_server_submit", "dbl_server_step",
-    "dbl_server_poll",
+    "dbl_request_bytes", "dbl_server_create", "dbl_server_destroy", "dbl_server_submit",
+    "dbl_server_step", "dbl_server_poll",
 ]
 
 
@@ -116,6 +116,7 @@ def lib():
         "dbl_deblur": (i, [vp, vp, dp, i, i, i, i, i, i, i, ctypes.POINTER(dbl_opts), vp,
                            ctypes.POINTER(dbl_report)]),
         "dbl_deblur_batch": (i, [vp, i, ctypes.POINTER(dbl_request), ctypes.POINTER(dbl_report)]),
+        "dbl_request_bytes": (sz, [ctypes.POINTER(dbl_request)]),
         "dbl_server_create": (i, [vp, i, sz, ctypes.POINTER(vp)]),
         "dbl_server_destroy": (i, [vp]),
         "dbl_server_submit": (i, [vp, ctypes.POINTER(dbl_request), ctypes.POINTER(ctypes.c_int64)]),
@@ -358,6 +359,11 @@ def dbl_deblur_batch(ctx, requests):
     reps = (dbl_report * n)()
     _check(ctx, lib().dbl_deblur_batch(ctx.handle, n, arr, reps))
     return [reps[i].to_dict() for i in range(n)]
+
+
+def dbl_request_bytes(request):
+    """Workspace bytes a resident solve of `request` needs (0 if invalid)."""
+    return int(lib().dbl_request_bytes(ctypes.byref(request)))
 
 
 class Server:

@@ -67,6 +67,10 @@ int check_request(dbl_ctx* ctx, const dbl_request& r) {
 
 }  // namespace
 
+namespace dbl {
+int validate_request(dbl_ctx* ctx, const dbl_request& r) { return check_request(ctx, r); }
+}  // namespace dbl
+
 extern "C" {
 
 void dbl_opts_default(dbl_opts* o) {
@@ -121,12 +125,19 @@ int dbl_destroy(dbl_ctx* ctx) {
   }
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
+  (void)prof_collect(ctx);
+  // Cached operators free their own buffers (and untrack them) first; every
+  // allocation still tracked after that is freed exactly once below.  A
+  // second hipFree of a pointer would leave hipErrorInvalidValue as the
+  // thread's last error, where the caller's next launch check would find it.
+  op_cache_clear(ctx);
+  ctx->pool.clear();
+  ctx->pool_bytes = 0;
   for (auto& kv : ctx->dct) (void)hipFree(kv.second);
   for (auto& kv : ctx->allocs) (void)hipFree(kv.first);
+  ctx->allocs.clear();
   if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
   for (auto& b : ctx->retired) (void)hipHostFree(b.first);
-  (void)prof_collect(ctx);
-  op_cache_clear(ctx);
   for (hipEvent_t e : ctx->prof_pool) (void)hipEventDestroy(e);
   if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
   if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
@@ -511,6 +522,14 @@ int dbl_gcv(dbl_ctx* ctx, const dbl_op* op, int level, const dbl_sub* sub, const
   *gamma_out = out[0];
   if (gcv_out) *gcv_out = out[1];
   return DBL_OK;
+}
+
+size_t dbl_request_bytes(const dbl_request* req) {
+  if (!req) return 0;
+  dbl_ctx tmp;
+  tmp.device = -1;
+  if (check_request(&tmp, *req)) return 0;
+  return slot_bytes(*req);
 }
 
 int dbl_deblur(dbl_ctx* ctx, const void* b, const double* psf, int ph, int pw, int m, int solver,

@@ -22,6 +22,7 @@ int hip_check(dbl_ctx* ctx, hipError_t e, const char* what) {
 int dmalloc(dbl_ctx* ctx, size_t bytes, void** p) {
   *p = nullptr;
   if (bytes == 0) bytes = 256;
+  if (ctx->budget && ctx->used + bytes > ctx->budget && ctx->pool_bytes) pool_trim(ctx, 0);
   if (ctx->budget && ctx->used + bytes > ctx->budget)
     return set_err(ctx, DBL_ENOMEM, "device workspace budget exceeded");
   hipError_t e = hipMalloc(p, bytes);
@@ -43,6 +44,35 @@ void dfree(dbl_ctx* ctx, void* p) {
     ctx->allocs.erase(it);
   }
   (void)hipFree(p);
+}
+
+int pool_get(dbl_ctx* ctx, size_t bytes, void** p) {
+  auto it = ctx->pool.find(bytes);
+  if (it != ctx->pool.end()) {
+    *p = it->second;
+    ctx->pool.erase(it);
+    ctx->pool_bytes -= bytes;
+    return DBL_OK;
+  }
+  return dmalloc(ctx, bytes, p);
+}
+
+void pool_put(dbl_ctx* ctx, void* p, size_t bytes) {
+  if (!p) return;
+  ctx->pool.insert({bytes, p});
+  ctx->pool_bytes += bytes;
+  const size_t kKeep = size_t(8) << 30;
+  if (ctx->pool_bytes > kKeep) pool_trim(ctx, kKeep / 2);
+}
+
+void pool_trim(dbl_ctx* ctx, size_t keep_bytes) {
+  if (ctx->pool_bytes <= keep_bytes) return;
+  (void)hipStreamSynchronize(ctx->stream);
+  for (auto it = ctx->pool.begin(); it != ctx->pool.end() && ctx->pool_bytes > keep_bytes;) {
+    ctx->pool_bytes -= it->first;
+    dfree(ctx, it->second);
+    it = ctx->pool.erase(it);
+  }
 }
 
 // Copy `bytes` to the device through the staging buffer; the copy is queued
@@ -407,7 +437,7 @@ int slot_init(dbl_ctx* ctx, const dbl_request& req, Slot* s) {
                       &s->op);
   if (rc) return rc;
   const size_t bytes = slot_bytes(req);
-  rc = dmalloc(ctx, bytes, &s->block);
+  rc = pool_get(ctx, bytes, &s->block);
   if (rc) {
     op_release(ctx, s->op);
     s->op = nullptr;
@@ -462,7 +492,7 @@ int slot_init(dbl_ctx* ctx, const dbl_request& req, Slot* s) {
 }
 
 void slot_free(dbl_ctx* ctx, Slot* s) {
-  if (s->block) dfree(ctx, s->block);
+  if (s->block) pool_put(ctx, s->block, slot_bytes(s->req));
   s->block = nullptr;
   if (s->op) op_release(ctx, s->op);
   s->op = nullptr;

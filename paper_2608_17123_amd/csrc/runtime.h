@@ -40,6 +40,9 @@ struct dbl_ctx {
   std::vector<double> prof_ms, prof_bytes;
   // operator hierarchies shared by solves with identical (kernel, m, levels,
   // wavelet, precision); entries without users are evicted beyond a bound
+  // released solve workspaces kept for reuse (size -> block)
+  std::multimap<size_t, void*> pool;
+  size_t pool_bytes = 0;
   struct OpEntry { dbl_op* op; int refs; unsigned long long last; };
   std::map<std::string, OpEntry> op_cache;
   unsigned long long op_clock = 0;
@@ -61,6 +64,11 @@ int set_err(dbl_ctx* ctx, int code, const std::string& msg);
 int hip_check(dbl_ctx* ctx, hipError_t e, const char* what);
 int dmalloc(dbl_ctx* ctx, size_t bytes, void** p);
 void dfree(dbl_ctx* ctx, void* p);
+// Workspace blocks recycled through the context pool (no hipMalloc/hipFree
+// on the steady-state path).
+int pool_get(dbl_ctx* ctx, size_t bytes, void** p);
+void pool_put(dbl_ctx* ctx, void* p, size_t bytes);
+void pool_trim(dbl_ctx* ctx, size_t keep_bytes);
 int stage(dbl_ctx* ctx, const void* src, size_t bytes, void** dptr);
 int stage_checkpoint(dbl_ctx* ctx);
 
