@@ -141,6 +141,18 @@ typedef struct dbl_sub {
  * validates its arguments as usual and then returns DBL_EDEVICE. */
 int dbl_create(dbl_ctx** out, int device, void* hip_stream, size_t hbm_budget_bytes);
 int dbl_destroy(dbl_ctx* ctx);
+/* Context options (dbl_set_option). */
+typedef enum dbl_option {
+  /* 1 (default): a level with m <= 64 whose CGLS state fits in one block's
+   * LDS runs all K_in iterations of a subproblem in one launch (one block per
+   * subproblem); 0: every level uses the tiled two-phase launches.  Both
+   * compute the CGLS recurrence of eq. (augmented) with the same element
+   * arithmetic; the FP64 norm sums are ordered differently. */
+  DBL_OPT_SMALL_CGLS = 1
+} dbl_option;
+/* Set a context option.  Returns DBL_EINVAL for an unknown option or value.
+ * Takes effect for work issued afterwards. */
+int dbl_set_option(dbl_ctx* ctx, int option, long long value);
 /* Message describing the last error on ctx (never NULL). */
 const char* dbl_last_error(const dbl_ctx* ctx);
 /* Wait for all work issued by ctx. */

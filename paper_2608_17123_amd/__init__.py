@@ -27,6 +27,7 @@ DBL_XFER_X, DBL_XFER_D = 0, 1
 DBL_F32, DBL_F64 = 0, 1
 DBL_GCV_AUTO, DBL_GCV_EXACT, DBL_GCV_SPECTRAL = 0, 1, 2
 DBL_MAX_LEVELS, DBL_MAX_KOUT, DBL_GCV_GRID_MAX = 8, 64, 64
+DBL_OPT_SMALL_CGLS = 1
 
 SOLVERS = {"irls": DBL_IRLS, "mm": DBL_MM, "sb": DBL_SB}
 WAVELETS = {"haar": DBL_HAAR, "db4": DBL_DB4}
@@ -34,7 +35,7 @@ TRANSFERS = {"X": DBL_XFER_X, "D": DBL_XFER_D, "I": DBL_XFER_X}
 GCV_MODES = {"auto": DBL_GCV_AUTO, "exact": DBL_GCV_EXACT, "spectral": DBL_GCV_SPECTRAL}
 
 EXPORTS = [
-    "dbl_create", "dbl_destroy", "dbl_last_error", "dbl_sync", "dbl_workspace_bytes",
+    "dbl_create", "dbl_destroy", "dbl_set_option", "dbl_last_error", "dbl_sync", "dbl_workspace_bytes",
     "dbl_opts_default", "dbl_profile", "dbl_profile_read", "dbl_op_create", "dbl_op_destroy", "dbl_apply_A", "dbl_apply_L",
     "dbl_dwt", "dbl_dtransfer", "dbl_cgls", "dbl_gcv", "dbl_deblur", "dbl_deblur_batch",
     "dbl_request_bytes", "dbl_server_create", "dbl_server_destroy", "dbl_server_submit",
@@ -98,6 +99,7 @@ def lib():
     sig = {
         "dbl_create": (i, [ctypes.POINTER(vp), i, vp, sz]),
         "dbl_destroy": (i, [vp]),
+        "dbl_set_option": (i, [vp, i, ctypes.c_longlong]),
         "dbl_last_error": (ctypes.c_char_p, [vp]),
         "dbl_sync": (i, [vp]),
         "dbl_workspace_bytes": (sz, [vp]),
@@ -197,6 +199,10 @@ def dbl_create(device=0, stream=None, budget=0):
 
 def dbl_destroy(ctx):
     ctx.close()
+
+
+def dbl_set_option(ctx, option, value):
+    _check(ctx, lib().dbl_set_option(ctx.handle, int(option), int(value)))
 
 
 def dbl_sync(ctx):

@@ -109,12 +109,31 @@ int dbl_create(dbl_ctx** out, int device, void* hip_stream, size_t budget) {
   ctx->device = device;
   ctx->stream = static_cast<hipStream_t>(hip_stream);
   ctx->budget = budget;
+  int lds = 0;
+  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) ==
+          hipSuccess &&
+      lds > 0)
+    ctx->lds_limit = (size_t)lds;
+  else
+    (void)hipGetLastError();
   if (hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess) {
     delete ctx;
     return DBL_EDEVICE;
   }
   *out = ctx;
   return DBL_OK;
+}
+
+int dbl_set_option(dbl_ctx* ctx, int option, long long value) {
+  if (!ctx) return DBL_EINVAL;
+  switch (option) {
+    case DBL_OPT_SMALL_CGLS:
+      if (value != 0 && value != 1) return set_err(ctx, DBL_EINVAL, "DBL_OPT_SMALL_CGLS takes 0 or 1");
+      ctx->small_cgls = (int)value;
+      return DBL_OK;
+    default:
+      return set_err(ctx, DBL_EINVAL, "unknown option");
+  }
 }
 
 int dbl_destroy(dbl_ctx* ctx) {
@@ -319,7 +338,7 @@ int dbl_cgls(dbl_ctx* ctx, const dbl_op* op, int level, const dbl_sub* sub, cons
   if (!ctx || !op) return DBL_EINVAL;
   if (!sub || !b || !x) return set_err(ctx, DBL_EINVAL, "sub, b or x is NULL");
   if (level < 0 || level >= op->levels) return set_err(ctx, DBL_EINVAL, "level out of range");
-  if (iters < 0 || iters > NSCAL - S_HIST) return set_err(ctx, DBL_EINVAL, "iters out of range [0, 128]");
+  if (iters < 0 || iters > HIST_MAX) return set_err(ctx, DBL_EINVAL, "iters out of range [0, 128]");
   if (sub->d_kind != 0 && sub->d_kind != 1) return set_err(ctx, DBL_EINVAL, "bad d_kind");
   if (sub->d_kind == 1 && !sub->w) return set_err(ctx, DBL_EINVAL, "weights required for d_kind 1");
   if (!(sub->gamma >= 0.0) || !std::isfinite(sub->gamma)) return set_err(ctx, DBL_EINVAL, "gamma must be finite and >= 0");
@@ -376,6 +395,32 @@ int dbl_cgls(dbl_ctx* ctx, const dbl_op* op, int level, const dbl_sub* sub, cons
   j.v[V_B] = const_cast<void*>(b);
   j.v[V_C1] = const_cast<void*>(sub->c);
   const int sep = L.sep ? 1 : 0, rb = L.rb, H = L.sep ? L.rb : L.R;
+  int wl = 0;
+  const size_t small = x0 ? 0 : small_lds_bytes(ctx, op, level, sub->d_kind == 1, &wl);
+  if (small && iters > 0) {
+    Job js = j;
+    if (wl) js.flags |= F_WLDS;
+    js.v[V_C1] = const_cast<void*>(sub->c);
+    js.i0 = iters;
+    Launch Ls;
+    Ls.add(js, 1, 4);
+    LaunchArgs la;
+    if ((rc = Ls.upload(ctx, la))) return rc;
+    const double bytes = job_bytes("cgls_small", js, esz);
+    if ((rc = hip_check(ctx, timed(ctx, "cgls_small", bytes, [&] {
+                          return launch_cgls_small(la, prec, rb, m, small);
+                        }),
+                        "cgls small")))
+      return rc;
+    if (resid_hist) {
+      if ((rc = hip_check(ctx, hipMemcpyAsync(resid_hist, scal + S_HIST, iters * sizeof(double),
+                                              hipMemcpyDeviceToHost, ctx->stream),
+                          "read history")))
+        return rc;
+      if ((rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "sync"))) return rc;
+    }
+    return DBL_OK;
+  }
   if (x0) {
     Job ja = j;
     ja.v[0] = const_cast<void*>(x0);

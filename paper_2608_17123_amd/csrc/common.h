@@ -77,6 +77,43 @@ struct LevelOp {
   Table2D f2, a2;
 };
 
+// One-block CGLS for small levels (kernels_small.hip): a block of
+// small_nt(m, esz) threads keeps a whole level (separable operator) in LDS
+// for all iterations.  Byte layout of its dynamic LDS, shared by the host
+// (launch size, eligibility) and the kernel:
+//   XP, XR : p and r1 with a periodic halo of H, (m+2H) x (m+2H+1) each
+//   Z      : pass-A scratch (m+2H) x (m+1)
+//   S, Q1  : n each (s, then q1 = A p or the gradient part of s)
+//   R2     : n_L (gradient-space residual)
+//   W      : n_L IRLS weights, when they fit (else read from global memory)
+//   TB     : the level's four 1-D tap tables (tab_elems values)
+constexpr int SMALL_MAX_M = 64;
+// threads of the one-block CGLS for an m x m level with esz-byte elements:
+// one pixel per thread up to m = 16, then 512 threads (at 1024 the kernel's
+// registers would spill)
+__host__ __device__ constexpr int small_nt(int m, int esz) {
+  return (m >= 32 || esz == 0) ? 512 : m * m;
+}
+struct SmallLds {
+  int E, ld;
+  size_t halo, z, s, q1, r2, w, tb, total;  // byte offsets of the regions and the total
+};
+__host__ __device__ inline size_t align16(size_t b) { return (b + 15) & ~size_t(15); }
+__host__ __device__ inline SmallLds small_lds(int m, int H, int esz, bool wlds, int tab_elems) {
+  SmallLds L;
+  L.E = m + 2 * H;
+  L.ld = L.E + 1;
+  L.halo = align16((size_t)L.E * L.ld * esz);
+  L.z = 2 * L.halo;
+  L.s = L.z + align16((size_t)L.E * (m + 1) * esz);
+  L.q1 = L.s + align16((size_t)m * m * esz);
+  L.r2 = L.q1 + align16((size_t)m * m * esz);
+  L.w = L.r2 + align16((size_t)2 * m * (m - 1) * esz);
+  L.tb = L.w + (wlds ? align16((size_t)2 * m * (m - 1) * esz) : 0);
+  L.total = L.tb + align16((size_t)tab_elems * esz);
+  return L;
+}
+
 __host__ __device__ inline int class_of(int i, int m, int St, int Sb) {
   if (i < St) return i;
   if (i >= m - Sb) return St + 1 + (i - (m - Sb));
@@ -108,6 +145,7 @@ enum : int {
   F_ADJ = 16,       // transpose
   F_HIST = 32,      // record CGLS residual history
   F_FIRST = 64,     // first phase after init (alpha = 0)
+  F_WLDS = 128,     // one-block CGLS: IRLS weights staged in LDS
 };
 
 __device__ __forceinline__ void decode_tile(const Job* __restrict__ jobs,
@@ -128,9 +166,9 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Sum over the block (NTHREADS threads), result valid in thread 0.  `red`
-// must hold NTHREADS/64 doubles per value.  Order is fixed.
-template <int K>
+// Sum over the block (NT threads), result valid in thread 0.  `red` must
+// hold NT/64 doubles per value.  Order is fixed.
+template <int K, int NT = NTHREADS>
 __device__ __forceinline__ void block_sum(double (&v)[K], double* red) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
@@ -138,16 +176,38 @@ __device__ __forceinline__ void block_sum(double (&v)[K], double* red) {
   __syncthreads();
   if (lane == 0) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) red[k * (NTHREADS / 64) + wid] = v[k];
+    for (int k = 0; k < K; ++k) red[k * (NT / 64) + wid] = v[k];
   }
   __syncthreads();
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       double s = 0.0;
-      for (int w = 0; w < NTHREADS / 64; ++w) s += red[k * (NTHREADS / 64) + w];
+      for (int w = 0; w < NT / 64; ++w) s += red[k * (NT / 64) + w];
       v[k] = s;
     }
+  }
+}
+
+// Block sum with the totals returned in every thread: every thread adds the
+// per-wave sums in the same fixed order, so all of them hold the same bits.
+// `red` holds K * NT/64 doubles.
+template <int K, int NT = NTHREADS>
+__device__ __forceinline__ void block_allsum(double (&v)[K], double* red) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
+  __syncthreads();  // earlier readers of red are done
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) red[k * (NT / 64) + wid] = v[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double s = 0.0;
+    for (int w = 0; w < NT / 64; ++w) s += red[k * (NT / 64) + w];
+    v[k] = s;
   }
 }
 

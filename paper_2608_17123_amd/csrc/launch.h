@@ -46,6 +46,12 @@ hipError_t launch_stats(const LaunchArgs& la, int precision, int sep, int rb, in
 hipError_t launch_fill(const LaunchArgs& la, int precision);
 hipError_t launch_stats_fin(const LaunchArgs& la);
 hipError_t launch_cgls_hist(const LaunchArgs& la);
+// One-block CGLS (kernels_small.hip): one block per job, all iterations, for
+// levels with a separable operator.  Every job of a launch has m x m grids,
+// m in {8, 16, 32, 64}.
+size_t small_cgls_lds(int m, int precision, int rb, int tab_rows, bool irls, size_t limit,
+                      int* wlds);
+hipError_t launch_cgls_small(const LaunchArgs& la, int precision, int rb, int m, size_t lds);
 
 // aux modes (Job::i0)
 enum AuxMode : int {

@@ -178,6 +178,8 @@ double job_bytes(const char* k, const Job& j, size_t esz) {
   else if (s == "stats") e = 3 * n;
   else if (s == "aux") e = n + 2 * nl;
   else if (s == "cgls_init") e = 3 * n + 2 * nl;
+  else if (s == "cgls_small")  // the tiled path's traffic for the same iterations
+    e = 3 * n + 2 * nl + j.i0 * (11 * n + 4 * nl + (irls ? 2 * nl : 0)) + 7 * n + 3 * nl;
   return e * (double)esz;
 }
 
@@ -520,6 +522,15 @@ int slot_report(dbl_ctx* ctx, Slot* s, dbl_report* rep) {
   return DBL_OK;
 }
 
+size_t small_lds_bytes(const dbl_ctx* ctx, const dbl_op* op, int level, bool irls, int* wlds) {
+  *wlds = 0;
+  if (!ctx->small_cgls) return 0;
+  const LevelHost& L = op->host.levels[level];
+  if (!L.sep) return 0;
+  const int rows = L.f0.rows + L.f1.rows + L.a0.rows + L.a1.rows;
+  return small_cgls_lds(L.m, op->precision, L.rb, rows, irls, ctx->lds_limit, wlds);
+}
+
 // -------------------------------------------------------------- engine ----
 
 namespace {
@@ -769,6 +780,8 @@ int engine_step(dbl_ctx* ctx, std::vector<Slot*>& slots) {
     std::map<int, Launch> initL;
     std::map<GroupKey, Launch> first, p1f, p1[2], p2[2];
     std::map<GroupKey, std::vector<int>> kin;
+    std::map<std::pair<GroupKey, int>, Launch> smallL;  // by (group, m)
+    std::map<std::pair<GroupKey, int>, size_t> smallB;
     for (Slot* s : ord) {
       const int lv = s->level;
       const int nw = 1 - s->cur;
@@ -783,12 +796,22 @@ int engine_step(dbl_ctx* ctx, std::vector<Slot*>& slots) {
       j.v[V_B] = const_cast<void*>(s->B[lv]);
       j.v[V_C1] = s->C1;
       j.v[V_C2] = s->C2;
+      const GroupKey gk = key_of(s, lv);
+      int wl = 0;
+      if (const size_t lb = small_lds_bytes(ctx, s->op, lv, s->solver == DBL_IRLS, &wl)) {
+        Job js = j;
+        js.i0 = s->opts.k_in;
+        if (wl) js.flags |= F_WLDS;
+        const auto sk = std::make_pair(gk, js.m);
+        smallL[sk].add(js, 1, 4);
+        smallB[sk] = std::max(smallB[sk], lb);
+        continue;
+      }
       Job ji = j;
       ji.v[V_PA] = s->P[0];
       ji.v[V_R1A] = s->R1[0];
       ji.v[V_R2A] = s->R2[0];
       initL[s->prec].add(ji, ji.m, (int)s->esz);
-      const GroupKey gk = key_of(s, lv);
       Job jf = j;
       jf.flags |= F_FIRST;
       jf.v[V_R1A] = s->R1[0];
@@ -823,6 +846,20 @@ int engine_step(dbl_ctx* ctx, std::vector<Slot*>& slots) {
       }
       kin[gk].push_back(s->opts.k_in);
     }
+    for (auto& kv : smallL) {
+      const GroupKey& g = kv.first.first;
+      const int mm = kv.first.second;
+      LaunchArgs la;
+      if ((rc = kv.second.upload(ctx, la))) return rc;
+      double b = 0.0;
+      for (const Job& jj : kv.second.jobs) b += job_bytes("cgls_small", jj, g.prec == 1 ? 8 : 4);
+      const size_t lds = smallB[kv.first];
+      if ((rc = hip_check(ctx, timed(ctx, "cgls_small", b, [&] {
+                            return launch_cgls_small(la, g.prec, g.rb, mm, lds);
+                          }),
+                          "cgls small")))
+        return rc;
+    }
     if ((rc = run_simple(ctx, launch_cgls_init, initL, "cgls_init"))) return rc;
     std::map<GroupKey, LaunchArgs> aF, a1f, a1[2], a2[2];
     for (auto& kv : first) {
@@ -845,7 +882,8 @@ int engine_step(dbl_ctx* ctx, std::vector<Slot*>& slots) {
         return rc;
     }
     int kmax = 0;
-    for (Slot* s : ord) kmax = std::max(kmax, s->opts.k_in);
+    for (auto& kv : kin)
+      for (int k : kv.second) kmax = std::max(kmax, k);
     for (int it = 0; it < kmax; ++it) {
       const int par = it & 1;
       for (auto& kv : kin) {

@@ -46,6 +46,10 @@ struct dbl_ctx {
   struct OpEntry { dbl_op* op; int refs; unsigned long long last; };
   std::map<std::string, OpEntry> op_cache;
   unsigned long long op_clock = 0;
+  // one-block CGLS for small levels (DBL_OPT_SMALL_CGLS) and the device's
+  // dynamic LDS limit per block
+  int small_cgls = 1;
+  size_t lds_limit = 65536;
 };
 
 struct dbl_op {
@@ -96,6 +100,10 @@ hipError_t timed(dbl_ctx* ctx, const char* name, double bytes, F&& launch) {
   ctx->prof_pending.push_back(p);
   return e;
 }
+
+// Dynamic LDS of the one-block CGLS at `level` when this context runs that
+// level with it, else 0; *wlds = 1 when IRLS weights are staged in LDS.
+size_t small_lds_bytes(const dbl_ctx* ctx, const dbl_op* op, int level, bool irls, int* wlds);
 
 // Algorithmic bytes of one job (each operand read or written once).
 double job_bytes(const char* kernel, const Job& j, size_t esz);

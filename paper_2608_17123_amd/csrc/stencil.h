@@ -48,18 +48,18 @@ __host__ __device__ inline int col_lds_elems(int TI, int TJ, int H) {
 // periodic wrap.  f(gi) returns the value at flat global index gi.  Loads are
 // issued in groups of U per thread before the LDS stores, so the whole tile
 // is requested in one or two memory round trips.
-template <typename T, bool ROWMAJOR, class F>
+template <typename T, bool ROWMAJOR, int NT = NTHREADS, class F>
 __device__ __forceinline__ void load_tile(T* Xs, int ld, int i0, int j0, int TI, int TJ, int H,
                                           int m, F f) {
   constexpr int U = sizeof(T) == 4 ? 16 : 8;
   const int NR = TI + 2 * H, NC = TJ + 2 * H, tot = NR * NC;
   const int msk = m - 1;
 #pragma unroll 1
-  for (int base = threadIdx.x; base < tot; base += NTHREADS * U) {
+  for (int base = threadIdx.x; base < tot; base += NT * U) {
     T v[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int idx = base + u * NTHREADS;
+      const int idx = base + u * NT;
       if (idx < tot) {
         const int r = idx % NR, c = idx / NR;
         const int gi = (i0 - H + r) & msk, gj = (j0 - H + c) & msk;
@@ -68,7 +68,7 @@ __device__ __forceinline__ void load_tile(T* Xs, int ld, int i0, int j0, int TI,
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int idx = base + u * NTHREADS;
+      const int idx = base + u * NT;
       if (idx < tot) {
         const int r = idx % NR, c = idx / NR;
         if (ROWMAJOR) Xs[r * ld + c] = v[u]; else Xs[c * ld + r] = v[u];
@@ -78,18 +78,19 @@ __device__ __forceinline__ void load_tile(T* Xs, int ld, int i0, int j0, int TI,
 }
 
 // Separable two-pass tile convolution.  Tables padded to radius RB (2RB+1
-// taps per row), RB <= H.  epi(i_local, j_local, value) consumes outputs;
+// taps per row), RB <= H; each thread computes V consecutive outputs per
+// item (register blocking).  epi(i_local, j_local, value) consumes outputs;
 // every thread calls it for the outputs it owns (rows i, columns j..j+V-1).
 struct NoHook {
   __device__ __forceinline__ void operator()() const {}
 };
 
-template <typename T, int RB, class Epi, class Hook = NoHook>
+template <typename T, int RB, int NTH = NTHREADS, int V = TileCfg<T>::V, class Epi,
+          class Hook = NoHook>
 __device__ __forceinline__ void sep_tile(const T* __restrict__ Xs, int H, T* __restrict__ Zs,
                                          const Table1D& t0, const Table1D& t1, int i0, int j0,
                                          int TI, int TJ, int m, Epi epi, Hook hook = Hook()) {
-  constexpr int V = TileCfg<T>::V;
-  constexpr int NT = 2 * RB + 1;
+  constexpr int NTAP = 2 * RB + 1;
   constexpr int NW = V + 2 * RB;
   const int LX = sep_lx(TJ, H), LZ = sep_lz(TI);
   const T* __restrict__ T0 = taps1<T>(t0);
@@ -98,13 +99,13 @@ __device__ __forceinline__ void sep_tile(const T* __restrict__ Xs, int H, T* __r
 
   // ---- pass A: along axis 0, for the TJ + 2RB columns pass B needs
   {
-    T tp[NT];
+    T tp[NTAP];
 #pragma unroll
-    for (int e = 0; e < NT; ++e) tp[e] = T0[t0.St * NT + e];
+    for (int e = 0; e < NTAP; ++e) tp[e] = T0[t0.St * NTAP + e];
     const int NC = TJ + 2 * RB;
     const int nch = (TI + V - 1) / V;
 #pragma unroll 1
-    for (int item = threadIdx.x; item < NC * nch; item += NTHREADS) {
+    for (int item = threadIdx.x; item < NC * nch; item += NTH) {
       const int c = item % NC, ch = item / NC;
       const int r0 = ch * V;
       const int xc = c + (H - RB);
@@ -122,7 +123,7 @@ __device__ __forceinline__ void sep_tile(const T* __restrict__ Xs, int H, T* __r
         for (int v = 0; v < V; ++v) {
           T a = T(0);
 #pragma unroll
-          for (int e = 0; e < NT; ++e) a = fma(tp[e], win[v + e], a);
+          for (int e = 0; e < NTAP; ++e) a = fma(tp[e], win[v + e], a);
           out[v] = a;
         }
       } else {
@@ -130,10 +131,10 @@ __device__ __forceinline__ void sep_tile(const T* __restrict__ Xs, int H, T* __r
         for (int v = 0; v < V; ++v) {
           const int i = ia + v;
           const int cls = (i < m) ? class_of(i, m, t0.St, t0.Sb) : t0.St;
-          const T* __restrict__ row = T0 + cls * NT;
+          const T* __restrict__ row = T0 + cls * NTAP;
           T a = T(0);
 #pragma unroll
-          for (int e = 0; e < NT; ++e) a = fma(row[e], win[v + e], a);
+          for (int e = 0; e < NTAP; ++e) a = fma(row[e], win[v + e], a);
           out[v] = a;
         }
       }
@@ -146,13 +147,13 @@ __device__ __forceinline__ void sep_tile(const T* __restrict__ Xs, int H, T* __r
   hook();  // Xs is no longer read: the hook may reuse it (and must sync)
   // ---- pass B: along axis 1
   {
-    T tp[NT];
+    T tp[NTAP];
 #pragma unroll
-    for (int e = 0; e < NT; ++e) tp[e] = T1[t1.St * NT + e];
+    for (int e = 0; e < NTAP; ++e) tp[e] = T1[t1.St * NTAP + e];
     const int NC = TJ + 2 * RB;
     const int nch = (TJ + V - 1) / V;
 #pragma unroll 1
-    for (int item = threadIdx.x; item < TI * nch; item += NTHREADS) {
+    for (int item = threadIdx.x; item < TI * nch; item += NTH) {
       const int r = item % TI, ch = item / TI;
       const int c0 = ch * V;
       T win[NW];
@@ -165,7 +166,7 @@ __device__ __forceinline__ void sep_tile(const T* __restrict__ Xs, int H, T* __r
         for (int v = 0; v < V; ++v) {
           T a = T(0);
 #pragma unroll
-          for (int e = 0; e < NT; ++e) a = fma(tp[e], win[v + e], a);
+          for (int e = 0; e < NTAP; ++e) a = fma(tp[e], win[v + e], a);
           if (c0 + v < TJ) epi(r, c0 + v, a);
         }
       } else {
@@ -173,10 +174,10 @@ __device__ __forceinline__ void sep_tile(const T* __restrict__ Xs, int H, T* __r
         for (int v = 0; v < V; ++v) {
           const int j = ja + v;
           const int cls = (j < m) ? class_of(j, m, t1.St, t1.Sb) : t1.St;
-          const T* __restrict__ row = T1 + cls * NT;
+          const T* __restrict__ row = T1 + cls * NTAP;
           T a = T(0);
 #pragma unroll
-          for (int e = 0; e < NT; ++e) a = fma(row[e], win[v + e], a);
+          for (int e = 0; e < NTAP; ++e) a = fma(row[e], win[v + e], a);
           if (c0 + v < TJ) epi(r, c0 + v, a);
         }
       }
@@ -187,7 +188,7 @@ __device__ __forceinline__ void sep_tile(const T* __restrict__ Xs, int H, T* __r
 // General 2-D tile convolution over class-pair tap lists.  Xs is the
 // column-major tile (halo H >= max(R0, R1)); `itaps` is LDS scratch for up
 // to (2H+1)^2 interior taps.  epi(i_local, j_local, value).
-template <typename T, class Epi>
+template <typename T, int NT = NTHREADS, class Epi>
 __device__ __forceinline__ void gen_tile(const T* __restrict__ Xs, int H, const Table2D& tb,
                                          short2* s_e, T* s_v, int i0, int j0, int TI, int TJ,
                                          int m, Epi epi) {
@@ -198,12 +199,12 @@ __device__ __forceinline__ void gen_tile(const T* __restrict__ Xs, int H, const 
   if (inter) {
     const int cls = tb.St0 + tb.St1 * tb.rows0;
     const int b = tb.off[cls], n = tb.off[cls + 1] - b;
-    for (int k = threadIdx.x; k < n; k += NTHREADS) {
+    for (int k = threadIdx.x; k < n; k += NT) {
       s_e[k] = tb.e[b + k];
       s_v[k] = vals[b + k];
     }
     __syncthreads();
-    for (int o = threadIdx.x; o < TI * TJ; o += NTHREADS) {
+    for (int o = threadIdx.x; o < TI * TJ; o += NT) {
       const int i = o % TI, j = o / TI;
       T a = T(0);
       for (int k = 0; k < n; ++k) {
@@ -213,7 +214,7 @@ __device__ __forceinline__ void gen_tile(const T* __restrict__ Xs, int H, const 
       epi(i, j, a);
     }
   } else {
-    for (int o = threadIdx.x; o < TI * TJ; o += NTHREADS) {
+    for (int o = threadIdx.x; o < TI * TJ; o += NT) {
       const int i = o % TI, j = o / TI;
       const int c0 = class_of(i0 + i, m, tb.St0, tb.Sb0);
       const int c1 = class_of(j0 + j, m, tb.St1, tb.Sb1);
@@ -229,22 +230,22 @@ __device__ __forceinline__ void gen_tile(const T* __restrict__ Xs, int H, const 
   }
 }
 
-// Apply `body(o, vals)` to the thread's pixels o = tid, tid + NTHREADS, ...
+// Apply `body(o, vals)` to the thread's pixels o = tid, tid + NT, ...
 // of a tile with N pixels, U pixels at a time: `ld(o, vals)` first issues
 // every load of the group (into registers), then `body` consumes them.
-template <int U, int NV, typename T, class LD, class BODY>
+template <int U, int NV, typename T, int NT = NTHREADS, class LD, class BODY>
 __device__ __forceinline__ void batched_pixels(int N, LD ld, BODY body) {
 #pragma unroll 1
-  for (int base = threadIdx.x; base < N; base += NTHREADS * U) {
+  for (int base = threadIdx.x; base < N; base += NT * U) {
     T vals[U][NV];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int o = base + u * NTHREADS;
+      const int o = base + u * NT;
       if (o < N) ld(o, vals[u]);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int o = base + u * NTHREADS;
+      const int o = base + u * NT;
       if (o < N) body(o, vals[u]);
     }
   }

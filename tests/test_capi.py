@@ -130,3 +130,12 @@ def test_package_and_oracle_are_independent():
             text = open(os.path.join(ROOT, "oracle", f)).read()
             assert "paper_2608_17123_amd" not in text, f
             assert "synth" not in re.findall(r"(?:import|from)\s+(\w+)", text), f
+
+
+def test_set_option_validates(hctx):
+    L = D.lib()
+    assert L.dbl_set_option(hctx.handle, D.DBL_OPT_SMALL_CGLS, 0) == D.DBL_OK
+    assert L.dbl_set_option(hctx.handle, D.DBL_OPT_SMALL_CGLS, 1) == D.DBL_OK
+    assert L.dbl_set_option(hctx.handle, D.DBL_OPT_SMALL_CGLS, 2) == D.DBL_EINVAL
+    assert L.dbl_set_option(hctx.handle, 999, 0) == D.DBL_EINVAL
+    assert L.dbl_set_option(None, D.DBL_OPT_SMALL_CGLS, 1) == D.DBL_EINVAL

@@ -58,13 +58,20 @@ def problem(m, seed, sigma=1.5, r=4, noise=0.01, prec=D.DBL_F32):
 CGLS_TOL = {D.DBL_F32: 2e-5, D.DBL_F64: 1e-10}
 
 
+@pytest.mark.parametrize("small", [1, 0])
 @pytest.mark.parametrize("prec", [D.DBL_F32, D.DBL_F64])
 @pytest.mark.parametrize("kind", ["irls", "mm", "plain"])
-@pytest.mark.parametrize("wavelet,level", [("haar", 0), ("haar", 1), ("db4", 2)])
-def test_cgls_matches_oracle(ctx, prec, kind, wavelet, level):
+@pytest.mark.parametrize("wavelet,level,psf", [("haar", 0, "gauss"), ("haar", 1, "gauss"),
+                                               ("db4", 2, "gauss"), ("db4", 1, "motion"),
+                                               ("haar", 2, "motion")])
+def test_cgls_matches_oracle(ctx, prec, kind, wavelet, level, psf, small):
+    """Levels with m <= 64 run the one-block kernel when `small` is 1 (FP32 up
+    to m = 64, FP64 up to m = 32) and the tiled phases when it is 0."""
     m, levels = 128, 3
-    print(f"cgls {kind} {wavelet} level={level} prec={prec}", flush=True)
-    P = synth.gaussian_psf(2.0, 6)
+    print(f"cgls {kind} {wavelet} level={level} psf={psf} prec={prec} small={small}", flush=True)
+    D.dbl_set_option(ctx, D.DBL_OPT_SMALL_CGLS, small)
+    P = synth.gaussian_psf(2.0, 6) if psf == "gauss" else \
+        synth.motion_psf(21, np.random.default_rng(level + 3).uniform(0.0, np.pi))
     H = Hierarchy(P, m, levels, wavelet)
     mi = m >> level
     nl = 2 * mi * (mi - 1)
@@ -84,6 +91,7 @@ def test_cgls_matches_oracle(ctx, prec, kind, wavelet, level):
     err = relerr(host(x), ops.vec(Xr))
     herr = float(np.max(np.abs(np.asarray(gh) - np.asarray(hist)) / np.asarray(hist)))
     print(f"  x relerr {err:.3e}  resid-hist relerr {herr:.3e}", flush=True)
+    D.dbl_set_option(ctx, D.DBL_OPT_SMALL_CGLS, 1)
     assert err <= CGLS_TOL[prec]
     assert herr <= CGLS_TOL[prec] * 10
     op.close()
@@ -93,13 +101,16 @@ SOLVE_TOL = {D.DBL_F32: 1e-4, D.DBL_F64: 1e-9}
 OBJ_TOL = {D.DBL_F32: 1e-6, D.DBL_F64: 1e-11}
 
 
+@pytest.mark.parametrize("small", [1, 0])
 @pytest.mark.parametrize("prec", [D.DBL_F32, D.DBL_F64])
 @pytest.mark.parametrize("solver", ["irls", "mm", "sb"])
 @pytest.mark.parametrize("wavelet,transfer,levels", [("haar", "X", 3), ("db4", "D", 3),
                                                      ("haar", "D", 2), ("db4", "X", 1)])
-def test_deblur_fixed_mu_matches_oracle(ctx, prec, solver, wavelet, transfer, levels):
+def test_deblur_fixed_mu_matches_oracle(ctx, prec, solver, wavelet, transfer, levels, small):
     m, k_out, k_in = 64, 3, 12
-    print(f"deblur {solver} {wavelet} {transfer} L={levels} prec={prec}", flush=True)
+    print(f"deblur {solver} {wavelet} {transfer} L={levels} prec={prec} small={small}",
+          flush=True)
+    D.dbl_set_option(ctx, D.DBL_OPT_SMALL_CGLS, small)
     X, P, B = problem(m, 3, prec=prec)
     mu = [[2e-3 * (1.5 ** i) * (1.1 ** k) for k in range(k_out)] for i in range(levels)]
     Xo, rep_o = vcycle.deblur(B, P, solver, wavelet, levels, transfer, k_out, k_in, mu=mu)
@@ -108,6 +119,7 @@ def test_deblur_fixed_mu_matches_oracle(ctx, prec, solver, wavelet, transfer, le
     x = torch.zeros(m * m, dtype=torch.float32 if prec == 0 else torch.float64, device="cuda")
     rep = D.dbl_deblur(ctx, dev(ops.vec(B), prec), P, m, solver, wavelet, levels, transfer, x,
                        opts)
+    D.dbl_set_option(ctx, D.DBL_OPT_SMALL_CGLS, 1)
     err = relerr(host(x), ops.vec(Xo))
     objg = np.array(rep["objective"])
     objo = np.array([h["objective"] for h in rep_o["levels"]])
