@@ -13,8 +13,15 @@ vectors with FP64 scalars, GCV (spectral tier) on the device.
 
 Printed: one JSON line with solves/s of the batched path (value), the plain
 one-solve-at-a-time path on the same workload, the roofline of the dominant
-kernel (HIP events inside this process), and the FP64 oracle timed on the
-host cores (cpu_baseline) together with the GPU result's error against it.
+kernel (HIP events inside this process; HBM traffic from the committed
+rocprofv3 counter record when it was taken on the current kernel sources),
+the serving leg (Poisson arrivals of the same requests into the
+continuous-batching server against the plain path fed the same trace: p50/p99
+latency and solves/s), and the FP64 oracle timed on the host cores
+(cpu_baseline) together with the GPU result's error against it.
+
+--calib-copy runs only a plain 1 GiB device-to-device copy (three times): the
+known-size kernel that scales the FETCH_SIZE / WRITE_SIZE counters.
 """
 import argparse
 import json
@@ -30,6 +37,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "solves/s batched vs plain at rel.err<=1e-4 vs FP64; p99 latency; HBM GB/s"
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_RECORD = {"c2": os.path.join(ROOT, "profiles", "traffic_cgls_p2_m256_batch24.json")}
+CALIB_BYTES = 1 << 30
 
 
 def parse():
@@ -40,7 +49,84 @@ def parse():
     p.add_argument("--workload", default="c2", choices=["c2", "c4"])
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-plain", action="store_true")
+    p.add_argument("--no-serve", action="store_true")
+    p.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrivals per second")
+    p.add_argument("--serve-requests", type=int, default=128)
+    p.add_argument("--calib-copy", action="store_true")
     return p.parse_args()
+
+
+def calib_copy(torch):
+    x = torch.ones(CALIB_BYTES // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"calib_copy_bytes_each_way": CALIB_BYTES, "copies": 3}))
+
+
+def serve_leg(D, torch, ctx, items, opts_kw, rate, nreq, seed=11):
+    """Poisson arrivals (rate per second) of nreq requests cycling through the
+    workload's solves.  Served: the continuous-batching server (arrivals are
+    submitted as they come, every step advances all resident solves).  Plain:
+    the same trace solved one request at a time in arrival order.  Latency =
+    completion - arrival, host clock."""
+    rng = np.random.default_rng(seed)
+    arr = np.cumsum(rng.exponential(1.0 / rate, nreq))
+    reqs, xs = [], []
+    for q in range(nreq):
+        w, b, _ = items[q % len(items)]
+        x = torch.zeros_like(b)
+        xs.append(x)
+        reqs.append(D.make_request(b, x, w.psf, w.m, w.solver, w.wavelet, w.levels, w.transfer,
+                                   D.dbl_opts_default(k_out=w.k_out, k_in=w.k_in, **opts_kw)))
+    torch.cuda.synchronize()
+
+    srv = D.dbl_server_create(ctx, max_slots=64)
+    lat = np.zeros(nreq)
+    tickets = {}
+    sub = done = 0
+    max_active = 0
+    t0 = time.perf_counter()
+    while done < nreq:
+        now = time.perf_counter() - t0
+        while sub < nreq and arr[sub] <= now:
+            tickets[D.dbl_server_submit(srv, reqs[sub])] = sub
+            sub += 1
+        if not tickets:
+            time.sleep(max(0.0, arr[sub] - now))
+            continue
+        max_active = max(max_active, D.dbl_server_step(srv))
+        for t, q in list(tickets.items()):
+            if D.dbl_server_poll(srv, t) is not None:
+                lat[q] = time.perf_counter() - t0 - arr[q]
+                del tickets[t]
+                done += 1
+    t_served = time.perf_counter() - t0
+    srv.close()
+
+    plat = np.zeros(nreq)
+    t0 = time.perf_counter()
+    for q in range(nreq):
+        now = time.perf_counter() - t0
+        if arr[q] > now:
+            time.sleep(arr[q] - now)
+        w, b, _ = items[q % len(items)]
+        D.dbl_deblur(ctx, b, w.psf, w.m, w.solver, w.wavelet, w.levels, w.transfer, xs[q],
+                     D.dbl_opts_default(k_out=w.k_out, k_in=w.k_in, **opts_kw))
+        plat[q] = time.perf_counter() - t0 - arr[q]
+    t_plain = time.perf_counter() - t0
+
+    def pct(a, p):
+        return round(1e3 * float(np.percentile(a, p)), 2)
+
+    return {
+        "arrivals": f"Poisson, {rate:g} requests/s, {nreq} requests cycling through the workload",
+        "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
+        "solves_per_s": round(nreq / t_served, 2), "max_resident": max_active,
+        "plain_p50_ms": pct(plat, 50), "plain_p99_ms": pct(plat, 99),
+        "plain_solves_per_s": round(nreq / t_plain, 2),
+    }
 
 
 def build_inputs(D, torch, ctx, workloads, prec):
@@ -117,7 +203,11 @@ def main():
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
+    if args.calib_copy:
+        calib_copy(torch)
+        return
     import paper_2608_17123_amd as D
+    from paper_2608_17123_amd import profiling
     import synth
 
     D.lib()  # fail loudly when the library is missing
@@ -165,13 +255,23 @@ def main():
     dom = max((k for k in stats if stats[k][2] > 0), key=lambda k: stats[k][1])
     n, ms, by = stats[dom]
     achieved = by / (ms * 1e-3) / 1e9
+    traffic = None
+    rec = profiling.read_traffic(TRAFFIC_RECORD[args.workload]) \
+        if args.workload in TRAFFIC_RECORD else None
+    if rec is not None and rec["kernel"] == "k_" + dom:
+        traffic = rec["hbm_bytes_per_dispatch"]
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None, "launches": n, "avg_launch_us": round(1e3 * ms / n, 2),
+                "traffic": traffic, "traffic_unit": "bytes per launch",
+                "launches": n, "avg_launch_us": round(1e3 * ms / n, 2),
                 "bytes_per_launch": by / n}
     kernels = {k: {"launches": v[0], "ms": round(v[1], 3),
                    "GB/s": (round(v[2] / (v[1] * 1e-3) / 1e9, 1) if v[2] > 0 else None)}
                for k, v in sorted(stats.items(), key=lambda kv: -kv[1][1])}
+
+    serving = None
+    if not args.no_serve:
+        serving = serve_leg(D, torch, ctx, items, opts_kw, args.serve_rate, args.serve_requests)
 
     cpu = None
     err = None
@@ -196,6 +296,7 @@ def main():
         "batched_over_plain": None if plain is None else round(value / plain, 2),
         "rel_err_vs_oracle": err,
         "roofline": roofline,
+        "serving": serving,
         "kernels": kernels,
         "cpu_baseline": cpu,
     }

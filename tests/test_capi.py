@@ -139,3 +139,20 @@ def test_set_option_validates(hctx):
     assert L.dbl_set_option(hctx.handle, D.DBL_OPT_SMALL_CGLS, 2) == D.DBL_EINVAL
     assert L.dbl_set_option(hctx.handle, 999, 0) == D.DBL_EINVAL
     assert L.dbl_set_option(None, D.DBL_OPT_SMALL_CGLS, 1) == D.DBL_EINVAL
+
+
+def test_traffic_record_tracks_kernel_sources(tmp_path):
+    """bench.py reports counter traffic only while the kernel sources are
+    those the counters were taken on."""
+    import json
+    from paper_2608_17123_amd import profiling
+    h = profiling.source_hash()
+    assert len(h) == 16 and h == profiling.source_hash()
+    rec = {"kernel": "k_cgls_p2", "hbm_bytes_per_dispatch": 1.0, "source_hash": h}
+    p = tmp_path / "t.json"
+    p.write_text(json.dumps(rec))
+    assert profiling.read_traffic(str(p))["hbm_bytes_per_dispatch"] == 1.0
+    rec["source_hash"] = "0" * 16
+    p.write_text(json.dumps(rec))
+    assert profiling.read_traffic(str(p)) is None
+    assert profiling.read_traffic(str(tmp_path / "missing.json")) is None
