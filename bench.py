@@ -53,6 +53,8 @@ def parse():
     p.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrivals per second")
     p.add_argument("--serve-requests", type=int, default=128)
     p.add_argument("--calib-copy", action="store_true")
+    p.add_argument("--precision", default="f32", choices=["f32", "bf16", "f64"],
+                   help="vector storage: FP32, BF16 CGLS state with FP32 arithmetic, or FP64")
     return p.parse_args()
 
 
@@ -174,7 +176,8 @@ def cpu_baseline(D, torch, ctx, w, opts_kw, k_out_sample=3):
         Xo, rep = vcycle.deblur(B32, w.psf, w.solver, w.wavelet, w.levels, w.transfer,
                                 k_out_sample, w.k_in, gcv_mode="spectral", fast=True)
         t = time.perf_counter() - t0
-    b = torch.from_numpy(np.ascontiguousarray(B32.ravel(order="F"), dtype=np.float32)).cuda()
+    npdt = np.float64 if opts_kw["precision"] == D.DBL_F64 else np.float32
+    b = torch.from_numpy(np.ascontiguousarray(B32.ravel(order="F"), dtype=npdt)).cuda()
     x = torch.zeros_like(b)
     opts = D.dbl_opts_default(k_out=k_out_sample, k_in=w.k_in, **opts_kw)
     D.dbl_deblur(ctx, b, w.psf, w.m, w.solver, w.wavelet, w.levels, w.transfer, x, opts)
@@ -212,7 +215,7 @@ def main():
 
     D.lib()  # fail loudly when the library is missing
     ctx = D.dbl_create(0)
-    prec = D.DBL_F32
+    prec = {"f32": D.DBL_F32, "bf16": D.DBL_BF16, "f64": D.DBL_F64}[args.precision]
     if args.workload == "c2":
         workloads = synth.config2()
         wdesc = ("m=256 single image, 60 shapes, Gaussian sigma 2.5 on 15x15, noise 1%/5%, "
@@ -289,7 +292,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f64" if prec == D.DBL_F64 else "f32",
+        "storage": {"f32": "f32", "bf16": "bf16 CGLS state, f32 data", "f64": "f64"}[args.precision],
         "data": "synthetic",
         "config": {"workload": wdesc, "solves_per_step": nsolve, "path": "batched"},
         "plain_solves_per_s": None if plain is None else round(plain, 2),

@@ -68,7 +68,15 @@ typedef enum { DBL_HAAR = 0, DBL_DB4 = 1 } dbl_wavelet;
 /* Information transfer of Sec. 4.1: X = coarse solution, D = auxiliaries.
  * With levels == 1 the transfer is unused (Approach I). */
 typedef enum { DBL_XFER_X = 0, DBL_XFER_D = 1 } dbl_transfer;
-typedef enum { DBL_F32 = 0, DBL_F64 = 1 } dbl_precision;
+/* Element types.  DBL_F32 / DBL_F64: every device vector in float / double.
+ * DBL_BF16: every vector a caller passes (b, x, weights, shifts, operator
+ * inputs and outputs) is float; inside CGLS the state vectors p, s, r1, r2,
+ * q1, q2 are stored as bfloat16 (rounded to nearest even from FP32) and
+ * every operation on them is FP32, with FP64 scalars (alpha, beta, norms);
+ * each outer iteration restarts CGLS from the FP32 data (r1 = b) and its
+ * residual and objective are recomputed in FP32 from x.  Levels that run
+ * the one-block CGLS keep their state in LDS in FP32. */
+typedef enum { DBL_F32 = 0, DBL_F64 = 1, DBL_BF16 = 2 } dbl_precision;
 /* GCV tiers: SPECTRAL evaluates the GCV function of eq. (GCV) on the DCT
  * surrogate (reflexive-boundary blur, exact Neumann gradient); EXACT uses the
  * generalised eigendecomposition of the pair {A, D} (the paper's GSVD route,

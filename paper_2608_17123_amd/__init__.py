@@ -24,7 +24,7 @@ DBL_OK, DBL_EINVAL, DBL_ENOMEM, DBL_EDEVICE, DBL_ENOTSUP, DBL_ENUMERIC, DBL_ENOT
 DBL_IRLS, DBL_MM, DBL_SB = 0, 1, 2
 DBL_HAAR, DBL_DB4 = 0, 1
 DBL_XFER_X, DBL_XFER_D = 0, 1
-DBL_F32, DBL_F64 = 0, 1
+DBL_F32, DBL_F64, DBL_BF16 = 0, 1, 2
 DBL_GCV_AUTO, DBL_GCV_EXACT, DBL_GCV_SPECTRAL = 0, 1, 2
 DBL_MAX_LEVELS, DBL_MAX_KOUT, DBL_GCV_GRID_MAX = 8, 64, 64
 DBL_OPT_SMALL_CGLS = 1

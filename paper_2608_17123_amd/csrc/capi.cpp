@@ -14,7 +14,8 @@ namespace {
 bool pow2(int m) { return m > 0 && (m & (m - 1)) == 0; }
 
 int check_prec(dbl_ctx* ctx, int p) {
-  if (p != DBL_F32 && p != DBL_F64) return set_err(ctx, DBL_EINVAL, "precision must be F32 or F64");
+  if (p != DBL_F32 && p != DBL_F64 && p != DBL_BF16)
+    return set_err(ctx, DBL_EINVAL, "precision must be F32, F64 or BF16");
   return DBL_OK;
 }
 
@@ -251,7 +252,7 @@ int dbl_apply_A(dbl_ctx* ctx, const dbl_op* op, int level, int transpose, const 
   LaunchArgs la;
   int rc = Lc.upload(ctx, la);
   if (rc) return rc;
-  return hip_check(ctx, timed(ctx, "apply_A", job_bytes("apply_A", Lc.jobs[0], esz), [&] {
+  return hip_check(ctx, timed(ctx, "apply_A", job_bytes("apply_A", Lc.jobs[0], op->precision), [&] {
                      return launch_apply_A(la, op->precision, L.sep ? 1 : 0, L.rb,
                                            L.sep ? L.rb : L.R);
                    }),
@@ -348,9 +349,10 @@ int dbl_cgls(dbl_ctx* ctx, const dbl_op* op, int level, const dbl_sub* sub, cons
   const LevelHost& L = op->host.levels[level];
   const int m = L.m, prec = op->precision;
   const size_t esz = prec == DBL_F64 ? 8 : 4;
+  const size_t ssz = prec == DBL_BF16 ? 2 : esz;  // CGLS state vectors
   const size_t n = (size_t)m * m, nl = 2 * (size_t)m * (m - 1);
   auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
-  const size_t need = 6 * al(n * esz) + 3 * al(nl * esz) + al(NSCAL * 8) +
+  const size_t need = 6 * al(n * ssz) + 3 * al(nl * ssz) + al(n * esz) + al(NSCAL * 8) +
                       al(part_doubles(m) * 8) + 256;
   int rc = DBL_OK;
   if (ctx->scratch_bytes < need) {
@@ -363,12 +365,13 @@ int dbl_cgls(dbl_ctx* ctx, const dbl_op* op, int level, const dbl_sub* sub, cons
   }
   char* p = static_cast<char*>(ctx->scratch);
   auto take = [&](size_t b) { void* r = p; p += al(b); return r; };
-  void* P[2] = {take(n * esz), take(n * esz)};
-  void* S = take(n * esz);
-  void* R1[2] = {take(n * esz), take(n * esz)};
-  void* Q1 = take(n * esz);
-  void* R2[2] = {take(nl * esz), take(nl * esz)};
-  void* Q2 = take(nl * esz);
+  void* P[2] = {take(n * ssz), take(n * ssz)};
+  void* S = take(n * ssz);
+  void* R1[2] = {take(n * ssz), take(n * ssz)};
+  void* Q1 = take(n * ssz);
+  void* R2[2] = {take(nl * ssz), take(nl * ssz)};
+  void* Q2 = take(nl * ssz);
+  void* AX0 = take(n * esz);  // A x0 (compute type)
   double* scal = static_cast<double*>(take(NSCAL * 8));
   double* part = static_cast<double*>(take(part_doubles(m) * 8));
   unsigned* cnt = static_cast<unsigned*>(take(256));
@@ -406,7 +409,7 @@ int dbl_cgls(dbl_ctx* ctx, const dbl_op* op, int level, const dbl_sub* sub, cons
     Ls.add(js, 1, 4);
     LaunchArgs la;
     if ((rc = Ls.upload(ctx, la))) return rc;
-    const double bytes = job_bytes("cgls_small", js, esz);
+    const double bytes = job_bytes("cgls_small", js, prec);
     if ((rc = hip_check(ctx, timed(ctx, "cgls_small", bytes, [&] {
                           return launch_cgls_small(la, prec, rb, m, small);
                         }),
@@ -424,7 +427,7 @@ int dbl_cgls(dbl_ctx* ctx, const dbl_op* op, int level, const dbl_sub* sub, cons
   if (x0) {
     Job ja = j;
     ja.v[0] = const_cast<void*>(x0);
-    ja.v[1] = R1[0];
+    ja.v[1] = AX0;
     ja.flags = 0;
     Launch La;
     La.add(ja, m, (int)esz);
@@ -437,6 +440,7 @@ int dbl_cgls(dbl_ctx* ctx, const dbl_op* op, int level, const dbl_sub* sub, cons
   ji.v[V_R1A] = R1[0];
   ji.v[V_R2A] = R2[0];
   ji.v[V_X0] = const_cast<void*>(x0);
+  ji.v[V_XOLD] = AX0;
   Launch Li;
   Li.add(ji, m, (int)esz);
   LaunchArgs la;

@@ -158,6 +158,46 @@ __device__ __forceinline__ void decode_tile(const Job* __restrict__ jobs,
   tj = tix / job->nti;
 }
 
+// ------------------------------------------------------------ storage --
+// Storage types of the CGLS state vectors.  With DBL_BF16 the vectors p, s,
+// r1, r2, q1, q2 are stored as bfloat16 (round to nearest even from FP32)
+// and every operation on them runs in FP32; otherwise storage = compute type.
+struct bf16s {
+  uint16_t u;
+};
+
+__device__ __forceinline__ float bf16_to_f32(bf16s v) {
+  return __uint_as_float((uint32_t)v.u << 16);
+}
+__device__ __forceinline__ bf16s f32_to_bf16(float f) {
+  const uint32_t b = __float_as_uint(f);
+  bf16s r;
+  if ((b & 0x7f800000u) == 0x7f800000u && (b & 0x007fffffu))
+    r.u = (uint16_t)((b >> 16) | 0x40u);  // NaN stays a (quiet) NaN
+  else
+    r.u = (uint16_t)((b + 0x7fffu + ((b >> 16) & 1u)) >> 16);
+  return r;
+}
+
+// load element i of a storage-S vector as compute type T
+template <typename T, typename S>
+__device__ __forceinline__ T ldv(const S* p, size_t i) {
+  if constexpr (sizeof(S) == 2) return (T)bf16_to_f32(p[i]);
+  else return (T)p[i];
+}
+// value of v after a round trip through storage S
+template <typename S, typename T>
+__device__ __forceinline__ T rtv(T v) {
+  if constexpr (sizeof(S) == 2) return (T)bf16_to_f32(f32_to_bf16((float)v));
+  else return v;
+}
+// store v (already representable in S when it came from rtv) at element i
+template <typename S, typename T>
+__device__ __forceinline__ void stv(S* p, size_t i, T v) {
+  if constexpr (sizeof(S) == 2) p[i] = f32_to_bf16((float)v);
+  else p[i] = (S)v;
+}
+
 // ---------------------------------------------------------------- reduce --
 
 __device__ __forceinline__ double wave_sum(double v) {

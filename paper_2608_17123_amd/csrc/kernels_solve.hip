@@ -12,6 +12,8 @@
 //          beta = |s|^2 / gs
 // p, r1 and r2 are double-buffered (read one copy, write the other) because
 // the stencils read neighbours that other blocks update in the same launch.
+// S is the storage type of the state vectors p, s, r1, r2, q1, q2 (T, or
+// bfloat16 with FP32 arithmetic); norms are taken of the stored values.
 // The norms are per-tile FP64 partials: p1 writes |q|^2 partials and sums the
 // |s|^2 partials of the previous p2 (beta); p2 sums both (alpha) and writes
 // new |s|^2 and |r|^2 partials, which the next p1 reads.
@@ -58,7 +60,7 @@ template <typename T> __device__ __forceinline__ T* vp(const Job* j, int k) {
 }
 
 // ------------------------------------------------------------------ init --
-template <typename T>
+template <typename T, typename S>
 __global__ void __launch_bounds__(NTHREADS) k_cgls_init(const Job* __restrict__ jobs,
                                                         const uint32_t* __restrict__ tiles) {
   const Job* job; int ti, tj, tix;
@@ -69,14 +71,15 @@ __global__ void __launch_bounds__(NTHREADS) k_cgls_init(const Job* __restrict__ 
   const double sg = job->scal[S_SQRTG];
   const bool shift = job->flags & F_SHIFT, sb = job->flags & F_SB, irls = job->flags & F_IRLS;
   T* x = vp<T>(job, V_X);
-  T* p = vp<T>(job, V_PA);
-  T* r1 = vp<T>(job, V_R1A);
-  T* r2 = vp<T>(job, V_R2A);
+  S* p = vp<S>(job, V_PA);
+  S* r1 = vp<S>(job, V_R1A);
+  S* r2 = vp<S>(job, V_R2A);
   const T* b = vp<T>(job, V_B);
   const T* c1 = vp<T>(job, V_C1);
   const T* c2 = vp<T>(job, V_C2);
   const T* w = vp<T>(job, V_W);
-  const T* x0 = vp<T>(job, V_X0);   // optional start; r1 then already holds A x0
+  const T* x0 = vp<T>(job, V_X0);   // optional start
+  const T* ax0 = vp<T>(job, V_XOLD);  // A x0 when x0 is given
   const size_t nx = (size_t)(m - 1) * m;
   for (int o = threadIdx.x; o < TI * TJ; o += NTHREADS) {
     const int gi = i0 + o % TI, gj = j0 + o / TI;
@@ -84,12 +87,12 @@ __global__ void __launch_bounds__(NTHREADS) k_cgls_init(const Job* __restrict__ 
     double xv = 0.0;
     if (x0) {
       xv = (double)x0[g];
-      r1[g] = (T)((double)b[g] - (double)r1[g]);
+      stv(r1, g, (T)((double)b[g] - (double)ax0[g]));
     } else {
-      r1[g] = b[g];
+      stv(r1, g, b[g]);
     }
     x[g] = (T)xv;
-    p[g] = T(0);
+    stv(p, g, T(0));
     for (int dir = 0; dir < 2; ++dir) {
       if ((dir == 0 && gi >= m - 1) || (dir == 1 && gj >= m - 1)) continue;
       const size_t k = dir == 0 ? gi + (size_t)gj * (m - 1) : nx + g;
@@ -101,13 +104,13 @@ __global__ void __launch_bounds__(NTHREADS) k_cgls_init(const Job* __restrict__ 
         if (irls) d *= (double)w[k];
         c -= d;
       }
-      r2[k] = (T)(sg * c);
+      stv(r2, k, (T)(sg * c));
     }
   }
 }
 
 // --------------------------------------------------------------- phase 1 --
-template <typename T, int RB, bool SEP>
+template <typename T, typename S, int RB, bool SEP>
 __global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 3 : 2) k_cgls_p1(const Job* __restrict__ jobs,
                                                       const uint32_t* __restrict__ tiles) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -137,14 +140,14 @@ __global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 3 : 2) k_cgls_p1(co
   const T tb = (T)beta;
   const double sg = job->scal[S_SQRTG];
   const bool irls = job->flags & F_IRLS;
-  const T* __restrict__ s = vp<T>(job, V_S);
-  const T* __restrict__ pa = vp<T>(job, V_PA);
-  T* __restrict__ pb = vp<T>(job, V_PB);
-  T* __restrict__ q1 = vp<T>(job, V_Q1);
-  T* __restrict__ q2 = vp<T>(job, V_Q2);
+  const S* __restrict__ s = vp<S>(job, V_S);
+  const S* __restrict__ pa = vp<S>(job, V_PA);
+  S* __restrict__ pb = vp<S>(job, V_PB);
+  S* __restrict__ q1 = vp<S>(job, V_Q1);
+  S* __restrict__ q2 = vp<S>(job, V_Q2);
   const T* __restrict__ w = vp<T>(job, V_W);
   load_tile<T, SEP>(Xs, xs_ld<SEP>(H, TI, TJ), i0, j0, TI, TJ, H, m,
-                    [&](int g) { return s[g] + tb * pa[g]; });
+                    [&](int g) { return rtv<S>(ldv<T>(s, g) + tb * ldv<T>(pa, g)); });
   __syncthreads();
   double acc = 0.0;
   const size_t nx = (size_t)(m - 1) * m;
@@ -160,30 +163,31 @@ __global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 3 : 2) k_cgls_p1(co
         const int i = o % TI, j = o / TI, gi = i0 + i, gj = j0 + j;
         const size_t g = gi + (size_t)gj * m;
         const T pc = Xs[xs_at<SEP>(i, j, H, TI, TJ)];
-        pb[g] = pc;
+        stv(pb, g, pc);
         if (gi < m - 1) {
           const double d = ((double)Xs[xs_at<SEP>(i + 1, j, H, TI, TJ)] - (double)pc) * (double)v[0];
-          const T qv = (T)(sg * d);
-          q2[gi + (size_t)gj * (m - 1)] = qv;
+          const T qv = rtv<S>((T)(sg * d));
+          stv(q2, gi + (size_t)gj * (m - 1), qv);
           acc += (double)qv * (double)qv;
         }
         if (gj < m - 1) {
           const double d = ((double)Xs[xs_at<SEP>(i, j + 1, H, TI, TJ)] - (double)pc) * (double)v[1];
-          const T qv = (T)(sg * d);
-          q2[nx + g] = qv;
+          const T qv = rtv<S>((T)(sg * d));
+          stv(q2, nx + g, qv);
           acc += (double)qv * (double)qv;
         }
       });
   conv_tile<T, RB, SEP>(Xs, H, scratch, op, false, i0, j0, TI, TJ, m, [&](int i, int j, T v) {
-    q1[(i0 + i) + (size_t)(j0 + j) * m] = v;
-    acc += (double)v * (double)v;
+    const T qv = rtv<S>(v);
+    stv(q1, (i0 + i) + (size_t)(j0 + j) * m, qv);
+    acc += (double)qv * (double)qv;
   });
   double vv[1] = {acc};
   put_partials<1>(job->pw, tix, vv, red);
 }
 
 // --------------------------------------------------------------- phase 2 --
-template <typename T, int RB, bool SEP>
+template <typename T, typename S, int RB, bool SEP>
 __global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 3 : 2) k_cgls_p2(const Job* __restrict__ jobs,
                                                       const uint32_t* __restrict__ tiles) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -210,21 +214,21 @@ __global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 3 : 2) k_cgls_p2(co
   const T ta = (T)alpha;
   const double sg = job->scal[S_SQRTG];
   T* __restrict__ x = vp<T>(job, V_X);
-  const T* __restrict__ p = vp<T>(job, V_PB);
-  const T* __restrict__ r1a = vp<T>(job, V_R1A);
-  T* __restrict__ r1b = vp<T>(job, V_R1B);
-  const T* __restrict__ q1 = vp<T>(job, V_Q1);
-  const T* __restrict__ r2a = vp<T>(job, V_R2A);
-  T* __restrict__ r2b = vp<T>(job, V_R2B);
-  const T* __restrict__ q2 = vp<T>(job, V_Q2);
+  const S* __restrict__ p = vp<S>(job, V_PB);
+  const S* __restrict__ r1a = vp<S>(job, V_R1A);
+  S* __restrict__ r1b = vp<S>(job, V_R1B);
+  const S* __restrict__ q1 = vp<S>(job, V_Q1);
+  const S* __restrict__ r2a = vp<S>(job, V_R2A);
+  S* __restrict__ r2b = vp<S>(job, V_R2B);
+  const S* __restrict__ q2 = vp<S>(job, V_Q2);
   const T* __restrict__ w = vp<T>(job, V_W);
-  T* __restrict__ s = vp<T>(job, V_S);
+  S* __restrict__ s = vp<S>(job, V_S);
   if (first) {
     load_tile<T, SEP>(Xs, xs_ld<SEP>(H, TI, TJ), i0, j0, TI, TJ, H, m,
-                      [&](int g) { return r1a[g]; });
+                      [&](int g) { return ldv<T>(r1a, g); });
   } else {
     load_tile<T, SEP>(Xs, xs_ld<SEP>(H, TI, TJ), i0, j0, TI, TJ, H, m,
-                      [&](int g) { return r1a[g] - ta * q1[g]; });
+                      [&](int g) { return rtv<S>(ldv<T>(r1a, g) - ta * ldv<T>(q1, g)); });
   }
   __syncthreads();
   double accr = 0.0, accs = 0.0;
@@ -234,14 +238,14 @@ __global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 3 : 2) k_cgls_p2(co
         const size_t g = (i0 + o % TI) + (size_t)(j0 + o / TI) * m;
         if (!first) {
           v[0] = x[g];
-          v[1] = p[g];
+          v[1] = ldv<T>(p, g);
         }
       },
       [&](int o, T* v) {
         const int i = o % TI, j = o / TI;
         const size_t g = (i0 + i) + (size_t)(j0 + j) * m;
         const T rv = Xs[xs_at<SEP>(i, j, H, TI, TJ)];
-        r1b[g] = rv;
+        stv(r1b, g, rv);
         accr += (double)rv * (double)rv;
         if (!first) x[g] = v[0] + ta * v[1];
       });
@@ -266,8 +270,8 @@ __global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 3 : 2) k_cgls_p2(co
           ok[3] = gj < m - 1;   ks[3] = nx + g;
 #pragma unroll
           for (int d = 0; d < 4; ++d) {
-            v[3 * d] = ok[d] ? r2a[ks[d]] : T(0);
-            v[3 * d + 1] = (ok[d] && !first) ? q2[ks[d]] : T(0);
+            v[3 * d] = ok[d] ? ldv<T>(r2a, ks[d]) : T(0);
+            v[3 * d + 1] = (ok[d] && !first) ? ldv<T>(q2, ks[d]) : T(0);
             v[3 * d + 2] = (ok[d] && irls) ? w[ks[d]] : T(1);
           }
         },
@@ -276,17 +280,18 @@ __global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 3 : 2) k_cgls_p2(co
           const size_t g = gi + (size_t)gj * m;
           T rn[4];
 #pragma unroll
-          for (int d = 0; d < 4; ++d) rn[d] = first ? v[3 * d] : (T)(v[3 * d] - ta * v[3 * d + 1]);
+          for (int d = 0; d < 4; ++d)
+            rn[d] = first ? v[3 * d] : rtv<S>((T)(v[3 * d] - ta * v[3 * d + 1]));
           double lt = 0.0;
           if (gi >= 1) lt += (double)v[2] * (double)rn[0];
           if (gi < m - 1) {
-            r2b[gi + (size_t)gj * (m - 1)] = rn[1];
+            stv(r2b, gi + (size_t)gj * (m - 1), rn[1]);
             accr += (double)rn[1] * (double)rn[1];
             lt -= (double)v[5] * (double)rn[1];
           }
           if (gj >= 1) lt += (double)v[8] * (double)rn[2];
           if (gj < m - 1) {
-            r2b[nx + g] = rn[3];
+            stv(r2b, nx + g, rn[3]);
             accr += (double)rn[3] * (double)rn[3];
             lt -= (double)v[11] * (double)rn[3];
           }
@@ -299,8 +304,8 @@ __global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 3 : 2) k_cgls_p2(co
         Xs, H, scratch, op, true, i0, j0, TI, TJ, m,
         [&](int i, int j, T v) {
           const size_t g = (i0 + i) + (size_t)(j0 + j) * m;
-          const T sv = v + LT[i + j * TI];
-          s[g] = sv;
+          const T sv = rtv<S>(v + LT[i + j * TI]);
+          stv(s, g, sv);
           accs += (double)sv * (double)sv;
         },
         [&] { grad_part(Xs); });
@@ -308,8 +313,8 @@ __global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 3 : 2) k_cgls_p2(co
     grad_part(reinterpret_cast<T*>(scratch) + (2 * H + 1) * (2 * H + 1) * 2);
     conv_tile<T, RB, SEP>(Xs, H, scratch, op, true, i0, j0, TI, TJ, m, [&](int i, int j, T v) {
       const size_t g = (i0 + i) + (size_t)(j0 + j) * m;
-      const T sv = v + LT[i + j * TI];
-      s[g] = sv;
+      const T sv = rtv<S>(v + LT[i + j * TI]);
+      stv(s, g, sv);
       accs += (double)sv * (double)sv;
     });
   }
@@ -504,15 +509,46 @@ struct Dummy {};
     }                                                                                  \
   } while (0)
 
+// Same, for kernels that also take the storage type S of the state vectors.
+#define DISPATCH_STENCIL_S(KERNEL, T, S, la, sep, rb, H)                           \
+  do {                                                                                 \
+    const int TS_ = TileCfg<T>::TS;                                                    \
+    const int ts_ = (la).m_max < TS_ ? (la).m_max : TS_;                               \
+    if (sep) {                                                                         \
+      const size_t lds_ = sizeof(T) * sep_lds_elems(ts_, ts_, rb);                     \
+      switch (rb) {                                                                    \
+        case 2: hipLaunchKernelGGL((KERNEL<T, S, 2, true>), dim3((la).ntiles),           \
+                    dim3(NTHREADS), lds_, (la).stream, (la).jobs, (la).tiles); break;  \
+        case 4: hipLaunchKernelGGL((KERNEL<T, S, 4, true>), dim3((la).ntiles),           \
+                    dim3(NTHREADS), lds_, (la).stream, (la).jobs, (la).tiles); break;  \
+        case 8: hipLaunchKernelGGL((KERNEL<T, S, 8, true>), dim3((la).ntiles),           \
+                    dim3(NTHREADS), lds_, (la).stream, (la).jobs, (la).tiles); break;  \
+        case 12: hipLaunchKernelGGL((KERNEL<T, S, 12, true>), dim3((la).ntiles),         \
+                    dim3(NTHREADS), lds_, (la).stream, (la).jobs, (la).tiles); break;  \
+        case 16: hipLaunchKernelGGL((KERNEL<T, S, 16, true>), dim3((la).ntiles),         \
+                    dim3(NTHREADS), lds_, (la).stream, (la).jobs, (la).tiles); break;  \
+        default: return hipErrorInvalidValue;                                          \
+      }                                                                                \
+    } else {                                                                           \
+      const size_t lds_ = sizeof(T) * col_lds_elems(ts_, ts_, H) +                     \
+                          (2 * sizeof(T) + sizeof(short2)) * (2 * (H) + 1) * (2 * (H) + 1) + \
+                          sizeof(T) * ts_ * ts_;                                      \
+      hipLaunchKernelGGL((KERNEL<T, S, 0, false>), dim3((la).ntiles), dim3(NTHREADS),    \
+                         lds_, (la).stream, (la).jobs, (la).tiles);                    \
+    }                                                                                  \
+  } while (0)
+
 hipError_t launch_cgls_p1(const LaunchArgs& la, int precision, int sep, int rb, int H) {
-  if (precision == 1) DISPATCH_STENCIL(k_cgls_p1, double, la, sep, rb, H, 0);
-  else DISPATCH_STENCIL(k_cgls_p1, float, la, sep, rb, H, 0);
+  if (precision == 1) DISPATCH_STENCIL_S(k_cgls_p1, double, double, la, sep, rb, H);
+  else if (precision == 2) DISPATCH_STENCIL_S(k_cgls_p1, float, bf16s, la, sep, rb, H);
+  else DISPATCH_STENCIL_S(k_cgls_p1, float, float, la, sep, rb, H);
   return hipGetLastError();
 }
 
 hipError_t launch_cgls_p2(const LaunchArgs& la, int precision, int sep, int rb, int H) {
-  if (precision == 1) DISPATCH_STENCIL(k_cgls_p2, double, la, sep, rb, H, 0);
-  else DISPATCH_STENCIL(k_cgls_p2, float, la, sep, rb, H, 0);
+  if (precision == 1) DISPATCH_STENCIL_S(k_cgls_p2, double, double, la, sep, rb, H);
+  else if (precision == 2) DISPATCH_STENCIL_S(k_cgls_p2, float, bf16s, la, sep, rb, H);
+  else DISPATCH_STENCIL_S(k_cgls_p2, float, float, la, sep, rb, H);
   return hipGetLastError();
 }
 
@@ -533,7 +569,18 @@ hipError_t launch_stats(const LaunchArgs& la, int precision, int sep, int rb, in
     return hipGetLastError();                                                          \
   }
 
-SIMPLE_LAUNCHER(launch_cgls_init, k_cgls_init)
+hipError_t launch_cgls_init(const LaunchArgs& la, int precision) {
+  if (precision == 1)
+    hipLaunchKernelGGL((k_cgls_init<double, double>), dim3(la.ntiles), dim3(NTHREADS), 0,
+                       la.stream, la.jobs, la.tiles);
+  else if (precision == 2)
+    hipLaunchKernelGGL((k_cgls_init<float, bf16s>), dim3(la.ntiles), dim3(NTHREADS), 0,
+                       la.stream, la.jobs, la.tiles);
+  else
+    hipLaunchKernelGGL((k_cgls_init<float, float>), dim3(la.ntiles), dim3(NTHREADS), 0,
+                       la.stream, la.jobs, la.tiles);
+  return hipGetLastError();
+}
 
 hipError_t launch_stats_fin(const LaunchArgs& la) {
   hipLaunchKernelGGL(k_stats_fin, dim3(la.ntiles), dim3(NTHREADS), 0, la.stream, la.jobs,

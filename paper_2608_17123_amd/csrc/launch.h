@@ -26,7 +26,7 @@ enum VSlot : int {
   V_W,       // IRLS weights (n_L)
   V_B,       // right-hand side b (n)
   V_C1, V_C2,// shift c = C1 - C2 (SB: d - g), c = C1 (MM)
-  V_XOLD,    // previous outer iterate
+  V_XOLD,    // previous outer iterate (CGLS start: A x0)
   V_X0       // optional CGLS start
 };
 

@@ -167,20 +167,24 @@ int prof_collect(dbl_ctx* ctx) {
   return DBL_OK;
 }
 
-double job_bytes(const char* k, const Job& j, size_t esz) {
+double job_bytes(const char* k, const Job& j, int prec) {
   const double n = (double)j.m * j.m, nl = 2.0 * j.m * (j.m - 1);
   const bool irls = j.flags & F_IRLS;
+  const double e = prec == DBL_F64 ? 8.0 : 4.0;                            // x, b, w, c
+  const double v = prec == DBL_F64 ? 8.0 : (prec == DBL_BF16 ? 2.0 : 4.0);  // CGLS state
+  const double wb = irls ? nl * e : 0.0;
   const std::string s(k);
-  double e = 0.0;  // elements moved
-  if (s == "cgls_p1") e = 2 * n + 2 * n + nl + (irls ? nl : 0);            // s, p in; p, q1, q2 out
-  else if (s == "cgls_p2") e = 7 * n + 3 * nl + (irls ? nl : 0);           // r1,q1,x,p in; r1,x,s out; r2,q2 in; r2 out
-  else if (s == "apply_A") e = 2 * n;
-  else if (s == "stats") e = 3 * n;
-  else if (s == "aux") e = n + 2 * nl;
-  else if (s == "cgls_init") e = 3 * n + 2 * nl;
-  else if (s == "cgls_small")  // the tiled path's traffic for the same iterations
-    e = 3 * n + 2 * nl + j.i0 * (11 * n + 4 * nl + (irls ? 2 * nl : 0)) + 7 * n + 3 * nl;
-  return e * (double)esz;
+  // each operand read or written once
+  if (s == "cgls_p1") return (4 * n + nl) * v + wb;              // s, p in; p, q1, q2 out
+  if (s == "cgls_p2") return (5 * n + 3 * nl) * v + 2 * n * e + wb;  // r1,q1,p,r2,q2 in; r1,s,r2 out; x
+  if (s == "cgls_init") return (2 * n + nl) * v + (2 * n + nl) * e;
+  if (s == "cgls_small")  // the tiled path's traffic for the same iterations
+    return (2 * n + 2 * nl) * e + j.i0 * ((9 * n + 4 * nl) * v + 2 * n * e + 2 * wb);
+  double el = 0.0;  // elements of x, b, w, c moved
+  if (s == "apply_A") el = 2 * n;
+  else if (s == "stats") el = 3 * n;
+  else if (s == "aux") el = n + 2 * nl;
+  return el * e;
 }
 
 // Tiles per axis of a launch over an m x m grid.  Image, gradient and GCV
@@ -405,10 +409,13 @@ static bool wants_gcv(const dbl_opts& o) { return !o.mu_schedule && !(o.mu_fixed
 
 size_t slot_bytes(const dbl_request& req) {
   const size_t esz = req.opts.precision == DBL_F64 ? 8 : 4;
+  const size_t ssz = req.opts.precision == DBL_BF16 ? 2 : esz;  // CGLS state vectors
   const size_t n = (size_t)req.m * req.m, nl = 2 * (size_t)req.m * (req.m - 1);
   size_t b = 0;
-  b += 8 * align256(n * esz);
-  b += 6 * align256(nl * esz);
+  b += 2 * align256(n * esz) + 6 * align256(n * ssz);   // x x2; p x2, s, r1 x2, q1
+  // w, c1, c2 and r2 x2 (full width: Approach D transfers w / c into r2's
+  // buffers and swaps them with the originals); q2
+  b += 5 * align256(nl * esz) + align256(nl * ssz);
   for (int i = 1; i < req.levels; ++i) b += align256(((size_t)req.m >> i) * (req.m >> i) * esz);
   b += align256(NSCAL * 8) + align256(part_doubles(req.m) * 8) + 256;
   b += align256((size_t)req.levels * DBL_MAX_KOUT * 3 * 8);
@@ -452,17 +459,18 @@ int slot_init(dbl_ctx* ctx, const dbl_request& req, Slot* s) {
     return r;
   };
   const size_t n = s->n0, nl = s->nl0, e = s->esz;
+  const size_t v = s->prec == DBL_BF16 ? 2 : e;  // CGLS state vectors
   s->X[0] = take(n * e);
   s->X[1] = take(n * e);
-  s->P[0] = take(n * e);
-  s->P[1] = take(n * e);
-  s->S = take(n * e);
-  s->R1[0] = take(n * e);
-  s->R1[1] = take(n * e);
-  s->Q1 = take(n * e);
-  s->R2[0] = take(nl * e);
+  s->P[0] = take(n * v);
+  s->P[1] = take(n * v);
+  s->S = take(n * v);
+  s->R1[0] = take(n * v);
+  s->R1[1] = take(n * v);
+  s->Q1 = take(n * v);
+  s->R2[0] = take(nl * e);  // full width: Approach D swaps these with W / C1 / C2
   s->R2[1] = take(nl * e);
-  s->Q2 = take(nl * e);
+  s->Q2 = take(nl * v);
   s->W = take(nl * e);
   s->C1 = take(nl * e);
   s->C2 = take(nl * e);
@@ -578,7 +586,7 @@ int run_simple(dbl_ctx* ctx, SimpleFn fn, std::map<int, Launch>& byprec, const c
     int rc = kv.second.upload(ctx, la);
     if (rc) return rc;
     double b = 0.0;
-    for (const Job& jj : kv.second.jobs) b += job_bytes(what, jj, kv.first == 1 ? 8 : 4);
+    for (const Job& jj : kv.second.jobs) b += job_bytes(what, jj, kv.first);
     rc = hip_check(ctx, timed(ctx, what, b, [&] { return fn(la, kv.first); }), what);
     if (rc) return rc;
   }
@@ -852,7 +860,7 @@ int engine_step(dbl_ctx* ctx, std::vector<Slot*>& slots) {
       LaunchArgs la;
       if ((rc = kv.second.upload(ctx, la))) return rc;
       double b = 0.0;
-      for (const Job& jj : kv.second.jobs) b += job_bytes("cgls_small", jj, g.prec == 1 ? 8 : 4);
+      for (const Job& jj : kv.second.jobs) b += job_bytes("cgls_small", jj, g.prec);
       const size_t lds = smallB[kv.first];
       if ((rc = hip_check(ctx, timed(ctx, "cgls_small", b, [&] {
                             return launch_cgls_small(la, g.prec, g.rb, mm, lds);
@@ -874,7 +882,7 @@ int engine_step(dbl_ctx* ctx, std::vector<Slot*>& slots) {
     for (auto& kv : aF) {
       const GroupKey& g = kv.first;
       double b = 0.0;
-      for (const Job& jj : first[g].jobs) b += job_bytes("cgls_p2", jj, g.prec == 1 ? 8 : 4);
+      for (const Job& jj : first[g].jobs) b += job_bytes("cgls_p2", jj, g.prec);
       if ((rc = hip_check(ctx, timed(ctx, "cgls_p2", b, [&] {
                             return launch_cgls_p2(kv.second, g.prec, g.sep, g.rb, g.H);
                           }),
@@ -896,7 +904,7 @@ int engine_step(dbl_ctx* ctx, std::vector<Slot*>& slots) {
         la.ntiles = p1[par][g].tiles_upto[q - 1];
         double b = 0.0;
         for (int jq = 0; jq < q; ++jq)
-          b += job_bytes("cgls_p1", p1[par][g].jobs[jq], g.prec == 1 ? 8 : 4);
+          b += job_bytes("cgls_p1", p1[par][g].jobs[jq], g.prec);
         if ((rc = hip_check(ctx, timed(ctx, "cgls_p1", b, [&] {
                               return launch_cgls_p1(la, g.prec, g.sep, g.rb, g.H);
                             }),
@@ -913,7 +921,7 @@ int engine_step(dbl_ctx* ctx, std::vector<Slot*>& slots) {
         la.ntiles = p2[par][g].tiles_upto[q - 1];
         double b = 0.0;
         for (int jq = 0; jq < q; ++jq)
-          b += job_bytes("cgls_p2", p2[par][g].jobs[jq], g.prec == 1 ? 8 : 4);
+          b += job_bytes("cgls_p2", p2[par][g].jobs[jq], g.prec);
         if ((rc = hip_check(ctx, timed(ctx, "cgls_p2", b, [&] {
                               return launch_cgls_p2(la, g.prec, g.sep, g.rb, g.H);
                             }),
@@ -955,7 +963,7 @@ int engine_step(dbl_ctx* ctx, std::vector<Slot*>& slots) {
       if ((rc = kv.second.upload(ctx, la))) return rc;
       const GroupKey& g = kv.first;
       double b = 0.0;
-      for (const Job& jj : kv.second.jobs) b += job_bytes("stats", jj, g.prec == 1 ? 8 : 4);
+      for (const Job& jj : kv.second.jobs) b += job_bytes("stats", jj, g.prec);
       if ((rc = hip_check(ctx, timed(ctx, "stats", b, [&] {
                             return launch_stats(la, g.prec, g.sep, g.rb, g.H);
                           }),

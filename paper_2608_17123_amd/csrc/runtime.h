@@ -106,7 +106,7 @@ hipError_t timed(dbl_ctx* ctx, const char* name, double bytes, F&& launch) {
 size_t small_lds_bytes(const dbl_ctx* ctx, const dbl_op* op, int level, bool irls, int* wlds);
 
 // Algorithmic bytes of one job (each operand read or written once).
-double job_bytes(const char* kernel, const Job& j, size_t esz);
+double job_bytes(const char* kernel, const Job& j, int precision);
 
 // Jobs of one launch plus its tile table.
 struct Launch {

@@ -19,7 +19,7 @@ torch = pytest.importorskip("torch")
 D = pytest.importorskip("paper_2608_17123_amd")
 pytestmark = pytest.mark.gpu
 
-NP = {D.DBL_F32: np.float32, D.DBL_F64: np.float64}
+NP = {D.DBL_F32: np.float32, D.DBL_F64: np.float64, D.DBL_BF16: np.float32}
 
 
 @pytest.fixture(scope="module")
@@ -95,6 +95,73 @@ def test_cgls_matches_oracle(ctx, prec, kind, wavelet, level, psf, small):
     assert err <= CGLS_TOL[prec]
     assert herr <= CGLS_TOL[prec] * 10
     op.close()
+
+
+@pytest.mark.parametrize("prec", [D.DBL_F32, D.DBL_F64, D.DBL_BF16])
+@pytest.mark.parametrize("kind", ["irls", "mm"])
+def test_cgls_warm_start_matches_oracle(ctx, kind, prec):
+    """CGLS from a given x0 (the warm start of the subproblem): r1 = b - A x0
+    and r2 = sqrt(g) (c - D x0) in the compute type, then the same recurrence."""
+    m, levels, level = 128, 3, 0
+    P = synth.gaussian_psf(2.0, 6)
+    H = Hierarchy(P, m, levels, "haar")
+    nl = 2 * m * (m - 1)
+    rng = np.random.default_rng(33)
+    B = rnd(rng.standard_normal((m, m)), prec)
+    X0 = rnd(0.5 * rng.standard_normal((m, m)), prec)
+    w = rnd(rng.uniform(0.5, 5.0, nl), prec) if kind == "irls" else None
+    c = rnd(0.1 * rng.standard_normal(nl), prec) if kind == "mm" else None
+    sub = Subproblem(lambda X: H.apply(level, X), lambda X: H.apply_adjoint(level, X), m, B,
+                     0.02, weights=w, shift=c)
+    Xr, _ = sub.solve_cgls(20, x0=X0)
+    op = D.dbl_op_create(ctx, P, m, levels, "haar", prec)
+    x = torch.zeros(m * m, dtype=torch.float64 if prec == D.DBL_F64 else torch.float32,
+                    device="cuda")
+    D.dbl_cgls(ctx, op, level, dev(ops.vec(B), prec), 20, x, 0.02,
+               w=None if w is None else dev(w, prec), c=None if c is None else dev(c, prec),
+               x0=dev(ops.vec(X0), prec))
+    err = relerr(host(x), ops.vec(Xr))
+    print(f"cgls warm {kind} prec={prec}: x relerr {err:.2e}", flush=True)
+    op.close()
+    assert err <= (2e-2 if prec == D.DBL_BF16 else CGLS_TOL[prec])
+
+
+@pytest.mark.parametrize("small", [1, 0])
+@pytest.mark.parametrize("kind", ["irls", "mm"])
+def test_cgls_bf16_storage(ctx, kind, small):
+    """BF16 storage of the CGLS state (FP32 arithmetic, FP64 scalars) on the
+    tiled path (small = 0 at every level; small = 1 sends the 64 x 64 level
+    to the one-block kernel, whose LDS state is FP32): the error against the
+    FP64 oracle is reported and bounded by the BF16 unit roundoff scale."""
+    m, levels, level = 128, 3, 1
+    D.dbl_set_option(ctx, D.DBL_OPT_SMALL_CGLS, small)
+    P = synth.gaussian_psf(2.0, 6)
+    H = Hierarchy(P, m, levels, "db4")
+    mi = m >> level
+    nl = 2 * mi * (mi - 1)
+    rng = np.random.default_rng(21)
+    B = rnd(rng.standard_normal((mi, mi)), D.DBL_F32)
+    w = rnd(rng.uniform(0.5, 5.0, nl), D.DBL_F32) if kind == "irls" else None
+    c = rnd(0.1 * rng.standard_normal(nl), D.DBL_F32) if kind == "mm" else None
+    sub = Subproblem(lambda X: H.apply(level, X), lambda X: H.apply_adjoint(level, X), mi, B,
+                     0.02, weights=w, shift=c)
+    Xr, hist = sub.solve_cgls(30)
+    errs = {}
+    for prec in (D.DBL_F32, D.DBL_BF16):
+        op = D.dbl_op_create(ctx, P, m, levels, "db4", prec)
+        x = torch.zeros(mi * mi, dtype=torch.float32, device="cuda")
+        D.dbl_cgls(ctx, op, level, dev(ops.vec(B), prec), 30, x, 0.02,
+                   w=None if w is None else dev(w, prec), c=None if c is None else dev(c, prec))
+        errs[prec] = relerr(host(x), ops.vec(Xr))
+        op.close()
+    D.dbl_set_option(ctx, D.DBL_OPT_SMALL_CGLS, 1)
+    print(f"cgls {kind} small={small}: x relerr FP32 {errs[D.DBL_F32]:.2e}, "
+          f"BF16 storage {errs[D.DBL_BF16]:.2e}", flush=True)
+    assert errs[D.DBL_F32] <= CGLS_TOL[D.DBL_F32]
+    if small:
+        assert errs[D.DBL_BF16] == errs[D.DBL_F32]  # LDS state is FP32 there
+    else:
+        assert errs[D.DBL_BF16] <= 2e-2
 
 
 SOLVE_TOL = {D.DBL_F32: 1e-4, D.DBL_F64: 1e-9}

@@ -221,3 +221,42 @@ def test_context_teardown_leaves_no_hip_error():
     y = torch.ones(1024, device="cuda") * 2.0
     torch.cuda.synchronize()
     assert float(y.sum()) == 2048.0
+
+
+@pytest.mark.parametrize("solver,wavelet,transfer", [("irls", "haar", "X"), ("sb", "db4", "D"),
+                                                     ("mm", "db4", "X")])
+def test_config2_bf16_storage_error(ctx, solver, wavelet, transfer):
+    """BF16 storage of the CGLS state on the m = 256 configuration (fixed
+    parameters from the oracle, 3 outer iterations per level): the error in x
+    against the FP64 oracle is reported per solver, next to FP32's.  A batch
+    with BF16 storage equals its plain solves bit for bit."""
+    ws = [w for w in synth.config2() if (w.solver, w.wavelet, w.transfer) ==
+          (solver, wavelet, transfer)]
+    w = ws[0]
+    k_out = 3
+    B = blurred(w)
+    Xo, rep_o = vcycle.deblur(B, w.psf, w.solver, w.wavelet, w.levels, w.transfer, k_out, w.k_in,
+                              gcv_mode="spectral", fast=True)
+    mu = np.array([h["gamma"] for h in rep_o["levels"]]).ravel()
+    b = dev(B)
+    errs = {}
+    xs = {}
+    for prec in (D.DBL_F32, D.DBL_BF16):
+        x = torch.zeros_like(b)
+        D.dbl_deblur(ctx, b, w.psf, w.m, w.solver, w.wavelet, w.levels, w.transfer, x,
+                     D.dbl_opts_default(k_out=k_out, k_in=w.k_in, mu_schedule=mu, precision=prec))
+        xs[prec] = host(x)
+        errs[prec] = float(np.linalg.norm(xs[prec] - Xo.ravel(order="F")) / np.linalg.norm(Xo))
+    print(f"config2 {solver}/{wavelet}/{transfer}: x relerr FP32 {errs[D.DBL_F32]:.2e}, "
+          f"BF16 storage {errs[D.DBL_BF16]:.2e}", flush=True)
+    assert errs[D.DBL_F32] <= 1e-4
+    assert errs[D.DBL_BF16] <= 5e-2
+    # batch == plain with BF16 storage
+    x2 = torch.zeros_like(b)
+    x3 = torch.zeros_like(b)
+    kw = dict(k_out=k_out, k_in=w.k_in, mu_schedule=mu, precision=D.DBL_BF16)
+    reqs = [D.make_request(b, xx, w.psf, w.m, w.solver, w.wavelet, w.levels, w.transfer,
+                           D.dbl_opts_default(**kw)) for xx in (x2, x3)]
+    D.dbl_deblur_batch(ctx, reqs)
+    assert np.array_equal(host(x2), xs[D.DBL_BF16])
+    assert np.array_equal(host(x3), xs[D.DBL_BF16])
