@@ -57,6 +57,25 @@ def blur(X, P):
     return Y
 
 
+def blur_at(X, P, rows, cols, adjoint=False):
+    """(A X)[i, j] (adjoint: (A^T X)[i, j]) at the listed pixels only: the
+    zero-boundary convolution (correlation) summed term by term, for checks
+    on images too large for a whole-image product."""
+    X = np.asarray(X, dtype=np.float64)
+    m0, m1 = X.shape
+    rh, rw = _radii(P)
+    out = np.zeros(len(rows))
+    for k, (i, j) in enumerate(zip(rows, cols)):
+        acc = 0.0
+        for a in range(-rh, rh + 1):
+            for b in range(-rw, rw + 1):
+                ii, jj = (i + a, j + b) if adjoint else (i - a, j - b)
+                if 0 <= ii < m0 and 0 <= jj < m1:
+                    acc += P[a + rh, b + rw] * X[ii, jj]
+        out[k] = acc
+    return out
+
+
 def blur_adjoint(X, P):
     """(A^T X)[i, j] = sum_{a, b} P[a, b] X[i + a, j + b] (correlation)."""
     X = np.asarray(X, dtype=np.float64)

@@ -33,6 +33,20 @@ def test_blur_matches_scipy_same_convolution(m, shape):
     assert np.max(np.abs(ops.blur(X, P) - ref)) < 1e-12
 
 
+@pytest.mark.parametrize("m,shape", [(9, (5, 3)), (24, (21, 21))])
+def test_blur_at_matches_library_convolution(m, shape):
+    """The single-pixel sums agree with SciPy's zero-fill convolution and its
+    correlation (the adjoint) at every pixel, corners and edges included."""
+    P = rand(shape, 6)
+    X = rand((m, m), 7)
+    ii, jj = np.meshgrid(np.arange(m), np.arange(m), indexing="ij")
+    rows, cols = ii.ravel(), jj.ravel()
+    conv = convolve2d(X, P, mode="same", boundary="fill", fillvalue=0.0)
+    corr = convolve2d(X, P[::-1, ::-1], mode="same", boundary="fill", fillvalue=0.0)
+    assert np.max(np.abs(ops.blur_at(X, P, rows, cols) - conv.ravel())) < 1e-12
+    assert np.max(np.abs(ops.blur_at(X, P, rows, cols, adjoint=True) - corr.ravel())) < 1e-12
+
+
 @pytest.mark.parametrize("m,sigma,r", [(8, 1.5, 3), (16, 3.5, 6)])
 def test_blur_is_kronecker_of_toeplitz(m, sigma, r):
     """Sec. 5: A = At (x) At, At symmetric banded Toeplitz with first row z."""
