@@ -80,7 +80,11 @@ typedef enum { DBL_F32 = 0, DBL_F64 = 1, DBL_BF16 = 2 } dbl_precision;
 /* GCV tiers: SPECTRAL evaluates the GCV function of eq. (GCV) on the DCT
  * surrogate (reflexive-boundary blur, exact Neumann gradient); EXACT uses the
  * generalised eigendecomposition of the pair {A, D} (the paper's GSVD route,
- * Sec. 3) and is limited to n <= 4096; AUTO picks EXACT when n <= 4096. */
+ * Sec. 3): the dense level operator is formed on the device, A^T A v =
+ * nu (A^T A + D^T D) v is solved in FP64 (rocSOLVER sygvd), and the GCV
+ * function is evaluated from (nu, V^T A^T b, V^T D^T c, ||b||^2).  EXACT is
+ * limited to n <= 4096 (DBL_ENOTSUP above) and needs about 3 n^2 doubles of
+ * workspace (384 MB at n = 4096); AUTO picks EXACT when n <= 4096. */
 typedef enum { DBL_GCV_AUTO = 0, DBL_GCV_EXACT = 1, DBL_GCV_SPECTRAL = 2 } dbl_gcv_mode;
 
 typedef struct dbl_ctx dbl_ctx;

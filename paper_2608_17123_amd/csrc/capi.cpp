@@ -5,6 +5,8 @@
 #include <limits>
 #include <new>
 
+#include <rocblas/rocblas.h>
+
 #include "runtime.h"
 
 using namespace dbl;
@@ -146,6 +148,7 @@ int dbl_destroy(dbl_ctx* ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
   (void)prof_collect(ctx);
+  if (ctx->blas) (void)rocblas_destroy_handle(static_cast<rocblas_handle>(ctx->blas));
   // Cached operators free their own buffers (and untrack them) first; every
   // allocation still tracked after that is freed exactly once below.  A
   // second hipFree of a pointer would leave hipErrorInvalidValue as the
@@ -566,6 +569,7 @@ int dbl_gcv(dbl_ctx* ctx, const dbl_op* op, int level, const dbl_sub* sub, const
     rc = hip_check(ctx, hipMemcpyAsync(out + 1, g.scal + S_G_FBEST, sizeof(double),
                                        hipMemcpyDeviceToHost, ctx->stream), "read gcv");
   if (!rc) rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "sync");
+  else (void)hipStreamSynchronize(ctx->stream);  // queued work may still read blk
   dfree(ctx, blk);
   if (rc) return rc;
   *gamma_out = out[0];

@@ -37,7 +37,7 @@ enum Scal : int {
   // GCV state
   S_G_TLO = 32, S_G_THI, S_G_A, S_G_B, S_G_X, S_G_W, S_G_V, S_G_FX, S_G_FW,
   S_G_FV, S_G_D, S_G_E, S_G_U, S_G_DONE, S_G_NEV, S_G_XTOL, S_G_IT, S_G_RMIN,
-  S_G_RMAX, S_G_NPTS, S_G_WBAR, S_G_RES, S_G_TR, S_G_FBEST,
+  S_G_RMAX, S_G_NPTS, S_G_WBAR, S_G_RES, S_G_TR, S_G_FBEST, S_G_BB,
   S_GRID = 64,   // up to 64 grid values
   S_HIST = 128,  // CGLS residual history (up to 128 iterations)
   S_BR = 256     // Brent state, two copies of BR_SIZE (read one, write the other)
@@ -146,6 +146,7 @@ enum : int {
   F_HIST = 32,      // record CGLS residual history
   F_FIRST = 64,     // first phase after init (alpha = 0)
   F_WLDS = 128,     // one-block CGLS: IRLS weights staged in LDS
+  F_EXACT = 256,    // GCV job on exact pencil data (nu, f, g, ||b||^2)
 };
 
 __device__ __forceinline__ void decode_tile(const Job* __restrict__ jobs,

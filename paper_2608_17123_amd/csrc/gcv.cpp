@@ -1,5 +1,10 @@
-// GCV driver (Sec. 3): spectral data, grid search and Brent refinement for a
-// batch of subproblems; writes gamma and sqrt(gamma) into each scalar block.
+// GCV driver (Sec. 3): spectral (DCT surrogate) or exact (generalised
+// eigendecomposition of the pencil, n <= 4096) data, grid search and Brent
+// refinement for a batch of subproblems; writes gamma and sqrt(gamma) into
+// each scalar block.
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
 #include <cmath>
 #include <cstring>
 
@@ -79,22 +84,153 @@ int ensure_symbol(dbl_ctx* ctx, const dbl_op* cop, int level, double** sym) {
   return DBL_OK;
 }
 
+int blas_check(dbl_ctx* ctx, rocblas_status st, const char* what) {
+  if (st == rocblas_status_success) return DBL_OK;
+  return set_err(ctx, DBL_EDEVICE, std::string(what) + ": rocBLAS/rocSOLVER status " +
+                                       std::to_string((int)st));
+}
+
+// EXACT tier data of one request (n = m^2 <= 4096), in FP64 on the device:
+//   Ad  = A^(level) applied to every unit vector (the library's own stencil
+//         kernel, FP64 tables) -- the dense level operator;
+//   K   = Ad^T Ad (rocBLAS syrk), M = K + D^T D (D = diag(w) L or L);
+//   (nu, V) = generalised eigenpairs of K v = nu M v with V^T M V = I
+//         (rocSOLVER sygvd, ascending nu);
+//   f = V^T Ad^T b, g = V^T L^T c (0 without a shift), ||b||^2.
+// Results: nu in r.in, f in r.bh, g in r.e, ||b||^2 in scal[S_G_BB].
+int exact_data(dbl_ctx* ctx, const GcvReq& r, Job& base) {
+  const LevelHost& L = r.op->host.levels[r.level];
+  const int m = L.m, n = m * m;
+  int rc = DBL_OK;
+  const size_t nn = (size_t)n * n;
+  const size_t need = 3 * nn * 8 + 2 * (size_t)n * 8 + 256;
+  if (ctx->gx_bytes < need) {
+    if ((rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "sync"))) return rc;
+    dfree(ctx, ctx->gx);
+    ctx->gx = nullptr;
+    ctx->gx_bytes = 0;
+    if ((rc = dmalloc(ctx, need, &ctx->gx))) return rc;
+    ctx->gx_bytes = need;
+  }
+  if (!ctx->blas) {
+    rocblas_handle h = nullptr;
+    if ((rc = blas_check(ctx, rocblas_create_handle(&h), "rocblas_create_handle"))) return rc;
+    ctx->blas = h;
+  }
+  rocblas_handle h = static_cast<rocblas_handle>(ctx->blas);
+  if ((rc = blas_check(ctx, rocblas_set_stream(h, ctx->stream), "rocblas_set_stream"))) return rc;
+  double* X1 = static_cast<double*>(ctx->gx);  // identity, then M
+  double* Ad = X1 + nn;
+  double* K = Ad + nn;                           // K, then V
+  double* nu = K + nn;
+  double* E = nu + n;
+  rocblas_int* info = reinterpret_cast<rocblas_int*>(E + n);
+  // b in FP64 (r.in), ||b||^2
+  {
+    Launch P;
+    Job j = base;
+    j.i0 = 0;
+    P.add(j, m, 4);
+    LaunchArgs la;
+    if ((rc = P.upload(ctx, la))) return rc;
+    if ((rc = hip_check(ctx, launch_gcv_prep(la, r.prec), "gcv prep"))) return rc;
+  }
+  if ((rc = blas_check(ctx, rocblas_set_pointer_mode(h, rocblas_pointer_mode_device), "mode")))
+    return rc;
+  if ((rc = blas_check(ctx, rocblas_ddot(h, n, r.in, 1, r.in, 1, r.scal + S_G_BB), "ddot")))
+    return rc;
+  if ((rc = blas_check(ctx, rocblas_set_pointer_mode(h, rocblas_pointer_mode_host), "mode")))
+    return rc;
+  // dense operator: Ad = A I, column by column in one launch (one job per column)
+  if ((rc = hip_check(ctx, launch_gcv_eye(X1, n, ctx->stream), "gcv eye"))) return rc;
+  {
+    Launch La;
+    for (int c = 0; c < n; ++c) {
+      Job j;
+      std::memset(&j, 0, sizeof(j));
+      j.m = m;
+      j.op = r.op->d_ops + r.level;
+      j.v[0] = X1 + (size_t)c * n;
+      j.v[1] = Ad + (size_t)c * n;
+      La.add(j, m, 8);
+    }
+    LaunchArgs la;
+    if ((rc = La.upload(ctx, la))) return rc;
+    const int sep = L.sep ? 1 : 0, H = L.sep ? L.rb : L.R;
+    if ((rc = hip_check(ctx, launch_apply_A(la, 1, sep, L.rb, H), "dense operator"))) return rc;
+  }
+  const double one = 1.0, zero = 0.0;
+  // A^T b into r.tmp; K = Ad^T Ad (lower triangle)
+  if ((rc = blas_check(ctx, rocblas_dgemv(h, rocblas_operation_transpose, n, n, &one, Ad, n,
+                                          r.in, 1, &zero, r.tmp, 1), "dgemv A^T b")))
+    return rc;
+  if ((rc = blas_check(ctx, rocblas_dsyrk(h, rocblas_fill_lower, rocblas_operation_transpose, n,
+                                          n, &one, Ad, n, &zero, K, n), "dsyrk")))
+    return rc;
+  // L^T c into r.in (shift), M = K + D^T D
+  if (r.c1) {
+    Launch P;
+    Job j = base;
+    j.i0 = 1;
+    j.v[G_W] = nullptr;  // no weight partials needed here
+    P.add(j, m, 4);
+    LaunchArgs la;
+    if ((rc = P.upload(ctx, la))) return rc;
+    if ((rc = hip_check(ctx, launch_gcv_prep(la, r.prec), "gcv prep"))) return rc;
+  }
+  if ((rc = hip_check(ctx, hipMemcpyAsync(X1, K, nn * 8, hipMemcpyDeviceToDevice, ctx->stream),
+                      "copy K")))
+    return rc;
+  if ((rc = hip_check(ctx, launch_gcv_add_dtd(X1, r.w, r.prec, m, ctx->stream), "D^T D")))
+    return rc;
+  if ((rc = blas_check(ctx, rocsolver_dsygvd(h, rocblas_eform_ax, rocblas_evect_original,
+                                             rocblas_fill_lower, n, K, n, X1, n, nu, E, info),
+                       "dsygvd")))
+    return rc;
+  rocblas_int hinfo = 0;
+  if ((rc = hip_check(ctx, hipMemcpyAsync(&hinfo, info, sizeof(hinfo), hipMemcpyDeviceToHost,
+                                          ctx->stream), "read info")))
+    return rc;
+  if ((rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "sync"))) return rc;
+  if (hinfo != 0)
+    return set_err(ctx, DBL_ENUMERIC, "generalised eigensolver failed (info " +
+                                          std::to_string(hinfo) + ")");
+  // f = V^T (A^T b) into r.bh; g = V^T (L^T c) into r.e; nu into r.in
+  if ((rc = blas_check(ctx, rocblas_dgemv(h, rocblas_operation_transpose, n, n, &one, K, n,
+                                          r.tmp, 1, &zero, r.bh, 1), "dgemv f")))
+    return rc;
+  if (r.c1) {
+    if ((rc = blas_check(ctx, rocblas_dgemv(h, rocblas_operation_transpose, n, n, &one, K, n,
+                                            r.in, 1, &zero, r.e, 1), "dgemv g")))
+      return rc;
+  } else if ((rc = hip_check(ctx, hipMemsetAsync(r.e, 0, (size_t)n * 8, ctx->stream), "g = 0"))) {
+    return rc;
+  }
+  return hip_check(ctx, hipMemcpyAsync(r.in, nu, (size_t)n * 8, hipMemcpyDeviceToDevice,
+                                       ctx->stream), "copy nu");
+}
+
 }  // namespace
 
 int gcv_run(dbl_ctx* ctx, std::vector<GcvReq>& reqs) {
   int rc = DBL_OK;
-  for (auto& r : reqs)
-    if (r.mode == DBL_GCV_EXACT)
-      return set_err(ctx, DBL_ENOTSUP, "EXACT GCV is not available in this build; use SPECTRAL");
+  for (auto& r : reqs) {
+    const int m = r.op->host.levels[r.level].m;
+    if (r.mode == DBL_GCV_EXACT && m * m > 4096)
+      return set_err(ctx, DBL_ENOTSUP, "EXACT GCV needs n <= 4096; use SPECTRAL");
+  }
   std::vector<Job> base(reqs.size());
   std::vector<PartLayout> PLs(reqs.size());
   for (size_t q = 0; q < reqs.size(); ++q) {
     GcvReq& r = reqs[q];
     const int m = r.op->host.levels[r.level].m;
     PLs[q] = part_layout(r.part, m);
+    const bool exact = r.mode == DBL_GCV_EXACT;
     double *sym = nullptr, *dct = nullptr;
-    if ((rc = ensure_symbol(ctx, r.op, r.level, &sym))) return rc;
-    if ((rc = ensure_dct(ctx, m, &dct))) return rc;
+    if (!exact) {
+      if ((rc = ensure_symbol(ctx, r.op, r.level, &sym))) return rc;
+      if ((rc = ensure_dct(ctx, m, &dct))) return rc;
+    }
     Job& j = base[q];
     std::memset(&j, 0, sizeof(j));
     j.m = m;
@@ -109,10 +245,14 @@ int gcv_run(dbl_ctx* ctx, std::vector<GcvReq>& reqs) {
     j.v[G_TMP] = r.tmp;
     j.v[G_BH] = r.bh;
     j.v[G_E] = r.e;
-    j.v[G_SYM] = sym;
-    j.v[G_LAM] = sym + (size_t)m * m;
+    j.v[G_SYM] = exact ? r.in : sym;  // exact: nu (written by exact_data)
+    j.v[G_LAM] = exact ? nullptr : sym + (size_t)m * m;
     j.v[G_DCT] = dct;
+    if (exact) j.flags |= F_EXACT;
   }
+  // EXACT tier data, one request at a time (shared dense workspace)
+  for (size_t q = 0; q < reqs.size(); ++q)
+    if (reqs[q].mode == DBL_GCV_EXACT && (rc = exact_data(ctx, reqs[q], base[q]))) return rc;
   auto run = [&](hipError_t (*fn)(const LaunchArgs&), Launch& L, const char* what) -> int {
     if (L.empty()) return DBL_OK;
     LaunchArgs la;
@@ -158,7 +298,7 @@ int gcv_run(dbl_ctx* ctx, std::vector<GcvReq>& reqs) {
     std::map<int, Launch> P;
     std::vector<size_t> sel;
     for (size_t q = 0; q < reqs.size(); ++q) {
-      if (reqs[q].bh_valid) continue;
+      if (reqs[q].bh_valid || reqs[q].mode == DBL_GCV_EXACT) continue;
       Job j = base[q];
       j.i0 = 0;
       P[reqs[q].prec].add(j, j.m, 4);
@@ -172,6 +312,7 @@ int gcv_run(dbl_ctx* ctx, std::vector<GcvReq>& reqs) {
     std::map<int, Launch> P;
     std::vector<size_t> sel;
     for (size_t q = 0; q < reqs.size(); ++q) {
+      if (reqs[q].mode == DBL_GCV_EXACT) continue;
       Job j = base[q];
       j.i0 = 1;
       j.pw = PLs[q].gw;
@@ -186,9 +327,10 @@ int gcv_run(dbl_ctx* ctx, std::vector<GcvReq>& reqs) {
     Launch Ld, Lg, Lf, Lb[2];
     for (size_t q = 0; q < reqs.size(); ++q) {
       const PartLayout& PL = PLs[q];
+      const bool exact = reqs[q].mode == DBL_GCV_EXACT;
       Job j = base[q];
       j.i0 = reqs[q].c1 ? 1 : 0;
-      j.pr[0] = reqs[q].w ? PL.gw : nullptr;
+      j.pr[0] = (reqs[q].w && !exact) ? PL.gw : nullptr;
       j.pw = PL.gmm;
       Ld.add(j, j.m, 4);
       Job g = base[q];

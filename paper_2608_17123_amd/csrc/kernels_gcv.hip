@@ -13,12 +13,23 @@
 // the smallest and largest s/lp, lower bound clamped to 14 decades below the
 // upper), then Brent's method (golden section with parabolic steps) on the
 // interval around the grid minimum, xtol 1e-8 in log10(g), at most 100 steps.
+// EXACT tier (levels with n <= 4096): the data are the generalised
+// eigenvalues nu_k of the pencil (A^T A, A^T A + D^T D) with B-orthonormal
+// eigenvectors V, f = V^T A^T b, g = V^T D^T c and ||b||^2 (built on the
+// host side by gcv.cpp), and with den_k = nu_k + g (1 - nu_k),
+// y_k = (f_k + g g_k) / den_k:
+//   resid(g) = ||b||^2 - 2 sum f_k y_k + sum nu_k y_k^2,
+//   trace(g) = sum nu_k / den_k,  GCV(g) = resid(g) / (n - trace(g))^2,
+// grid bounds from log10(nu / (1 - nu)) over 0 < nu < 1 - 1e-10.  The same
+// grid and Brent kernels evaluate both tiers (Job flag F_EXACT).
 // Brent runs as a device state machine over a fixed number of launches: each
 // launch sums the previous evaluation's per-tile partials (every block, same
 // order), advances the state identically in every block, persists it (tile 0
 // of the job) in the copy the next launch reads, and evaluates GCV at the new
 // point.  State copies and partial arrays alternate between launches, so no
 // block ever reads what another block of the same launch writes.
+#include <algorithm>
+
 #include "launch.h"
 #include "stencil.h"
 
@@ -42,9 +53,46 @@ enum : int {
 
 constexpr int DBL_GCV_GRID_MAX_DEV = 64;
 
-__device__ __forceinline__ double gcv_from(double gam, double res, double tr, int n) {
+// GCV from the summed terms: spectral resid = gam^2 res; exact resid = bb + res.
+__device__ __forceinline__ double gcv_from(const Job* job, double gam, double res, double tr,
+                                           int n) {
   const double d = (double)n - tr;
+  if (job->flags & F_EXACT) return (job->scal[S_G_BB] + res) / (d * d);
   return gam * gam * res / (d * d);
+}
+
+// ------------------------------------------------------ EXACT tier prep --
+// n x n identity, column-major: the input columns of the dense-operator
+// launch (A applied to every unit vector).
+__global__ void __launch_bounds__(NTHREADS) k_gcv_eye(double* __restrict__ I, int n) {
+  const size_t tot = (size_t)n * n;
+  for (size_t q = blockIdx.x * (size_t)NTHREADS + threadIdx.x; q < tot;
+       q += (size_t)gridDim.x * NTHREADS)
+    I[q] = (q % (size_t)(n + 1) == 0) ? 1.0 : 0.0;
+}
+
+// M += D^T D for D = diag(w) L (w null: D = L) on an m x m grid.  Thread p
+// owns column p of M: its diagonal (the sum of the squared weights of the
+// differences that touch pixel p) and minus the squared weight at each grid
+// neighbour, so no two threads write the same entry.
+template <typename T>
+__global__ void __launch_bounds__(NTHREADS) k_gcv_add_dtd(double* __restrict__ M,
+                                                          const T* __restrict__ w, int m) {
+  const int n = m * m, nx = (m - 1) * m;
+  auto om = [&](int k) {
+    const double v = w ? (double)w[k] : 1.0;
+    return v * v;
+  };
+  for (int p = blockIdx.x * NTHREADS + threadIdx.x; p < n; p += gridDim.x * NTHREADS) {
+    const int i = p % m, j = p / m;
+    double* col = M + (size_t)p * n;
+    double diag = 0.0;
+    if (i > 0) { const double o = om(i - 1 + j * (m - 1)); diag += o; col[p - 1] -= o; }
+    if (i < m - 1) { const double o = om(i + j * (m - 1)); diag += o; col[p + 1] -= o; }
+    if (j > 0) { const double o = om(nx + p - m); diag += o; col[p - m] -= o; }
+    if (j < m - 1) { const double o = om(nx + p); diag += o; col[p + m] -= o; }
+    col[p] += diag;
+  }
 }
 
 // -------------------------------------------------------------- symbol ----
@@ -202,6 +250,7 @@ __global__ void __launch_bounds__(NTHREADS) k_gcv_data(const Job* __restrict__ j
   const double* __restrict__ bh = static_cast<const double*>(job->v[G_BH]);
   double* __restrict__ e = static_cast<double*>(job->v[G_E]);
   const bool shift = job->i0 != 0;
+  const bool exact = job->flags & F_EXACT;
   // IRLS weight scale wbar^2 = mean(w^2) from the prep partials, else 1
   double wb2 = 1.0;
   if (job->pr[0])
@@ -209,7 +258,20 @@ __global__ void __launch_bounds__(NTHREADS) k_gcv_data(const Job* __restrict__ j
           (2.0 * (double)m * (m - 1));
   if (tix == 0 && threadIdx.x == 0) job->scal[S_G_WBAR] = wb2;
   double lo = 1e300, hi = -1e300;
-  for (int o = threadIdx.x; o < TI * TJ; o += NTHREADS) {
+  for (int o = threadIdx.x; o < TI * TJ && exact; o += NTHREADS) {
+    // nu in the symbol slot: bounds from nu / (1 - nu) over 0 < nu < 1 - 1e-10
+    const size_t g = (i0 + o % TI) + (size_t)(j0 + o / TI) * m;
+    const double nu = fmin(fmax(sym[g], 0.0), 1.0);
+    if (nu > 0.0 && nu < 1.0 - 1e-10) {
+      const double r = nu / (1.0 - nu);
+      if (r > 0.0 && r < 1e308) {
+        const double t = log10(r);
+        lo = fmin(lo, t);
+        hi = fmax(hi, t);
+      }
+    }
+  }
+  for (int o = threadIdx.x; o < TI * TJ && !exact; o += NTHREADS) {
     const int k0 = i0 + o % TI, k1 = j0 + o / TI;
     const size_t g = k0 + (size_t)k1 * m;
     const double a = sym[g];
@@ -253,22 +315,45 @@ __device__ __forceinline__ void load_freqs(const Job* job, int i0, int j0, int T
   const double* __restrict__ lam = static_cast<const double*>(job->v[G_LAM]);
   const double* __restrict__ e = static_cast<const double*>(job->v[G_E]);
   const double wb2 = job->scal[S_G_WBAR];
+  const bool exact = job->flags & F_EXACT;
+  const double* __restrict__ fv = static_cast<const double*>(job->v[G_BH]);
   f.cnt = 0;
   for (int o = threadIdx.x; o < TI * TJ; o += NTHREADS) {
     const int k0 = i0 + o % TI, k1 = j0 + o / TI;
     const size_t g = k0 + (size_t)k1 * m;
-    const double a = sym[g];
-    f.s[f.cnt] = a * a;
-    f.lp[f.cnt] = wb2 * (lam[k0] + lam[k1]);
-    f.e[f.cnt] = e[g];
+    if (exact) {  // (nu, f, g) in the (s, lp, e) registers
+      f.s[f.cnt] = fmin(fmax(sym[g], 0.0), 1.0);
+      f.lp[f.cnt] = fv[g];
+      f.e[f.cnt] = e[g];
+    } else {
+      const double a = sym[g];
+      f.s[f.cnt] = a * a;
+      f.lp[f.cnt] = wb2 * (lam[k0] + lam[k1]);
+      f.e[f.cnt] = e[g];
+    }
     ++f.cnt;
   }
 }
 
-__device__ __forceinline__ void eval_freqs(const FreqRegs& f, double gam, double& res,
-                                           double& tr) {
+__device__ __forceinline__ void eval_freqs(const Job* job, const FreqRegs& f, double gam,
+                                           double& res, double& tr) {
   res = 0.0;
   tr = 0.0;
+  if (job->flags & F_EXACT) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      if (q < f.cnt) {
+        const double nu = f.s[q];
+        const double den = nu + gam * (1.0 - nu);
+        if (den > 0.0) {
+          const double y = (f.lp[q] + gam * f.e[q]) / den;
+          res += nu * y * y - 2.0 * f.lp[q] * y;
+          tr += nu / den;
+        }
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
     if (q < f.cnt) {
@@ -323,7 +408,7 @@ __global__ void __launch_bounds__(NTHREADS) k_gcv_grid(const Job* __restrict__ j
   for (int p = 0; p < npts; ++p) {
     const double t = tlo + (thi - tlo) * p / (npts - 1);
     double res, tr;
-    eval_freqs(f, pow(10.0, t), res, tr);
+    eval_freqs(job, f, pow(10.0, t), res, tr);
     res = wave_sum(res);
     tr = wave_sum(tr);
     __syncthreads();
@@ -355,7 +440,7 @@ __global__ void __launch_bounds__(NTHREADS) k_gcv_gridfin(const Job* __restrict_
       b += job->pr[0][(size_t)t * 2 * npts + 2 * p + 1];
     }
     const double t = tlo + (thi - tlo) * p / (npts - 1);
-    vals[p] = gcv_from(pow(10.0, t), a, b, n);
+    vals[p] = gcv_from(job, pow(10.0, t), a, b, n);
     sc[S_GRID + p] = vals[p];
   }
   __syncthreads();
@@ -414,7 +499,7 @@ __global__ void __launch_bounds__(NTHREADS) k_gcv_brent(const Job* __restrict__ 
     const double res = sum_partials<2>(job->pr[0], nt, 0, red, &bc);
     const double tr = sum_partials<2>(job->pr[0], nt, 1, red, &bc);
     const double u = st[BR_U];
-    const double fu = gcv_from(pow(10.0, u), res, tr, n);
+    const double fu = gcv_from(job, pow(10.0, u), res, tr, n);
     const double golden = 0.5 * (3.0 - sqrt(5.0));
     const double sqeps = sqrt(2.220446049250313e-16);
     const double xtol = job->p0;
@@ -491,7 +576,7 @@ __global__ void __launch_bounds__(NTHREADS) k_gcv_brent(const Job* __restrict__ 
   FreqRegs f;
   load_freqs(job, i0, j0, TI, TJ, f);
   double res, tr;
-  eval_freqs(f, pow(10.0, st[BR_U]), res, tr);
+  eval_freqs(job, f, pow(10.0, st[BR_U]), res, tr);
   double vv[2] = {res, tr};
   put_partials<2>(job->pw, tix, vv, red);
 }
@@ -512,6 +597,25 @@ hipError_t launch_gcv_symbol(const LaunchArgs& la) {
   GLAUNCH(k_gcv_symbol, la);
   return hipGetLastError();
 }
+hipError_t launch_gcv_eye(double* I, int n, hipStream_t stream) {
+  const size_t tot = (size_t)n * n;
+  const int blocks = (int)std::min<size_t>((tot + NTHREADS - 1) / NTHREADS, 4096);
+  hipLaunchKernelGGL(k_gcv_eye, dim3(blocks), dim3(NTHREADS), 0, stream, I, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_gcv_add_dtd(double* M, const void* w, int precision, int m,
+                              hipStream_t stream) {
+  const int blocks = (m * m + NTHREADS - 1) / NTHREADS;
+  if (precision == 1)
+    hipLaunchKernelGGL((k_gcv_add_dtd<double>), dim3(blocks), dim3(NTHREADS), 0, stream, M,
+                       static_cast<const double*>(w), m);
+  else
+    hipLaunchKernelGGL((k_gcv_add_dtd<float>), dim3(blocks), dim3(NTHREADS), 0, stream, M,
+                       static_cast<const float*>(w), m);
+  return hipGetLastError();
+}
+
 hipError_t launch_gcv_data(const LaunchArgs& la) { GLAUNCH(k_gcv_data, la); return hipGetLastError(); }
 hipError_t launch_gcv_grid(const LaunchArgs& la, int) { GLAUNCH(k_gcv_grid, la); return hipGetLastError(); }
 hipError_t launch_gcv_brent(const LaunchArgs& la) { GLAUNCH(k_gcv_brent, la); return hipGetLastError(); }

@@ -69,5 +69,9 @@ hipError_t launch_gcv_data(const LaunchArgs& la);
 hipError_t launch_gcv_grid(const LaunchArgs& la, int ngroups);
 hipError_t launch_gcv_brent(const LaunchArgs& la);
 hipError_t launch_gcv_gridfin(const LaunchArgs& la);
+// EXACT tier: n x n identity; M += D^T D (D = diag(w) L, w of `precision`, or L)
+hipError_t launch_gcv_eye(double* I, int n, hipStream_t stream);
+hipError_t launch_gcv_add_dtd(double* M, const void* w, int precision, int m,
+                              hipStream_t stream);
 
 }  // namespace dbl

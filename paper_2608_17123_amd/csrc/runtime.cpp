@@ -774,7 +774,7 @@ int engine_step(dbl_ctx* ctx, std::vector<Slot*>& slots) {
       g.mode = s->opts.gcv_mode == DBL_GCV_AUTO ? (n <= 4096 ? DBL_GCV_EXACT : DBL_GCV_SPECTRAL)
                                                 : s->opts.gcv_mode;
       greqs.push_back(g);
-      s->bh_valid = true;
+      s->bh_valid = g.mode == DBL_GCV_SPECTRAL;  // the exact tier reuses the DCT buffer
     }
     if (!greqs.empty() && (rc = gcv_run(ctx, greqs))) return rc;
   }

@@ -50,6 +50,10 @@ struct dbl_ctx {
   // dynamic LDS limit per block
   int small_cgls = 1;
   size_t lds_limit = 65536;
+  // EXACT-tier GCV: rocBLAS handle (rocblas_handle) and dense FP64 workspace
+  void* blas = nullptr;
+  void* gx = nullptr;
+  size_t gx_bytes = 0;
 };
 
 struct dbl_op {

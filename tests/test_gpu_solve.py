@@ -198,6 +198,36 @@ def test_deblur_fixed_mu_matches_oracle(ctx, prec, solver, wavelet, transfer, le
     assert oerr <= max(OBJ_TOL[prec], 0.0) * 100  # reported; tightened once measured
 
 
+@pytest.mark.parametrize("prec", [D.DBL_F64, D.DBL_F32])
+@pytest.mark.parametrize("kind", ["irls", "mm", "plain"])
+@pytest.mark.parametrize("m,level,wavelet", [(64, 0, "haar"), (64, 1, "db4"), (128, 2, "db4")])
+def test_gcv_exact_matches_oracle(ctx, kind, m, level, wavelet, prec):
+    """EXACT tier (n <= 4096): the generalised eigendecomposition of the
+    pencil on the device against the oracle's dense eigh route, gamma within
+    1e-3 and the GCV value within 1e-6."""
+    X, P, B = problem(m, 17, prec=prec)
+    H = Hierarchy(P, m, 3, wavelet)
+    Bi = rnd(H.restrict_rhs(B)[level], prec)
+    mi = m >> level
+    nl = 2 * mi * (mi - 1)
+    rng = np.random.default_rng(19)
+    w = rnd(rng.uniform(0.5, 5.0, nl), prec) if kind == "irls" else None
+    c = rnd(0.05 * rng.standard_normal(nl), prec) if kind == "mm" else None
+    Ld = ops.grad_dense(mi)
+    Dd = Ld if w is None else w[:, None] * Ld
+    data = ogcv.exact_data(H.dense(level), Dd, ops.vec(Bi), c)
+    g_ref, f_ref, _ = ogcv.choose_gamma(data)
+    op = D.dbl_op_create(ctx, P, m, 3, wavelet, prec)
+    g, f = D.dbl_gcv(ctx, op, level, dev(ops.vec(Bi), prec),
+                     w=None if w is None else dev(w, prec), c=None if c is None else dev(c, prec),
+                     mode="exact")
+    print(f"gcv exact {kind} m={mi} prec={prec}: gpu {g:.10e} oracle {g_ref:.10e} "
+          f"(GCV {f:.6e} vs {f_ref:.6e})", flush=True)
+    op.close()
+    assert abs(g - g_ref) <= 1e-3 * g_ref
+    assert abs(f - f_ref) <= 1e-6 * f_ref
+
+
 @pytest.mark.parametrize("kind", ["irls", "mm", "sb", "plain"])
 @pytest.mark.parametrize("m,level", [(64, 0), (256, 1)])
 def test_gcv_spectral_matches_oracle(ctx, kind, m, level):

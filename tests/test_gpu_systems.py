@@ -172,6 +172,28 @@ def test_config1_gcv_on_matches_oracle(ctx, prec):
     assert xerr <= 1e-4
 
 
+@pytest.mark.parametrize("prec", [D.DBL_F64, D.DBL_F32])
+def test_config1_exact_gcv_matches_oracle(ctx, prec):
+    """m = 64, 3 grids, IRLS two-pass GCV with the EXACT tier at every level
+    (AUTO: n <= 4096) on both sides; 10 x 30 as configured."""
+    w = synth.config1()
+    npdt = np.float32 if prec == D.DBL_F32 else np.float64
+    B = blurred(w, npdt)
+    Xo, rep_o = vcycle.deblur(B, w.psf, w.solver, w.wavelet, w.levels, w.transfer, w.k_out,
+                              w.k_in, gcv_mode="auto")
+    b = dev(B, torch.float32 if prec == D.DBL_F32 else torch.float64)
+    x = torch.zeros_like(b)
+    rep = D.dbl_deblur(ctx, b, w.psf, w.m, w.solver, w.wavelet, w.levels, w.transfer, x,
+                       D.dbl_opts_default(k_out=w.k_out, k_in=w.k_in, precision=prec))
+    g_o = np.array([h["gamma"] for h in rep_o["levels"]])
+    g_g = np.array(rep["gamma"])
+    gerr = float(np.max(np.abs(g_g - g_o) / g_o))
+    xerr = float(np.linalg.norm(host(x) - Xo.ravel(order="F")) / np.linalg.norm(Xo))
+    print(f"config1 exact GCV prec={prec}: gamma relerr {gerr:.2e}, x relerr {xerr:.2e}")
+    assert gerr <= 1e-3
+    assert xerr <= 1e-4
+
+
 def test_config2_sample_fixed_mu_and_gcv(ctx):
     """m = 256, 4 grids: the oracle's GCV parameters frozen and passed to the
     GPU (x within 1e-4, objective within 1e-6), and the GPU's own GCV run
