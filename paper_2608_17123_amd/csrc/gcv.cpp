@@ -322,9 +322,10 @@ int gcv_run(dbl_ctx* ctx, std::vector<GcvReq>& reqs) {
     if ((rc = run_prec(P, "gcv_prep"))) return rc;
     if (!sel.empty() && (rc = dct2(sel, G_E))) return rc;
   }
-  // 3. per-frequency data and grid bounds; 4. grid; 5. Brent
+  // 3. per-frequency data and grid bounds; 4. grid; 5. Brent (levels of at
+  //    most 64 x 64: 4 and 5 in one block per job)
   {
-    Launch Ld, Lg, Lf, Lb[2];
+    Launch Ld, Lg, Lf, Lb[2], Ls;
     for (size_t q = 0; q < reqs.size(); ++q) {
       const PartLayout& PL = PLs[q];
       const bool exact = reqs[q].mode == DBL_GCV_EXACT;
@@ -333,6 +334,17 @@ int gcv_run(dbl_ctx* ctx, std::vector<GcvReq>& reqs) {
       j.pr[0] = (reqs[q].w && !exact) ? PL.gw : nullptr;
       j.pw = PL.gmm;
       Ld.add(j, j.m, 4);
+      if (j.m <= 64) {
+        Job o = base[q];
+        o.i0 = reqs[q].grid;
+        const int t = tiles_per_axis(o.m, 4);
+        o.i1 = t * t;
+        o.pr[0] = PL.gmm;
+        o.p0 = BRENT_XTOL;
+        o.p1 = BRENT_MAXIT;
+        Ls.add(o, 1, 4);
+        continue;
+      }
       Job g = base[q];
       g.i1 = reqs[q].grid;
       g.pr[0] = PL.gmm;
@@ -355,6 +367,8 @@ int gcv_run(dbl_ctx* ctx, std::vector<GcvReq>& reqs) {
       }
     }
     if ((rc = run(launch_gcv_data, Ld, "gcv_data"))) return rc;
+    if ((rc = run(launch_gcv_solo, Ls, "gcv_solo"))) return rc;
+    if (Lg.empty()) return DBL_OK;
     LaunchArgs lg;
     if ((rc = Lg.upload(ctx, lg))) return rc;
     if ((rc = hip_check(ctx, timed(ctx, "gcv_grid", 0.0, [&] { return launch_gcv_grid(lg, 0); }),

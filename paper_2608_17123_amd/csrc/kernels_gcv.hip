@@ -366,6 +366,91 @@ __device__ __forceinline__ void eval_freqs(const Job* job, const FreqRegs& f, do
   }
 }
 
+// One step of Brent's minimisation without derivatives (golden section with
+// parabolic interpolation) on the state st, given f(st[BR_U]): updates the
+// bracket and the best points, then sets st[BR_U] to the next point.
+// Returns true when the bracket meets the tolerance or maxit steps are done.
+__device__ __forceinline__ bool brent_step(double* st, double fu, double xtol, int maxit) {
+  const double u = st[BR_U];
+  const double golden = 0.5 * (3.0 - sqrt(5.0));
+  const double sqeps = sqrt(2.220446049250313e-16);
+  double a = st[BR_A], b = st[BR_B], x = st[BR_X], w = st[BR_W], v = st[BR_V];
+  double fx = st[BR_FX], fw = st[BR_FW], fv = st[BR_FV], d = st[BR_D], e = st[BR_E];
+  int it = (int)st[BR_IT];
+  if (it < 0) {
+    fx = fw = fv = fu;
+    it = 0;
+  } else {
+    if (fu <= fx) {
+      if (u >= x) a = x; else b = x;
+      v = w; fv = fw; w = x; fw = fx; x = u; fx = fu;
+    } else {
+      if (u < x) a = u; else b = u;
+      if (fu <= fw || w == x) { v = w; fv = fw; w = u; fw = fu; }
+      else if (fu <= fv || v == x || v == w) { v = u; fv = fu; }
+    }
+    it += 1;
+  }
+  bool done = it >= maxit;
+  double unext = x;
+  if (!done) {
+    const double xm = 0.5 * (a + b);
+    const double tol = sqeps * fabs(x) + xtol / 3.0;
+    const double tol2 = 2.0 * tol;
+    if (fabs(x - xm) <= tol2 - 0.5 * (b - a)) {
+      done = true;
+    } else {
+      bool use_golden = true;
+      if (fabs(e) > tol) {
+        double r = (x - w) * (fx - fv);
+        double q = (x - v) * (fx - fw);
+        double p = (x - v) * q - (x - w) * r;
+        q = 2.0 * (q - r);
+        if (q > 0.0) p = -p;
+        q = fabs(q);
+        const double e_prev = e;
+        e = d;
+        if (fabs(p) < fabs(0.5 * q * e_prev) && p > q * (a - x) && p < q * (b - x)) {
+          d = p / q;
+          const double uu = x + d;
+          if ((uu - a) < tol2 || (b - uu) < tol2) d = xm >= x ? tol : -tol;
+          use_golden = false;
+        }
+      }
+      if (use_golden) {
+        e = x >= xm ? (a - x) : (b - x);
+        d = golden * e;
+      }
+      unext = fabs(d) >= tol ? x + d : (d > 0.0 ? x + tol : x - tol);
+    }
+  }
+  st[BR_A] = a; st[BR_B] = b; st[BR_X] = x; st[BR_W] = w; st[BR_V] = v;
+  st[BR_FX] = fx; st[BR_FW] = fw; st[BR_FV] = fv; st[BR_D] = d; st[BR_E] = e;
+  st[BR_IT] = (double)it;
+  st[BR_U] = unext;
+  st[BR_DONE] = done ? 1.0 : 0.0;
+  return done;
+}
+
+// Bracket around the lowest-index grid minimum and Brent's start state.
+__device__ __forceinline__ void brent_start(double* st, double tlo, double thi, int npts, int jb) {
+  const double step = (thi - tlo) / (npts - 1);
+  const double a = tlo + step * (jb > 0 ? jb - 1 : 0);
+  const double b = tlo + step * (jb < npts - 1 ? jb + 1 : npts - 1);
+  const double golden = 0.5 * (3.0 - sqrt(5.0));
+  const double x = a + golden * (b - a);
+  for (int q = 0; q < BR_SIZE; ++q) st[q] = 0.0;
+  st[BR_A] = a;
+  st[BR_B] = b;
+  st[BR_X] = x;
+  st[BR_W] = x;
+  st[BR_V] = x;
+  st[BR_U] = x;
+  st[BR_IT] = -1.0;    // the first evaluation is the start point
+  st[BR_PHASE] = 0.0;  // nothing evaluated yet
+  st[BR_DONE] = 0.0;
+}
+
 // ---------------------------------------------------------------- grid ----
 // Job::i1 = number of grid points; pr[0] = (min, max) partials of k_gcv_data.
 // Writes 2 partials (residual sum, trace) per grid point per tile.
@@ -449,22 +534,7 @@ __global__ void __launch_bounds__(NTHREADS) k_gcv_gridfin(const Job* __restrict_
   double best = vals[0];
   for (int p = 1; p < npts; ++p)
     if (vals[p] < best) { best = vals[p]; jb = p; }
-  const double step = (thi - tlo) / (npts - 1);
-  const double a = tlo + step * (jb > 0 ? jb - 1 : 0);
-  const double b = tlo + step * (jb < npts - 1 ? jb + 1 : npts - 1);
-  const double golden = 0.5 * (3.0 - sqrt(5.0));
-  const double x = a + golden * (b - a);
-  double* st = sc + S_BR;  // copy 0: read by the first Brent launch
-  for (int q = 0; q < BR_SIZE; ++q) st[q] = 0.0;
-  st[BR_A] = a;
-  st[BR_B] = b;
-  st[BR_X] = x;
-  st[BR_W] = x;
-  st[BR_V] = x;
-  st[BR_U] = x;
-  st[BR_IT] = -1.0;    // the first evaluation is the start point
-  st[BR_PHASE] = 0.0;  // nothing evaluated yet
-  st[BR_DONE] = 0.0;
+  brent_start(sc + S_BR, tlo, thi, npts, jb);  // copy 0: read by the first Brent launch
 }
 
 // --------------------------------------------------------------- Brent ----
@@ -498,67 +568,8 @@ __global__ void __launch_bounds__(NTHREADS) k_gcv_brent(const Job* __restrict__ 
     // the previous launch evaluated GCV at U: total its partials
     const double res = sum_partials<2>(job->pr[0], nt, 0, red, &bc);
     const double tr = sum_partials<2>(job->pr[0], nt, 1, red, &bc);
-    const double u = st[BR_U];
-    const double fu = gcv_from(job, pow(10.0, u), res, tr, n);
-    const double golden = 0.5 * (3.0 - sqrt(5.0));
-    const double sqeps = sqrt(2.220446049250313e-16);
-    const double xtol = job->p0;
-    const int maxit = job->i1;
-    double a = st[BR_A], b = st[BR_B], x = st[BR_X], w = st[BR_W], v = st[BR_V];
-    double fx = st[BR_FX], fw = st[BR_FW], fv = st[BR_FV], d = st[BR_D], e = st[BR_E];
-    int it = (int)st[BR_IT];
-    if (it < 0) {
-      fx = fw = fv = fu;
-      it = 0;
-    } else {
-      if (fu <= fx) {
-        if (u >= x) a = x; else b = x;
-        v = w; fv = fw; w = x; fw = fx; x = u; fx = fu;
-      } else {
-        if (u < x) a = u; else b = u;
-        if (fu <= fw || w == x) { v = w; fv = fw; w = u; fw = fu; }
-        else if (fu <= fv || v == x || v == w) { v = u; fv = fu; }
-      }
-      it += 1;
-    }
-    done = it >= maxit;
-    double unext = x;
-    if (!done) {
-      const double xm = 0.5 * (a + b);
-      const double tol = sqeps * fabs(x) + xtol / 3.0;
-      const double tol2 = 2.0 * tol;
-      if (fabs(x - xm) <= tol2 - 0.5 * (b - a)) {
-        done = true;
-      } else {
-        bool use_golden = true;
-        if (fabs(e) > tol) {
-          double r = (x - w) * (fx - fv);
-          double q = (x - v) * (fx - fw);
-          double p = (x - v) * q - (x - w) * r;
-          q = 2.0 * (q - r);
-          if (q > 0.0) p = -p;
-          q = fabs(q);
-          const double e_prev = e;
-          e = d;
-          if (fabs(p) < fabs(0.5 * q * e_prev) && p > q * (a - x) && p < q * (b - x)) {
-            d = p / q;
-            const double uu = x + d;
-            if ((uu - a) < tol2 || (b - uu) < tol2) d = xm >= x ? tol : -tol;
-            use_golden = false;
-          }
-        }
-        if (use_golden) {
-          e = x >= xm ? (a - x) : (b - x);
-          d = golden * e;
-        }
-        unext = fabs(d) >= tol ? x + d : (d > 0.0 ? x + tol : x - tol);
-      }
-    }
-    st[BR_A] = a; st[BR_B] = b; st[BR_X] = x; st[BR_W] = w; st[BR_V] = v;
-    st[BR_FX] = fx; st[BR_FW] = fw; st[BR_FV] = fv; st[BR_D] = d; st[BR_E] = e;
-    st[BR_IT] = (double)it;
-    st[BR_U] = unext;
-    st[BR_DONE] = done ? 1.0 : 0.0;
+    const double fu = gcv_from(job, pow(10.0, st[BR_U]), res, tr, n);
+    done = brent_step(st, fu, job->p0, job->i1);
   }
   if (owner) {
     for (int q = 0; q < BR_SIZE; ++q) out[q] = st[q];
@@ -579,6 +590,75 @@ __global__ void __launch_bounds__(NTHREADS) k_gcv_brent(const Job* __restrict__ 
   eval_freqs(job, f, pow(10.0, st[BR_U]), res, tr);
   double vv[2] = {res, tr};
   put_partials<2>(job->pw, tix, vv, red);
+}
+
+// ----------------------------------------------------------- one block --
+// Levels of at most 64 x 64: every frequency of a job fits in one block's
+// registers (16 per thread), so the grid bounds, the grid, the bracket and
+// all Brent steps run in one launch, one block per job.  The steps are those
+// of k_gcv_grid / k_gcv_gridfin / k_gcv_brent; the sums over frequencies are
+// block sums instead of per-tile partials.  Job: i0 = grid points, i1 = tiles
+// of the data launch, pr[0] = its (min, max) partials, p0 = xtol, p1 = max
+// Brent steps.  Every thread holds the same Brent state (the block sums are
+// identical in all threads), so all threads leave the loop together.
+__global__ void __launch_bounds__(NTHREADS) k_gcv_solo(const Job* __restrict__ jobs,
+                                                       const uint32_t* __restrict__ tiles) {
+  __shared__ double red[2 * (NTHREADS / 64)];
+  __shared__ double vals[DBL_GCV_GRID_MAX_DEV];
+  const Job* job = jobs + (tiles[blockIdx.x] >> 16);
+  double* sc = job->scal;
+  const int m = job->m, n = m * m, npts = job->i0, nt = job->i1;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  constexpr int NW = NTHREADS / 64;
+  // grid bounds from the data partials
+  double lo = 1e300, hi = -1e300;
+  for (int t = threadIdx.x; t < nt; t += NTHREADS) {
+    lo = fmin(lo, job->pr[0][2 * t]);
+    hi = fmax(hi, job->pr[0][2 * t + 1]);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, off, 64));
+    hi = fmax(hi, __shfl_xor(hi, off, 64));
+  }
+  if (lane == 0) { red[wid] = lo; red[NW + wid] = hi; }
+  __syncthreads();
+  for (int w = 0; w < NW; ++w) { lo = fmin(lo, red[w]); hi = fmax(hi, red[NW + w]); }
+  const double thi = hi, tlo = fmax(lo, hi - 14.0);
+  FreqRegs f;
+  load_freqs(job, 0, 0, m, m, f);
+  auto gcv_at = [&](double t) {
+    double v[2];
+    eval_freqs(job, f, pow(10.0, t), v[0], v[1]);
+    block_allsum<2>(v, red);
+    return gcv_from(job, pow(10.0, t), v[0], v[1], n);
+  };
+  for (int p = 0; p < npts; ++p) {
+    const double val = gcv_at(tlo + (thi - tlo) * p / (npts - 1));
+    if (threadIdx.x == 0) {
+      vals[p] = val;
+      sc[S_GRID + p] = val;
+    }
+  }
+  __syncthreads();
+  int jb = 0;
+  double best = vals[0];
+  for (int p = 1; p < npts; ++p)
+    if (vals[p] < best) { best = vals[p]; jb = p; }
+  double st[BR_SIZE];
+  brent_start(st, tlo, thi, npts, jb);
+  const double xtol = job->p0;
+  const int maxit = (int)job->p1;
+  bool done = false;
+  while (!done) done = brent_step(st, gcv_at(st[BR_U]), xtol, maxit);
+  if (threadIdx.x == 0) {
+    const double g = pow(10.0, st[BR_X]);
+    sc[S_G_TLO] = tlo;
+    sc[S_G_THI] = thi;
+    sc[S_GAMMA] = g;
+    sc[S_SQRTG] = sqrt(g);
+    sc[S_G_FBEST] = st[BR_FX];
+  }
 }
 
 // -------------------------------------------------------------- launchers --
@@ -616,6 +696,7 @@ hipError_t launch_gcv_add_dtd(double* M, const void* w, int precision, int m,
   return hipGetLastError();
 }
 
+hipError_t launch_gcv_solo(const LaunchArgs& la) { GLAUNCH(k_gcv_solo, la); return hipGetLastError(); }
 hipError_t launch_gcv_data(const LaunchArgs& la) { GLAUNCH(k_gcv_data, la); return hipGetLastError(); }
 hipError_t launch_gcv_grid(const LaunchArgs& la, int) { GLAUNCH(k_gcv_grid, la); return hipGetLastError(); }
 hipError_t launch_gcv_brent(const LaunchArgs& la) { GLAUNCH(k_gcv_brent, la); return hipGetLastError(); }

@@ -451,6 +451,17 @@ __global__ void __launch_bounds__(NTHREADS) k_stats_fin(const Job* __restrict__ 
   h[2] = tot[2] + coef * tot[3];
 }
 
+// ------------------------------------------------------------- set gamma --
+// One block per job: scal[S_GAMMA] = p0, scal[S_SQRTG] = p1 (fixed parameters).
+__global__ void __launch_bounds__(64) k_set_gamma(const Job* __restrict__ jobs,
+                                                  const uint32_t* __restrict__ tiles) {
+  const Job* job = jobs + (tiles[blockIdx.x] >> 16);
+  if (threadIdx.x == 0) {
+    job->scal[S_GAMMA] = job->p0;
+    job->scal[S_SQRTG] = job->p1;
+  }
+}
+
 // ------------------------------------------------------------------ fill --
 // v[0] (image space, may be null) and v[1] (gradient space, may be null) <- p0.
 template <typename T>
@@ -585,6 +596,11 @@ hipError_t launch_cgls_init(const LaunchArgs& la, int precision) {
 hipError_t launch_stats_fin(const LaunchArgs& la) {
   hipLaunchKernelGGL(k_stats_fin, dim3(la.ntiles), dim3(NTHREADS), 0, la.stream, la.jobs,
                      la.tiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_gamma(const LaunchArgs& la) {
+  hipLaunchKernelGGL(k_set_gamma, dim3(la.ntiles), dim3(64), 0, la.stream, la.jobs, la.tiles);
   return hipGetLastError();
 }
 

@@ -46,6 +46,7 @@ hipError_t launch_stats(const LaunchArgs& la, int precision, int sep, int rb, in
 hipError_t launch_fill(const LaunchArgs& la, int precision);
 hipError_t launch_stats_fin(const LaunchArgs& la);
 hipError_t launch_cgls_hist(const LaunchArgs& la);
+hipError_t launch_set_gamma(const LaunchArgs& la);
 // One-block CGLS (kernels_small.hip): one block per job, all iterations, for
 // levels with a separable operator.  Every job of a launch has m x m grids,
 // m in {8, 16, 32, 64}.
@@ -69,6 +70,8 @@ hipError_t launch_gcv_data(const LaunchArgs& la);
 hipError_t launch_gcv_grid(const LaunchArgs& la, int ngroups);
 hipError_t launch_gcv_brent(const LaunchArgs& la);
 hipError_t launch_gcv_gridfin(const LaunchArgs& la);
+// levels of at most 64 x 64: grid and all Brent steps in one block per job
+hipError_t launch_gcv_solo(const LaunchArgs& la);
 // EXACT tier: n x n identity; M += D^T D (D = diag(w) L, w of `precision`, or L)
 hipError_t launch_gcv_eye(double* I, int n, hipStream_t stream);
 hipError_t launch_gcv_add_dtd(double* M, const void* w, int precision, int m,

@@ -111,6 +111,27 @@ int stage(dbl_ctx* ctx, const void* src, size_t bytes, void** dptr) {
   return DBL_OK;
 }
 
+// Two arrays staged back to back with one copy.
+int stage2(dbl_ctx* ctx, const void* a, size_t na, const void* b, size_t nb, void** da,
+           void** db) {
+  const size_t ea = (na + 255) & ~size_t(255);
+  std::vector<char> both;  // only when the pair is large; the common case fits below
+  char tmp[16384];
+  char* buf = tmp;
+  if (ea + nb > sizeof(tmp)) {
+    both.resize(ea + nb);
+    buf = both.data();
+  }
+  std::memcpy(buf, a, na);
+  std::memcpy(buf + ea, b, nb);
+  void* d = nullptr;
+  int rc = stage(ctx, buf, ea + nb, &d);
+  if (rc) return rc;
+  *da = d;
+  *db = static_cast<char*>(d) + ea;
+  return DBL_OK;
+}
+
 // Called only where no staged array is waiting for its launch: when the
 // buffer is more than half used (or old buffers are retired), wait for the
 // stream, free retired buffers and restart at offset 0.
@@ -229,9 +250,8 @@ void Launch::add(const Job& j0, int grid_m, int esz) {
 
 int Launch::upload(dbl_ctx* ctx, LaunchArgs& la) {
   void *dj = nullptr, *dt = nullptr;
-  int rc = stage(ctx, jobs.data(), jobs.size() * sizeof(Job), &dj);
-  if (rc) return rc;
-  rc = stage(ctx, tiles.data(), tiles.size() * sizeof(uint32_t), &dt);
+  int rc = stage2(ctx, jobs.data(), jobs.size() * sizeof(Job), tiles.data(),
+                  tiles.size() * sizeof(uint32_t), &dj, &dt);
   if (rc) return rc;
   la.jobs = static_cast<const Job*>(dj);
   la.tiles = static_cast<const uint32_t*>(dt);
@@ -734,16 +754,14 @@ int engine_step(dbl_ctx* ctx, std::vector<Slot*>& slots) {
   // ---- C. the parameter gamma ----------------------------------------------
   {
     std::vector<GcvReq> greqs;
+    Launch setg;  // fixed parameters: one launch writes gamma, sqrt(gamma) of every slot
     for (Slot* s : act) {
       if (!s->gcv) {
         const double g = s->mu[(size_t)s->level * s->opts.k_out + s->k];
-        const double gv[2] = {g, std::sqrt(g)};
-        void* d = nullptr;
-        if ((rc = stage(ctx, gv, sizeof(gv), &d))) return rc;
-        if ((rc = hip_check(ctx, hipMemcpyAsync(s->scal + S_GAMMA, d, sizeof(gv),
-                                                 hipMemcpyDeviceToDevice, ctx->stream),
-                            "set gamma")))
-          return rc;
+        Job j = base_job(s, s->level);
+        j.p0 = g;
+        j.p1 = std::sqrt(g);
+        setg.add(j, 1, 4);
         continue;
       }
       // GCV schedule (Sec. 3): MM / SB at k = 0, 1, 2; IRLS every k with at
@@ -775,6 +793,13 @@ int engine_step(dbl_ctx* ctx, std::vector<Slot*>& slots) {
                                                 : s->opts.gcv_mode;
       greqs.push_back(g);
       s->bh_valid = g.mode == DBL_GCV_SPECTRAL;  // the exact tier reuses the DCT buffer
+    }
+    if (!setg.empty()) {
+      LaunchArgs la;
+      if ((rc = setg.upload(ctx, la))) return rc;
+      if ((rc = hip_check(ctx, timed(ctx, "set_gamma", 0.0, [&] { return launch_set_gamma(la); }),
+                          "set gamma")))
+        return rc;
     }
     if (!greqs.empty() && (rc = gcv_run(ctx, greqs))) return rc;
   }

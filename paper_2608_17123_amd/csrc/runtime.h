@@ -78,6 +78,8 @@ int pool_get(dbl_ctx* ctx, size_t bytes, void** p);
 void pool_put(dbl_ctx* ctx, void* p, size_t bytes);
 void pool_trim(dbl_ctx* ctx, size_t keep_bytes);
 int stage(dbl_ctx* ctx, const void* src, size_t bytes, void** dptr);
+int stage2(dbl_ctx* ctx, const void* a, size_t na, const void* b, size_t nb, void** da,
+           void** db);
 int stage_checkpoint(dbl_ctx* ctx);
 
 // Per-kernel timing: when profiling is on, `launch` runs between two events on

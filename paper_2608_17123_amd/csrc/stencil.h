@@ -85,8 +85,12 @@ struct NoHook {
   __device__ __forceinline__ void operator()() const {}
 };
 
-template <typename T, int RB, int NTH = NTHREADS, int V = TileCfg<T>::V, class Epi,
-          class Hook = NoHook>
+// ROLLED: seam rows computed one output at a time straight from LDS (small
+// register footprint; right for tiles, where seam rows are rare) or, when
+// false, register-blocked like the interior (for whole small levels, where
+// a large share of the rows are seam rows).
+template <typename T, int RB, int NTH = NTHREADS, int V = TileCfg<T>::V, bool ROLLED = true,
+          class Epi, class Hook = NoHook>
 __device__ __forceinline__ void sep_tile(const T* __restrict__ Xs, int H, T* __restrict__ Zs,
                                          const Table1D& t0, const Table1D& t1, int i0, int j0,
                                          int TI, int TJ, int m, Epi epi, Hook hook = Hook()) {
@@ -117,8 +121,8 @@ __device__ __forceinline__ void sep_tile(const T* __restrict__ Xs, int H, T* __r
       }
       const int ia = i0 + r0;
       const bool inter = (ia >= t0.St) && (ia + V - 1 < m - t0.Sb);
-      T out[V];
       if (inter) {
+        T out[V];
 #pragma unroll
         for (int v = 0; v < V; ++v) {
           T a = T(0);
@@ -126,7 +130,26 @@ __device__ __forceinline__ void sep_tile(const T* __restrict__ Xs, int H, T* __r
           for (int e = 0; e < NTAP; ++e) a = fma(tp[e], win[v + e], a);
           out[v] = a;
         }
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+          if (r0 + v < TI) Zs[c * LZ + r0 + v] = out[v];
+      } else if constexpr (ROLLED) {
+        // rows near a seam: own tap row, operands straight from LDS, one
+        // output at a time
+#pragma unroll 1
+        for (int v = 0; v < V; ++v) {
+          const int i = ia + v;
+          if (r0 + v >= TI) break;
+          const int cls = (i < m) ? class_of(i, m, t0.St, t0.Sb) : t0.St;
+          const T* __restrict__ row = T0 + cls * NTAP;
+          const T* __restrict__ xcol = Xs + (r0 + v + (H - RB)) * LX + xc;
+          T a = T(0);
+#pragma unroll
+          for (int e = 0; e < NTAP; ++e) a = fma(row[e], xcol[e * LX], a);
+          Zs[c * LZ + r0 + v] = a;
+        }
       } else {
+        T out[V];
 #pragma unroll
         for (int v = 0; v < V; ++v) {
           const int i = ia + v;
@@ -137,10 +160,10 @@ __device__ __forceinline__ void sep_tile(const T* __restrict__ Xs, int H, T* __r
           for (int e = 0; e < NTAP; ++e) a = fma(row[e], win[v + e], a);
           out[v] = a;
         }
-      }
 #pragma unroll
-      for (int v = 0; v < V; ++v)
-        if (r0 + v < TI) Zs[c * LZ + r0 + v] = out[v];
+        for (int v = 0; v < V; ++v)
+          if (r0 + v < TI) Zs[c * LZ + r0 + v] = out[v];
+      }
     }
   }
   __syncthreads();
@@ -168,6 +191,19 @@ __device__ __forceinline__ void sep_tile(const T* __restrict__ Xs, int H, T* __r
 #pragma unroll
           for (int e = 0; e < NTAP; ++e) a = fma(tp[e], win[v + e], a);
           if (c0 + v < TJ) epi(r, c0 + v, a);
+        }
+      } else if constexpr (ROLLED) {
+#pragma unroll 1
+        for (int v = 0; v < V; ++v) {
+          const int j = ja + v;
+          if (c0 + v >= TJ) break;
+          const int cls = (j < m) ? class_of(j, m, t1.St, t1.Sb) : t1.St;
+          const T* __restrict__ row = T1 + cls * NTAP;
+          const T* __restrict__ zrow = Zs + (c0 + v) * LZ + r;
+          T a = T(0);
+#pragma unroll
+          for (int e = 0; e < NTAP; ++e) a = fma(row[e], zrow[e * LZ], a);
+          epi(r, c0 + v, a);
         }
       } else {
 #pragma unroll
