@@ -325,7 +325,7 @@ int gcv_run(dbl_ctx* ctx, std::vector<GcvReq>& reqs) {
   // 3. per-frequency data and grid bounds; 4. grid; 5. Brent (levels of at
   //    most 64 x 64: 4 and 5 in one block per job)
   {
-    Launch Ld, Lg, Lf, Lb[2], Ls;
+    Launch Ld, Lg, Lf, Lb[2], Ls[2];
     for (size_t q = 0; q < reqs.size(); ++q) {
       const PartLayout& PL = PLs[q];
       const bool exact = reqs[q].mode == DBL_GCV_EXACT;
@@ -342,7 +342,7 @@ int gcv_run(dbl_ctx* ctx, std::vector<GcvReq>& reqs) {
         o.pr[0] = PL.gmm;
         o.p0 = BRENT_XTOL;
         o.p1 = BRENT_MAXIT;
-        Ls.add(o, 1, 4);
+        Ls[0].add(o, 1, 4);
         continue;
       }
       Job g = base[q];
@@ -367,7 +367,8 @@ int gcv_run(dbl_ctx* ctx, std::vector<GcvReq>& reqs) {
       }
     }
     if ((rc = run(launch_gcv_data, Ld, "gcv_data"))) return rc;
-    if ((rc = run(launch_gcv_solo, Ls, "gcv_solo"))) return rc;
+    for (int c = 0; c < 2; ++c)
+      if ((rc = run(launch_gcv_solo, Ls[c], "gcv_solo"))) return rc;
     if (Lg.empty()) return DBL_OK;
     LaunchArgs lg;
     if ((rc = Lg.upload(ctx, lg))) return rc;

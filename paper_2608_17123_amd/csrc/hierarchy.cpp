@@ -204,7 +204,7 @@ static bool separable(const double* P, int ph, int pw, std::vector<double>& u,
   return true;
 }
 
-static void pad_table(Table1DHost& t, int R) {
+void pad_table(Table1DHost& t, int R) {
   if (t.R == R) return;
   const int NT0 = 2 * t.R + 1, NT = 2 * R + 1;
   std::vector<double> nt((size_t)t.rows * NT, 0.0);

@@ -17,6 +17,18 @@ struct Table1DHost {
   std::vector<double> taps;  // rows * (2R+1)
 };
 
+// Zero-pad a 1-D class table to radius R >= t.R (2R + 1 taps per row).
+void pad_table(Table1DHost& t, int R);
+
+// Radius buckets of the separable kernels (tables padded to one of these).
+constexpr int NBUCKETS = 5;
+constexpr int RB_BUCKETS[NBUCKETS] = {2, 4, 8, 12, 16};
+inline int bucket_index(int rb) {
+  for (int k = 0; k < NBUCKETS; ++k)
+    if (RB_BUCKETS[k] == rb) return k;
+  return -1;
+}
+
 struct Table2DHost {
   int R0 = 0, R1 = 0, St0 = 0, Sb0 = 0, St1 = 0, Sb1 = 0, rows0 = 1, rows1 = 1;
   std::vector<int> off;

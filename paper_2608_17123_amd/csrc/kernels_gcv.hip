@@ -308,6 +308,7 @@ struct FreqRegs {
   int cnt;
 };
 
+template <int NT = NTHREADS>
 __device__ __forceinline__ void load_freqs(const Job* job, int i0, int j0, int TI, int TJ,
                                            FreqRegs& f) {
   const int m = job->m;
@@ -318,7 +319,7 @@ __device__ __forceinline__ void load_freqs(const Job* job, int i0, int j0, int T
   const bool exact = job->flags & F_EXACT;
   const double* __restrict__ fv = static_cast<const double*>(job->v[G_BH]);
   f.cnt = 0;
-  for (int o = threadIdx.x; o < TI * TJ; o += NTHREADS) {
+  for (int o = threadIdx.x; o < TI * TJ; o += NT) {
     const int k0 = i0 + o % TI, k1 = j0 + o / TI;
     const size_t g = k0 + (size_t)k1 * m;
     if (exact) {  // (nu, f, g) in the (s, lp, e) registers
@@ -346,9 +347,10 @@ __device__ __forceinline__ void eval_freqs(const Job* job, const FreqRegs& f, do
         const double nu = f.s[q];
         const double den = nu + gam * (1.0 - nu);
         if (den > 0.0) {
-          const double y = (f.lp[q] + gam * f.e[q]) / den;
+          const double inv = 1.0 / den;
+          const double y = (f.lp[q] + gam * f.e[q]) * inv;
           res += nu * y * y - 2.0 * f.lp[q] * y;
-          tr += nu / den;
+          tr += nu * inv;
         }
       }
     }
@@ -359,8 +361,9 @@ __device__ __forceinline__ void eval_freqs(const Job* job, const FreqRegs& f, do
     if (q < f.cnt) {
       const double den = f.s[q] + gam * f.lp[q];
       if (den > 0.0) {
-        res += f.e[q] / (den * den);
-        tr += f.s[q] / den;
+        const double inv = 1.0 / den;
+        res += f.e[q] * inv * inv;
+        tr += f.s[q] * inv;
       }
     }
   }
@@ -595,24 +598,26 @@ __global__ void __launch_bounds__(NTHREADS) k_gcv_brent(const Job* __restrict__ 
 // ----------------------------------------------------------- one block --
 // Levels of at most 64 x 64: every frequency of a job fits in one block's
 // registers (16 per thread), so the grid bounds, the grid, the bracket and
-// all Brent steps run in one launch, one block per job.  The steps are those
+// all Brent steps run in one launch, one block per job.  (At 128 x 128 a
+// 1024-thread block is slower than the multi-launch path: measured.)  The steps are those
 // of k_gcv_grid / k_gcv_gridfin / k_gcv_brent; the sums over frequencies are
 // block sums instead of per-tile partials.  Job: i0 = grid points, i1 = tiles
 // of the data launch, pr[0] = its (min, max) partials, p0 = xtol, p1 = max
 // Brent steps.  Every thread holds the same Brent state (the block sums are
 // identical in all threads), so all threads leave the loop together.
-__global__ void __launch_bounds__(NTHREADS) k_gcv_solo(const Job* __restrict__ jobs,
-                                                       const uint32_t* __restrict__ tiles) {
-  __shared__ double red[2 * (NTHREADS / 64)];
+template <int NT>
+__global__ void __launch_bounds__(NT) k_gcv_solo(const Job* __restrict__ jobs,
+                                                 const uint32_t* __restrict__ tiles) {
+  __shared__ double red[2 * (NT / 64)];
   __shared__ double vals[DBL_GCV_GRID_MAX_DEV];
   const Job* job = jobs + (tiles[blockIdx.x] >> 16);
   double* sc = job->scal;
   const int m = job->m, n = m * m, npts = job->i0, nt = job->i1;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  constexpr int NW = NTHREADS / 64;
+  constexpr int NW = NT / 64;
   // grid bounds from the data partials
   double lo = 1e300, hi = -1e300;
-  for (int t = threadIdx.x; t < nt; t += NTHREADS) {
+  for (int t = threadIdx.x; t < nt; t += NT) {
     lo = fmin(lo, job->pr[0][2 * t]);
     hi = fmax(hi, job->pr[0][2 * t + 1]);
   }
@@ -626,11 +631,11 @@ __global__ void __launch_bounds__(NTHREADS) k_gcv_solo(const Job* __restrict__ j
   for (int w = 0; w < NW; ++w) { lo = fmin(lo, red[w]); hi = fmax(hi, red[NW + w]); }
   const double thi = hi, tlo = fmax(lo, hi - 14.0);
   FreqRegs f;
-  load_freqs(job, 0, 0, m, m, f);
+  load_freqs<NT>(job, 0, 0, m, m, f);
   auto gcv_at = [&](double t) {
     double v[2];
     eval_freqs(job, f, pow(10.0, t), v[0], v[1]);
-    block_allsum<2>(v, red);
+    block_allsum<2, NT>(v, red);
     return gcv_from(job, pow(10.0, t), v[0], v[1], n);
   };
   for (int p = 0; p < npts; ++p) {
@@ -696,7 +701,12 @@ hipError_t launch_gcv_add_dtd(double* M, const void* w, int precision, int m,
   return hipGetLastError();
 }
 
-hipError_t launch_gcv_solo(const LaunchArgs& la) { GLAUNCH(k_gcv_solo, la); return hipGetLastError(); }
+hipError_t launch_gcv_solo(const LaunchArgs& la) {
+  if (la.m_max > 64) return hipErrorInvalidValue;  // 16 frequencies per thread
+  hipLaunchKernelGGL(k_gcv_solo<NTHREADS>, dim3(la.ntiles), dim3(NTHREADS), 0, la.stream,
+                     la.jobs, la.tiles);
+  return hipGetLastError();
+}
 hipError_t launch_gcv_data(const LaunchArgs& la) { GLAUNCH(k_gcv_data, la); return hipGetLastError(); }
 hipError_t launch_gcv_grid(const LaunchArgs& la, int) { GLAUNCH(k_gcv_grid, la); return hipGetLastError(); }
 hipError_t launch_gcv_brent(const LaunchArgs& la) { GLAUNCH(k_gcv_brent, la); return hipGetLastError(); }

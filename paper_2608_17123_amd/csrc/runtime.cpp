@@ -315,6 +315,7 @@ void op_free(dbl_op* op) {
   for (void* p : op->bufs) dfree(op->ctx, p);
   for (double* p : op->sym) dfree(op->ctx, p);
   if (op->d_ops) dfree(op->ctx, op->d_ops);
+  if (op->d_pad) dfree(op->ctx, op->d_pad);
   delete op;
 }
 
@@ -359,6 +360,36 @@ int op_build(dbl_ctx* ctx, const double* psf, int ph, int pw, int m, int levels,
     rc = hip_check(ctx, hipMemcpy(op->d_ops, lv.data(), sizeof(LevelOp) * levels,
                                   hipMemcpyHostToDevice),
                    "upload level ops");
+  // padded variants for the larger radius buckets of separable levels
+  std::vector<LevelOp> pad((size_t)levels * NBUCKETS);
+  std::memset(pad.data(), 0, pad.size() * sizeof(LevelOp));
+  for (int i = 0; i < levels && !rc; ++i) {
+    const LevelHost& L = op->host.levels[i];
+    if (!L.sep) continue;
+    for (int k = 0; k < NBUCKETS && !rc; ++k) {
+      const int b = RB_BUCKETS[k];
+      if (b < L.rb) continue;
+      LevelOp& d = pad[(size_t)i * NBUCKETS + k];
+      if (b == L.rb) {
+        d = lv[i];
+        continue;
+      }
+      d = lv[i];
+      d.rb = b;
+      d.R = b;
+      Table1DHost t[4] = {L.f0, L.f1, L.a0, L.a1};
+      Table1D* dt[4] = {&d.f0, &d.f1, &d.a0, &d.a1};
+      for (int q = 0; q < 4 && !rc; ++q) {
+        pad_table(t[q], b);
+        rc = upload_t1(ctx, op, t[q], *dt[q]);
+      }
+    }
+  }
+  if (!rc) rc = dmalloc(ctx, sizeof(LevelOp) * pad.size(), (void**)&op->d_pad);
+  if (!rc)
+    rc = hip_check(ctx, hipMemcpy(op->d_pad, pad.data(), sizeof(LevelOp) * pad.size(),
+                                  hipMemcpyHostToDevice),
+                   "upload padded level ops");
   op->sym.assign(levels, nullptr);
   if (rc) {
     op_free(op);
@@ -550,6 +581,12 @@ int slot_report(dbl_ctx* ctx, Slot* s, dbl_report* rep) {
   return DBL_OK;
 }
 
+const LevelOp* op_dev(const dbl_op* op, int level, int rb) {
+  const LevelHost& L = op->host.levels[level];
+  if (!L.sep || rb == L.rb) return op->d_ops + level;
+  return op->d_pad + (size_t)level * NBUCKETS + bucket_index(rb);
+}
+
 size_t small_lds_bytes(const dbl_ctx* ctx, const dbl_op* op, int level, bool irls, int* wlds) {
   *wlds = 0;
   if (!ctx->small_cgls) return 0;
@@ -594,6 +631,86 @@ int solver_flags(const Slot* s) {
   if (s->solver == DBL_IRLS) return F_IRLS;
   if (s->solver == DBL_MM) return F_SHIFT | F_MM;
   return F_SHIFT | F_SB;
+}
+
+// Launch groups of the CGLS stage.  Jobs share a launch when they have the
+// same precision and kind of operator and their tables are padded to the
+// same radius bucket.  A group that cannot fill the chip on its own (fewer
+// than MERGE_TILES tiles, or one-block jobs of one level size) is latency
+// bound, so it joins the next larger bucket: its jobs run with their tables
+// zero-padded to that bucket (the same operator, a few more multiply-adds).
+struct GroupPlan {
+  struct Entry {
+    GroupKey key;       // the launch group (rb = the bucket the tables are padded to)
+    size_t small_lds;   // > 0: one-block CGLS with this much LDS
+    int wlds;           // one-block CGLS stages the IRLS weights in LDS
+  };
+  std::map<const Slot*, Entry> e;
+  const Entry& at(const Slot* s) const { return e.at(s); }
+};
+
+constexpr int MERGE_TILES = 256;
+
+GroupPlan plan_groups(dbl_ctx* ctx, const std::vector<Slot*>& slots) {
+  GroupPlan P;
+  // one-block candidates by (precision, m): one bucket for all when every
+  // member still fits in LDS with it
+  std::map<std::pair<int, int>, std::vector<const Slot*>> small;
+  std::map<GroupKey, std::vector<const Slot*>> tiled;
+  for (const Slot* s : slots) {
+    const int lv = s->level;
+    const LevelHost& L = s->op->host.levels[lv];
+    GroupPlan::Entry en{key_of(s, lv), 0, 0};
+    en.small_lds = small_lds_bytes(ctx, s->op, lv, s->solver == DBL_IRLS, &en.wlds);
+    P.e[s] = en;
+    if (en.small_lds) small[{s->prec, L.m}].push_back(s);
+    else tiled[en.key].push_back(s);
+  }
+  for (auto& kv : small) {
+    int rbt = 0;
+    for (const Slot* s : kv.second) rbt = std::max(rbt, s->op->host.levels[s->level].rb);
+    std::vector<std::pair<size_t, int>> got;
+    bool ok = true;
+    for (const Slot* s : kv.second) {
+      const LevelHost& L = s->op->host.levels[s->level];
+      int wl = 0;
+      const size_t b =
+          small_cgls_lds(L.m, s->prec, rbt, L.f0.rows + L.f1.rows + L.a0.rows + L.a1.rows,
+                         s->solver == DBL_IRLS, ctx->lds_limit, &wl);
+      if (!b) ok = false;
+      got.push_back({b, wl});
+    }
+    if (!ok) continue;
+    for (size_t q = 0; q < kv.second.size(); ++q) {
+      GroupPlan::Entry& en = P.e[kv.second[q]];
+      en.key.rb = en.key.H = rbt;
+      en.small_lds = got[q].first;
+      en.wlds = got[q].second;
+    }
+  }
+  // tiled groups: separable groups below MERGE_TILES tiles join the next
+  // larger bucket of the same precision (cascading upward)
+  std::map<GroupKey, size_t> tiles;
+  for (auto& kv : tiled)
+    for (const Slot* s : kv.second) {
+      const int t = tiles_per_axis(s->m >> s->level, (int)s->esz);
+      tiles[kv.first] += (size_t)t * t;
+    }
+  std::vector<GroupKey> keys;
+  for (auto& kv : tiles) keys.push_back(kv.first);  // ordered by (prec, sep, rb)
+  std::map<GroupKey, GroupKey> target;
+  for (size_t q = 0; q < keys.size(); ++q) target[keys[q]] = keys[q];
+  for (size_t q = 0; q + 1 < keys.size(); ++q) {
+    const GroupKey& a = keys[q];
+    const GroupKey& b = keys[q + 1];
+    if (!a.sep || a.prec != b.prec || a.sep != b.sep || tiles[a] >= (size_t)MERGE_TILES) continue;
+    tiles[b] += tiles[a];
+    for (auto& t : target)
+      if (!(t.second < a) && !(a < t.second)) t.second = b;
+  }
+  for (auto& kv : tiled)
+    for (const Slot* s : kv.second) P.e[s].key = target[kv.first];
+  return P;
 }
 
 // Launch helpers: one launch per precision for simple kernels.
@@ -815,11 +932,14 @@ int engine_step(dbl_ctx* ctx, std::vector<Slot*>& slots) {
     std::map<GroupKey, std::vector<int>> kin;
     std::map<std::pair<GroupKey, int>, Launch> smallL;  // by (group, m)
     std::map<std::pair<GroupKey, int>, size_t> smallB;
+    const GroupPlan plan = plan_groups(ctx, ord);
     for (Slot* s : ord) {
       const int lv = s->level;
       const int nw = 1 - s->cur;
       const PartLayout PL = part_layout(s->part, s->m >> lv);
+      const GroupPlan::Entry& pe = plan.at(s);
       Job j = base_job(s, lv);
+      j.op = op_dev(s->op, lv, pe.key.rb ? pe.key.rb : s->op->host.levels[lv].rb);
       j.flags = solver_flags(s);
       j.v[V_X] = s->X[nw];
       j.v[V_S] = s->S;
@@ -829,15 +949,14 @@ int engine_step(dbl_ctx* ctx, std::vector<Slot*>& slots) {
       j.v[V_B] = const_cast<void*>(s->B[lv]);
       j.v[V_C1] = s->C1;
       j.v[V_C2] = s->C2;
-      const GroupKey gk = key_of(s, lv);
-      int wl = 0;
-      if (const size_t lb = small_lds_bytes(ctx, s->op, lv, s->solver == DBL_IRLS, &wl)) {
+      const GroupKey gk = pe.key;
+      if (pe.small_lds) {
         Job js = j;
         js.i0 = s->opts.k_in;
-        if (wl) js.flags |= F_WLDS;
+        if (pe.wlds) js.flags |= F_WLDS;
         const auto sk = std::make_pair(gk, js.m);
         smallL[sk].add(js, 1, 4);
-        smallB[sk] = std::max(smallB[sk], lb);
+        smallB[sk] = std::max(smallB[sk], pe.small_lds);
         continue;
       }
       Job ji = j;

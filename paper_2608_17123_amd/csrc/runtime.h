@@ -62,6 +62,10 @@ struct dbl_op {
   bool sep = true;
   dbl::HierHost host;
   dbl::LevelOp* d_ops = nullptr;     // device array [levels]
+  // separable levels: the same operators with tables padded to every radius
+  // bucket >= the level's own ([levels * NBUCKETS]; smaller buckets unset),
+  // so jobs of different radii can share one launch
+  dbl::LevelOp* d_pad = nullptr;
   std::vector<void*> bufs;           // device table storage
   std::vector<double*> sym;          // per level GCV symbol a_k (FP64, n_i), lazily built
 };
@@ -106,6 +110,10 @@ hipError_t timed(dbl_ctx* ctx, const char* name, double bytes, F&& launch) {
   ctx->prof_pending.push_back(p);
   return e;
 }
+
+// Device operator of `level` with tables padded to radius bucket rb (the
+// level's own bucket, or a larger one for a separable level).
+const LevelOp* op_dev(const dbl_op* op, int level, int rb);
 
 // Dynamic LDS of the one-block CGLS at `level` when this context runs that
 // level with it, else 0; *wlds = 1 when IRLS weights are staged in LDS.
