@@ -6,8 +6,12 @@ Each outer iteration k forms the generic subproblem of eq. (generic_sub)
   SB:   gamma = lambda, D = L,         c = d - g; then d = shrink(L x + g, tau),
                                                    g = g + L x - d
 and solves it by a fixed number of CGLS steps from x0 = 0 (project reading:
-the paper's LSQR start and stopping are not stated).  The outer count is
-fixed; the relative change RC of eq. (stop) is computed and reported.
+the paper's LSQR start and stopping are not stated).  The relative change
+RC(x^(k+1)) = ||x^(k+1) - x^(k)|| / ||x^(k)|| of eq. (stop) is computed and
+reported after every outer iteration; with a tolerance the level stops after
+the first iteration whose RC is below it, else after k_out iterations (the
+loop bound K_max of Algs. 1-3).  RC is undefined when x^(k) = 0 (the first
+iteration from a zero start); such an iteration never stops the level.
 
 Start state (Sec. 4.1): Approach I uses identity weights (IRLS) or zero
 auxiliaries (MM, SB); Approach X rebuilds the auxiliaries from the
@@ -133,10 +137,11 @@ def gcv_gamma(op, B, solver, weights, shift, mode):
 
 
 def solve_level(op, B, solver, state, k_out, k_in, mu=None, n_grids=1,
-                gcv_mode="auto", eps=EPS, tau=TAU, inner=None):
-    """Run k_out outer iterations at one level from ``state``.
+                gcv_mode="auto", eps=EPS, tau=TAU, inner=None, tol=0.0):
+    """Run at most k_out outer iterations at one level from ``state``.
 
     mu: None (GCV per the schedule) or a sequence of k_out fixed values.
+    tol: stop after the first iteration with RC < tol (0: run all k_out).
     inner: optional replacement subproblem solver ``inner(sub) -> X`` (tests
     use a dense direct solve to check properties of exact minimisation).
     Returns (state, history) with history lists 'gamma', 'rc', 'objective'."""
@@ -178,4 +183,6 @@ def solve_level(op, B, solver, state, k_out, k_in, mu=None, n_grids=1,
         hist["gamma"].append(gamma)
         hist["rc"].append(rc)
         hist["objective"].append(objective(solver, r2, Lx, gamma, eps, tau))
+        if rc < tol:  # eq. (stop); False for an undefined (NaN) RC
+            break
     return st, hist

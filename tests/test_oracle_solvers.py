@@ -142,3 +142,48 @@ def test_multilevel_improves_on_data(solver, transfer):
                             mu=[[1e-3] * 4] * 3)
     assert np.linalg.norm(Xr - X) < np.linalg.norm(B - X)
     assert len(rep["levels"]) == 3 and rep["sizes"] == [32, 16, 8]
+
+
+@pytest.mark.parametrize("solver", ["irls", "mm", "sb"])
+def test_rc_stopping_rule(solver):
+    """eq. (stop): the level stops after the first outer iteration whose
+    relative change ||x^(k+1) - x^(k)|| / ||x^(k)|| is below tol.  The RC
+    values are recomputed here from the iterates of fixed-count runs (each a
+    prefix of the longer ones), and the stopping index is found by hand."""
+    X, P, B = small_problem(m=16, seed=3)
+    H = Hierarchy(P, 16, 1, "haar")
+    op = S.LevelOperator(H, 0)
+    K = 8
+    st0 = S.init_state(solver, "I", 16)
+    xs = [st0["x"]] + [S.solve_level(op, B, solver, st0, k, 10, mu=[0.01] * k)[0]["x"]
+                       for k in range(1, K + 1)]
+    rc = [np.linalg.norm(xs[k] - xs[k - 1]) / np.linalg.norm(xs[k - 1])
+          for k in range(2, K + 1)]                      # RC after iterations 2..K
+    assert np.linalg.norm(xs[0]) == 0.0                  # RC after iteration 1 undefined
+    for tol in (rc[2] * (1 + 1e-9), rc[4] * (1 + 1e-9), 10.0, 0.0, 1e-30):
+        below = [k + 2 for k, v in enumerate(rc) if v < tol]
+        expect = below[0] if below else K
+        st, hist = S.solve_level(op, B, solver, st0, K, 10, mu=[0.01] * K, tol=tol)
+        assert len(hist["rc"]) == expect, (tol, expect)
+        assert np.array_equal(st["x"], xs[expect])
+        assert np.isnan(hist["rc"][0])
+        np.testing.assert_allclose(hist["rc"][1:], rc[:expect - 1], rtol=1e-12)
+
+
+def test_vcycle_tolerances_per_grid():
+    """tol_coarse applies to the coarser grids and tol_fine to the finest."""
+    X, P, B = small_problem(m=32, seed=6, sigma=1.5, r=4, noise=0.01)
+    mu = [[1e-3] * 6] * 3
+    Xf, full = vcycle.deblur(B, P, "mm", "haar", 3, "X", k_out=6, k_in=10, mu=mu)
+    assert [len(h["rc"]) for h in full["levels"]] == [6, 6, 6]
+    # a coarse tolerance above every coarse RC stops each coarse grid at its
+    # first defined RC: iteration 2 on the coarsest (zero start), 1 above it
+    Xt, rep = vcycle.deblur(B, P, "mm", "haar", 3, "X", k_out=6, k_in=10, mu=mu,
+                            tol_coarse=1e3)
+    assert [len(h["rc"]) for h in rep["levels"]] == [6, 1, 2]
+    # the coarsest grid runs the same first two iterations as without a tolerance
+    assert rep["levels"][2]["objective"] == full["levels"][2]["objective"][:2]
+    Xs, rep = vcycle.deblur(B, P, "mm", "haar", 3, "X", k_out=6, k_in=10, mu=mu,
+                            tol_fine=1e3)
+    assert [len(h["rc"]) for h in rep["levels"]] == [1, 6, 6]
+    assert rep["levels"][1]["objective"] == full["levels"][1]["objective"]
