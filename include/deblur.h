@@ -105,6 +105,19 @@ typedef struct dbl_opts {
   int gcv_mode;          /* dbl_gcv_mode                                      */
   int gcv_grid;          /* grid points, 3..DBL_GCV_GRID_MAX                  */
   int precision;         /* dbl_precision for vectors on the device           */
+  void* x_hist;          /* optional device array of k_out * m * m elements of
+                            x's type, owned by the caller and kept valid until
+                            the solve completes: slice k receives the finest
+                            level's iterate after outer iteration k, so that
+                            convergence curves (RRE per iteration, Sec. 5) can
+                            be drawn from one solve.  NULL: no history.
+                            Slices past an early stop are left untouched.    */
+  double tol_fine;       /* RC tolerance of eq. (stop) on the finest grid (and
+                            the single grid of Approach I): the grid stops
+                            after the first outer iteration with
+                            ||x_k+1 - x_k|| / ||x_k|| < tol, else after k_out.
+                            Sec. 5 uses 1e-3.  0: always run k_out.         */
+  double tol_coarse;     /* the same on every coarser grid; Sec. 5: 1e-6     */
 } dbl_opts;
 
 /* Per-solve report.  Level 0 is the finest grid.  Arrays are filled for
@@ -119,6 +132,9 @@ typedef struct dbl_report {
   double objective[DBL_MAX_LEVELS][DBL_MAX_KOUT]; /* solver objective, FP64        */
   double seconds;        /* device time of the solve (plain path), or latency */
   int status;            /* dbl_status of this solve                          */
+  int iters[DBL_MAX_LEVELS]; /* outer iterations run per level (k_out unless a
+                                tolerance stopped the level earlier); entries
+                                past iters[l] are NaN                        */
 } dbl_report;
 
 /* A deblurring request for the batched and serving entry points.  b and x
@@ -227,9 +243,20 @@ int dbl_dtransfer(dbl_ctx* ctx, int wavelet, int m_coarse, int precision,
 /* Run exactly `iters` CGLS iterations on min ||A^ x - b^|| with
  * A^ = [A^(level); sqrt(gamma) D] and b^ = [b; sqrt(gamma) c] (eq.
  * (augmented)), from x0 (NULL = 0).  resid_hist (host, may be NULL) receives
- * ||b^ - A^ x_k||^2 after each iteration, in FP64.  CGLS replaces the
- * paper's LSQR: both produce the same iterates in exact arithmetic. */
+ * ||b^ - A^ x_k||^2 after each iteration, in FP64.  CGLS is the default
+ * inner solver: it produces the same iterates as the paper's LSQR in exact
+ * arithmetic, with fewer vectors per iteration.  iters in [0, 128]. */
 int dbl_cgls(dbl_ctx* ctx, const dbl_op* op, int level, const dbl_sub* sub, const void* b,
+             const void* x0, int iters, void* x, double* resid_hist);
+
+/* The same subproblem and arguments solved by LSQR (Golub-Kahan
+ * bidiagonalisation with Givens rotations; the inner solver of Sec. 3), for
+ * exactly `iters` iterations from x0 (correction form: LSQR runs on the
+ * residual b^ - A^ x0).  resid_hist receives LSQR's residual estimate
+ * phibar_{k+1}^2 = ||b^ - A^ x_k||^2 (exact in exact arithmetic), FP64.
+ * Always runs the tiled phase kernels (no one-block variant).  Errors as
+ * dbl_cgls. */
+int dbl_lsqr(dbl_ctx* ctx, const dbl_op* op, int level, const dbl_sub* sub, const void* b,
              const void* x0, int iters, void* x, double* resid_hist);
 
 /* GCV choice of gamma for the subproblem {A^(level), D, c} and data b

@@ -37,7 +37,7 @@ GCV_MODES = {"auto": DBL_GCV_AUTO, "exact": DBL_GCV_EXACT, "spectral": DBL_GCV_S
 EXPORTS = [
     "dbl_create", "dbl_destroy", "dbl_set_option", "dbl_last_error", "dbl_sync", "dbl_workspace_bytes",
     "dbl_opts_default", "dbl_profile", "dbl_profile_read", "dbl_op_create", "dbl_op_destroy", "dbl_apply_A", "dbl_apply_L",
-    "dbl_dwt", "dbl_dtransfer", "dbl_cgls", "dbl_gcv", "dbl_deblur", "dbl_deblur_batch",
+    "dbl_dwt", "dbl_dtransfer", "dbl_cgls", "dbl_lsqr", "dbl_gcv", "dbl_deblur", "dbl_deblur_batch",
     "dbl_request_bytes", "dbl_server_create", "dbl_server_destroy", "dbl_server_submit",
     "dbl_server_step", "dbl_server_poll",
 ]
@@ -47,7 +47,9 @@ class dbl_opts(ctypes.Structure):
     _fields_ = [("eps", ctypes.c_double), ("tau", ctypes.c_double), ("k_out", ctypes.c_int),
                 ("k_in", ctypes.c_int), ("mu_fixed", ctypes.c_double),
                 ("mu_schedule", ctypes.POINTER(ctypes.c_double)), ("gcv_mode", ctypes.c_int),
-                ("gcv_grid", ctypes.c_int), ("precision", ctypes.c_int)]
+                ("gcv_grid", ctypes.c_int), ("precision", ctypes.c_int),
+                ("x_hist", ctypes.c_void_p), ("tol_fine", ctypes.c_double),
+                ("tol_coarse", ctypes.c_double)]
 
 
 class dbl_report(ctypes.Structure):
@@ -56,7 +58,8 @@ class dbl_report(ctypes.Structure):
                 ("gamma", (ctypes.c_double * DBL_MAX_KOUT) * DBL_MAX_LEVELS),
                 ("rc", (ctypes.c_double * DBL_MAX_KOUT) * DBL_MAX_LEVELS),
                 ("objective", (ctypes.c_double * DBL_MAX_KOUT) * DBL_MAX_LEVELS),
-                ("seconds", ctypes.c_double), ("status", ctypes.c_int)]
+                ("seconds", ctypes.c_double), ("status", ctypes.c_int),
+                ("iters", ctypes.c_int * DBL_MAX_LEVELS)]
 
     def to_dict(self):
         L, K = self.levels, self.k_out
@@ -66,6 +69,7 @@ class dbl_report(ctypes.Structure):
             "rc": [[self.rc[i][k] for k in range(K)] for i in range(L)],
             "objective": [[self.objective[i][k] for k in range(K)] for i in range(L)],
             "seconds": self.seconds, "status": self.status,
+            "iters": [self.iters[i] for i in range(L)],
         }
 
 
@@ -93,6 +97,12 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                            "`python -m paper_2608_17123_amd.build`")
+    # torch ships its own HIP runtime; loading it first lets the library bind
+    # to that same runtime instead of bringing a second one into the process
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(LIB_PATH)
     vp, i, d, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
     dp = ctypes.POINTER(ctypes.c_double)
@@ -114,6 +124,7 @@ def lib():
         "dbl_dwt": (i, [vp, i, i, i, i, i, vp, vp]),
         "dbl_dtransfer": (i, [vp, i, i, i, vp, vp]),
         "dbl_cgls": (i, [vp, vp, i, ctypes.POINTER(dbl_sub), vp, vp, i, vp, dp]),
+        "dbl_lsqr": (i, [vp, vp, i, ctypes.POINTER(dbl_sub), vp, vp, i, vp, dp]),
         "dbl_gcv": (i, [vp, vp, i, ctypes.POINTER(dbl_sub), vp, i, i, dp, dp]),
         "dbl_deblur": (i, [vp, vp, dp, i, i, i, i, i, i, i, ctypes.POINTER(dbl_opts), vp,
                            ctypes.POINTER(dbl_report)]),
@@ -238,6 +249,10 @@ def dbl_opts_default(**kw):
     o = dbl_opts()
     lib().dbl_opts_default(ctypes.byref(o))
     sched = kw.pop("mu_schedule", None)
+    hist = kw.pop("x_hist", None)
+    if hist is not None:
+        o._hist = hist  # keep the history tensor alive with the options
+        o.x_hist = _ptr(hist)
     for k, v in kw.items():
         if k == "gcv_mode" and isinstance(v, str):
             v = GCV_MODES[v]
@@ -310,16 +325,24 @@ def _sub(d_kind, w, gamma, c):
     return s
 
 
-def dbl_cgls(ctx, op, level, b, iters, x, gamma, w=None, c=None, x0=None, d_kind=None):
-    """Run `iters` CGLS steps; returns the FP64 residual history."""
+def _krylov(entry, ctx, op, level, b, iters, x, gamma, w, c, x0, d_kind):
     if d_kind is None:
         d_kind = 1 if w is not None else 0
     s = _sub(d_kind, w, gamma, c)
     hist = np.zeros(max(iters, 1), dtype=np.float64)
-    _check(ctx, lib().dbl_cgls(ctx.handle, op.handle, level, ctypes.byref(s), _ptr(b), _ptr(x0),
-                               iters, _ptr(x),
-                               hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    _check(ctx, entry(ctx.handle, op.handle, level, ctypes.byref(s), _ptr(b), _ptr(x0), iters,
+                      _ptr(x), hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
     return hist[:iters]
+
+
+def dbl_cgls(ctx, op, level, b, iters, x, gamma, w=None, c=None, x0=None, d_kind=None):
+    """Run `iters` CGLS steps; returns the FP64 residual history."""
+    return _krylov(lib().dbl_cgls, ctx, op, level, b, iters, x, gamma, w, c, x0, d_kind)
+
+
+def dbl_lsqr(ctx, op, level, b, iters, x, gamma, w=None, c=None, x0=None, d_kind=None):
+    """Run `iters` LSQR steps; returns LSQR's FP64 residual estimates."""
+    return _krylov(lib().dbl_lsqr, ctx, op, level, b, iters, x, gamma, w, c, x0, d_kind)
 
 
 def dbl_gcv(ctx, op, level, b, w=None, c=None, mode=DBL_GCV_SPECTRAL, grid=50):

@@ -50,6 +50,9 @@ int check_opts(dbl_ctx* ctx, const dbl_opts& o) {
   if (o.k_in < 1 || o.k_in > 100000) return set_err(ctx, DBL_EINVAL, "k_in out of range");
   if (o.gcv_mode < 0 || o.gcv_mode > 2) return set_err(ctx, DBL_EINVAL, "bad gcv_mode");
   if (o.gcv_grid < 3 || o.gcv_grid > DBL_GCV_GRID_MAX) return set_err(ctx, DBL_EINVAL, "bad gcv_grid");
+  if (!(o.tol_fine >= 0.0) || !(o.tol_coarse >= 0.0) || !std::isfinite(o.tol_fine) ||
+      !std::isfinite(o.tol_coarse))
+    return set_err(ctx, DBL_EINVAL, "tolerances must be finite and >= 0");
   return check_prec(ctx, o.precision);
 }
 
@@ -88,6 +91,9 @@ void dbl_opts_default(dbl_opts* o) {
   o->gcv_mode = DBL_GCV_AUTO;
   o->gcv_grid = 50;
   o->precision = DBL_F32;
+  o->x_hist = nullptr;
+  o->tol_fine = 0.0;
+  o->tol_coarse = 0.0;
 }
 
 int dbl_create(dbl_ctx** out, int device, void* hip_stream, size_t budget) {
@@ -161,6 +167,7 @@ int dbl_destroy(dbl_ctx* ctx) {
   ctx->allocs.clear();
   if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
   for (auto& b : ctx->retired) (void)hipHostFree(b.first);
+  if (ctx->h_rc) (void)hipHostFree(ctx->h_rc);
   for (hipEvent_t e : ctx->prof_pool) (void)hipEventDestroy(e);
   if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
   if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
@@ -337,8 +344,68 @@ int dbl_dtransfer(dbl_ctx* ctx, int wavelet, int m_coarse, int precision, const 
   return hip_check(ctx, launch_dtransfer(la, precision), "dtransfer");
 }
 
-int dbl_cgls(dbl_ctx* ctx, const dbl_op* op, int level, const dbl_sub* sub, const void* b,
-             const void* x0, int iters, void* x, double* resid_hist) {
+}  // extern "C"
+
+namespace {
+
+// LSQR phase sequence of one subproblem (the scratch layout of krylov_entry):
+// init, B_1, then A_i and B_{i+1} for i < iters, A_iters, finish.
+int lsqr_sequence(dbl_ctx* ctx, const Job& j, int m, int esz, int prec, int sep, int rb, int H,
+                  int iters, void* W, void* V, void* U1, void* U2, const void* x0, void* AX0) {
+  const PartLayout PL = part_layout(j.part, m);
+  const int t = tiles_per_axis(m, esz);
+  double* PA[2] = {PL.s[0], PL.s[0] + (size_t)t * t};  // |u|^2 partials by parity
+  double* PB[2] = {PL.s[1], PL.s[1] + (size_t)t * t};  // |v|^2 partials by parity
+  Job jl = j;
+  jl.v[V_PA] = W;
+  jl.v[V_S] = V;
+  jl.v[V_R1A] = U1;
+  jl.v[V_R2A] = U2;
+  int rc = DBL_OK;
+  auto run = [&](Job jj, const char* what, auto launcher) {
+    Launch L;
+    L.add(jj, m, esz);
+    LaunchArgs la;
+    if ((rc = L.upload(ctx, la))) return rc;
+    return rc = hip_check(ctx, launcher(la), what);
+  };
+  Job ji = jl;
+  ji.v[V_X0] = const_cast<void*>(x0);
+  ji.v[V_XOLD] = AX0;
+  ji.pw = PA[0];
+  if (run(ji, "lsqr init", [&](const LaunchArgs& la) { return launch_lsqr_init(la, prec); }))
+    return rc;
+  if (iters == 0) return DBL_OK;
+  for (int i = 1; i <= iters; ++i) {
+    Job jb = jl;
+    jb.i0 = i;
+    if (i == 1) jb.flags |= F_FIRST;
+    jb.pr[0] = PA[(i - 1) & 1];
+    jb.pr[1] = PB[(i - 1) & 1];
+    jb.pw = PB[i & 1];
+    if (run(jb, "lsqr B", [&](const LaunchArgs& la) {
+          return launch_lsqr_b(la, prec, sep, rb, H);
+        }))
+      return rc;
+    Job ja = jl;
+    ja.i0 = i;
+    if (i == 1) ja.flags |= F_FIRST;
+    ja.pr[0] = PB[i & 1];
+    ja.pr[1] = PA[(i - 1) & 1];
+    ja.pw = PA[i & 1];
+    if (run(ja, "lsqr A", [&](const LaunchArgs& la) {
+          return launch_lsqr_a(la, prec, sep, rb, H);
+        }))
+      return rc;
+  }
+  Job jf = jl;
+  jf.i0 = iters;
+  jf.pr[0] = PA[iters & 1];
+  return run(jf, "lsqr finish", [&](const LaunchArgs& la) { return launch_lsqr_fin(la, prec); });
+}
+
+int krylov_entry(dbl_ctx* ctx, const dbl_op* op, int level, const dbl_sub* sub, const void* b,
+                 const void* x0, int iters, void* x, double* resid_hist, bool lsqr) {
   if (!ctx || !op) return DBL_EINVAL;
   if (!sub || !b || !x) return set_err(ctx, DBL_EINVAL, "sub, b or x is NULL");
   if (level < 0 || level >= op->levels) return set_err(ctx, DBL_EINVAL, "level out of range");
@@ -402,7 +469,7 @@ int dbl_cgls(dbl_ctx* ctx, const dbl_op* op, int level, const dbl_sub* sub, cons
   j.v[V_C1] = const_cast<void*>(sub->c);
   const int sep = L.sep ? 1 : 0, rb = L.rb, H = L.sep ? L.rb : L.R;
   int wl = 0;
-  const size_t small = x0 ? 0 : small_lds_bytes(ctx, op, level, sub->d_kind == 1, &wl);
+  const size_t small = (x0 || lsqr) ? 0 : small_lds_bytes(ctx, op, level, sub->d_kind == 1, &wl);
   if (small && iters > 0) {
     Job js = j;
     if (wl) js.flags |= F_WLDS;
@@ -437,6 +504,19 @@ int dbl_cgls(dbl_ctx* ctx, const dbl_op* op, int level, const dbl_sub* sub, cons
     LaunchArgs la;
     if ((rc = La.upload(ctx, la))) return rc;
     if ((rc = hip_check(ctx, launch_apply_A(la, prec, sep, rb, H), "A x0"))) return rc;
+  }
+  if (lsqr) {
+    if ((rc = lsqr_sequence(ctx, j, m, (int)esz, prec, sep, rb, H, iters, P[0], S, R1[0], R2[0],
+                            x0, AX0)))
+      return rc;
+    if (resid_hist && iters > 0) {
+      if ((rc = hip_check(ctx, hipMemcpyAsync(resid_hist, scal + S_HIST, iters * sizeof(double),
+                                              hipMemcpyDeviceToHost, ctx->stream),
+                          "read history")))
+        return rc;
+      if ((rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "sync"))) return rc;
+    }
+    return DBL_OK;
   }
   Job ji = j;
   ji.v[V_PA] = P[0];
@@ -512,6 +592,20 @@ int dbl_cgls(dbl_ctx* ctx, const dbl_op* op, int level, const dbl_sub* sub, cons
     if ((rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "sync"))) return rc;
   }
   return DBL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dbl_cgls(dbl_ctx* ctx, const dbl_op* op, int level, const dbl_sub* sub, const void* b,
+             const void* x0, int iters, void* x, double* resid_hist) {
+  return krylov_entry(ctx, op, level, sub, b, x0, iters, x, resid_hist, false);
+}
+
+int dbl_lsqr(dbl_ctx* ctx, const dbl_op* op, int level, const dbl_sub* sub, const void* b,
+             const void* x0, int iters, void* x, double* resid_hist) {
+  return krylov_entry(ctx, op, level, sub, b, x0, iters, x, resid_hist, true);
 }
 
 int dbl_gcv(dbl_ctx* ctx, const dbl_op* op, int level, const dbl_sub* sub, const void* b,

@@ -34,6 +34,7 @@ constexpr int NSCAL = 512;  // doubles per job scalar block
 enum Scal : int {
   S_GAMMA = 0, S_SQRTG, S_GS, S_ALPHA, S_BETA, S_QQ, S_RR, S_GS0,
   S_RCNUM, S_RCDEN, S_RES2, S_PEN, S_EPS, S_TAU, S_WSQ, S_ITER,
+  S_LQ = 16,     // LSQR rotation state (rhobar, phibar), two copies by parity
   // GCV state
   S_G_TLO = 32, S_G_THI, S_G_A, S_G_B, S_G_X, S_G_W, S_G_V, S_G_FX, S_G_FW,
   S_G_FV, S_G_D, S_G_E, S_G_U, S_G_DONE, S_G_NEV, S_G_XTOL, S_G_IT, S_G_RMIN,
@@ -277,6 +278,29 @@ __device__ __forceinline__ double sum_partials(const double* p, int nt, int comp
   const double r = *bcast;
   __syncthreads();
   return r;
+}
+
+// Two partial sums at once (components c0 of K0-component partials p0 and c1
+// of K1-component partials p1, nt tiles each), with one block reduction; each
+// total is bitwise what sum_partials returns for it.  bcast holds 2 doubles.
+template <int K0, int K1>
+__device__ __forceinline__ void sum_partials2(const double* p0, int c0, const double* p1, int c1,
+                                              int nt, double* red, double* bcast, double& s0,
+                                              double& s1) {
+  double v[2] = {0.0, 0.0};
+  for (int t = threadIdx.x; t < nt; t += NTHREADS) {
+    v[0] += p0[t * K0 + c0];
+    v[1] += p1[t * K1 + c1];
+  }
+  block_sum<2>(v, red);
+  if (threadIdx.x == 0) {
+    bcast[0] = v[0];
+    bcast[1] = v[1];
+  }
+  __syncthreads();
+  s0 = bcast[0];
+  s1 = bcast[1];
+  __syncthreads();
 }
 
 // Publish a scalar written by the finalising thread so later kernels and

@@ -112,12 +112,12 @@ __global__ void __launch_bounds__(NTHREADS) k_gcv_symbol(const Job* __restrict__
   const double w = 3.14159265358979323846 / m;
   // cos(pi k a / m) for the tile's frequencies and every kernel offset
   for (int q = threadIdx.x; q < TI * n0; q += NTHREADS)
-    c0[q] = cos(w * (double)(i0 + q % TI) * (double)(q / TI - r0));
+    c0[q] = cos(w * (double)(i0 + (q & (TI - 1))) * (double)((q >> (__ffs(TI) - 1)) - r0));
   for (int q = threadIdx.x; q < TJ * n1; q += NTHREADS)
-    c1[q] = cos(w * (double)(j0 + q % TJ) * (double)(q / TJ - r1));
+    c1[q] = cos(w * (double)(j0 + (q & (TJ - 1))) * (double)((q >> (__ffs(TJ) - 1)) - r1));
   __syncthreads();
   for (int o = threadIdx.x; o < TI * TJ; o += NTHREADS) {
-    const int u = o % TI, v = o / TI;
+    const int u = (o & (TI - 1)), v = (o >> (__ffs(TI) - 1));
     double acc = 0.0;
     for (int b = 0; b < n1; ++b) {
       double inner = 0.0;
@@ -146,7 +146,7 @@ __global__ void __launch_bounds__(NTHREADS) k_gcv_prep(const Job* __restrict__ j
   if (job->i0 == 0) {
     const T* __restrict__ b = static_cast<const T*>(job->v[G_B]);
     for (int o = threadIdx.x; o < TI * TJ; o += NTHREADS) {
-      const size_t g = (i0 + o % TI) + (size_t)(j0 + o / TI) * m;
+      const size_t g = (i0 + (o & (TI - 1))) + (size_t)(j0 + (o >> (__ffs(TI) - 1))) * m;
       in[g] = (double)b[g];
     }
     return;
@@ -158,7 +158,7 @@ __global__ void __launch_bounds__(NTHREADS) k_gcv_prep(const Job* __restrict__ j
     return c1 ? (double)c1[k] - (c2 ? (double)c2[k] : 0.0) : 0.0;
   };
   for (int o = threadIdx.x; o < TI * TJ; o += NTHREADS) {
-    const int gi = i0 + o % TI, gj = j0 + o / TI;
+    const int gi = i0 + (o & (TI - 1)), gj = j0 + (o >> (__ffs(TI) - 1));
     const size_t g = gi + (size_t)gj * m;
     double a = 0.0;
     if (c1) {
@@ -260,7 +260,7 @@ __global__ void __launch_bounds__(NTHREADS) k_gcv_data(const Job* __restrict__ j
   double lo = 1e300, hi = -1e300;
   for (int o = threadIdx.x; o < TI * TJ && exact; o += NTHREADS) {
     // nu in the symbol slot: bounds from nu / (1 - nu) over 0 < nu < 1 - 1e-10
-    const size_t g = (i0 + o % TI) + (size_t)(j0 + o / TI) * m;
+    const size_t g = (i0 + (o & (TI - 1))) + (size_t)(j0 + (o >> (__ffs(TI) - 1))) * m;
     const double nu = fmin(fmax(sym[g], 0.0), 1.0);
     if (nu > 0.0 && nu < 1.0 - 1e-10) {
       const double r = nu / (1.0 - nu);
@@ -272,7 +272,7 @@ __global__ void __launch_bounds__(NTHREADS) k_gcv_data(const Job* __restrict__ j
     }
   }
   for (int o = threadIdx.x; o < TI * TJ && !exact; o += NTHREADS) {
-    const int k0 = i0 + o % TI, k1 = j0 + o / TI;
+    const int k0 = i0 + (o & (TI - 1)), k1 = j0 + (o >> (__ffs(TI) - 1));
     const size_t g = k0 + (size_t)k1 * m;
     const double a = sym[g];
     const double lp = wb2 * (lam[k0] + lam[k1]);
@@ -320,7 +320,7 @@ __device__ __forceinline__ void load_freqs(const Job* job, int i0, int j0, int T
   const double* __restrict__ fv = static_cast<const double*>(job->v[G_BH]);
   f.cnt = 0;
   for (int o = threadIdx.x; o < TI * TJ; o += NT) {
-    const int k0 = i0 + o % TI, k1 = j0 + o / TI;
+    const int k0 = i0 + (o & (TI - 1)), k1 = j0 + (o >> (__ffs(TI) - 1));
     const size_t g = k0 + (size_t)k1 * m;
     if (exact) {  // (nu, f, g) in the (s, lp, e) registers
       f.s[f.cnt] = fmin(fmax(sym[g], 0.0), 1.0);

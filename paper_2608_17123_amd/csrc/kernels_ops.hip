@@ -85,7 +85,7 @@ __global__ void __launch_bounds__(NTHREADS) k_grad(const Job* __restrict__ jobs,
   T* __restrict__ q = static_cast<T*>(job->v[1]);
   const size_t nx = (size_t)(m - 1) * m;
   for (int o = threadIdx.x; o < TI * TJ; o += NTHREADS) {
-    const int i = i0 + o % TI, j = j0 + o / TI;
+    const int i = i0 + (o & (TI - 1)), j = j0 + (o >> (__ffs(TI) - 1));
     const T xc = x[i + (size_t)j * m];
     if (i < m - 1) q[i + (size_t)j * (m - 1)] = x[i + 1 + (size_t)j * m] - xc;
     if (j < m - 1) q[nx + i + (size_t)j * m] = x[i + (size_t)(j + 1) * m] - xc;
@@ -105,7 +105,7 @@ __global__ void __launch_bounds__(NTHREADS) k_gradT(const Job* __restrict__ jobs
   T* __restrict__ y = static_cast<T*>(job->v[1]);
   const T* __restrict__ qy = q + (size_t)(m - 1) * m;
   for (int o = threadIdx.x; o < TI * TJ; o += NTHREADS) {
-    const int i = i0 + o % TI, j = j0 + o / TI;
+    const int i = i0 + (o & (TI - 1)), j = j0 + (o >> (__ffs(TI) - 1));
     T a = T(0);
     if (i >= 1) a += q[i - 1 + (size_t)j * (m - 1)];
     if (i < m - 1) a -= q[i + (size_t)j * (m - 1)];
@@ -135,7 +135,7 @@ __global__ void __launch_bounds__(NTHREADS) k_dwt_fwd(const Job* __restrict__ jo
   T* __restrict__ y = static_cast<T*>(job->v[1]);
   const size_t nc = (size_t)mc * mc;
   for (int o = threadIdx.x; o < TI * TJ; o += NTHREADS) {
-    const int a0 = i0 + o % TI, a1 = j0 + o / TI;
+    const int a0 = i0 + (o & (TI - 1)), a1 = j0 + (o >> (__ffs(TI) - 1));
     double ll = 0, lh = 0, hl = 0, hh = 0;
     for (int b = 0; b < K; ++b) {
       const size_t col = (size_t)((2 * a1 + b) & msk) * m;
@@ -177,7 +177,7 @@ __global__ void __launch_bounds__(NTHREADS) k_dwt_inv(const Job* __restrict__ jo
   T* __restrict__ x = static_cast<T*>(job->v[1]);
   const size_t nc = (size_t)mc * mc;
   for (int o = threadIdx.x; o < TI * TJ; o += NTHREADS) {
-    const int f0 = i0 + o % TI, f1 = j0 + o / TI;
+    const int f0 = i0 + (o & (TI - 1)), f1 = j0 + (o >> (__ffs(TI) - 1));
     double acc = 0;
     for (int t1 = 0; t1 < K2; ++t1) {
       const int c1 = ((f1 >> 1) - t1) & cm, k1 = (f1 & 1) + 2 * t1;
@@ -213,7 +213,7 @@ __global__ void __launch_bounds__(NTHREADS) k_dtransfer(const Job* __restrict__ 
   const T* __restrict__ qyc = qc + (size_t)(mc - 1) * mc;
   T* __restrict__ qyf = qf + (size_t)(m - 1) * m;
   for (int o = threadIdx.x; o < TI * TJ; o += NTHREADS) {
-    const int f0 = i0 + o % TI, f1 = j0 + o / TI;
+    const int f0 = i0 + (o & (TI - 1)), f1 = j0 + (o >> (__ffs(TI) - 1));
     if (f0 < m - 1) {  // row block: rows of W~1 x columns of W1
       double acc = 0;
       for (int t1 = 0; t1 < K2; ++t1) {

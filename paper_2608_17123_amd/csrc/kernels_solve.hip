@@ -17,47 +17,9 @@
 // The norms are per-tile FP64 partials: p1 writes |q|^2 partials and sums the
 // |s|^2 partials of the previous p2 (beta); p2 sums both (alpha) and writes
 // new |s|^2 and |r|^2 partials, which the next p1 reads.
-#include "launch.h"
-#include "stencil.h"
+#include "phase.h"
 
 namespace dbl {
-
-template <bool SEP>
-__device__ __forceinline__ int xs_at(int i, int j, int H, int TI, int TJ) {
-  return SEP ? (i + H) * sep_lx(TJ, H) + (j + H) : (j + H) * col_lx(TI, H) + (i + H);
-}
-
-template <bool SEP>
-__device__ __forceinline__ int xs_ld(int H, int TI, int TJ) {
-  return SEP ? sep_lx(TJ, H) : col_lx(TI, H);
-}
-
-template <bool SEP>
-__device__ __forceinline__ int xs_elems(int H, int TI, int TJ) {
-  return SEP ? (TI + 2 * H) * sep_lx(TJ, H) : col_lds_elems(TI, TJ, H);
-}
-
-// Tile convolution.  `hook` runs once all threads are done reading the input
-// tile Xs (separable: between the two passes; general: after an extra sync,
-// which requires a copy of the input -- the general path instead runs the
-// hook before the convolution, so it must not overwrite Xs there).
-template <typename T, int RB, bool SEP, class Epi, class Hook = NoHook>
-__device__ __forceinline__ void conv_tile(const T* Xs, int H, void* scratch, const LevelOp& op,
-                                          bool adj, int i0, int j0, int TI, int TJ, int m,
-                                          Epi epi, Hook hook = Hook()) {
-  if constexpr (SEP) {
-    sep_tile<T, RB>(Xs, H, static_cast<T*>(scratch), adj ? op.a0 : op.f0, adj ? op.a1 : op.f1,
-                    i0, j0, TI, TJ, m, epi, hook);
-  } else {
-    T* s_v = static_cast<T*>(scratch);
-    short2* s_e = reinterpret_cast<short2*>(s_v + (2 * H + 1) * (2 * H + 1));
-    gen_tile<T>(Xs, H, adj ? op.a2 : op.f2, s_e, s_v, i0, j0, TI, TJ, m, epi);
-  }
-}
-
-template <typename T> __device__ __forceinline__ T* vp(const Job* j, int k) {
-  return static_cast<T*>(j->v[k]);
-}
 
 // ------------------------------------------------------------------ init --
 template <typename T, typename S>
@@ -82,7 +44,7 @@ __global__ void __launch_bounds__(NTHREADS) k_cgls_init(const Job* __restrict__ 
   const T* ax0 = vp<T>(job, V_XOLD);  // A x0 when x0 is given
   const size_t nx = (size_t)(m - 1) * m;
   for (int o = threadIdx.x; o < TI * TJ; o += NTHREADS) {
-    const int gi = i0 + o % TI, gj = j0 + o / TI;
+    const int gi = i0 + (o & (TI - 1)), gj = j0 + (o >> (__ffs(TI) - 1));
     const size_t g = gi + (size_t)gj * m;
     double xv = 0.0;
     if (x0) {
@@ -111,11 +73,12 @@ __global__ void __launch_bounds__(NTHREADS) k_cgls_init(const Job* __restrict__ 
 
 // --------------------------------------------------------------- phase 1 --
 template <typename T, typename S, int RB, bool SEP>
-__global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 3 : 2) k_cgls_p1(const Job* __restrict__ jobs,
+__global__ void __launch_bounds__(NTHREADS, (waves_per_simd<T, RB>())) k_cgls_p1(const Job* __restrict__ jobs,
                                                       const uint32_t* __restrict__ tiles) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red[8];
   __shared__ double bc;
+  __shared__ double bc2[2];
   const Job* job; int ti, tj, tix;
   decode_tile(jobs, tiles, job, ti, tj, tix);
   const int m = job->m;
@@ -128,8 +91,8 @@ __global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 3 : 2) k_cgls_p1(co
   const int nt = job->nti * job->ntj;
   double beta = 0.0;
   if (!(job->flags & F_FIRST)) {  // iteration > 0: beta = |s_k|^2 / |s_{k-1}|^2
-    const double gcur = sum_partials<2>(job->pr[0], nt, 0, red, &bc);
-    const double gprev = sum_partials<2>(job->pr[1], nt, 0, red, &bc);
+    double gcur, gprev;
+    sum_partials2<2, 2>(job->pr[0], 0, job->pr[1], 0, nt, red, bc2, gcur, gprev);
     beta = gprev > 0.0 ? gcur / gprev : 0.0;
     if ((job->flags & F_HIST) && tix == 0) {
       const double rr = sum_partials<2>(job->pr[0], nt, 1, red, &bc);
@@ -154,13 +117,13 @@ __global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 3 : 2) k_cgls_p1(co
   batched_pixels<8, 2, T>(
       TI * TJ,
       [&](int o, T* v) {
-        const int gi = i0 + o % TI, gj = j0 + o / TI;
+        const int gi = i0 + (o & (TI - 1)), gj = j0 + (o >> (__ffs(TI) - 1));
         const size_t g = gi + (size_t)gj * m;
         v[0] = (irls && gi < m - 1) ? w[gi + (size_t)gj * (m - 1)] : T(1);
         v[1] = (irls && gj < m - 1) ? w[nx + g] : T(1);
       },
       [&](int o, T* v) {
-        const int i = o % TI, j = o / TI, gi = i0 + i, gj = j0 + j;
+        const int i = (o & (TI - 1)), j = (o >> (__ffs(TI) - 1)), gi = i0 + i, gj = j0 + j;
         const size_t g = gi + (size_t)gj * m;
         const T pc = Xs[xs_at<SEP>(i, j, H, TI, TJ)];
         stv(pb, g, pc);
@@ -188,11 +151,12 @@ __global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 3 : 2) k_cgls_p1(co
 
 // --------------------------------------------------------------- phase 2 --
 template <typename T, typename S, int RB, bool SEP>
-__global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 3 : 2) k_cgls_p2(const Job* __restrict__ jobs,
+__global__ void __launch_bounds__(NTHREADS, (waves_per_simd<T, RB>())) k_cgls_p2(const Job* __restrict__ jobs,
                                                       const uint32_t* __restrict__ tiles) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red[8];
   __shared__ double bc;
+  __shared__ double bc2[2];
   const Job* job; int ti, tj, tix;
   decode_tile(jobs, tiles, job, ti, tj, tix);
   const int m = job->m;
@@ -207,8 +171,8 @@ __global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 3 : 2) k_cgls_p2(co
   const int nt = job->nti * job->ntj;
   double alpha = 0.0;
   if (!first) {  // alpha = |s|^2 / |q|^2
-    const double qq = sum_partials<1>(job->pr[0], nt, 0, red, &bc);
-    const double gs = sum_partials<2>(job->pr[1], nt, 0, red, &bc);
+    double qq, gs;
+    sum_partials2<1, 2>(job->pr[0], 0, job->pr[1], 0, nt, red, bc2, qq, gs);
     alpha = qq > 0.0 ? gs / qq : 0.0;
   }
   const T ta = (T)alpha;
@@ -235,14 +199,14 @@ __global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 3 : 2) k_cgls_p2(co
   batched_pixels<8, 2, T>(
       TI * TJ,
       [&](int o, T* v) {
-        const size_t g = (i0 + o % TI) + (size_t)(j0 + o / TI) * m;
+        const size_t g = (i0 + (o & (TI - 1))) + (size_t)(j0 + (o >> (__ffs(TI) - 1))) * m;
         if (!first) {
           v[0] = x[g];
           v[1] = ldv<T>(p, g);
         }
       },
       [&](int o, T* v) {
-        const int i = o % TI, j = o / TI;
+        const int i = (o & (TI - 1)), j = (o >> (__ffs(TI) - 1));
         const size_t g = (i0 + i) + (size_t)(j0 + j) * m;
         const T rv = Xs[xs_at<SEP>(i, j, H, TI, TJ)];
         stv(r1b, g, rv);
@@ -257,10 +221,10 @@ __global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 3 : 2) k_cgls_p2(co
   auto grad_part = [&](T* buf) {
     LT = buf;
     // per pixel: entries qx(i-1,j), qx(i,j), qy(i,j-1), qy(i,j) -> (r2a, q2, w)
-    batched_pixels<4, 12, T>(
+    batched_pixels<2, 12, T>(
         TI * TJ,
         [&](int o, T* v) {
-          const int gi = i0 + o % TI, gj = j0 + o / TI;
+          const int gi = i0 + (o & (TI - 1)), gj = j0 + (o >> (__ffs(TI) - 1));
           const size_t g = gi + (size_t)gj * m;
           size_t ks[4];
           bool ok[4];
@@ -276,7 +240,7 @@ __global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 3 : 2) k_cgls_p2(co
           }
         },
         [&](int o, T* v) {
-          const int i = o % TI, j = o / TI, gi = i0 + i, gj = j0 + j;
+          const int i = (o & (TI - 1)), j = (o >> (__ffs(TI) - 1)), gi = i0 + i, gj = j0 + j;
           const size_t g = gi + (size_t)gj * m;
           T rn[4];
 #pragma unroll
@@ -351,7 +315,7 @@ __global__ void __launch_bounds__(NTHREADS) k_aux(const Job* __restrict__ jobs,
   T* __restrict__ c2 = vp<T>(job, V_C2);
   const size_t nx = (size_t)(m - 1) * m;
   for (int o = threadIdx.x; o < TI * TJ; o += NTHREADS) {
-    const int gi = i0 + o % TI, gj = j0 + o / TI;
+    const int gi = i0 + (o & (TI - 1)), gj = j0 + (o >> (__ffs(TI) - 1));
     const size_t g = gi + (size_t)gj * m;
     const double xc = (double)x[g];
     for (int dir = 0; dir < 2; ++dir) {
@@ -403,7 +367,7 @@ __global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 3 : 2) k_stats(cons
   __syncthreads();
   double num = 0.0, den = 0.0, res = 0.0, pen = 0.0;
   for (int o = threadIdx.x; o < TI * TJ; o += NTHREADS) {
-    const int i = o % TI, j = o / TI, gi = i0 + i, gj = j0 + j;
+    const int i = (o & (TI - 1)), j = (o >> (__ffs(TI) - 1)), gi = i0 + i, gj = j0 + j;
     const size_t g = gi + (size_t)gj * m;
     const double xc = (double)Xs[xs_at<SEP>(i, j, H, TI, TJ)];
     const double xv = (double)xo[g];
@@ -449,6 +413,7 @@ __global__ void __launch_bounds__(NTHREADS) k_stats_fin(const Job* __restrict__ 
   h[0] = gam;
   h[1] = rc;
   h[2] = tot[2] + coef * tot[3];
+  if (double* out = static_cast<double*>(job->v[V_RCOUT])) *out = rc;
 }
 
 // ------------------------------------------------------------- set gamma --
@@ -477,7 +442,7 @@ __global__ void __launch_bounds__(NTHREADS) k_fill(const Job* __restrict__ jobs,
   const T val = (T)job->p0;
   const size_t nx = (size_t)(m - 1) * m;
   for (int o = threadIdx.x; o < TI * TJ; o += NTHREADS) {
-    const int gi = i0 + o % TI, gj = j0 + o / TI;
+    const int gi = i0 + (o & (TI - 1)), gj = j0 + (o >> (__ffs(TI) - 1));
     const size_t g = gi + (size_t)gj * m;
     if (a) a[g] = val;
     if (q) {
@@ -516,35 +481,6 @@ struct Dummy {};
                           (2 * sizeof(T) + sizeof(short2)) * (2 * (H) + 1) * (2 * (H) + 1) + \
                           sizeof(T) * ts_ * ts_;                                      \
       hipLaunchKernelGGL((KERNEL<T, 0, false>), dim3((la).ntiles), dim3(NTHREADS),    \
-                         lds_, (la).stream, (la).jobs, (la).tiles);                    \
-    }                                                                                  \
-  } while (0)
-
-// Same, for kernels that also take the storage type S of the state vectors.
-#define DISPATCH_STENCIL_S(KERNEL, T, S, la, sep, rb, H)                           \
-  do {                                                                                 \
-    const int TS_ = TileCfg<T>::TS;                                                    \
-    const int ts_ = (la).m_max < TS_ ? (la).m_max : TS_;                               \
-    if (sep) {                                                                         \
-      const size_t lds_ = sizeof(T) * sep_lds_elems(ts_, ts_, rb);                     \
-      switch (rb) {                                                                    \
-        case 2: hipLaunchKernelGGL((KERNEL<T, S, 2, true>), dim3((la).ntiles),           \
-                    dim3(NTHREADS), lds_, (la).stream, (la).jobs, (la).tiles); break;  \
-        case 4: hipLaunchKernelGGL((KERNEL<T, S, 4, true>), dim3((la).ntiles),           \
-                    dim3(NTHREADS), lds_, (la).stream, (la).jobs, (la).tiles); break;  \
-        case 8: hipLaunchKernelGGL((KERNEL<T, S, 8, true>), dim3((la).ntiles),           \
-                    dim3(NTHREADS), lds_, (la).stream, (la).jobs, (la).tiles); break;  \
-        case 12: hipLaunchKernelGGL((KERNEL<T, S, 12, true>), dim3((la).ntiles),         \
-                    dim3(NTHREADS), lds_, (la).stream, (la).jobs, (la).tiles); break;  \
-        case 16: hipLaunchKernelGGL((KERNEL<T, S, 16, true>), dim3((la).ntiles),         \
-                    dim3(NTHREADS), lds_, (la).stream, (la).jobs, (la).tiles); break;  \
-        default: return hipErrorInvalidValue;                                          \
-      }                                                                                \
-    } else {                                                                           \
-      const size_t lds_ = sizeof(T) * col_lds_elems(ts_, ts_, H) +                     \
-                          (2 * sizeof(T) + sizeof(short2)) * (2 * (H) + 1) * (2 * (H) + 1) + \
-                          sizeof(T) * ts_ * ts_;                                      \
-      hipLaunchKernelGGL((KERNEL<T, S, 0, false>), dim3((la).ntiles), dim3(NTHREADS),    \
                          lds_, (la).stream, (la).jobs, (la).tiles);                    \
     }                                                                                  \
   } while (0)

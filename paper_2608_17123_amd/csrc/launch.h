@@ -27,7 +27,9 @@ enum VSlot : int {
   V_B,       // right-hand side b (n)
   V_C1, V_C2,// shift c = C1 - C2 (SB: d - g), c = C1 (MM)
   V_XOLD,    // previous outer iterate (CGLS start: A x0)
-  V_X0       // optional CGLS start
+  V_X0,      // optional CGLS start
+  // statistics finish jobs: optional FP64 destination of the step's RC
+  V_RCOUT = V_X0
 };
 
 hipError_t launch_apply_A(const LaunchArgs& la, int precision, int sep, int rb, int H);
@@ -47,6 +49,11 @@ hipError_t launch_fill(const LaunchArgs& la, int precision);
 hipError_t launch_stats_fin(const LaunchArgs& la);
 hipError_t launch_cgls_hist(const LaunchArgs& la);
 hipError_t launch_set_gamma(const LaunchArgs& la);
+// LSQR phases (kernels_lsqr.hip)
+hipError_t launch_lsqr_init(const LaunchArgs& la, int precision);
+hipError_t launch_lsqr_a(const LaunchArgs& la, int precision, int sep, int rb, int H);
+hipError_t launch_lsqr_b(const LaunchArgs& la, int precision, int sep, int rb, int H);
+hipError_t launch_lsqr_fin(const LaunchArgs& la, int precision);
 // One-block CGLS (kernels_small.hip): one block per job, all iterations, for
 // levels with a separable operator.  Every job of a launch has m x m grids,
 // m in {8, 16, 32, 64}.

@@ -547,6 +547,8 @@ int slot_init(dbl_ctx* ctx, const dbl_request& req, Slot* s) {
   s->level = req.levels - 1;
   s->k = 0;
   s->cur = 0;
+  for (int& it : s->iters) it = 0;
+  s->rc_idx = -1;
   s->started = false;
   s->done = false;
   return rc;
@@ -578,6 +580,7 @@ int slot_report(dbl_ctx* ctx, Slot* s, dbl_report* rep) {
       rep->objective[i][k] = e[2];
     }
   rep->status = s->status;
+  for (int i = 0; i < DBL_MAX_LEVELS; ++i) rep->iters[i] = i < s->levels ? s->iters[i] : 0;
   return DBL_OK;
 }
 
@@ -625,6 +628,11 @@ Job base_job(const Slot* s, int level) {
 GroupKey key_of(const Slot* s, int level) {
   const LevelHost& L = s->op->host.levels[level];
   return GroupKey{s->prec, L.sep ? 1 : 0, L.sep ? L.rb : 0, L.sep ? L.rb : L.R};
+}
+
+// RC tolerance of the slot's current level (0: fixed outer count).
+double level_tol(const Slot* s) {
+  return s->level == 0 ? s->opts.tol_fine : s->opts.tol_coarse;
 }
 
 int solver_flags(const Slot* s) {
@@ -1076,6 +1084,26 @@ int engine_step(dbl_ctx* ctx, std::vector<Slot*>& slots) {
   }
 
   // ---- E. Split Bregman update (Alg. 3) and statistics ----------------------
+  // Solves that stop on a tolerance get an entry of ctx->d_rc, which the
+  // statistics kernel fills with this step's RC for the host's test in F.
+  int n_rc = 0;
+  for (Slot* s : act) s->rc_idx = level_tol(s) > 0.0 ? n_rc++ : -1;
+  if (n_rc > ctx->rc_cap) {
+    const int cap = std::max(64, 2 * n_rc);
+    if ((rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "sync"))) return rc;
+    if (ctx->d_rc) dfree(ctx, ctx->d_rc);
+    if (ctx->h_rc) (void)hipHostFree(ctx->h_rc);
+    ctx->d_rc = ctx->h_rc = nullptr;
+    ctx->rc_cap = 0;
+    void* d = nullptr;
+    if ((rc = dmalloc(ctx, (size_t)cap * 8, &d))) return rc;
+    ctx->d_rc = static_cast<double*>(d);
+    if ((rc = hip_check(ctx, hipHostMalloc((void**)&ctx->h_rc, (size_t)cap * 8,
+                                           hipHostMallocDefault),
+                        "hipHostMalloc")))
+      return rc;
+    ctx->rc_cap = cap;
+  }
   {
     std::map<int, Launch> L;
     for (Slot* s : act)
@@ -1100,6 +1128,7 @@ int engine_step(dbl_ctx* ctx, std::vector<Slot*>& slots) {
       jf.pr[0] = PL.st;
       const int t = tiles_per_axis(j.m, (int)s->esz);
       jf.i1 = t * t;
+      if (s->rc_idx >= 0) jf.v[V_RCOUT] = ctx->d_rc + s->rc_idx;
       F.add(jf, 1, 4);
     }
     for (auto& kv : S) {
@@ -1121,13 +1150,30 @@ int engine_step(dbl_ctx* ctx, std::vector<Slot*>& slots) {
                           "stats fin")))
         return rc;
     }
+    if (n_rc > 0) {
+      rc = hip_check(ctx, hipMemcpyAsync(ctx->h_rc, ctx->d_rc, (size_t)n_rc * 8,
+                                         hipMemcpyDeviceToHost, ctx->stream),
+                     "read RC");
+      if (!rc) rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "sync RC");
+      if (rc) return rc;
+    }
   }
 
   // ---- F. advance ------------------------------------------------------------
   for (Slot* s : act) {
     s->cur = 1 - s->cur;
     s->k += 1;
-    if (s->k == s->opts.k_out) {
+    s->iters[s->level] = s->k;
+    // eq. (stop); a NaN RC (iteration from x = 0) never stops the level
+    const bool converged = s->rc_idx >= 0 && ctx->h_rc[s->rc_idx] < level_tol(s);
+    if (s->level == 0 && s->opts.x_hist) {
+      char* dst = static_cast<char*>(s->opts.x_hist) + (size_t)(s->k - 1) * s->n0 * s->esz;
+      rc = hip_check(ctx, hipMemcpyAsync(dst, s->X[s->cur], (size_t)s->n0 * s->esz,
+                                         hipMemcpyDeviceToDevice, ctx->stream),
+                     "copy iterate history");
+      if (rc) return rc;
+    }
+    if (s->k == s->opts.k_out || converged) {
       s->k = 0;
       if (s->level == 0) {
         s->done = true;

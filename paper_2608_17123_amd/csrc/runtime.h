@@ -54,6 +54,11 @@ struct dbl_ctx {
   void* blas = nullptr;
   void* gx = nullptr;
   size_t gx_bytes = 0;
+  // RC of the solves that stop on a tolerance, gathered once per engine step
+  // (device array written by the statistics kernel, pinned host copy)
+  double* d_rc = nullptr;
+  double* h_rc = nullptr;
+  int rc_cap = 0;
 };
 
 struct dbl_op {
@@ -187,6 +192,8 @@ struct Slot {
   std::vector<double> mu;  // levels * k_out fixed parameters (when !gcv)
   // progress
   int level = 0, k = 0, cur = 0;
+  int iters[DBL_MAX_LEVELS]{};  // outer iterations run per level
+  int rc_idx = -1;              // this step's entry of ctx->d_rc (tolerance stop)
   bool started = false, done = false, bh_valid = false;
   int status = 0;
   double t_submit = 0.0, t_done = 0.0;

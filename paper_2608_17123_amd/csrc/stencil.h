@@ -44,6 +44,28 @@ __host__ __device__ inline int col_lds_elems(int TI, int TJ, int H) {
   return (TJ + 2 * H) * col_lx(TI, H);
 }
 
+// q = n / d and r = n % d for 0 <= n <= 4096 and 1 <= d <= 128 without an
+// integer division: (n + 1/2) / d lies at least 1/(2d) >= 1/256 from an
+// integer, and its FP32 evaluation with the hardware reciprocal (1 ulp) errs
+// by less than 1e-3 at these sizes, so the truncation is exact.  A divisor
+// known at compile time (after inlining, as in the one-block kernels) keeps
+// the compiler's multiply-shift sequence, which is shorter.
+__device__ __forceinline__ void divmod_small(int n, int d, float rd, int& q, int& r) {
+  if (__builtin_constant_p(d)) {
+    q = (int)((unsigned)n / (unsigned)d);
+  } else {
+    q = (int)(((float)n + 0.5f) * rd);
+  }
+  r = n - q * d;
+}
+__device__ __forceinline__ float rcp_small(int d) { return __builtin_amdgcn_rcpf((float)d); }
+
+// Row and column of pixel o in a tile of TI rows (TI a power of two).
+__device__ __forceinline__ void tile_ij(int o, int TI, int& i, int& j) {
+  i = o & (TI - 1);
+  j = o >> (__ffs(TI) - 1);
+}
+
 // Load the (TI+2H) x (TJ+2H) region starting at global (i0-H, j0-H) with
 // periodic wrap.  f(gi) returns the value at flat global index gi.  Loads are
 // issued in groups of U per thread before the LDS stores, so the whole tile
@@ -52,8 +74,9 @@ template <typename T, bool ROWMAJOR, int NT = NTHREADS, class F>
 __device__ __forceinline__ void load_tile(T* Xs, int ld, int i0, int j0, int TI, int TJ, int H,
                                           int m, F f) {
   constexpr int U = sizeof(T) == 4 ? 16 : 8;
-  const int NR = TI + 2 * H, NC = TJ + 2 * H, tot = NR * NC;
+  const int NR = TI + 2 * H, NC = TJ + 2 * H, tot = NR * NC;  // <= 64 x 64
   const int msk = m - 1;
+  const float rNR = rcp_small(NR);
 #pragma unroll 1
   for (int base = threadIdx.x; base < tot; base += NT * U) {
     T v[U];
@@ -61,7 +84,8 @@ __device__ __forceinline__ void load_tile(T* Xs, int ld, int i0, int j0, int TI,
     for (int u = 0; u < U; ++u) {
       const int idx = base + u * NT;
       if (idx < tot) {
-        const int r = idx % NR, c = idx / NR;
+        int c, r;
+        divmod_small(idx, NR, rNR, c, r);
         const int gi = (i0 - H + r) & msk, gj = (j0 - H + c) & msk;
         v[u] = f(gi + gj * m);
       }
@@ -70,7 +94,8 @@ __device__ __forceinline__ void load_tile(T* Xs, int ld, int i0, int j0, int TI,
     for (int u = 0; u < U; ++u) {
       const int idx = base + u * NT;
       if (idx < tot) {
-        const int r = idx % NR, c = idx / NR;
+        int c, r;
+        divmod_small(idx, NR, rNR, c, r);
         if (ROWMAJOR) Xs[r * ld + c] = v[u]; else Xs[c * ld + r] = v[u];
       }
     }
@@ -106,11 +131,13 @@ __device__ __forceinline__ void sep_tile(const T* __restrict__ Xs, int H, T* __r
     T tp[NTAP];
 #pragma unroll
     for (int e = 0; e < NTAP; ++e) tp[e] = T0[t0.St * NTAP + e];
-    const int NC = TJ + 2 * RB;
+    const int NC = TJ + 2 * RB;  // <= 128; NC * nch <= 4096
     const int nch = (TI + V - 1) / V;
+    const float rNC = rcp_small(NC);
 #pragma unroll 1
     for (int item = threadIdx.x; item < NC * nch; item += NTH) {
-      const int c = item % NC, ch = item / NC;
+      int c, ch;
+      divmod_small(item, NC, rNC, ch, c);
       const int r0 = ch * V;
       const int xc = c + (H - RB);
       T win[NW];
@@ -177,7 +204,8 @@ __device__ __forceinline__ void sep_tile(const T* __restrict__ Xs, int H, T* __r
     const int nch = (TJ + V - 1) / V;
 #pragma unroll 1
     for (int item = threadIdx.x; item < TI * nch; item += NTH) {
-      const int r = item % TI, ch = item / TI;
+      int r, ch;
+      tile_ij(item, TI, r, ch);
       const int c0 = ch * V;
       T win[NW];
 #pragma unroll
@@ -241,7 +269,8 @@ __device__ __forceinline__ void gen_tile(const T* __restrict__ Xs, int H, const 
     }
     __syncthreads();
     for (int o = threadIdx.x; o < TI * TJ; o += NT) {
-      const int i = o % TI, j = o / TI;
+      int i, j;
+      tile_ij(o, TI, i, j);
       T a = T(0);
       for (int k = 0; k < n; ++k) {
         const short2 e = s_e[k];
@@ -251,7 +280,8 @@ __device__ __forceinline__ void gen_tile(const T* __restrict__ Xs, int H, const 
     }
   } else {
     for (int o = threadIdx.x; o < TI * TJ; o += NT) {
-      const int i = o % TI, j = o / TI;
+      int i, j;
+      tile_ij(o, TI, i, j);
       const int c0 = class_of(i0 + i, m, tb.St0, tb.Sb0);
       const int c1 = class_of(j0 + j, m, tb.St1, tb.Sb1);
       const int cls = c0 + c1 * tb.rows0;

@@ -1,0 +1,201 @@
+"""Reconstruction quality of the multilevel method on the synthetic stand-ins.
+
+The paper measures quality by the relative reconstruction error
+RRE(x) = ||x - x_true|| / ||x_true|| (Sec. 5) and plots it against the
+fine-level outer iteration for five combinations per solver: the one-level
+method (Approach I) and the multilevel method with Haar or Db4 and with
+solution transfer (X) or auxiliary transfer (D).  Its findings are that the
+multilevel starts reach in a few fine-level iterations what the one-level
+method needs more than ten for, that Haar does better than Db4 under
+Approach D, and that Db4 does better than Haar under Approach X.
+
+This harness solves the m = 256 workload (60-shape piecewise-constant image,
+Gaussian blur sigma = 2.5 on 15 x 15, noise 1% and 5%) with every solver in
+those five combinations, K_out outer iterations per level and K_in CGLS
+steps, all solves in one batch on the device.  The fine level's iterate
+after each outer iteration comes back through the x_hist option, and the
+RRE per iteration is taken on the device in FP64 against the known image;
+SSIM (Sec. 5, the paper's second measure) is taken on the host from the same
+iterates.  It reports the curves and, per solver and noise level, whether
+each of the paper's findings holds on this data.
+
+SSIM follows the statistic the paper states: per pixel, the local means,
+variances and covariance of the true and reconstructed images under a
+Gaussian window, combined with c1 = (0.01 L)^2 and c2 = (0.03 L)^2 (L the
+dynamic range, 1 for images in [0, 1]), averaged over all windows.  The
+paper computes it with MATLAB's ssim, whose window is not restated there;
+this module takes the window of the SSIM reference it cites (Gaussian,
+standard deviation 1.5, truncated to 11 x 11, normalised to unit mass) and
+replicates edge pixels outside the image.
+
+Usage: python -m paper_2608_17123_amd.quality [--k-out 10] [--k-in 30] [--out FILE]
+"""
+import argparse
+import json
+import sys
+
+import numpy as np
+
+SOLVERS = ("irls", "mm", "sb")
+# (label, wavelet, multilevel?, transfer); Approach I runs one grid.
+COMBOS = (("I", "haar", False, "X"), ("HWT-X", "haar", True, "X"),
+          ("HWT-D", "haar", True, "D"), ("DWT-X", "db4", True, "X"),
+          ("DWT-D", "db4", True, "D"))
+
+
+def gaussian_window(sigma=1.5, radius=5):
+    """Normalised 1-D Gaussian taps exp(-k^2 / (2 sigma^2)), |k| <= radius."""
+    k = np.arange(-radius, radius + 1, dtype=np.float64)
+    g = np.exp(-k * k / (2.0 * sigma * sigma))
+    return g / g.sum()
+
+
+def ssim(x_true, x, L=1.0, sigma=1.5, radius=5):
+    """Mean structural similarity of two m x m images (FP64, host)."""
+    from scipy.ndimage import correlate1d
+
+    g = gaussian_window(sigma, radius)
+
+    def smooth(a):
+        return correlate1d(correlate1d(a, g, axis=0, mode="nearest"), g, axis=1, mode="nearest")
+
+    a = np.asarray(x_true, dtype=np.float64)
+    b = np.asarray(x, dtype=np.float64)
+    mu_a, mu_b = smooth(a), smooth(b)
+    var_a = smooth(a * a) - mu_a * mu_a
+    var_b = smooth(b * b) - mu_b * mu_b
+    cov = smooth(a * b) - mu_a * mu_b
+    c1, c2 = (0.01 * L) ** 2, (0.03 * L) ** 2
+    s = ((2 * mu_a * mu_b + c1) * (2 * cov + c2)) / ((mu_a ** 2 + mu_b ** 2 + c1) *
+                                                      (var_a + var_b + c2))
+    return float(s.mean())
+
+
+def _observed(D, torch, ctx, w):
+    """b = A x_true + e on the device in FP64, stored as FP32."""
+    op = D.dbl_op_create(ctx, w.psf, w.m, 1, "haar", D.DBL_F64)
+    xt = torch.from_numpy(np.ascontiguousarray(w.x_true.ravel(order="F"))).cuda()
+    bt = torch.empty_like(xt)
+    D.dbl_apply_A(ctx, op, 0, 0, xt, bt)
+    op.close()
+    xi = torch.from_numpy(np.ascontiguousarray(w.xi.ravel(order="F"))).cuda()
+    b = bt + w.noise_level * torch.linalg.norm(bt) * xi / torch.linalg.norm(xi)
+    return xt, b.float().contiguous()
+
+
+def run(k_out=10, k_in=30, workloads=None, solvers=SOLVERS, combos=COMBOS, ctx=None):
+    """Solve every (noise level, solver, combination) in one batch; return the
+    RRE after each fine-level outer iteration."""
+    import torch
+    import paper_2608_17123_amd as D
+    import synth
+
+    own = ctx is None
+    ctx = D.dbl_create(0) if own else ctx
+    if workloads is None:
+        # one workload per noise level (the config-2 list repeats the image)
+        workloads = {w.noise_level: w for w in synth.config2()}.values()
+    cases, reqs = [], []
+    for w in workloads:
+        xt, b = _observed(D, torch, ctx, w)
+        for solver in solvers:
+            for label, wavelet, multi, transfer in combos:
+                levels = w.levels if multi else 1
+                x = torch.zeros_like(b)
+                hist = torch.zeros((k_out, b.numel()), dtype=b.dtype, device=b.device)
+                opts = D.dbl_opts_default(k_out=k_out, k_in=k_in, x_hist=hist)
+                reqs.append(D.make_request(b, x, w.psf, w.m, solver, wavelet, levels, transfer,
+                                           opts))
+                cases.append((w, solver, label, levels, xt, b, x, hist))
+    reps = D.dbl_deblur_batch(ctx, reqs)
+    torch.cuda.synchronize()
+    rows = []
+    for (w, solver, label, levels, xt, b, x, hist), rep in zip(cases, reps):
+        nt = torch.linalg.norm(xt)
+        if not torch.equal(hist[-1], x):
+            raise RuntimeError("iterate history does not end at the returned solution")
+        rre = (torch.linalg.norm(hist.double() - xt[None, :], dim=1) / nt).tolist()
+        hh = hist.double().cpu().numpy()
+        ssims = [ssim(w.x_true, hh[k].reshape(w.m, w.m, order="F")) for k in range(k_out)]
+        rows.append({"m": w.m, "noise": w.noise_level, "solver": solver, "combo": label,
+                     "levels": levels, "rre": rre, "ssim": ssims,
+                     "rre_data": float(torch.linalg.norm(b.double() - xt) / nt),
+                     "gamma_fine": rep["gamma"][0]})
+    if own:
+        ctx.close()
+    return {"k_out": k_out, "k_in": k_in, "rows": rows, "findings": findings(rows)}
+
+
+def _iters_to(curve, target):
+    """First fine-level iteration (1-based) whose RRE is at or below target."""
+    for k, v in enumerate(curve):
+        if v <= target:
+            return k + 1
+    return None
+
+
+def findings(rows):
+    """The paper's three qualitative findings, checked per (noise, solver)."""
+    out = []
+    for noise in sorted({r["noise"] for r in rows}):
+        for solver in SOLVERS:
+            c = {r["combo"]: r["rre"] for r in rows
+                 if r["noise"] == noise and r["solver"] == solver}
+            if len(c) < len(COMBOS):
+                continue
+            target = c["I"][-1]
+            reach = {k: _iters_to(v, target) for k, v in c.items() if k != "I"}
+            best = min((v for v in reach.values() if v is not None), default=None)
+            out.append({
+                "noise": noise, "solver": solver,
+                "one_level_final_rre": target,
+                "multilevel_iters_to_match": reach,
+                "multilevel_faster": best is not None and best < len(c["I"]),
+                "haar_better_under_D": c["HWT-D"][-1] < c["DWT-D"][-1],
+                "db4_better_under_X": c["DWT-X"][-1] < c["HWT-X"][-1],
+            })
+    return out
+
+
+def markdown(res):
+    ks = [k for k in (1, 2, 3, 5, res["k_out"]) if k <= res["k_out"]]
+    ks = sorted(set(ks))
+    out = [f"RRE = ||x - x_true|| / ||x_true|| after fine-level outer iteration k "
+           f"(K_out = {res['k_out']} per level, K_in = {res['k_in']}).", "",
+           "| noise | solver | combination | grids | RRE(b) | " +
+           " | ".join(f"k={k}" for k in ks) + f" | SSIM at k={res['k_out']} |",
+           "|---|---|---|---|---|" + "---|" * len(ks) + "---|"]
+    for r in res["rows"]:
+        out.append(f"| {r['noise']:.0%} | {r['solver']} | {r['combo']} | {r['levels']} | "
+                   f"{r['rre_data']:.4f} | " +
+                   " | ".join(f"{r['rre'][k - 1]:.4f}" for k in ks) +
+                   f" | {r['ssim'][-1]:.4f} |")
+    out += ["", "| noise | solver | I final RRE | fine iterations to match it "
+            "(HWT-X, HWT-D, DWT-X, DWT-D) | multilevel faster | Haar better under D | "
+            "Db4 better under X |", "|---|---|---|---|---|---|---|"]
+    for f in res["findings"]:
+        it = ", ".join(str(f["multilevel_iters_to_match"].get(c) or "-")
+                       for c in ("HWT-X", "HWT-D", "DWT-X", "DWT-D"))
+        out.append(f"| {f['noise']:.0%} | {f['solver']} | {f['one_level_final_rre']:.4f} | "
+                   f"{it} | {f['multilevel_faster']} | {f['haar_better_under_D']} | "
+                   f"{f['db4_better_under_X']} |")
+    return "\n".join(out) + "\n"
+
+
+def main(argv=None):
+    p = argparse.ArgumentParser()
+    p.add_argument("--k-out", type=int, default=10)
+    p.add_argument("--k-in", type=int, default=30)
+    p.add_argument("--out", default=None, help="also write the markdown tables here")
+    a = p.parse_args(argv)
+    res = run(a.k_out, a.k_in)
+    md = markdown(res)
+    sys.stdout.write(md)
+    print(json.dumps(res))
+    if a.out:
+        with open(a.out, "w") as f:
+            f.write(md)
+
+
+if __name__ == "__main__":
+    main()

@@ -49,6 +49,18 @@ def test_opts_defaults_are_the_papers():
     o = D.dbl_opts()
     D.lib().dbl_opts_default(ctypes.byref(o))
     assert (o.eps, o.tau, o.gcv_grid, o.k_out, o.k_in) == (0.03, 0.005, 50, 10, 30)
+    assert (o.tol_fine, o.tol_coarse, o.x_hist) == (0.0, 0.0, None)
+
+
+def test_opts_struct_size_matches_the_library():
+    """dbl_opts_default clears sizeof(dbl_opts) bytes: on a buffer of 0xAB
+    bytes it must set the binding's last field and touch nothing after it."""
+    n = ctypes.sizeof(D.dbl_opts)
+    buf = (ctypes.c_ubyte * (n + 64))(*([0xAB] * (n + 64)))
+    D.lib().dbl_opts_default(ctypes.cast(buf, ctypes.POINTER(D.dbl_opts)))
+    o = D.dbl_opts.from_buffer_copy(bytes(buf[:n]))
+    assert (o.tol_fine, o.tol_coarse, o.x_hist) == (0.0, 0.0, None)
+    assert bytes(buf[n:]) == b"\xab" * 64
 
 
 def deblur_code(h, m=64, ph=9, pw=9, levels=3, solver=0, wavelet=0, transfer=0, opts=None,
@@ -85,6 +97,11 @@ def test_deblur_validation_codes(hctx):
     D.lib().dbl_opts_default(ctypes.byref(o))
     o.precision = 3
     assert deblur_code(h, opts=o) == D.DBL_EINVAL
+    for name, bad in (("tol_fine", -1e-3), ("tol_coarse", float("nan")),
+                      ("tol_fine", float("inf"))):
+        D.lib().dbl_opts_default(ctypes.byref(o))
+        setattr(o, name, bad)
+        assert deblur_code(h, opts=o) == D.DBL_EINVAL, name
     # a valid request reaches the device check
     assert deblur_code(h) == D.DBL_EDEVICE
     assert b"device" in D.lib().dbl_last_error(h)

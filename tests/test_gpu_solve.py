@@ -13,7 +13,7 @@ from oracle import operators as ops
 from oracle import gcv as ogcv
 from oracle import vcycle
 from oracle.hierarchy import Hierarchy
-from oracle.krylov import Subproblem
+from oracle.krylov import Subproblem, lsqr
 
 torch = pytest.importorskip("torch")
 D = pytest.importorskip("paper_2608_17123_amd")
@@ -94,6 +94,85 @@ def test_cgls_matches_oracle(ctx, prec, kind, wavelet, level, psf, small):
     D.dbl_set_option(ctx, D.DBL_OPT_SMALL_CGLS, 1)
     assert err <= CGLS_TOL[prec]
     assert herr <= CGLS_TOL[prec] * 10
+    op.close()
+
+
+def lsqr_case(level, psf, wavelet, kind, prec, seed, m=128, levels=3):
+    P = synth.gaussian_psf(2.0, 6) if psf == "gauss" else \
+        synth.motion_psf(21, np.random.default_rng(level + 3).uniform(0.0, np.pi))
+    H = Hierarchy(P, m, levels, wavelet)
+    mi = m >> level
+    nl = 2 * mi * (mi - 1)
+    rng = np.random.default_rng(seed)
+    B = rnd(rng.standard_normal((mi, mi)), prec)
+    w = rnd(rng.uniform(0.5, 5.0, nl), prec) if kind == "irls" else None
+    c = rnd(0.1 * rng.standard_normal(nl), prec) if kind == "mm" else None
+    sub = Subproblem(lambda X: H.apply(level, X), lambda X: H.apply_adjoint(level, X), mi, B,
+                     0.02, weights=w, shift=c)
+    return P, mi, B, w, c, sub
+
+
+def oracle_lsqr(sub, iters, x0=None):
+    """The oracle's LSQR in correction form: x0 + LSQR on bhat - A^ x0."""
+    x0v = np.zeros(sub.n) if x0 is None else ops.vec(x0)
+    return x0v + lsqr(sub.matvec, sub.rmatvec, sub.bhat() - sub.matvec(x0v), sub.n, iters)
+
+
+@pytest.mark.parametrize("prec", [D.DBL_F32, D.DBL_F64])
+@pytest.mark.parametrize("kind", ["irls", "mm", "plain"])
+@pytest.mark.parametrize("wavelet,level,psf", [("haar", 0, "gauss"), ("db4", 1, "motion"),
+                                               ("db4", 2, "gauss")])
+def test_lsqr_matches_oracle(ctx, prec, kind, wavelet, level, psf):
+    """dbl_lsqr against the oracle's LSQR after 30 iterations; its residual
+    estimates against the true residuals of the oracle's iterates at
+    iterations 1, 2, 10 and 30 (LSQR's estimate is exact in exact
+    arithmetic); and against CGLS (the same iterates in exact arithmetic)."""
+    print(f"lsqr {kind} {wavelet} level={level} psf={psf} prec={prec}", flush=True)
+    P, mi, B, w, c, sub = lsqr_case(level, psf, wavelet, kind, prec, level + 20)
+    iters = 30
+    xr = oracle_lsqr(sub, iters)
+    op = D.dbl_op_create(ctx, P, 128, 3, wavelet, prec)
+    x = torch.zeros(mi * mi, dtype=torch.float32 if prec == 0 else torch.float64, device="cuda")
+    wd = None if w is None else dev(w, prec)
+    cd = None if c is None else dev(c, prec)
+    bd = dev(ops.vec(B), prec)
+    gh = D.dbl_lsqr(ctx, op, level, bd, iters, x, 0.02, w=wd, c=cd)
+    err = relerr(host(x), xr)
+    true_r = {k: float(np.sum((sub.bhat() - sub.matvec(oracle_lsqr(sub, k))) ** 2))
+              for k in (1, 2, 10, 30)}
+    herr = max(abs(gh[k - 1] - v) / v for k, v in true_r.items())
+    xc = torch.zeros_like(x)
+    D.dbl_cgls(ctx, op, level, bd, iters, xc, 0.02, w=wd, c=cd)
+    cerr = relerr(host(x), host(xc))
+    print(f"  x relerr {err:.3e}  resid-est relerr {herr:.3e}  vs CGLS {cerr:.3e}", flush=True)
+    op.close()
+    assert err <= CGLS_TOL[prec]
+    assert herr <= CGLS_TOL[prec] * 10
+    assert cerr <= 2 * CGLS_TOL[prec]
+
+
+@pytest.mark.parametrize("prec", [D.DBL_F32, D.DBL_F64, D.DBL_BF16])
+@pytest.mark.parametrize("kind", ["irls", "mm"])
+def test_lsqr_warm_start_and_short_runs(ctx, kind, prec):
+    """dbl_lsqr from a given x0 (correction form) at 0, 1, 2 and 20 iterations:
+    0 iterations return x0 itself."""
+    P, mi, B, w, c, sub = lsqr_case(0, "gauss", "haar", kind, prec, 44)
+    rng = np.random.default_rng(45)
+    X0 = rnd(0.5 * rng.standard_normal((mi, mi)), prec)
+    op = D.dbl_op_create(ctx, P, 128, 3, "haar", prec)
+    dt = torch.float64 if prec == D.DBL_F64 else torch.float32
+    for iters in (0, 1, 2, 20):
+        x = torch.zeros(mi * mi, dtype=dt, device="cuda")
+        D.dbl_lsqr(ctx, op, 0, dev(ops.vec(B), prec), iters, x, 0.02,
+                   w=None if w is None else dev(w, prec), c=None if c is None else dev(c, prec),
+                   x0=dev(ops.vec(X0), prec))
+        xr = oracle_lsqr(sub, iters, X0)
+        err = relerr(host(x), xr)
+        print(f"lsqr warm {kind} prec={prec} iters={iters}: x relerr {err:.2e}", flush=True)
+        if iters == 0:
+            assert np.array_equal(host(x), ops.vec(X0))
+        else:
+            assert err <= (2e-2 if prec == D.DBL_BF16 else CGLS_TOL[prec])
     op.close()
 
 

@@ -2,6 +2,8 @@
 alone == in a mix (bitwise), run-to-run determinism, and end-to-end parity
 with GCV on (spectral tier on both sides) for the m = 64 and m = 256
 configurations."""
+from dataclasses import replace
+
 import numpy as np
 import pytest
 
@@ -282,3 +284,102 @@ def test_config2_bf16_storage_error(ctx, solver, wavelet, transfer):
     D.dbl_deblur_batch(ctx, reqs)
     assert np.array_equal(host(x2), xs[D.DBL_BF16])
     assert np.array_equal(host(x3), xs[D.DBL_BF16])
+
+
+def test_iterate_history_is_the_fine_level_iterate_sequence(ctx):
+    """x_hist slice k is the iterate after fine-level outer iteration k: on one
+    grid it equals the result of a solve stopped after k + 1 outer
+    iterations (bitwise), and on several grids its last slice is the result."""
+    w = synth.config1()
+    b = dev(blurred(w))
+    base = dict(k_in=10, mu_fixed=0.02)
+    for solver in ("irls", "mm", "sb"):
+        hist = torch.full((3, b.numel()), float("nan"), device="cuda")
+        x = torch.zeros_like(b)
+        D.dbl_deblur(ctx, b, w.psf, w.m, solver, "haar", 1, "X", x,
+                     D.dbl_opts_default(k_out=3, x_hist=hist, **base))
+        for k in (1, 2, 3):
+            xk, _ = solve_alone(ctx, replace(w, solver=solver, levels=1), b,
+                                dict(k_out=k, **base))
+            assert np.array_equal(host(hist[k - 1]), xk), (solver, k)
+        for transfer in ("X", "D"):
+            hist = torch.full((4, b.numel()), float("nan"), device="cuda")
+            x = torch.zeros_like(b)
+            D.dbl_deblur(ctx, b, w.psf, w.m, solver, "db4", 3, transfer, x,
+                         D.dbl_opts_default(k_out=4, x_hist=hist, **base))
+            h = host(hist)
+            assert np.isfinite(h).all()
+            assert np.array_equal(h[-1], host(x))
+
+
+def test_quality_harness_small_workload(ctx):
+    """The quality harness on the m = 64 workload: every curve is finite and
+    every combination ends below the RRE of the blurred data."""
+    from paper_2608_17123_amd import quality
+    res = quality.run(k_out=3, k_in=30, workloads=[synth.config1()], ctx=ctx)
+    assert len(res["rows"]) == len(quality.SOLVERS) * len(quality.COMBOS)
+    for r in res["rows"]:
+        assert len(r["rre"]) == 3 and np.isfinite(r["rre"]).all()
+        assert r["rre"][-1] < r["rre_data"], r
+    assert len(res["findings"]) == len(quality.SOLVERS)
+    assert "| 1% | irls | DWT-D | 3 |" in quality.markdown(res)
+
+
+# RC of FP32 iterates carries an absolute error of about 1e-7 (the FP32
+# resolution of ||x_k - x_{k-1}|| / ||x_k||, seen up to 2.6e-8 at m = 64).
+RC_ABS_F32 = 1e-7
+
+
+def decisions_clear_of(levels_rc, tols, rel=0.02, absolute=RC_ABS_F32):
+    """True when every stopping decision of the oracle run lies farther from
+    its tolerance than rel * tol + absolute, so that FP32 rounding of RC on
+    the device cannot flip it."""
+    for rc, tol in zip(levels_rc, tols):
+        if tol <= 0:
+            continue
+        for v in rc:
+            if not np.isnan(v) and abs(v - tol) <= rel * tol + absolute:
+                return False
+    return True
+
+
+TOL_CASES = [(s, t, 1e-3, 1e-6) for s in ("irls", "mm", "sb") for t in ("X", "D")] + [
+    ("irls", "X", 1e-3, 3e-3), ("mm", "D", 1e-3, 3e-3), ("sb", "X", 1e-3, 3e-3)]
+
+
+@pytest.mark.parametrize("solver,transfer,tol_fine,tol_coarse", TOL_CASES)
+def test_tolerance_stop_matches_oracle(ctx, solver, transfer, tol_fine, tol_coarse):
+    """eq. (stop) with the tolerances of Sec. 5 (1e-3 fine, 1e-6 coarse) and a
+    coarse tolerance that stops the coarse grids early: m = 64, 3 grids, Haar,
+    GCV on (spectral tier), at most 10 x 30.  The device stops every grid after
+    the same outer iteration as the oracle and ends at the same solution."""
+    w = synth.config1()
+    B = blurred(w)
+    Xo, rep_o = vcycle.deblur(B, w.psf, solver, "haar", 3, transfer, 10, 30,
+                              gcv_mode="spectral", tol_fine=tol_fine, tol_coarse=tol_coarse)
+    rc_o = [h["rc"] for h in rep_o["levels"]]
+    tols = [tol_fine, tol_coarse, tol_coarse]
+    assert decisions_clear_of(rc_o, tols), rc_o
+    it_o = [len(r) for r in rc_o]
+    b = dev(B)
+    x = torch.zeros_like(b)
+    hist = torch.full((10, b.numel()), float("nan"), device="cuda")
+    rep = D.dbl_deblur(ctx, b, w.psf, w.m, solver, "haar", 3, transfer, x,
+                       D.dbl_opts_default(k_out=10, k_in=30, gcv_mode="spectral",
+                                          tol_fine=tol_fine, tol_coarse=tol_coarse,
+                                          x_hist=hist))
+    print(f"{solver}-{transfer} tol {tol_fine:g}/{tol_coarse:g}: iterations oracle {it_o} "
+          f"device {rep['iters']}")
+    assert rep["iters"] == it_o
+    for lv, k in enumerate(it_o):
+        rg = np.array(rep["rc"][lv])
+        assert np.isnan(rg[k:]).all()                 # nothing recorded past the stop
+        ro = np.array(rc_o[lv])
+        ok = ~np.isnan(ro)
+        assert np.array_equal(np.isnan(rg[:k]), ~ok)
+        np.testing.assert_allclose(rg[:k][ok], ro[ok], rtol=5e-3, atol=RC_ABS_F32)
+    xerr = float(np.linalg.norm(host(x) - Xo.ravel(order="F")) / np.linalg.norm(Xo))
+    assert xerr <= 1e-4, xerr
+    h = host(hist)
+    assert np.array_equal(h[it_o[0] - 1], host(x))
+    assert np.isnan(h[it_o[0]:]).all()                # slices past the stop untouched
