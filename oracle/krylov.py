@@ -119,3 +119,9 @@ class Subproblem:
         x0 = np.zeros(self.n) if x0 is None else self.ops.vec(x0)
         x, hist = cgls(self.matvec, self.rmatvec, self.bhat(), x0, iters)
         return self.ops.unvec(x, self.m), hist
+
+    def solve_lsqr(self, iters, x0=None):
+        """LSQR for `iters` steps from x0 (on the residual bhat - M x0)."""
+        x0 = np.zeros(self.n) if x0 is None else self.ops.vec(x0)
+        x = x0 + lsqr(self.matvec, self.rmatvec, self.bhat() - self.matvec(x0), self.n, iters)
+        return self.ops.unvec(x, self.m)

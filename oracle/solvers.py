@@ -137,11 +137,13 @@ def gcv_gamma(op, B, solver, weights, shift, mode):
 
 
 def solve_level(op, B, solver, state, k_out, k_in, mu=None, n_grids=1,
-                gcv_mode="auto", eps=EPS, tau=TAU, inner=None, tol=0.0):
+                gcv_mode="auto", eps=EPS, tau=TAU, inner=None, tol=0.0, krylov="cgls"):
     """Run at most k_out outer iterations at one level from ``state``.
 
     mu: None (GCV per the schedule) or a sequence of k_out fixed values.
     tol: stop after the first iteration with RC < tol (0: run all k_out).
+    krylov: "cgls" (default) or "lsqr" (the paper's inner solver, Sec. 3),
+    k_in steps from x0 = 0 either way.
     inner: optional replacement subproblem solver ``inner(sub) -> X`` (tests
     use a dense direct solve to check properties of exact minimisation).
     Returns (state, history) with history lists 'gamma', 'rc', 'objective'."""
@@ -170,7 +172,12 @@ def solve_level(op, B, solver, state, k_out, k_in, mu=None, n_grids=1,
             elif which == "current":
                 gamma = gcv_gamma(op, B, solver, weights, shift, gcv_mode)
         sub = Subproblem(op.A, op.AT, m, B, gamma, weights=weights, shift=shift)
-        X = sub.solve_cgls(k_in)[0] if inner is None else inner(sub)
+        if inner is not None:
+            X = inner(sub)
+        elif krylov == "lsqr":
+            X = sub.solve_lsqr(k_in)
+        else:
+            X = sub.solve_cgls(k_in)[0]
         st["x"] = X
         Lx = ops.grad(X)
         if solver == "sb":

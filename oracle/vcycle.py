@@ -19,14 +19,15 @@ from .solvers import (LevelOperator, init_state, final_aux, solve_level, EPS, TA
 
 def deblur(B, psf, solver="irls", wavelet="haar", levels=3, transfer="X",
            k_out=10, k_in=30, mu=None, gcv_mode="auto", eps=EPS, tau=TAU, fast=False,
-           tol_fine=0.0, tol_coarse=0.0):
+           tol_fine=0.0, tol_coarse=0.0, krylov="cgls"):
     """Solve min ||A x - b||^2 + mu ||L x||_1 by the V-cycle.
 
     B: m x m observed image.  mu: None (GCV) or a list over levels (finest
     first) of k_out fixed parameters each.  tol_fine / tol_coarse: the RC
     tolerance of eq. (stop) on the finest grid (also the single grid of
     Approach I) and on the coarser grids; Sec. 5 uses 1e-3 and 1e-6.  0 runs
-    k_out outer iterations on every grid.  Returns (X, report) where the
+    k_out outer iterations on every grid.  krylov: the inner solver, "cgls"
+    or "lsqr".  Returns (X, report) where the
     report holds per-level histories (finest level first)."""
     B = np.asarray(B, dtype=np.float64)
     m = B.shape[0]
@@ -51,5 +52,5 @@ def deblur(B, psf, solver="irls", wavelet="haar", levels=3, transfer="X",
         mu_i = None if mu is None else mu[i]
         state, hists[i] = solve_level(op, bs[i], solver, st0, k_out, k_in, mu_i,
                                       n_grids, gcv_mode, eps, tau,
-                                      tol=tol_fine if i == 0 else tol_coarse)
+                                      tol=tol_fine if i == 0 else tol_coarse, krylov=krylov)
     return state["x"], {"levels": hists, "sizes": hier.sizes}

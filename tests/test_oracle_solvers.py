@@ -187,3 +187,17 @@ def test_vcycle_tolerances_per_grid():
                             tol_fine=1e3)
     assert [len(h["rc"]) for h in rep["levels"]] == [1, 6, 6]
     assert rep["levels"][1]["objective"] == full["levels"][1]["objective"]
+
+
+@pytest.mark.parametrize("solver,transfer", [("irls", "X"), ("sb", "D")])
+def test_vcycle_with_lsqr_inner_equals_cgls_inner(solver, transfer):
+    """LSQR and CGLS produce the same iterates in exact arithmetic, so whole
+    V-cycles with either inner solver agree to FP64 rounding."""
+    X, P, B = small_problem(m=32, seed=6, sigma=1.5, r=4, noise=0.01)
+    mu = [[1e-3] * 3] * 3
+    Xc, rc = vcycle.deblur(B, P, solver, "db4", 3, transfer, k_out=3, k_in=12, mu=mu)
+    Xl, rl = vcycle.deblur(B, P, solver, "db4", 3, transfer, k_out=3, k_in=12, mu=mu,
+                           krylov="lsqr")
+    assert np.linalg.norm(Xl - Xc) <= 1e-9 * np.linalg.norm(Xc)
+    for hc, hl in zip(rc["levels"], rl["levels"]):
+        np.testing.assert_allclose(hl["objective"], hc["objective"], rtol=1e-9)
