@@ -55,6 +55,8 @@ def parse():
     p.add_argument("--calib-copy", action="store_true")
     p.add_argument("--precision", default="f32", choices=["f32", "bf16", "f64"],
                    help="vector storage: FP32, BF16 CGLS state with FP32 arithmetic, or FP64")
+    p.add_argument("--inner", default="cgls", choices=["cgls", "lsqr"],
+                   help="inner Krylov solver of every subproblem")
     return p.parse_args()
 
 
@@ -174,7 +176,8 @@ def cpu_baseline(D, torch, ctx, w, opts_kw, k_out_sample=3):
     with threadpool_limits(1):
         t0 = time.perf_counter()
         Xo, rep = vcycle.deblur(B32, w.psf, w.solver, w.wavelet, w.levels, w.transfer,
-                                k_out_sample, w.k_in, gcv_mode="spectral", fast=True)
+                                k_out_sample, w.k_in, gcv_mode="spectral", fast=True,
+                                krylov=opts_kw.get("inner_solver", "cgls"))
         t = time.perf_counter() - t0
     npdt = np.float64 if opts_kw["precision"] == D.DBL_F64 else np.float32
     b = torch.from_numpy(np.ascontiguousarray(B32.ravel(order="F"), dtype=npdt)).cuda()
@@ -224,7 +227,7 @@ def main():
         workloads = synth.config4(256)
         wdesc = ("256 images, m~U{64,128,256,512}, sigma~U[1,4], noise~U[0.5%,5%], mixed "
                  "solver/wavelet/transfer, min(5,log2 m-4) grids, 10x30, spectral GCV")
-    opts_kw = {"precision": prec, "gcv_mode": "spectral"}
+    opts_kw = {"precision": prec, "gcv_mode": "spectral", "inner_solver": args.inner}
     items = build_inputs(D, torch, ctx, workloads, prec)
     reqs = make_requests(D, items, opts_kw)
     nsolve = len(reqs)
@@ -295,7 +298,8 @@ def main():
         "dtype": "f64" if prec == D.DBL_F64 else "f32",
         "storage": {"f32": "f32", "bf16": "bf16 CGLS state, f32 data", "f64": "f64"}[args.precision],
         "data": "synthetic",
-        "config": {"workload": wdesc, "solves_per_step": nsolve, "path": "batched"},
+        "config": {"workload": wdesc, "solves_per_step": nsolve, "path": "batched",
+                   "inner_solver": args.inner},
         "plain_solves_per_s": None if plain is None else round(plain, 2),
         "batched_over_plain": None if plain is None else round(value / plain, 2),
         "rel_err_vs_oracle": err,

@@ -77,6 +77,7 @@ typedef enum { DBL_XFER_X = 0, DBL_XFER_D = 1 } dbl_transfer;
  * residual and objective are recomputed in FP32 from x.  Levels that run
  * the one-block CGLS keep their state in LDS in FP32. */
 typedef enum { DBL_F32 = 0, DBL_F64 = 1, DBL_BF16 = 2 } dbl_precision;
+typedef enum { DBL_INNER_CGLS = 0, DBL_INNER_LSQR = 1 } dbl_inner;
 /* GCV tiers: SPECTRAL evaluates the GCV function of eq. (GCV) on the DCT
  * surrogate (reflexive-boundary blur, exact Neumann gradient); EXACT uses the
  * generalised eigendecomposition of the pair {A, D} (the paper's GSVD route,
@@ -118,6 +119,11 @@ typedef struct dbl_opts {
                             ||x_k+1 - x_k|| / ||x_k|| < tol, else after k_out.
                             Sec. 5 uses 1e-3.  0: always run k_out.         */
   double tol_coarse;     /* the same on every coarser grid; Sec. 5: 1e-6     */
+  int inner_solver;      /* dbl_inner: the Krylov solver of every subproblem,
+                            k_in iterations from x = 0.  CGLS (default) and
+                            LSQR (the paper's, Sec. 3) give the same iterates
+                            in exact arithmetic; LSQR always runs the tiled
+                            phase kernels.                                   */
 } dbl_opts;
 
 /* Per-solve report.  Level 0 is the finest grid.  Arrays are filled for

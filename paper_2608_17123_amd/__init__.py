@@ -33,6 +33,8 @@ SOLVERS = {"irls": DBL_IRLS, "mm": DBL_MM, "sb": DBL_SB}
 WAVELETS = {"haar": DBL_HAAR, "db4": DBL_DB4}
 TRANSFERS = {"X": DBL_XFER_X, "D": DBL_XFER_D, "I": DBL_XFER_X}
 GCV_MODES = {"auto": DBL_GCV_AUTO, "exact": DBL_GCV_EXACT, "spectral": DBL_GCV_SPECTRAL}
+DBL_INNER_CGLS, DBL_INNER_LSQR = 0, 1
+INNER_SOLVERS = {"cgls": DBL_INNER_CGLS, "lsqr": DBL_INNER_LSQR}
 
 EXPORTS = [
     "dbl_create", "dbl_destroy", "dbl_set_option", "dbl_last_error", "dbl_sync", "dbl_workspace_bytes",
@@ -49,7 +51,7 @@ class dbl_opts(ctypes.Structure):
                 ("mu_schedule", ctypes.POINTER(ctypes.c_double)), ("gcv_mode", ctypes.c_int),
                 ("gcv_grid", ctypes.c_int), ("precision", ctypes.c_int),
                 ("x_hist", ctypes.c_void_p), ("tol_fine", ctypes.c_double),
-                ("tol_coarse", ctypes.c_double)]
+                ("tol_coarse", ctypes.c_double), ("inner_solver", ctypes.c_int)]
 
 
 class dbl_report(ctypes.Structure):
@@ -256,6 +258,8 @@ def dbl_opts_default(**kw):
     for k, v in kw.items():
         if k == "gcv_mode" and isinstance(v, str):
             v = GCV_MODES[v]
+        if k == "inner_solver" and isinstance(v, str):
+            v = INNER_SOLVERS[v]
         setattr(o, k, v)
     if sched is not None:
         arr = np.ascontiguousarray(np.asarray(sched, dtype=np.float64).ravel())

@@ -53,6 +53,8 @@ int check_opts(dbl_ctx* ctx, const dbl_opts& o) {
   if (!(o.tol_fine >= 0.0) || !(o.tol_coarse >= 0.0) || !std::isfinite(o.tol_fine) ||
       !std::isfinite(o.tol_coarse))
     return set_err(ctx, DBL_EINVAL, "tolerances must be finite and >= 0");
+  if (o.inner_solver != DBL_INNER_CGLS && o.inner_solver != DBL_INNER_LSQR)
+    return set_err(ctx, DBL_EINVAL, "bad inner_solver");
   return check_prec(ctx, o.precision);
 }
 
@@ -94,6 +96,7 @@ void dbl_opts_default(dbl_opts* o) {
   o->x_hist = nullptr;
   o->tol_fine = 0.0;
   o->tol_coarse = 0.0;
+  o->inner_solver = DBL_INNER_CGLS;
 }
 
 int dbl_create(dbl_ctx** out, int device, void* hip_stream, size_t budget) {

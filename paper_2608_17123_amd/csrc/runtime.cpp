@@ -198,7 +198,10 @@ double job_bytes(const char* k, const Job& j, int prec) {
   // each operand read or written once
   if (s == "cgls_p1") return (4 * n + nl) * v + wb;              // s, p in; p, q1, q2 out
   if (s == "cgls_p2") return (5 * n + 3 * nl) * v + 2 * n * e + wb;  // r1,q1,p,r2,q2 in; r1,s,r2 out; x
-  if (s == "cgls_init") return (2 * n + nl) * v + (2 * n + nl) * e;
+  if (s == "cgls_init" || s == "lsqr_init") return (2 * n + nl) * v + (2 * n + nl) * e;
+  if (s == "lsqr_a") return (5 * n + 2 * nl) * v + 2 * n * e + wb;  // v,u,w in; u,w out; x
+  if (s == "lsqr_b") return (3 * n + nl) * v + wb;                  // u, v in; v out
+  if (s == "lsqr_fin") return n * v + 2 * n * e;                    // w in; x in and out
   if (s == "cgls_small")  // the tiled path's traffic for the same iterations
     return (2 * n + 2 * nl) * e + j.i0 * ((9 * n + 4 * nl) * v + 2 * n * e + 2 * wb);
   double el = 0.0;  // elements of x, b, w, c moved
@@ -659,7 +662,7 @@ struct GroupPlan {
 
 constexpr int MERGE_TILES = 256;
 
-GroupPlan plan_groups(dbl_ctx* ctx, const std::vector<Slot*>& slots) {
+GroupPlan plan_groups(dbl_ctx* ctx, const std::vector<Slot*>& slots, bool allow_small = true) {
   GroupPlan P;
   // one-block candidates by (precision, m): one bucket for all when every
   // member still fits in LDS with it
@@ -669,7 +672,8 @@ GroupPlan plan_groups(dbl_ctx* ctx, const std::vector<Slot*>& slots) {
     const int lv = s->level;
     const LevelHost& L = s->op->host.levels[lv];
     GroupPlan::Entry en{key_of(s, lv), 0, 0};
-    en.small_lds = small_lds_bytes(ctx, s->op, lv, s->solver == DBL_IRLS, &en.wlds);
+    if (allow_small)
+      en.small_lds = small_lds_bytes(ctx, s->op, lv, s->solver == DBL_IRLS, &en.wlds);
     P.e[s] = en;
     if (en.small_lds) small[{s->prec, L.m}].push_back(s);
     else tiled[en.key].push_back(s);
@@ -734,6 +738,122 @@ int run_simple(dbl_ctx* ctx, SimpleFn fn, std::map<int, Launch>& byprec, const c
     for (const Job& jj : kv.second.jobs) b += job_bytes(what, jj, kv.first);
     rc = hip_check(ctx, timed(ctx, what, b, [&] { return fn(la, kv.first); }), what);
     if (rc) return rc;
+  }
+  return DBL_OK;
+}
+
+// LSQR on the subproblems of the slots in `lq` (Sec. 3): per slot, init,
+// then B_i and A_i for i = 1..k_in and the finishing update, all tiled
+// (kernels_lsqr.hip), batched across slots like the CGLS phases.  Slots are
+// ordered by decreasing k_in so that each iteration launches a prefix.
+int run_lsqr(dbl_ctx* ctx, std::vector<Slot*> lq) {
+  if (lq.empty()) return DBL_OK;
+  int rc = DBL_OK;
+  std::stable_sort(lq.begin(), lq.end(),
+                   [](const Slot* a, const Slot* b) { return a->opts.k_in > b->opts.k_in; });
+  const GroupPlan plan = plan_groups(ctx, lq, false);
+  std::map<int, Launch> initL;
+  std::map<GroupKey, Launch> bF, aF, bP[2], aP[2];
+  std::map<std::pair<GroupKey, int>, Launch> finL;  // by (group, k_in)
+  std::map<GroupKey, std::vector<int>> kin;
+  for (Slot* s : lq) {
+    const int lv = s->level;
+    const int mi = s->m >> lv;
+    const PartLayout PL = part_layout(s->part, mi);
+    const size_t nt = (size_t)tiles_per_axis(mi, (int)s->esz) * tiles_per_axis(mi, (int)s->esz);
+    double* PA[2] = {PL.s[0], PL.s[0] + nt};  // |u|^2 partials by iteration parity
+    double* PB[2] = {PL.s[1], PL.s[1] + nt};  // |v|^2 partials by iteration parity
+    const GroupPlan::Entry& pe = plan.at(s);
+    const GroupKey gk = pe.key;
+    Job j = base_job(s, lv);
+    j.op = op_dev(s->op, lv, gk.rb ? gk.rb : s->op->host.levels[lv].rb);
+    j.flags = solver_flags(s);
+    j.v[V_X] = s->X[1 - s->cur];
+    j.v[V_PA] = s->P[0];   // w
+    j.v[V_S] = s->S;       // v
+    j.v[V_R1A] = s->R1[0];  // u (image part)
+    j.v[V_R2A] = s->R2[0];  // u (gradient part)
+    j.v[V_W] = s->W;
+    j.v[V_B] = const_cast<void*>(s->B[lv]);
+    j.v[V_C1] = s->C1;
+    j.v[V_C2] = s->C2;
+    Job ji = j;
+    ji.pw = PA[0];
+    initL[s->prec].add(ji, mi, (int)s->esz);
+    for (int i = 1; i <= 3; ++i) {  // i = 1 (first), 2 and 3 (the two parities)
+      Job jb = j;
+      jb.i0 = i;
+      if (i == 1) jb.flags |= F_FIRST;
+      jb.pr[0] = PA[(i - 1) & 1];
+      jb.pr[1] = PB[(i - 1) & 1];
+      jb.pw = PB[i & 1];
+      Job ja = j;
+      ja.i0 = i;
+      if (i == 1) ja.flags |= F_FIRST;
+      ja.pr[0] = PB[i & 1];
+      ja.pr[1] = PA[(i - 1) & 1];
+      ja.pw = PA[i & 1];
+      Launch& B = i == 1 ? bF[gk] : bP[i & 1][gk];
+      Launch& A = i == 1 ? aF[gk] : aP[i & 1][gk];
+      B.add(jb, mi, (int)s->esz);
+      A.add(ja, mi, (int)s->esz);
+    }
+    Job jf = j;
+    jf.i0 = s->opts.k_in;
+    jf.pr[0] = PA[s->opts.k_in & 1];
+    finL[{gk, s->opts.k_in}].add(jf, mi, (int)s->esz);
+    kin[gk].push_back(s->opts.k_in);
+  }
+  if ((rc = run_simple(ctx, launch_lsqr_init, initL, "lsqr_init"))) return rc;
+  std::map<GroupKey, LaunchArgs> lbF, laF, lbP[2], laP[2];
+  for (auto& kv : kin) {
+    const GroupKey& g = kv.first;
+    if ((rc = bF[g].upload(ctx, lbF[g])) || (rc = aF[g].upload(ctx, laF[g]))) return rc;
+    for (int par = 0; par < 2; ++par)
+      if ((rc = bP[par][g].upload(ctx, lbP[par][g])) || (rc = aP[par][g].upload(ctx, laP[par][g])))
+        return rc;
+  }
+  int kmax = 0;
+  for (auto& kv : kin)
+    for (int k : kv.second) kmax = std::max(kmax, k);
+  for (int it = 1; it <= kmax; ++it) {
+    const int par = it & 1;
+    for (int phase = 0; phase < 2; ++phase) {  // B_it, then A_it
+      for (auto& kv : kin) {
+        const GroupKey& g = kv.first;
+        const std::vector<int>& ks = kv.second;
+        int q = 0;
+        while (q < (int)ks.size() && ks[q] >= it) ++q;
+        if (!q) continue;
+        const Launch& src = phase == 0 ? (it == 1 ? bF[g] : bP[par][g])
+                                       : (it == 1 ? aF[g] : aP[par][g]);
+        LaunchArgs la = phase == 0 ? (it == 1 ? lbF[g] : lbP[par][g])
+                                   : (it == 1 ? laF[g] : laP[par][g]);
+        la.ntiles = src.tiles_upto[q - 1];
+        const char* name = phase == 0 ? "lsqr_b" : "lsqr_a";
+        double b = 0.0;
+        for (int jq = 0; jq < q; ++jq) b += job_bytes(name, src.jobs[jq], g.prec);
+        if ((rc = hip_check(ctx, timed(ctx, name, b, [&] {
+                              return phase == 0 ? launch_lsqr_b(la, g.prec, g.sep, g.rb, g.H)
+                                                : launch_lsqr_a(la, g.prec, g.sep, g.rb, g.H);
+                            }),
+                            name)))
+          return rc;
+      }
+    }
+    for (auto& kv : finL) {
+      if (kv.first.second != it) continue;
+      const GroupKey& g = kv.first.first;
+      LaunchArgs la;
+      if ((rc = kv.second.upload(ctx, la))) return rc;
+      double b = 0.0;
+      for (const Job& jj : kv.second.jobs) b += job_bytes("lsqr_fin", jj, g.prec);
+      if ((rc = hip_check(ctx, timed(ctx, "lsqr_fin", b, [&] {
+                            return launch_lsqr_fin(la, g.prec);
+                          }),
+                          "lsqr fin")))
+        return rc;
+    }
   }
   return DBL_OK;
 }
@@ -929,10 +1049,16 @@ int engine_step(dbl_ctx* ctx, std::vector<Slot*>& slots) {
     if (!greqs.empty() && (rc = gcv_run(ctx, greqs))) return rc;
   }
 
-  // ---- D. CGLS on the augmented system -------------------------------------
+  // ---- D. CGLS (or LSQR) on the augmented system ---------------------------
+  std::vector<Slot*> lq;
+  for (Slot* s : act)
+    if (s->opts.inner_solver == DBL_INNER_LSQR) lq.push_back(s);
+  if ((rc = run_lsqr(ctx, lq))) return rc;
   {
     // order slots by decreasing k_in so every iteration launches a prefix
-    std::vector<Slot*> ord = act;
+    std::vector<Slot*> ord;
+    for (Slot* s : act)
+      if (s->opts.inner_solver != DBL_INNER_LSQR) ord.push_back(s);
     std::stable_sort(ord.begin(), ord.end(),
                      [](const Slot* a, const Slot* b) { return a->opts.k_in > b->opts.k_in; });
     std::map<int, Launch> initL;

@@ -50,6 +50,7 @@ def test_opts_defaults_are_the_papers():
     D.lib().dbl_opts_default(ctypes.byref(o))
     assert (o.eps, o.tau, o.gcv_grid, o.k_out, o.k_in) == (0.03, 0.005, 50, 10, 30)
     assert (o.tol_fine, o.tol_coarse, o.x_hist) == (0.0, 0.0, None)
+    assert o.inner_solver == D.DBL_INNER_CGLS
 
 
 def test_opts_struct_size_matches_the_library():
@@ -59,7 +60,7 @@ def test_opts_struct_size_matches_the_library():
     buf = (ctypes.c_ubyte * (n + 64))(*([0xAB] * (n + 64)))
     D.lib().dbl_opts_default(ctypes.cast(buf, ctypes.POINTER(D.dbl_opts)))
     o = D.dbl_opts.from_buffer_copy(bytes(buf[:n]))
-    assert (o.tol_fine, o.tol_coarse, o.x_hist) == (0.0, 0.0, None)
+    assert (o.tol_fine, o.tol_coarse, o.x_hist, o.inner_solver) == (0.0, 0.0, None, 0)
     assert bytes(buf[n:]) == b"\xab" * 64
 
 
@@ -98,7 +99,7 @@ def test_deblur_validation_codes(hctx):
     o.precision = 3
     assert deblur_code(h, opts=o) == D.DBL_EINVAL
     for name, bad in (("tol_fine", -1e-3), ("tol_coarse", float("nan")),
-                      ("tol_fine", float("inf"))):
+                      ("tol_fine", float("inf")), ("inner_solver", 2)):
         D.lib().dbl_opts_default(ctypes.byref(o))
         setattr(o, name, bad)
         assert deblur_code(h, opts=o) == D.DBL_EINVAL, name

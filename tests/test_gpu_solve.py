@@ -277,6 +277,58 @@ def test_deblur_fixed_mu_matches_oracle(ctx, prec, solver, wavelet, transfer, le
     assert oerr <= max(OBJ_TOL[prec], 0.0) * 100  # reported; tightened once measured
 
 
+@pytest.mark.parametrize("prec", [D.DBL_F32, D.DBL_F64])
+@pytest.mark.parametrize("solver", ["irls", "mm", "sb"])
+@pytest.mark.parametrize("wavelet,transfer,levels", [("haar", "X", 3), ("db4", "D", 3),
+                                                     ("db4", "X", 1)])
+def test_deblur_lsqr_inner_matches_oracle(ctx, prec, solver, wavelet, transfer, levels):
+    """Whole V-cycles with LSQR as the inner solver (inner_solver = LSQR) at a
+    fixed parameter schedule against the oracle's V-cycle with its LSQR."""
+    m, k_out, k_in = 64, 3, 12
+    print(f"deblur lsqr {solver} {wavelet} {transfer} L={levels} prec={prec}", flush=True)
+    X, P, B = problem(m, 3, prec=prec)
+    mu = [[2e-3 * (1.5 ** i) * (1.1 ** k) for k in range(k_out)] for i in range(levels)]
+    Xo, rep_o = vcycle.deblur(B, P, solver, wavelet, levels, transfer, k_out, k_in, mu=mu,
+                              krylov="lsqr")
+    opts = D.dbl_opts_default(k_out=k_out, k_in=k_in, precision=prec,
+                              mu_schedule=np.array(mu).ravel(), inner_solver="lsqr")
+    x = torch.zeros(m * m, dtype=torch.float32 if prec == 0 else torch.float64, device="cuda")
+    rep = D.dbl_deblur(ctx, dev(ops.vec(B), prec), P, m, solver, wavelet, levels, transfer, x,
+                       opts)
+    err = relerr(host(x), ops.vec(Xo))
+    objg = np.array(rep["objective"])
+    objo = np.array([h["objective"] for h in rep_o["levels"]])
+    oerr = float(np.max(np.abs(objg - objo) / np.abs(objo)))
+    print(f"  x relerr {err:.3e}  objective relerr {oerr:.3e}", flush=True)
+    assert rep["status"] == 0
+    assert err <= SOLVE_TOL[prec]
+    assert oerr <= max(OBJ_TOL[prec], 0.0) * 100
+
+
+def test_batch_mixing_lsqr_and_cgls_equals_plain(ctx):
+    """A batch whose solves use different inner solvers and k_in: every result
+    equals its plain solve bitwise."""
+    m = 64
+    X, P, B = problem(m, 5)
+    b = dev(ops.vec(B), D.DBL_F32)
+    cases = [("irls", "haar", "X", 3, "lsqr", 12), ("mm", "db4", "D", 3, "cgls", 12),
+             ("sb", "haar", "D", 2, "lsqr", 7), ("mm", "db4", "X", 1, "lsqr", 12),
+             ("irls", "db4", "X", 3, "cgls", 5)]
+    plain, xs, reqs = [], [], []
+    for solver, wavelet, transfer, levels, inner, k_in in cases:
+        kw = dict(k_out=3, k_in=k_in, mu_fixed=3e-3, inner_solver=inner)
+        xp = torch.zeros_like(b)
+        D.dbl_deblur(ctx, b, P, m, solver, wavelet, levels, transfer, xp, D.dbl_opts_default(**kw))
+        plain.append(host(xp))
+        x = torch.zeros_like(b)
+        xs.append(x)
+        reqs.append(D.make_request(b, x, P, m, solver, wavelet, levels, transfer,
+                                   D.dbl_opts_default(**kw)))
+    D.dbl_deblur_batch(ctx, reqs)
+    for c, xp, x in zip(cases, plain, xs):
+        assert np.array_equal(host(x), xp), c
+
+
 @pytest.mark.parametrize("prec", [D.DBL_F64, D.DBL_F32])
 @pytest.mark.parametrize("kind", ["irls", "mm", "plain"])
 @pytest.mark.parametrize("m,level,wavelet", [(64, 0, "haar"), (64, 1, "db4"), (128, 2, "db4")])
