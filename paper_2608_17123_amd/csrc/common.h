@@ -27,6 +27,8 @@ namespace dbl {
 
 constexpr int TILE = 64;
 constexpr int NTHREADS = 256;
+// XCDs of the device: the dispatcher hands workgroup ids to them round-robin.
+constexpr int XCDS = 8;
 constexpr int MAX_R = 16;
 constexpr int NSCAL = 512;  // doubles per job scalar block
 

@@ -241,20 +241,42 @@ PartLayout part_layout(double* base, int m) {
   return L;
 }
 
-void Launch::add(const Job& j0, int grid_m, int esz) {
+void Launch::add(const Job& j0, int grid_m, int esz, int group) {
   Job j = j0;
   j.nti = j.ntj = tiles_per_axis(grid_m, esz);
   const uint32_t idx = (uint32_t)jobs.size();
+  if (jobs.empty() || group != last_group) seg_start.push_back((int)tiles.size());
+  last_group = group;
   jobs.push_back(j);
   for (int t = 0; t < j.nti * j.ntj; ++t) tiles.push_back((idx << 16) | (uint32_t)t);
   tiles_upto.push_back((int)tiles.size());
   m_max = std::max(m_max, j.m);
 }
 
+void xcd_order(std::vector<uint32_t>& tiles, size_t s0, size_t s1, int nxcd) {
+  const size_t n = s1 - s0;
+  if (n < 2 || nxcd < 2) return;
+  std::vector<uint32_t> run(tiles.begin() + s0, tiles.begin() + s1);
+  // chunk start of each XCD: positions p in [s0, s1) with p % nxcd == x
+  std::vector<size_t> cnt(nxcd, 0), next(nxcd, 0);
+  for (size_t p = s0; p < s1; ++p) ++cnt[p % nxcd];
+  size_t acc = 0;
+  for (int x = 0; x < nxcd; ++x) {
+    next[x] = acc;
+    acc += cnt[x];
+  }
+  for (size_t p = s0; p < s1; ++p) tiles[p] = run[next[p % nxcd]++];
+}
+
 int Launch::upload(dbl_ctx* ctx, LaunchArgs& la) {
   void *dj = nullptr, *dt = nullptr;
-  int rc = stage2(ctx, jobs.data(), jobs.size() * sizeof(Job), tiles.data(),
-                  tiles.size() * sizeof(uint32_t), &dj, &dt);
+  std::vector<uint32_t> order = tiles;
+  for (size_t q = 0; q < seg_start.size(); ++q) {
+    const size_t s1 = q + 1 < seg_start.size() ? (size_t)seg_start[q + 1] : order.size();
+    xcd_order(order, (size_t)seg_start[q], s1, XCDS);
+  }
+  int rc = stage2(ctx, jobs.data(), jobs.size() * sizeof(Job), order.data(),
+                  order.size() * sizeof(uint32_t), &dj, &dt);
   if (rc) return rc;
   la.jobs = static_cast<const Job*>(dj);
   la.tiles = static_cast<const uint32_t*>(dt);
@@ -795,8 +817,8 @@ int run_lsqr(dbl_ctx* ctx, std::vector<Slot*> lq) {
       ja.pw = PA[i & 1];
       Launch& B = i == 1 ? bF[gk] : bP[i & 1][gk];
       Launch& A = i == 1 ? aF[gk] : aP[i & 1][gk];
-      B.add(jb, mi, (int)s->esz);
-      A.add(ja, mi, (int)s->esz);
+      B.add(jb, mi, (int)s->esz, s->opts.k_in);
+      A.add(ja, mi, (int)s->esz, s->opts.k_in);
     }
     Job jf = j;
     jf.i0 = s->opts.k_in;
@@ -1113,11 +1135,11 @@ int engine_step(dbl_ctx* ctx, std::vector<Slot*>& slots) {
         a.pw = PL.q;
         a.pr[0] = PL.s[par];
         a.pr[1] = PL.s[1 - par];
-        p1[par][gk].add(a, a.m, (int)s->esz);
+        p1[par][gk].add(a, a.m, (int)s->esz, s->opts.k_in);
         if (par == 0) {
           Job a0 = a;
           a0.flags |= F_FIRST;  // iteration 0: beta = 0
-          p1f[gk].add(a0, a0.m, (int)s->esz);
+          p1f[gk].add(a0, a0.m, (int)s->esz, s->opts.k_in);
         }
         Job b = j;
         b.v[V_PB] = s->P[1 - par];
@@ -1128,7 +1150,7 @@ int engine_step(dbl_ctx* ctx, std::vector<Slot*>& slots) {
         b.pr[0] = PL.q;
         b.pr[1] = PL.s[par];
         b.pw = PL.s[1 - par];
-        p2[par][gk].add(b, b.m, (int)s->esz);
+        p2[par][gk].add(b, b.m, (int)s->esz, s->opts.k_in);
       }
       kin[gk].push_back(s->opts.k_in);
     }

@@ -127,16 +127,30 @@ size_t small_lds_bytes(const dbl_ctx* ctx, const dbl_op* op, int level, bool irl
 // Algorithmic bytes of one job (each operand read or written once).
 double job_bytes(const char* kernel, const Job& j, int precision);
 
-// Jobs of one launch plus its tile table.
+// Tile table of one launch.  Jobs are added in order; `group` separates jobs
+// that a prefix launch (tiles_upto) may cut between (the CGLS and LSQR
+// phases launch the prefix of jobs with the most iterations left).  At
+// upload the table is reordered within each run of equal group so that the
+// blocks that the dispatcher sends to one XCD (block ids equal mod 8) take a
+// contiguous run of tiles: neighbouring tiles then share that XCD's L2 for
+// their halos.  Every block still finds its job and tile in the table, so
+// results do not depend on the order.
 struct Launch {
   std::vector<Job> jobs;
   std::vector<uint32_t> tiles;
   std::vector<int> tiles_upto;  // tiles after each job (prefix launches)
+  std::vector<int> seg_start;   // first tile of each run of equal group
+  int last_group = 0;
   int m_max = 0;
-  void add(const Job& j, int grid_m, int esz);
+  void add(const Job& j, int grid_m, int esz, int group = 0);
   int upload(dbl_ctx* ctx, LaunchArgs& la);
   bool empty() const { return jobs.empty(); }
 };
+
+// Reorder tiles[s0, s1) so that positions p with p % nxcd == x hold the x-th
+// contiguous chunk of the run (chunk x has as many tiles as there are such
+// positions).  Exposed for the host tests.
+void xcd_order(std::vector<uint32_t>& tiles, size_t s0, size_t s1, int nxcd);
 
 int tiles_per_axis(int grid_m, int esz);
 // FP64 partial-sum slots a job on an m x m grid may need (CGLS, GCV grid).
