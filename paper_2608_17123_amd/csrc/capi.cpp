@@ -171,6 +171,7 @@ int dbl_destroy(dbl_ctx* ctx) {
   if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
   for (auto& b : ctx->retired) (void)hipHostFree(b.first);
   if (ctx->h_rc) (void)hipHostFree(ctx->h_rc);
+  if (ctx->h_gflag) (void)hipHostFree(ctx->h_gflag);
   for (hipEvent_t e : ctx->prof_pool) (void)hipEventDestroy(e);
   if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
   if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);

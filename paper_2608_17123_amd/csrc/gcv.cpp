@@ -5,6 +5,7 @@
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -14,9 +15,12 @@ namespace dbl {
 
 namespace {
 
-enum : int { G_B = 0, G_W, G_C1, G_C2, G_IN, G_TMP, G_BH, G_E, G_SYM, G_LAM, G_KINT, G_DCT };
+enum : int { G_B = 0, G_W, G_C1, G_C2, G_IN, G_TMP, G_BH, G_E, G_SYM, G_LAM, G_KINT, G_DCT,
+             G_DONE };
 
 const int BRENT_MAXIT = 100;
+const int BRENT_CHECK0 = 16;  // Brent launches before the host first reads the done flags
+const int BRENT_CHECK = 8;    // launches between later reads
 const double BRENT_XTOL = 1e-8;
 
 int ensure_dct(dbl_ctx* ctx, int m, double** out) {
@@ -325,6 +329,26 @@ int gcv_run(dbl_ctx* ctx, std::vector<GcvReq>& reqs) {
   // 3. per-frequency data and grid bounds; 4. grid; 5. Brent (levels of at
   //    most 64 x 64: 4 and 5 in one block per job)
   {
+    // done flags of the multi-launch Brent jobs (one FP64 per job)
+    int nb = 0;
+    for (size_t q = 0; q < reqs.size(); ++q) nb += base[q].m > 64 ? 1 : 0;
+    if (nb > ctx->gflag_cap) {
+      if ((rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "sync"))) return rc;
+      if (ctx->d_gflag) dfree(ctx, ctx->d_gflag);
+      if (ctx->h_gflag) (void)hipHostFree(ctx->h_gflag);
+      ctx->d_gflag = ctx->h_gflag = nullptr;
+      ctx->gflag_cap = 0;
+      const int cap = std::max(64, 2 * nb);
+      void* d = nullptr;
+      if ((rc = dmalloc(ctx, (size_t)cap * 8, &d))) return rc;
+      ctx->d_gflag = static_cast<double*>(d);
+      if ((rc = hip_check(ctx, hipHostMalloc((void**)&ctx->h_gflag, (size_t)cap * 8,
+                                             hipHostMallocDefault),
+                          "hipHostMalloc")))
+        return rc;
+      ctx->gflag_cap = cap;
+    }
+    int ib = 0;
     Launch Ld, Lg, Lf, Lb[2], Ls[2];
     for (size_t q = 0; q < reqs.size(); ++q) {
       const PartLayout& PL = PLs[q];
@@ -363,8 +387,10 @@ int gcv_run(dbl_ctx* ctx, std::vector<GcvReq>& reqs) {
         b.p0 = BRENT_XTOL;
         b.pr[0] = PL.gb[par];
         b.pw = PL.gb[1 - par];
+        b.v[G_DONE] = ctx->d_gflag + ib;
         Lb[par].add(b, b.m, 4);
       }
+      ++ib;
     }
     if ((rc = run(launch_gcv_data, Ld, "gcv_data"))) return rc;
     for (int c = 0; c < 2; ++c)
@@ -379,12 +405,28 @@ int gcv_run(dbl_ctx* ctx, std::vector<GcvReq>& reqs) {
     LaunchArgs lb[2];
     for (int par = 0; par < 2; ++par)
       if ((rc = Lb[par].upload(ctx, lb[par]))) return rc;
-    // one start evaluation, up to BRENT_MAXIT steps, one final reduction
-    for (int it = 0; it < BRENT_MAXIT + 2; ++it)
-      if ((rc = hip_check(ctx, timed(ctx, "gcv_brent", 0.0,
-                                     [&] { return launch_gcv_brent(lb[it & 1]); }),
-                          "gcv brent")))
-        return rc;
+    // one start evaluation, up to BRENT_MAXIT steps, one final reduction.
+    // Every launch leaves each job's done flag; after BRENT_CHECK0 launches,
+    // and every BRENT_CHECK after that, the host reads them and stops once
+    // all are set (the launches left would only copy the final states).
+    int it = 0;
+    while (it < BRENT_MAXIT + 2) {
+      const int upto = std::min(BRENT_MAXIT + 2, it == 0 ? BRENT_CHECK0 : it + BRENT_CHECK);
+      for (; it < upto; ++it)
+        if ((rc = hip_check(ctx, timed(ctx, "gcv_brent", 0.0,
+                                       [&] { return launch_gcv_brent(lb[it & 1]); }),
+                            "gcv brent")))
+          return rc;
+      if (it >= BRENT_MAXIT + 2) break;
+      rc = hip_check(ctx, hipMemcpyAsync(ctx->h_gflag, ctx->d_gflag, (size_t)ib * 8,
+                                         hipMemcpyDeviceToHost, ctx->stream),
+                     "read Brent flags");
+      if (!rc) rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "sync Brent flags");
+      if (rc) return rc;
+      bool all = true;
+      for (int q = 0; q < ib; ++q) all = all && ctx->h_gflag[q] != 0.0;
+      if (all) break;
+    }
   }
   return DBL_OK;
 }

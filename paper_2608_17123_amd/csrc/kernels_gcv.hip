@@ -48,7 +48,10 @@ enum : int {
   G_SYM = 8,   // FP64 n: symbol a_k
   G_LAM = 9,   // FP64 m: l(k)
   G_KINT = 10, // FP64 interior kernel (2r0+1) x (2r1+1), column-major
-  G_DCT = 11   // FP64 m x m DCT-II matrix, column-major
+  G_DCT = 11,  // FP64 m x m DCT-II matrix, column-major
+  G_DONE = 12  // optional FP64 flag, written by every Brent step: 1 once the
+               // job's minimisation has ended (the host stops launching steps
+               // when every flag of a launch reads 1)
 };
 
 constexpr int DBL_GCV_GRID_MAX_DEV = 64;
@@ -555,12 +558,15 @@ __global__ void __launch_bounds__(NTHREADS) k_gcv_brent(const Job* __restrict__ 
   const double* in = sc + S_BR + par * BR_SIZE;
   double* out = sc + S_BR + (1 - par) * BR_SIZE;
   const bool owner = (tix == 0 && threadIdx.x == 0);
+  double* dflag = static_cast<double*>(job->v[G_DONE]);
   double st[BR_SIZE];
 #pragma unroll
   for (int q = 0; q < BR_SIZE; ++q) st[q] = in[q];
   if (st[BR_DONE] != 0.0) {
-    if (owner)
+    if (owner) {
       for (int q = 0; q < BR_SIZE; ++q) out[q] = st[q];
+      if (dflag) *dflag = 1.0;
+    }
     return;
   }
   const int m = job->m, n = m * m, nt = job->nti * job->ntj;
@@ -582,6 +588,7 @@ __global__ void __launch_bounds__(NTHREADS) k_gcv_brent(const Job* __restrict__ 
       sc[S_SQRTG] = sqrt(g);
       sc[S_G_FBEST] = st[BR_FX];
     }
+    if (dflag) *dflag = done ? 1.0 : 0.0;
   }
   if (done) return;
   // evaluate GCV at U: per-tile partials (residual sum, trace)

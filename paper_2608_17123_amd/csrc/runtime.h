@@ -59,6 +59,10 @@ struct dbl_ctx {
   double* d_rc = nullptr;
   double* h_rc = nullptr;
   int rc_cap = 0;
+  // done flags of the multi-launch Brent minimisations of one GCV batch
+  double* d_gflag = nullptr;
+  double* h_gflag = nullptr;
+  int gflag_cap = 0;
 };
 
 struct dbl_op {
