@@ -150,9 +150,13 @@ __global__ void __launch_bounds__(NTHREADS, (waves_per_simd<T, RB>())) k_cgls_p1
 }
 
 // --------------------------------------------------------------- phase 2 --
+constexpr int P2_V = 4;  // outputs per item of the separable convolution
+// Launches of more tiles than this (5 resident 256-thread blocks on each of
+// 256 CUs at the unconstrained register use) take k_cgls_p2_wide.
+constexpr int P2_WIDE_TILES = 5 * 256;
 template <typename T, typename S, int RB, bool SEP>
-__global__ void __launch_bounds__(NTHREADS, (waves_per_simd<T, RB>())) k_cgls_p2(const Job* __restrict__ jobs,
-                                                      const uint32_t* __restrict__ tiles) {
+__device__ __forceinline__ void cgls_p2_body(const Job* __restrict__ jobs,
+                                             const uint32_t* __restrict__ tiles) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red[8];
   __shared__ double bc;
@@ -264,15 +268,15 @@ __global__ void __launch_bounds__(NTHREADS, (waves_per_simd<T, RB>())) k_cgls_p2
     __syncthreads();
   };
   if constexpr (SEP) {
-    conv_tile<T, RB, SEP>(
-        Xs, H, scratch, op, true, i0, j0, TI, TJ, m,
-        [&](int i, int j, T v) {
-          const size_t g = (i0 + i) + (size_t)(j0 + j) * m;
-          const T sv = rtv<S>(v + LT[i + j * TI]);
-          stv(s, g, sv);
-          accs += (double)sv * (double)sv;
-        },
-        [&] { grad_part(Xs); });
+    auto epi2 = [&](int i, int j, T v) {
+      const size_t g = (i0 + i) + (size_t)(j0 + j) * m;
+      const T sv = rtv<S>(v + LT[i + j * TI]);
+      stv(s, g, sv);
+      accs += (double)sv * (double)sv;
+    };
+    auto hook = [&] { grad_part(Xs); };
+    conv_tile<T, RB, SEP, decltype(epi2), decltype(hook), P2_V>(Xs, H, scratch, op, true, i0, j0,
+                                                                 TI, TJ, m, epi2, hook);
   } else {
     grad_part(reinterpret_cast<T*>(scratch) + (2 * H + 1) * (2 * H + 1) * 2);
     conv_tile<T, RB, SEP>(Xs, H, scratch, op, true, i0, j0, TI, TJ, m, [&](int i, int j, T v) {
@@ -284,6 +288,21 @@ __global__ void __launch_bounds__(NTHREADS, (waves_per_simd<T, RB>())) k_cgls_p2
   }
   double vv[2] = {accs, accr};
   put_partials<2>(job->pw, tix, vv, red);
+}
+
+// Phase 2 compiled twice: for launches that fill the chip (more tiles than
+// are resident at the unconstrained occupancy) with the register bound of
+// p2_waves, so that all tiles are resident in one round; otherwise without
+// it (more registers, shorter per-block latency for small launches).
+template <typename T, typename S, int RB, bool SEP>
+__global__ void __launch_bounds__(NTHREADS, (waves_per_simd<T, RB>()))
+    k_cgls_p2(const Job* __restrict__ jobs, const uint32_t* __restrict__ tiles) {
+  cgls_p2_body<T, S, RB, SEP>(jobs, tiles);
+}
+template <typename T, typename S, int RB, bool SEP>
+__global__ void __launch_bounds__(NTHREADS, (p2_waves<T, RB>()))
+    k_cgls_p2_wide(const Job* __restrict__ jobs, const uint32_t* __restrict__ tiles) {
+  cgls_p2_body<T, S, RB, SEP>(jobs, tiles);
 }
 
 // Residual norm after the last CGLS iteration (one block per job): sums the
@@ -494,7 +513,11 @@ hipError_t launch_cgls_p1(const LaunchArgs& la, int precision, int sep, int rb, 
 
 hipError_t launch_cgls_p2(const LaunchArgs& la, int precision, int sep, int rb, int H) {
   if (precision == 1) DISPATCH_STENCIL_S(k_cgls_p2, double, double, la, sep, rb, H);
+  else if (la.ntiles > P2_WIDE_TILES && precision == 2)
+    DISPATCH_STENCIL_S(k_cgls_p2_wide, float, bf16s, la, sep, rb, H);
   else if (precision == 2) DISPATCH_STENCIL_S(k_cgls_p2, float, bf16s, la, sep, rb, H);
+  else if (la.ntiles > P2_WIDE_TILES)
+    DISPATCH_STENCIL_S(k_cgls_p2_wide, float, float, la, sep, rb, H);
   else DISPATCH_STENCIL_S(k_cgls_p2, float, float, la, sep, rb, H);
   return hipGetLastError();
 }

@@ -27,13 +27,14 @@ __device__ __forceinline__ int xs_elems(int H, int TI, int TJ) {
 // tile Xs (separable: between the two passes; general: after an extra sync,
 // which requires a copy of the input -- the general path instead runs the
 // hook before the convolution, so it must not overwrite Xs there).
-template <typename T, int RB, bool SEP, class Epi, class Hook = NoHook>
+template <typename T, int RB, bool SEP, class Epi, class Hook = NoHook,
+          int V = TileCfg<T>::V>
 __device__ __forceinline__ void conv_tile(const T* Xs, int H, void* scratch, const LevelOp& op,
                                           bool adj, int i0, int j0, int TI, int TJ, int m,
                                           Epi epi, Hook hook = Hook()) {
   if constexpr (SEP) {
-    sep_tile<T, RB>(Xs, H, static_cast<T*>(scratch), adj ? op.a0 : op.f0, adj ? op.a1 : op.f1,
-                    i0, j0, TI, TJ, m, epi, hook);
+    sep_tile<T, RB, NTHREADS, V>(Xs, H, static_cast<T*>(scratch), adj ? op.a0 : op.f0,
+                                 adj ? op.a1 : op.f1, i0, j0, TI, TJ, m, epi, hook);
   } else {
     T* s_v = static_cast<T*>(scratch);
     short2* s_e = reinterpret_cast<short2*>(s_v + (2 * H + 1) * (2 * H + 1));
@@ -42,12 +43,18 @@ __device__ __forceinline__ void conv_tile(const T* Xs, int H, void* scratch, con
 }
 
 // Minimum waves per SIMD the CGLS phase kernels are compiled for (one wave
-// per SIMD per 256-thread block): 3 for FP32, 2 for FP64.  A target of 6 for
-// the FP32 radius-8 phases (80 VGPRs) makes a 1536-tile launch resident in
-// one round but spills phase 2, and measured slower end to end.
+// per SIMD per 256-thread block).  Phase 1: 3 (FP32) or 2 (FP64); a tighter
+// bound costs it latency where launches are small.  Phase 2: 6 for FP32 up
+// to radius bucket 8 (77 VGPRs with its 4-output convolution window, no
+// spills), so the 1536 tiles of a 24-image 256 x 256 launch are resident in
+// one round; else as phase 1.
 template <typename T, int RB>
 constexpr int waves_per_simd() {
   return sizeof(T) == 4 ? 3 : 2;
+}
+template <typename T, int RB>
+constexpr int p2_waves() {
+  return sizeof(T) == 4 ? (RB <= 8 ? 6 : 3) : 2;
 }
 
 template <typename T> __device__ __forceinline__ T* vp(const Job* j, int k) {
