@@ -72,9 +72,13 @@ __global__ void __launch_bounds__(NTHREADS) k_cgls_init(const Job* __restrict__ 
 }
 
 // --------------------------------------------------------------- phase 1 --
+constexpr int P2_V = 4;  // outputs per item of the separable convolution
+// Launches of more tiles than this (5 resident 256-thread blocks on each of
+// 256 CUs at the unconstrained register use) take the _wide phase kernels.
+constexpr int P2_WIDE_TILES = 5 * 256;
 template <typename T, typename S, int RB, bool SEP>
-__global__ void __launch_bounds__(NTHREADS, (waves_per_simd<T, RB>())) k_cgls_p1(const Job* __restrict__ jobs,
-                                                      const uint32_t* __restrict__ tiles) {
+__device__ __forceinline__ void cgls_p1_body(const Job* __restrict__ jobs,
+                                             const uint32_t* __restrict__ tiles) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red[8];
   __shared__ double bc;
@@ -149,11 +153,21 @@ __global__ void __launch_bounds__(NTHREADS, (waves_per_simd<T, RB>())) k_cgls_p1
   put_partials<1>(job->pw, tix, vv, red);
 }
 
+// Phase 1 compiled twice, as phase 2 below: k_cgls_p1_wide (register bound
+// of 6 waves per SIMD for FP32 up to radius bucket 8: 78 VGPRs, no spills)
+// for launches of more than P2_WIDE_TILES tiles, k_cgls_p1 otherwise.
+template <typename T, typename S, int RB, bool SEP>
+__global__ void __launch_bounds__(NTHREADS, (waves_per_simd<T, RB>()))
+    k_cgls_p1(const Job* __restrict__ jobs, const uint32_t* __restrict__ tiles) {
+  cgls_p1_body<T, S, RB, SEP>(jobs, tiles);
+}
+template <typename T, typename S, int RB, bool SEP>
+__global__ void __launch_bounds__(NTHREADS, (p2_waves<T, RB>()))
+    k_cgls_p1_wide(const Job* __restrict__ jobs, const uint32_t* __restrict__ tiles) {
+  cgls_p1_body<T, S, RB, SEP>(jobs, tiles);
+}
+
 // --------------------------------------------------------------- phase 2 --
-constexpr int P2_V = 4;  // outputs per item of the separable convolution
-// Launches of more tiles than this (5 resident 256-thread blocks on each of
-// 256 CUs at the unconstrained register use) take k_cgls_p2_wide.
-constexpr int P2_WIDE_TILES = 5 * 256;
 template <typename T, typename S, int RB, bool SEP>
 __device__ __forceinline__ void cgls_p2_body(const Job* __restrict__ jobs,
                                              const uint32_t* __restrict__ tiles) {
@@ -506,7 +520,11 @@ struct Dummy {};
 
 hipError_t launch_cgls_p1(const LaunchArgs& la, int precision, int sep, int rb, int H) {
   if (precision == 1) DISPATCH_STENCIL_S(k_cgls_p1, double, double, la, sep, rb, H);
+  else if (la.ntiles > P2_WIDE_TILES && precision == 2)
+    DISPATCH_STENCIL_S(k_cgls_p1_wide, float, bf16s, la, sep, rb, H);
   else if (precision == 2) DISPATCH_STENCIL_S(k_cgls_p1, float, bf16s, la, sep, rb, H);
+  else if (la.ntiles > P2_WIDE_TILES)
+    DISPATCH_STENCIL_S(k_cgls_p1_wide, float, float, la, sep, rb, H);
   else DISPATCH_STENCIL_S(k_cgls_p1, float, float, la, sep, rb, H);
   return hipGetLastError();
 }
