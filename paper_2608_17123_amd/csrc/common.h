@@ -3,7 +3,8 @@
 // Device data model
 // -----------------
 // * Every kernel launch covers a list of jobs (one job = one image at one
-//   level) cut into TILE x TILE output tiles.  Block b of a launch handles tile
+//   level) cut into square output tiles (tile_edge(m) pixels a side; the
+//   FP64 DCT products use 64 x 64).  Block b of a launch handles tile
 //   table entry b: job index in the upper 16 bits, tile index within the job in
 //   the lower 16 bits.  A single solve is a launch with one job; a batch or a
 //   server step is the same launch with many jobs.
@@ -25,8 +26,13 @@
 
 namespace dbl {
 
-constexpr int TILE = 64;
 constexpr int NTHREADS = 256;
+// Edge of the output tiles of the image and gradient kernels on an m x m
+// grid: the whole grid below 32, else 32.  (16 x 16 tiles on grids of 64 and
+// 128 quadruple the blocks but measured slower in batched launches: 4x halo
+// reads per output against 2.25x, and idle threads in the convolution
+// passes.)  Non-decreasing in m, so the largest grid of a launch sizes its LDS.
+__host__ __device__ constexpr int tile_edge(int m) { return m < 32 ? m : 32; }
 // XCDs of the device: the dispatcher hands workgroup ids to them round-robin.
 constexpr int XCDS = 8;
 constexpr int MAX_R = 16;

@@ -245,8 +245,7 @@ __global__ void __launch_bounds__(NTHREADS) k_dtransfer(const Job* __restrict__ 
 
 template <typename T>
 static hipError_t launch_apply(const LaunchArgs& la, int sep, int rb, int H) {
-  const int TS = TileCfg<T>::TS;
-  const int ts = la.m_max < TS ? la.m_max : TS;
+  const int ts = tile_edge(la.m_max);
   if (sep) {
     const size_t lds = sizeof(T) * sep_lds_elems(ts, ts, rb);
     switch (rb) {

@@ -492,8 +492,7 @@ struct Dummy {};
 
 #define DISPATCH_STENCIL(KERNEL, T, la, sep, rb, H, extra_lds)                           \
   do {                                                                                 \
-    const int TS_ = TileCfg<T>::TS;                                                    \
-    const int ts_ = (la).m_max < TS_ ? (la).m_max : TS_;                               \
+    const int ts_ = tile_edge((la).m_max);                                             \
     if (sep) {                                                                         \
       const size_t lds_ = sizeof(T) * sep_lds_elems(ts_, ts_, rb);                     \
       switch (rb) {                                                                    \

@@ -66,8 +66,7 @@ template <typename T> __device__ __forceinline__ T* vp(const Job* j, int k) {
 // Same, for kernels that also take the storage type S of the state vectors.
 #define DISPATCH_STENCIL_S(KERNEL, T, S, la, sep, rb, H)                           \
   do {                                                                                 \
-    const int TS_ = TileCfg<T>::TS;                                                    \
-    const int ts_ = (la).m_max < TS_ ? (la).m_max : TS_;                               \
+    const int ts_ = tile_edge((la).m_max);                                             \
     if (sep) {                                                                         \
       const size_t lds_ = sizeof(T) * sep_lds_elems(ts_, ts_, rb);                     \
       switch (rb) {                                                                    \

@@ -212,10 +212,10 @@ double job_bytes(const char* k, const Job& j, int prec) {
 }
 
 // Tiles per axis of a launch over an m x m grid.  Image, gradient and GCV
-// kernels use 32 x 32 tiles (esz 4 or 8); esz 0 selects the 64 x 64 output
-// tiles of the FP64 GEMM.
+// kernels use tile_edge(m) tiles (esz 4 or 8); esz 0 selects the 64 x 64
+// output tiles of the FP64 GEMM.
 int tiles_per_axis(int grid_m, int esz) {
-  const int ts = esz == 0 ? 64 : 32;
+  const int ts = esz == 0 ? 64 : tile_edge(grid_m);
   return grid_m < ts ? 1 : grid_m / ts;
 }
 

@@ -27,8 +27,8 @@ template <> __device__ __forceinline__ const float* taps2<float>(const Table2D& 
 template <> __device__ __forceinline__ const double* taps2<double>(const Table2D& t) { return t.vd; }
 
 template <typename T> struct TileCfg;
-template <> struct TileCfg<float> { static constexpr int TS = 32; static constexpr int V = 8; };
-template <> struct TileCfg<double> { static constexpr int TS = 32; static constexpr int V = 8; };
+template <> struct TileCfg<float> { static constexpr int V = 8; };
+template <> struct TileCfg<double> { static constexpr int V = 8; };
 
 // Row-major LDS tile (separable kernels): Xs[r * LX + c], r indexes axis 0
 // (rows, i) and c axis 1 (columns, j), both offset by the halo H.
@@ -321,8 +321,7 @@ __device__ __forceinline__ void batched_pixels(int N, LD ld, BODY body) {
 template <typename T>
 __device__ __forceinline__ void tile_geom(int m, int ti, int tj, int& i0, int& j0, int& TI,
                                           int& TJ) {
-  constexpr int TS = TileCfg<T>::TS;
-  TI = TJ = (m < TS) ? m : TS;
+  TI = TJ = tile_edge(m);
   i0 = ti * TI;
   j0 = tj * TJ;
 }
