@@ -55,6 +55,9 @@ enum : int {
 };
 
 constexpr int DBL_GCV_GRID_MAX_DEV = 64;
+// Grid points evaluated per block reduction.  Each point keeps its own
+// summation order, so the values do not depend on this grouping.
+constexpr int GRID_GROUP = 4;
 
 // GCV from the summed terms: spectral resid = gam^2 res; exact resid = bb + res.
 __device__ __forceinline__ double gcv_from(const Job* job, double gam, double res, double tr,
@@ -305,15 +308,19 @@ __global__ void __launch_bounds__(NTHREADS) k_gcv_data(const Job* __restrict__ j
   }
 }
 
-// Per-thread view of the frequencies of one tile (at most 16 per thread).
+// Per-thread view of the frequencies of one tile: at most Q per thread (4
+// for the 32 x 32 tiles of the multi-block kernels, 16 for one block over a
+// grid of up to 64 x 64).  Entry q is frequency threadIdx.x + q * NT of the
+// tile; every index is known at compile time so the arrays stay in registers.
+template <int Q>
 struct FreqRegs {
-  double s[16], lp[16], e[16];
+  double s[Q], lp[Q], e[Q];
   int cnt;
 };
 
-template <int NT = NTHREADS>
+template <int NT = NTHREADS, int Q>
 __device__ __forceinline__ void load_freqs(const Job* job, int i0, int j0, int TI, int TJ,
-                                           FreqRegs& f) {
+                                           FreqRegs<Q>& f) {
   const int m = job->m;
   const double* __restrict__ sym = static_cast<const double*>(job->v[G_SYM]);
   const double* __restrict__ lam = static_cast<const double*>(job->v[G_LAM]);
@@ -322,30 +329,35 @@ __device__ __forceinline__ void load_freqs(const Job* job, int i0, int j0, int T
   const bool exact = job->flags & F_EXACT;
   const double* __restrict__ fv = static_cast<const double*>(job->v[G_BH]);
   f.cnt = 0;
-  for (int o = threadIdx.x; o < TI * TJ; o += NT) {
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int o = threadIdx.x + q * NT;
+    f.s[q] = f.lp[q] = f.e[q] = 0.0;
+    if (o >= TI * TJ) continue;
     const int k0 = i0 + (o & (TI - 1)), k1 = j0 + (o >> (__ffs(TI) - 1));
     const size_t g = k0 + (size_t)k1 * m;
     if (exact) {  // (nu, f, g) in the (s, lp, e) registers
-      f.s[f.cnt] = fmin(fmax(sym[g], 0.0), 1.0);
-      f.lp[f.cnt] = fv[g];
-      f.e[f.cnt] = e[g];
+      f.s[q] = fmin(fmax(sym[g], 0.0), 1.0);
+      f.lp[q] = fv[g];
+      f.e[q] = e[g];
     } else {
       const double a = sym[g];
-      f.s[f.cnt] = a * a;
-      f.lp[f.cnt] = wb2 * (lam[k0] + lam[k1]);
-      f.e[f.cnt] = e[g];
+      f.s[q] = a * a;
+      f.lp[q] = wb2 * (lam[k0] + lam[k1]);
+      f.e[q] = e[g];
     }
-    ++f.cnt;
+    f.cnt = q + 1;
   }
 }
 
-__device__ __forceinline__ void eval_freqs(const Job* job, const FreqRegs& f, double gam,
+template <int Q>
+__device__ __forceinline__ void eval_freqs(const Job* job, const FreqRegs<Q>& f, double gam,
                                            double& res, double& tr) {
   res = 0.0;
   tr = 0.0;
   if (job->flags & F_EXACT) {
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
+    for (int q = 0; q < Q; ++q) {
       if (q < f.cnt) {
         const double nu = f.s[q];
         const double den = nu + gam * (1.0 - nu);
@@ -360,13 +372,49 @@ __device__ __forceinline__ void eval_freqs(const Job* job, const FreqRegs& f, do
     return;
   }
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
+  for (int q = 0; q < Q; ++q) {
     if (q < f.cnt) {
       const double den = f.s[q] + gam * f.lp[q];
       if (den > 0.0) {
         const double inv = 1.0 / den;
         res += f.e[q] * inv * inv;
         tr += f.s[q] * inv;
+      }
+    }
+  }
+}
+
+// eval_freqs at G parameters at once (v[2g], v[2g+1] = res, tr at gam[g]; g
+// with gam[g] < 0 are skipped and left at zero).  Each parameter's terms are
+// added in the same order as by eval_freqs.
+template <int G, int Q>
+__device__ __forceinline__ void eval_freqs_multi(const Job* job, const FreqRegs<Q>& f,
+                                                 const double (&gam)[G], double (&v)[2 * G]) {
+#pragma unroll
+  for (int k = 0; k < 2 * G; ++k) v[k] = 0.0;
+  const bool exact = job->flags & F_EXACT;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    if (q >= f.cnt) break;
+    const double s = f.s[q], lp = f.lp[q], e = f.e[q];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      if (gam[g] < 0.0) continue;
+      if (exact) {
+        const double den = s + gam[g] * (1.0 - s);
+        if (den > 0.0) {
+          const double inv = 1.0 / den;
+          const double y = (lp + gam[g] * e) * inv;
+          v[2 * g] += s * y * y - 2.0 * lp * y;
+          v[2 * g + 1] += s * inv;
+        }
+      } else {
+        const double den = s + gam[g] * lp;
+        if (den > 0.0) {
+          const double inv = 1.0 / den;
+          v[2 * g] += e * inv * inv;
+          v[2 * g + 1] += s * inv;
+        }
       }
     }
   }
@@ -462,7 +510,8 @@ __device__ __forceinline__ void brent_start(double* st, double tlo, double thi, 
 // Writes 2 partials (residual sum, trace) per grid point per tile.
 __global__ void __launch_bounds__(NTHREADS) k_gcv_grid(const Job* __restrict__ jobs,
                                                        const uint32_t* __restrict__ tiles) {
-  __shared__ double red[2 * 4];
+  __shared__ double red[2 * GRID_GROUP * 4];
+  __shared__ double gam_s[DBL_GCV_GRID_MAX_DEV];
   __shared__ double bl, bh_;
   const Job* job; int ti, tj, tix;
   decode_tile(jobs, tiles, job, ti, tj, tix);
@@ -494,20 +543,28 @@ __global__ void __launch_bounds__(NTHREADS) k_gcv_grid(const Job* __restrict__ j
     job->scal[S_G_TLO] = tlo;
     job->scal[S_G_THI] = thi;
   }
-  FreqRegs f;
+  for (int p = threadIdx.x; p < npts; p += NTHREADS)
+    gam_s[p] = pow(10.0, tlo + (thi - tlo) * p / (npts - 1));
+  FreqRegs<4> f;  // 32 x 32 tile over 256 threads
   load_freqs(job, i0, j0, TI, TJ, f);
-  for (int p = 0; p < npts; ++p) {
-    const double t = tlo + (thi - tlo) * p / (npts - 1);
-    double res, tr;
-    eval_freqs(job, f, pow(10.0, t), res, tr);
-    res = wave_sum(res);
-    tr = wave_sum(tr);
+  __syncthreads();
+  for (int p0 = 0; p0 < npts; p0 += GRID_GROUP) {
+    double v[2 * GRID_GROUP], gg[GRID_GROUP];
+#pragma unroll
+    for (int g = 0; g < GRID_GROUP; ++g) gg[g] = p0 + g < npts ? gam_s[p0 + g] : -1.0;
+    eval_freqs_multi(job, f, gg, v);
+#pragma unroll
+    for (int k = 0; k < 2 * GRID_GROUP; ++k) v[k] = wave_sum(v[k]);
     __syncthreads();
-    if (lane == 0) { red[wid] = res; red[4 + wid] = tr; }
+    if (lane == 0)
+#pragma unroll
+      for (int k = 0; k < 2 * GRID_GROUP; ++k) red[k * 4 + wid] = v[k];
     __syncthreads();
-    if (threadIdx.x == 0) {
+    const int g = threadIdx.x;
+    if (g < GRID_GROUP && p0 + g < npts) {
+      const int p = p0 + g;
       double a = 0.0, b = 0.0;
-      for (int w = 0; w < 4; ++w) { a += red[w]; b += red[4 + w]; }
+      for (int w = 0; w < 4; ++w) { a += red[(2 * g) * 4 + w]; b += red[(2 * g + 1) * 4 + w]; }
       job->pw[(size_t)tix * 2 * npts + 2 * p] = a;
       job->pw[(size_t)tix * 2 * npts + 2 * p + 1] = b;
     }
@@ -594,7 +651,7 @@ __global__ void __launch_bounds__(NTHREADS) k_gcv_brent(const Job* __restrict__ 
   // evaluate GCV at U: per-tile partials (residual sum, trace)
   int i0, j0, TI, TJ;
   tile_geom<float>(m, ti, tj, i0, j0, TI, TJ);
-  FreqRegs f;
+  FreqRegs<4> f;  // 32 x 32 tile over 256 threads
   load_freqs(job, i0, j0, TI, TJ, f);
   double res, tr;
   eval_freqs(job, f, pow(10.0, st[BR_U]), res, tr);
@@ -615,8 +672,9 @@ __global__ void __launch_bounds__(NTHREADS) k_gcv_brent(const Job* __restrict__ 
 template <int NT>
 __global__ void __launch_bounds__(NT) k_gcv_solo(const Job* __restrict__ jobs,
                                                  const uint32_t* __restrict__ tiles) {
-  __shared__ double red[2 * (NT / 64)];
+  __shared__ double red[2 * GRID_GROUP * (NT / 64)];
   __shared__ double vals[DBL_GCV_GRID_MAX_DEV];
+  __shared__ double gam_s[DBL_GCV_GRID_MAX_DEV];
   const Job* job = jobs + (tiles[blockIdx.x] >> 16);
   double* sc = job->scal;
   const int m = job->m, n = m * m, npts = job->i0, nt = job->i1;
@@ -637,7 +695,7 @@ __global__ void __launch_bounds__(NT) k_gcv_solo(const Job* __restrict__ jobs,
   __syncthreads();
   for (int w = 0; w < NW; ++w) { lo = fmin(lo, red[w]); hi = fmax(hi, red[NW + w]); }
   const double thi = hi, tlo = fmax(lo, hi - 14.0);
-  FreqRegs f;
+  FreqRegs<64 * 64 / NT> f;
   load_freqs<NT>(job, 0, 0, m, m, f);
   auto gcv_at = [&](double t) {
     double v[2];
@@ -645,12 +703,21 @@ __global__ void __launch_bounds__(NT) k_gcv_solo(const Job* __restrict__ jobs,
     block_allsum<2, NT>(v, red);
     return gcv_from(job, pow(10.0, t), v[0], v[1], n);
   };
-  for (int p = 0; p < npts; ++p) {
-    const double val = gcv_at(tlo + (thi - tlo) * p / (npts - 1));
-    if (threadIdx.x == 0) {
-      vals[p] = val;
-      sc[S_GRID + p] = val;
-    }
+  for (int p = threadIdx.x; p < npts; p += NT)
+    gam_s[p] = pow(10.0, tlo + (thi - tlo) * p / (npts - 1));
+  __syncthreads();
+  for (int p0 = 0; p0 < npts; p0 += GRID_GROUP) {
+    double v[2 * GRID_GROUP], gg[GRID_GROUP];
+#pragma unroll
+    for (int g = 0; g < GRID_GROUP; ++g) gg[g] = p0 + g < npts ? gam_s[p0 + g] : -1.0;
+    eval_freqs_multi(job, f, gg, v);
+    block_allsum<2 * GRID_GROUP, NT>(v, red);
+    if (threadIdx.x == 0)
+      for (int g = 0; g < GRID_GROUP && p0 + g < npts; ++g) {
+        const double val = gcv_from(job, gam_s[p0 + g], v[2 * g], v[2 * g + 1], n);
+        vals[p0 + g] = val;
+        sc[S_GRID + p0 + g] = val;
+      }
   }
   __syncthreads();
   int jb = 0;
@@ -708,9 +775,13 @@ hipError_t launch_gcv_add_dtd(double* M, const void* w, int precision, int m,
   return hipGetLastError();
 }
 
+// Threads of the one-block GCV: 8 frequencies of a 64 x 64 grid per thread,
+// all in registers.
+constexpr int SOLO_NT = 512;
+
 hipError_t launch_gcv_solo(const LaunchArgs& la) {
-  if (la.m_max > 64) return hipErrorInvalidValue;  // 16 frequencies per thread
-  hipLaunchKernelGGL(k_gcv_solo<NTHREADS>, dim3(la.ntiles), dim3(NTHREADS), 0, la.stream,
+  if (la.m_max > 64) return hipErrorInvalidValue;  // 8 frequencies per thread
+  hipLaunchKernelGGL(k_gcv_solo<SOLO_NT>, dim3(la.ntiles), dim3(SOLO_NT), 0, la.stream,
                      la.jobs, la.tiles);
   return hipGetLastError();
 }
