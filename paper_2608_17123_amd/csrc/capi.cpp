@@ -738,8 +738,9 @@ int dbl_deblur_batch(dbl_ctx* ctx, int count, const dbl_request* reqs, dbl_repor
       rc = slot_report(ctx, &slots[i], &reps[i]);
       reps[i].seconds = ms * 1e-3;
       bool bad = false;
+      // iterations a tolerance skipped are NaN by design; only run ones count
       for (int l = 0; l < slots[i].levels; ++l)
-        for (int k = 0; k < slots[i].opts.k_out; ++k)
+        for (int k = 0; k < reps[i].iters[l]; ++k)
           if (!std::isfinite(reps[i].objective[l][k])) bad = true;
       if (bad) reps[i].status = DBL_ENUMERIC;
     }

@@ -140,8 +140,9 @@ int dbl_server_step(dbl_server* srv, int* active) {
       rc = slot_report(ctx, sl, &f.rep);
       if (rc) return rc;
       f.rep.seconds = t - sl->t_submit;
+      // iterations a tolerance skipped are NaN by design; only run ones count
       for (int l = 0; l < sl->levels; ++l)
-        for (int k = 0; k < sl->opts.k_out; ++k)
+        for (int k = 0; k < f.rep.iters[l]; ++k)
           if (!std::isfinite(f.rep.objective[l][k])) f.rep.status = DBL_ENUMERIC;
       srv->finished[sl->ticket] = f;
       srv->used -= slot_bytes(sl->req);

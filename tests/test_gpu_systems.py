@@ -370,6 +370,7 @@ def test_tolerance_stop_matches_oracle(ctx, solver, transfer, tol_fine, tol_coar
                                           x_hist=hist))
     print(f"{solver}-{transfer} tol {tol_fine:g}/{tol_coarse:g}: iterations oracle {it_o} "
           f"device {rep['iters']}")
+    assert rep["status"] == 0
     assert rep["iters"] == it_o
     for lv, k in enumerate(it_o):
         rg = np.array(rep["rc"][lv])
@@ -383,3 +384,48 @@ def test_tolerance_stop_matches_oracle(ctx, solver, transfer, tol_fine, tol_coar
     h = host(hist)
     assert np.array_equal(h[it_o[0] - 1], host(x))
     assert np.isnan(h[it_o[0]:]).all()                # slices past the stop untouched
+
+
+def test_server_mixes_stopping_rules_inner_solvers_and_history(ctx):
+    """Continuous batching of requests that differ in stopping rule (fixed
+    counts or the Sec. 5 tolerances), inner solver (CGLS or LSQR) and iterate
+    history: every result, iteration count and history equals the same
+    request solved alone."""
+    items, kw = mixed_requests(k_out=6, count=6)
+    variants = [dict(), dict(tol_fine=1e-3, tol_coarse=1e-6), dict(inner_solver="lsqr"),
+                dict(tol_fine=1e-3, tol_coarse=3e-3, inner_solver="lsqr"), dict(), dict()]
+    alone, hist_alone = [], []
+    for (w, b), v in zip(items, variants):
+        h = torch.full((kw["k_out"], b.numel()), float("nan"), device="cuda")
+        x = torch.zeros_like(b)
+        rep = D.dbl_deblur(ctx, b, w.psf, w.m, w.solver, w.wavelet, w.levels, w.transfer, x,
+                           D.dbl_opts_default(x_hist=h, **kw, **v))
+        assert rep["status"] == 0, (w.name, v)
+        alone.append((host(x), rep))
+        hist_alone.append(host(h))
+    srv = D.dbl_server_create(ctx, max_slots=4)
+    xs = [torch.zeros_like(b) for _, b in items]
+    hs = [torch.full((kw["k_out"], b.numel()), float("nan"), device="cuda") for _, b in items]
+    reqs = [D.make_request(b, x, w.psf, w.m, w.solver, w.wavelet, w.levels, w.transfer,
+                           D.dbl_opts_default(x_hist=h, **kw, **v))
+            for (w, b), x, h, v in zip(items, xs, hs, variants)]
+    tickets, done, pending, step = {}, {}, list(range(len(reqs))), 0
+    while len(done) < len(reqs):
+        if pending:
+            q = pending.pop(0)
+            tickets[D.dbl_server_submit(srv, reqs[q])] = q
+        D.dbl_server_step(srv)
+        for t, q in list(tickets.items()):
+            rep = D.dbl_server_poll(srv, t)
+            if rep is not None:
+                done[q] = rep
+                del tickets[t]
+        step += 1
+        assert step < 500
+    for q in range(len(reqs)):
+        xa, ra = alone[q]
+        assert done[q]["status"] == 0
+        assert done[q]["iters"] == ra["iters"], q
+        assert np.array_equal(host(xs[q]), xa), q
+        assert np.array_equal(host(hs[q]), hist_alone[q], equal_nan=True), q
+    srv.close()
