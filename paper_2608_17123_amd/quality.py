@@ -28,10 +28,17 @@ this module takes the window of the SSIM reference it cites (Gaussian,
 standard deviation 1.5, truncated to 11 x 11, normalised to unit mass) and
 replicates edge pixels outside the image.
 
-Usage: python -m paper_2608_17123_amd.quality [--k-out 10] [--k-in 30] [--out FILE]
+With --sigma the image and noise direction of that workload are blurred
+instead by Gaussian kernels of the given widths (radius ceil(3 sigma), at
+most 16), at the --noise level: Sec. 5 tests sigma = 3.5 and 4.5 at 1% noise.
+
+Usage: python -m paper_2608_17123_amd.quality [--k-out 10] [--k-in 30]
+       [--sigma 3.5 4.5 --noise 0.01] [--out FILE]
 """
 import argparse
+import dataclasses
 import json
+import math
 import sys
 
 import numpy as np
@@ -69,6 +76,19 @@ def ssim(x_true, x, L=1.0, sigma=1.5, radius=5):
     s = ((2 * mu_a * mu_b + c1) * (2 * cov + c2)) / ((mu_a ** 2 + mu_b ** 2 + c1) *
                                                       (var_a + var_b + c2))
     return float(s.mean())
+
+
+def sigma_workloads(sigmas, noise):
+    """The m = 256 workload's image and noise direction under Gaussian blurs of
+    the given widths (radius ceil(3 sigma), capped at 16) at one noise level."""
+    import synth
+    base = synth.config2()[0]
+    out = []
+    for s in sigmas:
+        r = min(16, int(math.ceil(3.0 * s)))
+        out.append(dataclasses.replace(base, name=f"sigma{s:g}", psf=synth.gaussian_psf(s, r),
+                                       noise_level=noise, extra={"sigma": s}))
+    return out
 
 
 def _observed(D, torch, ctx, w):
@@ -117,7 +137,8 @@ def run(k_out=10, k_in=30, workloads=None, solvers=SOLVERS, combos=COMBOS, ctx=N
         rre = (torch.linalg.norm(hist.double() - xt[None, :], dim=1) / nt).tolist()
         hh = hist.double().cpu().numpy()
         ssims = [ssim(w.x_true, hh[k].reshape(w.m, w.m, order="F")) for k in range(k_out)]
-        rows.append({"m": w.m, "noise": w.noise_level, "solver": solver, "combo": label,
+        rows.append({"m": w.m, "noise": w.noise_level, "sigma": w.extra.get("sigma"),
+                     "solver": solver, "combo": label,
                      "levels": levels, "rre": rre, "ssim": ssims,
                      "rre_data": float(torch.linalg.norm(b.double() - xt) / nt),
                      "gamma_fine": rep["gamma"][0]})
@@ -137,17 +158,19 @@ def _iters_to(curve, target):
 def findings(rows):
     """The paper's three qualitative findings, checked per (noise, solver)."""
     out = []
-    for noise in sorted({r["noise"] for r in rows}):
+    cases = sorted({(r.get("sigma") or 0.0, r["noise"]) for r in rows})
+    for sigma, noise in cases:
         for solver in SOLVERS:
             c = {r["combo"]: r["rre"] for r in rows
-                 if r["noise"] == noise and r["solver"] == solver}
+                 if (r.get("sigma") or 0.0, r["noise"]) == (sigma, noise)
+                 and r["solver"] == solver}
             if len(c) < len(COMBOS):
                 continue
             target = c["I"][-1]
             reach = {k: _iters_to(v, target) for k, v in c.items() if k != "I"}
             best = min((v for v in reach.values() if v is not None), default=None)
             out.append({
-                "noise": noise, "solver": solver,
+                "sigma": sigma or None, "noise": noise, "solver": solver,
                 "one_level_final_rre": target,
                 "multilevel_iters_to_match": reach,
                 "multilevel_faster": best is not None and best < len(c["I"]),
@@ -162,21 +185,23 @@ def markdown(res):
     ks = sorted(set(ks))
     out = [f"RRE = ||x - x_true|| / ||x_true|| after fine-level outer iteration k "
            f"(K_out = {res['k_out']} per level, K_in = {res['k_in']}).", "",
-           "| noise | solver | combination | grids | RRE(b) | " +
+           "| blur | noise | solver | combination | grids | RRE(b) | " +
            " | ".join(f"k={k}" for k in ks) + f" | SSIM at k={res['k_out']} |",
-           "|---|---|---|---|---|" + "---|" * len(ks) + "---|"]
+           "|---|---|---|---|---|---|" + "---|" * len(ks) + "---|"]
     for r in res["rows"]:
-        out.append(f"| {r['noise']:.0%} | {r['solver']} | {r['combo']} | {r['levels']} | "
+        blur = f"sigma {r['sigma']:g}" if r.get("sigma") else "c2"
+        out.append(f"| {blur} | {r['noise']:.0%} | {r['solver']} | {r['combo']} | {r['levels']} | "
                    f"{r['rre_data']:.4f} | " +
                    " | ".join(f"{r['rre'][k - 1]:.4f}" for k in ks) +
                    f" | {r['ssim'][-1]:.4f} |")
-    out += ["", "| noise | solver | I final RRE | fine iterations to match it "
+    out += ["", "| blur | noise | solver | I final RRE | fine iterations to match it "
             "(HWT-X, HWT-D, DWT-X, DWT-D) | multilevel faster | Haar better under D | "
-            "Db4 better under X |", "|---|---|---|---|---|---|---|"]
+            "Db4 better under X |", "|---|---|---|---|---|---|---|---|"]
     for f in res["findings"]:
         it = ", ".join(str(f["multilevel_iters_to_match"].get(c) or "-")
                        for c in ("HWT-X", "HWT-D", "DWT-X", "DWT-D"))
-        out.append(f"| {f['noise']:.0%} | {f['solver']} | {f['one_level_final_rre']:.4f} | "
+        blur = f"sigma {f['sigma']:g}" if f.get("sigma") else "c2"
+        out.append(f"| {blur} | {f['noise']:.0%} | {f['solver']} | {f['one_level_final_rre']:.4f} | "
                    f"{it} | {f['multilevel_faster']} | {f['haar_better_under_D']} | "
                    f"{f['db4_better_under_X']} |")
     return "\n".join(out) + "\n"
@@ -186,9 +211,13 @@ def main(argv=None):
     p = argparse.ArgumentParser()
     p.add_argument("--k-out", type=int, default=10)
     p.add_argument("--k-in", type=int, default=30)
+    p.add_argument("--sigma", type=float, nargs="*", default=None,
+                   help="Gaussian blur widths to run instead of the m = 256 workload's")
+    p.add_argument("--noise", type=float, default=0.01, help="noise level with --sigma")
     p.add_argument("--out", default=None, help="also write the markdown tables here")
     a = p.parse_args(argv)
-    res = run(a.k_out, a.k_in)
+    wl = sigma_workloads(a.sigma, a.noise) if a.sigma else None
+    res = run(a.k_out, a.k_in, workloads=wl)
     md = markdown(res)
     sys.stdout.write(md)
     print(json.dumps(res))
