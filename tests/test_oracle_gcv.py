@@ -133,3 +133,43 @@ def test_choose_gamma_matches_exhaustive_search():
     vals = [gcv.gcv_value(10 ** t, data) for t in ts]
     assert f <= min(vals) * (1 + 1e-9)
     assert abs(math.log10(g) - ts[int(np.argmin(vals))]) < 1e-3
+
+
+def _zero_bc_problem(sigma, r, m=32, seed=0):
+    """Zero-boundary blur of a piecewise-constant image (the paper's operator,
+    Sec. 5), 1% noise, with the dense pieces of the Tikhonov problem."""
+    rng = synth.rng_for(99, seed)
+    X = synth.piecewise_constant_image(m, 10, rng)
+    P = synth.gaussian_psf(sigma, r)
+    B0 = ops.blur(X, P)
+    xi = rng.standard_normal((m, m))
+    B = B0 + 0.01 * np.linalg.norm(B0) * xi / np.linalg.norm(xi)
+    H = Hierarchy(P, m, 1, "haar")
+    Ad, Ld = H.dense(0), ops.grad_dense(m)
+    AtA, LtL, Atb = Ad.T @ Ad, Ld.T @ Ld, Ad.T @ ops.vec(B)
+
+    def rre(g):
+        x = np.linalg.solve(AtA + g * LtL, Atb)
+        return float(np.linalg.norm(x - ops.vec(X)) / np.linalg.norm(X))
+
+    best = min(rre(10.0 ** t) for t in np.linspace(-9, 1, 81))
+    return H, Ad, Ld, B, rre, best
+
+
+@pytest.mark.parametrize("sigma,r", [(1.0, 3), (2.0, 6), (2.5, 8)])
+def test_exact_gcv_tracks_rre_optimal_tikhonov(sigma, r):
+    """The exact tier's choice gives a Tikhonov solution within 2% of the best
+    RRE over a fine parameter grid (GCV as a parameter rule, Sec. 3)."""
+    H, Ad, Ld, B, rre, best = _zero_bc_problem(sigma, r)
+    g, _, _ = gcv.choose_gamma(gcv.exact_data(Ad, Ld, ops.vec(B), None))
+    assert rre(g) <= 1.02 * best, (g, rre(g), best)
+
+
+@pytest.mark.xfail(strict=True, reason="known limitation: the DCT surrogate assumes reflexive "
+                   "boundaries; on zero-boundary data at 1% noise it under-regularises once the "
+                   "blur is wide (sigma >= 1.5 here), where the exact tier does not")
+@pytest.mark.parametrize("sigma,r", [(2.0, 6)])
+def test_spectral_gcv_tracks_rre_optimal_tikhonov(sigma, r):
+    H, Ad, Ld, B, rre, best = _zero_bc_problem(sigma, r)
+    g, _, _ = gcv.choose_gamma(gcv.spectral_data(H.interior_stencil(0), B))
+    assert rre(g) <= 1.02 * best, (g, rre(g), best)
