@@ -72,11 +72,14 @@ __global__ void __launch_bounds__(NTHREADS) k_cgls_init(const Job* __restrict__ 
 }
 
 // --------------------------------------------------------------- phase 1 --
-constexpr int P2_V = 4;  // outputs per item of the separable convolution
+// Outputs per item of the separable convolution in each phase kernel (the
+// per-output sums do not depend on it, only register use does).
+constexpr int P1_V_NARROW = 2, P1_V_WIDE = 2;
+constexpr int P2_V_NARROW = 2, P2_V_WIDE = 2;
 // Launches of more tiles than this (5 resident 256-thread blocks on each of
 // 256 CUs at the unconstrained register use) take the _wide phase kernels.
 constexpr int P2_WIDE_TILES = 5 * 256;
-template <typename T, typename S, int RB, bool SEP>
+template <typename T, typename S, int RB, bool SEP, int CV>
 __device__ __forceinline__ void cgls_p1_body(const Job* __restrict__ jobs,
                                              const uint32_t* __restrict__ tiles) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -144,11 +147,13 @@ __device__ __forceinline__ void cgls_p1_body(const Job* __restrict__ jobs,
           acc += (double)qv * (double)qv;
         }
       });
-  conv_tile<T, RB, SEP>(Xs, H, scratch, op, false, i0, j0, TI, TJ, m, [&](int i, int j, T v) {
+  auto epi1 = [&](int i, int j, T v) {
     const T qv = rtv<S>(v);
     stv(q1, (i0 + i) + (size_t)(j0 + j) * m, qv);
     acc += (double)qv * (double)qv;
-  });
+  };
+  conv_tile<T, RB, SEP, decltype(epi1), NoHook, CV>(Xs, H, scratch, op, false, i0, j0, TI, TJ,
+                                                    m, epi1);
   double vv[1] = {acc};
   put_partials<1>(job->pw, tix, vv, red);
 }
@@ -159,16 +164,16 @@ __device__ __forceinline__ void cgls_p1_body(const Job* __restrict__ jobs,
 template <typename T, typename S, int RB, bool SEP>
 __global__ void __launch_bounds__(NTHREADS, (waves_per_simd<T, RB>()))
     k_cgls_p1(const Job* __restrict__ jobs, const uint32_t* __restrict__ tiles) {
-  cgls_p1_body<T, S, RB, SEP>(jobs, tiles);
+  cgls_p1_body<T, S, RB, SEP, P1_V_NARROW>(jobs, tiles);
 }
 template <typename T, typename S, int RB, bool SEP>
 __global__ void __launch_bounds__(NTHREADS, (p2_waves<T, RB>()))
     k_cgls_p1_wide(const Job* __restrict__ jobs, const uint32_t* __restrict__ tiles) {
-  cgls_p1_body<T, S, RB, SEP>(jobs, tiles);
+  cgls_p1_body<T, S, RB, SEP, P1_V_WIDE>(jobs, tiles);
 }
 
 // --------------------------------------------------------------- phase 2 --
-template <typename T, typename S, int RB, bool SEP>
+template <typename T, typename S, int RB, bool SEP, int CV>
 __device__ __forceinline__ void cgls_p2_body(const Job* __restrict__ jobs,
                                              const uint32_t* __restrict__ tiles) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -289,8 +294,8 @@ __device__ __forceinline__ void cgls_p2_body(const Job* __restrict__ jobs,
       accs += (double)sv * (double)sv;
     };
     auto hook = [&] { grad_part(Xs); };
-    conv_tile<T, RB, SEP, decltype(epi2), decltype(hook), P2_V>(Xs, H, scratch, op, true, i0, j0,
-                                                                 TI, TJ, m, epi2, hook);
+    conv_tile<T, RB, SEP, decltype(epi2), decltype(hook), CV>(Xs, H, scratch, op, true, i0, j0,
+                                                               TI, TJ, m, epi2, hook);
   } else {
     grad_part(reinterpret_cast<T*>(scratch) + (2 * H + 1) * (2 * H + 1) * 2);
     conv_tile<T, RB, SEP>(Xs, H, scratch, op, true, i0, j0, TI, TJ, m, [&](int i, int j, T v) {
@@ -311,12 +316,12 @@ __device__ __forceinline__ void cgls_p2_body(const Job* __restrict__ jobs,
 template <typename T, typename S, int RB, bool SEP>
 __global__ void __launch_bounds__(NTHREADS, (waves_per_simd<T, RB>()))
     k_cgls_p2(const Job* __restrict__ jobs, const uint32_t* __restrict__ tiles) {
-  cgls_p2_body<T, S, RB, SEP>(jobs, tiles);
+  cgls_p2_body<T, S, RB, SEP, P2_V_NARROW>(jobs, tiles);
 }
 template <typename T, typename S, int RB, bool SEP>
 __global__ void __launch_bounds__(NTHREADS, (p2_waves<T, RB>()))
     k_cgls_p2_wide(const Job* __restrict__ jobs, const uint32_t* __restrict__ tiles) {
-  cgls_p2_body<T, S, RB, SEP>(jobs, tiles);
+  cgls_p2_body<T, S, RB, SEP, P2_V_WIDE>(jobs, tiles);
 }
 
 // Residual norm after the last CGLS iteration (one block per job): sums the
