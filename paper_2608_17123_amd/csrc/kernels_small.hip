@@ -114,7 +114,7 @@ __global__ void __launch_bounds__(small_nt(M, sizeof(T))) k_cgls_small(const Job
   };
   auto conv = [&](const T* X, bool adj, auto epi) {
     // outputs per item: enough items for every thread of the block
-    constexpr int V = m >= 64 ? 8 : 2;
+    constexpr int V = 2;
     sep_tile<T, RB, NT, V, false>(X, H, Z, adj ? tab[2] : tab[0], adj ? tab[3] : tab[1], 0, 0,
                                   m, m, m, epi);
   };

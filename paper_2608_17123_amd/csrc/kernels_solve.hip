@@ -76,6 +76,7 @@ __global__ void __launch_bounds__(NTHREADS) k_cgls_init(const Job* __restrict__ 
 // per-output sums do not depend on it, only register use does).
 constexpr int P1_V_NARROW = 2, P1_V_WIDE = 2;
 constexpr int P2_V_NARROW = 2, P2_V_WIDE = 2;
+constexpr int STATS_V = 2;
 // Launches of more tiles than this (5 resident 256-thread blocks on each of
 // 256 CUs at the unconstrained register use) take the _wide phase kernels.
 constexpr int P2_WIDE_TILES = 5 * 256;
@@ -421,10 +422,12 @@ __global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 3 : 2) k_stats(cons
       else pen += at;
     }
   }
-  conv_tile<T, RB, SEP>(Xs, H, scratch, op, false, i0, j0, TI, TJ, m, [&](int i, int j, T v) {
+  auto epi = [&](int i, int j, T v) {
     const double r = (double)v - (double)b[(i0 + i) + (size_t)(j0 + j) * m];
     res += r * r;
-  });
+  };
+  conv_tile<T, RB, SEP, decltype(epi), NoHook, STATS_V>(Xs, H, scratch, op, false, i0, j0, TI,
+                                                        TJ, m, epi);
   double vv[4] = {num, den, res, pen};
   put_partials<4>(job->pw, tix, vv, red);
 }
