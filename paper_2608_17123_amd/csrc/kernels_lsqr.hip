@@ -36,6 +36,9 @@ __device__ __forceinline__ double rinv(double v) { return v > 0.0 ? 1.0 / v : 0.
 // Occupancy target of the LSQR phases (waves per SIMD): they carry more live
 // values than the CGLS phases (rotation scalars, the in-place u and v updates),
 // so they are held at 4 (FP32) to stay free of register spills.
+// Outputs per item of the separable convolutions (as in the CGLS phases).
+constexpr int LSQR_V = 2;
+
 template <typename T, int RB>
 constexpr int lsqr_waves() {
   return sizeof(T) == 4 ? (RB <= 8 ? 4 : 3) : 2;
@@ -207,12 +210,14 @@ __global__ void __launch_bounds__(NTHREADS, (lsqr_waves<T, RB>()))
           acc += (double)un * (double)un;
         }
       });
-  conv_tile<T, RB, SEP>(Xs, H, scratch, op, false, i0, j0, TI, TJ, m, [&](int i, int j, T av) {
+  auto epia = [&](int i, int j, T av) {
     const size_t g = (i0 + i) + (size_t)(j0 + j) * m;
     const T un = rtv<S>(av - cu * ldv<T>(u1, g));
     stv(u1, g, un);
     acc += (double)un * (double)un;
-  });
+  };
+  conv_tile<T, RB, SEP, decltype(epia), NoHook, LSQR_V>(Xs, H, scratch, op, false, i0, j0, TI,
+                                                        TJ, m, epia);
   double vv[1] = {acc};
   put_partials<1>(job->pw, tix, vv, red);
 }
@@ -294,8 +299,9 @@ __global__ void __launch_bounds__(NTHREADS, (lsqr_waves<T, RB>()))
     acc += (double)vn * (double)vn;
   };
   if constexpr (SEP) {
-    conv_tile<T, RB, SEP>(Xs, H, scratch, op, true, i0, j0, TI, TJ, m, epi,
-                          [&] { grad_part(Xs); });
+    auto hook = [&] { grad_part(Xs); };
+    conv_tile<T, RB, SEP, decltype(epi), decltype(hook), LSQR_V>(Xs, H, scratch, op, true, i0,
+                                                                 j0, TI, TJ, m, epi, hook);
   } else {
     grad_part(reinterpret_cast<T*>(scratch) + (2 * H + 1) * (2 * H + 1) * 2);
     conv_tile<T, RB, SEP>(Xs, H, scratch, op, true, i0, j0, TI, TJ, m, epi);

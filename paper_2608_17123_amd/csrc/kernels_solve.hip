@@ -77,6 +77,8 @@ __global__ void __launch_bounds__(NTHREADS) k_cgls_init(const Job* __restrict__ 
 constexpr int P1_V_NARROW = 2, P1_V_WIDE = 2;
 constexpr int P2_V_NARROW = 2, P2_V_WIDE = 2;
 constexpr int STATS_V = 2;
+// Pixels whose loads each thread issues together in the pointwise passes.
+constexpr int P1_BATCH = 4, P2_BATCH = 4, P2_GRAD_BATCH = 2;
 // Launches of more tiles than this (5 resident 256-thread blocks on each of
 // 256 CUs at the unconstrained register use) take the _wide phase kernels.
 constexpr int P2_WIDE_TILES = 5 * 256;
@@ -122,7 +124,7 @@ __device__ __forceinline__ void cgls_p1_body(const Job* __restrict__ jobs,
   __syncthreads();
   double acc = 0.0;
   const size_t nx = (size_t)(m - 1) * m;
-  batched_pixels<8, 2, T>(
+  batched_pixels<P1_BATCH, 2, T>(
       TI * TJ,
       [&](int o, T* v) {
         const int gi = i0 + (o & (TI - 1)), gj = j0 + (o >> (__ffs(TI) - 1));
@@ -220,7 +222,7 @@ __device__ __forceinline__ void cgls_p2_body(const Job* __restrict__ jobs,
   }
   __syncthreads();
   double accr = 0.0, accs = 0.0;
-  batched_pixels<8, 2, T>(
+  batched_pixels<P2_BATCH, 2, T>(
       TI * TJ,
       [&](int o, T* v) {
         const size_t g = (i0 + (o & (TI - 1))) + (size_t)(j0 + (o >> (__ffs(TI) - 1))) * m;
@@ -245,7 +247,7 @@ __device__ __forceinline__ void cgls_p2_body(const Job* __restrict__ jobs,
   auto grad_part = [&](T* buf) {
     LT = buf;
     // per pixel: entries qx(i-1,j), qx(i,j), qy(i,j-1), qy(i,j) -> (r2a, q2, w)
-    batched_pixels<2, 12, T>(
+    batched_pixels<P2_GRAD_BATCH, 12, T>(
         TI * TJ,
         [&](int o, T* v) {
           const int gi = i0 + (o & (TI - 1)), gj = j0 + (o >> (__ffs(TI) - 1));
