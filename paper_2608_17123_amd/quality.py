@@ -39,7 +39,13 @@ import argparse
 import dataclasses
 import json
 import math
+import os
 import sys
+
+# the seeded workload generators live beside the package, at the repository root
+_ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if _ROOT not in sys.path:
+    sys.path.insert(0, _ROOT)
 
 import numpy as np
 
