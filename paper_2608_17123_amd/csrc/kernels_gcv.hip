@@ -187,9 +187,19 @@ __global__ void __launch_bounds__(NTHREADS) k_gcv_prep(const Job* __restrict__ j
 
 // ---------------------------------------------------------------- GEMM ----
 // out = A * B (i0 = 0) or A * B^T (i0 = 1); m x m FP64, column-major.
-// v[0] = A, v[1] = B, v[2] = out.  64 x 64 output tiles, 4 x 4 per thread.
-__global__ void __launch_bounds__(NTHREADS) k_gemm64(const Job* __restrict__ jobs,
-                                                     const uint32_t* __restrict__ tiles) {
+// v[0] = A, v[1] = B, v[2] = out.  64 x 64 output tiles.
+// On the FP64 matrix cores (v_mfma_f64_16x16x4f64): the block stages
+// 16-deep slabs of A and B in LDS; wave w computes the
+// 32 x 32 quarter (rows 32 (w % 2), columns 32 (w / 2)) of the 64 x 64 tile
+// as four 16 x 16 accumulators, four k-steps of 4 per slab.  Operand lanes:
+// A fragment a = A[row 16 rb + lane % 16][k 4 q + lane / 16], B fragment
+// b = B[k 4 q + lane / 16][column 16 cb + lane % 16]; result element v of a
+// lane is D[4 (lane / 16) + v][lane % 16] of its 16 x 16 block.  Stores are
+// guarded by the tile size (a grid below 64 is one partial tile).
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(NTHREADS) k_gemm64_mfma(const Job* __restrict__ jobs,
+                                                          const uint32_t* __restrict__ tiles) {
   __shared__ double As[16][65];
   __shared__ double Bs[16][65];
   const Job* job; int ti, tj, tix;
@@ -201,42 +211,51 @@ __global__ void __launch_bounds__(NTHREADS) k_gemm64(const Job* __restrict__ job
   const double* __restrict__ B = static_cast<const double*>(job->v[1]);
   double* __restrict__ C = static_cast<double*>(job->v[2]);
   const bool tb = job->i0 != 0;
-  const int tr = threadIdx.x % 16, tc = threadIdx.x / 16;  // 16 x 16 threads
-  double acc[4][4] = {};
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int wr = 32 * (wid & 1), wc = 32 * (wid >> 1);  // the wave's quarter
+  const int fr = lane & 15, fk = lane >> 4;              // fragment row / column, k
+  dbl4 acc[2][2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v) acc[u][v] = dbl4{0.0, 0.0, 0.0, 0.0};
   for (int k0 = 0; k0 < m; k0 += 16) {
     const int kk = m - k0 < 16 ? m - k0 : 16;
     for (int idx = threadIdx.x; idx < 16 * 64; idx += NTHREADS) {
-      const int r = idx % 64, k = idx / 64;  // A(i0 + r, k0 + k)
+      const int r = idx % 64, k = idx / 64;
       As[k][r] = (r < TS && k < kk) ? A[(i0 + r) + (size_t)(k0 + k) * m] : 0.0;
-      const int c = idx % 64, k2 = idx / 64;
       double bv = 0.0;
-      if (c < TS && k2 < kk)
-        bv = tb ? B[(j0 + c) + (size_t)(k0 + k2) * m] : B[(k0 + k2) + (size_t)(j0 + c) * m];
-      Bs[k2][c] = bv;
+      if (r < TS && k < kk)
+        bv = tb ? B[(j0 + r) + (size_t)(k0 + k) * m] : B[(k0 + k) + (size_t)(j0 + r) * m];
+      Bs[k][r] = bv;
     }
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      double a[4], b[4];
+    for (int q = 0; q < 4; ++q) {
+      const int k = 4 * q + fk;
+      double a[2], b[2];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        a[u] = As[k][tr + 16 * u];
-        b[u] = Bs[k][tc + 16 * u];
+      for (int u = 0; u < 2; ++u) {
+        a[u] = As[k][wr + 16 * u + fr];
+        b[u] = Bs[k][wc + 16 * u + fr];
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < 2; ++u)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
+        for (int v = 0; v < 2; ++v)
+          acc[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[v], acc[u][v], 0, 0, 0);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
+  for (int u = 0; u < 2; ++u)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int r = tr + 16 * u, c = tc + 16 * v;
-      if (r < TS && c < TS) C[(i0 + r) + (size_t)(j0 + c) * m] = acc[u][v];
-    }
+    for (int v = 0; v < 2; ++v)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = wr + 16 * u + 4 * fk + e, c = wc + 16 * v + fr;
+        if (r < TS && c < TS) C[(i0 + r) + (size_t)(j0 + c) * m] = acc[u][v][e];
+      }
 }
 
 // ---------------------------------------------------------------- data ----
@@ -751,7 +770,7 @@ hipError_t launch_gcv_prep(const LaunchArgs& la, int precision) {
   else GLAUNCH(k_gcv_prep<float>, la);
   return hipGetLastError();
 }
-hipError_t launch_gemm64(const LaunchArgs& la) { GLAUNCH(k_gemm64, la); return hipGetLastError(); }
+hipError_t launch_gemm64(const LaunchArgs& la) { GLAUNCH(k_gemm64_mfma, la); return hipGetLastError(); }
 hipError_t launch_gcv_symbol(const LaunchArgs& la) {
   GLAUNCH(k_gcv_symbol, la);
   return hipGetLastError();

@@ -383,3 +383,28 @@ def test_gcv_spectral_matches_oracle(ctx, kind, m, level):
     assert abs(g - g_ref) <= 1e-3 * g_ref
     assert abs(f - f_ref) <= 1e-6 * f_ref
     op.close()
+
+
+@pytest.mark.parametrize("m,level", [(128, 0), (256, 1)])
+def test_gcv_spectral_motion_blur_matches_oracle(ctx, m, level):
+    """Spectral GCV with a motion kernel: its cosine symbol is not symmetric in
+    (k1, k2), so the DCT products on the device (FP64 matrix cores) must place
+    every coefficient exactly; gamma and GCV(gamma) against the oracle."""
+    prec = D.DBL_F64
+    rng = np.random.default_rng(21)
+    P = synth.motion_psf(15, 0.6)
+    X = synth.piecewise_constant_image(m, max(6, m // 4), rng)
+    B = ops.blur(X, P)
+    B = rnd(B + 0.01 * np.linalg.norm(B) * rng.standard_normal((m, m)) / m, prec)
+    H = Hierarchy(P, m, 2, "haar")
+    Bi = H.restrict_rhs(B)[level]
+    kern = H.interior_stencil(level)
+    assert not np.allclose(kern, kern.T)
+    data = ogcv.spectral_data(kern, Bi)
+    g_ref, f_ref, _ = ogcv.choose_gamma(data)
+    op = D.dbl_op_create(ctx, P, m, 2, "haar", prec)
+    g, f = D.dbl_gcv(ctx, op, level, dev(ops.vec(Bi), prec), mode="spectral")
+    print(f"gcv motion m={m} level={level}: gpu {g:.10e} oracle {g_ref:.10e}", flush=True)
+    op.close()
+    assert abs(g - g_ref) <= 1e-3 * g_ref
+    assert abs(f - f_ref) <= 1e-6 * f_ref
