@@ -28,6 +28,18 @@ reflexive-boundary blur of an axis-symmetric kernel (and IRLS weights are
 constant); a_k equals the DCT of the blurred impulse divided by the DCT of
 the impulse.
 
+Boundary completion (this project's reading, for the surrogate only): the
+level operator blurs with zero boundaries (Sec. 5), the surrogate models a
+reflexive one, and the two differ by the exterior term E(y) = R(y) - Z(y)
+(R: blur of the half-sample symmetric extension, Z: zero-boundary blur).
+The surrogate therefore takes its data b^ from b_c, the completion of b
+under the reflexive model: b_c = b + E(b_c), approximated by
+COMPLETION_PASSES fixed-point passes from b_c = b.  Pinned: R is diagonal in
+the DCT-II basis with eigenvalues a_k (textbook, symmetric K), R equals a
+brute-force mirrored blur at tiny size, and the passes converge to the
+exact fixed point (a constant image for constant data under a unit-sum
+kernel).
+
 Minimiser (the paper's 50-point log grid followed by fminbnd): 50 values of
 t = log10 gamma evenly spaced on [t_lo, t_hi], from the smallest and largest
 finite positive nu/(1-nu) (EXACT) or s/lp over lp > 0 (SPECTRAL), with t_lo
@@ -119,14 +131,43 @@ def cosine_symbol(kernel, m):
     return out
 
 
-def spectral_data(kernel, B, wbar=1.0, dtc=None):
+COMPLETION_PASSES = 2
+
+
+def reflexive_blur(X, kernel):
+    """R X: the convolution of operators.blur taken on the half-sample
+    symmetric extension of X (x[-1 - i] = x[i], x[m + i] = x[m - 1 - i] on
+    each axis, repeated for kernels wider than the grid)."""
+    r0, r1 = kernel.shape[0] // 2, kernel.shape[1] // 2
+    m0, m1 = X.shape
+    Xe = np.pad(np.asarray(X, dtype=np.float64), ((r0, r0), (r1, r1)), mode="symmetric")
+    return ops.blur(Xe, kernel)[r0:r0 + m0, r1:r1 + m1]
+
+
+def exterior_term(Y, kernel):
+    """E(Y) = R Y - Z Y: what the reflexive model adds to the zero-boundary
+    blur (nonzero only within the kernel radius of an edge)."""
+    return reflexive_blur(Y, kernel) - ops.blur(Y, kernel)
+
+
+def boundary_completion(kernel, B, passes=COMPLETION_PASSES):
+    """b_c = b + E(b_c) by fixed-point passes from b_c = b."""
+    B = np.asarray(B, dtype=np.float64)
+    Bc = B
+    for _ in range(passes):
+        Bc = B + exterior_term(Bc, kernel)
+    return Bc
+
+
+def spectral_data(kernel, B, wbar=1.0, dtc=None, passes=COMPLETION_PASSES):
     """Per-frequency arrays (s, lp, e) of the DCT surrogate.
 
-    kernel: the level's interior kernel; B: m x m data; dtc: m x m array
-    D^T c = L^T c (None when c = 0); wbar: IRLS weight scale (1 for MM, SB)."""
+    kernel: the level's interior kernel; B: m x m data (completed under the
+    reflexive model before its transform); dtc: m x m array D^T c = L^T c
+    (None when c = 0); wbar: IRLS weight scale (1 for MM, SB)."""
     m = B.shape[0]
     a = cosine_symbol(kernel, m)
-    bh = dct2(B)
+    bh = dct2(boundary_completion(kernel, B, passes))
     lp = (wbar * wbar) * neumann_symbol(m)
     ch = np.zeros_like(bh) if dtc is None else dct2(dtc)
     e = (a * ch - lp * bh) ** 2

@@ -309,6 +309,29 @@ int gcv_run(dbl_ctx* ctx, std::vector<GcvReq>& reqs) {
       sel.push_back(q);
     }
     if ((rc = run_prec(P, "gcv_prep"))) return rc;
+    // boundary completion of b under the surrogate's reflexive model, two
+    // passes: tmp = b + E(b), then in = b + E(tmp) (b is held in `in`)
+    Launch c1, c2;
+    for (size_t q : sel) {
+      const LevelHost& L = reqs[q].op->host.levels[reqs[q].level];
+      if (L.kint_r0 > 16 || L.kint_r1 > 16)
+        return set_err(ctx, DBL_ENOTSUP, "GCV boundary completion needs a kernel radius <= 16");
+      Job a = base[q];
+      a.i0 = L.kint_r0;
+      a.i1 = L.kint_r1;
+      a.v[G_KINT] = static_cast<double*>(base[q].v[G_LAM]) + a.m;
+      Job b = a;
+      a.v[0] = base[q].v[G_IN];
+      a.v[1] = base[q].v[G_IN];
+      a.v[2] = base[q].v[G_TMP];
+      b.v[0] = base[q].v[G_IN];
+      b.v[1] = base[q].v[G_TMP];
+      b.v[2] = base[q].v[G_IN];
+      c1.add(a, a.m, 4);
+      c2.add(b, b.m, 4);
+    }
+    if ((rc = run(launch_gcv_complete, c1, "gcv_complete"))) return rc;
+    if ((rc = run(launch_gcv_complete, c2, "gcv_complete"))) return rc;
     if (!sel.empty() && (rc = dct2(sel, G_BH))) return rc;
   }
   // 2. L^T c (shift) and the IRLS weight scale, then DCT(L^T c)

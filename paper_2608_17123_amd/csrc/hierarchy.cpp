@@ -214,6 +214,35 @@ void pad_table(Table1DHost& t, int R) {
   t.R = R;
 }
 
+// Drop all-zero outer rings of the interior kernel (the class tables it is
+// read from are padded to the radius bucket).  Zero taps add exactly nothing
+// to the GCV symbol or to the boundary completion, so only their cost goes.
+static void trim_kint(LevelHost& L) {
+  const int R0 = L.kint_r0, R1 = L.kint_r1, N0 = 2 * R0 + 1;
+  auto at = [&](int a, int b) { return L.kint[(a + R0) + (size_t)(b + R1) * N0]; };
+  int r0 = R0, r1 = R1;
+  auto row_zero = [&](int a) {
+    for (int b = -r1; b <= r1; ++b)
+      if (at(a, b) != 0.0) return false;
+    return true;
+  };
+  while (r0 > 0 && row_zero(r0) && row_zero(-r0)) --r0;
+  auto col_zero = [&](int b) {
+    for (int a = -r0; a <= r0; ++a)
+      if (at(a, b) != 0.0) return false;
+    return true;
+  };
+  while (r1 > 0 && col_zero(r1) && col_zero(-r1)) --r1;
+  if (r0 == R0 && r1 == R1) return;
+  const int n0 = 2 * r0 + 1, n1 = 2 * r1 + 1;
+  std::vector<double> k((size_t)n0 * n1);
+  for (int b = -r1; b <= r1; ++b)
+    for (int a = -r0; a <= r0; ++a) k[(a + r0) + (size_t)(b + r1) * n0] = at(a, b);
+  L.kint.swap(k);
+  L.kint_r0 = r0;
+  L.kint_r1 = r1;
+}
+
 static int bucket(int R) {
   for (int b : {2, 4, 8, 12, 16})
     if (R <= b) return b;
@@ -264,6 +293,7 @@ void build_hierarchy(const double* P, int ph, int pw, int m, int levels, int wav
           L.kint[(a + L.kint_r0) + (size_t)(b + L.kint_r1) * n0] =
               L.f0.taps[(size_t)L.f0.St * n0 + (-a) + L.f0.R] *
               L.f1.taps[(size_t)L.f1.St * n1 + (-b) + L.f1.R];
+      trim_kint(L);
     }
     return;
   }
@@ -346,6 +376,7 @@ void build_hierarchy(const double* P, int ph, int pw, int m, int levels, int wav
     L.kint.assign((size_t)n0 * n0, 0.0);
     for (int k = tb.off[cls]; k < tb.off[cls + 1]; ++k)
       L.kint[(-tb.e0[k] + tb.R0) + (size_t)(-tb.e1[k] + tb.R0) * n0] = tb.val[k];
+    trim_kint(L);
   }
 }
 

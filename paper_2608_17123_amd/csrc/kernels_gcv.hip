@@ -185,6 +185,101 @@ __global__ void __launch_bounds__(NTHREADS) k_gcv_prep(const Job* __restrict__ j
   }
 }
 
+// ---------------------------------------------------- boundary completion --
+// The level operator blurs with zero boundaries, the surrogate models a
+// reflexive one.  One pass writes out = b + E(Y), with E(Y) the reflexive-
+// boundary blur of Y minus its zero-boundary blur: at a pixel within the
+// kernel radius of an edge, the taps of the interior kernel K (convolution
+// orientation, column-major (2 r0 + 1) x (2 r1 + 1)) whose source lies
+// outside the grid, applied to the half-sample symmetric reflection of Y.
+// Two passes (Y = b, then Y = the first result) complete the data before its
+// transform.  A thread reads b and writes out only at its own pixel, so out
+// may be b; Y is never written.  Job: m, i0 = r0, i1 = r1, v[0] = b,
+// v[1] = Y, v[2] = out, v[G_KINT] = K (all FP64).
+__device__ __forceinline__ int mirror_index(int s, int m) {
+  // ..., 1, 0 | 0, 1, ..., m - 1 | m - 1, ...: one reflection per step, a
+  // single step for offsets at most m outside the grid; two steps shift s by
+  // 2m towards the grid, so the loop ends for every m >= 1
+  while (s < 0 || s >= m) s = s < 0 ? -1 - s : 2 * m - 1 - s;
+  return s;
+}
+
+// Every source pixel that a tile's band reads (reflected or not) lies in the
+// tile grown by the kernel radius and clipped to the grid, so a band tile
+// stages that region of Y, and K, in LDS; tiles with no band pixel copy b.
+constexpr int CMP_RMAX = 16;                  // interior kernel radius bound
+constexpr int CMP_EDGE = 32 + 2 * CMP_RMAX;   // staged region edge (32-pixel tiles)
+
+__global__ void __launch_bounds__(NTHREADS) k_gcv_complete(const Job* __restrict__ jobs,
+                                                           const uint32_t* __restrict__ tiles) {
+  __shared__ double ys[CMP_EDGE * CMP_EDGE];
+  __shared__ double ks[(2 * CMP_RMAX + 1) * (2 * CMP_RMAX + 1)];
+  const Job* job; int ti, tj, tix;
+  decode_tile(jobs, tiles, job, ti, tj, tix);
+  const int m = job->m;
+  int i0, j0, TI, TJ;
+  tile_geom<float>(m, ti, tj, i0, j0, TI, TJ);
+  const int r0 = job->i0, r1 = job->i1, n0 = 2 * r0 + 1, n1 = 2 * r1 + 1;
+  const double* b = static_cast<const double*>(job->v[0]);
+  const double* Y = static_cast<const double*>(job->v[1]);
+  double* out = static_cast<double*>(job->v[2]);
+  const double* __restrict__ K = static_cast<const double*>(job->v[G_KINT]);
+  const int lg = __ffs(TI) - 1;
+  const bool band = i0 < r0 || i0 + TI > m - r0 || j0 < r1 || j0 + TJ > m - r1;
+  if (!band || r0 > CMP_RMAX || r1 > CMP_RMAX || TI > 32 || TJ > 32) {
+    // (the host never launches radii above the bound)
+    for (int o = threadIdx.x; o < TI * TJ; o += NTHREADS) {
+      const size_t g = (i0 + (o & (TI - 1))) + (size_t)(j0 + (o >> lg)) * m;
+      out[g] = b[g];
+    }
+    return;
+  }
+  const int a0 = max(0, i0 - r0), a1 = min(m, i0 + TI + r0);
+  const int c0 = max(0, j0 - r1), c1 = min(m, j0 + TJ + r1);
+  const int H = a1 - a0, W = c1 - c0;
+  const bool single = r0 <= m && r1 <= m;
+  for (int q = threadIdx.x; q < H * W; q += NTHREADS) {
+    const int u = q % H, v = q / H;
+    ys[q] = Y[(a0 + u) + (size_t)(c0 + v) * m];
+  }
+  for (int q = threadIdx.x; q < n0 * n1; q += NTHREADS) ks[q] = K[q];
+  __syncthreads();
+  for (int o = threadIdx.x; o < TI * TJ; o += NTHREADS) {
+    const int gi = i0 + (o & (TI - 1)), gj = j0 + (o >> lg);
+    const size_t g = gi + (size_t)gj * m;
+    double acc = b[g];
+    if (gi < r0 || gi >= m - r0 || gj < r1 || gj >= m - r1) {
+      // source row si = gi - aa lies below the grid for aa <= gi - m and
+      // above it for aa > gi; a column outside takes every row.  With
+      // r0, r1 <= m one reflection suffices and the staged row is linear in
+      // aa on each of the three ranges: 2m - 1 - si, si, -1 - si.
+      const int hi_lo = min(r0, gi - m), lo_hi = max(-r0, gi + 1);
+      double e = 0.0;
+      for (int bb = -r1; bb <= r1; ++bb) {
+        const int sj = gj - bb;
+        const bool col_out = sj < 0 || sj >= m;
+        const int kc = (bb + r1) * n0 + r0;                  // ks[kc + aa] = K[aa, bb]
+        const int yc = (mirror_index(sj, m) - c0) * H - a0;  // ys[yc + row]
+        if (single) {
+          const int yb = yc + 2 * m - 1 - gi, ym = yc + gi, ya = yc - gi - 1;
+          for (int aa = -r0; aa <= hi_lo; ++aa) e += ks[kc + aa] * ys[yb + aa];
+          if (col_out)
+            for (int aa = max(-r0, gi - m + 1); aa <= min(r0, gi); ++aa)
+              e += ks[kc + aa] * ys[ym - aa];
+          for (int aa = lo_hi; aa <= r0; ++aa) e += ks[kc + aa] * ys[ya + aa];
+        } else {
+          for (int aa = -r0; aa <= r0; ++aa) {
+            const int si = gi - aa;
+            if (col_out || si < 0 || si >= m) e += ks[kc + aa] * ys[yc + mirror_index(si, m)];
+          }
+        }
+      }
+      acc += e;
+    }
+    out[g] = acc;
+  }
+}
+
 // ---------------------------------------------------------------- GEMM ----
 // out = A * B (i0 = 0) or A * B^T (i0 = 1); m x m FP64, column-major.
 // v[0] = A, v[1] = B, v[2] = out.  64 x 64 output tiles.
@@ -768,6 +863,10 @@ __global__ void __launch_bounds__(NT) k_gcv_solo(const Job* __restrict__ jobs,
 hipError_t launch_gcv_prep(const LaunchArgs& la, int precision) {
   if (precision == 1) GLAUNCH(k_gcv_prep<double>, la);
   else GLAUNCH(k_gcv_prep<float>, la);
+  return hipGetLastError();
+}
+hipError_t launch_gcv_complete(const LaunchArgs& la) {
+  GLAUNCH(k_gcv_complete, la);
   return hipGetLastError();
 }
 hipError_t launch_gemm64(const LaunchArgs& la) { GLAUNCH(k_gemm64_mfma, la); return hipGetLastError(); }

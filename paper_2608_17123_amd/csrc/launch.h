@@ -71,6 +71,7 @@ enum AuxMode : int {
 
 // GCV (kernels_gcv.hip)
 hipError_t launch_gcv_prep(const LaunchArgs& la, int precision);
+hipError_t launch_gcv_complete(const LaunchArgs& la);
 hipError_t launch_gemm64(const LaunchArgs& la);
 hipError_t launch_gcv_symbol(const LaunchArgs& la);
 hipError_t launch_gcv_data(const LaunchArgs& la);

@@ -91,7 +91,8 @@ def test_spectral_tier_exact_for_reflexive_blur(mode):
     else:
         wbar, D, c, dtc = 1.7, 1.7 * L, np.zeros(L.shape[0]), None
     de = gcv.exact_data(A, D, ops.vec(B), c)
-    ds = gcv.spectral_data(K, B, wbar, dtc)
+    # without boundary completion: the surrogate formulas alone
+    ds = gcv.spectral_data(K, B, wbar, dtc, passes=0)
     for gamma in (1e-3, 0.1, 3.0):
         r1, t1 = gcv.exact_terms(gamma, de)
         r2, t2 = gcv.spectral_terms(gamma, ds)
@@ -135,7 +136,61 @@ def test_choose_gamma_matches_exhaustive_search():
     assert abs(math.log10(g) - ts[int(np.argmin(vals))]) < 1e-3
 
 
-def _zero_bc_problem(sigma, r, m=32, seed=0):
+def _mirror(i, m):
+    """Half-sample symmetric index: ..., 1, 0 | 0, 1, ..., m-1 | m-1, m-2, ..."""
+    while i < 0 or i >= m:
+        i = -1 - i if i < 0 else 2 * m - 1 - i
+    return i
+
+
+@pytest.mark.parametrize("m,shape", [(4, (3, 5)), (5, (11, 3)), (7, (5, 5))])
+def test_reflexive_blur_matches_mirrored_brute_force(m, shape):
+    """R X summed pixel by pixel over the mirrored image, for kernels with no
+    symmetry (orientation) and wider than the grid (repeated reflection)."""
+    rng = np.random.default_rng(11)
+    X = rng.standard_normal((m, m))
+    K = rng.standard_normal(shape)
+    r0, r1 = shape[0] // 2, shape[1] // 2
+    ref = np.zeros((m, m))
+    for i in range(m):
+        for j in range(m):
+            for a in range(-r0, r0 + 1):
+                for b in range(-r1, r1 + 1):
+                    ref[i, j] += K[a + r0, b + r1] * X[_mirror(i - a, m), _mirror(j - b, m)]
+    assert np.max(np.abs(gcv.reflexive_blur(X, K) - ref)) < 1e-12
+
+
+def test_reflexive_blur_is_diagonal_in_dct_basis():
+    """For a kernel symmetric in each axis the half-sample reflexive blur is
+    diagonalised by the orthonormal 2-D DCT-II with eigenvalues a_k."""
+    rng = np.random.default_rng(12)
+    m = 12
+    K = np.outer(synth.gaussian_psf(1.2, 3)[:, 3], synth.gaussian_psf(0.8, 1)[1, :])
+    X = rng.standard_normal((m, m))
+    lhs = dctn(gcv.reflexive_blur(X, K), norm="ortho")
+    rhs = gcv.cosine_symbol(K, m) * dctn(X, norm="ortho")
+    assert np.max(np.abs(lhs - rhs)) < 1e-12
+
+
+def test_boundary_completion_fixed_point_and_band():
+    """Constant data under a unit-sum kernel: the exact completion is the
+    constant image (R 1 = 1), and the passes approach it monotonically.
+    Pixels farther than the kernel radius from every edge are unchanged."""
+    m, c = 24, 0.7
+    K = synth.gaussian_psf(2.0, 5)
+    K = K / K.sum()
+    B = ops.blur(np.full((m, m), c), K)
+    errs = [np.max(np.abs(gcv.boundary_completion(K, B, p) - c)) for p in range(6)]
+    assert all(e1 < 0.6 * e0 for e0, e1 in zip(errs, errs[1:])), errs
+    assert np.max(np.abs(gcv.boundary_completion(K, B, 80) - c)) < 1e-12
+    rng = np.random.default_rng(13)
+    Y = rng.standard_normal((m, m))
+    Bc = gcv.boundary_completion(K, Y)
+    assert np.array_equal(Bc[5:m - 5, 5:m - 5], Y[5:m - 5, 5:m - 5])
+    assert np.max(np.abs(Bc - Y)) > 1e-2
+
+
+def _zero_bc_problem(sigma, r, m=32, seed=0, grid=(-9.0, 1.0, 81)):
     """Zero-boundary blur of a piecewise-constant image (the paper's operator,
     Sec. 5), 1% noise, with the dense pieces of the Tikhonov problem."""
     rng = synth.rng_for(99, seed)
@@ -152,7 +207,7 @@ def _zero_bc_problem(sigma, r, m=32, seed=0):
         x = np.linalg.solve(AtA + g * LtL, Atb)
         return float(np.linalg.norm(x - ops.vec(X)) / np.linalg.norm(X))
 
-    best = min(rre(10.0 ** t) for t in np.linspace(-9, 1, 81))
+    best = min(rre(10.0 ** t) for t in np.linspace(*grid))
     return H, Ad, Ld, B, rre, best
 
 
@@ -165,11 +220,24 @@ def test_exact_gcv_tracks_rre_optimal_tikhonov(sigma, r):
     assert rre(g) <= 1.02 * best, (g, rre(g), best)
 
 
-@pytest.mark.xfail(strict=True, reason="known limitation: the DCT surrogate assumes reflexive "
-                   "boundaries; on zero-boundary data at 1% noise it under-regularises once the "
-                   "blur is wide (sigma >= 1.5 here), where the exact tier does not")
-@pytest.mark.parametrize("sigma,r", [(2.0, 6)])
-def test_spectral_gcv_tracks_rre_optimal_tikhonov(sigma, r):
-    H, Ad, Ld, B, rre, best = _zero_bc_problem(sigma, r)
+@pytest.mark.parametrize("m,sigma,r,seed", [(32, 1.0, 3, 0), (32, 2.0, 6, 0), (48, 2.0, 6, 2)])
+def test_spectral_gcv_tracks_rre_optimal_tikhonov(m, sigma, r, seed):
+    """With boundary completion the surrogate's choice is within 2% of the
+    best Tikhonov RRE on zero-boundary data; without it the same data give a
+    vanishing gamma and an RRE several times the best."""
+    H, Ad, Ld, B, rre, best = _zero_bc_problem(sigma, r, m=m, seed=seed, grid=(-7.0, -2.0, 41))
+    K = H.interior_stencil(0)
+    g, _, _ = gcv.choose_gamma(gcv.spectral_data(K, B))
+    assert rre(g) <= 1.02 * best, (g, rre(g), best)
+    if sigma >= 2.0:
+        g0, _, _ = gcv.choose_gamma(gcv.spectral_data(K, B, passes=0))
+        assert rre(g0) > 3.0 * best, (g0, rre(g0), best)
+
+
+@pytest.mark.xfail(strict=True, reason="known limitation: when the kernel radius is a quarter of "
+                   "the grid (r = 8 on 32 x 32) the completed boundary band is half the image and "
+                   "the surrogate still under-regularises, where the exact tier does not")
+def test_spectral_gcv_wide_kernel_small_grid():
+    H, Ad, Ld, B, rre, best = _zero_bc_problem(2.5, 8)
     g, _, _ = gcv.choose_gamma(gcv.spectral_data(H.interior_stencil(0), B))
     assert rre(g) <= 1.02 * best, (g, rre(g), best)
