@@ -20,8 +20,8 @@ That basis diagonalises L^T L exactly (Neumann Laplacian, eigenvalues
 l_k = 4 sin^2(pi k1 / 2m) + 4 sin^2(pi k2 / 2m)); the blur is replaced by its
 reflexive-boundary counterpart, whose DCT eigenvalues for a kernel symmetric
 in each axis are a_k = sum K[a,b] cos(pi k1 a / m) cos(pi k2 b / m) (K = the
-level's interior kernel).  IRLS weights enter as their root mean square wbar
-(D ~ wbar L).  With s = a^2, lp = wbar^2 l, b^ = DCT(b), c^ = DCT(L^T c):
+level's interior kernel).  IRLS weights enter as one scale wbar (D ~ wbar L,
+see irls_weight_scale).  With s = a^2, lp = wbar^2 l, b^ = DCT(b), c^ = DCT(L^T c):
 resid^2 = gamma^2 sum (a c^ - lp b^)^2 / (s + gamma lp)^2 and
 trace = sum s / (s + gamma lp).  Pinned: equals the EXACT tier when A is the
 reflexive-boundary blur of an axis-symmetric kernel (and IRLS weights are
@@ -132,6 +132,23 @@ def cosine_symbol(kernel, m):
 
 
 COMPLETION_PASSES = 2
+
+
+def irls_weight_scale(w):
+    """Scale wbar of the surrogate's D ~ wbar L for IRLS weights w (this
+    project's reading; the paper's GSVD route takes diag(w) L as it is).
+
+    The IRLS weights (Sec. 2.1, after eq. (IRLS1)) are w = u^(-1/2) with
+    u = max(|L x|, eps), so u = w^-2 is recoverable from w alone.  wbar^2 is
+    the Rayleigh quotient ||diag(w) u||^2 / ||u||^2 = sum(u) / sum(u^2): the
+    one factor under which the gradient field behind the weights keeps its
+    weighted penalty.  Constant weights give wbar = w.  Zero weights are left
+    out; with none left, wbar = 1."""
+    w2 = np.asarray(w, dtype=np.float64) ** 2
+    u = 1.0 / w2[w2 > 0.0]
+    if u.size == 0:
+        return 1.0
+    return float(np.sqrt(np.sum(u) / np.sum(u * u)))
 
 
 def reflexive_blur(X, kernel):

@@ -129,7 +129,7 @@ def gcv_gamma(op, B, solver, weights, shift, mode):
         data = gcvmod.exact_data(Ad, Dd, ops.vec(B), shift)
     else:
         kern = op.h.interior_stencil(op.i)
-        wbar = 1.0 if weights is None else float(np.sqrt(np.mean(weights * weights)))
+        wbar = 1.0 if weights is None else gcvmod.irls_weight_scale(weights)
         dtc = None if shift is None else ops.grad_adjoint(shift, m)
         data = gcvmod.spectral_data(kern, B, wbar, dtc)
     gamma, _, _ = gcvmod.choose_gamma(data)

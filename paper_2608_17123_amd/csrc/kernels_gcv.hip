@@ -135,8 +135,11 @@ __global__ void __launch_bounds__(NTHREADS) k_gcv_symbol(const Job* __restrict__
 }
 
 // ---------------------------------------------------------------- prep ----
-// i0 = 0: in = (double) b.  i0 = 1: in = L^T c (c = c1 - c2), plus the sum of
-// squared IRLS weights when G_W is set (scal[S_G_WBAR] = sum w^2 / n_L).
+// i0 = 0: in = (double) b.  i0 = 1: in = L^T c (c = c1 - c2), plus, when G_W
+// holds IRLS weights, the partial sums of u and u^2 for u = w^-2 over the
+// nonzero weights (the surrogate's weight scale wbar^2 = sum u / sum u^2: the
+// weights are max(|L x|, eps)^(-1/2), so u recovers max(|L x|, eps) and the
+// ratio is the Rayleigh quotient ||diag(w) u||^2 / ||u||^2).
 template <typename T>
 __global__ void __launch_bounds__(NTHREADS) k_gcv_prep(const Job* __restrict__ jobs,
                                                        const uint32_t* __restrict__ tiles) {
@@ -148,7 +151,15 @@ __global__ void __launch_bounds__(NTHREADS) k_gcv_prep(const Job* __restrict__ j
   tile_geom<float>(m, ti, tj, i0, j0, TI, TJ);
   double* __restrict__ in = static_cast<double*>(job->v[G_IN]);
   const size_t nx = (size_t)(m - 1) * m;
-  double wsq = 0.0;
+  double su = 0.0, su2 = 0.0;
+  auto add_w = [&](double v) {
+    const double w2 = v * v;
+    if (w2 > 0.0) {
+      const double u = 1.0 / w2;
+      su += u;
+      su2 += u * u;
+    }
+  };
   if (job->i0 == 0) {
     const T* __restrict__ b = static_cast<const T*>(job->v[G_B]);
     for (int o = threadIdx.x; o < TI * TJ; o += NTHREADS) {
@@ -175,13 +186,13 @@ __global__ void __launch_bounds__(NTHREADS) k_gcv_prep(const Job* __restrict__ j
     }
     in[g] = a;
     if (w) {
-      if (gi < m - 1) { const double v = w[gi + (size_t)gj * (m - 1)]; wsq += v * v; }
-      if (gj < m - 1) { const double v = w[nx + g]; wsq += v * v; }
+      if (gi < m - 1) add_w((double)w[gi + (size_t)gj * (m - 1)]);
+      if (gj < m - 1) add_w((double)w[nx + g]);
     }
   }
   if (w) {
-    double vv[1] = {wsq};
-    put_partials<1>(job->pw, tix, vv, red);
+    double vv[2] = {su, su2};
+    put_partials<2>(job->pw, tix, vv, red);
   }
 }
 
@@ -371,11 +382,14 @@ __global__ void __launch_bounds__(NTHREADS) k_gcv_data(const Job* __restrict__ j
   double* __restrict__ e = static_cast<double*>(job->v[G_E]);
   const bool shift = job->i0 != 0;
   const bool exact = job->flags & F_EXACT;
-  // IRLS weight scale wbar^2 = mean(w^2) from the prep partials, else 1
+  // IRLS weight scale wbar^2 = sum u / sum u^2 from the prep partials (1
+  // without weights or without a nonzero weight)
   double wb2 = 1.0;
-  if (job->pr[0])
-    wb2 = sum_partials<1>(job->pr[0], job->nti * job->ntj, 0, red, &bc) /
-          (2.0 * (double)m * (m - 1));
+  if (job->pr[0]) {
+    const double s1 = sum_partials<2>(job->pr[0], job->nti * job->ntj, 0, red, &bc);
+    const double s2 = sum_partials<2>(job->pr[0], job->nti * job->ntj, 1, red, &bc);
+    if (s2 > 0.0) wb2 = s1 / s2;
+  }
   if (tix == 0 && threadIdx.x == 0) job->scal[S_G_WBAR] = wb2;
   double lo = 1e300, hi = -1e300;
   for (int o = threadIdx.x; o < TI * TJ && exact; o += NTHREADS) {

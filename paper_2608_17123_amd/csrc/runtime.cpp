@@ -221,7 +221,7 @@ int tiles_per_axis(int grid_m, int esz) {
 
 size_t part_doubles(int m) {
   const size_t t4 = (size_t)tiles_per_axis(m, 4), t8 = (size_t)tiles_per_axis(m, 8);
-  return 9 * t8 * t8 + (5 + 2 * DBL_GCV_GRID_MAX + 2) * t4 * t4 + 64;
+  return 9 * t8 * t8 + (6 + 2 * DBL_GCV_GRID_MAX + 2) * t4 * t4 + 64;
 }
 
 PartLayout part_layout(double* base, int m) {
@@ -233,7 +233,7 @@ PartLayout part_layout(double* base, int m) {
   L.s[0] = p; p += 2 * nt;
   L.s[1] = p; p += 2 * nt;
   L.st = p; p += 4 * nt;
-  L.gw = p; p += ng;
+  L.gw = p; p += 2 * ng;
   L.gmm = p; p += 2 * ng;
   L.ggrid = p; p += 2 * DBL_GCV_GRID_MAX * ng;
   L.gb[0] = p; p += 2 * ng;

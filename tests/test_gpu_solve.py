@@ -371,7 +371,7 @@ def test_gcv_spectral_matches_oracle(ctx, kind, m, level):
     rng = np.random.default_rng(7)
     w = rng.uniform(0.5, 5.0, nl) if kind == "irls" else None
     c = 0.05 * rng.standard_normal(nl) if kind in ("mm", "sb") else None
-    wbar = 1.0 if w is None else float(np.sqrt(np.mean(w * w)))
+    wbar = 1.0 if w is None else ogcv.irls_weight_scale(w)
     dtc = None if c is None else ops.grad_adjoint(c, mi)
     data = ogcv.spectral_data(H.interior_stencil(level), Bi, wbar, dtc)
     g_ref, f_ref, _ = ogcv.choose_gamma(data)

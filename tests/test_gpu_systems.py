@@ -343,7 +343,10 @@ def decisions_clear_of(levels_rc, tols, rel=0.02, absolute=RC_ABS_F32):
     return True
 
 
-TOL_CASES = [(s, t, 1e-3, 1e-6) for s in ("irls", "mm", "sb") for t in ("X", "D")] + [
+# IRLS with Approach D passes RC = 1.0166e-3 on its fine grid, within the 2%
+# margin of 1e-3, so it takes 1.5e-3 there (and stops that grid early).
+TOL_CASES = [(s, t, 1.5e-3 if (s, t) == ("irls", "D") else 1e-3, 1e-6)
+             for s in ("irls", "mm", "sb") for t in ("X", "D")] + [
     ("irls", "X", 1e-3, 3e-3), ("mm", "D", 1e-3, 3e-3), ("sb", "X", 1e-3, 3e-3)]
 
 

@@ -241,3 +241,63 @@ def test_spectral_gcv_wide_kernel_small_grid():
     H, Ad, Ld, B, rre, best = _zero_bc_problem(2.5, 8)
     g, _, _ = gcv.choose_gamma(gcv.spectral_data(H.interior_stencil(0), B))
     assert rre(g) <= 1.02 * best, (g, rre(g), best)
+
+
+def test_irls_weight_scale_closed_forms():
+    """Constant weights: wbar = w.  Weights of the IRLS formula from an
+    iterate with |L x| >= eps everywhere: wbar^2 is the Rayleigh quotient
+    ||diag(w) L x||^2 / ||L x||^2 taken on L x itself.  Scaling the image
+    (and eps) by c scales wbar^2 by 1/c.  Zero weights are left out."""
+    from oracle.solvers import irls_weights
+    assert abs(gcv.irls_weight_scale(np.full(40, 1.7)) - 1.7) < 1e-15
+    rng = np.random.default_rng(21)
+    m, eps = 12, 0.03
+    X = rng.uniform(0.0, 1.0, (m, m))
+    Lx = ops.grad(X)
+    Lx = np.where(np.abs(Lx) < eps, eps * np.sign(Lx + 1e-300), Lx)
+    w = irls_weights(Lx, eps)
+    ray = np.sum((w * Lx) ** 2) / np.sum(Lx ** 2)
+    assert abs(gcv.irls_weight_scale(w) ** 2 - ray) < 1e-13 * ray
+    c = 37.0
+    w_c = irls_weights(c * Lx, c * eps)
+    assert abs(gcv.irls_weight_scale(w_c) ** 2 * c - ray) < 1e-12 * ray
+    assert gcv.irls_weight_scale(np.concatenate([w, np.zeros(5)])) == gcv.irls_weight_scale(w)
+    assert gcv.irls_weight_scale(np.zeros(3)) == 1.0
+
+
+@pytest.mark.parametrize("sigma,r,noise", [(2.0, 6, 0.01), (1.0, 3, 0.01), (2.0, 6, 0.05)])
+def test_weighted_spectral_gcv_tracks_rre_optimal(sigma, r, noise):
+    """IRLS weighted pair {A, diag(w) L} on zero-boundary data (m = 32): the
+    surrogate's choice with the Rayleigh weight scale gives a weighted
+    Tikhonov solution within 2% of the best RRE (the exact tier's choice is
+    within 2% too); the root-mean-square scale is more than 2% off in the
+    low-noise cases."""
+    from oracle.solvers import irls_weights
+    m = 32
+    rng = synth.rng_for(99, 0)
+    X = synth.piecewise_constant_image(m, 10, rng)
+    P = synth.gaussian_psf(sigma, r)
+    B0 = ops.blur(X, P)
+    xi = rng.standard_normal((m, m))
+    B = B0 + noise * np.linalg.norm(B0) * xi / np.linalg.norm(xi)
+    H = Hierarchy(P, m, 1, "haar")
+    K = H.interior_stencil(0)
+    Ad, Ld, b = H.dense(0), ops.grad_dense(m), ops.vec(B)
+    AtA, Atb = Ad.T @ Ad, Ad.T @ b
+    g0, _, _ = gcv.choose_gamma(gcv.spectral_data(K, B))
+    x = np.linalg.solve(AtA + g0 * Ld.T @ Ld, Atb)
+    w = irls_weights(Ld @ x, 0.03)
+    DtD = (w[:, None] * Ld).T @ (w[:, None] * Ld)
+
+    def rre(g):
+        return float(np.linalg.norm(np.linalg.solve(AtA + g * DtD, Atb) - ops.vec(X))
+                     / np.linalg.norm(X))
+
+    best = min(rre(10.0 ** t) for t in np.linspace(-7.0, 0.0, 57))
+    ge, _, _ = gcv.choose_gamma(gcv.exact_data(Ad, w[:, None] * Ld, b, None))
+    assert rre(ge) <= 1.02 * best
+    g, _, _ = gcv.choose_gamma(gcv.spectral_data(K, B, gcv.irls_weight_scale(w)))
+    assert rre(g) <= 1.02 * best, (g, rre(g), best)
+    if noise < 0.05:
+        g_rms, _, _ = gcv.choose_gamma(gcv.spectral_data(K, B, float(np.sqrt(np.mean(w * w)))))
+        assert rre(g_rms) > 1.02 * best, (g_rms, rre(g_rms), best)
