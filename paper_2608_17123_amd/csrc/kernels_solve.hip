@@ -99,18 +99,6 @@ __device__ __forceinline__ void cgls_p1_body(const Job* __restrict__ jobs,
   T* Xs = reinterpret_cast<T*>(smem);
   void* scratch = Xs + xs_elems<SEP>(H, TI, TJ);
   const int nt = job->nti * job->ntj;
-  double beta = 0.0;
-  if (!(job->flags & F_FIRST)) {  // iteration > 0: beta = |s_k|^2 / |s_{k-1}|^2
-    double gcur, gprev;
-    sum_partials2<2, 2>(job->pr[0], 0, job->pr[1], 0, nt, red, bc2, gcur, gprev);
-    beta = gprev > 0.0 ? gcur / gprev : 0.0;
-    if ((job->flags & F_HIST) && tix == 0) {
-      const double rr = sum_partials<2>(job->pr[0], nt, 1, red, &bc);
-      if (threadIdx.x == 0 && job->i0 >= 1 && job->i0 <= HIST_MAX)
-        job->scal[S_HIST + job->i0 - 1] = rr;
-    }
-  }
-  const T tb = (T)beta;
   const double sg = job->scal[S_SQRTG];
   const bool irls = job->flags & F_IRLS;
   const S* __restrict__ s = vp<S>(job, V_S);
@@ -119,8 +107,28 @@ __device__ __forceinline__ void cgls_p1_body(const Job* __restrict__ jobs,
   S* __restrict__ q1 = vp<S>(job, V_Q1);
   S* __restrict__ q2 = vp<S>(job, V_Q2);
   const T* __restrict__ w = vp<T>(job, V_W);
-  load_tile<T, SEP>(Xs, xs_ld<SEP>(H, TI, TJ), i0, j0, TI, TJ, H, m,
-                    [&](int g) { return rtv<S>(ldv<T>(s, g) + tb * ldv<T>(pa, g)); });
+  if (job->flags & F_FIRST) {  // p = s
+    load_tile<T, SEP>(Xs, xs_ld<SEP>(H, TI, TJ), i0, j0, TI, TJ, H, m,
+                      [&](int g) { return rtv<S>(ldv<T>(s, g) + T(0) * ldv<T>(pa, g)); });
+  } else {
+    // iteration > 0: beta = |s_k|^2 / |s_{k-1}|^2 from the partials, summed
+    // while the tile loads are in flight
+    load_tile_overlap<T, SEP>(
+        Xs, xs_ld<SEP>(H, TI, TJ), i0, j0, TI, TJ, H, m,
+        [&](int g) { return ldv<T>(s, g); }, [&](int g) { return ldv<T>(pa, g); },
+        [&]() {
+          double gcur, gprev;
+          sum_partials2<2, 2>(job->pr[0], 0, job->pr[1], 0, nt, red, bc2, gcur, gprev);
+          const double beta = gprev > 0.0 ? gcur / gprev : 0.0;
+          if ((job->flags & F_HIST) && tix == 0) {
+            const double rr = sum_partials<2>(job->pr[0], nt, 1, red, &bc);
+            if (threadIdx.x == 0 && job->i0 >= 1 && job->i0 <= HIST_MAX)
+              job->scal[S_HIST + job->i0 - 1] = rr;
+          }
+          return (T)beta;
+        },
+        [&](T a, T b, T c) { return rtv<S>(a + c * b); });
+  }
   __syncthreads();
   double acc = 0.0;
   const size_t nx = (size_t)(m - 1) * m;
@@ -196,12 +204,6 @@ __device__ __forceinline__ void cgls_p2_body(const Job* __restrict__ jobs,
   const bool irls = job->flags & F_IRLS;
   const int nt = job->nti * job->ntj;
   double alpha = 0.0;
-  if (!first) {  // alpha = |s|^2 / |q|^2
-    double qq, gs;
-    sum_partials2<1, 2>(job->pr[0], 0, job->pr[1], 0, nt, red, bc2, qq, gs);
-    alpha = qq > 0.0 ? gs / qq : 0.0;
-  }
-  const T ta = (T)alpha;
   const double sg = job->scal[S_SQRTG];
   T* __restrict__ x = vp<T>(job, V_X);
   const S* __restrict__ p = vp<S>(job, V_PB);
@@ -213,12 +215,24 @@ __device__ __forceinline__ void cgls_p2_body(const Job* __restrict__ jobs,
   const S* __restrict__ q2 = vp<S>(job, V_Q2);
   const T* __restrict__ w = vp<T>(job, V_W);
   S* __restrict__ s = vp<S>(job, V_S);
+  T ta = T(0);
   if (first) {
     load_tile<T, SEP>(Xs, xs_ld<SEP>(H, TI, TJ), i0, j0, TI, TJ, H, m,
                       [&](int g) { return ldv<T>(r1a, g); });
   } else {
-    load_tile<T, SEP>(Xs, xs_ld<SEP>(H, TI, TJ), i0, j0, TI, TJ, H, m,
-                      [&](int g) { return rtv<S>(ldv<T>(r1a, g) - ta * ldv<T>(q1, g)); });
+    // alpha = |s|^2 / |q|^2 from the partials, summed while the tile loads
+    // are in flight
+    load_tile_overlap<T, SEP>(
+        Xs, xs_ld<SEP>(H, TI, TJ), i0, j0, TI, TJ, H, m,
+        [&](int g) { return ldv<T>(r1a, g); }, [&](int g) { return ldv<T>(q1, g); },
+        [&]() {
+          double qq, gs;
+          sum_partials2<1, 2>(job->pr[0], 0, job->pr[1], 0, nt, red, bc2, qq, gs);
+          alpha = qq > 0.0 ? gs / qq : 0.0;
+          ta = (T)alpha;
+          return ta;
+        },
+        [&](T a, T b, T c) { return rtv<S>(a - c * b); });
   }
   __syncthreads();
   double accr = 0.0, accs = 0.0;

@@ -69,16 +69,17 @@ __device__ __forceinline__ void tile_ij(int o, int TI, int& i, int& j) {
 // Load the (TI+2H) x (TJ+2H) region starting at global (i0-H, j0-H) with
 // periodic wrap.  f(gi) returns the value at flat global index gi.  Loads are
 // issued in groups of U per thread before the LDS stores, so the whole tile
-// is requested in one or two memory round trips.
+// is requested in one or two memory round trips.  Elements before `start`
+// (in the thread-strided order) are left to the caller.
 template <typename T, bool ROWMAJOR, int NT = NTHREADS, class F>
 __device__ __forceinline__ void load_tile(T* Xs, int ld, int i0, int j0, int TI, int TJ, int H,
-                                          int m, F f) {
+                                          int m, F f, int start = 0) {
   constexpr int U = sizeof(T) == 4 ? 16 : 8;
   const int NR = TI + 2 * H, NC = TJ + 2 * H, tot = NR * NC;  // <= 64 x 64
   const int msk = m - 1;
   const float rNR = rcp_small(NR);
 #pragma unroll 1
-  for (int base = threadIdx.x; base < tot; base += NT * U) {
+  for (int base = start + threadIdx.x; base < tot; base += NT * U) {
     T v[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -100,6 +101,50 @@ __device__ __forceinline__ void load_tile(T* Xs, int ld, int i0, int j0, int TI,
       }
     }
   }
+}
+
+// load_tile for values comb(a[g], b[g], c) whose scalar c comes from a block
+// reduction (the CGLS step lengths): the first batch of a and b is requested
+// before scalar() runs, so those loads and the reduction's reads of the
+// previous launch's partials are in flight together.  scalar() holds
+// barriers: every thread calls it exactly once, outside any branch.  The
+// first batch holds U elements per thread (a whole 48 x 48 FP32 tile), few
+// enough that the held values do not raise the phases' register peak.
+template <typename T, bool ROWMAJOR, int NT = NTHREADS, class FA, class FB, class FS, class FC>
+__device__ __forceinline__ void load_tile_overlap(T* Xs, int ld, int i0, int j0, int TI, int TJ,
+                                                  int H, int m, FA fa, FB fb, FS scalar,
+                                                  FC comb) {
+  constexpr int U = sizeof(T) == 4 ? 10 : 5;
+  const int NR = TI + 2 * H, NC = TJ + 2 * H, tot = NR * NC;  // <= 64 x 64
+  const int msk = m - 1;
+  const float rNR = rcp_small(NR);
+  T va[U], vb[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int idx = threadIdx.x + u * NT;
+    if (idx < tot) {
+      int c, r;
+      divmod_small(idx, NR, rNR, c, r);
+      const int g = ((i0 - H + r) & msk) + ((j0 - H + c) & msk) * m;
+      va[u] = fa(g);
+      vb[u] = fb(g);
+    }
+  }
+  const T cv = scalar();
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int idx = threadIdx.x + u * NT;
+    if (idx < tot) {
+      int c, r;
+      divmod_small(idx, NR, rNR, c, r);
+      const T v = comb(va[u], vb[u], cv);
+      if (ROWMAJOR) Xs[r * ld + c] = v; else Xs[c * ld + r] = v;
+    }
+  }
+  // tiles beyond one batch per thread (FP64 with the widest halos)
+  load_tile<T, ROWMAJOR, NT>(Xs, ld, i0, j0, TI, TJ, H, m, [&](int g) {
+    return comb(fa(g), fb(g), cv);
+  }, NT * U);
 }
 
 // Separable two-pass tile convolution.  Tables padded to radius RB (2RB+1
