@@ -140,27 +140,34 @@ __global__ void __launch_bounds__(NTHREADS, (lsqr_waves<T, RB>()))
   const int nt = job->nti * job->ntj;
   const bool first = job->flags & F_FIRST;
   const int it = job->i0;
-  double aa, bb;
-  sum_partials2<1, 1>(job->pr[0], 0, job->pr[1], 0, nt, red, bc2, aa, bb);
-  const double alpha = sqrt(aa), beta = sqrt(bb);
   double* st = job->scal + S_LQ;
-  Rot r;
-  if (first) {
-    r.rho = r.theta = r.phi = 0.0;
-    r.rhobar = alpha;
-    r.phibar = beta;
-  } else {
-    r = rotate(st[2 * ((it - 1) & 1)], st[2 * ((it - 1) & 1) + 1], beta, alpha);
-  }
-  if (tix == 0 && threadIdx.x == 0) {
-    st[2 * (it & 1)] = r.rhobar;
-    st[2 * (it & 1) + 1] = r.phibar;
-    if ((job->flags & F_HIST) && !first && it - 2 < HIST_MAX)
-      job->scal[S_HIST + it - 2] = r.phibar * r.phibar;
-  }
-  const T tx = (T)(r.phi * rinv(r.rho)), tw = (T)(r.theta * rinv(r.rho));
-  const T ta = (T)rinv(alpha);
-  const T cu = (T)(alpha * rinv(beta));  // u_new = Abar v_i - alpha_i u_i, u_i = u / beta_i
+  T tx, tw, ta, cu;
+  // norms, rotation and step scalars; run by every thread inside the tile
+  // load, while the first batch of v is in flight
+  auto scalars = [&]() {
+    double aa, bb;
+    sum_partials2<1, 1>(job->pr[0], 0, job->pr[1], 0, nt, red, bc2, aa, bb);
+    const double alpha = sqrt(aa), beta = sqrt(bb);
+    Rot r;
+    if (first) {
+      r.rho = r.theta = r.phi = 0.0;
+      r.rhobar = alpha;
+      r.phibar = beta;
+    } else {
+      r = rotate(st[2 * ((it - 1) & 1)], st[2 * ((it - 1) & 1) + 1], beta, alpha);
+    }
+    if (tix == 0 && threadIdx.x == 0) {
+      st[2 * (it & 1)] = r.rhobar;
+      st[2 * (it & 1) + 1] = r.phibar;
+      if ((job->flags & F_HIST) && !first && it - 2 < HIST_MAX)
+        job->scal[S_HIST + it - 2] = r.phibar * r.phibar;
+    }
+    tx = (T)(r.phi * rinv(r.rho));
+    tw = (T)(r.theta * rinv(r.rho));
+    ta = (T)rinv(alpha);
+    cu = (T)(alpha * rinv(beta));  // u_new = Abar v_i - alpha_i u_i, u_i = u / beta_i
+    return ta;
+  };
   const double sg = job->scal[S_SQRTG];
   const bool irls = job->flags & F_IRLS;
   T* __restrict__ x = vp<T>(job, V_X);
@@ -169,8 +176,9 @@ __global__ void __launch_bounds__(NTHREADS, (lsqr_waves<T, RB>()))
   S* __restrict__ u1 = vp<S>(job, V_R1A);
   S* __restrict__ u2 = vp<S>(job, V_R2A);
   const T* __restrict__ wt = vp<T>(job, V_W);
-  load_tile<T, SEP>(Xs, xs_ld<SEP>(H, TI, TJ), i0, j0, TI, TJ, H, m,
-                    [&](int g) { return ldv<T>(v, g) * ta; });
+  load_tile_overlap<T, SEP>(
+      Xs, xs_ld<SEP>(H, TI, TJ), i0, j0, TI, TJ, H, m, [&](int g) { return ldv<T>(v, g); },
+      [&](int) { return T(0); }, scalars, [&](T a, T, T c) { return a * c; });
   __syncthreads();
   double acc = 0.0;
   const size_t nx = (size_t)(m - 1) * m;
@@ -243,18 +251,26 @@ __global__ void __launch_bounds__(NTHREADS, (lsqr_waves<T, RB>()))
   const int nt = job->nti * job->ntj;
   const bool first = job->flags & F_FIRST;
   const bool irls = job->flags & F_IRLS;
-  double bb, aa;
-  sum_partials2<1, 1>(job->pr[0], 0, first ? job->pr[0] : job->pr[1], 0, nt, red, bc2, bb, aa);
-  const double beta = sqrt(bb), alpha = sqrt(aa);
-  const T tb = (T)rinv(beta);
-  const T cv = first ? T(0) : (T)(beta * rinv(alpha));  // v_new = ... - beta v_old / alpha
+  T tb, cv;
+  // 1 / beta and the v recurrence factor; run by every thread inside the
+  // tile load, while the first batch of u1 is in flight
+  auto scalars = [&]() {
+    double bb, aa;
+    sum_partials2<1, 1>(job->pr[0], 0, first ? job->pr[0] : job->pr[1], 0, nt, red, bc2, bb,
+                        aa);
+    const double beta = sqrt(bb), alpha = sqrt(aa);
+    tb = (T)rinv(beta);
+    cv = first ? T(0) : (T)(beta * rinv(alpha));  // v_new = ... - beta v_old / alpha
+    return tb;
+  };
   const double sg = job->scal[S_SQRTG];
   S* __restrict__ v = vp<S>(job, V_S);
   const S* __restrict__ u1 = vp<S>(job, V_R1A);
   const S* __restrict__ u2 = vp<S>(job, V_R2A);
   const T* __restrict__ wt = vp<T>(job, V_W);
-  load_tile<T, SEP>(Xs, xs_ld<SEP>(H, TI, TJ), i0, j0, TI, TJ, H, m,
-                    [&](int g) { return ldv<T>(u1, g) * tb; });
+  load_tile_overlap<T, SEP>(
+      Xs, xs_ld<SEP>(H, TI, TJ), i0, j0, TI, TJ, H, m, [&](int g) { return ldv<T>(u1, g); },
+      [&](int) { return T(0); }, scalars, [&](T a, T, T c) { return a * c; });
   __syncthreads();
   double acc = 0.0;
   const size_t nx = (size_t)(m - 1) * m;
