@@ -78,7 +78,7 @@ constexpr int P1_V_NARROW = 2, P1_V_WIDE = 2;
 constexpr int P2_V_NARROW = 2, P2_V_WIDE = 2;
 constexpr int STATS_V = 2;
 // Pixels whose loads each thread issues together in the pointwise passes.
-constexpr int P1_BATCH = 4, P2_BATCH = 4, P2_GRAD_BATCH = 2;
+constexpr int P1_BATCH = 4, P2_GRAD_BATCH = 2;
 // Launches of more tiles than this (5 resident 256-thread blocks on each of
 // 256 CUs at the unconstrained register use) take the _wide phase kernels.
 constexpr int P2_WIDE_TILES = 5 * 256;
@@ -236,23 +236,15 @@ __device__ __forceinline__ void cgls_p2_body(const Job* __restrict__ jobs,
   }
   __syncthreads();
   double accr = 0.0, accs = 0.0;
-  batched_pixels<P2_BATCH, 2, T>(
-      TI * TJ,
-      [&](int o, T* v) {
-        const size_t g = (i0 + (o & (TI - 1))) + (size_t)(j0 + (o >> (__ffs(TI) - 1))) * m;
-        if (!first) {
-          v[0] = x[g];
-          v[1] = ldv<T>(p, g);
-        }
-      },
-      [&](int o, T* v) {
-        const int i = (o & (TI - 1)), j = (o >> (__ffs(TI) - 1));
-        const size_t g = (i0 + i) + (size_t)(j0 + j) * m;
-        const T rv = Xs[xs_at<SEP>(i, j, H, TI, TJ)];
-        stv(r1b, g, rv);
-        accr += (double)rv * (double)rv;
-        if (!first) x[g] = v[0] + ta * v[1];
-      });
+  // r1 of the tile from LDS (no global loads: x and p are read with the
+  // gradient entries below, in the same memory round trip)
+  for (int o = threadIdx.x; o < TI * TJ; o += NTHREADS) {
+    const int i = (o & (TI - 1)), j = (o >> (__ffs(TI) - 1));
+    const size_t g = (i0 + i) + (size_t)(j0 + j) * m;
+    const T rv = Xs[xs_at<SEP>(i, j, H, TI, TJ)];
+    stv(r1b, g, rv);
+    accr += (double)rv * (double)rv;
+  }
   const size_t nx = (size_t)(m - 1) * m;
   // Gradient part: LT[i, j] = sqrt(g) (L^T (w r2_new))[i, j] for the tile,
   // computed cooperatively (coalesced loads, all threads) into LDS, and
@@ -260,8 +252,9 @@ __device__ __forceinline__ void cgls_p2_body(const Job* __restrict__ jobs,
   T* LT = nullptr;
   auto grad_part = [&](T* buf) {
     LT = buf;
-    // per pixel: entries qx(i-1,j), qx(i,j), qy(i,j-1), qy(i,j) -> (r2a, q2, w)
-    batched_pixels<P2_GRAD_BATCH, 12, T>(
+    // per pixel: entries qx(i-1,j), qx(i,j), qy(i,j-1), qy(i,j) -> (r2a, q2, w),
+    // then x and p for x += alpha p
+    batched_pixels<P2_GRAD_BATCH, 14, T>(
         TI * TJ,
         [&](int o, T* v) {
           const int gi = i0 + (o & (TI - 1)), gj = j0 + (o >> (__ffs(TI) - 1));
@@ -277,6 +270,10 @@ __device__ __forceinline__ void cgls_p2_body(const Job* __restrict__ jobs,
             v[3 * d] = ok[d] ? ldv<T>(r2a, ks[d]) : T(0);
             v[3 * d + 1] = (ok[d] && !first) ? ldv<T>(q2, ks[d]) : T(0);
             v[3 * d + 2] = (ok[d] && irls) ? w[ks[d]] : T(1);
+          }
+          if (!first) {
+            v[12] = x[g];
+            v[13] = ldv<T>(p, g);
           }
         },
         [&](int o, T* v) {
@@ -300,6 +297,7 @@ __device__ __forceinline__ void cgls_p2_body(const Job* __restrict__ jobs,
             lt -= (double)v[11] * (double)rn[3];
           }
           buf[i + j * TI] = (T)(sg * lt);
+          if (!first) x[g] = v[12] + ta * v[13];
         });
     __syncthreads();
   };
