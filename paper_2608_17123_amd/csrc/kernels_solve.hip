@@ -77,8 +77,8 @@ __global__ void __launch_bounds__(NTHREADS) k_cgls_init(const Job* __restrict__ 
 constexpr int P1_V_NARROW = 2, P1_V_WIDE = 2;
 constexpr int P2_V_NARROW = 2, P2_V_WIDE = 2;
 constexpr int STATS_V = 2;
-// Pixels whose loads each thread issues together in the pointwise passes.
-constexpr int P1_BATCH = 4, P2_GRAD_BATCH = 2;
+// Pixels whose gradient-entry loads each thread issues together in phase 2.
+constexpr int P2_GRAD_BATCH = 2;
 // Launches of more tiles than this (5 resident 256-thread blocks on each of
 // 256 CUs at the unconstrained register use) take the _wide phase kernels.
 constexpr int P2_WIDE_TILES = 5 * 256;
@@ -107,7 +107,28 @@ __device__ __forceinline__ void cgls_p1_body(const Job* __restrict__ jobs,
   S* __restrict__ q1 = vp<S>(job, V_Q1);
   S* __restrict__ q2 = vp<S>(job, V_Q2);
   const T* __restrict__ w = vp<T>(job, V_W);
+  const size_t nx = (size_t)(m - 1) * m;
+  // IRLS weights of the thread's pixels (o = tid + u NTHREADS; a tile has at
+  // most 32 x 32 pixels), requested with the tile so that they share its
+  // memory round trip
+  constexpr int WPT = 32 * 32 / NTHREADS;
+  T wv[2 * WPT];
+  auto load_w = [&]() {
+#pragma unroll
+    for (int u = 0; u < WPT; ++u) {
+      const int o = threadIdx.x + u * NTHREADS;
+      wv[2 * u] = T(1);
+      wv[2 * u + 1] = T(1);
+      if (irls && o < TI * TJ) {
+        const int gi = i0 + (o & (TI - 1)), gj = j0 + (o >> (__ffs(TI) - 1));
+        const size_t g = gi + (size_t)gj * m;
+        if (gi < m - 1) wv[2 * u] = w[gi + (size_t)gj * (m - 1)];
+        if (gj < m - 1) wv[2 * u + 1] = w[nx + g];
+      }
+    }
+  };
   if (job->flags & F_FIRST) {  // p = s
+    load_w();
     load_tile<T, SEP>(Xs, xs_ld<SEP>(H, TI, TJ), i0, j0, TI, TJ, H, m,
                       [&](int g) { return rtv<S>(ldv<T>(s, g) + T(0) * ldv<T>(pa, g)); });
   } else {
@@ -117,6 +138,7 @@ __device__ __forceinline__ void cgls_p1_body(const Job* __restrict__ jobs,
         Xs, xs_ld<SEP>(H, TI, TJ), i0, j0, TI, TJ, H, m,
         [&](int g) { return ldv<T>(s, g); }, [&](int g) { return ldv<T>(pa, g); },
         [&]() {
+          load_w();
           double gcur, gprev;
           sum_partials2<2, 2>(job->pr[0], 0, job->pr[1], 0, nt, red, bc2, gcur, gprev);
           const double beta = gprev > 0.0 ? gcur / gprev : 0.0;
@@ -131,33 +153,29 @@ __device__ __forceinline__ void cgls_p1_body(const Job* __restrict__ jobs,
   }
   __syncthreads();
   double acc = 0.0;
-  const size_t nx = (size_t)(m - 1) * m;
-  batched_pixels<P1_BATCH, 2, T>(
-      TI * TJ,
-      [&](int o, T* v) {
-        const int gi = i0 + (o & (TI - 1)), gj = j0 + (o >> (__ffs(TI) - 1));
-        const size_t g = gi + (size_t)gj * m;
-        v[0] = (irls && gi < m - 1) ? w[gi + (size_t)gj * (m - 1)] : T(1);
-        v[1] = (irls && gj < m - 1) ? w[nx + g] : T(1);
-      },
-      [&](int o, T* v) {
-        const int i = (o & (TI - 1)), j = (o >> (__ffs(TI) - 1)), gi = i0 + i, gj = j0 + j;
-        const size_t g = gi + (size_t)gj * m;
-        const T pc = Xs[xs_at<SEP>(i, j, H, TI, TJ)];
-        stv(pb, g, pc);
-        if (gi < m - 1) {
-          const double d = ((double)Xs[xs_at<SEP>(i + 1, j, H, TI, TJ)] - (double)pc) * (double)v[0];
-          const T qv = rtv<S>((T)(sg * d));
-          stv(q2, gi + (size_t)gj * (m - 1), qv);
-          acc += (double)qv * (double)qv;
-        }
-        if (gj < m - 1) {
-          const double d = ((double)Xs[xs_at<SEP>(i, j + 1, H, TI, TJ)] - (double)pc) * (double)v[1];
-          const T qv = rtv<S>((T)(sg * d));
-          stv(q2, nx + g, qv);
-          acc += (double)qv * (double)qv;
-        }
-      });
+#pragma unroll
+  for (int u = 0; u < WPT; ++u) {
+    const int o = threadIdx.x + u * NTHREADS;
+    if (o < TI * TJ) {
+      const T* v = wv + 2 * u;
+      const int i = (o & (TI - 1)), j = (o >> (__ffs(TI) - 1)), gi = i0 + i, gj = j0 + j;
+      const size_t g = gi + (size_t)gj * m;
+      const T pc = Xs[xs_at<SEP>(i, j, H, TI, TJ)];
+      stv(pb, g, pc);
+      if (gi < m - 1) {
+        const double d = ((double)Xs[xs_at<SEP>(i + 1, j, H, TI, TJ)] - (double)pc) * (double)v[0];
+        const T qv = rtv<S>((T)(sg * d));
+        stv(q2, gi + (size_t)gj * (m - 1), qv);
+        acc += (double)qv * (double)qv;
+      }
+      if (gj < m - 1) {
+        const double d = ((double)Xs[xs_at<SEP>(i, j + 1, H, TI, TJ)] - (double)pc) * (double)v[1];
+        const T qv = rtv<S>((T)(sg * d));
+        stv(q2, nx + g, qv);
+        acc += (double)qv * (double)qv;
+      }
+    }
+  }
   auto epi1 = [&](int i, int j, T v) {
     const T qv = rtv<S>(v);
     stv(q1, (i0 + i) + (size_t)(j0 + j) * m, qv);
@@ -170,7 +188,7 @@ __device__ __forceinline__ void cgls_p1_body(const Job* __restrict__ jobs,
 }
 
 // Phase 1 compiled twice, as phase 2 below: k_cgls_p1_wide (register bound
-// of 6 waves per SIMD for FP32 up to radius bucket 8: 78 VGPRs, no spills)
+// of 6 waves per SIMD for FP32 up to radius bucket 8: 75 VGPRs, no spills)
 // for launches of more than P2_WIDE_TILES tiles, k_cgls_p1 otherwise.
 template <typename T, typename S, int RB, bool SEP>
 __global__ void __launch_bounds__(NTHREADS, (waves_per_simd<T, RB>()))
