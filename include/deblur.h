@@ -300,7 +300,12 @@ size_t dbl_request_bytes(const dbl_request* req);
  * valid until the ticket completes. */
 int dbl_server_submit(dbl_server* srv, const dbl_request* req, int64_t* ticket);
 /* Advance the server by one outer-iteration step (admits, computes,
- * retires).  *active receives the number of resident solves afterwards. */
+ * retires).  *active receives the number of resident solves afterwards.
+ * A request whose workspace or hierarchy cannot be set up completes at
+ * once: its ticket's report carries the error in `status` (DBL_ENOMEM when
+ * it does not fit even with no other solve resident) and admission goes on
+ * with the next request.  Out of memory while other solves are resident
+ * only defers the request until they retire. */
 int dbl_server_step(dbl_server* srv, int* active);
 /* *done = 1 when the ticket has completed; then rep (may be NULL) receives
  * its report and the ticket is released. */

@@ -167,6 +167,39 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _dtype_of(precision):
+    """torch element type of every caller-visible vector at `precision`
+    (DBL_BF16 keeps b, x, weights and shifts in float32 at the API)."""
+    import torch
+    return {DBL_F32: torch.float32, DBL_BF16: torch.float32, DBL_F64: torch.float64}.get(precision)
+
+
+def _dev(t, precision, elems, what, optional=False):
+    """Pointer of a device tensor after checking what the library cannot:
+    that it is a contiguous cuda tensor of the element type `precision` asks
+    for and holds at least the `elems` elements the call reads or writes.
+    The C ABI takes bare pointers, so a short or mistyped buffer would
+    otherwise be written past its end on the device."""
+    if t is None:
+        if optional:
+            return None
+        raise ValueError(f"{what} is required")
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{what}: device tensors must be contiguous cuda tensors")
+    want = _dtype_of(precision)
+    if want is not None and t.dtype != want:
+        raise ValueError(f"{what}: dtype {t.dtype} does not match precision {precision} "
+                         f"(needs {want})")
+    if t.numel() < elems:
+        raise ValueError(f"{what}: {t.numel()} elements, the call touches {elems}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _nl(m):
+    """Length of a gradient-space vector on an m x m grid."""
+    return 2 * m * (m - 1)
+
+
 def _psf_arg(psf):
     """Host kernel as a column-major float64 array (PSF[a, b] -> a + b*ph)."""
     P = np.asfortranarray(np.asarray(psf, dtype=np.float64))
@@ -298,63 +331,83 @@ def dbl_op_destroy(op):
     op.close()
 
 
+def _level_m(op, level):
+    if not 0 <= int(level) < op.levels:
+        raise ValueError(f"level {level} outside [0, {op.levels})")
+    return op.m >> int(level)
+
+
 def dbl_apply_A(ctx, op, level, transpose, x_in, x_out):
-    _check(ctx, lib().dbl_apply_A(ctx.handle, op.handle, level, int(transpose), _ptr(x_in),
-                                  _ptr(x_out)))
+    n = _level_m(op, level) ** 2
+    pi, po = _dev(x_in, op.precision, n, "x_in"), _dev(x_out, op.precision, n, "x_out")
+    _check(ctx, lib().dbl_apply_A(ctx.handle, op.handle, level, int(transpose), pi, po))
 
 
 def dbl_apply_L(ctx, m, precision, transpose, x_in, x_out):
-    _check(ctx, lib().dbl_apply_L(ctx.handle, m, precision, int(transpose), _ptr(x_in),
-                                  _ptr(x_out)))
+    n, nl = m * m, _nl(m)
+    pi = _dev(x_in, precision, nl if transpose else n, "x_in")
+    po = _dev(x_out, precision, n if transpose else nl, "x_out")
+    _check(ctx, lib().dbl_apply_L(ctx.handle, m, precision, int(transpose), pi, po))
 
 
 def dbl_dwt(ctx, wavelet, m, precision, inverse, lowpass_only, x_in, x_out):
     wavelet = WAVELETS.get(wavelet, wavelet)
+    fine, coarse = m * m, (m // 2) ** 2
+    n_in = coarse if (inverse and lowpass_only) else fine
+    n_out = coarse if (lowpass_only and not inverse) else fine
+    pi, po = _dev(x_in, precision, n_in, "x_in"), _dev(x_out, precision, n_out, "x_out")
     _check(ctx, lib().dbl_dwt(ctx.handle, wavelet, m, precision, int(inverse),
-                              int(lowpass_only), _ptr(x_in), _ptr(x_out)))
+                              int(lowpass_only), pi, po))
 
 
 def dbl_dtransfer(ctx, wavelet, m_coarse, precision, q_in, q_out):
     wavelet = WAVELETS.get(wavelet, wavelet)
-    _check(ctx, lib().dbl_dtransfer(ctx.handle, wavelet, m_coarse, precision, _ptr(q_in),
-                                    _ptr(q_out)))
+    pi = _dev(q_in, precision, _nl(m_coarse), "q_in")
+    po = _dev(q_out, precision, _nl(2 * m_coarse), "q_out")
+    _check(ctx, lib().dbl_dtransfer(ctx.handle, wavelet, m_coarse, precision, pi, po))
 
 
-def _sub(d_kind, w, gamma, c):
+def _sub(d_kind, w, gamma, c, precision, m):
     s = dbl_sub()
     s.d_kind = d_kind
-    s.w = _ptr(w)
+    s.w = _dev(w, precision, _nl(m), "w", optional=True)
     s.gamma = float(gamma)
-    s.c = _ptr(c)
+    s.c = _dev(c, precision, _nl(m), "c", optional=True)
     return s
 
 
 def _krylov(entry, ctx, op, level, b, iters, x, gamma, w, c, x0, d_kind):
     if d_kind is None:
         d_kind = 1 if w is not None else 0
-    s = _sub(d_kind, w, gamma, c)
+    mi = _level_m(op, level)
+    s = _sub(d_kind, w, gamma, c, op.precision, mi)
+    n = mi * mi
+    pb, p0 = _dev(b, op.precision, n, "b"), _dev(x0, op.precision, n, "x0", True)
+    px = _dev(x, op.precision, n, "x")
     hist = np.zeros(max(iters, 1), dtype=np.float64)
-    _check(ctx, entry(ctx.handle, op.handle, level, ctypes.byref(s), _ptr(b), _ptr(x0), iters,
-                      _ptr(x), hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    _check(ctx, entry()(ctx.handle, op.handle, level, ctypes.byref(s), pb, p0, iters, px,
+                        hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
     return hist[:iters]
 
 
 def dbl_cgls(ctx, op, level, b, iters, x, gamma, w=None, c=None, x0=None, d_kind=None):
     """Run `iters` CGLS steps; returns the FP64 residual history."""
-    return _krylov(lib().dbl_cgls, ctx, op, level, b, iters, x, gamma, w, c, x0, d_kind)
+    return _krylov(lambda: lib().dbl_cgls, ctx, op, level, b, iters, x, gamma, w, c, x0, d_kind)
 
 
 def dbl_lsqr(ctx, op, level, b, iters, x, gamma, w=None, c=None, x0=None, d_kind=None):
     """Run `iters` LSQR steps; returns LSQR's FP64 residual estimates."""
-    return _krylov(lib().dbl_lsqr, ctx, op, level, b, iters, x, gamma, w, c, x0, d_kind)
+    return _krylov(lambda: lib().dbl_lsqr, ctx, op, level, b, iters, x, gamma, w, c, x0, d_kind)
 
 
 def dbl_gcv(ctx, op, level, b, w=None, c=None, mode=DBL_GCV_SPECTRAL, grid=50):
     """GCV choice of gamma; returns (gamma, GCV(gamma))."""
     mode = GCV_MODES.get(mode, mode)
-    s = _sub(1 if w is not None else 0, w, 0.0, c)
+    mi = _level_m(op, level)
+    s = _sub(1 if w is not None else 0, w, 0.0, c, op.precision, mi)
     g, f = ctypes.c_double(), ctypes.c_double()
-    _check(ctx, lib().dbl_gcv(ctx.handle, op.handle, level, ctypes.byref(s), _ptr(b), mode, grid,
+    pb = _dev(b, op.precision, mi * mi, "b")
+    _check(ctx, lib().dbl_gcv(ctx.handle, op.handle, level, ctypes.byref(s), pb, mode, grid,
                               ctypes.byref(g), ctypes.byref(f)))
     return g.value, f.value
 
@@ -363,18 +416,29 @@ def dbl_deblur(ctx, b, psf, m, solver, wavelet, levels, transfer, x, opts=None):
     """Full V-cycle solve; returns the report as a dict."""
     keep, p, ph, pw = _psf_arg(psf)
     opts = opts if opts is not None else dbl_opts_default()
+    pb, px = _image_args(b, x, m, opts)
     rep = dbl_report()
-    _check(ctx, lib().dbl_deblur(ctx.handle, _ptr(b), p, ph, pw, m, SOLVERS.get(solver, solver),
+    _check(ctx, lib().dbl_deblur(ctx.handle, pb, p, ph, pw, m, SOLVERS.get(solver, solver),
                                  WAVELETS.get(wavelet, wavelet), levels,
-                                 TRANSFERS.get(transfer, transfer), ctypes.byref(opts), _ptr(x),
+                                 TRANSFERS.get(transfer, transfer), ctypes.byref(opts), px,
                                  ctypes.byref(rep)))
     return rep.to_dict()
+
+
+def _image_args(b, x, m, opts):
+    """Checked pointers of a solve's b and x (m x m each), after checking the
+    optional iterate history (k_out slices of m x m) the options carry."""
+    n = m * m
+    hist = getattr(opts, "_hist", None)
+    if hist is not None:
+        _dev(hist, opts.precision, max(opts.k_out, 0) * n, "x_hist")
+    return _dev(b, opts.precision, n, "b"), _dev(x, opts.precision, n, "x")
 
 
 def make_request(b, x, psf, m, solver, wavelet, levels, transfer, opts):
     keep, p, ph, pw = _psf_arg(psf)
     r = dbl_request()
-    r.b, r.x = _ptr(b), _ptr(x)
+    r.b, r.x = _image_args(b, x, m, opts)
     r.psf, r.ph, r.pw, r.m = p, ph, pw, m
     r.solver = SOLVERS.get(solver, solver)
     r.wavelet = WAVELETS.get(wavelet, wavelet)

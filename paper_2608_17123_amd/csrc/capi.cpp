@@ -427,7 +427,7 @@ int krylov_entry(dbl_ctx* ctx, const dbl_op* op, int level, const dbl_sub* sub, 
   const size_t n = (size_t)m * m, nl = 2 * (size_t)m * (m - 1);
   auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
   const size_t need = 6 * al(n * ssz) + 3 * al(nl * ssz) + al(n * esz) + al(NSCAL * 8) +
-                      al(part_doubles(m) * 8) + 256;
+                      al(part_doubles(m) * 8);
   int rc = DBL_OK;
   if (ctx->scratch_bytes < need) {
     if ((rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "sync"))) return rc;
@@ -448,8 +448,6 @@ int krylov_entry(dbl_ctx* ctx, const dbl_op* op, int level, const dbl_sub* sub, 
   void* AX0 = take(n * esz);  // A x0 (compute type)
   double* scal = static_cast<double*>(take(NSCAL * 8));
   double* part = static_cast<double*>(take(part_doubles(m) * 8));
-  unsigned* cnt = static_cast<unsigned*>(take(256));
-  if ((rc = hip_check(ctx, hipMemsetAsync(cnt, 0, 256, ctx->stream), "clear"))) return rc;
   const double gv[2] = {sub->gamma, std::sqrt(sub->gamma)};
   void* dg = nullptr;
   if ((rc = stage(ctx, gv, sizeof(gv), &dg))) return rc;
@@ -462,7 +460,6 @@ int krylov_entry(dbl_ctx* ctx, const dbl_op* op, int level, const dbl_sub* sub, 
   j.op = op->d_ops + level;
   j.scal = scal;
   j.part = part;
-  j.cnt = cnt;
   j.flags = (sub->d_kind == 1 ? F_IRLS : 0) | (sub->c ? F_SHIFT : 0) | F_HIST;
   j.v[V_X] = x;
   j.v[V_S] = S;
@@ -650,13 +647,11 @@ int dbl_gcv(dbl_ctx* ctx, const dbl_op* op, int level, const dbl_sub* sub, const
   g.tmp = static_cast<double*>(take(n * 8));
   g.in = static_cast<double*>(take(n * 8));
   g.scal = static_cast<double*>(take(NSCAL * 8));
-  g.cnt = static_cast<unsigned*>(take(256));
   g.part = static_cast<double*>(take(part_doubles(m) * 8));
   g.bh_valid = false;
   g.grid = grid;
   g.mode = mode;
-  rc = hip_check(ctx, hipMemsetAsync(g.cnt, 0, 256, ctx->stream), "clear");
-  if (!rc) rc = hip_check(ctx, hipMemsetAsync(g.scal, 0, NSCAL * 8, ctx->stream), "clear");
+  rc = hip_check(ctx, hipMemsetAsync(g.scal, 0, NSCAL * 8, ctx->stream), "clear");
   std::vector<GcvReq> v{g};
   if (!rc) rc = gcv_run(ctx, v);
   double out[2] = {0, 0};

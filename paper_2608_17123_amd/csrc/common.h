@@ -137,7 +137,6 @@ struct Job {
   void* v[16];      // vectors (meaning set by each kernel)
   double* scal;     // FP64 scalar block
   double* part;     // FP64 partials, >= 4 per tile
-  unsigned* cnt;    // completion counter (reset by the last block)
   double p0, p1;    // extra scalars passed by value
   int i0, i1;       // extra integers passed by value
   double* hist;     // per-solve history (gamma, rc, objective) for stats kernels

@@ -240,7 +240,6 @@ int gcv_run(dbl_ctx* ctx, std::vector<GcvReq>& reqs) {
     j.m = m;
     j.scal = r.scal;
     j.part = r.part;
-    j.cnt = r.cnt;
     j.v[G_B] = const_cast<void*>(r.b);
     j.v[G_W] = const_cast<void*>(r.w);
     j.v[G_C1] = const_cast<void*>(r.c1);

@@ -493,7 +493,7 @@ size_t slot_bytes(const dbl_request& req) {
   // buffers and swaps them with the originals); q2
   b += 5 * align256(nl * esz) + align256(nl * ssz);
   for (int i = 1; i < req.levels; ++i) b += align256(((size_t)req.m >> i) * (req.m >> i) * esz);
-  b += align256(NSCAL * 8) + align256(part_doubles(req.m) * 8) + 256;
+  b += align256(NSCAL * 8) + align256(part_doubles(req.m) * 8);
   b += align256((size_t)req.levels * DBL_MAX_KOUT * 3 * 8);
   if (wants_gcv(req.opts)) b += 4 * align256(n * 8);
   return b;
@@ -555,7 +555,6 @@ int slot_init(dbl_ctx* ctx, const dbl_request& req, Slot* s) {
   for (int i = 1; i < req.levels; ++i) s->B[i] = take(((size_t)req.m >> i) * (req.m >> i) * e);
   s->scal = static_cast<double*>(take(NSCAL * 8));
   s->part = static_cast<double*>(take(part_doubles(req.m) * 8));
-  s->cnt = static_cast<unsigned*>(take(256));
   s->hist = static_cast<double*>(take((size_t)req.levels * DBL_MAX_KOUT * 3 * 8));
   if (s->gcv) {
     s->g_bh = static_cast<double*>(take(n * 8));
@@ -563,8 +562,7 @@ int slot_init(dbl_ctx* ctx, const dbl_request& req, Slot* s) {
     s->g_tmp = static_cast<double*>(take(n * 8));
     s->g_in = static_cast<double*>(take(n * 8));
   }
-  rc = hip_check(ctx, hipMemsetAsync(s->cnt, 0, 256, ctx->stream), "clear counters");
-  if (!rc) rc = hip_check(ctx, hipMemsetAsync(s->scal, 0, NSCAL * 8, ctx->stream), "clear scalars");
+  rc = hip_check(ctx, hipMemsetAsync(s->scal, 0, NSCAL * 8, ctx->stream), "clear scalars");
   if (!rc)
     rc = hip_check(ctx, hipMemsetAsync(s->hist, 0xff, (size_t)req.levels * DBL_MAX_KOUT * 3 * 8,
                                        ctx->stream),
@@ -645,7 +643,6 @@ Job base_job(const Slot* s, int level) {
   j.op = s->op->d_ops + level;
   j.scal = s->scal;
   j.part = s->part;
-  j.cnt = s->cnt;
   j.hist = s->hist;
   return j;
 }
@@ -1048,7 +1045,6 @@ int engine_step(dbl_ctx* ctx, std::vector<Slot*>& slots) {
       g.c2 = s->solver == DBL_SB ? s->C2 : nullptr;
       g.scal = s->scal;
       g.part = s->part;
-      g.cnt = s->cnt;
       g.bh = s->g_bh;
       g.e = s->g_e;
       g.tmp = s->g_tmp;

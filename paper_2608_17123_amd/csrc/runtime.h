@@ -200,7 +200,6 @@ struct Slot {
   std::vector<const void*> B;  // b per level (B[0] = caller's b)
   double* scal = nullptr;
   double* part = nullptr;
-  unsigned* cnt = nullptr;
   double* hist = nullptr;  // levels * k_out * 3 (gamma, rc, objective)
   double* g_bh = nullptr;  // GCV: DCT of b (per level, recomputed on entry)
   double* g_e = nullptr;   // GCV: per-frequency residual numerator
@@ -237,7 +236,6 @@ struct GcvReq {
   const void* c2;    // shift part 2 (SB: c = c1 - c2) or null
   double* scal;
   double* part;
-  unsigned* cnt;
   double* bh;        // FP64 n: DCT(b) (computed when !bh_valid)
   double* e;         // FP64 n
   double* tmp;       // FP64 n

@@ -108,12 +108,23 @@ int dbl_server_step(dbl_server* srv, int* active) {
     if (srv->budget && srv->used + bytes > srv->budget) break;
     auto sl = std::make_unique<Slot>();
     rc = slot_init(ctx, p->req, sl.get());
-    if (rc == DBL_ENOMEM) {
+    if (rc) {
       slot_free(ctx, sl.get());
-      if (srv->resident.empty()) return rc;  // cannot ever fit
-      break;
+      // out of memory while other solves hold workspace: retry once they retire
+      if (rc == DBL_ENOMEM && !srv->resident.empty()) break;
+      // otherwise this request can never start: it finishes now with the
+      // error as its status, and admission goes on with the next one
+      Finished f;
+      std::memset(&f.rep, 0, sizeof(f.rep));
+      f.rep.levels = p->req.levels;
+      f.rep.k_out = p->req.opts.k_out;
+      f.rep.status = rc;
+      f.rep.seconds = now_s() - p->t_submit;
+      srv->finished[p->ticket] = f;
+      srv->queue.pop_front();
+      rc = DBL_OK;
+      continue;
     }
-    if (rc) return rc;
     sl->ticket = p->ticket;
     sl->t_submit = p->t_submit;
     srv->used += bytes;

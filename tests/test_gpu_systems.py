@@ -151,6 +151,52 @@ def test_server_budget_admission(ctx):
     srv.close()
 
 
+def test_server_request_that_cannot_start_completes_with_its_error():
+    """A request whose workspace can never be allocated (the context's HBM
+    cap is below its footprint although the server has no cap) finishes with
+    DBL_ENOMEM in its report, and the requests queued behind it are still
+    admitted and solved -- the server does not retry it forever."""
+    kw = dict(k_out=3, k_in=8, gcv_mode="spectral")
+    small_w, big = synth.config4(1, start=0)[0], synth.config4(1, start=40)[0]
+    assert (small_w.m, big.m) == (64, 512)
+    small_b, big_b = dev(blurred(small_w)), dev(blurred(big))
+    big_x = torch.zeros_like(big_b)
+    r_big = D.make_request(big_b, big_x, big.psf, big.m, big.solver, big.wavelet, big.levels,
+                           big.transfer, D.dbl_opts_default(**kw))
+    small_x = torch.zeros_like(small_b)
+    r_small = D.make_request(small_b, small_x, small_w.psf, small_w.m, small_w.solver,
+                             small_w.wavelet, small_w.levels, small_w.transfer,
+                             D.dbl_opts_default(**kw))
+    need_big, need_small = D.dbl_request_bytes(r_big), D.dbl_request_bytes(r_small)
+    assert need_big > 4 * need_small
+    # room for the staging ring, one small solve and its hierarchy, not the big one
+    cap = (16 << 20) + 2 * need_small
+    assert cap < need_big
+    c = D.dbl_create(0, budget=cap)
+    try:
+        srv = D.dbl_server_create(c, max_slots=4)
+        t_big = D.dbl_server_submit(srv, r_big)
+        t_small = D.dbl_server_submit(srv, r_small)
+        reps = {}
+        for _ in range(200):
+            D.dbl_server_step(srv)
+            for t in (t_big, t_small):
+                if t not in reps:
+                    rep = D.dbl_server_poll(srv, t)
+                    if rep is not None:
+                        reps[t] = rep
+            if len(reps) == 2:
+                break
+        assert len(reps) == 2
+        assert reps[t_big]["status"] == D.DBL_ENOMEM
+        assert reps[t_small]["status"] == 0
+        srv.close()
+    finally:
+        c.close()
+    xa, _ = solve_alone(ctx, small_w, small_b, kw)
+    assert np.array_equal(host(small_x), xa)
+
+
 @pytest.mark.parametrize("prec", [D.DBL_F32, D.DBL_F64])
 def test_config1_gcv_on_matches_oracle(ctx, prec):
     """m = 64, 3 grids, IRLS two-pass GCV (spectral tier on both sides),
