@@ -1,27 +1,41 @@
 #!/usr/bin/env python3
 """Benchmark of the multilevel l1 deblurring hot path on one MI355X.
 
-One step = one batched V-cycle solve of the whole workload (every step of the
-path: restriction, level solves with auxiliary updates, GCV, CGLS,
-statistics, transfers), inputs already resident in HBM.
+One step = one batched solve of the whole workload (every step of the path:
+restriction, level solves with auxiliary updates, GCV, CGLS, statistics,
+transfers), inputs already resident in HBM.
 
-Default workload (m = 256, the single-image configuration): one seeded
-piecewise-constant image with 60 shapes, Gaussian blur sigma 2.5 on a 15 x 15
-support, noise 1% and 5%, every solver (IRLS, MM, SB) x wavelet (Haar, Db4) x
-transfer (X, D): 24 solves, 4 grids, 10 outer x 30 CGLS iterations, FP32
-vectors with FP64 scalars, GCV (spectral tier) on the device.
+Default workload: the batched form -- 256 seeded images with m drawn from
+{64, 128, 256, 512}, Gaussian blur sigma ~ U[1, 4] on a (2 ceil(3 sigma) + 1)^2
+support, noise ~ U[0.5%, 5%], solver (IRLS, MM, SB), wavelet (Haar, Db4) and
+transfer (X, D) drawn uniformly, min(5, log2 m - 4) grids, 10 outer x 30 CGLS
+iterations, FP32 vectors with FP64 scalars, GCV (spectral tier) on the device.
+``--workload c2`` runs the 24 solves of the m = 256 single-image form instead.
 
-Printed: one JSON line with solves/s of the batched path (value), the plain
-one-solve-at-a-time path on the same workload, the roofline of the dominant
-kernel (HIP events inside this process; HBM traffic from the committed
-rocprofv3 counter record when it was taken on the current kernel sources),
-the serving leg (Poisson arrivals of the same requests into the
-continuous-batching server against the plain path fed the same trace: p50/p99
-latency and solves/s), and the FP64 oracle timed on the host cores
-(cpu_baseline) together with the GPU result's error against it.
+Printed: one JSON line with
+* value: solves/s of the batched path, and the plain one-solve-at-a-time path
+  on the same work;
+* roofline of the dominant kernel family: its algorithmic bytes per launch
+  (the fused minimum of a CGLS iteration) over its mean launch duration from
+  HIP events on the library stream, against 8 TB/s; HBM traffic from the
+  committed rocprofv3 counter record when that was taken on the current
+  kernel sources;
+* operators: A / A^T, L / L^T and the wavelet restriction / prolongation on
+  16 images of 2048 x 2048 (512 MB per FP32 image set, twice the Infinity
+  Cache), batched in one launch each, against the same peak;
+* serving: Poisson arrivals at several rates of requests with m from
+  {128, ..., 2048} (weights 4:4:3:2:1) and Gaussian or motion blur into the
+  continuous-batching server, against the plain path fed the same trace:
+  p50 / p99 latency and solves/s;
+* cpu_baseline: the FP64 oracle on a bounded sample of the workload (the
+  first 16 solves with m <= 128, full 10 x 30 solves with spectral GCV, data
+  built by the oracle's own blur) in a pool of single-threaded workers, and
+  the relative error of the timed batch's outputs for those solves against
+  it (rel_err_vs_oracle).
 
 --calib-copy runs only a plain 1 GiB device-to-device copy (three times): the
 known-size kernel that scales the FETCH_SIZE / WRITE_SIZE counters.
+--profile-run runs one batch of the workload and nothing else (for rocprofv3).
 """
 import argparse
 import json
@@ -37,8 +51,12 @@ sys.path.insert(0, ROOT)
 
 METRIC = "solves/s batched vs plain at rel.err<=1e-4 vs FP64; p99 latency; HBM GB/s"
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_RECORD = {"c2": os.path.join(ROOT, "profiles", "traffic_cgls_p2_m256_batch24.json")}
+TRAFFIC_RECORD = {
+    "c4": os.path.join(ROOT, "profiles", "traffic_cgls_p2_c4_batch256.json"),
+    "c2": os.path.join(ROOT, "profiles", "traffic_cgls_p2_m256_batch24.json"),
+}
 CALIB_BYTES = 1 << 30
+CPU_SAMPLE = 16
 
 
 def parse():
@@ -46,13 +64,16 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=1)
-    p.add_argument("--workload", default="c2", choices=["c2", "c4"])
+    p.add_argument("--workload", default="c4", choices=["c4", "c2"])
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-plain", action="store_true")
     p.add_argument("--no-serve", action="store_true")
-    p.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrivals per second")
-    p.add_argument("--serve-requests", type=int, default=128)
+    p.add_argument("--no-operators", action="store_true")
+    p.add_argument("--serve-rates", default="30,300,1000",
+                   help="Poisson arrival rates (requests per second), comma separated")
+    p.add_argument("--serve-requests", type=int, default=48, help="requests per rate")
     p.add_argument("--calib-copy", action="store_true")
+    p.add_argument("--profile-run", action="store_true")
     p.add_argument("--precision", default="f32", choices=["f32", "bf16", "f64"],
                    help="vector storage: FP32, BF16 CGLS state with FP32 arithmetic, or FP64")
     p.add_argument("--inner", default="cgls", choices=["cgls", "lsqr"],
@@ -69,143 +90,257 @@ def calib_copy(torch):
     print(json.dumps({"calib_copy_bytes_each_way": CALIB_BYTES, "copies": 3}))
 
 
-def serve_leg(D, torch, ctx, items, opts_kw, rate, nreq, seed=11):
-    """Poisson arrivals (rate per second) of nreq requests cycling through the
-    workload's solves.  Served: the continuous-batching server (arrivals are
-    submitted as they come, every step advances all resident solves).  Plain:
-    the same trace solved one request at a time in arrival order.  Latency =
-    completion - arrival, host clock."""
-    rng = np.random.default_rng(seed)
-    arr = np.cumsum(rng.exponential(1.0 / rate, nreq))
-    reqs, xs = [], []
-    for q in range(nreq):
-        w, b, _ = items[q % len(items)]
-        x = torch.zeros_like(b)
-        xs.append(x)
-        reqs.append(D.make_request(b, x, w.psf, w.m, w.solver, w.wavelet, w.levels, w.transfer,
-                                   D.dbl_opts_default(k_out=w.k_out, k_in=w.k_in, **opts_kw)))
-    torch.cuda.synchronize()
-
-    srv = D.dbl_server_create(ctx, max_slots=64)
-    lat = np.zeros(nreq)
-    tickets = {}
-    sub = done = 0
-    max_active = 0
-    t0 = time.perf_counter()
-    while done < nreq:
-        now = time.perf_counter() - t0
-        while sub < nreq and arr[sub] <= now:
-            tickets[D.dbl_server_submit(srv, reqs[sub])] = sub
-            sub += 1
-        if not tickets:
-            time.sleep(max(0.0, arr[sub] - now))
-            continue
-        max_active = max(max_active, D.dbl_server_step(srv))
-        for t, q in list(tickets.items()):
-            if D.dbl_server_poll(srv, t) is not None:
-                lat[q] = time.perf_counter() - t0 - arr[q]
-                del tickets[t]
-                done += 1
-    t_served = time.perf_counter() - t0
-    srv.close()
-
-    plat = np.zeros(nreq)
-    t0 = time.perf_counter()
-    for q in range(nreq):
-        now = time.perf_counter() - t0
-        if arr[q] > now:
-            time.sleep(arr[q] - now)
-        w, b, _ = items[q % len(items)]
-        D.dbl_deblur(ctx, b, w.psf, w.m, w.solver, w.wavelet, w.levels, w.transfer, xs[q],
-                     D.dbl_opts_default(k_out=w.k_out, k_in=w.k_in, **opts_kw))
-        plat[q] = time.perf_counter() - t0 - arr[q]
-    t_plain = time.perf_counter() - t0
-
-    def pct(a, p):
-        return round(1e3 * float(np.percentile(a, p)), 2)
-
-    return {
-        "arrivals": f"Poisson, {rate:g} requests/s, {nreq} requests cycling through the workload",
-        "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
-        "solves_per_s": round(nreq / t_served, 2), "max_resident": max_active,
-        "plain_p50_ms": pct(plat, 50), "plain_p99_ms": pct(plat, 99),
-        "plain_solves_per_s": round(nreq / t_plain, 2),
-    }
+def device_data(D, torch, ctx, w, dt):
+    """b = A x_true + e on the device (A from the library, e at the stated
+    relative level along the seeded direction)."""
+    op = D.dbl_op_create(ctx, w.psf, w.m, 1, "haar",
+                         D.DBL_F64 if dt == torch.float64 else D.DBL_F32)
+    xt = torch.from_numpy(np.ascontiguousarray(w.x_true.ravel(order="F"))).to("cuda", dt)
+    bt = torch.empty_like(xt)
+    D.dbl_apply_A(ctx, op, 0, 0, xt, bt)
+    op.close()
+    xi = torch.from_numpy(np.ascontiguousarray(w.xi.ravel(order="F"))).to("cuda", torch.float64)
+    e = w.noise_level * torch.linalg.norm(bt.double()) * xi / torch.linalg.norm(xi)
+    return (bt.double() + e).to(dt).contiguous()
 
 
 def build_inputs(D, torch, ctx, workloads, prec):
-    """b = A x_true + e on the device (A from the library, e at the stated
-    relative level along the seeded direction)."""
-    dt = torch.float32 if prec == D.DBL_F32 else torch.float64
-    items = []
-    for w in workloads:
-        m = w.m
-        op = D.dbl_op_create(ctx, w.psf, m, 1, "haar", prec)
-        xt = torch.from_numpy(np.ascontiguousarray(w.x_true.ravel(order="F"))).to("cuda", dt)
-        bt = torch.empty_like(xt)
-        D.dbl_apply_A(ctx, op, 0, 0, xt, bt)
-        op.close()
-        xi = torch.from_numpy(np.ascontiguousarray(w.xi.ravel(order="F"))).to("cuda", torch.float64)
-        e = w.noise_level * torch.linalg.norm(bt.double()) * xi / torch.linalg.norm(xi)
-        b = (bt.double() + e).to(dt).contiguous()
-        x = torch.zeros_like(b)
-        items.append((w, b, x))
+    dt = torch.float64 if prec == D.DBL_F64 else torch.float32
+    items = [(w, device_data(D, torch, ctx, w, dt), None) for w in workloads]
+    items = [(w, b, torch.zeros_like(b)) for w, b, _ in items]
     torch.cuda.synchronize()
     return items
 
 
 def make_requests(D, items, opts_kw):
-    reqs = []
-    for w, b, x in items:
-        opts = D.dbl_opts_default(k_out=w.k_out, k_in=w.k_in, **opts_kw)
-        reqs.append(D.make_request(b, x, w.psf, w.m, w.solver, w.wavelet, w.levels, w.transfer,
-                                   opts))
-    return reqs
+    return [D.make_request(b, x, w.psf, w.m, w.solver, w.wavelet, w.levels, w.transfer,
+                           D.dbl_opts_default(k_out=w.k_out, k_in=w.k_in, **opts_kw))
+            for w, b, x in items]
 
 
-def cpu_baseline(D, torch, ctx, w, opts_kw, k_out_sample=3):
-    """The FP64 oracle on a bounded sample of the workload: one solve of the
-    first request truncated to k_out_sample of its outer iterations per level
-    (full CGLS depth), single thread; scaled to whole solves.  The GPU solves
-    the same data with the same truncation for the error check."""
-    from threadpoolctl import threadpool_limits
-    from oracle import operators as ops, vcycle
+def work_units(w):
+    """Pixels summed over a solve's grids (times k_out x k_in, the same for
+    every solve here): the unit that converts sample throughput to the mix."""
+    return sum((w.m >> i) ** 2 for i in range(w.levels))
+
+
+# ---------------------------------------------------------------- cpu leg --
+# The oracle on a bounded sample of the workload.  Workers are spawned
+# processes that import only NumPy, the seeded generators and the oracle.
+
+def _oracle_data(args):
+    from oracle import operators as ops
+    import synth
+    kind, index = args
+    w = (synth.config4(1, start=index) if kind == "c4" else [synth.config2()[index]])[0]
     B = ops.blur(w.x_true, w.psf)
     B = B + w.noise_level * np.linalg.norm(B) * w.xi / np.linalg.norm(w.xi)
-    B32 = B.astype(np.float32).astype(np.float64)
-    with threadpool_limits(1):
-        t0 = time.perf_counter()
-        Xo, rep = vcycle.deblur(B32, w.psf, w.solver, w.wavelet, w.levels, w.transfer,
-                                k_out_sample, w.k_in, gcv_mode="spectral", fast=True,
-                                krylov=opts_kw.get("inner_solver", "cgls"))
-        t = time.perf_counter() - t0
-    npdt = np.float64 if opts_kw["precision"] == D.DBL_F64 else np.float32
-    b = torch.from_numpy(np.ascontiguousarray(B32.ravel(order="F"), dtype=npdt)).cuda()
-    x = torch.zeros_like(b)
-    opts = D.dbl_opts_default(k_out=k_out_sample, k_in=w.k_in, **opts_kw)
-    D.dbl_deblur(ctx, b, w.psf, w.m, w.solver, w.wavelet, w.levels, w.transfer, x, opts)
-    torch.cuda.synchronize()
-    xg = x.cpu().numpy().astype(np.float64)
-    xo = Xo.ravel(order="F")
-    err = float(np.linalg.norm(xg - xo) / np.linalg.norm(xo))
-    scale = k_out_sample / w.k_out
-    return {
-        "value": scale / t,
-        "unit": "solves/s",
-        "cores": 1,
-        "kind": "oracle",
-        "sample": (f"one m={w.m} {w.levels}-grid {w.solver}/{w.wavelet}/{w.transfer} solve "
-                   f"truncated to {k_out_sample} of {w.k_out} outer iterations per level "
-                   f"(k_in={w.k_in}, spectral GCV), {t:.1f} s single-threaded FP64 NumPy, "
-                   f"scaled by {k_out_sample}/{w.k_out}"),
-    }, err
+    return B.astype(np.float32)
 
+
+def _oracle_solve(args):
+    from oracle import vcycle
+    import synth
+    kind, index, B32, krylov = args
+    w = (synth.config4(1, start=index) if kind == "c4" else [synth.config2()[index]])[0]
+    t0 = time.perf_counter()
+    X, rep = vcycle.deblur(B32.astype(np.float64), w.psf, w.solver, w.wavelet, w.levels,
+                           w.transfer, w.k_out, w.k_in, gcv_mode="spectral", fast=True,
+                           krylov=krylov)
+    gam = np.array([h["gamma"] for h in rep["levels"]])
+    return index, X.ravel(order="F"), time.perf_counter() - t0, gam
+
+
+class CpuBaseline:
+    """cpu_baseline leg: picks the sample, builds its data with the oracle's
+    blur (so that no oracle input comes from the GPU), runs the oracle on it
+    in a pool of single-threaded workers and compares the GPU's outputs."""
+
+    def __init__(self, kind, workloads, krylov):
+        self.kind, self.krylov = kind, krylov
+        self.idx = [i for i, w in enumerate(workloads) if w.m <= 128][:CPU_SAMPLE]
+        if len(self.idx) < CPU_SAMPLE:
+            self.idx = list(range(min(CPU_SAMPLE, len(workloads))))
+        self.workloads = workloads
+        try:
+            ncpu = len(os.sched_getaffinity(0))
+        except AttributeError:
+            ncpu = os.cpu_count() or 1
+        self.ncpu = ncpu
+        self.workers = max(1, min(16, ncpu, len(self.idx)))
+        self.B = {}
+
+    def _pool(self):
+        import multiprocessing as mp
+        for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+            os.environ[k] = "1"
+        return mp.get_context("spawn").Pool(self.workers)
+
+    def inputs(self):
+        with self._pool() as pool:
+            Bs = pool.map(_oracle_data, [(self.kind, i) for i in self.idx])
+        self.B = dict(zip(self.idx, Bs))
+        return self.B
+
+    def run(self, x_gpu, gamma_gpu):
+        t0 = time.perf_counter()
+        with self._pool() as pool:
+            res = pool.map(_oracle_solve, [(self.kind, i, self.B[i], self.krylov)
+                                           for i in self.idx])
+        wall = time.perf_counter() - t0
+        errs = {i: float(np.linalg.norm(x_gpu[i] - xo) / np.linalg.norm(xo))
+                for i, xo, _, _ in res}
+        self.detail = []
+        for i, _, _, gam in res:
+            w = self.workloads[i]
+            gg = np.asarray(gamma_gpu[i])[: gam.shape[0], : gam.shape[1]]
+            self.detail.append({"index": i, "m": w.m, "solver": w.solver, "wavelet": w.wavelet,
+                                "transfer": w.transfer, "x_relerr": errs[i],
+                                "gamma_maxrel": float(np.max(np.abs(gg - gam) / gam))})
+        sample_work = sum(work_units(self.workloads[i]) for i in self.idx)
+        mix_work = float(np.mean([work_units(w) for w in self.workloads]))
+        rate = len(self.idx) / wall
+        value = (sample_work / wall) / mix_work
+        ms = sorted({self.workloads[i].m for i in self.idx})
+        cpu = {
+            "value": value, "unit": "solves/s", "cores": self.workers, "kind": "oracle",
+            "sample": (f"{len(self.idx)} solves of the workload (m in {ms}, full "
+                       f"{self.workloads[0].k_out}x{self.workloads[0].k_in} V-cycles, spectral "
+                       f"GCV, FP64 NumPy) in a pool of {self.workers} single-threaded workers: "
+                       f"{wall:.1f} s wall = {rate:.3f} sample solves/s, scaled to the "
+                       f"workload's mean pixels-over-grids per solve"),
+            "host_cpus": {"os_cpu_count": os.cpu_count(), "affinity": self.ncpu},
+            "per_solve_s": round(float(np.mean([t for _, _, t, _ in res])), 2),
+        }
+        return cpu, errs
+
+
+# ------------------------------------------------------------- operators --
+
+def operator_leg(D, torch, ctx, count=16, m=2048):
+    """A / A^T (Gaussian sigma 3 on 25 x 25, and the 21-tap motion kernel),
+    L / L^T and the Haar / Db4 restriction and prolongation on `count` FP32
+    images of m x m, one batched launch each, timed by HIP events inside the
+    library (dbl_profile).  Algorithmic bytes: each operand once."""
+    import synth
+    g = torch.Generator(device="cuda").manual_seed(3)
+    n, nl = m * m, 2 * m * (m - 1)
+    xs = [torch.randn(n, device="cuda", generator=g) for _ in range(count)]
+    ys = [torch.empty(n, device="cuda") for _ in range(count)]
+    qs = [torch.empty(nl, device="cuda") for _ in range(count)]
+    cs = [torch.empty(n // 4, device="cuda") for _ in range(count)]
+    ops = {"gaussian": D.dbl_op_create(ctx, synth.config3(m, "gaussian").psf, m, 1, "haar"),
+           "motion": D.dbl_op_create(ctx, synth.config3(m, "motion").psf, m, 1, "haar")}
+    torch.cuda.synchronize()
+    out = {}
+    reps = 5
+
+    def measure(label, fn):
+        fn()  # warm-up
+        D.dbl_profile(ctx, 1)
+        for _ in range(reps):
+            fn()
+        st = D.dbl_profile_read(ctx)
+        D.dbl_profile(ctx, 0)
+        (name, (nl_, ms, by)), = st.items()
+        gbs = by / (ms * 1e-3) / 1e9
+        out[label] = {"kernel": name, "launches": nl_, "avg_launch_us": round(1e3 * ms / nl_, 1),
+                      "bytes_per_launch": by / nl_, "GB/s": round(gbs, 1),
+                      "frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+    for kind, op in ops.items():
+        measure(f"A_{kind}", lambda: D.dbl_apply_A_batch(ctx, op, 0, 0, xs, ys))
+        measure(f"AT_{kind}", lambda: D.dbl_apply_A_batch(ctx, op, 0, 1, xs, ys))
+    measure("L", lambda: D.dbl_apply_L_batch(ctx, m, D.DBL_F32, 0, xs, qs))
+    measure("LT", lambda: D.dbl_apply_L_batch(ctx, m, D.DBL_F32, 1, qs, ys))
+    for wv in ("haar", "db4"):
+        measure(f"restrict_{wv}", lambda: D.dbl_dwt_batch(ctx, wv, m, D.DBL_F32, 0, 1, xs, cs))
+        measure(f"prolong_{wv}", lambda: D.dbl_dwt_batch(ctx, wv, m, D.DBL_F32, 1, 1, cs, ys))
+    for op in ops.values():
+        op.close()
+    del xs, ys, qs, cs
+    torch.cuda.empty_cache()
+    return {"images": count, "m": m, "dtype": "f32", "peak_GBs": HBM_PEAK_GBS,
+            "working_set_MB": round(count * (n + nl) * 4 / 1e6), "results": out}
+
+
+# --------------------------------------------------------------- serving --
+
+def serve_leg(D, torch, ctx, rates, nreq, opts_kw):
+    """For each rate: Poisson arrivals of nreq requests drawn as the serving
+    form (m from {128, ..., 2048} with weights 4:4:3:2:1, Gaussian or motion
+    blur, random solver / wavelet / transfer).  Served: the continuous-batching
+    server, arrivals submitted as they come.  Plain: the same trace solved one
+    request at a time in arrival order.  Latency = completion - arrival on
+    the host clock."""
+    import synth
+    legs = []
+    for rate in rates:
+        arr, ws = synth.config5_stream(rate, 1e9, start=int(rate) * 1000, max_requests=nreq)
+        arr = np.asarray(arr)
+        items = []
+        for w in ws:
+            b = device_data(D, torch, ctx, w, torch.float32)
+            items.append((w, b, torch.zeros_like(b)))
+        torch.cuda.synchronize()
+        reqs = make_requests(D, items, opts_kw)
+        srv = D.dbl_server_create(ctx, max_slots=64)
+        lat = np.zeros(len(reqs))
+        tickets, sub, done, max_active = {}, 0, 0, 0
+        t0 = time.perf_counter()
+        while done < len(reqs):
+            now = time.perf_counter() - t0
+            while sub < len(reqs) and arr[sub] <= now:
+                tickets[D.dbl_server_submit(srv, reqs[sub])] = sub
+                sub += 1
+            if not tickets:
+                time.sleep(max(0.0, arr[sub] - now))
+                continue
+            max_active = max(max_active, D.dbl_server_step(srv))
+            for t, q in list(tickets.items()):
+                rep = D.dbl_server_poll(srv, t)
+                if rep is not None:
+                    assert rep["status"] == 0, rep["status"]
+                    lat[q] = time.perf_counter() - t0 - arr[q]
+                    del tickets[t]
+                    done += 1
+        t_served = time.perf_counter() - t0
+        srv.close()
+        plat = np.zeros(len(reqs))
+        t0 = time.perf_counter()
+        for q, (w, b, x) in enumerate(items):
+            now = time.perf_counter() - t0
+            if arr[q] > now:
+                time.sleep(arr[q] - now)
+            D.dbl_deblur(ctx, b, w.psf, w.m, w.solver, w.wavelet, w.levels, w.transfer, x,
+                         D.dbl_opts_default(k_out=w.k_out, k_in=w.k_in, **opts_kw))
+            plat[q] = time.perf_counter() - t0 - arr[q]
+        t_plain = time.perf_counter() - t0
+
+        def pct(a, p):
+            return round(1e3 * float(np.percentile(a, p)), 2)
+
+        ms = [w.m for w in ws]
+        legs.append({
+            "rate": rate, "requests": len(reqs),
+            "sizes": {str(s): ms.count(s) for s in sorted(set(ms))},
+            "motion": sum(w.psf_kind == "motion" for w in ws),
+            "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
+            "solves_per_s": round(len(reqs) / t_served, 2), "max_resident": max_active,
+            "plain_p50_ms": pct(plat, 50), "plain_p99_ms": pct(plat, 99),
+            "plain_solves_per_s": round(len(reqs) / t_plain, 2),
+        })
+        del items, reqs
+    return legs
+
+
+# ------------------------------------------------------------------ main --
 
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the path is "
-                          "single-device (see the sharding plan in DESIGN.md)",
+                          "single-device (the sharding plan is documented, not built)",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
@@ -225,23 +360,44 @@ def main():
                  "{IRLS,MM,SB}x{Haar,Db4}x{X,D} = 24 solves, 4 grids, 10x30, spectral GCV")
     else:
         workloads = synth.config4(256)
-        wdesc = ("256 images, m~U{64,128,256,512}, sigma~U[1,4], noise~U[0.5%,5%], mixed "
-                 "solver/wavelet/transfer, min(5,log2 m-4) grids, 10x30, spectral GCV")
+        wdesc = ("256 images, m~U{64,128,256,512}, Gaussian sigma~U[1,4] on "
+                 "(2 ceil(3 sigma)+1)^2, noise~U[0.5%,5%], mixed solver/wavelet/transfer, "
+                 "min(5,log2 m-4) grids, 10x30, spectral GCV")
     opts_kw = {"precision": prec, "gcv_mode": "spectral", "inner_solver": args.inner}
     items = build_inputs(D, torch, ctx, workloads, prec)
+
+    cpu_leg = None
+    if not args.no_cpu_baseline and not args.profile_run:
+        # the sampled solves take the oracle's own data (no oracle input from the GPU)
+        cpu_leg = CpuBaseline(args.workload, workloads, args.inner)
+        npdt = np.float64 if prec == D.DBL_F64 else np.float32
+        for i, B in cpu_leg.inputs().items():
+            w, b, x = items[i]
+            items[i] = (w, torch.from_numpy(
+                np.ascontiguousarray(B.astype(npdt).ravel(order="F"))).cuda(), x)
+        torch.cuda.synchronize()
     reqs = make_requests(D, items, opts_kw)
     nsolve = len(reqs)
+
+    if args.profile_run:
+        D.dbl_deblur_batch(ctx, reqs)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_run": args.workload, "solves": nsolve}))
+        return
 
     for _ in range(args.warmup):
         D.dbl_deblur_batch(ctx, reqs)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        D.dbl_deblur_batch(ctx, reqs)
+        reps_timed = D.dbl_deblur_batch(ctx, reqs)
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
     ms_step = 1e3 * t_batch / args.steps
     value = nsolve * args.steps / t_batch
+    x_timed = {}
+    if cpu_leg is not None:
+        x_timed = {i: items[i][2].double().cpu().numpy() for i in cpu_leg.idx}
 
     plain = None
     if not args.no_plain:
@@ -262,27 +418,39 @@ def main():
     n, ms, by = stats[dom]
     achieved = by / (ms * 1e-3) / 1e9
     traffic = None
-    rec = profiling.read_traffic(TRAFFIC_RECORD[args.workload]) \
-        if args.workload in TRAFFIC_RECORD else None
-    if rec is not None and rec["kernel"] == "k_" + dom:
+    rec = profiling.read_traffic(TRAFFIC_RECORD[args.workload])
+    if rec is not None and rec["kernel"] == "k_" + dom and args.precision == "f32":
         traffic = rec["hbm_bytes_per_dispatch"]
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "traffic_unit": "bytes per launch",
                 "launches": n, "avg_launch_us": round(1e3 * ms / n, 2),
-                "bytes_per_launch": by / n}
+                "bytes_per_launch": by / n,
+                "bytes_basis": "fused-minimum CGLS bytes: p in; x, r1, r2 in and out; s out "
+                               "(+ IRLS weights), FP32"}
     kernels = {k: {"launches": v[0], "ms": round(v[1], 3),
                    "GB/s": (round(v[2] / (v[1] * 1e-3) / 1e9, 1) if v[2] > 0 else None)}
                for k, v in sorted(stats.items(), key=lambda kv: -kv[1][1])}
 
+    operators = None if args.no_operators else operator_leg(D, torch, ctx)
+
     serving = None
     if not args.no_serve:
-        serving = serve_leg(D, torch, ctx, items, opts_kw, args.serve_rate, args.serve_requests)
+        rates = [float(r) for r in args.serve_rates.split(",") if r]
+        serving = {"arrivals": "Poisson; m from {128,256,512,1024,2048} (4:4:3:2:1), Gaussian "
+                               "or motion blur, random solver/wavelet/transfer, 10x30, "
+                               "spectral GCV; server with 64 slots",
+                   "legs": serve_leg(D, torch, ctx, rates, args.serve_requests,
+                                     {"precision": D.DBL_F32, "gcv_mode": "spectral",
+                                      "inner_solver": args.inner})}
 
     cpu = None
     err = None
-    if not args.no_cpu_baseline:
-        cpu, err = cpu_baseline(D, torch, ctx, workloads[0], opts_kw)
+    if cpu_leg is not None:
+        cpu, errs = cpu_leg.run(x_timed, {i: reps_timed[i]["gamma"] for i in cpu_leg.idx})
+        err = {"max": max(errs.values()), "median": float(np.median(list(errs.values()))),
+               "solves": len(errs), "of": "timed batch outputs vs the FP64 oracle, GCV on "
+                                          "both sides", "per_solve": cpu_leg.detail}
 
     out = {
         "metric": METRIC,
@@ -304,6 +472,7 @@ def main():
         "batched_over_plain": None if plain is None else round(value / plain, 2),
         "rel_err_vs_oracle": err,
         "roofline": roofline,
+        "operators": operators,
         "serving": serving,
         "kernels": kernels,
         "cpu_baseline": cpu,

@@ -182,7 +182,12 @@ typedef enum dbl_option {
    * subproblem); 0: every level uses the tiled two-phase launches.  Both
    * compute the CGLS recurrence of eq. (augmented) with the same element
    * arithmetic; the FP64 norm sums are ordered differently. */
-  DBL_OPT_SMALL_CGLS = 1
+  DBL_OPT_SMALL_CGLS = 1,
+  /* 1 (default): dbl_apply_A / dbl_apply_A_batch on a separable FP32 level of
+   * at least 512 x 512 run the streaming column kernel (a block marches
+   * along the columns of a 512-row strip); 0: the tiled kernel.  Both form
+   * the same sums in the same order, so results are identical. */
+  DBL_OPT_STREAM_A = 2
 } dbl_option;
 /* Set a context option.  Returns DBL_EINVAL for an unknown option or value.
  * Takes effect for work issued afterwards. */
@@ -225,9 +230,19 @@ int dbl_op_destroy(dbl_op* op);
 int dbl_apply_A(dbl_ctx* ctx, const dbl_op* op, int level, int transpose,
                 const void* in, void* out);
 
+/* The same for `count` images at once (one launch; all share op and level):
+ * in[q] and out[q] are device pointers, 0 <= count <= 65536.  in and out
+ * are host arrays of count pointers, read during the call. */
+int dbl_apply_A_batch(dbl_ctx* ctx, const dbl_op* op, int level, int transpose, int count,
+                      const void* const* in, void* const* out);
+
 /* Gradient L of Sec. 4.2 on an m x m grid: transpose = 0 maps n -> n_L,
  * transpose = 1 maps n_L -> n (the negative divergence). */
 int dbl_apply_L(dbl_ctx* ctx, int m, int precision, int transpose, const void* in, void* out);
+/* The same for `count` vectors in one launch (pointer arrays as for
+ * dbl_apply_A_batch). */
+int dbl_apply_L_batch(dbl_ctx* ctx, int m, int precision, int transpose, int count,
+                      const void* const* in, void* const* out);
 
 /* One level of the periodic DWT with the filters of Sec. 4.
  * inverse = 0: in m x m -> out; lowpass_only = 1 writes only the (m/2)^2
@@ -239,6 +254,10 @@ int dbl_apply_L(dbl_ctx* ctx, int m, int precision, int transpose, const void* i
  * image (perfect reconstruction).  m is the fine size. */
 int dbl_dwt(dbl_ctx* ctx, int wavelet, int m, int precision, int inverse, int lowpass_only,
             const void* in, void* out);
+/* The same for `count` images in one launch (pointer arrays as for
+ * dbl_apply_A_batch). */
+int dbl_dwt_batch(dbl_ctx* ctx, int wavelet, int m, int precision, int inverse,
+                  int lowpass_only, int count, const void* const* in, void* const* out);
 
 /* Approach D block transfer (Sec. 4.2): a coarse gradient-space vector
  * (m_coarse) -> the fine one (2 m_coarse):  Q_x <- W~1 Q_x W1^T,

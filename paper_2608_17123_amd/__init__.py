@@ -28,6 +28,7 @@ DBL_F32, DBL_F64, DBL_BF16 = 0, 1, 2
 DBL_GCV_AUTO, DBL_GCV_EXACT, DBL_GCV_SPECTRAL = 0, 1, 2
 DBL_MAX_LEVELS, DBL_MAX_KOUT, DBL_GCV_GRID_MAX = 8, 64, 64
 DBL_OPT_SMALL_CGLS = 1
+DBL_OPT_STREAM_A = 2
 
 SOLVERS = {"irls": DBL_IRLS, "mm": DBL_MM, "sb": DBL_SB}
 WAVELETS = {"haar": DBL_HAAR, "db4": DBL_DB4}
@@ -39,7 +40,7 @@ INNER_SOLVERS = {"cgls": DBL_INNER_CGLS, "lsqr": DBL_INNER_LSQR}
 EXPORTS = [
     "dbl_create", "dbl_destroy", "dbl_set_option", "dbl_last_error", "dbl_sync", "dbl_workspace_bytes",
     "dbl_opts_default", "dbl_profile", "dbl_profile_read", "dbl_op_create", "dbl_op_destroy", "dbl_apply_A", "dbl_apply_L",
-    "dbl_dwt", "dbl_dtransfer", "dbl_cgls", "dbl_lsqr", "dbl_gcv", "dbl_deblur", "dbl_deblur_batch",
+    "dbl_dwt", "dbl_apply_A_batch", "dbl_apply_L_batch", "dbl_dwt_batch", "dbl_dtransfer", "dbl_cgls", "dbl_lsqr", "dbl_gcv", "dbl_deblur", "dbl_deblur_batch",
     "dbl_request_bytes", "dbl_server_create", "dbl_server_destroy", "dbl_server_submit",
     "dbl_server_step", "dbl_server_poll",
 ]
@@ -124,6 +125,9 @@ def lib():
         "dbl_apply_A": (i, [vp, vp, i, i, vp, vp]),
         "dbl_apply_L": (i, [vp, i, i, i, vp, vp]),
         "dbl_dwt": (i, [vp, i, i, i, i, i, vp, vp]),
+        "dbl_apply_A_batch": (i, [vp, vp, i, i, i, ctypes.POINTER(vp), ctypes.POINTER(vp)]),
+        "dbl_apply_L_batch": (i, [vp, i, i, i, i, ctypes.POINTER(vp), ctypes.POINTER(vp)]),
+        "dbl_dwt_batch": (i, [vp, i, i, i, i, i, i, ctypes.POINTER(vp), ctypes.POINTER(vp)]),
         "dbl_dtransfer": (i, [vp, i, i, i, vp, vp]),
         "dbl_cgls": (i, [vp, vp, i, ctypes.POINTER(dbl_sub), vp, vp, i, vp, dp]),
         "dbl_lsqr": (i, [vp, vp, i, ctypes.POINTER(dbl_sub), vp, vp, i, vp, dp]),
@@ -358,6 +362,46 @@ def dbl_dwt(ctx, wavelet, m, precision, inverse, lowpass_only, x_in, x_out):
     pi, po = _dev(x_in, precision, n_in, "x_in"), _dev(x_out, precision, n_out, "x_out")
     _check(ctx, lib().dbl_dwt(ctx.handle, wavelet, m, precision, int(inverse),
                               int(lowpass_only), pi, po))
+
+
+def _ptr_array(tensors, precision, elems, what):
+    ptrs = [_dev(t, precision, elems, f"{what}[{q}]") for q, t in enumerate(tensors)]
+    return (ctypes.c_void_p * max(len(ptrs), 1))(*ptrs)
+
+
+def dbl_apply_A_batch(ctx, op, level, transpose, xs_in, xs_out):
+    """A^(level) (or its transpose) of every tensor in xs_in, into xs_out, in
+    one launch."""
+    if len(xs_in) != len(xs_out):
+        raise ValueError("xs_in and xs_out differ in length")
+    n = _level_m(op, level) ** 2
+    pi, po = _ptr_array(xs_in, op.precision, n, "xs_in"), _ptr_array(xs_out, op.precision, n,
+                                                                       "xs_out")
+    _check(ctx, lib().dbl_apply_A_batch(ctx.handle, op.handle, level, int(transpose),
+                                        len(xs_in), pi, po))
+
+
+def dbl_apply_L_batch(ctx, m, precision, transpose, xs_in, xs_out):
+    if len(xs_in) != len(xs_out):
+        raise ValueError("xs_in and xs_out differ in length")
+    n, nl = m * m, _nl(m)
+    pi = _ptr_array(xs_in, precision, nl if transpose else n, "xs_in")
+    po = _ptr_array(xs_out, precision, n if transpose else nl, "xs_out")
+    _check(ctx, lib().dbl_apply_L_batch(ctx.handle, m, precision, int(transpose), len(xs_in),
+                                        pi, po))
+
+
+def dbl_dwt_batch(ctx, wavelet, m, precision, inverse, lowpass_only, xs_in, xs_out):
+    if len(xs_in) != len(xs_out):
+        raise ValueError("xs_in and xs_out differ in length")
+    wavelet = WAVELETS.get(wavelet, wavelet)
+    fine, coarse = m * m, (m // 2) ** 2
+    n_in = coarse if (inverse and lowpass_only) else fine
+    n_out = coarse if (lowpass_only and not inverse) else fine
+    pi, po = _ptr_array(xs_in, precision, n_in, "xs_in"), _ptr_array(xs_out, precision, n_out,
+                                                                       "xs_out")
+    _check(ctx, lib().dbl_dwt_batch(ctx.handle, wavelet, m, precision, int(inverse),
+                                    int(lowpass_only), len(xs_in), pi, po))
 
 
 def dbl_dtransfer(ctx, wavelet, m_coarse, precision, q_in, q_out):

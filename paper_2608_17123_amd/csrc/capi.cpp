@@ -143,6 +143,10 @@ int dbl_set_option(dbl_ctx* ctx, int option, long long value) {
       if (value != 0 && value != 1) return set_err(ctx, DBL_EINVAL, "DBL_OPT_SMALL_CGLS takes 0 or 1");
       ctx->small_cgls = (int)value;
       return DBL_OK;
+    case DBL_OPT_STREAM_A:
+      if (value != 0 && value != 1) return set_err(ctx, DBL_EINVAL, "DBL_OPT_STREAM_A takes 0 or 1");
+      ctx->stream_a = (int)value;
+      return DBL_OK;
     default:
       return set_err(ctx, DBL_EINVAL, "unknown option");
   }
@@ -243,63 +247,100 @@ int dbl_op_destroy(dbl_op* op) {
   return DBL_OK;
 }
 
-int dbl_apply_A(dbl_ctx* ctx, const dbl_op* op, int level, int transpose, const void* in,
-                void* out) {
+int dbl_apply_A_batch(dbl_ctx* ctx, const dbl_op* op, int level, int transpose, int count,
+                      const void* const* in, void* const* out) {
   if (!ctx || !op) return DBL_EINVAL;
-  if (!in || !out) return set_err(ctx, DBL_EINVAL, "in or out is NULL");
+  if (count < 0 || count > 65536) return set_err(ctx, DBL_EINVAL, "count out of range");
+  if (count > 0 && (!in || !out)) return set_err(ctx, DBL_EINVAL, "in or out array is NULL");
+  for (int q = 0; q < count; ++q)
+    if (!in[q] || !out[q]) return set_err(ctx, DBL_EINVAL, "in or out is NULL");
   if (level < 0 || level >= op->levels) return set_err(ctx, DBL_EINVAL, "level out of range");
   if (transpose != 0 && transpose != 1) return set_err(ctx, DBL_EINVAL, "bad transpose flag");
   if (ctx->device < 0) return set_err(ctx, DBL_EDEVICE, "context has no device");
+  if (count == 0) return DBL_OK;
   (void)hipSetDevice(ctx->device);
   if (int rc0 = stage_checkpoint(ctx)) return rc0;
   const LevelHost& L = op->host.levels[level];
-  Job j;
-  std::memset(&j, 0, sizeof(j));
-  j.m = L.m;
-  j.op = op->d_ops + level;
-  j.flags = transpose ? F_ADJ : 0;
-  j.v[0] = const_cast<void*>(in);
-  j.v[1] = out;
-  Launch Lc;
   const int esz = op->precision == DBL_F64 ? 8 : 4;
-  Lc.add(j, j.m, esz);
+  const bool stream = ctx->stream_a && apply_stream_ok(L.m, op->precision, L.sep ? 1 : 0);
+  int snti = 0, sntj = 0;
+  if (stream) apply_stream_grid(L.m, &snti, &sntj);
+  Launch Lc;
+  double bytes = 0.0;
+  for (int q = 0; q < count; ++q) {
+    Job j;
+    std::memset(&j, 0, sizeof(j));
+    j.m = L.m;
+    j.op = op->d_ops + level;
+    j.flags = transpose ? F_ADJ : 0;
+    j.v[0] = const_cast<void*>(in[q]);
+    j.v[1] = out[q];
+    if (stream) Lc.add_grid(j, snti, sntj);
+    else Lc.add(j, j.m, esz);
+    bytes += job_bytes("apply_A", j, op->precision);
+  }
   LaunchArgs la;
   int rc = Lc.upload(ctx, la);
   if (rc) return rc;
-  return hip_check(ctx, timed(ctx, "apply_A", job_bytes("apply_A", Lc.jobs[0], op->precision), [&] {
-                     return launch_apply_A(la, op->precision, L.sep ? 1 : 0, L.rb,
-                                           L.sep ? L.rb : L.R);
+  return hip_check(ctx, timed(ctx, "apply_A", bytes, [&] {
+                     return stream ? launch_apply_stream(la, L.rb)
+                                   : launch_apply_A(la, op->precision, L.sep ? 1 : 0, L.rb,
+                                                    L.sep ? L.rb : L.R);
                    }),
                    "apply A");
 }
 
-int dbl_apply_L(dbl_ctx* ctx, int m, int precision, int transpose, const void* in, void* out) {
+int dbl_apply_A(dbl_ctx* ctx, const dbl_op* op, int level, int transpose, const void* in,
+                void* out) {
+  return dbl_apply_A_batch(ctx, op, level, transpose, 1, &in, &out);
+}
+
+int dbl_apply_L_batch(dbl_ctx* ctx, int m, int precision, int transpose, int count,
+                      const void* const* in, void* const* out) {
   if (!ctx) return DBL_EINVAL;
-  if (!in || !out) return set_err(ctx, DBL_EINVAL, "in or out is NULL");
+  if (count < 0 || count > 65536) return set_err(ctx, DBL_EINVAL, "count out of range");
+  if (count > 0 && (!in || !out)) return set_err(ctx, DBL_EINVAL, "in or out array is NULL");
+  for (int q = 0; q < count; ++q)
+    if (!in[q] || !out[q]) return set_err(ctx, DBL_EINVAL, "in or out is NULL");
   if (!pow2(m) || m < 2) return set_err(ctx, DBL_EINVAL, "m must be a power of two >= 2");
   if (transpose != 0 && transpose != 1) return set_err(ctx, DBL_EINVAL, "bad transpose flag");
   int rc = check_prec(ctx, precision);
   if (rc) return rc;
   if (ctx->device < 0) return set_err(ctx, DBL_EDEVICE, "context has no device");
+  if (count == 0) return DBL_OK;
   (void)hipSetDevice(ctx->device);
   if (int rc0 = stage_checkpoint(ctx)) return rc0;
-  Job j;
-  std::memset(&j, 0, sizeof(j));
-  j.m = m;
-  j.v[0] = const_cast<void*>(in);
-  j.v[1] = out;
   Launch Lc;
-  Lc.add(j, m, precision == DBL_F64 ? 8 : 4);
+  double bytes = 0.0;
+  for (int q = 0; q < count; ++q) {
+    Job j;
+    std::memset(&j, 0, sizeof(j));
+    j.m = m;
+    j.v[0] = const_cast<void*>(in[q]);
+    j.v[1] = out[q];
+    Lc.add(j, m, precision == DBL_F64 ? 8 : 4);
+    bytes += job_bytes("apply_L", j, precision);
+  }
   LaunchArgs la;
   if ((rc = Lc.upload(ctx, la))) return rc;
-  return hip_check(ctx, transpose ? launch_gradT(la, precision) : launch_grad(la, precision),
+  const char* name = transpose ? "apply_LT" : "apply_L";
+  return hip_check(ctx, timed(ctx, name, bytes, [&] {
+                     return transpose ? launch_gradT(la, precision) : launch_grad(la, precision);
+                   }),
                    "apply L");
 }
 
-int dbl_dwt(dbl_ctx* ctx, int wavelet, int m, int precision, int inverse, int lowpass_only,
-            const void* in, void* out) {
+int dbl_apply_L(dbl_ctx* ctx, int m, int precision, int transpose, const void* in, void* out) {
+  return dbl_apply_L_batch(ctx, m, precision, transpose, 1, &in, &out);
+}
+
+int dbl_dwt_batch(dbl_ctx* ctx, int wavelet, int m, int precision, int inverse,
+                  int lowpass_only, int count, const void* const* in, void* const* out) {
   if (!ctx) return DBL_EINVAL;
-  if (!in || !out) return set_err(ctx, DBL_EINVAL, "in or out is NULL");
+  if (count < 0 || count > 65536) return set_err(ctx, DBL_EINVAL, "count out of range");
+  if (count > 0 && (!in || !out)) return set_err(ctx, DBL_EINVAL, "in or out array is NULL");
+  for (int q = 0; q < count; ++q)
+    if (!in[q] || !out[q]) return set_err(ctx, DBL_EINVAL, "in or out is NULL");
   if (!pow2(m) || m < 4) return set_err(ctx, DBL_EINVAL, "m must be a power of two >= 4");
   if (wavelet != DBL_HAAR && wavelet != DBL_DB4) return set_err(ctx, DBL_EINVAL, "bad wavelet");
   if ((inverse != 0 && inverse != 1) || (lowpass_only != 0 && lowpass_only != 1))
@@ -307,21 +348,35 @@ int dbl_dwt(dbl_ctx* ctx, int wavelet, int m, int precision, int inverse, int lo
   int rc = check_prec(ctx, precision);
   if (rc) return rc;
   if (ctx->device < 0) return set_err(ctx, DBL_EDEVICE, "context has no device");
+  if (count == 0) return DBL_OK;
   (void)hipSetDevice(ctx->device);
   if (int rc0 = stage_checkpoint(ctx)) return rc0;
-  Job j;
-  std::memset(&j, 0, sizeof(j));
-  j.m = m;
-  j.flags = wavelet;
-  j.p0 = lowpass_only ? 0.0 : 1.0;
-  j.v[0] = const_cast<void*>(in);
-  j.v[1] = out;
   Launch Lc;
-  Lc.add(j, inverse ? m : m / 2, precision == DBL_F64 ? 8 : 4);
+  double bytes = 0.0;
+  const char* name = inverse ? (lowpass_only ? "prolong" : "dwt_inv4")
+                             : (lowpass_only ? "restrict" : "dwt_fwd4");
+  for (int q = 0; q < count; ++q) {
+    Job j;
+    std::memset(&j, 0, sizeof(j));
+    j.m = m;
+    j.flags = wavelet;
+    j.p0 = lowpass_only ? 0.0 : 1.0;
+    j.v[0] = const_cast<void*>(in[q]);
+    j.v[1] = out[q];
+    Lc.add(j, inverse ? m : m / 2, precision == DBL_F64 ? 8 : 4);
+    bytes += job_bytes(name, j, precision);
+  }
   LaunchArgs la;
   if ((rc = Lc.upload(ctx, la))) return rc;
-  return hip_check(ctx, inverse ? launch_dwt_inv(la, precision) : launch_dwt_fwd(la, precision),
+  return hip_check(ctx, timed(ctx, name, bytes, [&] {
+                     return inverse ? launch_dwt_inv(la, precision) : launch_dwt_fwd(la, precision);
+                   }),
                    "dwt");
+}
+
+int dbl_dwt(dbl_ctx* ctx, int wavelet, int m, int precision, int inverse, int lowpass_only,
+            const void* in, void* out) {
+  return dbl_dwt_batch(ctx, wavelet, m, precision, inverse, lowpass_only, 1, &in, &out);
 }
 
 int dbl_dtransfer(dbl_ctx* ctx, int wavelet, int m_coarse, int precision, const void* in,

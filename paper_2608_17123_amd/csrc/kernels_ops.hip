@@ -48,6 +48,85 @@ __global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 3 : 2) k_apply_sep(
                   [&](int i, int j, T v) { out[(i0 + i) + (size_t)(j0 + j) * m] = v; });
 }
 
+// Streaming separable blur for large FP32 grids (m >= STREAM_MIN_M).  A block
+// owns a strip of STREAM_ROWS rows (one per thread) and STREAM_COLS output
+// columns, and marches along the columns: each input column of the strip
+// (plus RB halo rows above and below, periodic) goes through a double-
+// buffered LDS column; the thread forms its row's axis-0 sum Z[i, j] from it
+// and keeps the last 2 RB + 1 of them in registers, from which the axis-1 sum
+// gives the output column j - RB.  Halo re-reads are (STREAM_ROWS + 2 RB) /
+// STREAM_ROWS along rows and (STREAM_COLS + 2 RB) / STREAM_COLS along
+// columns.  Input columns are requested 2 RB + 1 steps before they are used
+// (a register queue), so that many column loads are in flight per block.
+// The two sums are formed in the same order as sep_tile's passes, so the
+// result equals the tiled kernel's bit for bit.
+constexpr int STREAM_ROWS = 512, STREAM_COLS = 256, STREAM_MIN_M = 512;
+template <int RB>
+__global__ void __launch_bounds__(STREAM_ROWS) k_apply_stream(const Job* __restrict__ jobs,
+                                                              const uint32_t* __restrict__ tiles) {
+  using T = float;
+  constexpr int NTAP = 2 * RB + 1, NT = STREAM_ROWS, JW = STREAM_COLS, K = JW + 2 * RB;
+  __shared__ T col[2][NT + 2 * RB];
+  const Job* job; int ti, tj, tix;
+  decode_tile(jobs, tiles, job, ti, tj, tix);
+  const int m = job->m, msk = m - 1;
+  const int tid = threadIdx.x;
+  const int i0 = ti * NT, j0 = tj * JW, i = i0 + tid;
+  const LevelOp& op = *job->op;
+  const bool adj = job->flags & F_ADJ;
+  const Table1D& t0 = adj ? op.a0 : op.f0;
+  const Table1D& t1 = adj ? op.a1 : op.f1;
+  const T* __restrict__ in = static_cast<const T*>(job->v[0]);
+  T* __restrict__ out = static_cast<T*>(job->v[1]);
+  const T* __restrict__ T1 = t1.tf;
+  T ta[NTAP];
+  {
+    const T* __restrict__ row = t0.tf + class_of(i, m, t0.St, t0.Sb) * NTAP;
+#pragma unroll
+    for (int e = 0; e < NTAP; ++e) ta[e] = row[e];
+  }
+  const bool halo = tid < 2 * RB;
+  const size_t ga = (size_t)((i0 - RB + tid) & msk);
+  const size_t gb = (size_t)((i0 - RB + NT + tid) & msk);
+  T qa[NTAP], qb[NTAP], z[NTAP];
+#pragma unroll
+  for (int u = 0; u < NTAP; ++u) {
+    const size_t c = (size_t)((j0 - RB + u) & msk) * m;
+    qa[u] = in[ga + c];
+    qb[u] = halo ? in[gb + c] : T(0);
+  }
+#pragma unroll 1
+  for (int kb = 0; kb < K; kb += NTAP) {
+#pragma unroll
+    for (int u = 0; u < NTAP; ++u) {
+      const int k = kb + u;
+      if (k >= K) break;
+      T* __restrict__ buf = col[k & 1];
+      buf[tid] = qa[u];
+      if (halo) buf[NT + tid] = qb[u];
+      const int kn = k + NTAP;
+      if (kn < K) {
+        const size_t c = (size_t)((j0 - RB + kn) & msk) * m;
+        qa[u] = in[ga + c];
+        if (halo) qb[u] = in[gb + c];
+      }
+      __syncthreads();
+      T a = T(0);
+#pragma unroll
+      for (int e = 0; e < NTAP; ++e) a = fma(ta[e], buf[tid + e], a);
+      z[u] = a;
+      if (k >= 2 * RB) {
+        const int j = j0 + k - 2 * RB;
+        const T* __restrict__ row = T1 + class_of(j, m, t1.St, t1.Sb) * NTAP;
+        T y = T(0);
+#pragma unroll
+        for (int e = 0; e < NTAP; ++e) y = fma(row[e], z[(u + 1 + e) % NTAP], y);
+        out[i + (size_t)j * m] = y;
+      }
+    }
+  }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(NTHREADS) k_apply_gen(const Job* __restrict__ jobs,
                                                         const uint32_t* __restrict__ tiles) {
@@ -72,7 +151,50 @@ __global__ void __launch_bounds__(NTHREADS) k_apply_gen(const Job* __restrict__ 
 }
 
 // ------------------------------------------------------------ gradient ----
-// v[0] = x (m x m), v[1] = q (n_L): q = L x.
+// Four consecutive elements of one column (16 B for FP32, 32 B for FP64): the
+// address is a multiple of 4 elements in every use below (m is a multiple of
+// 4 on the vector paths, and so are the row offsets).
+template <typename T> struct Vec4;
+template <> struct Vec4<float> {
+  static __device__ __forceinline__ void ld(const float* p, float (&v)[4]) {
+    const float4 a = *reinterpret_cast<const float4*>(p);
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+  }
+  static __device__ __forceinline__ void st(float* p, const float (&v)[4]) {
+    *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+  }
+};
+template <> struct Vec4<double> {
+  static __device__ __forceinline__ void ld(const double* p, double (&v)[4]) {
+    const double2 a = reinterpret_cast<const double2*>(p)[0];
+    const double2 b = reinterpret_cast<const double2*>(p)[1];
+    v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+  }
+  static __device__ __forceinline__ void st(double* p, const double (&v)[4]) {
+    reinterpret_cast<double2*>(p)[0] = make_double2(v[0], v[1]);
+    reinterpret_cast<double2*>(p)[1] = make_double2(v[2], v[3]);
+  }
+};
+
+// Vector paths need 16-byte aligned base pointers (every buffer the library
+// allocates is; a caller's offset view may not be, and then takes the
+// element-wise path).
+__device__ __forceinline__ bool aligned16(const void* p) {
+  return (reinterpret_cast<uintptr_t>(p) & 15u) == 0;
+}
+
+// Thread layout of the vector paths on a 32 x 32 tile: 8 threads per column,
+// each owning 4 consecutive rows; a wave covers 8 columns.
+__device__ __forceinline__ void quad_of(int TI, int& r4, int& jl) {
+  r4 = 4 * (threadIdx.x & 7);
+  jl = threadIdx.x >> 3;
+  (void)TI;
+}
+
+// v[0] = x (m x m), v[1] = q (n_L): q = L x.  On 32 x 32 tiles every thread
+// loads its four rows of columns j and j+1 as vectors and takes row i+4 from
+// the thread below (the same column) by a lane shuffle, so each x element is
+// fetched once per column it is used in.
 template <typename T>
 __global__ void __launch_bounds__(NTHREADS) k_grad(const Job* __restrict__ jobs,
                                                    const uint32_t* __restrict__ tiles) {
@@ -84,6 +206,30 @@ __global__ void __launch_bounds__(NTHREADS) k_grad(const Job* __restrict__ jobs,
   const T* __restrict__ x = static_cast<const T*>(job->v[0]);
   T* __restrict__ q = static_cast<T*>(job->v[1]);
   const size_t nx = (size_t)(m - 1) * m;
+  if (TI == 32 && aligned16(x) && aligned16(q)) {
+    int r4, jl;
+    quad_of(TI, r4, jl);
+    const int i = i0 + r4, j = j0 + jl;
+    const size_t g = i + (size_t)j * m;
+    const bool lastq = (threadIdx.x & 7) == 7, right = j < m - 1;
+    T a[4], b[4] = {T(0), T(0), T(0), T(0)}, below = T(0);
+    Vec4<T>::ld(x + g, a);
+    if (right) Vec4<T>::ld(x + g + m, b);
+    if (lastq && i + 4 < m) below = x[g + 4];
+    const T nxt = __shfl_down(a[0], 1, 64);
+    if (!lastq) below = nxt;
+    T* __restrict__ qx = q + i + (size_t)j * (m - 1);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (i + u < m - 1) qx[u] = (u < 3 ? a[u + 1] : below) - a[u];
+    if (right) {
+      T d[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) d[u] = b[u] - a[u];
+      Vec4<T>::st(q + nx + g, d);
+    }
+    return;
+  }
   for (int o = threadIdx.x; o < TI * TJ; o += NTHREADS) {
     const int i = i0 + (o & (TI - 1)), j = j0 + (o >> (__ffs(TI) - 1));
     const T xc = x[i + (size_t)j * m];
@@ -92,7 +238,10 @@ __global__ void __launch_bounds__(NTHREADS) k_grad(const Job* __restrict__ jobs,
   }
 }
 
-// v[0] = q (n_L), v[1] = y (m x m): y = L^T q = vec(D^T Qx + Qy D).
+// v[0] = q (n_L), v[1] = y (m x m): y = L^T q = vec(D^T Qx + Qy D).  On
+// 32 x 32 tiles each thread loads its four rows of the Qy columns j-1 and j as
+// vectors and its Qx entries (not 4-aligned: Qx has m-1 rows) as scalars,
+// taking the entry above its first row from the thread above by a shuffle.
 template <typename T>
 __global__ void __launch_bounds__(NTHREADS) k_gradT(const Job* __restrict__ jobs,
                                                     const uint32_t* __restrict__ tiles) {
@@ -104,6 +253,34 @@ __global__ void __launch_bounds__(NTHREADS) k_gradT(const Job* __restrict__ jobs
   const T* __restrict__ q = static_cast<const T*>(job->v[0]);
   T* __restrict__ y = static_cast<T*>(job->v[1]);
   const T* __restrict__ qy = q + (size_t)(m - 1) * m;
+  if (TI == 32 && aligned16(q) && aligned16(y)) {
+    int r4, jl;
+    quad_of(TI, r4, jl);
+    const int i = i0 + r4, j = j0 + jl;
+    const size_t g = i + (size_t)j * m;
+    const bool firstq = (threadIdx.x & 7) == 0;
+    const T* __restrict__ qx = q + i + (size_t)j * (m - 1);
+    T cx[4], up = T(0), yl[4] = {T(0), T(0), T(0), T(0)}, yr[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+    for (int u = 0; u < 4; ++u) cx[u] = (i + u < m - 1) ? qx[u] : T(0);
+    if (firstq && i >= 1) up = qx[-1];
+    if (j >= 1) Vec4<T>::ld(qy + g - m, yl);
+    if (j < m - 1) Vec4<T>::ld(qy + g, yr);
+    const T prv = __shfl_up(cx[3], 1, 64);
+    if (!firstq) up = prv;
+    T out[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      T a = T(0);
+      if (i + u >= 1) a += (u == 0 ? up : cx[u - 1]);
+      if (i + u < m - 1) a -= cx[u];
+      if (j >= 1) a += yl[u];
+      if (j < m - 1) a -= yr[u];
+      out[u] = a;
+    }
+    Vec4<T>::st(y + g, out);
+    return;
+  }
   for (int o = threadIdx.x; o < TI * TJ; o += NTHREADS) {
     const int i = i0 + (o & (TI - 1)), j = j0 + (o >> (__ffs(TI) - 1));
     T a = T(0);
@@ -134,6 +311,50 @@ __global__ void __launch_bounds__(NTHREADS) k_dwt_fwd(const Job* __restrict__ jo
   const T* __restrict__ x = static_cast<const T*>(job->v[0]);
   T* __restrict__ y = static_cast<T*>(job->v[1]);
   const size_t nc = (size_t)mc * mc;
+  if (!four && TI == 32 && aligned16(x) && aligned16(y)) {
+    // low-pass restriction: 4 coarse rows of one coarse column per thread,
+    // from fine rows 2 a0 .. 2 a0 + 7 (+ K - 2 below, wrapped) of K fine
+    // columns, all loads issued before any arithmetic; the sums are those of
+    // the element-wise path in the same order
+    int r4, jl;
+    quad_of(TI, r4, jl);
+    const int a0 = i0 + r4, a1 = j0 + jl, f = 2 * a0;
+    T v[4][10];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      if (b >= K) break;
+      const T* __restrict__ col = x + (size_t)((2 * a1 + b) & msk) * m;
+      T lo4[4], hi4[4];
+      Vec4<T>::ld(col + f, lo4);
+      Vec4<T>::ld(col + f + 4, hi4);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        v[b][u] = lo4[u];
+        v[b][4 + u] = hi4[u];
+      }
+      v[b][8] = K > 2 ? col[(f + 8) & msk] : T(0);
+      v[b][9] = K > 2 ? col[(f + 9) & msk] : T(0);
+    }
+    T out[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      double ll = 0;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        if (b >= K) break;
+        double lo = 0;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          if (a >= K) break;
+          lo += wl_h(wav, a) * (double)v[b][2 * u + a];
+        }
+        ll += wl_h(wav, b) * lo;
+      }
+      out[u] = (T)ll;
+    }
+    Vec4<T>::st(y + a0 + (size_t)a1 * mc, out);
+    return;
+  }
   for (int o = threadIdx.x; o < TI * TJ; o += NTHREADS) {
     const int a0 = i0 + (o & (TI - 1)), a1 = j0 + (o >> (__ffs(TI) - 1));
     double ll = 0, lh = 0, hl = 0, hh = 0;
@@ -176,6 +397,44 @@ __global__ void __launch_bounds__(NTHREADS) k_dwt_inv(const Job* __restrict__ jo
   const T* __restrict__ c = static_cast<const T*>(job->v[0]);
   T* __restrict__ x = static_cast<T*>(job->v[1]);
   const size_t nc = (size_t)mc * mc;
+  if (!four && TI == 32 && aligned16(x)) {
+    // low-pass prolongation: 4 fine rows f0 .. f0 + 3 of one fine column per
+    // thread; they need coarse rows f0/2 - K2 + 1 .. f0/2 + 1 (wrapped) of K2
+    // coarse columns, loaded before any arithmetic; the sums are those of the
+    // element-wise path in the same order
+    int r4, jl;
+    quad_of(TI, r4, jl);
+    const int f0 = i0 + r4, f1 = j0 + jl, h0 = f0 >> 1;
+    T cv[2][3];
+#pragma unroll
+    for (int t1 = 0; t1 < 2; ++t1) {
+      if (t1 >= K2) break;
+      const T* __restrict__ col = c + (size_t)(((f1 >> 1) - t1) & cm) * mc;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) cv[t1][d] = (d == 0 && K2 < 2) ? T(0) : col[(h0 - 1 + d) & cm];
+    }
+    T out[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int ff0 = f0 + u;
+      double acc = 0;
+#pragma unroll
+      for (int t1 = 0; t1 < 2; ++t1) {
+        if (t1 >= K2) break;
+        const int k1 = (f1 & 1) + 2 * t1;
+#pragma unroll
+        for (int t0 = 0; t0 < 2; ++t0) {
+          if (t0 >= K2) break;
+          const int k0 = (ff0 & 1) + 2 * t0;
+          // coarse row (ff0 >> 1) - t0 = h0 + (u >> 1) - t0 sits at d = 1 + (u >> 1) - t0
+          acc += wl_h(wav, k0) * wl_h(wav, k1) * (double)cv[t1][1 + (u >> 1) - t0];
+        }
+      }
+      out[u] = (T)acc;
+    }
+    Vec4<T>::st(x + f0 + (size_t)f1 * m, out);
+    return;
+  }
   for (int o = threadIdx.x; o < TI * TJ; o += NTHREADS) {
     const int f0 = i0 + (o & (TI - 1)), f1 = j0 + (o >> (__ffs(TI) - 1));
     double acc = 0;
@@ -270,6 +529,28 @@ static hipError_t launch_apply(const LaunchArgs& la, int sep, int rb, int H) {
 hipError_t launch_apply_A(const LaunchArgs& la, int precision, int sep, int rb, int H) {
   return precision == 1 ? launch_apply<double>(la, sep, rb, H)
                         : launch_apply<float>(la, sep, rb, H);
+}
+
+bool apply_stream_ok(int m, int precision, int sep) {
+  return precision != 1 && sep && m >= STREAM_MIN_M;
+}
+void apply_stream_grid(int m, int* nti, int* ntj) {
+  *nti = m / STREAM_ROWS;
+  *ntj = m / STREAM_COLS;
+}
+
+hipError_t launch_apply_stream(const LaunchArgs& la, int rb) {
+  switch (rb) {
+#define CASE(R)                                                                          \
+  case R:                                                                                \
+    hipLaunchKernelGGL((k_apply_stream<R>), dim3(la.ntiles), dim3(STREAM_ROWS), 0,       \
+                       la.stream, la.jobs, la.tiles);                                    \
+    break;
+    CASE(2) CASE(4) CASE(8) CASE(12) CASE(16)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 #define SIMPLE_LAUNCHER(NAME, KERNEL)                                                   \

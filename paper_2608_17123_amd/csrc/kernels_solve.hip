@@ -414,9 +414,13 @@ __global__ void __launch_bounds__(NTHREADS) k_aux(const Job* __restrict__ jobs,
 // Per outer iteration: partials of |x - x_old|^2, |x_old|^2, |A x - b|^2 and
 // the solver penalty; the last block writes (gamma, RC, objective) to
 // job->hist[3 * i0 ...].  flags: F_IRLS / F_MM / F_SB select the penalty.
+// Everything is evaluated in FP64 from the stored x, x_old and b (whatever
+// their type): A x with the FP64 tap tables, so that the objective is the
+// FP64 objective of the stored iterate.
 template <typename T, int RB, bool SEP>
-__global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 3 : 2) k_stats(const Job* __restrict__ jobs,
-                                                    const uint32_t* __restrict__ tiles) {
+__global__ void __launch_bounds__(NTHREADS, 2) k_stats(const Job* __restrict__ jobs,
+                                                      const uint32_t* __restrict__ tiles) {
+  using C = double;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red[16];
   const Job* job; int ti, tj, tix;
@@ -426,15 +430,15 @@ __global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 3 : 2) k_stats(cons
   tile_geom<T>(m, ti, tj, i0, j0, TI, TJ);
   const LevelOp& op = *job->op;
   const int H = SEP ? RB : op.R;
-  T* Xs = reinterpret_cast<T*>(smem);
+  C* Xs = reinterpret_cast<C*>(smem);
   void* scratch = Xs + xs_elems<SEP>(H, TI, TJ);
   const T* __restrict__ x = vp<T>(job, V_X);
   const T* __restrict__ xo = vp<T>(job, V_XOLD);
   const T* __restrict__ b = vp<T>(job, V_B);
   const double eps = job->p0;
   const int fl = job->flags;
-  load_tile<T, SEP>(Xs, xs_ld<SEP>(H, TI, TJ), i0, j0, TI, TJ, H, m,
-                    [&](int g) { return x[g]; });
+  load_tile<C, SEP>(Xs, xs_ld<SEP>(H, TI, TJ), i0, j0, TI, TJ, H, m,
+                    [&](int g) { return (C)x[g]; });
   __syncthreads();
   double num = 0.0, den = 0.0, res = 0.0, pen = 0.0;
   for (int o = threadIdx.x; o < TI * TJ; o += NTHREADS) {
@@ -454,11 +458,11 @@ __global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 3 : 2) k_stats(cons
       else pen += at;
     }
   }
-  auto epi = [&](int i, int j, T v) {
-    const double r = (double)v - (double)b[(i0 + i) + (size_t)(j0 + j) * m];
+  auto epi = [&](int i, int j, C v) {
+    const double r = v - (double)b[(i0 + i) + (size_t)(j0 + j) * m];
     res += r * r;
   };
-  conv_tile<T, RB, SEP, decltype(epi), NoHook, STATS_V>(Xs, H, scratch, op, false, i0, j0, TI,
+  conv_tile<C, RB, SEP, decltype(epi), NoHook, STATS_V>(Xs, H, scratch, op, false, i0, j0, TI,
                                                         TJ, m, epi);
   double vv[4] = {num, den, res, pen};
   put_partials<4>(job->pw, tix, vv, red);
@@ -579,9 +583,39 @@ hipError_t launch_cgls_p2(const LaunchArgs& la, int precision, int sep, int rb, 
   return hipGetLastError();
 }
 
+// The statistics kernel computes in FP64 whatever the storage type: its LDS
+// is sized for doubles.
+#define DISPATCH_STATS(T, la, sep, rb, H)                                               \
+  do {                                                                                 \
+    const int ts_ = tile_edge((la).m_max);                                             \
+    if (sep) {                                                                         \
+      const size_t lds_ = sizeof(double) * sep_lds_elems(ts_, ts_, rb);                \
+      switch (rb) {                                                                    \
+        case 2: hipLaunchKernelGGL((k_stats<T, 2, true>), dim3((la).ntiles),           \
+                    dim3(NTHREADS), lds_, (la).stream, (la).jobs, (la).tiles); break;  \
+        case 4: hipLaunchKernelGGL((k_stats<T, 4, true>), dim3((la).ntiles),           \
+                    dim3(NTHREADS), lds_, (la).stream, (la).jobs, (la).tiles); break;  \
+        case 8: hipLaunchKernelGGL((k_stats<T, 8, true>), dim3((la).ntiles),           \
+                    dim3(NTHREADS), lds_, (la).stream, (la).jobs, (la).tiles); break;  \
+        case 12: hipLaunchKernelGGL((k_stats<T, 12, true>), dim3((la).ntiles),         \
+                    dim3(NTHREADS), lds_, (la).stream, (la).jobs, (la).tiles); break;  \
+        case 16: hipLaunchKernelGGL((k_stats<T, 16, true>), dim3((la).ntiles),         \
+                    dim3(NTHREADS), lds_, (la).stream, (la).jobs, (la).tiles); break;  \
+        default: return hipErrorInvalidValue;                                          \
+      }                                                                                \
+    } else {                                                                           \
+      const size_t lds_ = sizeof(double) * col_lds_elems(ts_, ts_, H) +                \
+                          (2 * sizeof(double) + sizeof(short2)) * (2 * (H) + 1) *       \
+                              (2 * (H) + 1) +                                          \
+                          sizeof(double) * ts_ * ts_;                                  \
+      hipLaunchKernelGGL((k_stats<T, 0, false>), dim3((la).ntiles), dim3(NTHREADS),    \
+                         lds_, (la).stream, (la).jobs, (la).tiles);                    \
+    }                                                                                  \
+  } while (0)
+
 hipError_t launch_stats(const LaunchArgs& la, int precision, int sep, int rb, int H) {
-  if (precision == 1) DISPATCH_STENCIL(k_stats, double, la, sep, rb, H, 0);
-  else DISPATCH_STENCIL(k_stats, float, la, sep, rb, H, 0);
+  if (precision == 1) DISPATCH_STATS(double, la, sep, rb, H);
+  else DISPATCH_STATS(float, la, sep, rb, H);
   return hipGetLastError();
 }
 

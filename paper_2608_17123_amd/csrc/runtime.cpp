@@ -195,17 +195,26 @@ double job_bytes(const char* k, const Job& j, int prec) {
   const double v = prec == DBL_F64 ? 8.0 : (prec == DBL_BF16 ? 2.0 : 4.0);  // CGLS state
   const double wb = irls ? nl * e : 0.0;
   const std::string s(k);
-  // each operand read or written once
-  if (s == "cgls_p1") return (4 * n + nl) * v + wb;              // s, p in; p, q1, q2 out
-  if (s == "cgls_p2") return (5 * n + 3 * nl) * v + 2 * n * e + wb;  // r1,q1,p,r2,q2 in; r1,s,r2 out; x
+  // each operand read or written once.  The CGLS phases count the fused
+  // minimum of an iteration (q = A^ p is not an operand: a fully fused
+  // iteration recomputes it), so the bytes these kernels move beyond it (the
+  // q1, q2 round trip and re-read halos) show up against this figure in the
+  // memory counters, not in it.
+  if (s == "cgls_p1") return 3 * n * v + wb;                          // s, p in; p out
+  if (s == "cgls_p2") return (4 * n + 2 * nl) * v + 2 * n * e + wb;   // p in; x, r1, r2 in+out; s out
   if (s == "cgls_init" || s == "lsqr_init") return (2 * n + nl) * v + (2 * n + nl) * e;
   if (s == "lsqr_a") return (5 * n + 2 * nl) * v + 2 * n * e + wb;  // v,u,w in; u,w out; x
   if (s == "lsqr_b") return (3 * n + nl) * v + wb;                  // u, v in; v out
   if (s == "lsqr_fin") return n * v + 2 * n * e;                    // w in; x in and out
-  if (s == "cgls_small")  // the tiled path's traffic for the same iterations
-    return (2 * n + 2 * nl) * e + j.i0 * ((9 * n + 4 * nl) * v + 2 * n * e + 2 * wb);
+  if (s == "cgls_small")  // b, c, w in, x out; then the tiled phases' figure per iteration
+    return (2 * n + 2 * nl) * e + j.i0 * ((7 * n + 2 * nl) * v + 2 * n * e + 2 * wb);
   double el = 0.0;  // elements of x, b, w, c moved
   if (s == "apply_A") el = 2 * n;
+  else if (s == "apply_L" || s == "apply_LT") el = n + nl;
+  else if (s == "restrict" || s == "prolong" || s == "dwt_fwd" || s == "dwt_inv")
+    el = 1.25 * n;  // m x m <-> (m/2)^2 (m = fine)
+  else if (s == "dtransfer") el = 1.25 * nl;  // coarse n_L in, fine n_L out
+  else if (s == "dwt_fwd4" || s == "dwt_inv4") el = 2 * n;
   else if (s == "stats") el = 3 * n;
   else if (s == "aux") el = n + 2 * nl;
   return el * e;
@@ -242,8 +251,14 @@ PartLayout part_layout(double* base, int m) {
 }
 
 void Launch::add(const Job& j0, int grid_m, int esz, int group) {
+  const int t = tiles_per_axis(grid_m, esz);
+  add_grid(j0, t, t, group);
+}
+
+void Launch::add_grid(const Job& j0, int nti, int ntj, int group) {
   Job j = j0;
-  j.nti = j.ntj = tiles_per_axis(grid_m, esz);
+  j.nti = nti;
+  j.ntj = ntj;
   const uint32_t idx = (uint32_t)jobs.size();
   if (jobs.empty() || group != last_group) seg_start.push_back((int)tiles.size());
   last_group = group;

@@ -49,6 +49,8 @@ struct dbl_ctx {
   // one-block CGLS for small levels (DBL_OPT_SMALL_CGLS) and the device's
   // dynamic LDS limit per block
   int small_cgls = 1;
+  // streaming separable blur for large FP32 grids in the operator entry points
+  int stream_a = 1;
   size_t lds_limit = 65536;
   // EXACT-tier GCV: rocBLAS handle (rocblas_handle) and dense FP64 workspace
   void* blas = nullptr;
@@ -147,6 +149,8 @@ struct Launch {
   int last_group = 0;
   int m_max = 0;
   void add(const Job& j, int grid_m, int esz, int group = 0);
+  // a job cut into nti x ntj tiles of a kernel's own geometry
+  void add_grid(const Job& j, int nti, int ntj, int group = 0);
   int upload(dbl_ctx* ctx, LaunchArgs& la);
   bool empty() const { return jobs.empty(); }
 };
