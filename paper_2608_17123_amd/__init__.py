@@ -489,7 +489,7 @@ def make_request(b, x, psf, m, solver, wavelet, levels, transfer, opts):
     r.levels = levels
     r.transfer = TRANSFERS.get(transfer, transfer)
     r.opts = opts
-    r._keep = (keep, opts)
+    r._keep = (keep, opts, b, x)  # the struct holds raw pointers: keep their owners alive
     return r
 
 

@@ -1,5 +1,6 @@
 // extern "C" entry points (include/deblur.h): argument validation first, then
 // the runtime.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <limits>
@@ -262,7 +263,8 @@ int dbl_apply_A_batch(dbl_ctx* ctx, const dbl_op* op, int level, int transpose, 
   if (int rc0 = stage_checkpoint(ctx)) return rc0;
   const LevelHost& L = op->host.levels[level];
   const int esz = op->precision == DBL_F64 ? 8 : 4;
-  const bool stream = ctx->stream_a && apply_stream_ok(L.m, op->precision, L.sep ? 1 : 0);
+  const bool stream = ctx->stream_a && L.sep &&
+                      apply_stream_ok(L.m, op->precision, 1, std::max(L.f1.rows, L.a1.rows));
   int snti = 0, sntj = 0;
   if (stream) apply_stream_grid(L.m, &snti, &sntj);
   Launch Lc;

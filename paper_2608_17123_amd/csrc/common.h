@@ -310,6 +310,16 @@ __device__ __forceinline__ void sum_partials2(const double* p0, int c0, const do
   __syncthreads();
 }
 
+// Workgroup barrier that orders LDS accesses only.  A thread's global loads
+// stay in flight across it (__syncthreads also waits for them), so a kernel
+// that keeps loads queued ahead in registers uses this where its threads
+// exchange data through LDS alone.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Publish a scalar written by the finalising thread so later kernels and
 // other XCDs read it from memory.
 __device__ __forceinline__ void put_scal(double* s, int k, double v) {

@@ -61,12 +61,25 @@ __global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 3 : 2) k_apply_sep(
 // The two sums are formed in the same order as sep_tile's passes, so the
 // result equals the tiled kernel's bit for bit.
 constexpr int STREAM_ROWS = 512, STREAM_COLS = 256, STREAM_MIN_M = 512;
+// class rows of an axis-1 table the streaming kernel stages in LDS
+constexpr int STREAM_MAX_ROWS = 2 * (2 * MAX_R + 3) + 1;
+// A pointer the kernel may only use for device (global) memory: every vector
+// a job names is a device allocation (the library's or the caller's), whose
+// generic address is its global address.
+template <typename T> using GlobalPtr = __attribute__((address_space(1))) T*;
+template <typename T> __device__ __forceinline__ GlobalPtr<T> gview(T* p) {
+  return (GlobalPtr<T>)p;
+}
 template <int RB>
 __global__ void __launch_bounds__(STREAM_ROWS) k_apply_stream(const Job* __restrict__ jobs,
                                                               const uint32_t* __restrict__ tiles) {
   using T = float;
   constexpr int NTAP = 2 * RB + 1, NT = STREAM_ROWS, JW = STREAM_COLS, K = JW + 2 * RB;
   __shared__ T col[2][NT + 2 * RB];
+  // the axis-1 tap rows (interior and seam classes), read by every thread
+  // with one address per column step (LDS broadcast)
+  constexpr int MAX_T1 = STREAM_MAX_ROWS * NTAP;
+  __shared__ T tab1[MAX_T1];
   const Job* job; int ti, tj, tix;
   decode_tile(jobs, tiles, job, ti, tj, tix);
   const int m = job->m, msk = m - 1;
@@ -76,12 +89,18 @@ __global__ void __launch_bounds__(STREAM_ROWS) k_apply_stream(const Job* __restr
   const bool adj = job->flags & F_ADJ;
   const Table1D& t0 = adj ? op.a0 : op.f0;
   const Table1D& t1 = adj ? op.a1 : op.f1;
-  const T* __restrict__ in = static_cast<const T*>(job->v[0]);
-  T* __restrict__ out = static_cast<T*>(job->v[1]);
-  const T* __restrict__ T1 = t1.tf;
+  // global-address-space views of the caller's buffers: loads and stores
+  // then wait on the vector-memory counter only, so the LDS waits of each
+  // column step do not also drain the column loads queued ahead
+  const GlobalPtr<const T> in = gview(static_cast<const T*>(job->v[0]));
+  const GlobalPtr<T> out = gview(static_cast<T*>(job->v[1]));
+  // table fields read once: a reload through the job inside the column loop
+  // would be a generic-address load, whose wait also drains the queued loads
+  const int St1 = t1.St, Sb1 = t1.Sb, rows1 = t1.rows;
+  for (int q = tid; q < rows1 * NTAP; q += NT) tab1[q] = gview(t1.tf)[q];  // rows checked on the host
   T ta[NTAP];
   {
-    const T* __restrict__ row = t0.tf + class_of(i, m, t0.St, t0.Sb) * NTAP;
+    const GlobalPtr<const T> row = gview(t0.tf) + class_of(i, m, t0.St, t0.Sb) * NTAP;
 #pragma unroll
     for (int e = 0; e < NTAP; ++e) ta[e] = row[e];
   }
@@ -110,14 +129,14 @@ __global__ void __launch_bounds__(STREAM_ROWS) k_apply_stream(const Job* __restr
         qa[u] = in[ga + c];
         if (halo) qb[u] = in[gb + c];
       }
-      __syncthreads();
+      lds_barrier();
       T a = T(0);
 #pragma unroll
       for (int e = 0; e < NTAP; ++e) a = fma(ta[e], buf[tid + e], a);
       z[u] = a;
       if (k >= 2 * RB) {
         const int j = j0 + k - 2 * RB;
-        const T* __restrict__ row = T1 + class_of(j, m, t1.St, t1.Sb) * NTAP;
+        const T* row = tab1 + class_of(j, m, St1, Sb1) * NTAP;
         T y = T(0);
 #pragma unroll
         for (int e = 0; e < NTAP; ++e) y = fma(row[e], z[(u + 1 + e) % NTAP], y);
@@ -206,27 +225,27 @@ __global__ void __launch_bounds__(NTHREADS) k_grad(const Job* __restrict__ jobs,
   const T* __restrict__ x = static_cast<const T*>(job->v[0]);
   T* __restrict__ q = static_cast<T*>(job->v[1]);
   const size_t nx = (size_t)(m - 1) * m;
-  if (TI == 32 && aligned16(x) && aligned16(q)) {
-    int r4, jl;
-    quad_of(TI, r4, jl);
-    const int i = i0 + r4, j = j0 + jl;
-    const size_t g = i + (size_t)j * m;
-    const bool lastq = (threadIdx.x & 7) == 7, right = j < m - 1;
-    T a[4], b[4] = {T(0), T(0), T(0), T(0)}, below = T(0);
-    Vec4<T>::ld(x + g, a);
-    if (right) Vec4<T>::ld(x + g + m, b);
-    if (lastq && i + 4 < m) below = x[g + 4];
-    const T nxt = __shfl_down(a[0], 1, 64);
-    if (!lastq) below = nxt;
-    T* __restrict__ qx = q + i + (size_t)j * (m - 1);
+  if (TI == 32) {
+    // lane-row layout: a thread owns row i of four consecutive columns, so
+    // every load and store instruction covers 32 consecutive elements of a
+    // column; all loads are issued before any store
+    const int r = threadIdx.x & 31, jb = j0 + 4 * (threadIdx.x >> 5), i = i0 + r;
+    T xv[5], dn[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (i + u < m - 1) qx[u] = (u < 3 ? a[u + 1] : below) - a[u];
-    if (right) {
-      T d[4];
+    for (int c = 0; c < 5; ++c) xv[c] = (jb + c < m) ? x[i + (size_t)(jb + c) * m] : T(0);
 #pragma unroll
-      for (int u = 0; u < 4; ++u) d[u] = b[u] - a[u];
-      Vec4<T>::st(q + nx + g, d);
+    for (int c = 0; c < 4; ++c)
+      dn[c] = (r == 31 && i + 1 < m) ? x[i + 1 + (size_t)(jb + c) * m] : T(0);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const T nb = __shfl_down(xv[c], 1, 32);
+      if (r != 31) dn[c] = nb;
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int j = jb + c;
+      if (i < m - 1) q[i + (size_t)j * (m - 1)] = dn[c] - xv[c];
+      if (j < m - 1) q[nx + i + (size_t)j * m] = xv[c + 1] - xv[c];
     }
     return;
   }
@@ -253,32 +272,37 @@ __global__ void __launch_bounds__(NTHREADS) k_gradT(const Job* __restrict__ jobs
   const T* __restrict__ q = static_cast<const T*>(job->v[0]);
   T* __restrict__ y = static_cast<T*>(job->v[1]);
   const T* __restrict__ qy = q + (size_t)(m - 1) * m;
-  if (TI == 32 && aligned16(q) && aligned16(y)) {
-    int r4, jl;
-    quad_of(TI, r4, jl);
-    const int i = i0 + r4, j = j0 + jl;
-    const size_t g = i + (size_t)j * m;
-    const bool firstq = (threadIdx.x & 7) == 0;
-    const T* __restrict__ qx = q + i + (size_t)j * (m - 1);
-    T cx[4], up = T(0), yl[4] = {T(0), T(0), T(0), T(0)}, yr[4] = {T(0), T(0), T(0), T(0)};
+  if (TI == 32) {
+    // lane-row layout as in k_grad; the Qx entry above row i comes from the
+    // lane above (a load for the tile's first row)
+    const int r = threadIdx.x & 31, jb = j0 + 4 * (threadIdx.x >> 5), i = i0 + r;
+    T cx[4], up[4], cy[5];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) cx[u] = (i + u < m - 1) ? qx[u] : T(0);
-    if (firstq && i >= 1) up = qx[-1];
-    if (j >= 1) Vec4<T>::ld(qy + g - m, yl);
-    if (j < m - 1) Vec4<T>::ld(qy + g, yr);
-    const T prv = __shfl_up(cx[3], 1, 64);
-    if (!firstq) up = prv;
-    T out[4];
+    for (int c = 0; c < 4; ++c)
+      cx[c] = (i < m - 1) ? q[i + (size_t)(jb + c) * (m - 1)] : T(0);
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      T a = T(0);
-      if (i + u >= 1) a += (u == 0 ? up : cx[u - 1]);
-      if (i + u < m - 1) a -= cx[u];
-      if (j >= 1) a += yl[u];
-      if (j < m - 1) a -= yr[u];
-      out[u] = a;
+    for (int c = 0; c < 4; ++c)
+      up[c] = (r == 0 && i >= 1) ? q[i - 1 + (size_t)(jb + c) * (m - 1)] : T(0);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      const int j = jb + c - 1;
+      cy[c] = (j >= 0 && j < m - 1) ? qy[i + (size_t)j * m] : T(0);
     }
-    Vec4<T>::st(y + g, out);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const T ab = __shfl_up(cx[c], 1, 32);
+      if (r != 0) up[c] = ab;
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int j = jb + c;
+      T a = T(0);
+      if (i >= 1) a += up[c];
+      if (i < m - 1) a -= cx[c];
+      if (j >= 1) a += cy[c];
+      if (j < m - 1) a -= cy[c + 1];
+      y[i + (size_t)j * m] = a;
+    }
     return;
   }
   for (int o = threadIdx.x; o < TI * TJ; o += NTHREADS) {
@@ -332,8 +356,21 @@ __global__ void __launch_bounds__(NTHREADS) k_dwt_fwd(const Job* __restrict__ jo
         v[b][u] = lo4[u];
         v[b][4 + u] = hi4[u];
       }
-      v[b][8] = K > 2 ? col[(f + 8) & msk] : T(0);
-      v[b][9] = K > 2 ? col[(f + 9) & msk] : T(0);
+      // rows f + 8, f + 9 (Db4 only) are the next thread's first two rows
+      // (the same column); the last thread of a column loads them (wrapped)
+      const bool edge = K > 2 && (threadIdx.x & 7) == 7;
+      v[b][8] = edge ? col[(f + 8) & msk] : T(0);
+      v[b][9] = edge ? col[(f + 9) & msk] : T(0);
+    }
+    if (K > 2) {
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const T n8 = __shfl_down(v[b][0], 1, 8), n9 = __shfl_down(v[b][1], 1, 8);
+        if ((threadIdx.x & 7) != 7) {
+          v[b][8] = n8;
+          v[b][9] = n9;
+        }
+      }
     }
     T out[4];
 #pragma unroll
@@ -346,9 +383,9 @@ __global__ void __launch_bounds__(NTHREADS) k_dwt_fwd(const Job* __restrict__ jo
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
           if (a >= K) break;
-          lo += wl_h(wav, a) * (double)v[b][2 * u + a];
+          lo = fma(wl_h(wav, a), (double)v[b][2 * u + a], lo);
         }
-        ll += wl_h(wav, b) * lo;
+        ll = fma(wl_h(wav, b), lo, ll);
       }
       out[u] = (T)ll;
     }
@@ -363,14 +400,14 @@ __global__ void __launch_bounds__(NTHREADS) k_dwt_fwd(const Job* __restrict__ jo
       double lo = 0, hi = 0;
       for (int a = 0; a < K; ++a) {
         const double v = (double)x[((2 * a0 + a) & msk) + col];
-        lo += wl_h(wav, a) * v;
-        hi += wl_g(wav, a) * v;
+        lo = fma(wl_h(wav, a), v, lo);
+        hi = fma(wl_g(wav, a), v, hi);
       }
-      ll += wl_h(wav, b) * lo;
+      ll = fma(wl_h(wav, b), lo, ll);
       if (four) {
-        lh += wl_g(wav, b) * lo;
-        hl += wl_h(wav, b) * hi;
-        hh += wl_g(wav, b) * hi;
+        lh = fma(wl_g(wav, b), lo, lh);
+        hl = fma(wl_h(wav, b), hi, hl);
+        hh = fma(wl_g(wav, b), hi, hh);
       }
     }
     const size_t k = a0 + (size_t)a1 * mc;
@@ -397,7 +434,7 @@ __global__ void __launch_bounds__(NTHREADS) k_dwt_inv(const Job* __restrict__ jo
   const T* __restrict__ c = static_cast<const T*>(job->v[0]);
   T* __restrict__ x = static_cast<T*>(job->v[1]);
   const size_t nc = (size_t)mc * mc;
-  if (!four && TI == 32 && aligned16(x)) {
+  if (!four && TI == 32 && aligned16(x) && aligned16(c)) {
     // low-pass prolongation: 4 fine rows f0 .. f0 + 3 of one fine column per
     // thread; they need coarse rows f0/2 - K2 + 1 .. f0/2 + 1 (wrapped) of K2
     // coarse columns, loaded before any arithmetic; the sums are those of the
@@ -405,13 +442,24 @@ __global__ void __launch_bounds__(NTHREADS) k_dwt_inv(const Job* __restrict__ jo
     int r4, jl;
     quad_of(TI, r4, jl);
     const int f0 = i0 + r4, f1 = j0 + jl, h0 = f0 >> 1;
-    T cv[2][3];
+    // coarse rows h0, h0 + 1 (h0 even: one aligned pair) of each coarse
+    // column; row h0 - 1 (Db4) is the pair of the thread above, or a load
+    // (wrapped) for the first thread of a column
+    T cv[2][3] = {{T(0), T(0), T(0)}, {T(0), T(0), T(0)}};
 #pragma unroll
     for (int t1 = 0; t1 < 2; ++t1) {
       if (t1 >= K2) break;
       const T* __restrict__ col = c + (size_t)(((f1 >> 1) - t1) & cm) * mc;
+      cv[t1][1] = col[h0];
+      cv[t1][2] = col[h0 + 1];
+      if (K2 > 1 && (threadIdx.x & 7) == 0) cv[t1][0] = col[(h0 - 1) & cm];
+    }
+    if (K2 > 1) {
 #pragma unroll
-      for (int d = 0; d < 3; ++d) cv[t1][d] = (d == 0 && K2 < 2) ? T(0) : col[(h0 - 1 + d) & cm];
+      for (int t1 = 0; t1 < 2; ++t1) {
+        const T a = __shfl_up(cv[t1][2], 1, 8);
+        if ((threadIdx.x & 7) != 0) cv[t1][0] = a;
+      }
     }
     T out[4];
 #pragma unroll
@@ -427,7 +475,7 @@ __global__ void __launch_bounds__(NTHREADS) k_dwt_inv(const Job* __restrict__ jo
           if (t0 >= K2) break;
           const int k0 = (ff0 & 1) + 2 * t0;
           // coarse row (ff0 >> 1) - t0 = h0 + (u >> 1) - t0 sits at d = 1 + (u >> 1) - t0
-          acc += wl_h(wav, k0) * wl_h(wav, k1) * (double)cv[t1][1 + (u >> 1) - t0];
+          acc = fma(wl_h(wav, k0) * wl_h(wav, k1), (double)cv[t1][1 + (u >> 1) - t0], acc);
         }
       }
       out[u] = (T)acc;
@@ -443,7 +491,7 @@ __global__ void __launch_bounds__(NTHREADS) k_dwt_inv(const Job* __restrict__ jo
       for (int t0 = 0; t0 < K2; ++t0) {
         const int c0 = ((f0 >> 1) - t0) & cm, k0 = (f0 & 1) + 2 * t0;
         const size_t k = c0 + (size_t)c1 * mc;
-        acc += wl_h(wav, k0) * wl_h(wav, k1) * (double)c[k];
+        acc = fma(wl_h(wav, k0) * wl_h(wav, k1), (double)c[k], acc);
         if (four) {
           acc += wl_h(wav, k0) * wl_g(wav, k1) * (double)c[nc + k];
           acc += wl_g(wav, k0) * wl_h(wav, k1) * (double)c[2 * nc + k];
@@ -531,8 +579,8 @@ hipError_t launch_apply_A(const LaunchArgs& la, int precision, int sep, int rb, 
                         : launch_apply<float>(la, sep, rb, H);
 }
 
-bool apply_stream_ok(int m, int precision, int sep) {
-  return precision != 1 && sep && m >= STREAM_MIN_M;
+bool apply_stream_ok(int m, int precision, int sep, int rows1) {
+  return precision != 1 && sep && m >= STREAM_MIN_M && rows1 <= STREAM_MAX_ROWS;
 }
 void apply_stream_grid(int m, int* nti, int* ntj) {
   *nti = m / STREAM_ROWS;

@@ -35,7 +35,7 @@ enum VSlot : int {
 hipError_t launch_apply_A(const LaunchArgs& la, int precision, int sep, int rb, int H);
 // Streaming separable blur for large FP32 grids: eligibility, its strip grid
 // (tiles per axis of a job: row strips x column blocks) and the launch.
-bool apply_stream_ok(int m, int precision, int sep);
+bool apply_stream_ok(int m, int precision, int sep, int rows1);
 void apply_stream_grid(int m, int* nti, int* ntj);
 hipError_t launch_apply_stream(const LaunchArgs& la, int rb);
 hipError_t launch_grad(const LaunchArgs& la, int precision);

@@ -98,7 +98,7 @@ def test_apply_A_large_image_sampled(ctx, wavelet):
 
 
 @pytest.mark.parametrize("prec", [D.DBL_F32, D.DBL_F64])
-@pytest.mark.parametrize("m", [8, 64, 256])
+@pytest.mark.parametrize("m", [8, 16, 64, 256, 2048])
 def test_apply_L(ctx, prec, m):
     X = rounded((m, m), 5, prec)
     q = rounded(2 * m * (m - 1), 6, prec)
@@ -106,6 +106,10 @@ def test_apply_L(ctx, prec, m):
     qout = torch.empty(2 * m * (m - 1), dtype=xin.dtype, device="cuda")
     D.dbl_apply_L(ctx, m, prec, 0, xin, qout)
     close(host(qout), ops.grad(X), prec)
+    # each entry is one difference of two stored values: the device result is
+    # that difference rounded once to the storage type, i.e. the oracle's
+    # exact FP64 difference rounded to it
+    assert np.array_equal(host(qout), ops.grad(X).astype(NP[prec]).astype(np.float64))
     qin = dev(q, prec)
     yout = torch.empty_like(xin)
     D.dbl_apply_L(ctx, m, prec, 1, qin, yout)

@@ -300,10 +300,11 @@ def test_config2_all_24_solves_fixed_mu_match_oracle(ctx):
     of the 2-norm error, and the sampled pixels) and every outer iteration's
     objective within 1e-6 of the FP64 oracle."""
     fixtures, cases = c2_fixture_inputs()
-    xs, reqs = [], []
+    bs, xs, reqs = [], [], []  # the requests hold raw pointers: keep b and x alive
     for w, B, rec in cases:
         b = dev(B)
         x = torch.zeros_like(b)
+        bs.append(b)
         xs.append(x)
         mu = np.concatenate([np.asarray(g) for g in rec["gamma"]])
         reqs.append(D.make_request(b, x, w.psf, w.m, w.solver, w.wavelet, w.levels, w.transfer,
