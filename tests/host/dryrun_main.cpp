@@ -1,0 +1,82 @@
+// Dry run of whole solves through the C ABI with the host-only HIP stand-in
+// (hip_mock.cpp): every launch the engine issues is audited instead of run.
+//
+// usage: dryrun <psf-file> <m> <levels> <solver> <wavelet> <transfer> <precision>
+//               <k_out> <k_in> <small_cgls> <copies> [<inner>]
+// psf-file: "ph pw" then ph*pw values, column-major.  copies > 1 solves that
+// many copies of the request in one dbl_deblur_batch call.  Parameters are a
+// fixed schedule (no GCV).  Prints the launch counts per kernel family and
+// every violation; exits 1 when there is one.
+#include <cstdio>
+#include <cstdlib>
+#include <map>
+#include <string>
+#include <vector>
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/deblur.h"
+
+namespace mock {
+extern std::vector<std::string> violations;
+extern std::map<std::string, long> launches;
+extern long checked_pointers;
+}  // namespace mock
+
+int main(int argc, char** argv) {
+  if (argc < 12) {
+    std::fprintf(stderr, "usage: dryrun psf m levels solver wavelet transfer precision k_out k_in "
+                         "small copies [inner]\n");
+    return 2;
+  }
+  FILE* f = std::fopen(argv[1], "r");
+  if (!f) return 2;
+  int ph = 0, pw = 0;
+  if (std::fscanf(f, "%d %d", &ph, &pw) != 2) return 2;
+  std::vector<double> psf((size_t)ph * pw);
+  for (double& v : psf)
+    if (std::fscanf(f, "%lf", &v) != 1) return 2;
+  std::fclose(f);
+  const int m = std::atoi(argv[2]), levels = std::atoi(argv[3]), solver = std::atoi(argv[4]),
+            wavelet = std::atoi(argv[5]), transfer = std::atoi(argv[6]),
+            prec = std::atoi(argv[7]), k_out = std::atoi(argv[8]), k_in = std::atoi(argv[9]),
+            small = std::atoi(argv[10]), copies = std::atoi(argv[11]);
+  const int inner = argc > 12 ? std::atoi(argv[12]) : DBL_INNER_CGLS;
+
+  dbl_ctx* ctx = nullptr;
+  int rc = dbl_create(&ctx, 0, nullptr, 0);
+  if (rc) return 3;
+  dbl_set_option(ctx, DBL_OPT_SMALL_CGLS, small);
+  const size_t esz = prec == DBL_F64 ? 8 : 4;
+  std::vector<double> mu((size_t)levels * k_out);
+  for (int i = 0; i < levels; ++i)
+    for (int k = 0; k < k_out; ++k) mu[(size_t)i * k_out + k] = 1e-3 * (1 << i);
+  dbl_opts o;
+  dbl_opts_default(&o);
+  o.k_out = k_out;
+  o.k_in = k_in;
+  o.precision = prec;
+  o.mu_schedule = mu.data();
+  o.inner_solver = inner;
+  std::vector<dbl_request> reqs(copies);
+  for (int q = 0; q < copies; ++q) {
+    void *b = nullptr, *x = nullptr;
+    hipMalloc(&b, (size_t)m * m * esz);
+    // DRYRUN_SHORT_X: an x buffer one element too short (the audit must see it)
+    hipMalloc(&x, ((size_t)m * m - (std::getenv("DRYRUN_SHORT_X") ? 1 : 0)) * esz);
+    reqs[q] = dbl_request{b, x, psf.data(), ph, pw, m, solver, wavelet, levels, transfer, o};
+  }
+  dbl_report rep;
+  if (copies == 1)
+    rc = dbl_deblur(ctx, reqs[0].b, psf.data(), ph, pw, m, solver, wavelet, levels, transfer, &o,
+                    reqs[0].x, &rep);
+  else
+    rc = dbl_deblur_batch(ctx, copies, reqs.data(), nullptr);
+  std::printf("status %d (%s)\n", rc, rc ? dbl_last_error(ctx) : "ok");
+  for (auto& kv : mock::launches) std::printf("launches %s %ld\n", kv.first.c_str(), kv.second);
+  std::printf("checked %ld pointers\n", mock::checked_pointers);
+  for (auto& v : mock::violations) std::printf("VIOLATION %s\n", v.c_str());
+  std::printf("violations %zu\n", mock::violations.size());
+  dbl_destroy(ctx);
+  return (rc || !mock::violations.empty()) ? 1 : 0;
+}

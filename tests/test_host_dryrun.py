@@ -1,0 +1,119 @@
+"""Dry runs of whole solves on the CPU: the library's own objects linked with a
+host-only stand-in for the HIP runtime (tests/host/hip_mock.cpp), which
+audits every kernel launch the engine issues instead of running it.
+
+For each launch the audit checks that every tile entry names a job of the
+launch and a tile below nti * ntj, that the tile grid fits the kernel's
+geometry, and that every pointer the kernel can dereference for the job
+(vector slots -- including the optional ones a kernel reads under a
+condition -- partial sums, scalar block, history, operator tables) lies
+inside one live allocation with the extent the kernel touches there.
+
+The first plan is the one that faulted the GPU once (m = 1024, Gaussian
+sigma 3 on 25 x 25, Split Bregman, Haar, 5 grids, Approach X) in every
+precision."""
+import os
+import subprocess
+
+import pytest
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HOST = os.path.join(ROOT, "tests", "host")
+BUILD = os.path.join(ROOT, "paper_2608_17123_amd", "_build")
+HIPCC = "/opt/rocm/bin/hipcc"
+CLANG = "/opt/rocm/llvm/bin/clang++"
+
+pytestmark = pytest.mark.skipif(not (os.path.exists(HIPCC) and os.path.exists(CLANG)),
+                                reason="needs the ROCm toolchain")
+
+
+@pytest.fixture(scope="module")
+def dryrun(tmp_path_factory):
+    if not os.path.isdir(BUILD) or not any(f.endswith(".o") for f in os.listdir(BUILD)):
+        from paper_2608_17123_amd import build
+        build.build(verbose=False)
+    out = tmp_path_factory.mktemp("dryrun")
+    objs = []
+    for src in ("hip_mock.cpp", "dryrun_main.cpp"):
+        o = str(out / (src + ".o"))
+        subprocess.run([HIPCC, "-x", "hip", "--offload-host-only", "-O1", "-std=c++17", "-fPIC",
+                        "-c", os.path.join(HOST, src), "-o", o], check=True, capture_output=True)
+        objs.append(o)
+    lib_objs = sorted(os.path.join(BUILD, f) for f in os.listdir(BUILD) if f.endswith(".o"))
+    exe = str(out / "dryrun")
+    r = subprocess.run([CLANG, "-rdynamic", *objs, *lib_objs, "-o", exe, "-ldl"],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    return exe, out
+
+
+def psf_file(out, name, P):
+    p = out / f"{name}.txt"
+    p.write_text(f"{P.shape[0]} {P.shape[1]}\n" + " ".join(repr(float(v)) for v in
+                                                          P.ravel(order="F")))
+    return str(p)
+
+
+SOLVER = {"irls": 0, "mm": 1, "sb": 2}
+WAVELET = {"haar": 0, "db4": 1}
+XFER = {"X": 0, "D": 1}
+PREC = {"f32": 0, "f64": 1, "bf16": 2}
+
+
+def run(dryrun, psf, m, levels, solver, wavelet, xfer, prec, k_out=2, k_in=30, small=1,
+        copies=1, inner=0):
+    exe, out = dryrun
+    args = [exe, psf, str(m), str(levels), str(SOLVER[solver]), str(WAVELET[wavelet]),
+            str(XFER[xfer]), str(PREC[prec]), str(k_out), str(k_in), str(small), str(copies),
+            str(inner)]
+    r = subprocess.run(args, capture_output=True, text=True, timeout=600)
+    print(r.stdout[-3000:])
+    return r
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+def test_faulted_plan_tables_are_sound(dryrun, prec):
+    psf = psf_file(dryrun[1], "g12", synth.gaussian_psf(3.0, 12))
+    r = run(dryrun, psf, 1024, 5, "sb", "haar", "X", prec)
+    assert r.returncode == 0, r.stdout[-2000:]
+    assert "violations 0" in r.stdout
+    # the plan really ran its solve: tiled phases on the four finest grids and
+    # the one-block CGLS on the 64 x 64 one (FP32 and BF16)
+    assert "launches k_cgls_p2" in r.stdout and "launches k_aux" in r.stdout
+    if prec != "f64":
+        assert "launches k_cgls_small" in r.stdout
+
+
+@pytest.mark.parametrize("case", [
+    ("motion", 512, 4, "mm", "db4", "D", "f32", 1, 1, 0),
+    ("motion", 256, 3, "irls", "haar", "D", "f64", 1, 1, 0),
+    ("g12", 1024, 5, "irls", "db4", "D", "f32", 0, 1, 0),
+    ("g7", 256, 4, "sb", "db4", "D", "bf16", 1, 3, 0),
+    ("g7", 256, 4, "mm", "haar", "X", "f32", 1, 2, 1),
+    ("g16", 512, 3, "sb", "haar", "X", "f32", 1, 1, 1),
+])
+def test_other_plans_tables_are_sound(dryrun, case):
+    kind, m, levels, solver, wavelet, xfer, prec, small, copies, inner = case
+    P = {"motion": synth.motion_psf(21, 0.7), "g12": synth.gaussian_psf(3.0, 12),
+         "g7": synth.gaussian_psf(2.5, 7), "g16": synth.gaussian_psf(4.0, 16)}[kind]
+    psf = psf_file(dryrun[1], kind, P)
+    r = run(dryrun, psf, m, levels, solver, wavelet, xfer, prec, small=small, copies=copies,
+            inner=inner)
+    assert r.returncode == 0, r.stdout[-2000:]
+    assert "violations 0" in r.stdout
+
+
+def test_audit_catches_a_bad_pointer(dryrun, tmp_path):
+    """The audit is not vacuous: a driver run whose request names an x buffer
+    one element too short is reported (the copy of the result runs past its
+    end)."""
+    exe, out = dryrun
+    psf = psf_file(out, "g4", synth.gaussian_psf(1.5, 4))
+    env = dict(os.environ, DRYRUN_SHORT_X="1")
+    r = subprocess.run([exe, psf, "64", "2", "0", "0", "0", "0", "2", "5", "1", "1", "0"],
+                       capture_output=True, text=True, timeout=120, env=env)
+    print(r.stdout[-2000:])
+    assert r.returncode == 1
+    assert "VIOLATION copy destination" in r.stdout
