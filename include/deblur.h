@@ -274,6 +274,19 @@ int dbl_dtransfer(dbl_ctx* ctx, int wavelet, int m_coarse, int precision,
 int dbl_cgls(dbl_ctx* ctx, const dbl_op* op, int level, const dbl_sub* sub, const void* b,
              const void* x0, int iters, void* x, double* resid_hist);
 
+/* dbl_cgls for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and launches, with every buffer beyond the caller's (CGLS
+ * state vectors, scalars, partial sums, job and tile tables) in one static
+ * device array of 64 MiB that each GPU the library runs on holds until the
+ * process ends.  The call itself allocates nothing (no hipMalloc / hipFree).
+ * A subproblem whose workspace exceeds the array (about 52 n + 64 KiB bytes
+ * in FP32 and BF16, 104 n in FP64: up to m = 1024 FP32, 512 FP64) returns
+ * DBL_ENOMEM before any device work.  Results equal dbl_cgls's.  All calls on
+ * one GPU share the array: calls that overlap on one GPU race. */
+int dbl_cgls_noalloc(dbl_ctx* ctx, const dbl_op* op, int level, const dbl_sub* sub,
+                     const void* b, const void* x0, int iters, void* x, double* resid_hist);
+
 /* The same subproblem and arguments solved by LSQR (Golub-Kahan
  * bidiagonalisation with Givens rotations; the inner solver of Sec. 3), for
  * exactly `iters` iterations from x0 (correction form: LSQR runs on the

@@ -40,7 +40,7 @@ INNER_SOLVERS = {"cgls": DBL_INNER_CGLS, "lsqr": DBL_INNER_LSQR}
 EXPORTS = [
     "dbl_create", "dbl_destroy", "dbl_set_option", "dbl_last_error", "dbl_sync", "dbl_workspace_bytes",
     "dbl_opts_default", "dbl_profile", "dbl_profile_read", "dbl_op_create", "dbl_op_destroy", "dbl_apply_A", "dbl_apply_L",
-    "dbl_dwt", "dbl_apply_A_batch", "dbl_apply_L_batch", "dbl_dwt_batch", "dbl_dtransfer", "dbl_cgls", "dbl_lsqr", "dbl_gcv", "dbl_deblur", "dbl_deblur_batch",
+    "dbl_dwt", "dbl_apply_A_batch", "dbl_apply_L_batch", "dbl_dwt_batch", "dbl_dtransfer", "dbl_cgls", "dbl_cgls_noalloc", "dbl_lsqr", "dbl_gcv", "dbl_deblur", "dbl_deblur_batch",
     "dbl_request_bytes", "dbl_server_create", "dbl_server_destroy", "dbl_server_submit",
     "dbl_server_step", "dbl_server_poll",
 ]
@@ -131,6 +131,7 @@ def lib():
         "dbl_dtransfer": (i, [vp, i, i, i, vp, vp]),
         "dbl_cgls": (i, [vp, vp, i, ctypes.POINTER(dbl_sub), vp, vp, i, vp, dp]),
         "dbl_lsqr": (i, [vp, vp, i, ctypes.POINTER(dbl_sub), vp, vp, i, vp, dp]),
+        "dbl_cgls_noalloc": (i, [vp, vp, i, ctypes.POINTER(dbl_sub), vp, vp, i, vp, dp]),
         "dbl_gcv": (i, [vp, vp, i, ctypes.POINTER(dbl_sub), vp, i, i, dp, dp]),
         "dbl_deblur": (i, [vp, vp, dp, i, i, i, i, i, i, i, ctypes.POINTER(dbl_opts), vp,
                            ctypes.POINTER(dbl_report)]),
@@ -437,6 +438,12 @@ def _krylov(entry, ctx, op, level, b, iters, x, gamma, w, c, x0, d_kind):
 def dbl_cgls(ctx, op, level, b, iters, x, gamma, w=None, c=None, x0=None, d_kind=None):
     """Run `iters` CGLS steps; returns the FP64 residual history."""
     return _krylov(lambda: lib().dbl_cgls, ctx, op, level, b, iters, x, gamma, w, c, x0, d_kind)
+
+
+def dbl_cgls_noalloc(ctx, op, level, b, iters, x, gamma, w=None, c=None, x0=None, d_kind=None):
+    """dbl_cgls with the library's static workspace (allocates nothing)."""
+    return _krylov(lambda: lib().dbl_cgls_noalloc, ctx, op, level, b, iters, x, gamma, w, c, x0,
+                   d_kind)
 
 
 def dbl_lsqr(ctx, op, level, b, iters, x, gamma, w=None, c=None, x0=None, d_kind=None):

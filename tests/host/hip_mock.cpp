@@ -376,7 +376,25 @@ void __hipRegisterFunction(void**, const void* hostFunction, char*, const char* 
                            unsigned int, uint3*, uint3*, dim3*, dim3*, int*) {
   mock::registered[hostFunction] = deviceName;
 }
-void __hipRegisterVar(void**, void*, char*, char*, int, size_t, int, int) {}
+// device variables: a fake device block of the variable's size per symbol
+static std::map<const void*, size_t> g_var_size;
+static std::map<const void*, void*> g_var_block;
+void __hipRegisterVar(void**, void* var, char*, char*, int, size_t size, int, int) {
+  g_var_size[var] = size;
+}
+hipError_t hipMalloc(void** p, size_t bytes);
+hipError_t hipGetSymbolAddress(void** dev, const void* symbol) {
+  auto it = g_var_block.find(symbol);
+  if (it == g_var_block.end()) {
+    auto sz = g_var_size.find(symbol);
+    if (sz == g_var_size.end()) return hipErrorInvalidSymbol;
+    void* p = nullptr;
+    if (hipMalloc(&p, sz->second) != hipSuccess) return hipErrorOutOfMemory;
+    it = g_var_block.emplace(symbol, p).first;
+  }
+  *dev = it->second;
+  return hipSuccess;
+}
 void __hipUnregisterFatBinary(void**) {}
 
 hipError_t hipMalloc(void** p, size_t bytes) {
