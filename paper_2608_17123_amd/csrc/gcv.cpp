@@ -45,47 +45,52 @@ int ensure_dct(dbl_ctx* ctx, int m, double** out) {
   return DBL_OK;
 }
 
-// Symbol block per op level: [a_k (n) | l(k) (m) | interior kernel].
-int ensure_symbol(dbl_ctx* ctx, const dbl_op* cop, int level, double** sym) {
-  dbl_op* op = const_cast<dbl_op*>(cop);
-  if (op->sym[level]) {
-    *sym = op->sym[level];
-    return DBL_OK;
-  }
-  const LevelHost& L = op->host.levels[level];
-  const int m = L.m;
-  const size_t n = (size_t)m * m;
-  const size_t nk = L.kint.size();
-  double* blk = nullptr;
-  int rc = dmalloc(ctx, (n + m + nk) * 8, (void**)&blk);
-  if (rc) return rc;
-  std::vector<double> host(m + nk);
-  for (int k = 0; k < m; ++k) {
-    const double s = std::sin(M_PI * k / (2.0 * m));
-    host[k] = 4.0 * s * s;
-  }
-  std::memcpy(host.data() + m, L.kint.data(), nk * 8);
-  rc = hip_check(ctx, hipMemcpy(blk + n, host.data(), host.size() * 8, hipMemcpyHostToDevice),
-                 "upload symbol inputs");
-  if (rc) {
-    dfree(ctx, blk);
-    return rc;
-  }
-  Job j;
-  std::memset(&j, 0, sizeof(j));
-  j.m = m;
-  j.i0 = L.kint_r0;
-  j.i1 = L.kint_r1;
-  j.v[G_KINT] = blk + n + m;
-  j.v[G_SYM] = blk;
+// GCV symbols a_k of every (operator, level) among the spectral requests that
+// does not have one yet: the operator's symbol block (every level) is
+// allocated once, and all missing levels are computed in one launch from the
+// inputs the operator's upload carries (l(k) and the interior kernel).
+int ensure_symbols(dbl_ctx* ctx, const std::vector<GcvReq>& reqs) {
   Launch La;
-  La.add(j, m, 4);
+  std::vector<std::pair<dbl_op*, int>> built;
+  for (const GcvReq& r : reqs) {
+    if (r.mode == DBL_GCV_EXACT) continue;
+    dbl_op* op = const_cast<dbl_op*>(r.op);
+    if (op->sym_ready[r.level]) continue;
+    if (!op->sym_blk) {
+      size_t tot = 0;
+      for (int i = 0; i < op->levels; ++i) {
+        const size_t mi = (size_t)op->host.levels[i].m;
+        tot += mi * mi;
+      }
+      int rc = dmalloc(ctx, tot * 8, (void**)&op->sym_blk);
+      if (rc) return rc;
+      double* p = op->sym_blk;
+      for (int i = 0; i < op->levels; ++i) {
+        const size_t mi = (size_t)op->host.levels[i].m;
+        op->sym[i] = p;
+        p += mi * mi;
+      }
+    }
+    const LevelHost& L = op->host.levels[r.level];
+    Job j;
+    std::memset(&j, 0, sizeof(j));
+    j.m = L.m;
+    j.i0 = L.kint_r0;
+    j.i1 = L.kint_r1;
+    j.v[G_KINT] = op->lam[r.level] + L.m;
+    j.v[G_SYM] = op->sym[r.level];
+    La.add(j, L.m, 4);
+    op->sym_ready[r.level] = 1;  // several requests may share an (op, level)
+    built.push_back({op, r.level});
+  }
+  if (La.empty()) return DBL_OK;
   LaunchArgs la;
-  if ((rc = La.upload(ctx, la))) return rc;
-  if ((rc = hip_check(ctx, launch_gcv_symbol(la), "gcv symbol"))) return rc;
-  op->sym[level] = blk;
-  *sym = blk;
-  return DBL_OK;
+  int rc = La.upload(ctx, la);
+  if (!rc) rc = hip_check(ctx, timed(ctx, "gcv_symbol", 0.0, [&] { return launch_gcv_symbol(la); }),
+                          "gcv symbol");
+  if (rc)
+    for (auto& b : built) b.first->sym_ready[b.second] = 0;
+  return rc;
 }
 
 int blas_check(dbl_ctx* ctx, rocblas_status st, const char* what) {
@@ -223,6 +228,7 @@ int gcv_run(dbl_ctx* ctx, std::vector<GcvReq>& reqs) {
     if (r.mode == DBL_GCV_EXACT && m * m > 4096)
       return set_err(ctx, DBL_ENOTSUP, "EXACT GCV needs n <= 4096; use SPECTRAL");
   }
+  if ((rc = ensure_symbols(ctx, reqs))) return rc;
   std::vector<Job> base(reqs.size());
   std::vector<PartLayout> PLs(reqs.size());
   for (size_t q = 0; q < reqs.size(); ++q) {
@@ -230,9 +236,10 @@ int gcv_run(dbl_ctx* ctx, std::vector<GcvReq>& reqs) {
     const int m = r.op->host.levels[r.level].m;
     PLs[q] = part_layout(r.part, m);
     const bool exact = r.mode == DBL_GCV_EXACT;
-    double *sym = nullptr, *dct = nullptr;
+    double *sym = nullptr, *dct = nullptr, *lam = nullptr;
     if (!exact) {
-      if ((rc = ensure_symbol(ctx, r.op, r.level, &sym))) return rc;
+      sym = r.op->sym[r.level];
+      lam = r.op->lam[r.level];
       if ((rc = ensure_dct(ctx, m, &dct))) return rc;
     }
     Job& j = base[q];
@@ -249,7 +256,7 @@ int gcv_run(dbl_ctx* ctx, std::vector<GcvReq>& reqs) {
     j.v[G_BH] = r.bh;
     j.v[G_E] = r.e;
     j.v[G_SYM] = exact ? r.in : sym;  // exact: nu (written by exact_data)
-    j.v[G_LAM] = exact ? nullptr : sym + (size_t)m * m;
+    j.v[G_LAM] = exact ? nullptr : lam;
     j.v[G_DCT] = dct;
     if (exact) j.flags |= F_EXACT;
   }

@@ -303,29 +303,40 @@ int Launch::upload(dbl_ctx* ctx, LaunchArgs& la) {
 
 // ----------------------------------------------------------- operators ----
 
-static int upload_vec(dbl_ctx* ctx, dbl_op* op, const void* src, size_t bytes, void** d) {
-  int rc = dmalloc(ctx, bytes, d);
-  if (rc) return rc;
-  op->bufs.push_back(*d);
-  return hip_check(ctx, hipMemcpy(*d, src, bytes, hipMemcpyHostToDevice), "upload table");
+namespace {
+
+// Host image of an operator's device allocation.  Arrays are appended at
+// 256-byte offsets; pointer fields of the level structures hold offset + 1
+// (0 = no array) until the allocation exists, then fix() turns them into
+// device addresses.
+struct Blob {
+  std::vector<char> bytes;
+  size_t put(const void* src, size_t n) {
+    const size_t off = (bytes.size() + 255) & ~size_t(255);
+    bytes.resize(off + std::max<size_t>(n, 1), 0);
+    if (src && n) std::memcpy(bytes.data() + off, src, n);
+    return off;
+  }
+  template <typename T> T* ref(const std::vector<T>& v) {
+    return reinterpret_cast<T*>(put(v.data(), v.size() * sizeof(T)) + 1);
+  }
+};
+
+template <typename T> void fix(T*& p, char* base) {
+  if (p) p = reinterpret_cast<T*>(base + (reinterpret_cast<uintptr_t>(p) - 1));
 }
 
-static int upload_t1(dbl_ctx* ctx, dbl_op* op, const Table1DHost& h, Table1D& d) {
+void put_t1(Blob& B, const Table1DHost& h, Table1D& d) {
   d.R = h.R;
   d.St = h.St;
   d.Sb = h.Sb;
   d.rows = h.rows;
-  std::vector<float> f(h.taps.begin(), h.taps.end());
-  void *pf, *pd;
-  int rc = upload_vec(ctx, op, f.data(), f.size() * 4, &pf);
-  if (rc) return rc;
-  rc = upload_vec(ctx, op, h.taps.data(), h.taps.size() * 8, &pd);
-  d.tf = static_cast<const float*>(pf);
-  d.td = static_cast<const double*>(pd);
-  return rc;
+  const std::vector<float> f(h.taps.begin(), h.taps.end());
+  d.tf = B.ref(f);
+  d.td = B.ref(h.taps);
 }
 
-static int upload_t2(dbl_ctx* ctx, dbl_op* op, const Table2DHost& h, Table2D& d) {
+void put_t2(Blob& B, const Table2DHost& h, Table2D& d) {
   d.R0 = h.R0;
   d.R1 = h.R1;
   d.St0 = h.St0;
@@ -336,26 +347,34 @@ static int upload_t2(dbl_ctx* ctx, dbl_op* op, const Table2DHost& h, Table2D& d)
   d.rows1 = h.rows1;
   std::vector<short2> e(h.val.size());
   for (size_t k = 0; k < e.size(); ++k) e[k] = make_short2(h.e0[k], h.e1[k]);
-  std::vector<float> f(h.val.begin(), h.val.end());
-  void *po, *pe, *pf, *pd;
-  int rc = upload_vec(ctx, op, h.off.data(), h.off.size() * 4, &po);
-  if (!rc) rc = upload_vec(ctx, op, e.data(), std::max<size_t>(1, e.size()) * 4, &pe);
-  if (!rc) rc = upload_vec(ctx, op, f.data(), std::max<size_t>(1, f.size()) * 4, &pf);
-  if (!rc) rc = upload_vec(ctx, op, h.val.data(), std::max<size_t>(1, h.val.size()) * 8, &pd);
-  if (rc) return rc;
-  d.off = static_cast<const int*>(po);
-  d.e = static_cast<const short2*>(pe);
-  d.vf = static_cast<const float*>(pf);
-  d.vd = static_cast<const double*>(pd);
-  return DBL_OK;
+  const std::vector<float> f(h.val.begin(), h.val.end());
+  d.off = B.ref(h.off);
+  d.e = B.ref(e);
+  d.vf = B.ref(f);
+  d.vd = B.ref(h.val);
 }
+
+void fix_level(LevelOp& d, char* base) {
+  Table1D* t1[4] = {&d.f0, &d.f1, &d.a0, &d.a1};
+  for (Table1D* t : t1) {
+    fix(t->tf, base);
+    fix(t->td, base);
+  }
+  Table2D* t2[2] = {&d.f2, &d.a2};
+  for (Table2D* t : t2) {
+    fix(t->off, base);
+    fix(t->e, base);
+    fix(t->vf, base);
+    fix(t->vd, base);
+  }
+}
+
+}  // namespace
 
 void op_free(dbl_op* op) {
   if (!op) return;
-  for (void* p : op->bufs) dfree(op->ctx, p);
-  for (double* p : op->sym) dfree(op->ctx, p);
-  if (op->d_ops) dfree(op->ctx, op->d_ops);
-  if (op->d_pad) dfree(op->ctx, op->d_pad);
+  if (op->blob) dfree(op->ctx, op->blob);
+  if (op->sym_blk) dfree(op->ctx, op->sym_blk);
   delete op;
 }
 
@@ -375,9 +394,9 @@ int op_build(dbl_ctx* ctx, const double* psf, int ph, int pw, int m, int levels,
     return set_err(ctx, DBL_ENOTSUP, std::string("hierarchy: ") + ex.what());
   }
   op->sep = op->host.sep;
+  Blob B;
   std::vector<LevelOp> lv(levels);
-  int rc = DBL_OK;
-  for (int i = 0; i < levels && !rc; ++i) {
+  for (int i = 0; i < levels; ++i) {
     const LevelHost& L = op->host.levels[i];
     LevelOp& d = lv[i];
     std::memset(&d, 0, sizeof(d));
@@ -386,51 +405,75 @@ int op_build(dbl_ctx* ctx, const double* psf, int ph, int pw, int m, int levels,
     d.rb = L.rb;
     d.R = L.sep ? L.rb : L.R;
     if (L.sep) {
-      rc = upload_t1(ctx, op, L.f0, d.f0);
-      if (!rc) rc = upload_t1(ctx, op, L.f1, d.f1);
-      if (!rc) rc = upload_t1(ctx, op, L.a0, d.a0);
-      if (!rc) rc = upload_t1(ctx, op, L.a1, d.a1);
+      put_t1(B, L.f0, d.f0);
+      put_t1(B, L.f1, d.f1);
+      put_t1(B, L.a0, d.a0);
+      put_t1(B, L.a1, d.a1);
     } else {
-      rc = upload_t2(ctx, op, L.f2, d.f2);
-      if (!rc) rc = upload_t2(ctx, op, L.a2, d.a2);
+      put_t2(B, L.f2, d.f2);
+      put_t2(B, L.a2, d.a2);
     }
   }
-  if (!rc) rc = dmalloc(ctx, sizeof(LevelOp) * levels, (void**)&op->d_ops);
-  if (!rc)
-    rc = hip_check(ctx, hipMemcpy(op->d_ops, lv.data(), sizeof(LevelOp) * levels,
-                                  hipMemcpyHostToDevice),
-                   "upload level ops");
   // padded variants for the larger radius buckets of separable levels
   std::vector<LevelOp> pad((size_t)levels * NBUCKETS);
   std::memset(pad.data(), 0, pad.size() * sizeof(LevelOp));
-  for (int i = 0; i < levels && !rc; ++i) {
+  for (int i = 0; i < levels; ++i) {
     const LevelHost& L = op->host.levels[i];
     if (!L.sep) continue;
-    for (int k = 0; k < NBUCKETS && !rc; ++k) {
+    for (int k = 0; k < NBUCKETS; ++k) {
       const int b = RB_BUCKETS[k];
       if (b < L.rb) continue;
       LevelOp& d = pad[(size_t)i * NBUCKETS + k];
-      if (b == L.rb) {
-        d = lv[i];
-        continue;
-      }
       d = lv[i];
+      if (b == L.rb) continue;
       d.rb = b;
       d.R = b;
       Table1DHost t[4] = {L.f0, L.f1, L.a0, L.a1};
       Table1D* dt[4] = {&d.f0, &d.f1, &d.a0, &d.a1};
-      for (int q = 0; q < 4 && !rc; ++q) {
+      for (int q = 0; q < 4; ++q) {
         pad_table(t[q], b);
-        rc = upload_t1(ctx, op, t[q], *dt[q]);
+        put_t1(B, t[q], *dt[q]);
       }
     }
   }
-  if (!rc) rc = dmalloc(ctx, sizeof(LevelOp) * pad.size(), (void**)&op->d_pad);
-  if (!rc)
-    rc = hip_check(ctx, hipMemcpy(op->d_pad, pad.data(), sizeof(LevelOp) * pad.size(),
-                                  hipMemcpyHostToDevice),
-                   "upload padded level ops");
+  // GCV symbol inputs per level: l(k) = 4 sin^2(pi k / 2m), then the
+  // interior kernel
+  std::vector<size_t> lam_off(levels);
+  for (int i = 0; i < levels; ++i) {
+    const LevelHost& L = op->host.levels[i];
+    std::vector<double> h(L.m + L.kint.size());
+    for (int k = 0; k < L.m; ++k) {
+      const double s = std::sin(M_PI * k / (2.0 * L.m));
+      h[k] = 4.0 * s * s;
+    }
+    std::memcpy(h.data() + L.m, L.kint.data(), L.kint.size() * 8);
+    lam_off[i] = B.put(h.data(), h.size() * 8);
+  }
+  const size_t ops_off = B.put(nullptr, sizeof(LevelOp) * lv.size());
+  const size_t pad_off = B.put(nullptr, sizeof(LevelOp) * pad.size());
+  int rc = dmalloc(ctx, B.bytes.size(), &op->blob);
+  if (rc) {
+    delete op;
+    return rc;
+  }
+  char* base = static_cast<char*>(op->blob);
+  for (LevelOp& d : lv) fix_level(d, base);
+  for (LevelOp& d : pad) fix_level(d, base);
+  std::memcpy(B.bytes.data() + ops_off, lv.data(), sizeof(LevelOp) * lv.size());
+  std::memcpy(B.bytes.data() + pad_off, pad.data(), sizeof(LevelOp) * pad.size());
+  op->d_ops = reinterpret_cast<LevelOp*>(base + ops_off);
+  op->d_pad = reinterpret_cast<LevelOp*>(base + pad_off);
+  op->lam.resize(levels);
+  for (int i = 0; i < levels; ++i) op->lam[i] = reinterpret_cast<double*>(base + lam_off[i]);
   op->sym.assign(levels, nullptr);
+  op->sym_ready.assign(levels, 0);
+  // one asynchronous copy through the staging ring
+  void* staged = nullptr;
+  rc = stage(ctx, B.bytes.data(), B.bytes.size(), &staged);
+  if (!rc)
+    rc = hip_check(ctx, hipMemcpyAsync(op->blob, staged, B.bytes.size(), hipMemcpyDeviceToDevice,
+                                       ctx->stream),
+                   "upload operator");
   if (rc) {
     op_free(op);
     return rc;

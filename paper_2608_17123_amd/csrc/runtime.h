@@ -77,8 +77,15 @@ struct dbl_op {
   // bucket >= the level's own ([levels * NBUCKETS]; smaller buckets unset),
   // so jobs of different radii can share one launch
   dbl::LevelOp* d_pad = nullptr;
-  std::vector<void*> bufs;           // device table storage
-  std::vector<double*> sym;          // per level GCV symbol a_k (FP64, n_i), lazily built
+  // every table of the hierarchy, d_ops, d_pad and the GCV symbol inputs in
+  // one device allocation, uploaded with one copy
+  void* blob = nullptr;
+  std::vector<double*> lam;          // per level: l(k) (m) then the interior kernel (FP64)
+  // per level GCV symbol a_k (FP64, n_i each), in one allocation made and
+  // filled (one launch for every level that needs it) on first use
+  double* sym_blk = nullptr;
+  std::vector<double*> sym;
+  std::vector<char> sym_ready;
 };
 
 namespace dbl {

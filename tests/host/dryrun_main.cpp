@@ -2,10 +2,11 @@
 // (hip_mock.cpp): every launch the engine issues is audited instead of run.
 //
 // usage: dryrun <psf-file> <m> <levels> <solver> <wavelet> <transfer> <precision>
-//               <k_out> <k_in> <small_cgls> <copies> [<inner>]
+//               <k_out> <k_in> <small_cgls> <copies> [<inner> [<gcv mode>]]
 // psf-file: "ph pw" then ph*pw values, column-major.  copies > 1 solves that
 // many copies of the request in one dbl_deblur_batch call.  Parameters are a
-// fixed schedule (no GCV).  Prints the launch counts per kernel family and
+// fixed schedule, or chosen by GCV when a GCV mode is given (the stand-in's
+// device memory holds zeros, so the minimisations run their full length).  Prints the launch counts per kernel family and
 // every violation; exits 1 when there is one.
 #include <cstdio>
 #include <cstdlib>
@@ -42,6 +43,7 @@ int main(int argc, char** argv) {
             prec = std::atoi(argv[7]), k_out = std::atoi(argv[8]), k_in = std::atoi(argv[9]),
             small = std::atoi(argv[10]), copies = std::atoi(argv[11]);
   const int inner = argc > 12 ? std::atoi(argv[12]) : DBL_INNER_CGLS;
+  const int gcv = argc > 13 ? std::atoi(argv[13]) : 0;  // 0: fixed parameters; else a GCV mode
 
   dbl_ctx* ctx = nullptr;
   int rc = dbl_create(&ctx, 0, nullptr, 0);
@@ -56,7 +58,8 @@ int main(int argc, char** argv) {
   o.k_out = k_out;
   o.k_in = k_in;
   o.precision = prec;
-  o.mu_schedule = mu.data();
+  o.mu_schedule = gcv ? nullptr : mu.data();
+  if (gcv) o.gcv_mode = gcv;
   o.inner_solver = inner;
   std::vector<dbl_request> reqs(copies);
   for (int q = 0; q < copies; ++q) {

@@ -63,11 +63,11 @@ PREC = {"f32": 0, "f64": 1, "bf16": 2}
 
 
 def run(dryrun, psf, m, levels, solver, wavelet, xfer, prec, k_out=2, k_in=30, small=1,
-        copies=1, inner=0):
+        copies=1, inner=0, gcv=0):
     exe, out = dryrun
     args = [exe, psf, str(m), str(levels), str(SOLVER[solver]), str(WAVELET[wavelet]),
             str(XFER[xfer]), str(PREC[prec]), str(k_out), str(k_in), str(small), str(copies),
-            str(inner)]
+            str(inner), str(gcv)]
     r = subprocess.run(args, capture_output=True, text=True, timeout=600)
     print(r.stdout[-3000:])
     return r
@@ -117,3 +117,13 @@ def test_audit_catches_a_bad_pointer(dryrun, tmp_path):
     print(r.stdout[-2000:])
     assert r.returncode == 1
     assert "VIOLATION copy destination" in r.stdout
+
+
+@pytest.mark.parametrize("solver,prec", [("irls", "f32"), ("sb", "f64")])
+def test_spectral_gcv_plan_tables_are_sound(dryrun, solver, prec):
+    """Spectral GCV on every grid of a 3-grid batch of two solves: symbol,
+    DCT products, completion, grid and Brent launches are audited too."""
+    psf = psf_file(dryrun[1], "g7", synth.gaussian_psf(2.5, 7))
+    r = run(dryrun, psf, 256, 3, solver, "db4", "X", prec, k_out=3, k_in=5, copies=2, gcv=2)
+    assert r.returncode == 0, r.stdout[-2000:]
+    assert "violations 0" in r.stdout and "launches k_gcv_symbol" in r.stdout
