@@ -187,7 +187,12 @@ typedef enum dbl_option {
    * at least 512 x 512 run the streaming column kernel (a block marches
    * along the columns of a 512-row strip); 0: the tiled kernel.  Both form
    * the same sums in the same order, so results are identical. */
-  DBL_OPT_STREAM_A = 2
+  DBL_OPT_STREAM_A = 2,
+  /* 1 (default): the tiled CGLS phases of a level with a separable operator
+   * and m >= 32 run the 32 x 32 tile kernels laid out for the wavefront; 0:
+   * the generic tile kernels.  Both form every sum, including the per-tile
+   * FP64 norm partials, in the same order. */
+  DBL_OPT_TILE32 = 3
 } dbl_option;
 /* Set a context option.  Returns DBL_EINVAL for an unknown option or value.
  * Takes effect for work issued afterwards. */

@@ -167,6 +167,16 @@ __device__ __forceinline__ void decode_tile(const Job* __restrict__ jobs,
   tj = tix / job->nti;
 }
 
+// A pointer the kernel may only use for device (global) memory: every vector
+// a job names is a device allocation (the library's or the caller's), whose
+// generic address is its global address.  Loads through it are global loads,
+// which count in vmcnt alone (a generic load also counts in lgkmcnt, so every
+// later wait for LDS would wait for it too).
+template <typename T> using GlobalPtr = __attribute__((address_space(1))) T*;
+template <typename T> __device__ __forceinline__ GlobalPtr<T> gview(T* p) {
+  return (GlobalPtr<T>)p;
+}
+
 // ------------------------------------------------------------ storage --
 // Storage types of the CGLS state vectors.  With DBL_BF16 the vectors p, s,
 // r1, r2, q1, q2 are stored as bfloat16 (round to nearest even from FP32)

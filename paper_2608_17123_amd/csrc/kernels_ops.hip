@@ -63,13 +63,6 @@ __global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 3 : 2) k_apply_sep(
 constexpr int STREAM_ROWS = 512, STREAM_COLS = 256, STREAM_MIN_M = 512;
 // class rows of an axis-1 table the streaming kernel stages in LDS
 constexpr int STREAM_MAX_ROWS = 2 * (2 * MAX_R + 3) + 1;
-// A pointer the kernel may only use for device (global) memory: every vector
-// a job names is a device allocation (the library's or the caller's), whose
-// generic address is its global address.
-template <typename T> using GlobalPtr = __attribute__((address_space(1))) T*;
-template <typename T> __device__ __forceinline__ GlobalPtr<T> gview(T* p) {
-  return (GlobalPtr<T>)p;
-}
 template <int RB>
 __global__ void __launch_bounds__(STREAM_ROWS) k_apply_stream(const Job* __restrict__ jobs,
                                                               const uint32_t* __restrict__ tiles) {

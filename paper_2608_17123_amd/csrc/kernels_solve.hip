@@ -562,6 +562,7 @@ struct Dummy {};
   } while (0)
 
 hipError_t launch_cgls_p1(const LaunchArgs& la, int precision, int sep, int rb, int H) {
+  if (sep && la.tile32) return launch_cgls_p1_sep(la, precision, rb, la.ntiles > P2_WIDE_TILES);
   if (precision == 1) DISPATCH_STENCIL_S(k_cgls_p1, double, double, la, sep, rb, H);
   else if (la.ntiles > P2_WIDE_TILES && precision == 2)
     DISPATCH_STENCIL_S(k_cgls_p1_wide, float, bf16s, la, sep, rb, H);
@@ -573,6 +574,7 @@ hipError_t launch_cgls_p1(const LaunchArgs& la, int precision, int sep, int rb, 
 }
 
 hipError_t launch_cgls_p2(const LaunchArgs& la, int precision, int sep, int rb, int H) {
+  if (sep && la.tile32) return launch_cgls_p2_sep(la, precision, rb, la.ntiles > P2_WIDE_TILES);
   if (precision == 1) DISPATCH_STENCIL_S(k_cgls_p2, double, double, la, sep, rb, H);
   else if (la.ntiles > P2_WIDE_TILES && precision == 2)
     DISPATCH_STENCIL_S(k_cgls_p2_wide, float, bf16s, la, sep, rb, H);

@@ -11,6 +11,9 @@ struct LaunchArgs {
   int ntiles;            // blocks in the launch
   int m_max;             // largest grid among the jobs (sizes LDS)
   hipStream_t stream;
+  // every job has m >= 32 and the 32 x 32 tile kernels are enabled: the CGLS
+  // phases of separable operators take k_cgls_p1_sep / k_cgls_p2_sep
+  bool tile32 = false;
 };
 
 // Vector slots of CGLS / solver jobs (Job::v indices).
@@ -48,6 +51,11 @@ hipError_t launch_dtransfer(const LaunchArgs& la, int precision);
 hipError_t launch_cgls_init(const LaunchArgs& la, int precision);
 hipError_t launch_cgls_p1(const LaunchArgs& la, int precision, int sep, int rb, int H);
 hipError_t launch_cgls_p2(const LaunchArgs& la, int precision, int sep, int rb, int H);
+// CGLS phases for separable operators on 32 x 32 tiles (kernels_cgls_sep.hip);
+// `wide` selects the register-bounded variant for launches that fill the chip.
+hipError_t launch_cgls_p1_sep(const LaunchArgs& la, int precision, int rb, bool wide);
+hipError_t launch_cgls_p2_sep(const LaunchArgs& la, int precision, int rb, bool wide);
+size_t cgls_sep_lds(int phase, int precision, int rb);
 hipError_t launch_aux(const LaunchArgs& la, int precision);
 hipError_t launch_stats(const LaunchArgs& la, int precision, int sep, int rb, int H);
 hipError_t launch_fill(const LaunchArgs& la, int precision);

@@ -232,6 +232,7 @@ extern "C" int dbl_cgls_noalloc(dbl_ctx* ctx, const dbl_op* op, int level, const
     la.ntiles = tiles_n;
     la.m_max = m;
     la.stream = ctx->stream;
+    la.tile32 = ctx->tile32 && m >= 32;
     return la;
   };
   if ((rc = hip_check(ctx, launch_set_gamma(la_for(k_gamma, 1, d_one)), "set gamma"))) return rc;

@@ -266,6 +266,7 @@ void Launch::add_grid(const Job& j0, int nti, int ntj, int group) {
   for (int t = 0; t < j.nti * j.ntj; ++t) tiles.push_back((idx << 16) | (uint32_t)t);
   tiles_upto.push_back((int)tiles.size());
   m_max = std::max(m_max, j.m);
+  m_min = std::min(m_min, j.m);
 }
 
 void xcd_order(std::vector<uint32_t>& tiles, size_t s0, size_t s1, int nxcd) {
@@ -298,6 +299,7 @@ int Launch::upload(dbl_ctx* ctx, LaunchArgs& la) {
   la.ntiles = (int)tiles.size();
   la.m_max = m_max;
   la.stream = ctx->stream;
+  la.tile32 = ctx->tile32 && m_min >= 32;
   return DBL_OK;
 }
 
@@ -686,11 +688,16 @@ namespace {
 
 struct GroupKey {
   int prec, sep, rb, H;
+  // CGLS phases: separable jobs on grids of at least 32 (the 32 x 32 tile
+  // kernels) launch apart from smaller ones, so a job's kernel depends on
+  // its own grid alone, never on which jobs share its launch
+  int t32 = 0;
   bool operator<(const GroupKey& o) const {
     if (prec != o.prec) return prec < o.prec;
     if (sep != o.sep) return sep < o.sep;
     if (rb != o.rb) return rb < o.rb;
-    return H < o.H;
+    if (H != o.H) return H < o.H;
+    return t32 < o.t32;
   }
 };
 
@@ -1159,7 +1166,8 @@ int engine_step(dbl_ctx* ctx, std::vector<Slot*>& slots) {
       j.v[V_B] = const_cast<void*>(s->B[lv]);
       j.v[V_C1] = s->C1;
       j.v[V_C2] = s->C2;
-      const GroupKey gk = pe.key;
+      GroupKey gk = pe.key;
+      gk.t32 = gk.sep && j.m >= 32;
       if (pe.small_lds) {
         Job js = j;
         js.i0 = s->opts.k_in;

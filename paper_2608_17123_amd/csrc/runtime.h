@@ -51,6 +51,7 @@ struct dbl_ctx {
   int small_cgls = 1;
   // streaming separable blur for large FP32 grids in the operator entry points
   int stream_a = 1;
+  int tile32 = 1;  // 32 x 32 tile CGLS kernels for separable operators (DBL_OPT_TILE32)
   size_t lds_limit = 65536;
   // EXACT-tier GCV: rocBLAS handle (rocblas_handle) and dense FP64 workspace
   void* blas = nullptr;
@@ -155,6 +156,7 @@ struct Launch {
   std::vector<int> seg_start;   // first tile of each run of equal group
   int last_group = 0;
   int m_max = 0;
+  int m_min = 1 << 30;
   void add(const Job& j, int grid_m, int esz, int group = 0);
   // a job cut into nti x ntj tiles of a kernel's own geometry
   void add_grid(const Job& j, int nti, int ntj, int group = 0);

@@ -142,6 +142,32 @@ void check_op(const std::string& k, int jb, const Job& j, bool dbl_taps) {
 
 int tile_edge_of(int m) { return dbl::tile_edge(m); }
 
+// The 32 x 32 tile CGLS kernels: a grid of at least 32, a separable operator
+// whose four tables are padded to the kernel's radius bucket rb (every tap
+// row 2 rb + 1 long, the seam classes inside the rows), and the dynamic LDS
+// the kernel lays out (haloed tile, pass-A result, tap rows, gradient part).
+void check_sep32(const std::string& k, int jb, const Job& j, int rb, size_t esz, int phase,
+                 size_t shmem) {
+  if (j.m < 32) fail(k, jb, "32 x 32 tile kernel on a grid of " + std::to_string(j.m));
+  if (!j.op || !owner(j.op, sizeof(dbl::LevelOp))) return;
+  const dbl::LevelOp& op = *j.op;
+  if (!op.sep) {
+    fail(k, jb, "32 x 32 tile kernel on a non-separable operator");
+    return;
+  }
+  const dbl::Table1D* ts[4] = {&op.f0, &op.f1, &op.a0, &op.a1};
+  for (const dbl::Table1D* t : ts) {
+    if (t->R != rb) fail(k, jb, "table radius " + std::to_string(t->R) + " != bucket " +
+                                    std::to_string(rb));
+    if (t->rows != t->St + 1 + t->Sb) fail(k, jb, "table rows != St + 1 + Sb");
+    if (t->St + t->Sb > j.m) fail(k, jb, "seam rows exceed the grid");
+  }
+  const size_t e = (size_t)(32 + 2 * rb) * (32 + 2 * rb + 1) + (size_t)(32 + 2 * rb) * 33 +
+                   2 * (2 * rb + 1) + (phase == 2 ? 32 * 32 : 0);
+  if (shmem < e * esz)
+    fail(k, jb, "dynamic LDS " + std::to_string(shmem) + " < " + std::to_string(e * esz));
+}
+
 void audit(const void* func, dim3 grid, dim3 block, void** args, size_t shmem) {
   const std::string name = kernel_name(func);
   // family: the unqualified kernel name ("void dbl::k_cgls_p2<...>(...)" -> k_cgls_p2)
@@ -209,10 +235,11 @@ void audit(const void* func, dim3 grid, dim3 block, void** args, size_t shmem) {
         need(fam, jb, "V_XOLD", v(dbl::V_XOLD), n * T);
         if (irls) need(fam, jb, "V_W", v(dbl::V_W), nl * T);
       }
-    } else if (fam == "k_cgls_p1" || fam == "k_cgls_p1_wide") {
+    } else if (fam == "k_cgls_p1" || fam == "k_cgls_p1_wide" || fam == "k_cgls_p1_sep") {
       const size_t T = tsize(ta[0]), S = tsize(ta[1]);
       grid_is(m);
       check_op(fam, jb, j, T == 8);
+      if (fam == "k_cgls_p1_sep") check_sep32(fam, jb, j, std::atoi(ta[2].c_str()), T, 1, shmem);
       need(fam, jb, "V_S", v(dbl::V_S), n * S);
       need(fam, jb, "V_PA", v(dbl::V_PA), n * S);
       need(fam, jb, "V_PB", v(dbl::V_PB), n * S);
@@ -225,10 +252,11 @@ void audit(const void* func, dim3 grid, dim3 block, void** args, size_t shmem) {
         need(fam, jb, "pr[0]", j.pr[0], (size_t)ntile * 2 * 8);
         need(fam, jb, "pr[1]", j.pr[1], (size_t)ntile * 2 * 8);
       }
-    } else if (fam == "k_cgls_p2" || fam == "k_cgls_p2_wide") {
+    } else if (fam == "k_cgls_p2" || fam == "k_cgls_p2_wide" || fam == "k_cgls_p2_sep") {
       const size_t T = tsize(ta[0]), S = tsize(ta[1]);
       grid_is(m);
       check_op(fam, jb, j, T == 8);
+      if (fam == "k_cgls_p2_sep") check_sep32(fam, jb, j, std::atoi(ta[2].c_str()), T, 2, shmem);
       need(fam, jb, "V_R1A", v(dbl::V_R1A), n * S);
       need(fam, jb, "V_R1B", v(dbl::V_R1B), n * S);
       need(fam, jb, "V_R2A", v(dbl::V_R2A), nl * S);
