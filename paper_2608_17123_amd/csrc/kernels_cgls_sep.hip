@@ -97,12 +97,21 @@ template <typename E> struct LaneOff {
   uint32_t g;    // image grid: i + jh m
   uint32_t x;    // axis-0 differences (stride m - 1 per column): i + jh (m - 1)
   uint32_t xu;   // lane part of the axis-0 difference above
+  uint32_t gu;   // lane part of the pixel above (same rule as xu)
+  uint32_t r;    // i alone: the pixel's row in the column pair's first column
   __device__ __forceinline__ LaneOff(int i, int jh, int m, int row0) {
     g = (uint32_t)(i + jh * m) * (uint32_t)sizeof(E);
     x = (uint32_t)(i + jh * (m - 1)) * (uint32_t)sizeof(E);
     xu = (row0 > 0 || i == 0) ? x : x - (uint32_t)sizeof(E);
+    gu = (row0 > 0 || i == 0) ? g : g - (uint32_t)sizeof(E);
+    r = (uint32_t)i * (uint32_t)sizeof(E);
   }
 };
+
+// Every multiply-add of the vector updates is an explicit fma: a value such
+// as p = s + beta p is formed by its tile and again by each neighbour whose
+// halo holds it, and all of them must agree bit for bit (phase 2 recomputes
+// q2 from the stored p), whatever the compiler would contract in each copy.
 
 // ------------------------------------------------------ convolution passes --
 // Pass A along axis 0 for all NC haloed columns and the TE rows of the tile:
@@ -209,6 +218,15 @@ __device__ __forceinline__ void stage_taps(T* taps, GP<const T> tab0, int St0, G
   else if (t < 2 * NTAP) taps[t] = tab1[St1 * NTAP + t - NTAP];
 }
 
+// Entry of q2 = sqrt(g) diag(w) L p between pixel value a and its forward
+// neighbour b, as stored: both phases form it with these operations, so
+// phase 2 recomputes exactly the values phase 1 summed into |q|^2.
+template <typename T, typename S>
+__device__ __forceinline__ T grad_entry(double sg, T a, T b, T w) {
+  const double d = ((double)b - (double)a) * (double)w;
+  return rtv<S>((T)(sg * d));
+}
+
 // ------------------------------------------------------------------ phase 1 --
 // p = s + beta p (beta = |s_k|^2 / |s_{k-1}|^2; p = s on the first
 // iteration), q1 = A p, q2 = sqrt(g) D p; |q|^2 partial per tile.
@@ -245,8 +263,7 @@ __device__ __forceinline__ void p1_sep_body(const Job* __restrict__ jobs,
   const double sg = job->scal[S_SQRTG];
   const unsigned msk = (unsigned)m - 1u;
   const uint32_t n = (uint32_t)m * (uint32_t)m, nx = (uint32_t)(m - 1) * (uint32_t)m;
-  const Vec<S> s(job->v[V_S], n), pa(job->v[V_PA], n), pb(job->v[V_PB], n), q1(job->v[V_Q1], n),
-      q2(job->v[V_Q2], 2 * nx);
+  const Vec<S> s(job->v[V_S], n), pa(job->v[V_PA], n), pb(job->v[V_PB], n), q1(job->v[V_Q1], n);
   const Vec<T> w(job->v[V_W], 2 * nx);
 
   // haloed tile of s (and p): lane = row row0 - H + lane (periodic), wave wv
@@ -303,11 +320,12 @@ __device__ __forceinline__ void p1_sep_body(const Job* __restrict__ jobs,
   if (hrow) {
 #pragma unroll
     for (int k = 0; k < G::KC; ++k)
-      Xs[lane * G::LX + wv * G::KC + k] = first ? va[k] : rtv<S>(va[k] + tb * vb[k]);
+      Xs[lane * G::LX + wv * G::KC + k] = first ? va[k] : rtv<S>(fma(tb, vb[k], va[k]));
   }
   lds_barrier();
 
-  // p of the tile, q2 = sqrt(g) D p from the LDS tile
+  // p of the tile; |q2|^2 of q2 = sqrt(g) D p from the LDS tile (q2 itself
+  // is not stored: phase 2 forms the same values again from p)
   double acc = 0.0;
 #pragma unroll
   for (int u = 0; u < PX; ++u) {
@@ -315,20 +333,15 @@ __device__ __forceinline__ void p1_sep_body(const Job* __restrict__ jobs,
     const int j = jp + jh;
     const bool rt = col0 + j < m - 1;
     const uint32_t cg = (uint32_t)(col0 + jp) * (uint32_t)m + row0;
-    const uint32_t cx = (uint32_t)(col0 + jp) * (uint32_t)(m - 1) + row0;
     const int xo = (i + G::H) * G::LX + (j + G::H);
     const T pc = Xs[xo];
     pb.st(oS.g, cg * ES, pc);
     if (dn) {
-      const double d = ((double)Xs[xo + G::LX] - (double)pc) * (double)wx[u];
-      const T qv = rtv<S>((T)(sg * d));
-      q2.st(oS.x, cx * ES, qv);
+      const T qv = grad_entry<T, S>(sg, pc, Xs[xo + G::LX], wx[u]);
       acc += (double)qv * (double)qv;
     }
     if (rt) {
-      const double d = ((double)Xs[xo + 1] - (double)pc) * (double)wy[u];
-      const T qv = rtv<S>((T)(sg * d));
-      q2.st(oS.g, (nx + cg) * ES, qv);
+      const T qv = grad_entry<T, S>(sg, pc, Xs[xo + 1], wy[u]);
       acc += (double)qv * (double)qv;
     }
   }
@@ -381,7 +394,7 @@ __device__ __forceinline__ void p2_sep_body(const Job* __restrict__ jobs,
   const Vec<T> x(job->v[V_X], n), w(job->v[V_W], 2 * nx);
   const Vec<S> p(job->v[V_PB], n), r1a(job->v[V_R1A], n), r1b(job->v[V_R1B], n),
       q1(job->v[V_Q1], n), s(job->v[V_S], n), r2a(job->v[V_R2A], 2 * nx),
-      r2b(job->v[V_R2B], 2 * nx), q2(job->v[V_Q2], 2 * nx);
+      r2b(job->v[V_R2B], 2 * nx);
 
   // haloed tile of r1 (and q1)
   const bool hrow = lane < G::NR;
@@ -409,7 +422,7 @@ __device__ __forceinline__ void p2_sep_body(const Job* __restrict__ jobs,
   if (hrow) {
 #pragma unroll
     for (int k = 0; k < G::KC; ++k)
-      Xs[lane * G::LX + wv * G::KC + k] = first ? va[k] : rtv<S>(va[k] - ta * vb[k]);
+      Xs[lane * G::LX + wv * G::KC + k] = first ? va[k] : rtv<S>(fma(-ta, vb[k], va[k]));
   }
   lds_barrier();
 
@@ -429,10 +442,12 @@ __device__ __forceinline__ void p2_sep_body(const Job* __restrict__ jobs,
     accr += (double)rv * (double)rv;
   }
   // gradient part, two pixels at a time: the entries qx(i-1,j), qx(i,j),
-  // qy(i,j-1), qy(i,j) of r2 (and q2, w), then x and p for x += alpha p
+  // qy(i,j-1), qy(i,j) of r2 (and w), x, and p at the pixel and its four
+  // neighbours: x += alpha p, and the q2 entries (r2 -= alpha q2) formed
+  // from p as phase 1 formed them
 #pragma unroll
   for (int u0 = 0; u0 < PX; u0 += 2) {
-    T a[2][4], q[2][4], wg[2][4], xv[2], pv[2];
+    T a[2][4], wg[2][4], xv[2], pv[2], pn[2][4];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int jp = 2 * wv + 8 * (u0 + h);
@@ -449,16 +464,19 @@ __device__ __forceinline__ void p2_sep_body(const Job* __restrict__ jobs,
       a[h][3] = rt ? r2a.template ld<T>(oS.g, cy * ES) : T(0);
 #pragma unroll
       for (int d = 0; d < 4; ++d) {
-        q[h][d] = T(0);
+        pn[h][d] = T(0);
         wg[h][d] = T(1);
       }
       if (!first) {
-        q[h][0] = q2.template ld<T>(oS.xu, cu * ES);
-        q[h][1] = q2.template ld<T>(oS.x, cx * ES);
-        q[h][2] = q2.template ld<T>(oS.g, (cy - m) * ES);
-        if (rt) q[h][3] = q2.template ld<T>(oS.g, cy * ES);
+        // p above (grid row 0: own value, not used), left (grid column 0:
+        // the first column of the pair, not used), below, right
+        const bool c0 = col0 + jp == 0;
         xv[h] = x.template ld<T>(oT.g, cg * ET);
         pv[h] = p.template ld<T>(oS.g, cg * ES);
+        pn[h][0] = p.template ld<T>(oS.gu, (cg - xshift) * ES);
+        pn[h][2] = p.template ld<T>(c0 ? oS.r : oS.g, (c0 ? cg : cg - m) * ES);
+        if (dn) pn[h][1] = p.template ld<T>(oS.g + ES, cg * ES);
+        if (rt) pn[h][3] = p.template ld<T>(oS.g, (cg + m) * ES);
       }
       if (irls) {
         wg[h][0] = w.template ld<T>(oT.xu, cu * ET);
@@ -473,9 +491,16 @@ __device__ __forceinline__ void p2_sep_body(const Job* __restrict__ jobs,
       const int gj = col0 + jp + jh;
       const uint32_t cx = (uint32_t)(col0 + jp) * (uint32_t)(m - 1) + row0;
       const uint32_t cg = (uint32_t)(col0 + jp) * (uint32_t)m + row0;
+      T q[4];
+      if (!first) {
+        q[0] = grad_entry<T, S>(sg, pn[h][0], pv[h], wg[h][0]);
+        q[1] = grad_entry<T, S>(sg, pv[h], pn[h][1], wg[h][1]);
+        q[2] = grad_entry<T, S>(sg, pn[h][2], pv[h], wg[h][2]);
+        q[3] = grad_entry<T, S>(sg, pv[h], pn[h][3], wg[h][3]);
+      }
       T rn[4];
 #pragma unroll
-      for (int d = 0; d < 4; ++d) rn[d] = first ? a[h][d] : rtv<S>((T)(a[h][d] - ta * q[h][d]));
+      for (int d = 0; d < 4; ++d) rn[d] = first ? a[h][d] : rtv<S>(fma(-ta, q[d], a[h][d]));
       double lt = 0.0;
       if (up) lt += (double)wg[h][0] * (double)rn[0];
       if (dn) {
@@ -490,7 +515,7 @@ __device__ __forceinline__ void p2_sep_body(const Job* __restrict__ jobs,
         lt -= (double)wg[h][3] * (double)rn[3];
       }
       LTs[i + (jp + jh) * TE] = (T)(sg * lt);
-      if (!first) x.st(oT.g, cg * ET, xv[h] + ta * pv[h]);
+      if (!first) x.st(oT.g, cg * ET, fma(ta, pv[h], xv[h]));
     }
   }
   lds_barrier();  // LT complete (the haloed tile was complete before)
@@ -531,13 +556,21 @@ size_t cgls_sep_lds(int phase, int precision, int rb) {
   return esz * (e + (phase == 2 ? TE * TE : 0));
 }
 
+// Minimum waves per SIMD of the register-bounded (wide) variant: FP32 up to
+// radius bucket 12 in 80 VGPRs (no spills), bucket 16 in 128; FP64 as the
+// generic kernels.
+template <typename T, int RB>
+constexpr int sep_wide_waves() {
+  return sizeof(T) == 4 ? (RB <= 12 ? 6 : 4) : 2;
+}
+
 // Launch over the radius buckets: the register-bounded (wide) variant for
 // launches of more tiles than fit the chip at the unconstrained register use,
 // as for the generic kernels.
 #define DBL_SEP_CASE(KERNEL, T, S, R)                                                     \
   case R:                                                                                 \
     if (wide)                                                                             \
-      hipLaunchKernelGGL((KERNEL<T, S, R, p2_waves<T, R>()>), dim3(la.ntiles),             \
+      hipLaunchKernelGGL((KERNEL<T, S, R, sep_wide_waves<T, R>()>), dim3(la.ntiles),       \
                          dim3(NTHREADS), lds, la.stream, la.jobs, la.tiles);              \
     else                                                                                  \
       hipLaunchKernelGGL((KERNEL<T, S, R, waves_per_simd<T, R>()>), dim3(la.ntiles),       \

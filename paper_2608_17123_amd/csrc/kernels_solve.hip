@@ -149,7 +149,7 @@ __device__ __forceinline__ void cgls_p1_body(const Job* __restrict__ jobs,
           }
           return (T)beta;
         },
-        [&](T a, T b, T c) { return rtv<S>(a + c * b); });
+        [&](T a, T b, T c) { return rtv<S>(fma(c, b, a)); });
   }
   __syncthreads();
   double acc = 0.0;
@@ -250,7 +250,7 @@ __device__ __forceinline__ void cgls_p2_body(const Job* __restrict__ jobs,
           ta = (T)alpha;
           return ta;
         },
-        [&](T a, T b, T c) { return rtv<S>(a - c * b); });
+        [&](T a, T b, T c) { return rtv<S>(fma(-c, b, a)); });
   }
   __syncthreads();
   double accr = 0.0, accs = 0.0;
@@ -300,7 +300,7 @@ __device__ __forceinline__ void cgls_p2_body(const Job* __restrict__ jobs,
           T rn[4];
 #pragma unroll
           for (int d = 0; d < 4; ++d)
-            rn[d] = first ? v[3 * d] : rtv<S>((T)(v[3 * d] - ta * v[3 * d + 1]));
+            rn[d] = first ? v[3 * d] : rtv<S>(fma(-ta, v[3 * d + 1], v[3 * d]));
           double lt = 0.0;
           if (gi >= 1) lt += (double)v[2] * (double)rn[0];
           if (gi < m - 1) {
@@ -315,7 +315,7 @@ __device__ __forceinline__ void cgls_p2_body(const Job* __restrict__ jobs,
             lt -= (double)v[11] * (double)rn[3];
           }
           buf[i + j * TI] = (T)(sg * lt);
-          if (!first) x[g] = v[12] + ta * v[13];
+          if (!first) x[g] = fma(ta, v[13], v[12]);
         });
     __syncthreads();
   };
