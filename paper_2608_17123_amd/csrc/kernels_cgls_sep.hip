@@ -557,11 +557,11 @@ size_t cgls_sep_lds(int phase, int precision, int rb) {
 }
 
 // Minimum waves per SIMD of the register-bounded (wide) variant: FP32 up to
-// radius bucket 12 in 80 VGPRs (no spills), bucket 16 in 128; FP64 as the
-// generic kernels.
+// radius bucket 8 in 64 VGPRs (8 waves: as many as the LDS admits), bucket 12
+// in 80, bucket 16 in 128, all without spills; FP64 as the generic kernels.
 template <typename T, int RB>
 constexpr int sep_wide_waves() {
-  return sizeof(T) == 4 ? (RB <= 12 ? 6 : 4) : 2;
+  return sizeof(T) == 4 ? (RB <= 8 ? 8 : RB <= 12 ? 6 : 4) : 2;
 }
 
 // Launch over the radius buckets: the register-bounded (wide) variant for
