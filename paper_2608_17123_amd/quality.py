@@ -32,8 +32,19 @@ With --sigma the image and noise direction of that workload are blurred
 instead by Gaussian kernels of the given widths (radius ceil(3 sigma), at
 most 16), at the --noise level: Sec. 5 tests sigma = 3.5 and 4.5 at 1% noise.
 
+--paper-setup runs the configuration of the paper's own experiments (Sec. 5:
+64 x 64 images, two grids, Gaussian sigma 3.5 and 4.5, 1% noise, the
+parameter chosen by GCV on every grid, outer iterations stopped by the
+relative change of eq. (stop) at 1e-6 on the coarse grid and 1e-3 on the
+fine one) on the m = 64 stand-in image, with the exact GCV tier (the pencil
+eigendecomposition, which is the GSVD route's function of gamma).  Each grid
+then runs until its tolerance is met (at most --k-out iterations); the
+report gives the fine-level iteration count at which each combination
+stopped, next to the RRE curve, which is what the paper's "a few fine
+iterations against more than ten" finding is about.
+
 Usage: python -m paper_2608_17123_amd.quality [--k-out 10] [--k-in 30]
-       [--sigma 3.5 4.5 --noise 0.01] [--out FILE]
+       [--sigma 3.5 4.5 --noise 0.01] [--paper-setup] [--out FILE]
 """
 import argparse
 import dataclasses
@@ -97,6 +108,20 @@ def sigma_workloads(sigmas, noise):
     return out
 
 
+def paper_workloads(sigmas=(3.5, 4.5), noise=0.01):
+    """Sec. 5's setup on the m = 64 stand-in image (20 shapes): Gaussian
+    blurs sigma 3.5 and 4.5 (radius ceil(3 sigma)), 1% noise, two grids."""
+    import synth
+    base = synth.config1()
+    out = []
+    for s in sigmas:
+        r = min(16, int(math.ceil(3.0 * s)))
+        out.append(dataclasses.replace(base, name=f"paper-sigma{s:g}",
+                                       psf=synth.gaussian_psf(s, r), noise_level=noise,
+                                       levels=2, extra={"sigma": s}))
+    return out
+
+
 def _observed(D, torch, ctx, w):
     """b = A x_true + e on the device in FP64, stored as FP32."""
     op = D.dbl_op_create(ctx, w.psf, w.m, 1, "haar", D.DBL_F64)
@@ -109,9 +134,11 @@ def _observed(D, torch, ctx, w):
     return xt, b.float().contiguous()
 
 
-def run(k_out=10, k_in=30, workloads=None, solvers=SOLVERS, combos=COMBOS, ctx=None):
+def run(k_out=10, k_in=30, workloads=None, solvers=SOLVERS, combos=COMBOS, ctx=None,
+        gcv_mode=None, tol_fine=0.0, tol_coarse=0.0):
     """Solve every (noise level, solver, combination) in one batch; return the
-    RRE after each fine-level outer iteration."""
+    RRE after each fine-level outer iteration (up to the iteration at which a
+    tolerance stopped the fine grid)."""
     import torch
     import paper_2608_17123_amd as D
     import synth
@@ -129,7 +156,9 @@ def run(k_out=10, k_in=30, workloads=None, solvers=SOLVERS, combos=COMBOS, ctx=N
                 levels = w.levels if multi else 1
                 x = torch.zeros_like(b)
                 hist = torch.zeros((k_out, b.numel()), dtype=b.dtype, device=b.device)
-                opts = D.dbl_opts_default(k_out=k_out, k_in=k_in, x_hist=hist)
+                extra = {} if gcv_mode is None else {"gcv_mode": gcv_mode}
+                opts = D.dbl_opts_default(k_out=k_out, k_in=k_in, x_hist=hist,
+                                          tol_fine=tol_fine, tol_coarse=tol_coarse, **extra)
                 reqs.append(D.make_request(b, x, w.psf, w.m, solver, wavelet, levels, transfer,
                                            opts))
                 cases.append((w, solver, label, levels, xt, b, x, hist))
@@ -138,19 +167,22 @@ def run(k_out=10, k_in=30, workloads=None, solvers=SOLVERS, combos=COMBOS, ctx=N
     rows = []
     for (w, solver, label, levels, xt, b, x, hist), rep in zip(cases, reps):
         nt = torch.linalg.norm(xt)
+        kf = rep["iters"][0]  # fine-level outer iterations run (k_out without tolerances)
+        hist = hist[:kf]
         if not torch.equal(hist[-1], x):
             raise RuntimeError("iterate history does not end at the returned solution")
         rre = (torch.linalg.norm(hist.double() - xt[None, :], dim=1) / nt).tolist()
         hh = hist.double().cpu().numpy()
-        ssims = [ssim(w.x_true, hh[k].reshape(w.m, w.m, order="F")) for k in range(k_out)]
+        ssims = [ssim(w.x_true, hh[k].reshape(w.m, w.m, order="F")) for k in range(kf)]
         rows.append({"m": w.m, "noise": w.noise_level, "sigma": w.extra.get("sigma"),
                      "solver": solver, "combo": label,
-                     "levels": levels, "rre": rre, "ssim": ssims,
+                     "levels": levels, "rre": rre, "ssim": ssims, "iters": rep["iters"][:levels],
                      "rre_data": float(torch.linalg.norm(b.double() - xt) / nt),
                      "gamma_fine": rep["gamma"][0]})
     if own:
         ctx.close()
-    return {"k_out": k_out, "k_in": k_in, "rows": rows, "findings": findings(rows)}
+    return {"k_out": k_out, "k_in": k_in, "tol_fine": tol_fine, "tol_coarse": tol_coarse,
+            "gcv_mode": gcv_mode, "rows": rows, "findings": findings(rows)}
 
 
 def _iters_to(curve, target):
@@ -175,8 +207,13 @@ def findings(rows):
             target = c["I"][-1]
             reach = {k: _iters_to(v, target) for k, v in c.items() if k != "I"}
             best = min((v for v in reach.values() if v is not None), default=None)
+            its = {r["combo"]: r["iters"][0] for r in rows
+                   if (r.get("sigma") or 0.0, r["noise"]) == (sigma, noise)
+                   and r["solver"] == solver}
             out.append({
                 "sigma": sigma or None, "noise": noise, "solver": solver,
+                "fine_iterations": its,
+                "final_rre": {k: v[-1] for k, v in c.items()},
                 "one_level_final_rre": target,
                 "multilevel_iters_to_match": reach,
                 "multilevel_faster": best is not None and best < len(c["I"]),
@@ -187,29 +224,36 @@ def findings(rows):
 
 
 def markdown(res):
-    ks = [k for k in (1, 2, 3, 5, res["k_out"]) if k <= res["k_out"]]
+    ks = [k for k in (1, 2, 3, 5, 10, res["k_out"]) if k <= res["k_out"]]
     ks = sorted(set(ks))
+    at = lambda r, k: f"{r['rre'][k - 1]:.4f}" if k <= len(r["rre"]) else "-"
+    stop = (f", stopped by eq. (stop) at {res['tol_fine']:g} (fine) / {res['tol_coarse']:g} "
+            f"(coarse)" if res.get("tol_fine") else "")
     out = [f"RRE = ||x - x_true|| / ||x_true|| after fine-level outer iteration k "
-           f"(K_out = {res['k_out']} per level, K_in = {res['k_in']}).", "",
-           "| blur | noise | solver | combination | grids | RRE(b) | " +
-           " | ".join(f"k={k}" for k in ks) + f" | SSIM at k={res['k_out']} |",
-           "|---|---|---|---|---|---|" + "---|" * len(ks) + "---|"]
+           f"(K_out = {res['k_out']} per level{stop}, K_in = {res['k_in']}; GCV "
+           f"{res.get('gcv_mode') or 'auto'}).", "",
+           "| blur | noise | solver | combination | grids | fine its | RRE(b) | " +
+           " | ".join(f"k={k}" for k in ks) + " | final RRE | final SSIM |",
+           "|---|---|---|---|---|---|---|" + "---|" * len(ks) + "---|---|"]
     for r in res["rows"]:
         blur = f"sigma {r['sigma']:g}" if r.get("sigma") else "c2"
         out.append(f"| {blur} | {r['noise']:.0%} | {r['solver']} | {r['combo']} | {r['levels']} | "
-                   f"{r['rre_data']:.4f} | " +
-                   " | ".join(f"{r['rre'][k - 1]:.4f}" for k in ks) +
-                   f" | {r['ssim'][-1]:.4f} |")
-    out += ["", "| blur | noise | solver | I final RRE | fine iterations to match it "
-            "(HWT-X, HWT-D, DWT-X, DWT-D) | multilevel faster | Haar better under D | "
-            "Db4 better under X |", "|---|---|---|---|---|---|---|---|"]
+                   f"{len(r['rre'])} | {r['rre_data']:.4f} | " +
+                   " | ".join(at(r, k) for k in ks) +
+                   f" | {r['rre'][-1]:.4f} | {r['ssim'][-1]:.4f} |")
+    out += ["", "| blur | noise | solver | fine iterations run (I, HWT-X, HWT-D, DWT-X, "
+            "DWT-D) | I final RRE | fine iterations to match it (HWT-X, HWT-D, DWT-X, DWT-D) | "
+            "multilevel faster | Haar better under D | Db4 better under X |",
+            "|---|---|---|---|---|---|---|---|---|"]
     for f in res["findings"]:
         it = ", ".join(str(f["multilevel_iters_to_match"].get(c) or "-")
                        for c in ("HWT-X", "HWT-D", "DWT-X", "DWT-D"))
+        run = ", ".join(str(f["fine_iterations"].get(c, "-"))
+                        for c in ("I", "HWT-X", "HWT-D", "DWT-X", "DWT-D"))
         blur = f"sigma {f['sigma']:g}" if f.get("sigma") else "c2"
-        out.append(f"| {blur} | {f['noise']:.0%} | {f['solver']} | {f['one_level_final_rre']:.4f} | "
-                   f"{it} | {f['multilevel_faster']} | {f['haar_better_under_D']} | "
-                   f"{f['db4_better_under_X']} |")
+        out.append(f"| {blur} | {f['noise']:.0%} | {f['solver']} | {run} | "
+                   f"{f['one_level_final_rre']:.4f} | {it} | {f['multilevel_faster']} | "
+                   f"{f['haar_better_under_D']} | {f['db4_better_under_X']} |")
     return "\n".join(out) + "\n"
 
 
@@ -220,10 +264,17 @@ def main(argv=None):
     p.add_argument("--sigma", type=float, nargs="*", default=None,
                    help="Gaussian blur widths to run instead of the m = 256 workload's")
     p.add_argument("--noise", type=float, default=0.01, help="noise level with --sigma")
+    p.add_argument("--paper-setup", action="store_true",
+                   help="Sec. 5's setup: m = 64, two grids, sigma 3.5 / 4.5, 1%% noise, exact "
+                        "GCV, eq. (stop) at 1e-3 / 1e-6")
     p.add_argument("--out", default=None, help="also write the markdown tables here")
     a = p.parse_args(argv)
-    wl = sigma_workloads(a.sigma, a.noise) if a.sigma else None
-    res = run(a.k_out, a.k_in, workloads=wl)
+    if a.paper_setup:
+        res = run(a.k_out, a.k_in, workloads=paper_workloads(a.sigma or (3.5, 4.5), a.noise),
+                  gcv_mode="exact", tol_fine=1e-3, tol_coarse=1e-6)
+    else:
+        wl = sigma_workloads(a.sigma, a.noise) if a.sigma else None
+        res = run(a.k_out, a.k_in, workloads=wl)
     md = markdown(res)
     sys.stdout.write(md)
     print(json.dumps(res))
