@@ -78,6 +78,10 @@ def parse():
                    help="vector storage: FP32, BF16 CGLS state with FP32 arithmetic, or FP64")
     p.add_argument("--inner", default="cgls", choices=["cgls", "lsqr"],
                    help="inner Krylov solver of every subproblem")
+    p.add_argument("--no-tune", action="store_true",
+                   help="skip the autotuner (built-in CGLS variant rule)")
+    p.add_argument("--tune-cache", default=None,
+                   help="autotuner JSON cache: loaded when present, else written")
     return p.parse_args()
 
 
@@ -354,6 +358,14 @@ def main():
     D.lib()  # fail loudly when the library is missing
     ctx = D.dbl_create(0)
     prec = {"f32": D.DBL_F32, "bf16": D.DBL_BF16, "f64": D.DBL_F64}[args.precision]
+    tune = None
+    if not args.no_tune:
+        # untimed set-up: the fastest of the bit-identical CGLS phase variants
+        # per (phase, radius bucket, grid size, launch size)
+        t0 = time.perf_counter()
+        n_tune = D.dbl_autotune(ctx, prec, args.tune_cache)
+        tune = {"entries": n_tune, "seconds": round(time.perf_counter() - t0, 2),
+                "cache": args.tune_cache}
     if args.workload == "c2":
         workloads = synth.config2()
         wdesc = ("m=256 single image, 60 shapes, Gaussian sigma 2.5 on 15x15, noise 1%/5%, "
@@ -468,6 +480,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": wdesc, "solves_per_step": nsolve, "path": "batched",
                    "inner_solver": args.inner},
+        "autotune": tune,
         "plain_solves_per_s": None if plain is None else round(plain, 2),
         "batched_over_plain": None if plain is None else round(value / plain, 2),
         "rel_err_vs_oracle": err,

@@ -175,6 +175,36 @@ typedef struct dbl_sub {
  * validates its arguments as usual and then returns DBL_EDEVICE. */
 int dbl_create(dbl_ctx** out, int device, void* hip_stream, size_t hbm_budget_bytes);
 int dbl_destroy(dbl_ctx* ctx);
+/* Autotuner (for callers that want the fastest kernel variant per workload;
+ * no paper passage: it never changes a result).  The CGLS phase launches of
+ * separable operators have four compiled variants that form every sum in the
+ * same order: the generic tile kernels and the 32 x 32 tile kernels, each
+ * with and without a register bound.  dbl_autotune times all four on
+ * synthetic jobs (zero data, on the context's stream) for every
+ * (phase, radius bucket, grid size, launch size) of a sweep -- radius
+ * buckets 2..16, grids 32..1024, 1 to 64 jobs per launch, at most 2^22
+ * pixels per launch -- in `precision`, and keeps the fastest per key; every
+ * later phase launch of that precision on `ctx` takes the entry nearest its
+ * own key (same phase and bucket; grid size first, then tile count).
+ * cache_path (optional): a JSON file of the results; when it exists, was
+ * written on the same device kind for the same precision and flags lacks
+ * DBL_TUNE_REMEASURE, it is loaded instead of measuring; otherwise the
+ * measurement is written there.  DBL_TUNE_QUICK measures a reduced sweep
+ * (buckets 4 and 8, grids 64 and 256, 1 and 16 jobs).  *n_entries
+ * (optional) receives the number of entries installed.  DBL_EINVAL for an
+ * unknown precision or flag, or an unwritable cache path; DBL_ENOMEM when
+ * the synthetic jobs do not fit the context's budget.  Synchronises the
+ * context's stream. */
+#define DBL_TUNE_REMEASURE 1
+#define DBL_TUNE_QUICK 2
+int dbl_autotune(dbl_ctx* ctx, int precision, const char* cache_path, int flags,
+                 int* n_entries);
+/* The variant (0 generic, 1 generic register-bounded, 2 32 x 32 tile, 3 tile
+ * register-bounded) a CGLS phase launch (phase 1 or 2) of `precision` with
+ * radius bucket rb, largest grid m and ntiles tiles would take on ctx now.
+ * DBL_EINVAL for a bad phase, size or null pointer. */
+int dbl_tune_choice(const dbl_ctx* ctx, int phase, int precision, int rb, int m, int ntiles,
+                    int* variant);
 /* Context options (dbl_set_option). */
 typedef enum dbl_option {
   /* 1 (default): a level with m <= 64 whose CGLS state fits in one block's

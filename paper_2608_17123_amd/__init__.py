@@ -43,7 +43,7 @@ EXPORTS = [
     "dbl_opts_default", "dbl_profile", "dbl_profile_read", "dbl_op_create", "dbl_op_destroy", "dbl_apply_A", "dbl_apply_L",
     "dbl_dwt", "dbl_apply_A_batch", "dbl_apply_L_batch", "dbl_dwt_batch", "dbl_dtransfer", "dbl_cgls", "dbl_cgls_noalloc", "dbl_lsqr", "dbl_gcv", "dbl_deblur", "dbl_deblur_batch",
     "dbl_request_bytes", "dbl_server_create", "dbl_server_destroy", "dbl_server_submit",
-    "dbl_server_step", "dbl_server_poll",
+    "dbl_server_step", "dbl_server_poll", "dbl_autotune", "dbl_tune_choice",
 ]
 
 
@@ -143,6 +143,8 @@ def lib():
         "dbl_server_submit": (i, [vp, ctypes.POINTER(dbl_request), ctypes.POINTER(ctypes.c_int64)]),
         "dbl_server_step": (i, [vp, ctypes.POINTER(i)]),
         "dbl_server_poll": (i, [vp, ctypes.c_int64, ctypes.POINTER(i), ctypes.POINTER(dbl_report)]),
+        "dbl_autotune": (i, [vp, i, ctypes.c_char_p, i, ctypes.POINTER(i)]),
+        "dbl_tune_choice": (i, [vp, i, i, i, i, i, ctypes.POINTER(i)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -255,6 +257,28 @@ def dbl_destroy(ctx):
 
 def dbl_set_option(ctx, option, value):
     _check(ctx, lib().dbl_set_option(ctx.handle, int(option), int(value)))
+
+
+DBL_TUNE_REMEASURE, DBL_TUNE_QUICK = 1, 2
+TUNE_VARIANTS = ("generic", "generic wide", "tile32", "tile32 wide")
+
+
+def dbl_autotune(ctx, precision=DBL_F32, cache_path=None, quick=False, remeasure=False):
+    """Measure (or load from cache_path) the fastest CGLS phase variants for
+    `precision`; returns the number of table entries installed on ctx."""
+    n = ctypes.c_int(0)
+    flags = (DBL_TUNE_QUICK if quick else 0) | (DBL_TUNE_REMEASURE if remeasure else 0)
+    path = None if cache_path is None else os.fsencode(cache_path)
+    _check(ctx, lib().dbl_autotune(ctx.handle, int(precision), path, flags, ctypes.byref(n)))
+    return n.value
+
+
+def dbl_tune_choice(ctx, phase, precision, rb, m, ntiles):
+    """Variant index a CGLS phase launch with these keys takes on ctx."""
+    v = ctypes.c_int(-1)
+    _check(ctx, lib().dbl_tune_choice(ctx.handle, int(phase), int(precision), int(rb), int(m),
+                                      int(ntiles), ctypes.byref(v)))
+    return v.value
 
 
 def dbl_sync(ctx):

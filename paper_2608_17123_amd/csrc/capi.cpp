@@ -602,6 +602,7 @@ int krylov_entry(dbl_ctx* ctx, const dbl_op* op, int level, const dbl_sub* sub, 
   Launch Lf;
   Lf.add(jf, m, (int)esz);
   if ((rc = Lf.upload(ctx, la))) return rc;
+  tune_cgls_launch(ctx, 2, prec, sep, rb, la);
   if ((rc = hip_check(ctx, launch_cgls_p2(la, prec, sep, rb, H), "cgls p2"))) return rc;
   LaunchArgs a2[2];
   for (int par = 0; par < 2; ++par) {
@@ -617,6 +618,7 @@ int krylov_entry(dbl_ctx* ctx, const dbl_op* op, int level, const dbl_sub* sub, 
     Launch L2;
     L2.add(bb, m, (int)esz);
     if ((rc = L2.upload(ctx, a2[par]))) return rc;
+    tune_cgls_launch(ctx, 2, prec, sep, rb, a2[par]);
   }
   for (int it = 0; it < iters; ++it) {
     const int par = it & 1;
@@ -632,6 +634,7 @@ int krylov_entry(dbl_ctx* ctx, const dbl_op* op, int level, const dbl_sub* sub, 
     L1.add(a, m, (int)esz);
     LaunchArgs a1;
     if ((rc = L1.upload(ctx, a1))) return rc;
+    tune_cgls_launch(ctx, 1, prec, sep, rb, a1);
     if ((rc = hip_check(ctx, launch_cgls_p1(a1, prec, sep, rb, H), "cgls p1"))) return rc;
     if ((rc = hip_check(ctx, launch_cgls_p2(a2[par], prec, sep, rb, H), "cgls p2"))) return rc;
   }

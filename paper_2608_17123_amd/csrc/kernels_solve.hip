@@ -561,25 +561,29 @@ struct Dummy {};
     }                                                                                  \
   } while (0)
 
+int cgls_wide_tiles() { return P2_WIDE_TILES; }
+
 hipError_t launch_cgls_p1(const LaunchArgs& la, int precision, int sep, int rb, int H) {
-  if (sep && la.tile32) return launch_cgls_p1_sep(la, precision, rb, la.ntiles > P2_WIDE_TILES);
+  const bool wide = la.wide >= 0 ? la.wide != 0 : la.ntiles > P2_WIDE_TILES;
+  if (sep && la.tile32) return launch_cgls_p1_sep(la, precision, rb, wide);
   if (precision == 1) DISPATCH_STENCIL_S(k_cgls_p1, double, double, la, sep, rb, H);
-  else if (la.ntiles > P2_WIDE_TILES && precision == 2)
+  else if (wide && precision == 2)
     DISPATCH_STENCIL_S(k_cgls_p1_wide, float, bf16s, la, sep, rb, H);
   else if (precision == 2) DISPATCH_STENCIL_S(k_cgls_p1, float, bf16s, la, sep, rb, H);
-  else if (la.ntiles > P2_WIDE_TILES)
+  else if (wide)
     DISPATCH_STENCIL_S(k_cgls_p1_wide, float, float, la, sep, rb, H);
   else DISPATCH_STENCIL_S(k_cgls_p1, float, float, la, sep, rb, H);
   return hipGetLastError();
 }
 
 hipError_t launch_cgls_p2(const LaunchArgs& la, int precision, int sep, int rb, int H) {
-  if (sep && la.tile32) return launch_cgls_p2_sep(la, precision, rb, la.ntiles > P2_WIDE_TILES);
+  const bool wide = la.wide >= 0 ? la.wide != 0 : la.ntiles > P2_WIDE_TILES;
+  if (sep && la.tile32) return launch_cgls_p2_sep(la, precision, rb, wide);
   if (precision == 1) DISPATCH_STENCIL_S(k_cgls_p2, double, double, la, sep, rb, H);
-  else if (la.ntiles > P2_WIDE_TILES && precision == 2)
+  else if (wide && precision == 2)
     DISPATCH_STENCIL_S(k_cgls_p2_wide, float, bf16s, la, sep, rb, H);
   else if (precision == 2) DISPATCH_STENCIL_S(k_cgls_p2, float, bf16s, la, sep, rb, H);
-  else if (la.ntiles > P2_WIDE_TILES)
+  else if (wide)
     DISPATCH_STENCIL_S(k_cgls_p2_wide, float, float, la, sep, rb, H);
   else DISPATCH_STENCIL_S(k_cgls_p2, float, float, la, sep, rb, H);
   return hipGetLastError();

@@ -14,7 +14,11 @@ struct LaunchArgs {
   // every job has m >= 32 and the 32 x 32 tile kernels are enabled: the CGLS
   // phases of separable operators take k_cgls_p1_sep / k_cgls_p2_sep
   bool tile32 = false;
+  // CGLS phases: 1 / 0 forces the register-bounded / unbounded variant; -1
+  // takes the bounded one for launches of more than cgls_wide_tiles() tiles
+  int wide = -1;
 };
+int cgls_wide_tiles();
 
 // Vector slots of CGLS / solver jobs (Job::v indices).
 enum VSlot : int {

@@ -235,6 +235,12 @@ extern "C" int dbl_cgls_noalloc(dbl_ctx* ctx, const dbl_op* op, int level, const
     la.tile32 = ctx->tile32 && m >= 32;
     return la;
   };
+  // a CGLS phase launch with the autotuner's variant (host table lookup only)
+  auto la_phase = [&](int phase, int k) {
+    LaunchArgs la = la_for(k, ntiles, d_tiles);
+    tune_cgls_launch(ctx, phase, prec, sep, rb, la);
+    return la;
+  };
   if ((rc = hip_check(ctx, launch_set_gamma(la_for(k_gamma, 1, d_one)), "set gamma"))) return rc;
   if (k_small >= 0) {
     if ((rc = hip_check(ctx, launch_cgls_small(la_for(k_small, 1, d_one), prec, rb, m, small),
@@ -248,15 +254,15 @@ extern "C" int dbl_cgls_noalloc(dbl_ctx* ctx, const dbl_op* op, int level, const
     if ((rc = hip_check(ctx, launch_cgls_init(la_for(k_init, ntiles, d_tiles), prec),
                         "cgls init")))
       return rc;
-    if ((rc = hip_check(ctx, launch_cgls_p2(la_for(k_first, ntiles, d_tiles), prec, sep, rb, H),
+    if ((rc = hip_check(ctx, launch_cgls_p2(la_phase(2, k_first), prec, sep, rb, H),
                         "cgls p2")))
       return rc;
     for (int it = 0; it < iters; ++it) {
-      if ((rc = hip_check(ctx, launch_cgls_p1(la_for(k_p1[it], ntiles, d_tiles), prec, sep, rb,
-                                              H), "cgls p1")))
+      if ((rc = hip_check(ctx, launch_cgls_p1(la_phase(1, k_p1[it]), prec, sep, rb, H),
+                          "cgls p1")))
         return rc;
-      if ((rc = hip_check(ctx, launch_cgls_p2(la_for(k_p2[it & 1], ntiles, d_tiles), prec, sep,
-                                              rb, H), "cgls p2")))
+      if ((rc = hip_check(ctx, launch_cgls_p2(la_phase(2, k_p2[it & 1]), prec, sep, rb, H),
+                          "cgls p2")))
         return rc;
     }
     if (k_hist >= 0 &&

@@ -1245,8 +1245,10 @@ int engine_step(dbl_ctx* ctx, std::vector<Slot*>& slots) {
       const GroupKey& g = kv.first;
       double b = 0.0;
       for (const Job& jj : first[g].jobs) b += job_bytes("cgls_p2", jj, g.prec);
+      LaunchArgs la = kv.second;
+      tune_cgls_launch(ctx, 2, g.prec, g.sep, g.rb, la);
       if ((rc = hip_check(ctx, timed(ctx, "cgls_p2", b, [&] {
-                            return launch_cgls_p2(kv.second, g.prec, g.sep, g.rb, g.H);
+                            return launch_cgls_p2(la, g.prec, g.sep, g.rb, g.H);
                           }),
                           "cgls p2")))
         return rc;
@@ -1264,6 +1266,7 @@ int engine_step(dbl_ctx* ctx, std::vector<Slot*>& slots) {
         if (!q) continue;
         LaunchArgs la = it == 0 ? a1f[g] : a1[par][g];
         la.ntiles = p1[par][g].tiles_upto[q - 1];
+        tune_cgls_launch(ctx, 1, g.prec, g.sep, g.rb, la);
         double b = 0.0;
         for (int jq = 0; jq < q; ++jq)
           b += job_bytes("cgls_p1", p1[par][g].jobs[jq], g.prec);
@@ -1281,6 +1284,7 @@ int engine_step(dbl_ctx* ctx, std::vector<Slot*>& slots) {
         if (!q) continue;
         LaunchArgs la = a2[par][g];
         la.ntiles = p2[par][g].tiles_upto[q - 1];
+        tune_cgls_launch(ctx, 2, g.prec, g.sep, g.rb, la);
         double b = 0.0;
         for (int jq = 0; jq < q; ++jq)
           b += job_bytes("cgls_p2", p2[par][g].jobs[jq], g.prec);

@@ -11,6 +11,15 @@
 
 #include "host.h"
 
+// One autotuner choice: the fastest CGLS phase variant (0 generic, 1 generic
+// register-bounded, 2 32 x 32 tile, 3 tile register-bounded) measured for a
+// phase (1 or 2), precision, radius bucket, grid size 2^mlog and launch of
+// 2^tlog tiles, with the four timings (microseconds per launch).
+struct TuneEntry {
+  int phase, prec, rb, mlog, tlog, variant;
+  double us[4];
+};
+
 struct dbl_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -52,6 +61,8 @@ struct dbl_ctx {
   // streaming separable blur for large FP32 grids in the operator entry points
   int stream_a = 1;
   int tile32 = 1;  // 32 x 32 tile CGLS kernels for separable operators (DBL_OPT_TILE32)
+  // autotuned CGLS phase variants (dbl_autotune); empty: the built-in rule
+  std::vector<TuneEntry> tune;
   size_t lds_limit = 65536;
   // EXACT-tier GCV: rocBLAS handle (rocblas_handle) and dense FP64 workspace
   void* blas = nullptr;
@@ -129,6 +140,11 @@ hipError_t timed(dbl_ctx* ctx, const char* name, double bytes, F&& launch) {
   ctx->prof_pending.push_back(p);
   return e;
 }
+
+// Variant of a CGLS phase launch (phase 1 or 2) from the autotuner's table:
+// sets la.tile32 (kept off where the launch cannot take the tile kernels) and
+// la.wide.  No table, or a non-separable operator: la is left as it is.
+void tune_cgls_launch(const dbl_ctx* ctx, int phase, int prec, int sep, int rb, LaunchArgs& la);
 
 // Device operator of `level` with tables padded to radius bucket rb (the
 // level's own bucket, or a larger one for a separable level).

@@ -49,6 +49,14 @@ int main(int argc, char** argv) {
   int rc = dbl_create(&ctx, 0, nullptr, 0);
   if (rc) return 3;
   dbl_set_option(ctx, DBL_OPT_SMALL_CGLS, small);
+  if (std::getenv("DRYRUN_AUTOTUNE")) {
+    // the tuner's synthetic launches are audited like the solve's; the
+    // stand-in's events read 0 ms, so every key keeps variant 0
+    int n = 0;
+    rc = dbl_autotune(ctx, prec, nullptr, DBL_TUNE_QUICK, &n);
+    std::printf("autotune status %d entries %d\n", rc, n);
+    if (rc) return 1;
+  }
   const size_t esz = prec == DBL_F64 ? 8 : 4;
   std::vector<double> mu((size_t)levels * k_out);
   for (int i = 0; i < levels; ++i)

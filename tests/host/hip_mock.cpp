@@ -492,6 +492,13 @@ hipError_t hipEventElapsedTime(float* ms, hipEvent_t, hipEvent_t) {
   return hipSuccess;
 }
 hipError_t hipFuncSetAttribute(const void*, hipFuncAttribute, int) { return hipSuccess; }
+hipError_t hipEventSynchronize(hipEvent_t) { return hipSuccess; }
+hipError_t hipGetDevicePropertiesR0600(hipDeviceProp_tR0600* p, int) {
+  std::memset(p, 0, sizeof(*p));
+  std::strcpy(p->gcnArchName, "host-mock");
+  p->multiProcessorCount = 256;
+  return hipSuccess;
+}
 
 // the EXACT GCV tier's library calls are not part of a dry run
 rocblas_status rocblas_create_handle(rocblas_handle*) { return rocblas_status_not_implemented; }

@@ -127,3 +127,21 @@ def test_spectral_gcv_plan_tables_are_sound(dryrun, solver, prec):
     r = run(dryrun, psf, 256, 3, solver, "db4", "X", prec, k_out=3, k_in=5, copies=2, gcv=2)
     assert r.returncode == 0, r.stdout[-2000:]
     assert "violations 0" in r.stdout and "launches k_gcv_symbol" in r.stdout
+
+
+def test_autotune_launches_are_sound(dryrun):
+    """The autotuner's synthetic CGLS jobs (every variant of both phases, the
+    quick sweep) pass the same audit, before a small solve."""
+    exe, out = dryrun
+    psf = psf_file(out, "g4", synth.gaussian_psf(1.5, 4))
+    for prec in ("0", "1", "2"):
+        env = dict(os.environ, DRYRUN_AUTOTUNE="1")
+        r = subprocess.run([exe, psf, "64", "2", "0", "0", "0", prec, "2", "3", "1", "1", "0"],
+                           capture_output=True, text=True, timeout=300, env=env)
+        print(r.stdout[-2000:])
+        assert r.returncode == 0, r.stdout[-2000:]
+        assert "autotune status 0 entries 16" in r.stdout  # 2 buckets x 2 grids x 2 sizes x 2 phases
+        assert "violations 0" in r.stdout
+        assert "launches k_cgls_p2_sep" in r.stdout
+        if prec != "1":  # FP64 has one generic phase kernel (no register-bounded twin)
+            assert "launches k_cgls_p2_wide" in r.stdout
