@@ -73,6 +73,8 @@ def parse():
                    help="Poisson arrival rates (requests per second), comma separated")
     p.add_argument("--serve-requests", type=int, default=48, help="requests per rate")
     p.add_argument("--calib-copy", action="store_true")
+    p.add_argument("--operators-only", action="store_true",
+                   help="run only the standalone operator leg (for rocprofv3)")
     p.add_argument("--profile-run", action="store_true")
     p.add_argument("--precision", default="f32", choices=["f32", "bf16", "f64"],
                    help="vector storage: FP32, BF16 CGLS state with FP32 arithmetic, or FP64")
@@ -357,6 +359,9 @@ def main():
 
     D.lib()  # fail loudly when the library is missing
     ctx = D.dbl_create(0)
+    if args.operators_only:
+        print(json.dumps({"operators": operator_leg(D, torch, ctx)}))
+        return
     prec = {"f32": D.DBL_F32, "bf16": D.DBL_BF16, "f64": D.DBL_F64}[args.precision]
     tune = None
     if not args.no_tune:
