@@ -306,22 +306,45 @@ __device__ __forceinline__ void gen_tile(const T* __restrict__ Xs, int H, const 
   const bool inter = (i0 >= tb.St0) && (i0 + TI - 1 < m - tb.Sb0) && (j0 >= tb.St1) &&
                      (j0 + TJ - 1 < m - tb.Sb1);
   if (inter) {
+    // Interior tile: one tap list for every pixel.  Each tap is staged as its
+    // tile offset e1 LXC + e0 and value, and one pass over the taps updates
+    // all of the thread's pixels (each pixel's sum keeps the tap order): per
+    // tap and pixel, one LDS read of the tile and one fma.
     const int cls = tb.St0 + tb.St1 * tb.rows0;
     const int b = tb.off[cls], n = tb.off[cls + 1] - b;
+    int* s_off = reinterpret_cast<int*>(s_e);
     for (int k = threadIdx.x; k < n; k += NT) {
-      s_e[k] = tb.e[b + k];
+      const short2 e = tb.e[b + k];
+      s_off[k] = e.y * LXC + e.x;
       s_v[k] = vals[b + k];
     }
     __syncthreads();
-    for (int o = threadIdx.x; o < TI * TJ; o += NT) {
+    constexpr int UMAX = (32 * 32 + NT - 1) / NT;  // pixels per thread (tiles <= 32 x 32)
+    const int np = TI * TJ;
+    int base[UMAX];
+    T acc[UMAX];
+#pragma unroll
+    for (int u = 0; u < UMAX; ++u) {
+      const int o = threadIdx.x + u * NT;
       int i, j;
       tile_ij(o, TI, i, j);
-      T a = T(0);
-      for (int k = 0; k < n; ++k) {
-        const short2 e = s_e[k];
-        a = fma(s_v[k], Xs[(j + H + e.y) * LXC + (i + H + e.x)], a);
+      base[u] = o < np ? (j + H) * LXC + (i + H) : 0;  // a pixel past the tile reads (H, H)
+      acc[u] = T(0);
+    }
+    for (int k = 0; k < n; ++k) {
+      const int off = s_off[k];
+      const T v = s_v[k];
+#pragma unroll
+      for (int u = 0; u < UMAX; ++u) acc[u] = fma(v, Xs[base[u] + off], acc[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < UMAX; ++u) {
+      const int o = threadIdx.x + u * NT;
+      if (o < np) {
+        int i, j;
+        tile_ij(o, TI, i, j);
+        epi(i, j, acc[u]);
       }
-      epi(i, j, a);
     }
   } else {
     for (int o = threadIdx.x; o < TI * TJ; o += NT) {
