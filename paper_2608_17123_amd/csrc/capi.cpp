@@ -369,7 +369,10 @@ int dbl_dwt_batch(dbl_ctx* ctx, int wavelet, int m, int precision, int inverse,
     j.p0 = lowpass_only ? 0.0 : 1.0;
     j.v[0] = const_cast<void*>(in[q]);
     j.v[1] = out[q];
-    Lc.add(j, inverse ? m : m / 2, precision == DBL_F64 ? 8 : 4);
+    if (inverse && lowpass_only)
+      add_prolong(Lc, j, precision == DBL_F64 ? 8 : 4);
+    else
+      Lc.add(j, inverse ? m : m / 2, precision == DBL_F64 ? 8 : 4);
     bytes += job_bytes(name, j, precision);
   }
   LaunchArgs la;

@@ -422,58 +422,77 @@ __global__ void __launch_bounds__(NTHREADS) k_dwt_inv(const Job* __restrict__ jo
   const int m = job->m, mc = m >> 1, cm = mc - 1;
   int i0, j0, TI, TJ;
   tile_geom<T>(m, ti, tj, i0, j0, TI, TJ);
+  // low-pass prolongation onto grids of 64 and more runs on 32 x 64 fine
+  // tiles (add_prolong; four 32-column parts per block measured slower than
+  // two): the tile width is the job's
+  TJ = m / job->ntj;
+  j0 = tj * TJ;
   const int wav = job->flags, K2 = wl_len(wav) / 2;
   const bool four = job->p0 != 0.0;
   const T* __restrict__ c = static_cast<const T*>(job->v[0]);
   T* __restrict__ x = static_cast<T*>(job->v[1]);
   const size_t nc = (size_t)mc * mc;
-  if (!four && TI == 32 && aligned16(x) && aligned16(c)) {
+  constexpr int PQ = 2;  // 32-column parts of the widest tile
+  if (!four && TI == 32 && TJ % 32 == 0 && TJ <= 32 * PQ && aligned16(x) && aligned16(c)) {
     // low-pass prolongation: 4 fine rows f0 .. f0 + 3 of one fine column per
-    // thread; they need coarse rows f0/2 - K2 + 1 .. f0/2 + 1 (wrapped) of K2
-    // coarse columns, loaded before any arithmetic; the sums are those of the
+    // thread in each 32-column part of the tile; they need coarse rows
+    // f0/2 - K2 + 1 .. f0/2 + 1 (wrapped) of K2 coarse columns.  The loads of
+    // all parts are issued before any arithmetic; the sums are those of the
     // element-wise path in the same order
     int r4, jl;
     quad_of(TI, r4, jl);
-    const int f0 = i0 + r4, f1 = j0 + jl, h0 = f0 >> 1;
+    const int f0 = i0 + r4, h0 = f0 >> 1, nh = TJ / 32;
     // coarse rows h0, h0 + 1 (h0 even: one aligned pair) of each coarse
     // column; row h0 - 1 (Db4) is the pair of the thread above, or a load
     // (wrapped) for the first thread of a column
-    T cv[2][3] = {{T(0), T(0), T(0)}, {T(0), T(0), T(0)}};
+    T cv[PQ][2][3];
 #pragma unroll
-    for (int t1 = 0; t1 < 2; ++t1) {
-      if (t1 >= K2) break;
-      const T* __restrict__ col = c + (size_t)(((f1 >> 1) - t1) & cm) * mc;
-      cv[t1][1] = col[h0];
-      cv[t1][2] = col[h0 + 1];
-      if (K2 > 1 && (threadIdx.x & 7) == 0) cv[t1][0] = col[(h0 - 1) & cm];
-    }
-    if (K2 > 1) {
+    for (int hh = 0; hh < PQ; ++hh) {
 #pragma unroll
-      for (int t1 = 0; t1 < 2; ++t1) {
-        const T a = __shfl_up(cv[t1][2], 1, 8);
-        if ((threadIdx.x & 7) != 0) cv[t1][0] = a;
-      }
-    }
-    T out[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int ff0 = f0 + u;
-      double acc = 0;
+      for (int t1 = 0; t1 < 2; ++t1) cv[hh][t1][0] = cv[hh][t1][1] = cv[hh][t1][2] = T(0);
+      if (hh >= nh) break;
+      const int f1 = j0 + 32 * hh + jl;
 #pragma unroll
       for (int t1 = 0; t1 < 2; ++t1) {
         if (t1 >= K2) break;
-        const int k1 = (f1 & 1) + 2 * t1;
+        const T* __restrict__ col = c + (size_t)(((f1 >> 1) - t1) & cm) * mc;
+        cv[hh][t1][1] = col[h0];
+        cv[hh][t1][2] = col[h0 + 1];
+        if (K2 > 1 && (threadIdx.x & 7) == 0) cv[hh][t1][0] = col[(h0 - 1) & cm];
+      }
+    }
 #pragma unroll
-        for (int t0 = 0; t0 < 2; ++t0) {
-          if (t0 >= K2) break;
-          const int k0 = (ff0 & 1) + 2 * t0;
-          // coarse row (ff0 >> 1) - t0 = h0 + (u >> 1) - t0 sits at d = 1 + (u >> 1) - t0
-          acc = fma(wl_h(wav, k0) * wl_h(wav, k1), (double)cv[t1][1 + (u >> 1) - t0], acc);
+    for (int hh = 0; hh < PQ; ++hh) {
+      if (hh >= nh) break;
+      const int f1 = j0 + 32 * hh + jl;
+      if (K2 > 1) {
+#pragma unroll
+        for (int t1 = 0; t1 < 2; ++t1) {
+          const T a = __shfl_up(cv[hh][t1][2], 1, 8);
+          if ((threadIdx.x & 7) != 0) cv[hh][t1][0] = a;
         }
       }
-      out[u] = (T)acc;
+      T out[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int ff0 = f0 + u;
+        double acc = 0;
+#pragma unroll
+        for (int t1 = 0; t1 < 2; ++t1) {
+          if (t1 >= K2) break;
+          const int k1 = (f1 & 1) + 2 * t1;
+#pragma unroll
+          for (int t0 = 0; t0 < 2; ++t0) {
+            if (t0 >= K2) break;
+            const int k0 = (ff0 & 1) + 2 * t0;
+            // coarse row (ff0 >> 1) - t0 = h0 + (u >> 1) - t0 sits at d = 1 + (u >> 1) - t0
+            acc = fma(wl_h(wav, k0) * wl_h(wav, k1), (double)cv[hh][t1][1 + (u >> 1) - t0], acc);
+          }
+        }
+        out[u] = (T)acc;
+      }
+      Vec4<T>::st(x + f0 + (size_t)f1 * m, out);
     }
-    Vec4<T>::st(x + f0 + (size_t)f1 * m, out);
     return;
   }
   for (int o = threadIdx.x; o < TI * TJ; o += NTHREADS) {

@@ -269,6 +269,13 @@ void Launch::add_grid(const Job& j0, int nti, int ntj, int group) {
   m_min = std::min(m_min, j.m);
 }
 
+void add_prolong(Launch& L, const Job& j, int esz) {
+  if (j.m >= 64)
+    L.add_grid(j, j.m / 32, j.m / 64);
+  else
+    L.add(j, j.m, esz);
+}
+
 void xcd_order(std::vector<uint32_t>& tiles, size_t s0, size_t s1, int nxcd) {
   const size_t n = s1 - s0;
   if (n < 2 || nxcd < 2) return;
@@ -1015,7 +1022,7 @@ int engine_step(dbl_ctx* ctx, std::vector<Slot*>& slots) {
         j.v[0] = s->X[s->cur];
         j.v[1] = s->X[1 - s->cur];
         j.p0 = 0.0;
-        prolL[s->prec].add(j, j.m, (int)s->esz);
+        add_prolong(prolL[s->prec], j, (int)s->esz);
       } else {
         // coarse auxiliary state from the completed coarse solve
         if (s->solver == DBL_IRLS)

@@ -180,6 +180,11 @@ struct Launch {
   bool empty() const { return jobs.empty(); }
 };
 
+// A low-pass prolongation job onto its m x m grid: 32 x 64 fine tiles from
+// m = 64 on (k_dwt_inv takes the tile width from the job, two 32-column
+// halves per block), the usual tiles below.
+void add_prolong(Launch& L, const Job& j, int esz);
+
 // Reorder tiles[s0, s1) so that positions p with p % nxcd == x hold the x-th
 // contiguous chunk of the run (chunk x has as many tiles as there are such
 // positions).  Exposed for the host tests.

@@ -321,7 +321,17 @@ void audit(const void* func, dim3 grid, dim3 block, void** args, size_t shmem) {
       need(fam, jb, "v[1]", v(1), (j.p0 != 0.0 ? n : n / 4) * T);
     } else if (fam == "k_dwt_inv") {
       const size_t T = tsize(ta[0]);
-      grid_is(m);
+      // low-pass prolongation onto m >= 64: 32 x 64 tiles (the kernel takes
+      // the width m / ntj), else the square tiles
+      if (j.p0 == 0.0 && m >= 64) {
+        const size_t w = 64;
+        if ((size_t)j.nti * 32 != m || (size_t)j.ntj * w != m)
+          fail(fam, jb, "prolongation tile grid " + std::to_string(j.nti) + "x" +
+                            std::to_string(j.ntj) + " is not 32 x " + std::to_string(w) +
+                            " tiles of " + std::to_string(m));
+      } else {
+        grid_is(m);
+      }
       need(fam, jb, "v[0]", v(0), (j.p0 != 0.0 ? n : n / 4) * T);
       need(fam, jb, "v[1]", v(1), n * T);
     } else if (fam == "k_dtransfer") {
