@@ -91,6 +91,16 @@ __global__ void __launch_bounds__(STREAM_ROWS) k_apply_stream(const Job* __restr
   // would be a generic-address load, whose wait also drains the queued loads
   const int St1 = t1.St, Sb1 = t1.Sb, rows1 = t1.rows;
   for (int q = tid; q < rows1 * NTAP; q += NT) tab1[q] = gview(t1.tf)[q];  // rows checked on the host
+  // the interior axis-1 tap row, the one every column away from a seam uses,
+  // in scalar registers (the seam columns read their rows from LDS); up to
+  // radius bucket 12 (at 16 the registers would spill)
+  constexpr bool SREG = RB <= 12;
+  T tb1[NTAP];
+#pragma unroll
+  for (int e = 0; e < NTAP; ++e)
+    tb1[e] = SREG ? __builtin_bit_cast(T, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(
+                        int, gview(t1.tf)[St1 * NTAP + e])))
+                  : T(0);
   T ta[NTAP];
   {
     const GlobalPtr<const T> row = gview(t0.tf) + class_of(i, m, t0.St, t0.Sb) * NTAP;
@@ -129,10 +139,15 @@ __global__ void __launch_bounds__(STREAM_ROWS) k_apply_stream(const Job* __restr
       z[u] = a;
       if (k >= 2 * RB) {
         const int j = j0 + k - 2 * RB;
-        const T* row = tab1 + class_of(j, m, St1, Sb1) * NTAP;
         T y = T(0);
+        if (SREG && j >= St1 && j < m - Sb1) {
 #pragma unroll
-        for (int e = 0; e < NTAP; ++e) y = fma(row[e], z[(u + 1 + e) % NTAP], y);
+          for (int e = 0; e < NTAP; ++e) y = fma(tb1[e], z[(u + 1 + e) % NTAP], y);
+        } else {
+          const T* row = tab1 + class_of(j, m, St1, Sb1) * NTAP;
+#pragma unroll
+          for (int e = 0; e < NTAP; ++e) y = fma(row[e], z[(u + 1 + e) % NTAP], y);
+        }
         out[i + (size_t)j * m] = y;
       }
     }
