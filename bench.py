@@ -84,6 +84,9 @@ def parse():
                    help="skip the autotuner (built-in CGLS variant rule)")
     p.add_argument("--tune-cache", default=None,
                    help="autotuner JSON cache: loaded when present, else written")
+    p.add_argument("--multi-tiles", type=int, default=None,
+                   help="DBL_OPT_MULTI_BUCKET (mixed-bucket CGLS launches; < 0 off); "
+                        "default: the library's")
     return p.parse_args()
 
 
@@ -359,6 +362,8 @@ def main():
 
     D.lib()  # fail loudly when the library is missing
     ctx = D.dbl_create(0)
+    if args.multi_tiles is not None:
+        D.dbl_set_option(ctx, D.DBL_OPT_MULTI_BUCKET, args.multi_tiles)
     if args.operators_only:
         print(json.dumps({"operators": operator_leg(D, torch, ctx)}))
         return

@@ -222,7 +222,16 @@ typedef enum dbl_option {
    * and m >= 32 run the 32 x 32 tile kernels laid out for the wavefront; 0:
    * the generic tile kernels.  Both form every sum, including the per-tile
    * FP64 norm partials, in the same order. */
-  DBL_OPT_TILE32 = 3
+  DBL_OPT_TILE32 = 3,
+  /* Mixed-bucket CGLS launches in batched solves (dbl_deblur_batch, the
+   * server).  Jobs whose operators are padded to different radius buckets
+   * normally launch apart, one launch per bucket; with this option the
+   * separable levels of at least 32 x 32 on the tile kernels (DBL_OPT_TILE32)
+   * share launches in which every job keeps its own bucket, so results are
+   * identical.  Value < 0: off.  Value >= 0 (default 4096): buckets up to 8
+   * always share one launch, and buckets up to 12 do too in a CGLS stage
+   * with fewer such tiles (32 x 32 each) than the value. */
+  DBL_OPT_MULTI_BUCKET = 4
 } dbl_option;
 /* Set a context option.  Returns DBL_EINVAL for an unknown option or value.
  * Takes effect for work issued afterwards. */

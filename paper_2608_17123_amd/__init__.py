@@ -30,6 +30,7 @@ DBL_MAX_LEVELS, DBL_MAX_KOUT, DBL_GCV_GRID_MAX = 8, 64, 64
 DBL_OPT_SMALL_CGLS = 1
 DBL_OPT_STREAM_A = 2
 DBL_OPT_TILE32 = 3
+DBL_OPT_MULTI_BUCKET = 4
 
 SOLVERS = {"irls": DBL_IRLS, "mm": DBL_MM, "sb": DBL_SB}
 WAVELETS = {"haar": DBL_HAAR, "db4": DBL_DB4}

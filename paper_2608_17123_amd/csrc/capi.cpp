@@ -148,6 +148,9 @@ int dbl_set_option(dbl_ctx* ctx, int option, long long value) {
       if (value != 0 && value != 1) return set_err(ctx, DBL_EINVAL, "DBL_OPT_TILE32 takes 0 or 1");
       ctx->tile32 = (int)value;
       return DBL_OK;
+    case DBL_OPT_MULTI_BUCKET:
+      ctx->multi_tiles = value < 0 ? -1 : value;
+      return DBL_OK;
     case DBL_OPT_STREAM_A:
       if (value != 0 && value != 1) return set_err(ctx, DBL_EINVAL, "DBL_OPT_STREAM_A takes 0 or 1");
       ctx->stream_a = (int)value;

@@ -17,6 +17,10 @@ struct LaunchArgs {
   // CGLS phases: 1 / 0 forces the register-bounded / unbounded variant; -1
   // takes the bounded one for launches of more than cgls_wide_tiles() tiles
   int wide = -1;
+  // CGLS phases: the jobs' tables are padded to their own radius buckets,
+  // which differ, up to the bucket the launch names (kernels_cgls_multi.hip;
+  // implies the 32 x 32 tile kernels)
+  bool multi = false;
 };
 int cgls_wide_tiles();
 
@@ -60,6 +64,11 @@ hipError_t launch_cgls_p2(const LaunchArgs& la, int precision, int sep, int rb, 
 hipError_t launch_cgls_p1_sep(const LaunchArgs& la, int precision, int rb, bool wide);
 hipError_t launch_cgls_p2_sep(const LaunchArgs& la, int precision, int rb, bool wide);
 size_t cgls_sep_lds(int phase, int precision, int rb);
+// CGLS phase `phase` (1 or 2) over jobs of several radius buckets up to rbmax
+// (kernels_cgls_multi.hip); cgls_multi_bucket(rbmax): a launch can cover them.
+hipError_t launch_cgls_multi(const LaunchArgs& la, int phase, int precision, int rbmax,
+                             bool wide);
+bool cgls_multi_bucket(int rbmax);
 hipError_t launch_aux(const LaunchArgs& la, int precision);
 hipError_t launch_stats(const LaunchArgs& la, int precision, int sep, int rb, int H);
 hipError_t launch_fill(const LaunchArgs& la, int precision);

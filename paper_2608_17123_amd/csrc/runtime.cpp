@@ -699,12 +699,16 @@ struct GroupKey {
   // kernels) launch apart from smaller ones, so a job's kernel depends on
   // its own grid alone, never on which jobs share its launch
   int t32 = 0;
+  // CGLS phases: jobs of several radius buckets, each with tables padded to
+  // its own bucket, share the launch; rb is the largest of them
+  int multi = 0;
   bool operator<(const GroupKey& o) const {
     if (prec != o.prec) return prec < o.prec;
     if (sep != o.sep) return sep < o.sep;
     if (rb != o.rb) return rb < o.rb;
     if (H != o.H) return H < o.H;
-    return t32 < o.t32;
+    if (t32 != o.t32) return t32 < o.t32;
+    return multi < o.multi;
   }
 };
 
@@ -741,11 +745,18 @@ int solver_flags(const Slot* s) {
 // than MERGE_TILES tiles, or one-block jobs of one level size) is latency
 // bound, so it joins the next larger bucket: its jobs run with their tables
 // zero-padded to that bucket (the same operator, a few more multiply-adds).
+// With `multi`, separable levels on the 32 x 32 tile kernels instead share
+// mixed launches (kernels_cgls_multi.hip) in which every job keeps its own
+// bucket: buckets up to 8 always (their kernels run at one occupancy), and
+// buckets up to 12 as well when the stage has fewer than ctx->multi_tiles
+// such tiles, since then none of the separate launches would fill the chip.
 struct GroupPlan {
   struct Entry {
     GroupKey key;       // the launch group (rb = the bucket the tables are padded to)
     size_t small_lds;   // > 0: one-block CGLS with this much LDS
     int wlds;           // one-block CGLS stages the IRLS weights in LDS
+    int tab_rb = 0;     // > 0: the bucket of the job's tables in a mixed launch
+    int tables() const { return tab_rb ? tab_rb : key.rb; }
   };
   std::map<const Slot*, Entry> e;
   const Entry& at(const Slot* s) const { return e.at(s); }
@@ -753,12 +764,15 @@ struct GroupPlan {
 
 constexpr int MERGE_TILES = 256;
 
-GroupPlan plan_groups(dbl_ctx* ctx, const std::vector<Slot*>& slots, bool allow_small = true) {
+GroupPlan plan_groups(dbl_ctx* ctx, const std::vector<Slot*>& slots, bool allow_small = true,
+                      bool multi = false) {
   GroupPlan P;
   // one-block candidates by (precision, m): one bucket for all when every
   // member still fits in LDS with it
   std::map<std::pair<int, int>, std::vector<const Slot*>> small;
   std::map<GroupKey, std::vector<const Slot*>> tiled;
+  std::map<int, std::vector<const Slot*>> mixed;  // mixed-launch candidates by precision
+  multi = multi && ctx->multi_tiles >= 0 && ctx->tile32;
   for (const Slot* s : slots) {
     const int lv = s->level;
     const LevelHost& L = s->op->host.levels[lv];
@@ -767,7 +781,36 @@ GroupPlan plan_groups(dbl_ctx* ctx, const std::vector<Slot*>& slots, bool allow_
       en.small_lds = small_lds_bytes(ctx, s->op, lv, s->solver == DBL_IRLS, &en.wlds);
     P.e[s] = en;
     if (en.small_lds) small[{s->prec, L.m}].push_back(s);
+    else if (multi && L.sep && L.m >= 32 && L.rb <= 12) mixed[s->prec].push_back(s);
     else tiled[en.key].push_back(s);
+  }
+  for (auto& kv : mixed) {
+    std::map<int, size_t> per;  // tiles by bucket
+    size_t tot = 0;
+    for (const Slot* s : kv.second) {
+      const int mi = s->m >> s->level, t = mi / 32;
+      per[s->op->host.levels[s->level].rb] += (size_t)t * t;
+      tot += (size_t)t * t;
+    }
+    const bool all = tot < (size_t)ctx->multi_tiles;
+    int top = 0, nb = 0;
+    for (auto& b : per)
+      if (all || b.first <= 8) {
+        top = std::max(top, b.first);
+        ++nb;
+      }
+    for (const Slot* s : kv.second) {
+      const int rb = s->op->host.levels[s->level].rb;
+      GroupPlan::Entry& en = P.e[s];
+      if (nb < 2 || !(all || rb <= 8) || !cgls_multi_bucket(top)) {
+        tiled[en.key].push_back(s);  // a launch of its own bucket
+        continue;
+      }
+      en.key.rb = en.key.H = top;
+      en.key.t32 = 1;
+      en.key.multi = 1;
+      en.tab_rb = rb;
+    }
   }
   for (auto& kv : small) {
     int rbt = 0;
@@ -1156,14 +1199,14 @@ int engine_step(dbl_ctx* ctx, std::vector<Slot*>& slots) {
     std::map<GroupKey, std::vector<int>> kin;
     std::map<std::pair<GroupKey, int>, Launch> smallL;  // by (group, m)
     std::map<std::pair<GroupKey, int>, size_t> smallB;
-    const GroupPlan plan = plan_groups(ctx, ord);
+    const GroupPlan plan = plan_groups(ctx, ord, true, true);
     for (Slot* s : ord) {
       const int lv = s->level;
       const int nw = 1 - s->cur;
       const PartLayout PL = part_layout(s->part, s->m >> lv);
       const GroupPlan::Entry& pe = plan.at(s);
       Job j = base_job(s, lv);
-      j.op = op_dev(s->op, lv, pe.key.rb ? pe.key.rb : s->op->host.levels[lv].rb);
+      j.op = op_dev(s->op, lv, pe.tables() ? pe.tables() : s->op->host.levels[lv].rb);
       j.flags = solver_flags(s);
       j.v[V_X] = s->X[nw];
       j.v[V_S] = s->S;
@@ -1246,6 +1289,10 @@ int engine_step(dbl_ctx* ctx, std::vector<Slot*>& slots) {
       for (int par = 0; par < 2; ++par) {
         if ((rc = p1[par][g].upload(ctx, a1[par][g]))) return rc;
         if ((rc = p2[par][g].upload(ctx, a2[par][g]))) return rc;
+      }
+      if (g.multi) {
+        aF[g].multi = a1f[g].multi = true;
+        for (int par = 0; par < 2; ++par) a1[par][g].multi = a2[par][g].multi = true;
       }
     }
     for (auto& kv : aF) {

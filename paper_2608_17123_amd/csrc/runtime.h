@@ -61,6 +61,10 @@ struct dbl_ctx {
   // streaming separable blur for large FP32 grids in the operator entry points
   int stream_a = 1;
   int tile32 = 1;  // 32 x 32 tile CGLS kernels for separable operators (DBL_OPT_TILE32)
+  // CGLS stage launches that mix radius buckets (DBL_OPT_MULTI_BUCKET): < 0
+  // off; else buckets up to 8 share a launch, and buckets up to 12 do too in
+  // a stage with fewer tile-kernel tiles than this
+  long long multi_tiles = 4096;
   // autotuned CGLS phase variants (dbl_autotune); empty: the built-in rule
   std::vector<TuneEntry> tune;
   size_t lds_limit = 65536;

@@ -3,11 +3,14 @@
 //
 // usage: dryrun <psf-file> <m> <levels> <solver> <wavelet> <transfer> <precision>
 //               <k_out> <k_in> <small_cgls> <copies> [<inner> [<gcv mode>]]
-// psf-file: "ph pw" then ph*pw values, column-major.  copies > 1 solves that
-// many copies of the request in one dbl_deblur_batch call.  Parameters are a
+// psf-file: "ph pw" then ph*pw values, column-major; a comma-separated list
+// of such files gives the copies their PSFs in turn.  copies > 1 solves that
+// many copies of the request in one dbl_deblur_batch call.
+// DRYRUN_MULTI_TILES sets DBL_OPT_MULTI_BUCKET.  Parameters are a
 // fixed schedule, or chosen by GCV when a GCV mode is given (the stand-in's
 // device memory holds zeros, so the minimisations run their full length).  Prints the launch counts per kernel family and
 // every violation; exits 1 when there is one.
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <map>
@@ -30,14 +33,30 @@ int main(int argc, char** argv) {
                          "small copies [inner]\n");
     return 2;
   }
-  FILE* f = std::fopen(argv[1], "r");
-  if (!f) return 2;
-  int ph = 0, pw = 0;
-  if (std::fscanf(f, "%d %d", &ph, &pw) != 2) return 2;
-  std::vector<double> psf((size_t)ph * pw);
-  for (double& v : psf)
-    if (std::fscanf(f, "%lf", &v) != 1) return 2;
-  std::fclose(f);
+  struct Psf {
+    int ph = 0, pw = 0;
+    std::vector<double> v;
+  };
+  std::vector<Psf> psfs;
+  {
+    std::string list = argv[1];
+    size_t at = 0;
+    while (at <= list.size()) {
+      const size_t cut = std::min(list.find(',', at), list.size());
+      FILE* f = std::fopen(list.substr(at, cut - at).c_str(), "r");
+      if (!f) return 2;
+      Psf p;
+      if (std::fscanf(f, "%d %d", &p.ph, &p.pw) != 2) return 2;
+      p.v.resize((size_t)p.ph * p.pw);
+      for (double& v : p.v)
+        if (std::fscanf(f, "%lf", &v) != 1) return 2;
+      std::fclose(f);
+      psfs.push_back(std::move(p));
+      at = cut + 1;
+    }
+  }
+  const int ph = psfs[0].ph, pw = psfs[0].pw;
+  std::vector<double>& psf = psfs[0].v;
   const int m = std::atoi(argv[2]), levels = std::atoi(argv[3]), solver = std::atoi(argv[4]),
             wavelet = std::atoi(argv[5]), transfer = std::atoi(argv[6]),
             prec = std::atoi(argv[7]), k_out = std::atoi(argv[8]), k_in = std::atoi(argv[9]),
@@ -49,6 +68,8 @@ int main(int argc, char** argv) {
   int rc = dbl_create(&ctx, 0, nullptr, 0);
   if (rc) return 3;
   dbl_set_option(ctx, DBL_OPT_SMALL_CGLS, small);
+  if (const char* mt = std::getenv("DRYRUN_MULTI_TILES"))
+    dbl_set_option(ctx, DBL_OPT_MULTI_BUCKET, std::atoll(mt));
   if (std::getenv("DRYRUN_AUTOTUNE")) {
     // the tuner's synthetic launches are audited like the solve's; the
     // stand-in's events read 0 ms, so every key keeps variant 0
@@ -75,7 +96,8 @@ int main(int argc, char** argv) {
     hipMalloc(&b, (size_t)m * m * esz);
     // DRYRUN_SHORT_X: an x buffer one element too short (the audit must see it)
     hipMalloc(&x, ((size_t)m * m - (std::getenv("DRYRUN_SHORT_X") ? 1 : 0)) * esz);
-    reqs[q] = dbl_request{b, x, psf.data(), ph, pw, m, solver, wavelet, levels, transfer, o};
+    const Psf& p = psfs[q % psfs.size()];
+    reqs[q] = dbl_request{b, x, p.v.data(), p.ph, p.pw, m, solver, wavelet, levels, transfer, o};
   }
   dbl_report rep;
   if (copies == 1)

@@ -168,6 +168,24 @@ void check_sep32(const std::string& k, int jb, const Job& j, int rb, size_t esz,
     fail(k, jb, "dynamic LDS " + std::to_string(shmem) + " < " + std::to_string(e * esz));
 }
 
+// The mixed-bucket tile kernels: every job's tables are padded to a bucket
+// of its own, one the kernel has a body for (2, 4, 8, 12 up to its RBMAX),
+// and each job then meets the 32 x 32 tile kernel's conditions for that
+// bucket; the launch's LDS is sized for RBMAX, which covers every body.
+void check_multi(const std::string& k, int jb, const Job& j, int rbmax, size_t esz, int phase,
+                 size_t shmem) {
+  if (rbmax != 4 && rbmax != 8 && rbmax != 12) fail(k, jb, "mixed launch up to bucket " +
+                                                            std::to_string(rbmax));
+  if (!j.op || !owner(j.op, sizeof(dbl::LevelOp))) return;
+  const int rb = j.op->rb;
+  if ((rb != 2 && rb != 4 && rb != 8 && rb != 12) || rb > rbmax) {
+    fail(k, jb, "job bucket " + std::to_string(rb) + " outside the launch's bodies (up to " +
+                    std::to_string(rbmax) + ")");
+    return;
+  }
+  check_sep32(k, jb, j, rb, esz, phase, shmem);
+}
+
 void audit(const void* func, dim3 grid, dim3 block, void** args, size_t shmem) {
   const std::string name = kernel_name(func);
   // family: the unqualified kernel name ("void dbl::k_cgls_p2<...>(...)" -> k_cgls_p2)
@@ -235,11 +253,13 @@ void audit(const void* func, dim3 grid, dim3 block, void** args, size_t shmem) {
         need(fam, jb, "V_XOLD", v(dbl::V_XOLD), n * T);
         if (irls) need(fam, jb, "V_W", v(dbl::V_W), nl * T);
       }
-    } else if (fam == "k_cgls_p1" || fam == "k_cgls_p1_wide" || fam == "k_cgls_p1_sep") {
+    } else if (fam == "k_cgls_p1" || fam == "k_cgls_p1_wide" || fam == "k_cgls_p1_sep" ||
+               fam == "k_cgls_p1_multi") {
       const size_t T = tsize(ta[0]), S = tsize(ta[1]);
       grid_is(m);
       check_op(fam, jb, j, T == 8);
       if (fam == "k_cgls_p1_sep") check_sep32(fam, jb, j, std::atoi(ta[2].c_str()), T, 1, shmem);
+      if (fam == "k_cgls_p1_multi") check_multi(fam, jb, j, std::atoi(ta[2].c_str()), T, 1, shmem);
       need(fam, jb, "V_S", v(dbl::V_S), n * S);
       need(fam, jb, "V_PA", v(dbl::V_PA), n * S);
       need(fam, jb, "V_PB", v(dbl::V_PB), n * S);
@@ -252,11 +272,13 @@ void audit(const void* func, dim3 grid, dim3 block, void** args, size_t shmem) {
         need(fam, jb, "pr[0]", j.pr[0], (size_t)ntile * 2 * 8);
         need(fam, jb, "pr[1]", j.pr[1], (size_t)ntile * 2 * 8);
       }
-    } else if (fam == "k_cgls_p2" || fam == "k_cgls_p2_wide" || fam == "k_cgls_p2_sep") {
+    } else if (fam == "k_cgls_p2" || fam == "k_cgls_p2_wide" || fam == "k_cgls_p2_sep" ||
+               fam == "k_cgls_p2_multi") {
       const size_t T = tsize(ta[0]), S = tsize(ta[1]);
       grid_is(m);
       check_op(fam, jb, j, T == 8);
       if (fam == "k_cgls_p2_sep") check_sep32(fam, jb, j, std::atoi(ta[2].c_str()), T, 2, shmem);
+      if (fam == "k_cgls_p2_multi") check_multi(fam, jb, j, std::atoi(ta[2].c_str()), T, 2, shmem);
       need(fam, jb, "V_R1A", v(dbl::V_R1A), n * S);
       need(fam, jb, "V_R1B", v(dbl::V_R1B), n * S);
       need(fam, jb, "V_R2A", v(dbl::V_R2A), nl * S);

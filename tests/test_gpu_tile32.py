@@ -147,3 +147,44 @@ def test_batch_with_small_grids_equals_plain(ctx):
     assert all(r["status"] == 0 for r in reps)
     for x, xp in zip(xs, plain):
         assert torch.equal(x, xp)
+
+
+@pytest.mark.parametrize("prec", [D.DBL_F32, D.DBL_F64, D.DBL_BF16])
+@pytest.mark.parametrize("multi", [0, 1 << 20])
+def test_mixed_bucket_batch_equals_plain(ctx, prec, multi):
+    """Solves whose operators fall in buckets 2, 4, 8, 12 and 16 in one
+    batch: the CGLS stages run mixed-bucket launches (buckets up to 8, and
+    up to 12 under the larger threshold; 16 always launches apart), in which
+    every job keeps its own bucket, so each solve equals its plain run bit
+    for bit."""
+    print(f"mixed-bucket batch prec={prec} multi={multi}", flush=True)
+    D.dbl_set_option(ctx, D.DBL_OPT_MULTI_BUCKET, multi)
+    cases = [(128, 3, "irls", "haar", "X", (0.6, 2)), (256, 3, "sb", "db4", "D", (1.2, 4)),
+             (128, 2, "mm", "haar", "D", (2.5, 8)), (256, 4, "irls", "db4", "X", (3.5, 12)),
+             (64, 2, "sb", "haar", "X", (1.0, 3)), (128, 3, "mm", "db4", "X", (4.0, 16)),
+             (256, 3, "irls", "haar", "D", (2.0, 6))]
+    k_out, k_in = 2, 5
+    dt = DT[prec]
+    reqs, xs, plain = [], [], []
+    for q, (m, levels, solver, wavelet, transfer, (sig, r)) in enumerate(cases):
+        X, rng = image(m, 70 + q)
+        P = synth.gaussian_psf(sig, r)
+        B = ops.blur(X, P)
+        B = B + 0.01 * np.linalg.norm(B) * rng.standard_normal((m, m)) / m
+        mu = [[3e-3 * (1.3 ** i) for _ in range(k_out)] for i in range(levels)]
+        opts = D.dbl_opts_default(k_out=k_out, k_in=k_in, precision=prec,
+                                  mu_schedule=np.array(mu).ravel())
+        b = torch.tensor(ops.vec(B), dtype=dt, device="cuda")
+        xp = torch.zeros(m * m, dtype=dt, device="cuda")
+        assert D.dbl_deblur(ctx, b, P, m, solver, wavelet, levels, transfer, xp,
+                            opts)["status"] == 0
+        plain.append(xp)
+        x = torch.zeros(m * m, dtype=dt, device="cuda")
+        xs.append(x)
+        reqs.append(D.make_request(b, x, P, m, solver, wavelet, levels, transfer, opts))
+    reps = D.dbl_deblur_batch(ctx, reqs)
+    torch.cuda.synchronize()
+    D.dbl_set_option(ctx, D.DBL_OPT_MULTI_BUCKET, 4096)
+    assert all(r["status"] == 0 for r in reps)
+    for q, (x, xp) in enumerate(zip(xs, plain)):
+        assert torch.equal(x, xp), f"case {q}: max diff {float((x - xp).abs().max()):.3e}"
