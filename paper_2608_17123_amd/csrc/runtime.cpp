@@ -111,27 +111,6 @@ int stage(dbl_ctx* ctx, const void* src, size_t bytes, void** dptr) {
   return DBL_OK;
 }
 
-// Two arrays staged back to back with one copy.
-int stage2(dbl_ctx* ctx, const void* a, size_t na, const void* b, size_t nb, void** da,
-           void** db) {
-  const size_t ea = (na + 255) & ~size_t(255);
-  std::vector<char> both;  // only when the pair is large; the common case fits below
-  char tmp[16384];
-  char* buf = tmp;
-  if (ea + nb > sizeof(tmp)) {
-    both.resize(ea + nb);
-    buf = both.data();
-  }
-  std::memcpy(buf, a, na);
-  std::memcpy(buf + ea, b, nb);
-  void* d = nullptr;
-  int rc = stage(ctx, buf, ea + nb, &d);
-  if (rc) return rc;
-  *da = d;
-  *db = static_cast<char*>(d) + ea;
-  return DBL_OK;
-}
-
 // Called only where no staged array is waiting for its launch: when the
 // buffer is more than half used (or old buffers are retired), wait for the
 // stream, free retired buffers and restart at offset 0.
@@ -291,22 +270,51 @@ void xcd_order(std::vector<uint32_t>& tiles, size_t s0, size_t s1, int nxcd) {
   for (size_t p = s0; p < s1; ++p) tiles[p] = run[next[p % nxcd]++];
 }
 
-int Launch::upload(dbl_ctx* ctx, LaunchArgs& la) {
-  void *dj = nullptr, *dt = nullptr;
+size_t Launch::pack(std::vector<char>& buf) const {
   std::vector<uint32_t> order = tiles;
   for (size_t q = 0; q < seg_start.size(); ++q) {
     const size_t s1 = q + 1 < seg_start.size() ? (size_t)seg_start[q + 1] : order.size();
     xcd_order(order, (size_t)seg_start[q], s1, XCDS);
   }
-  int rc = stage2(ctx, jobs.data(), jobs.size() * sizeof(Job), order.data(),
-                  order.size() * sizeof(uint32_t), &dj, &dt);
-  if (rc) return rc;
-  la.jobs = static_cast<const Job*>(dj);
-  la.tiles = static_cast<const uint32_t*>(dt);
+  const size_t oj = (buf.size() + 255) & ~size_t(255);
+  const size_t nj = jobs.size() * sizeof(Job);
+  const size_t ot = (oj + nj + 255) & ~size_t(255);
+  buf.resize(ot + order.size() * sizeof(uint32_t), 0);
+  std::memcpy(buf.data() + oj, jobs.data(), nj);
+  std::memcpy(buf.data() + ot, order.data(), order.size() * sizeof(uint32_t));
+  return oj;
+}
+
+void Launch::bind(const dbl_ctx* ctx, char* d, size_t off, LaunchArgs& la) const {
+  const size_t ot = (off + jobs.size() * sizeof(Job) + 255) & ~size_t(255);
+  la.jobs = reinterpret_cast<const Job*>(d + off);
+  la.tiles = reinterpret_cast<const uint32_t*>(d + ot);
   la.ntiles = (int)tiles.size();
   la.m_max = m_max;
   la.stream = ctx->stream;
   la.tile32 = ctx->tile32 && m_min >= 32;
+}
+
+int Launch::upload(dbl_ctx* ctx, LaunchArgs& la) {
+  std::vector<char> buf;
+  const size_t off = pack(buf);
+  void* d = nullptr;
+  int rc = stage(ctx, buf.data(), buf.size(), &d);
+  if (rc) return rc;
+  bind(ctx, static_cast<char*>(d), off, la);
+  return DBL_OK;
+}
+
+int upload_all(dbl_ctx* ctx, const std::vector<std::pair<const Launch*, LaunchArgs*>>& ls) {
+  std::vector<char> buf;
+  std::vector<size_t> offs;
+  for (auto& l : ls) offs.push_back(l.first->pack(buf));
+  if (buf.empty()) return DBL_OK;
+  void* d = nullptr;
+  int rc = stage(ctx, buf.data(), buf.size(), &d);
+  if (rc) return rc;
+  for (size_t q = 0; q < ls.size(); ++q)
+    ls[q].first->bind(ctx, static_cast<char*>(d), offs[q], *ls[q].second);
   return DBL_OK;
 }
 
@@ -1266,11 +1274,28 @@ int engine_step(dbl_ctx* ctx, std::vector<Slot*>& slots) {
       }
       kin[gk].push_back(s->opts.k_in);
     }
+    // every table of the stage staged with one copy
+    std::map<std::pair<GroupKey, int>, LaunchArgs> laS;
+    std::map<int, LaunchArgs> laI;
+    std::map<GroupKey, LaunchArgs> aF, a1f, a1[2], a2[2];
+    std::vector<std::pair<const Launch*, LaunchArgs*>> up;
+    for (auto& kv : smallL) up.push_back({&kv.second, &laS[kv.first]});
+    for (auto& kv : initL)
+      if (!kv.second.empty()) up.push_back({&kv.second, &laI[kv.first]});
+    for (auto& kv : first) {
+      const GroupKey& g = kv.first;
+      up.push_back({&kv.second, &aF[g]});
+      up.push_back({&p1f[g], &a1f[g]});
+      for (int par = 0; par < 2; ++par) {
+        up.push_back({&p1[par][g], &a1[par][g]});
+        up.push_back({&p2[par][g], &a2[par][g]});
+      }
+    }
+    if ((rc = upload_all(ctx, up))) return rc;
     for (auto& kv : smallL) {
       const GroupKey& g = kv.first.first;
       const int mm = kv.first.second;
-      LaunchArgs la;
-      if ((rc = kv.second.upload(ctx, la))) return rc;
+      const LaunchArgs& la = laS[kv.first];
       double b = 0.0;
       for (const Job& jj : kv.second.jobs) b += job_bytes("cgls_small", jj, g.prec);
       const size_t lds = smallB[kv.first];
@@ -1280,16 +1305,17 @@ int engine_step(dbl_ctx* ctx, std::vector<Slot*>& slots) {
                           "cgls small")))
         return rc;
     }
-    if ((rc = run_simple(ctx, launch_cgls_init, initL, "cgls_init"))) return rc;
-    std::map<GroupKey, LaunchArgs> aF, a1f, a1[2], a2[2];
+    for (auto& kv : laI) {
+      double b = 0.0;
+      for (const Job& jj : initL[kv.first].jobs) b += job_bytes("cgls_init", jj, kv.first);
+      if ((rc = hip_check(ctx, timed(ctx, "cgls_init", b, [&] {
+                            return launch_cgls_init(kv.second, kv.first);
+                          }),
+                          "cgls_init")))
+        return rc;
+    }
     for (auto& kv : first) {
       const GroupKey& g = kv.first;
-      if ((rc = kv.second.upload(ctx, aF[g]))) return rc;
-      if ((rc = p1f[g].upload(ctx, a1f[g]))) return rc;
-      for (int par = 0; par < 2; ++par) {
-        if ((rc = p1[par][g].upload(ctx, a1[par][g]))) return rc;
-        if ((rc = p2[par][g].upload(ctx, a2[par][g]))) return rc;
-      }
       if (g.multi) {
         aF[g].multi = a1f[g].multi = true;
         for (int par = 0; par < 2; ++par) a1[par][g].multi = a2[par][g].multi = true;
@@ -1377,7 +1403,6 @@ int engine_step(dbl_ctx* ctx, std::vector<Slot*>& slots) {
     for (Slot* s : act)
       if (s->solver == DBL_SB)
         add_aux(L, s, s->level, AUX_SB_UPDATE, s->X[1 - s->cur], nullptr, s->C1, s->C2);
-    if ((rc = run_simple(ctx, launch_aux, L, "aux"))) return rc;
     std::map<GroupKey, Launch> S;
     Launch F;
     for (Slot* s : act) {
@@ -1399,9 +1424,25 @@ int engine_step(dbl_ctx* ctx, std::vector<Slot*>& slots) {
       if (s->rc_idx >= 0) jf.v[V_RCOUT] = ctx->d_rc + s->rc_idx;
       F.add(jf, 1, 4);
     }
+    // every table of the stage staged with one copy
+    std::map<int, LaunchArgs> laL;
+    std::map<GroupKey, LaunchArgs> laS;
+    LaunchArgs laF;
+    std::vector<std::pair<const Launch*, LaunchArgs*>> up;
+    for (auto& kv : L)
+      if (!kv.second.empty()) up.push_back({&kv.second, &laL[kv.first]});
+    for (auto& kv : S) up.push_back({&kv.second, &laS[kv.first]});
+    up.push_back({&F, &laF});
+    if ((rc = upload_all(ctx, up))) return rc;
+    for (auto& kv : laL) {
+      double b = 0.0;
+      for (const Job& jj : L[kv.first].jobs) b += job_bytes("aux", jj, kv.first);
+      if ((rc = hip_check(ctx, timed(ctx, "aux", b, [&] { return launch_aux(kv.second, kv.first); }),
+                          "aux")))
+        return rc;
+    }
     for (auto& kv : S) {
-      LaunchArgs la;
-      if ((rc = kv.second.upload(ctx, la))) return rc;
+      const LaunchArgs& la = laS[kv.first];
       const GroupKey& g = kv.first;
       double b = 0.0;
       for (const Job& jj : kv.second.jobs) b += job_bytes("stats", jj, g.prec);
@@ -1411,13 +1452,9 @@ int engine_step(dbl_ctx* ctx, std::vector<Slot*>& slots) {
                           "stats")))
         return rc;
     }
-    {
-      LaunchArgs la;
-      if ((rc = F.upload(ctx, la))) return rc;
-      if ((rc = hip_check(ctx, timed(ctx, "stats_fin", 0.0, [&] { return launch_stats_fin(la); }),
-                          "stats fin")))
-        return rc;
-    }
+    if ((rc = hip_check(ctx, timed(ctx, "stats_fin", 0.0, [&] { return launch_stats_fin(laF); }),
+                        "stats fin")))
+      return rc;
     if (n_rc > 0) {
       rc = hip_check(ctx, hipMemcpyAsync(ctx->h_rc, ctx->d_rc, (size_t)n_rc * 8,
                                          hipMemcpyDeviceToHost, ctx->stream),

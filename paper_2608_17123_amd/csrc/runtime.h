@@ -116,8 +116,6 @@ int pool_get(dbl_ctx* ctx, size_t bytes, void** p);
 void pool_put(dbl_ctx* ctx, void* p, size_t bytes);
 void pool_trim(dbl_ctx* ctx, size_t keep_bytes);
 int stage(dbl_ctx* ctx, const void* src, size_t bytes, void** dptr);
-int stage2(dbl_ctx* ctx, const void* a, size_t na, const void* b, size_t nb, void** da,
-           void** db);
 int stage_checkpoint(dbl_ctx* ctx);
 
 // Per-kernel timing: when profiling is on, `launch` runs between two events on
@@ -182,7 +180,16 @@ struct Launch {
   void add_grid(const Job& j, int nti, int ntj, int group = 0);
   int upload(dbl_ctx* ctx, LaunchArgs& la);
   bool empty() const { return jobs.empty(); }
+  // Host image of the launch's tables appended to buf at a 256-byte
+  // boundary: the job table, then the tile table (XCD-ordered) at the next
+  // boundary.  Returns the offset of the job table.
+  size_t pack(std::vector<char>& buf) const;
+  // la for the tables packed at `off` of a staged copy at device address d.
+  void bind(const dbl_ctx* ctx, char* d, size_t off, LaunchArgs& la) const;
 };
+// The tables of several launches staged with one copy (each LaunchArgs gets
+// the same fields as from Launch::upload).
+int upload_all(dbl_ctx* ctx, const std::vector<std::pair<const Launch*, LaunchArgs*>>& ls);
 
 // A low-pass prolongation job onto its m x m grid: 32 x 64 fine tiles from
 // m = 64 on (k_dwt_inv takes the tile width from the job, two 32-column

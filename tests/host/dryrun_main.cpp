@@ -25,6 +25,7 @@ namespace mock {
 extern std::vector<std::string> violations;
 extern std::map<std::string, long> launches;
 extern long checked_pointers;
+extern std::map<std::string, long> copies_before;
 }  // namespace mock
 
 int main(int argc, char** argv) {
@@ -107,6 +108,12 @@ int main(int argc, char** argv) {
     rc = dbl_deblur_batch(ctx, copies, reqs.data(), nullptr);
   std::printf("status %d (%s)\n", rc, rc ? dbl_last_error(ctx) : "ok");
   for (auto& kv : mock::launches) std::printf("launches %s %ld\n", kv.first.c_str(), kv.second);
+  long n_copies = 0;
+  for (auto& kv : mock::copies_before) {
+    if (kv.second) std::printf("copies before %s %ld\n", kv.first.c_str(), kv.second);
+    n_copies += kv.second;
+  }
+  std::printf("copies %ld\n", n_copies);
   std::printf("checked %ld pointers\n", mock::checked_pointers);
   for (auto& v : mock::violations) std::printf("VIOLATION %s\n", v.c_str());
   std::printf("violations %zu\n", mock::violations.size());

@@ -42,6 +42,10 @@ std::map<const char*, size_t> allocs;  // base -> bytes (std::less on pointers: 
 std::vector<std::string> violations;
 std::map<std::string, long> launches;  // kernel family -> launch count
 long checked_pointers = 0;
+// copies queued since the last launch, and per kernel family the copies
+// queued right before its launches (the table uploads each launch waits for)
+long pending_copies = 0;
+std::map<std::string, long> copies_before;
 
 const char* owner(const void* p, size_t bytes) {
   const char* c = static_cast<const char*>(p);
@@ -194,6 +198,8 @@ void audit(const void* func, dim3 grid, dim3 block, void** args, size_t shmem) {
   if (fam.rfind("dbl::", 0) == 0) fam = fam.substr(5);
   fam = fam.substr(0, std::min(fam.find('<'), fam.find('(')));
   launches[fam] += 1;
+  copies_before[fam] += pending_copies;
+  pending_copies = 0;
   const Job* jobs = *static_cast<const Job* const*>(args[0]);
   const uint32_t* tiles = *static_cast<const uint32_t* const*>(args[1]);
   const size_t nt = grid.x;
@@ -490,6 +496,7 @@ hipError_t hipMemcpy(void* d, const void* s, size_t n, hipMemcpyKind) {
   return hipSuccess;
 }
 hipError_t hipMemcpyAsync(void* d, const void* s, size_t n, hipMemcpyKind, hipStream_t) {
+  ++mock::pending_copies;
   if (range_ok("copy destination", d, n) && range_ok("copy source", s, n)) std::memmove(d, s, n);
   return hipSuccess;
 }
