@@ -228,9 +228,9 @@ typedef enum dbl_option {
    * normally launch apart, one launch per bucket; with this option the
    * separable levels of at least 32 x 32 on the tile kernels (DBL_OPT_TILE32)
    * share launches in which every job keeps its own bucket, so results are
-   * identical.  Value < 0: off.  Value >= 0 (default 4096): buckets up to 8
-   * always share one launch, and buckets up to 12 do too in a CGLS stage
-   * with fewer such tiles (32 x 32 each) than the value. */
+   * identical.  Value < 0: off.  Value >= 0 (default 3072): buckets up to 8
+   * always share one launch, and bucket 12 joins it in a CGLS stage where it
+   * has fewer tiles (32 x 32 each) than the value. */
   DBL_OPT_MULTI_BUCKET = 4
 } dbl_option;
 /* Set a context option.  Returns DBL_EINVAL for an unknown option or value.

@@ -49,10 +49,13 @@ __global__ void __launch_bounds__(NTHREADS, MINW)
 
 bool cgls_multi_bucket(int rbmax) { return rbmax == 4 || rbmax == 8 || rbmax == 12; }
 
-// Waves per SIMD of the register-bounded variant.  Branching between bucket
-// bodies keeps some values live across all of them, so the FP32 8-wave bound
-// of the one-bucket kernels (64 VGPRs) would spill here: 7 waves (72 VGPRs)
-// up to bucket 8, 6 (80) with bucket 12, no spills; FP64 as elsewhere.
+// Waves per SIMD.  A mixed launch gathers enough tiles to fill the chip, so
+// its kernels are register-bounded like the one-bucket kernels of large
+// launches (measured faster than the unbounded ones at every mixed stage of
+// the 256-image batch).  Branching between bucket bodies keeps some values
+// live across all of them, so the FP32 8-wave bound of the one-bucket
+// kernels (64 VGPRs) would spill here: 7 waves (72 VGPRs) up to bucket 8, 6
+// (80) with bucket 12, no spills; FP64 as elsewhere.
 template <typename T, int RBMAX>
 constexpr int multi_wide_waves() {
   return sizeof(T) == 4 ? (RBMAX <= 8 ? 7 : 6) : 2;
@@ -60,12 +63,8 @@ constexpr int multi_wide_waves() {
 
 #define DBL_MULTI_CASE(KERNEL, T, S, R)                                                   \
   case R:                                                                                 \
-    if (wide)                                                                             \
-      hipLaunchKernelGGL((KERNEL<T, S, R, multi_wide_waves<T, R>()>), dim3(la.ntiles),     \
-                         dim3(NTHREADS), lds, la.stream, la.jobs, la.tiles);              \
-    else                                                                                  \
-      hipLaunchKernelGGL((KERNEL<T, S, R, waves_per_simd<T, R>()>), dim3(la.ntiles),       \
-                         dim3(NTHREADS), lds, la.stream, la.jobs, la.tiles);              \
+    hipLaunchKernelGGL((KERNEL<T, S, R, multi_wide_waves<T, R>()>), dim3(la.ntiles),       \
+                       dim3(NTHREADS), lds, la.stream, la.jobs, la.tiles);                \
     break;
 #define DBL_MULTI_DISPATCH(KERNEL, T, S)                                                  \
   switch (rbmax) {                                                                        \
@@ -75,8 +74,7 @@ constexpr int multi_wide_waves() {
     default: return hipErrorInvalidValue;                                                 \
   }
 
-hipError_t launch_cgls_multi(const LaunchArgs& la, int phase, int precision, int rbmax,
-                             bool wide) {
+hipError_t launch_cgls_multi(const LaunchArgs& la, int phase, int precision, int rbmax) {
   const size_t lds = cgls_sep_lds(phase, precision, rbmax);
   if (phase == 1) {
     if (precision == 1) { DBL_MULTI_DISPATCH(k_cgls_p1_multi, double, double) }

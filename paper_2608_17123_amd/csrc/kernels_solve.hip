@@ -565,7 +565,7 @@ int cgls_wide_tiles() { return P2_WIDE_TILES; }
 
 hipError_t launch_cgls_p1(const LaunchArgs& la, int precision, int sep, int rb, int H) {
   const bool wide = la.wide >= 0 ? la.wide != 0 : la.ntiles > P2_WIDE_TILES;
-  if (sep && la.multi) return launch_cgls_multi(la, 1, precision, rb, wide);
+  if (sep && la.multi) return launch_cgls_multi(la, 1, precision, rb);
   if (sep && la.tile32) return launch_cgls_p1_sep(la, precision, rb, wide);
   if (precision == 1) DISPATCH_STENCIL_S(k_cgls_p1, double, double, la, sep, rb, H);
   else if (wide && precision == 2)
@@ -579,7 +579,7 @@ hipError_t launch_cgls_p1(const LaunchArgs& la, int precision, int sep, int rb, 
 
 hipError_t launch_cgls_p2(const LaunchArgs& la, int precision, int sep, int rb, int H) {
   const bool wide = la.wide >= 0 ? la.wide != 0 : la.ntiles > P2_WIDE_TILES;
-  if (sep && la.multi) return launch_cgls_multi(la, 2, precision, rb, wide);
+  if (sep && la.multi) return launch_cgls_multi(la, 2, precision, rb);
   if (sep && la.tile32) return launch_cgls_p2_sep(la, precision, rb, wide);
   if (precision == 1) DISPATCH_STENCIL_S(k_cgls_p2, double, double, la, sep, rb, H);
   else if (wide && precision == 2)

@@ -65,9 +65,10 @@ hipError_t launch_cgls_p1_sep(const LaunchArgs& la, int precision, int rb, bool 
 hipError_t launch_cgls_p2_sep(const LaunchArgs& la, int precision, int rb, bool wide);
 size_t cgls_sep_lds(int phase, int precision, int rb);
 // CGLS phase `phase` (1 or 2) over jobs of several radius buckets up to rbmax
-// (kernels_cgls_multi.hip); cgls_multi_bucket(rbmax): a launch can cover them.
-hipError_t launch_cgls_multi(const LaunchArgs& la, int phase, int precision, int rbmax,
-                             bool wide);
+// (kernels_cgls_multi.hip, register-bounded kernels only: a mixed launch
+// gathers enough tiles to fill the chip); cgls_multi_bucket(rbmax): a launch
+// can cover them.
+hipError_t launch_cgls_multi(const LaunchArgs& la, int phase, int precision, int rbmax);
 bool cgls_multi_bucket(int rbmax);
 hipError_t launch_aux(const LaunchArgs& la, int precision);
 hipError_t launch_stats(const LaunchArgs& la, int precision, int sep, int rb, int H);

@@ -756,8 +756,8 @@ int solver_flags(const Slot* s) {
 // With `multi`, separable levels on the 32 x 32 tile kernels instead share
 // mixed launches (kernels_cgls_multi.hip) in which every job keeps its own
 // bucket: buckets up to 8 always (their kernels run at one occupancy), and
-// buckets up to 12 as well when the stage has fewer than ctx->multi_tiles
-// such tiles, since then none of the separate launches would fill the chip.
+// bucket 12 too when it has fewer than ctx->multi_tiles tiles, too few to
+// keep the chip busy in a launch of its own.
 struct GroupPlan {
   struct Entry {
     GroupKey key;       // the launch group (rb = the bucket the tables are padded to)
@@ -794,23 +794,22 @@ GroupPlan plan_groups(dbl_ctx* ctx, const std::vector<Slot*>& slots, bool allow_
   }
   for (auto& kv : mixed) {
     std::map<int, size_t> per;  // tiles by bucket
-    size_t tot = 0;
     for (const Slot* s : kv.second) {
       const int mi = s->m >> s->level, t = mi / 32;
       per[s->op->host.levels[s->level].rb] += (size_t)t * t;
-      tot += (size_t)t * t;
     }
-    const bool all = tot < (size_t)ctx->multi_tiles;
+    // the buckets that share the launch
+    auto joins = [&](int rb) { return rb <= 8 || per[rb] < (size_t)ctx->multi_tiles; };
     int top = 0, nb = 0;
     for (auto& b : per)
-      if (all || b.first <= 8) {
+      if (joins(b.first)) {
         top = std::max(top, b.first);
         ++nb;
       }
     for (const Slot* s : kv.second) {
       const int rb = s->op->host.levels[s->level].rb;
       GroupPlan::Entry& en = P.e[s];
-      if (nb < 2 || !(all || rb <= 8) || !cgls_multi_bucket(top)) {
+      if (nb < 2 || !joins(rb) || !cgls_multi_bucket(top)) {
         tiled[en.key].push_back(s);  // a launch of its own bucket
         continue;
       }
@@ -1326,7 +1325,7 @@ int engine_step(dbl_ctx* ctx, std::vector<Slot*>& slots) {
       double b = 0.0;
       for (const Job& jj : first[g].jobs) b += job_bytes("cgls_p2", jj, g.prec);
       LaunchArgs la = kv.second;
-      tune_cgls_launch(ctx, 2, g.prec, g.sep, g.rb, la);
+      if (!g.multi) tune_cgls_launch(ctx, 2, g.prec, g.sep, g.rb, la);
       if ((rc = hip_check(ctx, timed(ctx, "cgls_p2", b, [&] {
                             return launch_cgls_p2(la, g.prec, g.sep, g.rb, g.H);
                           }),
@@ -1346,7 +1345,7 @@ int engine_step(dbl_ctx* ctx, std::vector<Slot*>& slots) {
         if (!q) continue;
         LaunchArgs la = it == 0 ? a1f[g] : a1[par][g];
         la.ntiles = p1[par][g].tiles_upto[q - 1];
-        tune_cgls_launch(ctx, 1, g.prec, g.sep, g.rb, la);
+        if (!g.multi) tune_cgls_launch(ctx, 1, g.prec, g.sep, g.rb, la);
         double b = 0.0;
         for (int jq = 0; jq < q; ++jq)
           b += job_bytes("cgls_p1", p1[par][g].jobs[jq], g.prec);
@@ -1364,7 +1363,7 @@ int engine_step(dbl_ctx* ctx, std::vector<Slot*>& slots) {
         if (!q) continue;
         LaunchArgs la = a2[par][g];
         la.ntiles = p2[par][g].tiles_upto[q - 1];
-        tune_cgls_launch(ctx, 2, g.prec, g.sep, g.rb, la);
+        if (!g.multi) tune_cgls_launch(ctx, 2, g.prec, g.sep, g.rb, la);
         double b = 0.0;
         for (int jq = 0; jq < q; ++jq)
           b += job_bytes("cgls_p2", p2[par][g].jobs[jq], g.prec);

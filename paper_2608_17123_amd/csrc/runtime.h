@@ -62,9 +62,10 @@ struct dbl_ctx {
   int stream_a = 1;
   int tile32 = 1;  // 32 x 32 tile CGLS kernels for separable operators (DBL_OPT_TILE32)
   // CGLS stage launches that mix radius buckets (DBL_OPT_MULTI_BUCKET): < 0
-  // off; else buckets up to 8 share a launch, and buckets up to 12 do too in
-  // a stage with fewer tile-kernel tiles than this
-  long long multi_tiles = 4096;
+  // off; else buckets up to 8 share a launch, and bucket 12 joins them when
+  // it has fewer tiles than this (3072: two rounds of the chip at 6 blocks
+  // per CU)
+  long long multi_tiles = 3072;
   // autotuned CGLS phase variants (dbl_autotune); empty: the built-in rule
   std::vector<TuneEntry> tune;
   size_t lds_limit = 65536;

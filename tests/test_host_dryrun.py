@@ -151,9 +151,9 @@ def test_autotune_launches_are_sound(dryrun):
                                         ("4096", "bf16")])
 def test_mixed_bucket_launches_are_sound(dryrun, multi, prec):
     """A batch of PSFs in buckets 2, 4, 8 and 12: the CGLS stages share
-    mixed-bucket launches (buckets up to 8 always; all of them in the small
-    stages with the default threshold), and every job in them passes the
-    tile kernel's audit for its own bucket."""
+    mixed-bucket launches (buckets up to 8 always; bucket 12 too when it has
+    fewer tiles than the threshold), and every job in them passes the tile
+    kernel's audit for its own bucket."""
     exe, out = dryrun
     kinds = [("g2", synth.gaussian_psf(0.6, 2)), ("g4", synth.gaussian_psf(1.2, 4)),
              ("g8", synth.gaussian_psf(2.5, 8)), ("g12", synth.gaussian_psf(3.5, 12))]
@@ -165,5 +165,5 @@ def test_mixed_bucket_launches_are_sound(dryrun, multi, prec):
     assert r.returncode == 0, r.stdout[-2000:]
     assert "violations 0" in r.stdout
     assert "launches k_cgls_p1_multi" in r.stdout and "launches k_cgls_p2_multi" in r.stdout
-    if multi == "0":  # bucket 12 launches apart when the threshold never admits it
+    if multi == "0":  # bucket 12 launches apart when the threshold admits none of it
         assert "launches k_cgls_p2_sep" in r.stdout
