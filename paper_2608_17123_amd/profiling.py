@@ -26,8 +26,8 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 # sources that decide the CGLS phase kernels' memory traffic
-TRAFFIC_SOURCES = ["kernels_solve.hip", "kernels_cgls_sep.hip", "phase.h", "stencil.h", "common.h",
-                   "launch.h"]
+TRAFFIC_SOURCES = ["kernels_solve.hip", "kernels_cgls_sep.hip", "kernels_cgls_multi.hip",
+                   "cgls_sep.h", "phase.h", "stencil.h", "common.h", "launch.h"]
 
 
 def source_hash(names=TRAFFIC_SOURCES):
