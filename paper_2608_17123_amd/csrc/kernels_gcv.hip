@@ -436,6 +436,20 @@ __global__ void __launch_bounds__(NTHREADS) k_gcv_data(const Job* __restrict__ j
   }
 }
 
+// 1 / d for d > 0 in the normal range: the hardware reciprocal (relative
+// error about 2^-23) refined by two Newton-Raphson steps r <- r + r (1 - d r),
+// each of which doubles the correct bits, so the result is within an ulp or
+// so of the rounded quotient; five instructions where IEEE division takes
+// about eleven.  The GCV sums are bound by these reciprocals (one per
+// frequency and parameter).
+__device__ __forceinline__ double recip_pos(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  double e = fma(-d, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-d, r, 1.0);
+  return fma(r, e, r);
+}
+
 // Per-thread view of the frequencies of one tile: at most Q per thread (4
 // for the 32 x 32 tiles of the multi-block kernels, 16 for one block over a
 // grid of up to 64 x 64).  Entry q is frequency threadIdx.x + q * NT of the
@@ -490,7 +504,7 @@ __device__ __forceinline__ void eval_freqs(const Job* job, const FreqRegs<Q>& f,
         const double nu = f.s[q];
         const double den = nu + gam * (1.0 - nu);
         if (den > 0.0) {
-          const double inv = 1.0 / den;
+          const double inv = recip_pos(den);
           const double y = (f.lp[q] + gam * f.e[q]) * inv;
           res += nu * y * y - 2.0 * f.lp[q] * y;
           tr += nu * inv;
@@ -504,7 +518,7 @@ __device__ __forceinline__ void eval_freqs(const Job* job, const FreqRegs<Q>& f,
     if (q < f.cnt) {
       const double den = f.s[q] + gam * f.lp[q];
       if (den > 0.0) {
-        const double inv = 1.0 / den;
+        const double inv = recip_pos(den);
         res += f.e[q] * inv * inv;
         tr += f.s[q] * inv;
       }
@@ -531,7 +545,7 @@ __device__ __forceinline__ void eval_freqs_multi(const Job* job, const FreqRegs<
       if (exact) {
         const double den = s + gam[g] * (1.0 - s);
         if (den > 0.0) {
-          const double inv = 1.0 / den;
+          const double inv = recip_pos(den);
           const double y = (lp + gam[g] * e) * inv;
           v[2 * g] += s * y * y - 2.0 * lp * y;
           v[2 * g + 1] += s * inv;
@@ -539,7 +553,7 @@ __device__ __forceinline__ void eval_freqs_multi(const Job* job, const FreqRegs<
       } else {
         const double den = s + gam[g] * lp;
         if (den > 0.0) {
-          const double inv = 1.0 / den;
+          const double inv = recip_pos(den);
           v[2 * g] += e * inv * inv;
           v[2 * g + 1] += s * inv;
         }
