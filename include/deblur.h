@@ -84,8 +84,12 @@ typedef enum { DBL_INNER_CGLS = 0, DBL_INNER_LSQR = 1 } dbl_inner;
  * Sec. 3): the dense level operator is formed on the device, A^T A v =
  * nu (A^T A + D^T D) v is solved in FP64 (rocSOLVER sygvd), and the GCV
  * function is evaluated from (nu, V^T A^T b, V^T D^T c, ||b||^2).  EXACT is
- * limited to n <= 4096 (DBL_ENOTSUP above) and needs about 3 n^2 doubles of
- * workspace (384 MB at n = 4096); AUTO picks EXACT when n <= 4096. */
+ * limited to n <= DBL_GCV_EXACT_MAX_N (a 128 x 128 level; DBL_ENOTSUP above)
+ * and needs about 3 n^2 doubles of workspace (384 MB at n = 4096, 6.4 GB at
+ * n = 16384) besides the eigensolver's own; AUTO picks EXACT when
+ * n <= DBL_GCV_AUTO_EXACT_N. */
+#define DBL_GCV_EXACT_MAX_N 16384
+#define DBL_GCV_AUTO_EXACT_N 4096
 typedef enum { DBL_GCV_AUTO = 0, DBL_GCV_EXACT = 1, DBL_GCV_SPECTRAL = 2 } dbl_gcv_mode;
 
 typedef struct dbl_ctx dbl_ctx;

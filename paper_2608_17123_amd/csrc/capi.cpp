@@ -691,9 +691,9 @@ int dbl_gcv(dbl_ctx* ctx, const dbl_op* op, int level, const dbl_sub* sub, const
   if (grid < 3 || grid > DBL_GCV_GRID_MAX) return set_err(ctx, DBL_EINVAL, "bad grid size");
   const int m = op->host.levels[level].m;
   const size_t n = (size_t)m * m;
-  if (mode == DBL_GCV_AUTO) mode = n <= 4096 ? DBL_GCV_EXACT : DBL_GCV_SPECTRAL;
-  if (mode == DBL_GCV_EXACT && n > 4096)
-    return set_err(ctx, DBL_ENOTSUP, "EXACT GCV is limited to n <= 4096");
+  if (mode == DBL_GCV_AUTO) mode = n <= DBL_GCV_AUTO_EXACT_N ? DBL_GCV_EXACT : DBL_GCV_SPECTRAL;
+  if (mode == DBL_GCV_EXACT && n > DBL_GCV_EXACT_MAX_N)
+    return set_err(ctx, DBL_ENOTSUP, "EXACT GCV is limited to n <= 16384");
   if (ctx->device < 0) return set_err(ctx, DBL_EDEVICE, "context has no device");
   (void)hipSetDevice(ctx->device);
   if (int rc0 = stage_checkpoint(ctx)) return rc0;

@@ -1,5 +1,5 @@
 // GCV driver (Sec. 3): spectral (DCT surrogate) or exact (generalised
-// eigendecomposition of the pencil, n <= 4096) data, grid search and Brent
+// eigendecomposition of the pencil, n <= 16384) data, grid search and Brent
 // refinement for a batch of subproblems; writes gamma and sqrt(gamma) into
 // each scalar block.
 #include <rocblas/rocblas.h>
@@ -99,7 +99,7 @@ int blas_check(dbl_ctx* ctx, rocblas_status st, const char* what) {
                                        std::to_string((int)st));
 }
 
-// EXACT tier data of one request (n = m^2 <= 4096), in FP64 on the device:
+// EXACT tier data of one request (n = m^2 <= DBL_GCV_EXACT_MAX_N), in FP64 on the device:
 //   Ad  = A^(level) applied to every unit vector (the library's own stencil
 //         kernel, FP64 tables) -- the dense level operator;
 //   K   = Ad^T Ad (rocBLAS syrk), M = K + D^T D (D = diag(w) L or L);
@@ -225,8 +225,8 @@ int gcv_run(dbl_ctx* ctx, std::vector<GcvReq>& reqs) {
   int rc = DBL_OK;
   for (auto& r : reqs) {
     const int m = r.op->host.levels[r.level].m;
-    if (r.mode == DBL_GCV_EXACT && m * m > 4096)
-      return set_err(ctx, DBL_ENOTSUP, "EXACT GCV needs n <= 4096; use SPECTRAL");
+    if (r.mode == DBL_GCV_EXACT && m * m > DBL_GCV_EXACT_MAX_N)
+      return set_err(ctx, DBL_ENOTSUP, "EXACT GCV needs n <= 16384; use SPECTRAL");
   }
   if ((rc = ensure_symbols(ctx, reqs))) return rc;
   std::vector<Job> base(reqs.size());

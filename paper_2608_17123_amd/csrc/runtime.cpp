@@ -1174,8 +1174,9 @@ int engine_step(dbl_ctx* ctx, std::vector<Slot*>& slots) {
       g.bh_valid = s->bh_valid;
       g.grid = s->opts.gcv_grid;
       const int n = (s->m >> s->level) * (s->m >> s->level);
-      g.mode = s->opts.gcv_mode == DBL_GCV_AUTO ? (n <= 4096 ? DBL_GCV_EXACT : DBL_GCV_SPECTRAL)
-                                                : s->opts.gcv_mode;
+      g.mode = s->opts.gcv_mode != DBL_GCV_AUTO ? s->opts.gcv_mode
+               : n <= DBL_GCV_AUTO_EXACT_N         ? DBL_GCV_EXACT
+                                                   : DBL_GCV_SPECTRAL;
       greqs.push_back(g);
       s->bh_valid = g.mode == DBL_GCV_SPECTRAL;  // the exact tier reuses the DCT buffer
     }
