@@ -35,7 +35,8 @@ Printed: one JSON line with
 
 --calib-copy runs only a plain 1 GiB device-to-device copy (three times): the
 known-size kernel that scales the FETCH_SIZE / WRITE_SIZE counters.
---profile-run runs one batch of the workload and nothing else (for rocprofv3).
+--profile-run runs one batch of the workload and nothing else (for rocprofv3);
+--operators-only and --serve-only run only those legs.
 """
 import argparse
 import json
@@ -75,6 +76,8 @@ def parse():
     p.add_argument("--calib-copy", action="store_true")
     p.add_argument("--operators-only", action="store_true",
                    help="run only the standalone operator leg (for rocprofv3)")
+    p.add_argument("--serve-only", action="store_true",
+                   help="run only the serving leg (for rocprofv3)")
     p.add_argument("--profile-run", action="store_true")
     p.add_argument("--precision", default="f32", choices=["f32", "bf16", "f64"],
                    help="vector storage: FP32, BF16 CGLS state with FP32 arithmetic, or FP64")
@@ -366,6 +369,12 @@ def main():
         D.dbl_set_option(ctx, D.DBL_OPT_MULTI_BUCKET, args.multi_tiles)
     if args.operators_only:
         print(json.dumps({"operators": operator_leg(D, torch, ctx)}))
+        return
+    if args.serve_only:
+        rates = [float(r) for r in args.serve_rates.split(",") if r]
+        print(json.dumps({"serving": serve_leg(D, torch, ctx, rates, args.serve_requests,
+                                               {"precision": D.DBL_F32, "gcv_mode": "spectral",
+                                                "inner_solver": args.inner})}))
         return
     prec = {"f32": D.DBL_F32, "bf16": D.DBL_BF16, "f64": D.DBL_F64}[args.precision]
     tune = None

@@ -549,7 +549,7 @@ int krylov_entry(dbl_ctx* ctx, const dbl_op* op, int level, const dbl_sub* sub, 
     if ((rc = Ls.upload(ctx, la))) return rc;
     const double bytes = job_bytes("cgls_small", js, prec);
     if ((rc = hip_check(ctx, timed(ctx, "cgls_small", bytes, [&] {
-                          return launch_cgls_small(la, prec, rb, m, small);
+                          return launch_cgls_small(la, prec, small_halo(L), m, small, !L.sep);
                         }),
                         "cgls small")))
       return rc;

@@ -87,15 +87,17 @@ struct LevelOp {
 };
 
 // One-block CGLS for small levels (kernels_small.hip): a block of
-// small_nt(m, esz) threads keeps a whole level (separable operator) in LDS
-// for all iterations.  Byte layout of its dynamic LDS, shared by the host
-// (launch size, eligibility) and the kernel:
+// small_nt(m, esz) threads keeps a whole level in LDS for all iterations.
+// Byte layout of its dynamic LDS, shared by the host (launch size,
+// eligibility) and the kernel:
 //   XP, XR : p and r1 with a periodic halo of H, (m+2H) x (m+2H+1) each
-//   Z      : pass-A scratch (m+2H) x (m+1)
+//   Z      : pass-A scratch (m+2H) x (m+1) (separable operator), or the
+//            staged interior taps (general operator)
 //   S, Q1  : n each (s, then q1 = A p or the gradient part of s)
 //   R2     : n_L (gradient-space residual)
 //   W      : n_L IRLS weights, when they fit (else read from global memory)
-//   TB     : the level's four 1-D tap tables (tab_elems values)
+//   TB     : the level's four 1-D tap tables (tab_elems values; none for a
+//            general operator, whose class lists are read from its tables)
 constexpr int SMALL_MAX_M = 64;
 // threads of the one-block CGLS for an m x m level with esz-byte elements:
 // one pixel per thread up to m = 16, then 512 threads (at 1024 the kernel's
@@ -108,13 +110,19 @@ struct SmallLds {
   size_t halo, z, s, q1, r2, w, tb, total;  // byte offsets of the regions and the total
 };
 __host__ __device__ inline size_t align16(size_t b) { return (b + 15) & ~size_t(15); }
-__host__ __device__ inline SmallLds small_lds(int m, int H, int esz, bool wlds, int tab_elems) {
+// gen: a general (2-D tap list) operator: no pass-A scratch; Z holds the
+// interior class's taps of the forward and the adjoint table, staged as
+// (tile offset, value) pairs, at most (2H + 1)^2 each (small_gen_taps).
+__host__ __device__ constexpr int small_gen_taps(int H) { return (2 * H + 1) * (2 * H + 1); }
+__host__ __device__ inline SmallLds small_lds(int m, int H, int esz, bool wlds, int tab_elems,
+                                              bool gen = false) {
   SmallLds L;
   L.E = m + 2 * H;
   L.ld = L.E + 1;
   L.halo = align16((size_t)L.E * L.ld * esz);
   L.z = 2 * L.halo;
-  L.s = L.z + align16((size_t)L.E * (m + 1) * esz);
+  L.s = L.z + (gen ? align16((size_t)2 * small_gen_taps(H) * (4 + esz))
+                   : align16((size_t)L.E * (m + 1) * esz));
   L.q1 = L.s + align16((size_t)m * m * esz);
   L.r2 = L.q1 + align16((size_t)m * m * esz);
   L.w = L.r2 + align16((size_t)2 * m * (m - 1) * esz);

@@ -28,6 +28,12 @@ inline int bucket_index(int rb) {
     if (RB_BUCKETS[k] == rb) return k;
   return -1;
 }
+// The smallest bucket >= R (-1 above the largest).
+inline int bucket_above(int R) {
+  for (int k = 0; k < NBUCKETS; ++k)
+    if (R <= RB_BUCKETS[k]) return RB_BUCKETS[k];
+  return -1;
+}
 
 struct Table2DHost {
   int R0 = 0, R1 = 0, St0 = 0, Sb0 = 0, St1 = 0, Sb1 = 0, rows0 = 1, rows1 = 1;

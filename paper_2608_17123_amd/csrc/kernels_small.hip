@@ -4,15 +4,19 @@
 // and on a coarse grid (m <= 64) each launch is a handful of blocks whose
 // time is dominated by the launch itself and by the memory round trips that
 // carry partial sums from one launch to the next.  Here one block owns a
-// whole level whose operator is separable: p and r1 (both with a periodic
-// halo), s, q1, r2 and the level's 1-D tap tables live in LDS, x lives in
+// whole level: p and r1 (both with a periodic halo), s, q1, r2 and the
+// level's 1-D tap tables (separable operator) live in LDS, x lives in
 // registers, the IRLS weights w are staged in LDS when they fit (else read
 // from global memory, where they stay cache resident), and all K_in
 // iterations of the CGLS recurrence on the augmented system of eq.
 // (augmented) run in one launch with block-level FP64 reductions.  The
 // arithmetic of every element is the tiled kernels' (same products, same
 // FP32/FP64 roundings); only the order of the FP64 norm summations differs.
-// Levels with a general (non-separable) operator use the tiled path.
+// A general (non-separable) operator (GEN; levels up to 32 x 32) convolves
+// each pixel over its class's 2-D tap list in list order, as the tiled
+// kernels do: the interior class's lists (forward and adjoint) are staged in
+// LDS as (offset, value) pairs, the seam and boundary classes are read from
+// the tables, where they stay cache resident.
 //
 // Job fields: m, op, flags (F_IRLS, F_SHIFT, F_SB, F_HIST, F_WLDS),
 // scal[S_SQRTG], v[V_B] = b, v[V_W] = w, v[V_C1] / v[V_C2] = c (MM: c1;
@@ -32,7 +36,7 @@ template <typename T> __device__ __forceinline__ T* vq(const Job* j, int k) {
 }  // namespace
 
 // M: the level size (every job of a launch has m = M); NT threads.
-template <typename T, int RB, int M>
+template <typename T, int RB, int M, bool GEN>
 __global__ void __launch_bounds__(small_nt(M, sizeof(T))) k_cgls_small(const Job* __restrict__ jobs,
                                                                        const uint32_t* __restrict__ tiles) {
   constexpr int NT = small_nt(M, sizeof(T));
@@ -50,7 +54,8 @@ __global__ void __launch_bounds__(small_nt(M, sizeof(T))) k_cgls_small(const Job
   const bool wl = irls && (fl & F_WLDS);
   const int trows[4] = {op.f0.rows, op.f1.rows, op.a0.rows, op.a1.rows};
   const SmallLds LL =
-      small_lds(m, H, (int)sizeof(T), wl, (trows[0] + trows[1] + trows[2] + trows[3]) * NTAP);
+      small_lds(m, H, (int)sizeof(T), wl, GEN ? 0 : (trows[0] + trows[1] + trows[2] + trows[3]) * NTAP,
+                GEN);
   T* XP = reinterpret_cast<T*>(smem);
   T* XR = reinterpret_cast<T*>(smem + LL.halo);
   T* Z = reinterpret_cast<T*>(smem + LL.z);
@@ -67,9 +72,28 @@ __global__ void __launch_bounds__(small_nt(M, sizeof(T))) k_cgls_small(const Job
   const T* __restrict__ c2 = vq<T>(job, V_C2);
   const int K = job->i0;
 
-  // the level's tap tables, copied to LDS once
+  // the level's tap tables, copied to LDS once (separable operator), or the
+  // interior class's 2-D tap lists as (offset into the halo'd buffers, value)
   Table1D tab[4] = {op.f0, op.f1, op.a0, op.a1};
-  {
+  constexpr int GT = small_gen_taps(H);
+  int* g_off = reinterpret_cast<int*>(Z);    // [2][GT]: forward, adjoint
+  T* g_val = reinterpret_cast<T*>(g_off + 2 * GT);
+  int g_cls[2] = {0, 0}, g_n[2] = {0, 0};
+  if constexpr (GEN) {
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const Table2D& tb = t ? op.a2 : op.f2;
+      const T* vals = taps2<T>(tb);
+      g_cls[t] = tb.St0 + tb.St1 * tb.rows0;
+      const int b = tb.off[g_cls[t]];
+      g_n[t] = tb.off[g_cls[t] + 1] - b;
+      for (int k = tid; k < g_n[t]; k += NT) {
+        const short2 e = tb.e[b + k];
+        g_off[t * GT + k] = e.x * ld + e.y;  // rows = axis 0 (e.x), columns = axis 1 (e.y)
+        g_val[t * GT + k] = vals[b + k];
+      }
+    }
+  } else {
     int off = 0;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
@@ -113,10 +137,47 @@ __global__ void __launch_bounds__(small_nt(M, sizeof(T))) k_cgls_small(const Job
     }
   };
   auto conv = [&](const T* X, bool adj, auto epi) {
-    // outputs per item: enough items for every thread of the block
-    constexpr int V = 2;
-    sep_tile<T, RB, NT, V, false>(X, H, Z, adj ? tab[2] : tab[0], adj ? tab[3] : tab[1], 0, 0,
-                                  m, m, m, epi);
+    if constexpr (GEN) {
+      // every pixel over its class's tap list, in list order: first all of
+      // the thread's pixels over the interior list, taps outermost (one
+      // staged offset and value per tap, the pixels' sums independent), then
+      // the seam and boundary pixels again over their own lists (their
+      // interior-list sums read the halo'd buffers in range and are dropped)
+      const Table2D& tb = adj ? op.a2 : op.f2;
+      const int t = adj ? 1 : 0;
+      const T* __restrict__ vals = taps2<T>(tb);
+      int base[XPT];
+      T acc[XPT];
+#pragma unroll
+      for (int u = 0; u < XPT; ++u) {
+        const int o = tid + u * NT;
+        base[u] = at(o % m + H, o / m + H);
+        acc[u] = T(0);
+      }
+      for (int k = 0; k < g_n[t]; ++k) {
+        const int off = g_off[t * GT + k];
+        const T v = g_val[t * GT + k];
+#pragma unroll
+        for (int u = 0; u < XPT; ++u) acc[u] = fma(v, X[base[u] + off], acc[u]);
+      }
+      for_px([&](int u, int, int i, int j) {
+        const int cls = class_of(i, m, tb.St0, tb.Sb0) + class_of(j, m, tb.St1, tb.Sb1) * tb.rows0;
+        if (cls != g_cls[t]) {
+          T a = T(0);
+          for (int k = tb.off[cls]; k < tb.off[cls + 1]; ++k) {
+            const short2 e = tb.e[k];
+            a = fma(vals[k], X[base[u] + e.x * ld + e.y], a);
+          }
+          acc[u] = a;
+        }
+        epi(i, j, acc[u]);
+      });
+    } else {
+      // outputs per item: enough items for every thread of the block
+      constexpr int V = 2;
+      sep_tile<T, RB, NT, V, false>(X, H, Z, adj ? tab[2] : tab[0], adj ? tab[3] : tab[1], 0, 0,
+                                    m, m, m, epi);
+    }
   };
   auto wgt = [&](int k) -> double {
     if (!irls) return 1.0;
@@ -253,18 +314,23 @@ __global__ void __launch_bounds__(small_nt(M, sizeof(T))) k_cgls_small(const Job
 }
 
 // Dynamic LDS of the one-block CGLS for a level with a separable operator
-// (1-D tables of `tab_rows` rows in total, padded to radius rb), 0 when the
+// (1-D tables of `tab_rows` rows in total, padded to radius rb) or, with
+// `gen`, a general operator of radius <= rb (tab_rows unused), 0 when the
 // level cannot run there.  IRLS subproblems stage their weights in LDS when
 // that still fits (*wlds = 1).
 size_t small_cgls_lds(int m, int precision, int rb, int tab_rows, bool irls, size_t limit,
-                      int* wlds) {
+                      int* wlds, bool gen) {
   *wlds = 0;
   if (m != 8 && m != 16 && m != 32 && !(m == 64 && precision != 1)) return 0;
-  const int esz = precision == 1 ? 8 : 4, te = tab_rows * (2 * rb + 1);
-  const size_t base = small_lds(m, rb, esz, false, te).total;
+  // a general operator's seam and boundary pixels read their lists from
+  // memory; at 64 x 64 that made the one-block kernel slower than the tiled
+  // phases (measured), up to 32 x 32 twice as fast
+  if (gen && m > 32) return 0;
+  const int esz = precision == 1 ? 8 : 4, te = gen ? 0 : tab_rows * (2 * rb + 1);
+  const size_t base = small_lds(m, rb, esz, false, te, gen).total;
   if (base > limit) return 0;
   if (irls) {
-    const size_t withw = small_lds(m, rb, esz, true, te).total;
+    const size_t withw = small_lds(m, rb, esz, true, te, gen).total;
     if (withw <= limit) {
       *wlds = 1;
       return withw;
@@ -276,11 +342,15 @@ size_t small_cgls_lds(int m, int precision, int rb, int tab_rows, bool irls, siz
 namespace {
 
 template <typename T, int M>
-hipError_t launch_small_m(const LaunchArgs& la, int rb, size_t lds) {
+hipError_t launch_small_m(const LaunchArgs& la, int rb, size_t lds, bool gen) {
   constexpr int NT = small_nt(M, sizeof(T));
 #define SMALL_CASE(R)                                                                      \
-  hipLaunchKernelGGL((k_cgls_small<T, R, M>), dim3(la.ntiles), dim3(NT), lds, la.stream, \
-                     la.jobs, la.tiles)
+  if (gen)                                                                                 \
+    hipLaunchKernelGGL((k_cgls_small<T, R, M, true>), dim3(la.ntiles), dim3(NT), lds,      \
+                       la.stream, la.jobs, la.tiles);                                     \
+  else                                                                                     \
+    hipLaunchKernelGGL((k_cgls_small<T, R, M, false>), dim3(la.ntiles), dim3(NT), lds,     \
+                       la.stream, la.jobs, la.tiles)
   switch (rb) {
     case 2: SMALL_CASE(2); break;
     case 4: SMALL_CASE(4); break;
@@ -294,13 +364,13 @@ hipError_t launch_small_m(const LaunchArgs& la, int rb, size_t lds) {
 }
 
 template <typename T>
-hipError_t launch_small_t(const LaunchArgs& la, int rb, int m, size_t lds) {
+hipError_t launch_small_t(const LaunchArgs& la, int rb, int m, size_t lds, bool gen) {
   switch (m) {
-    case 8: return launch_small_m<T, 8>(la, rb, lds);
-    case 16: return launch_small_m<T, 16>(la, rb, lds);
-    case 32: return launch_small_m<T, 32>(la, rb, lds);
+    case 8: return launch_small_m<T, 8>(la, rb, lds, gen);
+    case 16: return launch_small_m<T, 16>(la, rb, lds, gen);
+    case 32: return launch_small_m<T, 32>(la, rb, lds, gen);
     case 64:  // an FP64 level of 64 x 64 does not fit in LDS
-      if constexpr (sizeof(T) == 4) return launch_small_m<T, 64>(la, rb, lds);
+      if constexpr (sizeof(T) == 4) return launch_small_m<T, 64>(la, rb, lds, gen);
       return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
@@ -308,9 +378,10 @@ hipError_t launch_small_t(const LaunchArgs& la, int rb, int m, size_t lds) {
 
 }  // namespace
 
-hipError_t launch_cgls_small(const LaunchArgs& la, int precision, int rb, int m, size_t lds) {
-  const hipError_t e = precision == 1 ? launch_small_t<double>(la, rb, m, lds)
-                                      : launch_small_t<float>(la, rb, m, lds);
+hipError_t launch_cgls_small(const LaunchArgs& la, int precision, int rb, int m, size_t lds,
+                             bool gen) {
+  const hipError_t e = precision == 1 ? launch_small_t<double>(la, rb, m, lds, gen)
+                                      : launch_small_t<float>(la, rb, m, lds, gen);
   if (e != hipSuccess) return e;
   return hipGetLastError();
 }

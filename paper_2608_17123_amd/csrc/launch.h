@@ -81,12 +81,14 @@ hipError_t launch_lsqr_init(const LaunchArgs& la, int precision);
 hipError_t launch_lsqr_a(const LaunchArgs& la, int precision, int sep, int rb, int H);
 hipError_t launch_lsqr_b(const LaunchArgs& la, int precision, int sep, int rb, int H);
 hipError_t launch_lsqr_fin(const LaunchArgs& la, int precision);
-// One-block CGLS (kernels_small.hip): one block per job, all iterations, for
-// levels with a separable operator.  Every job of a launch has m x m grids,
-// m in {8, 16, 32, 64}.
+// One-block CGLS (kernels_small.hip): one block per job, all iterations.
+// Every job of a launch has m x m grids, m in {8, 16, 32, 64}, and operators
+// of one kind: separable with tables padded to bucket rb, or (gen) general
+// with radius <= rb (rb then only sets the halo).
 size_t small_cgls_lds(int m, int precision, int rb, int tab_rows, bool irls, size_t limit,
-                      int* wlds);
-hipError_t launch_cgls_small(const LaunchArgs& la, int precision, int rb, int m, size_t lds);
+                      int* wlds, bool gen = false);
+hipError_t launch_cgls_small(const LaunchArgs& la, int precision, int rb, int m, size_t lds,
+                             bool gen);
 
 // aux modes (Job::i0)
 enum AuxMode : int {

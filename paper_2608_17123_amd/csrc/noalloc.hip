@@ -243,7 +243,8 @@ extern "C" int dbl_cgls_noalloc(dbl_ctx* ctx, const dbl_op* op, int level, const
   };
   if ((rc = hip_check(ctx, launch_set_gamma(la_for(k_gamma, 1, d_one)), "set gamma"))) return rc;
   if (k_small >= 0) {
-    if ((rc = hip_check(ctx, launch_cgls_small(la_for(k_small, 1, d_one), prec, rb, m, small),
+    if ((rc = hip_check(ctx, launch_cgls_small(la_for(k_small, 1, d_one), prec, small_halo(L), m,
+                                               small, !L.sep),
                         "cgls small")))
       return rc;
   } else {

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstring>
 #include <stdexcept>
+#include <tuple>
 
 namespace dbl {
 
@@ -692,10 +693,13 @@ size_t small_lds_bytes(const dbl_ctx* ctx, const dbl_op* op, int level, bool irl
   *wlds = 0;
   if (!ctx->small_cgls) return 0;
   const LevelHost& L = op->host.levels[level];
-  if (!L.sep) return 0;
+  if (!L.sep) return small_cgls_lds(L.m, op->precision, small_halo(L), 0, irls, ctx->lds_limit,
+                                    wlds, true);
   const int rows = L.f0.rows + L.f1.rows + L.a0.rows + L.a1.rows;
   return small_cgls_lds(L.m, op->precision, L.rb, rows, irls, ctx->lds_limit, wlds);
 }
+
+int small_halo(const LevelHost& L) { return L.sep ? L.rb : bucket_above(L.R); }
 
 // -------------------------------------------------------------- engine ----
 
@@ -777,7 +781,7 @@ GroupPlan plan_groups(dbl_ctx* ctx, const std::vector<Slot*>& slots, bool allow_
   GroupPlan P;
   // one-block candidates by (precision, m): one bucket for all when every
   // member still fits in LDS with it
-  std::map<std::pair<int, int>, std::vector<const Slot*>> small;
+  std::map<std::tuple<int, int, int>, std::vector<const Slot*>> small;  // (prec, m, sep)
   std::map<GroupKey, std::vector<const Slot*>> tiled;
   std::map<int, std::vector<const Slot*>> mixed;  // mixed-launch candidates by precision
   multi = multi && ctx->multi_tiles >= 0 && ctx->tile32;
@@ -788,7 +792,7 @@ GroupPlan plan_groups(dbl_ctx* ctx, const std::vector<Slot*>& slots, bool allow_
     if (allow_small)
       en.small_lds = small_lds_bytes(ctx, s->op, lv, s->solver == DBL_IRLS, &en.wlds);
     P.e[s] = en;
-    if (en.small_lds) small[{s->prec, L.m}].push_back(s);
+    if (en.small_lds) small[{s->prec, L.m, L.sep ? 1 : 0}].push_back(s);
     else if (multi && L.sep && L.m >= 32 && L.rb <= 12) mixed[s->prec].push_back(s);
     else tiled[en.key].push_back(s);
   }
@@ -820,8 +824,9 @@ GroupPlan plan_groups(dbl_ctx* ctx, const std::vector<Slot*>& slots, bool allow_
     }
   }
   for (auto& kv : small) {
+    const bool gen = std::get<2>(kv.first) == 0;
     int rbt = 0;
-    for (const Slot* s : kv.second) rbt = std::max(rbt, s->op->host.levels[s->level].rb);
+    for (const Slot* s : kv.second) rbt = std::max(rbt, small_halo(s->op->host.levels[s->level]));
     std::vector<std::pair<size_t, int>> got;
     bool ok = true;
     for (const Slot* s : kv.second) {
@@ -829,7 +834,7 @@ GroupPlan plan_groups(dbl_ctx* ctx, const std::vector<Slot*>& slots, bool allow_
       int wl = 0;
       const size_t b =
           small_cgls_lds(L.m, s->prec, rbt, L.f0.rows + L.f1.rows + L.a0.rows + L.a1.rows,
-                         s->solver == DBL_IRLS, ctx->lds_limit, &wl);
+                         s->solver == DBL_IRLS, ctx->lds_limit, &wl, gen);
       if (!b) ok = false;
       got.push_back({b, wl});
     }
@@ -1300,7 +1305,7 @@ int engine_step(dbl_ctx* ctx, std::vector<Slot*>& slots) {
       for (const Job& jj : kv.second.jobs) b += job_bytes("cgls_small", jj, g.prec);
       const size_t lds = smallB[kv.first];
       if ((rc = hip_check(ctx, timed(ctx, "cgls_small", b, [&] {
-                            return launch_cgls_small(la, g.prec, g.rb, mm, lds);
+                            return launch_cgls_small(la, g.prec, g.rb, mm, lds, !g.sep);
                           }),
                           "cgls small")))
         return rc;

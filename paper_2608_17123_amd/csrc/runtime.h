@@ -156,6 +156,9 @@ const LevelOp* op_dev(const dbl_op* op, int level, int rb);
 // Dynamic LDS of the one-block CGLS at `level` when this context runs that
 // level with it, else 0; *wlds = 1 when IRLS weights are staged in LDS.
 size_t small_lds_bytes(const dbl_ctx* ctx, const dbl_op* op, int level, bool irls, int* wlds);
+// Halo (radius bucket) of the one-block CGLS on a level: the separable
+// tables' bucket, or the smallest bucket above a general operator's radius.
+int small_halo(const LevelHost& L);
 
 // Algorithmic bytes of one job (each operand read or written once).
 double job_bytes(const char* kernel, const Job& j, int precision);

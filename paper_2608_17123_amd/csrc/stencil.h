@@ -328,7 +328,8 @@ __device__ __forceinline__ void gen_tile(const T* __restrict__ Xs, int H, const 
       const int o = threadIdx.x + u * NT;
       int i, j;
       tile_ij(o, TI, i, j);
-      base[u] = o < np ? (j + H) * LXC + (i + H) : 0;  // a pixel past the tile reads (H, H)
+      // a slot past the tile reads around (H, H): every tap offset stays inside
+      base[u] = o < np ? (j + H) * LXC + (i + H) : H * LXC + H;
       acc[u] = T(0);
     }
     for (int k = 0; k < n; ++k) {

@@ -172,6 +172,45 @@ void check_sep32(const std::string& k, int jb, const Job& j, int rb, size_t esz,
     fail(k, jb, "dynamic LDS " + std::to_string(shmem) + " < " + std::to_string(e * esz));
 }
 
+// The one-block CGLS: a separable operator with tables padded to the kernel's
+// halo RB, or (gen) a general operator of radius <= RB whose interior class
+// lists fit the staging area; the dynamic LDS covers the kernel's layout.
+void check_small(const std::string& k, int jb, const Job& j, int RB, size_t esz, bool gen,
+                 size_t shmem) {
+  if (!j.op || !owner(j.op, sizeof(dbl::LevelOp))) return;
+  const dbl::LevelOp& op = *j.op;
+  if (gen != !op.sep) {
+    fail(k, jb, gen ? "general-operator kernel on a separable level"
+                    : "separable kernel on a general level");
+    return;
+  }
+  int tab_elems = 0;
+  if (gen) {
+    if (op.R > RB) fail(k, jb, "operator radius " + std::to_string(op.R) + " > halo " +
+                                   std::to_string(RB));
+    const dbl::Table2D* ts[2] = {&op.f2, &op.a2};
+    for (const dbl::Table2D* t : ts) {
+      if (t->R0 > RB || t->R1 > RB) fail(k, jb, "table radius above the halo");
+      const size_t ncls = (size_t)t->rows0 * t->rows1;
+      if (!owner(t->off, (ncls + 1) * 4)) continue;
+      const int cls = t->St0 + t->St1 * t->rows0;
+      if (t->off[cls + 1] - t->off[cls] > dbl::small_gen_taps(RB))
+        fail(k, jb, "interior tap list longer than the staging area");
+    }
+  } else {
+    const dbl::Table1D* ts[4] = {&op.f0, &op.f1, &op.a0, &op.a1};
+    for (const dbl::Table1D* t : ts) {
+      if (t->R != RB) fail(k, jb, "table radius " + std::to_string(t->R) + " != halo " +
+                                      std::to_string(RB));
+      tab_elems += t->rows * (2 * RB + 1);
+    }
+  }
+  const bool wl = j.flags & dbl::F_WLDS;
+  const size_t need_lds = dbl::small_lds(j.m, RB, (int)esz, wl, tab_elems, gen).total;
+  if (shmem < need_lds)
+    fail(k, jb, "dynamic LDS " + std::to_string(shmem) + " < " + std::to_string(need_lds));
+}
+
 // The mixed-bucket tile kernels: every job's tables are padded to a bucket
 // of its own, one the kernel has a body for (2, 4, 8, 12 up to its RBMAX),
 // and each job then meets the 32 x 32 tile kernel's conditions for that
@@ -303,9 +342,10 @@ void audit(const void* func, dim3 grid, dim3 block, void** args, size_t shmem) {
       }
     } else if (fam == "k_cgls_small") {
       const size_t T = tsize(ta[0]);
-      const int M = std::atoi(ta[2].c_str());
+      const int RB = std::atoi(ta[1].c_str()), M = std::atoi(ta[2].c_str());
       if ((int)m != M) fail(fam, jb, "job size differs from the kernel's M");
       check_op(fam, jb, j, T == 8);
+      check_small(fam, jb, j, RB, T, ta.size() > 3 && ta[3] == "true", shmem);
       need(fam, jb, "V_X", v(dbl::V_X), n * T);
       need(fam, jb, "V_B", v(dbl::V_B), n * T);
       need(fam, jb, "scal", j.scal, dbl::NSCAL * 8);

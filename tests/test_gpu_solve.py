@@ -81,7 +81,8 @@ def kernel_for(psf, level):
                                                ("haar", 0, "motion")])
 def test_cgls_matches_oracle(ctx, prec, kind, wavelet, level, psf, small):
     """Levels with m <= 64 run the one-block kernel when `small` is 1 (FP32 up
-    to m = 64, FP64 up to m = 32) and the tiled phases when it is 0.  The
+    to m = 64, FP64 up to m = 32; general operators up to m = 32: the motion
+    case at level 2) and the tiled phases when it is 0.  The
     128 x 128 finest level with the 25 x 25 and 33 x 33 kernels runs the
     phases at radius buckets 12 and 16."""
     m, levels = 128, 3
