@@ -114,6 +114,76 @@ template <typename E> struct LaneOff {
 // as p = s + beta p is formed by its tile and again by each neighbour whose
 // halo holds it, and all of them must agree bit for bit (phase 2 recomputes
 // q2 from the stored p), whatever the compiler would contract in each copy.
+// So is every term of the FP64 norm sums (acc = fma(v, v, acc)): an FP64
+// square is inexact, and a sum the compiler fused in one kernel and not in
+// another would give alpha and beta a different last bit.
+
+// ------------------------------------------- general operator (2-D taps) --
+// A general (non-separable) level on the same tiles (GEN): the halo is a
+// radius bucket RB >= the operator's radius, and the convolution visits the
+// thread's own pixels (i, 2 wave + 8 u + lane / 32), u < PX -- the pixel set
+// and order of the generic kernels' gen_tile, so every sum and every partial
+// is the same.  The interior class's tap list is staged in LDS as (offset in
+// the haloed tile, value) behind the tile, GT entries at most; an interior
+// tile takes it taps-outermost over the thread's pixels, a tile that reaches
+// a seam or the grid's edge takes each pixel's class list from the table.
+template <int RB> struct GenTile {
+  static constexpr int GT = (2 * RB + 1) * (2 * RB + 1);  // interior taps at most
+  static constexpr int GTI = (GT + 1) & ~1;                // ints, keeping T aligned
+};
+
+template <typename T, int RB>
+__device__ __forceinline__ int stage_gen(int* g_off, T* g_val, const Table2D& tb) {
+  using G = SepTile<RB>;
+  const T* __restrict__ vals = taps2<T>(tb);
+  const int icls = tb.St0 + tb.St1 * tb.rows0;
+  const int b = tb.off[icls], n = tb.off[icls + 1] - b;
+  for (int k = threadIdx.x; k < n; k += NTHREADS) {
+    const short2 e = tb.e[b + k];
+    g_off[k] = e.x * G::LX + e.y;  // rows = axis 0 (e.x), columns = axis 1 (e.y)
+    g_val[k] = vals[b + k];
+  }
+  return n;
+}
+
+template <typename T, int RB, class Epi>
+__device__ __forceinline__ void gen_conv(const T* __restrict__ Xs, const int* __restrict__ g_off,
+                                        const T* __restrict__ g_val, int n, const Table2D& tb,
+                                        int row0, int col0, int m, int i, int jh, int wv,
+                                        Epi epi) {
+  using G = SepTile<RB>;
+  const bool inter = row0 >= tb.St0 && row0 + TE - 1 < m - tb.Sb0 && col0 >= tb.St1 &&
+                     col0 + TE - 1 < m - tb.Sb1;
+  int xo[PX];
+#pragma unroll
+  for (int u = 0; u < PX; ++u) xo[u] = (i + G::H) * G::LX + (2 * wv + 8 * u + jh + G::H);
+  if (inter) {
+    T a[PX];
+#pragma unroll
+    for (int u = 0; u < PX; ++u) a[u] = T(0);
+    for (int k = 0; k < n; ++k) {
+      const int off = g_off[k];
+      const T v = g_val[k];
+#pragma unroll
+      for (int u = 0; u < PX; ++u) a[u] = fma(v, Xs[xo[u] + off], a[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < PX; ++u) epi(u, a[u]);
+  } else {
+    const T* __restrict__ vals = taps2<T>(tb);
+#pragma unroll
+    for (int u = 0; u < PX; ++u) {
+      const int gj = col0 + 2 * wv + 8 * u + jh;
+      const int cls = class_of(row0 + i, m, tb.St0, tb.Sb0) + class_of(gj, m, tb.St1, tb.Sb1) * tb.rows0;
+      T a = T(0);
+      for (int k = tb.off[cls]; k < tb.off[cls + 1]; ++k) {
+        const short2 e = tb.e[k];
+        a = fma(vals[k], Xs[xo[u] + e.x * G::LX + e.y], a);
+      }
+      epi(u, a);
+    }
+  }
+}
 
 // ------------------------------------------------------ convolution passes --
 // Pass A along axis 0 for all NC haloed columns and the TE rows of the tile:
@@ -237,7 +307,7 @@ __device__ __forceinline__ T grad_entry(double sg, T a, T b, T w) {
 // the axis-0 differences at gi + gj (m - 1) (gi < m - 1), the axis-1
 // differences at nx + gi + gj m (gj < m - 1), nx = m (m - 1).  Uniform parts
 // (the column) are in elements, times the element size at the access.
-template <typename T, typename S, int RB>
+template <typename T, typename S, int RB, bool GEN = false>
 __device__ __forceinline__ void p1_sep_body(const Job* __restrict__ jobs,
                                             const uint32_t* __restrict__ tiles) {
   using G = SepTile<RB>;
@@ -249,6 +319,8 @@ __device__ __forceinline__ void p1_sep_body(const Job* __restrict__ jobs,
   T* Xs = reinterpret_cast<T*>(smem);
   T* Zs = Xs + G::XS;
   T* taps = Zs + G::ZS;
+  int* g_off = reinterpret_cast<int*>(Xs + G::XS);  // GEN: the interior list behind the tile
+  T* g_val = reinterpret_cast<T*>(g_off + GenTile<RB>::GTI);
   const Job* job; int ti, tj, tix;
   decode_tile(jobs, tiles, job, ti, tj, tix);
   const int m = job->m;
@@ -256,9 +328,14 @@ __device__ __forceinline__ void p1_sep_body(const Job* __restrict__ jobs,
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const GP<const LevelOp> op = gview(job->op);
-  const int St0 = op->f0.St, Sb0 = op->f0.Sb, St1 = op->f1.St, Sb1 = op->f1.Sb;
-  const GP<const T> tab0 = gtaps<T>(&op->f0), tab1 = gtaps<T>(&op->f1);
-  stage_taps<T, G::NTAP>(taps, tab0, St0, tab1, St1);
+  Table2D tg;
+  int gn = 0;
+  if constexpr (GEN) {
+    tg = job->op->f2;
+    gn = stage_gen<T, RB>(g_off, g_val, tg);
+  } else {
+    stage_taps<T, G::NTAP>(taps, gtaps<T>(&op->f0), op->f0.St, gtaps<T>(&op->f1), op->f1.St);
+  }
   const int flags = job->flags;
   const bool first = flags & F_FIRST, irls = flags & F_IRLS;
   const int nt = job->nti * job->ntj;
@@ -340,24 +417,34 @@ __device__ __forceinline__ void p1_sep_body(const Job* __restrict__ jobs,
     pb.st(oS.g, cg * ES, pc);
     if (dn) {
       const T qv = grad_entry<T, S>(sg, pc, Xs[xo + G::LX], wx[u]);
-      acc += (double)qv * (double)qv;
+      acc = fma((double)qv, (double)qv, acc);
     }
     if (rt) {
       const T qv = grad_entry<T, S>(sg, pc, Xs[xo + 1], wy[u]);
-      acc += (double)qv * (double)qv;
+      acc = fma((double)qv, (double)qv, acc);
     }
   }
 
   // q1 = A p
-  pass_a<T, RB>(Xs, Zs, taps, tab0, St0, Sb0, row0, m);
-  lds_barrier();
-  // pass-B outputs: lane offset i + CV (lane / 32) m of the uniform column cu
-  const uint32_t ob = (uint32_t)(i + jh * CV * m) * ES;
-  pass_b<T, RB>(Zs, taps + G::NTAP, tab1, St1, Sb1, col0, m, [&](int, int, int cu, T v) {
-    const T qv = rtv<S>(v);
-    q1.st(ob, ((uint32_t)(col0 + cu) * (uint32_t)m + row0) * ES, qv);
-    acc += (double)qv * (double)qv;
-  });
+  if constexpr (GEN) {
+    gen_conv<T, RB>(Xs, g_off, g_val, gn, tg, row0, col0, m, i, jh, wv, [&](int u, T v) {
+      const T qv = rtv<S>(v);
+      q1.st(oS.g, ((uint32_t)(col0 + 2 * wv + 8 * u) * (uint32_t)m + row0) * ES, qv);
+      acc = fma((double)qv, (double)qv, acc);
+    });
+  } else {
+    const int St0 = op->f0.St, Sb0 = op->f0.Sb, St1 = op->f1.St, Sb1 = op->f1.Sb;
+    const GP<const T> tab0 = gtaps<T>(&op->f0), tab1 = gtaps<T>(&op->f1);
+    pass_a<T, RB>(Xs, Zs, taps, tab0, St0, Sb0, row0, m);
+    lds_barrier();
+    // pass-B outputs: lane offset i + CV (lane / 32) m of the uniform column cu
+    const uint32_t ob = (uint32_t)(i + jh * CV * m) * ES;
+    pass_b<T, RB>(Zs, taps + G::NTAP, tab1, St1, Sb1, col0, m, [&](int, int, int cu, T v) {
+      const T qv = rtv<S>(v);
+      q1.st(ob, ((uint32_t)(col0 + cu) * (uint32_t)m + row0) * ES, qv);
+      acc = fma((double)qv, (double)qv, acc);
+    });
+  }
   double vv[1] = {acc};
   put_partials<1>(job->pw, tix, vv, red);
 }
@@ -365,7 +452,7 @@ __device__ __forceinline__ void p1_sep_body(const Job* __restrict__ jobs,
 // ------------------------------------------------------------------ phase 2 --
 // alpha = |s|^2 / |q|^2; x += alpha p; r -= alpha q; s = A^T r1 + sqrt(g) D^T r2;
 // |s|^2 and |r|^2 partials per tile.
-template <typename T, typename S, int RB>
+template <typename T, typename S, int RB, bool GEN = false>
 __device__ __forceinline__ void p2_sep_body(const Job* __restrict__ jobs,
                                             const uint32_t* __restrict__ tiles) {
   using G = SepTile<RB>;
@@ -376,7 +463,10 @@ __device__ __forceinline__ void p2_sep_body(const Job* __restrict__ jobs,
   T* Xs = reinterpret_cast<T*>(smem);
   T* Zs = Xs + G::XS;
   T* taps = Zs + G::ZS;
-  T* LTs = taps + 2 * G::NTAP;  // sqrt(g) D^T (w r2) of the tile, column-major
+  int* g_off = reinterpret_cast<int*>(Xs + G::XS);  // GEN: the interior list behind the tile
+  T* g_val = reinterpret_cast<T*>(g_off + GenTile<RB>::GTI);
+  // sqrt(g) D^T (w r2) of the tile, column-major
+  T* LTs = GEN ? g_val + GenTile<RB>::GT : taps + 2 * G::NTAP;
   const Job* job; int ti, tj, tix;
   decode_tile(jobs, tiles, job, ti, tj, tix);
   const int m = job->m;
@@ -384,9 +474,14 @@ __device__ __forceinline__ void p2_sep_body(const Job* __restrict__ jobs,
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const GP<const LevelOp> op = gview(job->op);
-  const int St0 = op->a0.St, Sb0 = op->a0.Sb, St1 = op->a1.St, Sb1 = op->a1.Sb;
-  const GP<const T> tab0 = gtaps<T>(&op->a0), tab1 = gtaps<T>(&op->a1);
-  stage_taps<T, G::NTAP>(taps, tab0, St0, tab1, St1);
+  Table2D tg;
+  int gn = 0;
+  if constexpr (GEN) {
+    tg = job->op->a2;
+    gn = stage_gen<T, RB>(g_off, g_val, tg);
+  } else {
+    stage_taps<T, G::NTAP>(taps, gtaps<T>(&op->a0), op->a0.St, gtaps<T>(&op->a1), op->a1.St);
+  }
   const int flags = job->flags;
   const bool first = flags & F_FIRST, irls = flags & F_IRLS;
   const int nt = job->nti * job->ntj;
@@ -441,7 +536,7 @@ __device__ __forceinline__ void p2_sep_body(const Job* __restrict__ jobs,
     const int jp = 2 * wv + 8 * u;
     const T rv = Xs[(i + G::H) * G::LX + jp + jh + G::H];
     r1b.st(oS.g, ((uint32_t)(col0 + jp) * (uint32_t)m + row0) * ES, rv);
-    accr += (double)rv * (double)rv;
+    accr = fma((double)rv, (double)rv, accr);
   }
   // gradient part, two pixels at a time: the entries qx(i-1,j), qx(i,j),
   // qy(i,j-1), qy(i,j) of r2 (and w), x, and p at the pixel and its four
@@ -507,13 +602,13 @@ __device__ __forceinline__ void p2_sep_body(const Job* __restrict__ jobs,
       if (up) lt += (double)wg[h][0] * (double)rn[0];
       if (dn) {
         r2b.st(oS.x, cx * ES, rn[1]);
-        accr += (double)rn[1] * (double)rn[1];
+        accr = fma((double)rn[1], (double)rn[1], accr);
         lt -= (double)wg[h][1] * (double)rn[1];
       }
       if (gj >= 1) lt += (double)wg[h][2] * (double)rn[2];
       if (gj < m - 1) {
         r2b.st(oS.g, (nx + cg) * ES, rn[3]);
-        accr += (double)rn[3] * (double)rn[3];
+        accr = fma((double)rn[3], (double)rn[3], accr);
         lt -= (double)wg[h][3] * (double)rn[3];
       }
       LTs[i + (jp + jh) * TE] = (T)(sg * lt);
@@ -523,14 +618,25 @@ __device__ __forceinline__ void p2_sep_body(const Job* __restrict__ jobs,
   lds_barrier();  // LT complete (the haloed tile was complete before)
 
   // s = A^T r1 + LT
-  pass_a<T, RB>(Xs, Zs, taps, tab0, St0, Sb0, row0, m);
-  lds_barrier();
-  const uint32_t ob = (uint32_t)(i + jh * CV * m) * ES;
-  pass_b<T, RB>(Zs, taps + G::NTAP, tab1, St1, Sb1, col0, m, [&](int r, int c, int cu, T v) {
-    const T sv = rtv<S>(v + LTs[r + c * TE]);
-    s.st(ob, ((uint32_t)(col0 + cu) * (uint32_t)m + row0) * ES, sv);
-    accs += (double)sv * (double)sv;
-  });
+  if constexpr (GEN) {
+    gen_conv<T, RB>(Xs, g_off, g_val, gn, tg, row0, col0, m, i, jh, wv, [&](int u, T v) {
+      const int jp = 2 * wv + 8 * u;
+      const T sv = rtv<S>(v + LTs[i + (jp + jh) * TE]);
+      s.st(oS.g, ((uint32_t)(col0 + jp) * (uint32_t)m + row0) * ES, sv);
+      accs = fma((double)sv, (double)sv, accs);
+    });
+  } else {
+    const int St0 = op->a0.St, Sb0 = op->a0.Sb, St1 = op->a1.St, Sb1 = op->a1.Sb;
+    const GP<const T> tab0 = gtaps<T>(&op->a0), tab1 = gtaps<T>(&op->a1);
+    pass_a<T, RB>(Xs, Zs, taps, tab0, St0, Sb0, row0, m);
+    lds_barrier();
+    const uint32_t ob = (uint32_t)(i + jh * CV * m) * ES;
+    pass_b<T, RB>(Zs, taps + G::NTAP, tab1, St1, Sb1, col0, m, [&](int r, int c, int cu, T v) {
+      const T sv = rtv<S>(v + LTs[r + c * TE]);
+      s.st(ob, ((uint32_t)(col0 + cu) * (uint32_t)m + row0) * ES, sv);
+      accs = fma((double)sv, (double)sv, accs);
+    });
+  }
   double vv[2] = {accs, accr};
   put_partials<2>(job->pw, tix, vv, red);
 }

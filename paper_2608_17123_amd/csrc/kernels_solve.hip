@@ -152,6 +152,9 @@ __device__ __forceinline__ void cgls_p1_body(const Job* __restrict__ jobs,
         [&](T a, T b, T c) { return rtv<S>(fma(c, b, a)); });
   }
   __syncthreads();
+  // FP64 norm sums as explicit fma terms (an FP64 square is inexact: the
+  // tile kernels form the same sums, and the compiler must not fuse them
+  // differently in one kernel than in the other)
   double acc = 0.0;
 #pragma unroll
   for (int u = 0; u < WPT; ++u) {
@@ -166,20 +169,20 @@ __device__ __forceinline__ void cgls_p1_body(const Job* __restrict__ jobs,
         const double d = ((double)Xs[xs_at<SEP>(i + 1, j, H, TI, TJ)] - (double)pc) * (double)v[0];
         const T qv = rtv<S>((T)(sg * d));
         stv(q2, gi + (size_t)gj * (m - 1), qv);
-        acc += (double)qv * (double)qv;
+        acc = fma((double)qv, (double)qv, acc);
       }
       if (gj < m - 1) {
         const double d = ((double)Xs[xs_at<SEP>(i, j + 1, H, TI, TJ)] - (double)pc) * (double)v[1];
         const T qv = rtv<S>((T)(sg * d));
         stv(q2, nx + g, qv);
-        acc += (double)qv * (double)qv;
+        acc = fma((double)qv, (double)qv, acc);
       }
     }
   }
   auto epi1 = [&](int i, int j, T v) {
     const T qv = rtv<S>(v);
     stv(q1, (i0 + i) + (size_t)(j0 + j) * m, qv);
-    acc += (double)qv * (double)qv;
+    acc = fma((double)qv, (double)qv, acc);
   };
   conv_tile<T, RB, SEP, decltype(epi1), NoHook, CV>(Xs, H, scratch, op, false, i0, j0, TI, TJ,
                                                     m, epi1);
@@ -261,7 +264,7 @@ __device__ __forceinline__ void cgls_p2_body(const Job* __restrict__ jobs,
     const size_t g = (i0 + i) + (size_t)(j0 + j) * m;
     const T rv = Xs[xs_at<SEP>(i, j, H, TI, TJ)];
     stv(r1b, g, rv);
-    accr += (double)rv * (double)rv;
+    accr = fma((double)rv, (double)rv, accr);
   }
   const size_t nx = (size_t)(m - 1) * m;
   // Gradient part: LT[i, j] = sqrt(g) (L^T (w r2_new))[i, j] for the tile,
@@ -305,13 +308,13 @@ __device__ __forceinline__ void cgls_p2_body(const Job* __restrict__ jobs,
           if (gi >= 1) lt += (double)v[2] * (double)rn[0];
           if (gi < m - 1) {
             stv(r2b, gi + (size_t)gj * (m - 1), rn[1]);
-            accr += (double)rn[1] * (double)rn[1];
+            accr = fma((double)rn[1], (double)rn[1], accr);
             lt -= (double)v[5] * (double)rn[1];
           }
           if (gj >= 1) lt += (double)v[8] * (double)rn[2];
           if (gj < m - 1) {
             stv(r2b, nx + g, rn[3]);
-            accr += (double)rn[3] * (double)rn[3];
+            accr = fma((double)rn[3], (double)rn[3], accr);
             lt -= (double)v[11] * (double)rn[3];
           }
           buf[i + j * TI] = (T)(sg * lt);
@@ -324,7 +327,7 @@ __device__ __forceinline__ void cgls_p2_body(const Job* __restrict__ jobs,
       const size_t g = (i0 + i) + (size_t)(j0 + j) * m;
       const T sv = rtv<S>(v + LT[i + j * TI]);
       stv(s, g, sv);
-      accs += (double)sv * (double)sv;
+      accs = fma((double)sv, (double)sv, accs);
     };
     auto hook = [&] { grad_part(Xs); };
     conv_tile<T, RB, SEP, decltype(epi2), decltype(hook), CV>(Xs, H, scratch, op, true, i0, j0,
@@ -335,7 +338,7 @@ __device__ __forceinline__ void cgls_p2_body(const Job* __restrict__ jobs,
       const size_t g = (i0 + i) + (size_t)(j0 + j) * m;
       const T sv = rtv<S>(v + LT[i + j * TI]);
       stv(s, g, sv);
-      accs += (double)sv * (double)sv;
+      accs = fma((double)sv, (double)sv, accs);
     });
   }
   double vv[2] = {accs, accr};
@@ -563,10 +566,15 @@ struct Dummy {};
 
 int cgls_wide_tiles() { return P2_WIDE_TILES; }
 
+// The radius bucket that holds a general operator's radius H (its tile
+// kernels' halo).
+static int gen_halo(int H) { return H <= 2 ? 2 : H <= 4 ? 4 : H <= 8 ? 8 : H <= 12 ? 12 : 16; }
+
 hipError_t launch_cgls_p1(const LaunchArgs& la, int precision, int sep, int rb, int H) {
   const bool wide = la.wide >= 0 ? la.wide != 0 : la.ntiles > P2_WIDE_TILES;
   if (sep && la.multi) return launch_cgls_multi(la, 1, precision, rb);
   if (sep && la.tile32) return launch_cgls_p1_sep(la, precision, rb, wide);
+  if (!sep && la.tile32) return launch_cgls_p1_gen(la, precision, gen_halo(H));
   if (precision == 1) DISPATCH_STENCIL_S(k_cgls_p1, double, double, la, sep, rb, H);
   else if (wide && precision == 2)
     DISPATCH_STENCIL_S(k_cgls_p1_wide, float, bf16s, la, sep, rb, H);
@@ -581,6 +589,7 @@ hipError_t launch_cgls_p2(const LaunchArgs& la, int precision, int sep, int rb, 
   const bool wide = la.wide >= 0 ? la.wide != 0 : la.ntiles > P2_WIDE_TILES;
   if (sep && la.multi) return launch_cgls_multi(la, 2, precision, rb);
   if (sep && la.tile32) return launch_cgls_p2_sep(la, precision, rb, wide);
+  if (!sep && la.tile32) return launch_cgls_p2_gen(la, precision, gen_halo(H));
   if (precision == 1) DISPATCH_STENCIL_S(k_cgls_p2, double, double, la, sep, rb, H);
   else if (wide && precision == 2)
     DISPATCH_STENCIL_S(k_cgls_p2_wide, float, bf16s, la, sep, rb, H);

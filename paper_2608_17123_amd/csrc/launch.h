@@ -12,7 +12,8 @@ struct LaunchArgs {
   int m_max;             // largest grid among the jobs (sizes LDS)
   hipStream_t stream;
   // every job has m >= 32 and the 32 x 32 tile kernels are enabled: the CGLS
-  // phases of separable operators take k_cgls_p1_sep / k_cgls_p2_sep
+  // phases take k_cgls_p1_sep / k_cgls_p2_sep (separable operators) or
+  // k_cgls_p1_gen / k_cgls_p2_gen (general ones)
   bool tile32 = false;
   // CGLS phases: 1 / 0 forces the register-bounded / unbounded variant; -1
   // takes the bounded one for launches of more than cgls_wide_tiles() tiles
@@ -64,6 +65,10 @@ hipError_t launch_cgls_p2(const LaunchArgs& la, int precision, int sep, int rb, 
 hipError_t launch_cgls_p1_sep(const LaunchArgs& la, int precision, int rb, bool wide);
 hipError_t launch_cgls_p2_sep(const LaunchArgs& la, int precision, int rb, bool wide);
 size_t cgls_sep_lds(int phase, int precision, int rb);
+// The same for general operators of radius <= rb (kernels_cgls_gen.hip).
+hipError_t launch_cgls_p1_gen(const LaunchArgs& la, int precision, int rb);
+hipError_t launch_cgls_p2_gen(const LaunchArgs& la, int precision, int rb);
+size_t cgls_gen_lds(int phase, int precision, int rb);
 // CGLS phase `phase` (1 or 2) over jobs of several radius buckets up to rbmax
 // (kernels_cgls_multi.hip, register-bounded kernels only: a mixed launch
 // gathers enough tiles to fill the chip); cgls_multi_bucket(rbmax): a launch

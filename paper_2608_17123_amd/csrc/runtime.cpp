@@ -707,9 +707,9 @@ namespace {
 
 struct GroupKey {
   int prec, sep, rb, H;
-  // CGLS phases: separable jobs on grids of at least 32 (the 32 x 32 tile
-  // kernels) launch apart from smaller ones, so a job's kernel depends on
-  // its own grid alone, never on which jobs share its launch
+  // CGLS phases: jobs on grids of at least 32 (the 32 x 32 tile kernels)
+  // launch apart from smaller ones, so a job's kernel depends on its own
+  // grid alone, never on which jobs share its launch
   int t32 = 0;
   // CGLS phases: jobs of several radius buckets, each with tables padded to
   // its own bucket, share the launch; rb is the largest of them
@@ -1230,7 +1230,7 @@ int engine_step(dbl_ctx* ctx, std::vector<Slot*>& slots) {
       j.v[V_C1] = s->C1;
       j.v[V_C2] = s->C2;
       GroupKey gk = pe.key;
-      gk.t32 = gk.sep && j.m >= 32;
+      gk.t32 = j.m >= 32;
       if (pe.small_lds) {
         Job js = j;
         js.i0 = s->opts.k_in;

@@ -172,6 +172,34 @@ void check_sep32(const std::string& k, int jb, const Job& j, int rb, size_t esz,
     fail(k, jb, "dynamic LDS " + std::to_string(shmem) + " < " + std::to_string(e * esz));
 }
 
+// The 32 x 32 tile kernels for general operators: a grid of at least 32, a
+// non-separable operator of radius <= the kernel's halo rb whose interior
+// lists fit the staging area, and the dynamic LDS the kernel lays out
+// (haloed tile, staged list, in phase 2 the gradient part).
+void check_gen32(const std::string& k, int jb, const Job& j, int rb, size_t esz, int phase,
+                 size_t shmem) {
+  if (j.m < 32) fail(k, jb, "32 x 32 tile kernel on a grid of " + std::to_string(j.m));
+  if (!j.op || !owner(j.op, sizeof(dbl::LevelOp))) return;
+  const dbl::LevelOp& op = *j.op;
+  if (op.sep) {
+    fail(k, jb, "general-operator tile kernel on a separable level");
+    return;
+  }
+  const size_t gt = (size_t)(2 * rb + 1) * (2 * rb + 1);
+  const dbl::Table2D* ts[2] = {&op.f2, &op.a2};
+  for (const dbl::Table2D* t : ts) {
+    if (t->R0 > rb || t->R1 > rb) fail(k, jb, "table radius above the halo " + std::to_string(rb));
+    const size_t ncls = (size_t)t->rows0 * t->rows1;
+    if (!owner(t->off, (ncls + 1) * 4)) continue;
+    const int cls = t->St0 + t->St1 * t->rows0;
+    if ((size_t)(t->off[cls + 1] - t->off[cls]) > gt)
+      fail(k, jb, "interior tap list longer than the staging area");
+  }
+  const size_t xs = (size_t)(32 + 2 * rb) * (32 + 2 * rb + 1), gti = (gt + 1) & ~size_t(1);
+  const size_t e = esz * xs + 4 * gti + esz * gt + (phase == 2 ? esz * 32 * 32 : 0);
+  if (shmem < e) fail(k, jb, "dynamic LDS " + std::to_string(shmem) + " < " + std::to_string(e));
+}
+
 // The one-block CGLS: a separable operator with tables padded to the kernel's
 // halo RB, or (gen) a general operator of radius <= RB whose interior class
 // lists fit the staging area; the dynamic LDS covers the kernel's layout.
@@ -299,12 +327,13 @@ void audit(const void* func, dim3 grid, dim3 block, void** args, size_t shmem) {
         if (irls) need(fam, jb, "V_W", v(dbl::V_W), nl * T);
       }
     } else if (fam == "k_cgls_p1" || fam == "k_cgls_p1_wide" || fam == "k_cgls_p1_sep" ||
-               fam == "k_cgls_p1_multi") {
+               fam == "k_cgls_p1_multi" || fam == "k_cgls_p1_gen") {
       const size_t T = tsize(ta[0]), S = tsize(ta[1]);
       grid_is(m);
       check_op(fam, jb, j, T == 8);
       if (fam == "k_cgls_p1_sep") check_sep32(fam, jb, j, std::atoi(ta[2].c_str()), T, 1, shmem);
       if (fam == "k_cgls_p1_multi") check_multi(fam, jb, j, std::atoi(ta[2].c_str()), T, 1, shmem);
+      if (fam == "k_cgls_p1_gen") check_gen32(fam, jb, j, std::atoi(ta[2].c_str()), T, 1, shmem);
       need(fam, jb, "V_S", v(dbl::V_S), n * S);
       need(fam, jb, "V_PA", v(dbl::V_PA), n * S);
       need(fam, jb, "V_PB", v(dbl::V_PB), n * S);
@@ -318,12 +347,13 @@ void audit(const void* func, dim3 grid, dim3 block, void** args, size_t shmem) {
         need(fam, jb, "pr[1]", j.pr[1], (size_t)ntile * 2 * 8);
       }
     } else if (fam == "k_cgls_p2" || fam == "k_cgls_p2_wide" || fam == "k_cgls_p2_sep" ||
-               fam == "k_cgls_p2_multi") {
+               fam == "k_cgls_p2_multi" || fam == "k_cgls_p2_gen") {
       const size_t T = tsize(ta[0]), S = tsize(ta[1]);
       grid_is(m);
       check_op(fam, jb, j, T == 8);
       if (fam == "k_cgls_p2_sep") check_sep32(fam, jb, j, std::atoi(ta[2].c_str()), T, 2, shmem);
       if (fam == "k_cgls_p2_multi") check_multi(fam, jb, j, std::atoi(ta[2].c_str()), T, 2, shmem);
+      if (fam == "k_cgls_p2_gen") check_gen32(fam, jb, j, std::atoi(ta[2].c_str()), T, 2, shmem);
       need(fam, jb, "V_R1A", v(dbl::V_R1A), n * S);
       need(fam, jb, "V_R1B", v(dbl::V_R1B), n * S);
       need(fam, jb, "V_R2A", v(dbl::V_R2A), nl * S);

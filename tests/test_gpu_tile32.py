@@ -1,12 +1,11 @@
-"""The 32 x 32 tile CGLS kernels (k_cgls_p1_sep / k_cgls_p2_sep, used for
-separable operators on grids of at least 32) against the generic tile
-kernels: both form every sum in the same order, so whole solves and CGLS
-iterates must agree bit for bit (DBL_OPT_TILE32 switches between them).  The
-one allowance: the FP64 residual history, which no iterate depends on, may
-differ in the last bit where the compiler fuses a square into its running
-sum in one kernel and rounds it separately in the other.  The oracle
-comparisons of test_gpu_solve.py / test_gpu_large.py run the new kernels by
-default.
+"""The 32 x 32 tile CGLS kernels (k_cgls_p1_sep / k_cgls_p2_sep for
+separable operators, k_cgls_p1_gen / k_cgls_p2_gen for general ones, on
+grids of at least 32) against the generic tile kernels: both form every sum
+in the same order, so whole solves and CGLS iterates must agree bit for bit
+(DBL_OPT_TILE32 switches between them), residual
+histories included (both families form every term of the FP64 norm sums as
+an explicit fma).  The oracle comparisons of test_gpu_solve.py /
+test_gpu_large.py run the tile kernels by default.
 
 Cases cover every radius bucket (2 .. 16), the three precisions (BF16
 storage included), the three solvers with both transfers, IRLS weights,
@@ -113,7 +112,7 @@ def test_cgls_tile32_equals_generic(ctx, prec, kind, m, level, rb, wavelet):
 
         (xa, ha), (xb, hb) = both(ctx, run)
         assert torch.equal(xa, xb)
-        assert np.allclose(ha, hb, rtol=1e-14, atol=0.0)
+        assert ha == hb
     D.dbl_set_option(ctx, D.DBL_OPT_SMALL_CGLS, 1)
     op.close()
 
@@ -188,3 +187,68 @@ def test_mixed_bucket_batch_equals_plain(ctx, prec, multi):
     assert all(r["status"] == 0 for r in reps)
     for q, (x, xp) in enumerate(zip(xs, plain)):
         assert torch.equal(x, xp), f"case {q}: max diff {float((x - xp).abs().max()):.3e}"
+
+
+@pytest.mark.parametrize("prec", [D.DBL_F32, D.DBL_F64, D.DBL_BF16])
+@pytest.mark.parametrize("solver,wavelet,transfer", [("irls", "db4", "X"), ("sb", "haar", "D"),
+                                                     ("mm", "db4", "D")])
+def test_general_operator_tile32_equals_generic(ctx, prec, solver, wavelet, transfer):
+    """A motion PSF (general 2-D tap lists): the 32 x 32 tile kernels for
+    general operators against the generic tile kernels, whole solves bit for
+    bit (256 x 256, 4 grids, the one-block path off so that every grid from
+    32 up runs the phases)."""
+    m, levels, k_out, k_in = 256, 4, 2, 8
+    print(f"tile32 general {solver} {wavelet} {transfer} prec={prec}", flush=True)
+    D.dbl_set_option(ctx, D.DBL_OPT_SMALL_CGLS, 0)
+    X, rng = image(m, 91)
+    P = synth.motion_psf(21, 0.7)
+    B = ops.blur(X, P)
+    B = B + 0.01 * np.linalg.norm(B) * rng.standard_normal((m, m)) / m
+    mu = [[2e-3 * (1.5 ** i) * (1.1 ** k) for k in range(k_out)] for i in range(levels)]
+    opts = D.dbl_opts_default(k_out=k_out, k_in=k_in, precision=prec,
+                              mu_schedule=np.array(mu).ravel())
+    b = torch.tensor(ops.vec(B), dtype=DT[prec], device="cuda")
+
+    def run():
+        x = torch.zeros(m * m, dtype=DT[prec], device="cuda")
+        rep = D.dbl_deblur(ctx, b, P, m, solver, wavelet, levels, transfer, x, opts)
+        assert rep["status"] == 0
+        return x, rep
+
+    (x0, r0), (x1, r1) = both(ctx, run)
+    D.dbl_set_option(ctx, D.DBL_OPT_SMALL_CGLS, 1)
+    assert torch.equal(x0, x1)
+    assert r0["objective"] == r1["objective"]
+    assert float(x1.abs().max()) > 0.1
+
+
+@pytest.mark.parametrize("prec", [D.DBL_F32, D.DBL_F64])
+@pytest.mark.parametrize("kind", ["irls", "mm", "plain"])
+@pytest.mark.parametrize("m,level,wavelet", [(128, 0, "haar"), (256, 1, "db4"), (512, 0, "db4")])
+def test_general_cgls_tile32_equals_generic(ctx, prec, kind, m, level, wavelet):
+    """Single CGLS runs on a motion-blur level, with and without a warm start:
+    the general tile kernels against the generic ones, x and the residual
+    history bit for bit."""
+    print(f"tile32 general cgls {kind} m={m} level={level} prec={prec}", flush=True)
+    D.dbl_set_option(ctx, D.DBL_OPT_SMALL_CGLS, 0)
+    P = synth.motion_psf(21, 1.9)
+    op = D.dbl_op_create(ctx, P, m, level + 1, wavelet, prec)
+    mi = m >> level
+    nl = 2 * mi * (mi - 1)
+    rng = np.random.default_rng(m + level)
+    dt = DT[prec]
+    B = torch.tensor(rng.standard_normal(mi * mi), dtype=dt, device="cuda")
+    w = torch.tensor(rng.uniform(0.5, 5.0, nl), dtype=dt, device="cuda") if kind == "irls" else None
+    c = torch.tensor(0.1 * rng.standard_normal(nl), dtype=dt, device="cuda") if kind == "mm" else None
+    x0 = torch.tensor(0.3 * rng.standard_normal(mi * mi), dtype=dt, device="cuda")
+    for start in (None, x0):
+        def run():
+            x = torch.zeros(mi * mi, dtype=dt, device="cuda")
+            h = D.dbl_cgls(ctx, op, level, B, 12, x, 0.02, w=w, c=c, x0=start)
+            return x, list(h)
+
+        (xa, ha), (xb, hb) = both(ctx, run)
+        assert torch.equal(xa, xb)
+        assert ha == hb
+    D.dbl_set_option(ctx, D.DBL_OPT_SMALL_CGLS, 1)
+    op.close()
