@@ -328,13 +328,16 @@ __device__ __forceinline__ void p1_sep_body(const Job* __restrict__ jobs,
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const GP<const LevelOp> op = gview(job->op);
+  // separable tables (loaded with the tile; unused, and dropped, for GEN)
+  const int St0 = op->f0.St, Sb0 = op->f0.Sb, St1 = op->f1.St, Sb1 = op->f1.Sb;
+  const GP<const T> tab0 = gtaps<T>(&op->f0), tab1 = gtaps<T>(&op->f1);
   Table2D tg;
   int gn = 0;
   if constexpr (GEN) {
     tg = job->op->f2;
     gn = stage_gen<T, RB>(g_off, g_val, tg);
   } else {
-    stage_taps<T, G::NTAP>(taps, gtaps<T>(&op->f0), op->f0.St, gtaps<T>(&op->f1), op->f1.St);
+    stage_taps<T, G::NTAP>(taps, tab0, St0, tab1, St1);
   }
   const int flags = job->flags;
   const bool first = flags & F_FIRST, irls = flags & F_IRLS;
@@ -433,8 +436,6 @@ __device__ __forceinline__ void p1_sep_body(const Job* __restrict__ jobs,
       acc = fma((double)qv, (double)qv, acc);
     });
   } else {
-    const int St0 = op->f0.St, Sb0 = op->f0.Sb, St1 = op->f1.St, Sb1 = op->f1.Sb;
-    const GP<const T> tab0 = gtaps<T>(&op->f0), tab1 = gtaps<T>(&op->f1);
     pass_a<T, RB>(Xs, Zs, taps, tab0, St0, Sb0, row0, m);
     lds_barrier();
     // pass-B outputs: lane offset i + CV (lane / 32) m of the uniform column cu
@@ -474,13 +475,16 @@ __device__ __forceinline__ void p2_sep_body(const Job* __restrict__ jobs,
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const GP<const LevelOp> op = gview(job->op);
+  // separable tables (loaded with the tile; unused, and dropped, for GEN)
+  const int St0 = op->a0.St, Sb0 = op->a0.Sb, St1 = op->a1.St, Sb1 = op->a1.Sb;
+  const GP<const T> tab0 = gtaps<T>(&op->a0), tab1 = gtaps<T>(&op->a1);
   Table2D tg;
   int gn = 0;
   if constexpr (GEN) {
     tg = job->op->a2;
     gn = stage_gen<T, RB>(g_off, g_val, tg);
   } else {
-    stage_taps<T, G::NTAP>(taps, gtaps<T>(&op->a0), op->a0.St, gtaps<T>(&op->a1), op->a1.St);
+    stage_taps<T, G::NTAP>(taps, tab0, St0, tab1, St1);
   }
   const int flags = job->flags;
   const bool first = flags & F_FIRST, irls = flags & F_IRLS;
@@ -626,8 +630,6 @@ __device__ __forceinline__ void p2_sep_body(const Job* __restrict__ jobs,
       accs = fma((double)sv, (double)sv, accs);
     });
   } else {
-    const int St0 = op->a0.St, Sb0 = op->a0.Sb, St1 = op->a1.St, Sb1 = op->a1.Sb;
-    const GP<const T> tab0 = gtaps<T>(&op->a0), tab1 = gtaps<T>(&op->a1);
     pass_a<T, RB>(Xs, Zs, taps, tab0, St0, Sb0, row0, m);
     lds_barrier();
     const uint32_t ob = (uint32_t)(i + jh * CV * m) * ES;
