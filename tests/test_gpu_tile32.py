@@ -252,3 +252,43 @@ def test_general_cgls_tile32_equals_generic(ctx, prec, kind, m, level, wavelet):
         assert ha == hb
     D.dbl_set_option(ctx, D.DBL_OPT_SMALL_CGLS, 1)
     op.close()
+
+
+@pytest.mark.parametrize("prec", [D.DBL_F32, D.DBL_F64])
+def test_mixed_operator_kinds_batch_equals_plain(ctx, prec):
+    """One batch of motion (general) and Gaussian (separable) solves of
+    several sizes, with the one-block CGLS on: the general one-block kernel
+    (grids up to 32), the general and separable tile kernels, mixed-bucket
+    launches and separate bucket-16 launches in the same CGLS stages; every
+    solve equals its plain run bit for bit."""
+    print(f"mixed operator kinds batch prec={prec}", flush=True)
+    # (m, levels, solver, wavelet, transfer, PSF, motion angle); motion supports
+    # 9 / 21 / 31 fall in the radius buckets 4 / 12 / 16
+    cases = [(128, 3, "irls", "db4", "X", "motion21", 0.4), (256, 4, "sb", "haar", "D", "g8", 0),
+             (64, 2, "mm", "haar", "X", "motion9", 2.1), (128, 3, "sb", "db4", "D", "g16", 0),
+             (256, 4, "mm", "db4", "X", "motion31", 1.2), (64, 2, "irls", "haar", "D", "g4", 0)]
+    k_out, k_in = 2, 6
+    dt = DT[prec]
+    reqs, xs, plain = [], [], []
+    for q, (m, levels, solver, wavelet, transfer, kind, ang) in enumerate(cases):
+        X, rng = image(m, 120 + q)
+        P = (synth.motion_psf(int(kind[6:]), ang) if kind.startswith("motion")
+             else synth.gaussian_psf(*{"g4": (1.2, 4), "g8": (2.5, 8), "g16": (4.0, 16)}[kind]))
+        B = ops.blur(X, P)
+        B = B + 0.01 * np.linalg.norm(B) * rng.standard_normal((m, m)) / m
+        mu = [[3e-3 * (1.3 ** i) for _ in range(k_out)] for i in range(levels)]
+        opts = D.dbl_opts_default(k_out=k_out, k_in=k_in, precision=prec,
+                                  mu_schedule=np.array(mu).ravel())
+        b = torch.tensor(ops.vec(B), dtype=dt, device="cuda")
+        xp = torch.zeros(m * m, dtype=dt, device="cuda")
+        assert D.dbl_deblur(ctx, b, P, m, solver, wavelet, levels, transfer, xp,
+                            opts)["status"] == 0
+        plain.append(xp)
+        x = torch.zeros(m * m, dtype=dt, device="cuda")
+        xs.append(x)
+        reqs.append(D.make_request(b, x, P, m, solver, wavelet, levels, transfer, opts))
+    reps = D.dbl_deblur_batch(ctx, reqs)
+    torch.cuda.synchronize()
+    assert all(r["status"] == 0 for r in reps)
+    for q, (x, xp) in enumerate(zip(xs, plain)):
+        assert torch.equal(x, xp), f"case {q}: max diff {float((x - xp).abs().max()):.3e}"
