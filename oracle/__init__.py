@@ -14,6 +14,7 @@ Parity status of each part (what pins it) is listed in the module docstrings.
 One result is "parity unpinned": the end-to-end reconstructions against the
 paper's own figures and tables, which need the paper's images and MATLAB.
 """
-from . import operators, hierarchy, krylov, gcv, solvers, vcycle, objective
+from . import operators, hierarchy, krylov, gcv, solvers, vcycle, objective, metrics
 
-__all__ = ["operators", "hierarchy", "krylov", "gcv", "solvers", "vcycle", "objective"]
+__all__ = ["operators", "hierarchy", "krylov", "gcv", "solvers", "vcycle", "objective",
+           "metrics"]
