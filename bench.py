@@ -36,7 +36,9 @@ Printed: one JSON line with
 --calib-copy runs only a plain 1 GiB device-to-device copy (three times): the
 known-size kernel that scales the FETCH_SIZE / WRITE_SIZE counters.
 --profile-run runs one batch of the workload and nothing else (for rocprofv3);
---operators-only and --serve-only run only those legs.
+--operators-only and --serve-only run only those legs.  --ssim-only times the
+SSIM quality measure (dbl_ssim) at the quality harness's size and on large
+images, against the FP64 vector peak.
 """
 import argparse
 import json
@@ -52,6 +54,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "solves/s batched vs plain at rel.err<=1e-4 vs FP64; p99 latency; HBM GB/s"
 HBM_PEAK_GBS = 8000.0
+FP64_VECTOR_PEAK_TFLOPS = 78.6
 TRAFFIC_RECORD = {
     "c4": os.path.join(ROOT, "profiles", "traffic_cgls_p2_c4_batch256.json"),
     "c2": os.path.join(ROOT, "profiles", "traffic_cgls_p2_m256_batch24.json"),
@@ -79,6 +82,8 @@ def parse():
     p.add_argument("--serve-only", action="store_true",
                    help="run only the serving leg (for rocprofv3)")
     p.add_argument("--profile-run", action="store_true")
+    p.add_argument("--ssim-only", action="store_true",
+                   help="time dbl_ssim only (quality measure of Sec. 5)")
     p.add_argument("--precision", default="f32", choices=["f32", "bf16", "f64"],
                    help="vector storage: FP32, BF16 CGLS state with FP32 arithmetic, or FP64")
     p.add_argument("--inner", default="cgls", choices=["cgls", "lsqr"],
@@ -276,6 +281,44 @@ def operator_leg(D, torch, ctx, count=16, m=2048):
             "working_set_MB": round(count * (n + nl) * 4 / 1e6), "results": out}
 
 
+def ssim_leg(D, torch, ctx, cases=((256, 30), (2048, 16)), radius=5):
+    """dbl_ssim on `count` FP32 images of m x m against one FP64 reference
+    (the quality harness's call, then large images), timed by HIP events
+    inside the library.  The work is FP64 arithmetic: the algorithmic
+    minimum per pixel is 20 (2R + 1) + 23 flops (five window sums, each two
+    1-D passes of 2R + 1 multiply-adds; three products; the SSIM formula),
+    against the FP64 vector peak; bytes are both images read once."""
+    out = {}
+    reps = 5
+    g = torch.Generator(device="cuda").manual_seed(5)
+    nw = 2 * radius + 1
+    for m, count in cases:
+        ref = torch.rand(m * m, device="cuda", generator=g, dtype=torch.float64)
+        xs = [(ref + 0.05 * torch.randn(m * m, device="cuda", generator=g,
+                                        dtype=torch.float64)).float() for _ in range(count)]
+        res = torch.empty(count, dtype=torch.float64, device="cuda")
+        D.dbl_ssim(ctx, ref, xs, m, D.DBL_F32, out=res, radius=radius)  # warm-up
+        D.dbl_profile(ctx, 1)
+        for _ in range(reps):
+            D.dbl_ssim(ctx, ref, xs, m, D.DBL_F32, out=res, radius=radius)
+        st = D.dbl_profile_read(ctx)
+        D.dbl_profile(ctx, 0)
+        nl_, ms, by = st["ssim"]
+        us = 1e3 * ms / nl_
+        flops = count * m * m * (20 * nw + 23)
+        tfs = flops / (us * 1e-6) / 1e12
+        out[f"m{m}_x{count}"] = {
+            "kernel": "k_ssim", "launches": nl_, "avg_launch_us": round(us, 1),
+            "fin_avg_launch_us": round(1e3 * st["ssim_fin"][1] / st["ssim_fin"][0], 1),
+            "flops_per_launch": flops, "TFLOP/s": round(tfs, 2),
+            "frac_fp64_vector": round(tfs / FP64_VECTOR_PEAK_TFLOPS, 4),
+            "GB/s": round(by / nl_ / (us * 1e-6) / 1e9, 1)}
+        del xs, ref
+    torch.cuda.empty_cache()
+    return {"dtype": "f32 images, f64 reference and arithmetic", "radius": radius,
+            "sigma": 1.5, "peak_TFLOPs": FP64_VECTOR_PEAK_TFLOPS, "results": out}
+
+
 # --------------------------------------------------------------- serving --
 
 def serve_leg(D, torch, ctx, rates, nreq, opts_kw):
@@ -369,6 +412,9 @@ def main():
         D.dbl_set_option(ctx, D.DBL_OPT_MULTI_BUCKET, args.multi_tiles)
     if args.operators_only:
         print(json.dumps({"operators": operator_leg(D, torch, ctx)}))
+        return
+    if args.ssim_only:
+        print(json.dumps({"ssim": ssim_leg(D, torch, ctx)}))
         return
     if args.serve_only:
         rates = [float(r) for r in args.serve_rates.split(",") if r]

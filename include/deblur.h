@@ -391,6 +391,31 @@ int dbl_server_step(dbl_server* srv, int* active);
  * its report and the ticket is released. */
 int dbl_server_poll(dbl_server* srv, int64_t ticket, int* done, dbl_report* rep);
 
+/* ---------------------------------------------------------------- quality */
+
+#define DBL_SSIM_MAX_M 8192
+#define DBL_SSIM_MAX_RADIUS 16
+/* Mean structural similarity (SSIM), the second quality measure of Sec. 5,
+ * of `count` m x m images x[q] against one reference image ref.  Per pixel,
+ * the local means mu, variances s^2 and covariance s_ab of the two images
+ * under the Gaussian window w(k) w(l), w(k) = exp(-k^2 / (2 sigma^2)) for
+ * |k| <= radius normalised to unit mass, with pixels outside the image
+ * replaced by the nearest edge pixel, give
+ *   (2 mu_a mu_b + c1)(2 s_ab + c2) / ((mu_a^2 + mu_b^2 + c1)(s_a^2 + s_b^2 + c2)),
+ * c1 = (0.01 L)^2, c2 = (0.03 L)^2 with L = dyn_range; out[q] is its mean
+ * over the m^2 pixels.  (sigma = 1.5, radius = 5, L = 1 is the window of the
+ * SSIM reference the paper cites, for images in [0, 1].)
+ * ref: device m x m FP64 array, column-major.  x: host array of count device
+ * pointers, each an m x m column-major array of `precision` (DBL_F32 or
+ * DBL_F64), read during the call.  out: device array of count doubles.
+ * All statistics are formed in FP64.  1 <= m <= DBL_SSIM_MAX_M,
+ * 0 <= count <= 65536 with count * ceil(m/32)^2 <= 2^24 (one block per
+ * 32 x 32 tile), 0 <= radius <= DBL_SSIM_MAX_RADIUS, sigma and dyn_range
+ * finite and > 0; anything else is DBL_EINVAL.  Asynchronous: out is
+ * written on the context stream. */
+int dbl_ssim(dbl_ctx* ctx, int m, int precision, int count, const double* ref,
+             const void* const* x, double sigma, int radius, double dyn_range, double* out);
+
 #ifdef __cplusplus
 }
 #endif

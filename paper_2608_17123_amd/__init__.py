@@ -44,7 +44,7 @@ EXPORTS = [
     "dbl_opts_default", "dbl_profile", "dbl_profile_read", "dbl_op_create", "dbl_op_destroy", "dbl_apply_A", "dbl_apply_L",
     "dbl_dwt", "dbl_apply_A_batch", "dbl_apply_L_batch", "dbl_dwt_batch", "dbl_dtransfer", "dbl_cgls", "dbl_cgls_noalloc", "dbl_lsqr", "dbl_gcv", "dbl_deblur", "dbl_deblur_batch",
     "dbl_request_bytes", "dbl_server_create", "dbl_server_destroy", "dbl_server_submit",
-    "dbl_server_step", "dbl_server_poll", "dbl_autotune", "dbl_tune_choice",
+    "dbl_server_step", "dbl_server_poll", "dbl_autotune", "dbl_tune_choice", "dbl_ssim",
 ]
 
 
@@ -131,6 +131,8 @@ def lib():
         "dbl_apply_L_batch": (i, [vp, i, i, i, i, ctypes.POINTER(vp), ctypes.POINTER(vp)]),
         "dbl_dwt_batch": (i, [vp, i, i, i, i, i, i, ctypes.POINTER(vp), ctypes.POINTER(vp)]),
         "dbl_dtransfer": (i, [vp, i, i, i, vp, vp]),
+        "dbl_ssim": (i, [vp, i, i, i, vp, ctypes.POINTER(vp), ctypes.c_double, i,
+                         ctypes.c_double, vp]),
         "dbl_cgls": (i, [vp, vp, i, ctypes.POINTER(dbl_sub), vp, vp, i, vp, dp]),
         "dbl_lsqr": (i, [vp, vp, i, ctypes.POINTER(dbl_sub), vp, vp, i, vp, dp]),
         "dbl_cgls_noalloc": (i, [vp, vp, i, ctypes.POINTER(dbl_sub), vp, vp, i, vp, dp]),
@@ -436,6 +438,23 @@ def dbl_dtransfer(ctx, wavelet, m_coarse, precision, q_in, q_out):
     pi = _dev(q_in, precision, _nl(m_coarse), "q_in")
     po = _dev(q_out, precision, _nl(2 * m_coarse), "q_out")
     _check(ctx, lib().dbl_dtransfer(ctx.handle, wavelet, m_coarse, precision, pi, po))
+
+
+def dbl_ssim(ctx, ref, xs, m, precision=DBL_F32, out=None, sigma=1.5, radius=5, dyn_range=1.0):
+    """Mean SSIM of every m x m image in xs (device tensors of `precision`)
+    against ref (a device FP64 m x m tensor), one FP64 value per image in
+    `out` (a device tensor, allocated when None; returned)."""
+    import torch
+
+    n = len(xs)
+    r = _dev(ref, DBL_F64, m * m, "ref")
+    px = _ptr_array(xs, precision, m * m, "xs")
+    if out is None:
+        out = torch.empty(n, dtype=torch.float64, device=ref.device)
+    po = _dev(out, DBL_F64, n, "out")
+    _check(ctx, lib().dbl_ssim(ctx.handle, m, precision, n, r, px, float(sigma), int(radius),
+                               float(dyn_range), po))
+    return out
 
 
 def _sub(d_kind, w, gamma, c, precision, m):

@@ -8,6 +8,7 @@
 
 #include <rocblas/rocblas.h>
 
+#include "metrics.h"
 #include "runtime.h"
 
 using namespace dbl;
@@ -413,6 +414,84 @@ int dbl_dtransfer(dbl_ctx* ctx, int wavelet, int m_coarse, int precision, const 
   LaunchArgs la;
   if ((rc = Lc.upload(ctx, la))) return rc;
   return hip_check(ctx, launch_dtransfer(la, precision), "dtransfer");
+}
+
+int dbl_ssim(dbl_ctx* ctx, int m, int precision, int count, const double* ref,
+             const void* const* x, double sigma, int radius, double dyn_range, double* out) {
+  if (!ctx) return DBL_EINVAL;
+  if (m < 1 || m > DBL_SSIM_MAX_M) return set_err(ctx, DBL_EINVAL, "m out of range [1, 8192]");
+  if (count < 0 || count > 65536) return set_err(ctx, DBL_EINVAL, "count out of range");
+  if (count > 0 && (!ref || !x || !out)) return set_err(ctx, DBL_EINVAL, "ref, x or out is NULL");
+  for (int q = 0; q < count; ++q)
+    if (!x[q]) return set_err(ctx, DBL_EINVAL, "x is NULL");
+  if (precision != DBL_F32 && precision != DBL_F64)
+    return set_err(ctx, DBL_EINVAL, "precision must be DBL_F32 or DBL_F64");
+  if (radius < 0 || radius > DBL_SSIM_MAX_RADIUS)
+    return set_err(ctx, DBL_EINVAL, "radius out of range [0, 16]");
+  if (!(sigma > 0.0) || !std::isfinite(sigma)) return set_err(ctx, DBL_EINVAL, "sigma must be finite and > 0");
+  if (!(dyn_range > 0.0) || !std::isfinite(dyn_range))
+    return set_err(ctx, DBL_EINVAL, "dyn_range must be finite and > 0");
+  if (ctx->device < 0) return set_err(ctx, DBL_EDEVICE, "context has no device");
+  if (ssim_lds(radius) + 512 > ctx->lds_limit)
+    return set_err(ctx, DBL_ENOTSUP, "SSIM tile does not fit the device's LDS");
+  if (count == 0) return DBL_OK;
+  (void)hipSetDevice(ctx->device);
+  if (int rc0 = stage_checkpoint(ctx)) return rc0;
+  // the window taps, normalised to unit mass
+  double taps[2 * DBL_SSIM_MAX_RADIUS + 1];
+  double tsum = 0.0;
+  for (int k = -radius; k <= radius; ++k) {
+    taps[k + radius] = std::exp(-(double)k * k / (2.0 * sigma * sigma));
+    tsum += taps[k + radius];
+  }
+  for (int k = 0; k <= 2 * radius; ++k) taps[k] /= tsum;
+  void* dtaps = nullptr;
+  int rc = stage(ctx, taps, sizeof(double) * (2 * radius + 1), &dtaps);
+  if (rc) return rc;
+  // one FP64 partial per 32 x 32 tile of every image
+  const int nt1 = (m + 31) / 32, nt = nt1 * nt1;
+  if ((size_t)count * nt > (size_t(1) << 24))
+    return set_err(ctx, DBL_EINVAL, "count x tiles above 2^24");
+  const size_t need = ((size_t)count * nt * sizeof(double) + 255) & ~size_t(255);
+  if (ctx->scratch_bytes < need) {
+    if ((rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "sync"))) return rc;
+    dfree(ctx, ctx->scratch);
+    ctx->scratch = nullptr;
+    ctx->scratch_bytes = 0;
+    if ((rc = dmalloc(ctx, need, &ctx->scratch))) return rc;
+    ctx->scratch_bytes = need;
+  }
+  double* part = static_cast<double*>(ctx->scratch);
+  Launch Lt, Lf;
+  for (int q = 0; q < count; ++q) {
+    Job j;
+    std::memset(&j, 0, sizeof(j));
+    j.m = m;
+    j.v[0] = const_cast<double*>(ref);
+    j.v[1] = const_cast<void*>(x[q]);
+    j.v[2] = dtaps;
+    j.v[3] = out + q;
+    j.i0 = radius;
+    j.p0 = (0.01 * dyn_range) * (0.01 * dyn_range);
+    j.p1 = (0.03 * dyn_range) * (0.03 * dyn_range);
+    j.pw = part + (size_t)q * nt;
+    j.pr[0] = j.pw;
+    j.i1 = nt;
+    Lt.add_grid(j, nt1, nt1);
+    Lf.add_grid(j, 1, 1);
+  }
+  LaunchArgs lt, lf;
+  if ((rc = upload_all(ctx, {{&Lt, &lt}, {&Lf, &lf}}))) return rc;
+  // algorithmic bytes: both images read once, one partial per tile
+  const double bytes = (double)count * ((double)m * m * (8.0 + (precision == DBL_F64 ? 8 : 4)) +
+                                        8.0 * nt);
+  if ((rc = hip_check(ctx, timed(ctx, "ssim", bytes,
+                                 [&] { return launch_ssim(lt, precision, radius); }),
+                      "ssim")))
+    return rc;
+  return hip_check(ctx, timed(ctx, "ssim_fin", 8.0 * count * (nt + 1),
+                              [&] { return launch_ssim_fin(lf); }),
+                   "ssim finish");
 }
 
 }  // extern "C"

@@ -14,19 +14,19 @@ Gaussian blur sigma = 2.5 on 15 x 15, noise 1% and 5%) with every solver in
 those five combinations, K_out outer iterations per level and K_in CGLS
 steps, all solves in one batch on the device.  The fine level's iterate
 after each outer iteration comes back through the x_hist option, and the
-RRE per iteration is taken on the device in FP64 against the known image;
-SSIM (Sec. 5, the paper's second measure) is taken on the host from the same
-iterates.  It reports the curves and, per solver and noise level, whether
-each of the paper's findings holds on this data.
+RRE per iteration is taken on the device in FP64 against the known image,
+and so is SSIM (Sec. 5, the paper's second measure), by the library's
+dbl_ssim over the same iterates.  It reports the curves and, per solver and
+noise level, whether each of the paper's findings holds on this data.
 
 SSIM follows the statistic the paper states: per pixel, the local means,
 variances and covariance of the true and reconstructed images under a
 Gaussian window, combined with c1 = (0.01 L)^2 and c2 = (0.03 L)^2 (L the
-dynamic range, 1 for images in [0, 1]), averaged over all windows.  The
+dynamic range, 1 for these images in [0, 1]), averaged over all pixels.  The
 paper computes it with MATLAB's ssim, whose window is not restated there;
-this module takes the window of the SSIM reference it cites (Gaussian,
-standard deviation 1.5, truncated to 11 x 11, normalised to unit mass) and
-replicates edge pixels outside the image.
+the harness takes the window of the SSIM reference it cites (Gaussian,
+standard deviation 1.5, truncated to 11 x 11, normalised to unit mass) with
+edge pixels replicated outside the image.
 
 With --sigma the image and noise direction of that workload are blurred
 instead by Gaussian kernels of the given widths (radius ceil(3 sigma), at
@@ -65,34 +65,6 @@ SOLVERS = ("irls", "mm", "sb")
 COMBOS = (("I", "haar", False, "X"), ("HWT-X", "haar", True, "X"),
           ("HWT-D", "haar", True, "D"), ("DWT-X", "db4", True, "X"),
           ("DWT-D", "db4", True, "D"))
-
-
-def gaussian_window(sigma=1.5, radius=5):
-    """Normalised 1-D Gaussian taps exp(-k^2 / (2 sigma^2)), |k| <= radius."""
-    k = np.arange(-radius, radius + 1, dtype=np.float64)
-    g = np.exp(-k * k / (2.0 * sigma * sigma))
-    return g / g.sum()
-
-
-def ssim(x_true, x, L=1.0, sigma=1.5, radius=5):
-    """Mean structural similarity of two m x m images (FP64, host)."""
-    from scipy.ndimage import correlate1d
-
-    g = gaussian_window(sigma, radius)
-
-    def smooth(a):
-        return correlate1d(correlate1d(a, g, axis=0, mode="nearest"), g, axis=1, mode="nearest")
-
-    a = np.asarray(x_true, dtype=np.float64)
-    b = np.asarray(x, dtype=np.float64)
-    mu_a, mu_b = smooth(a), smooth(b)
-    var_a = smooth(a * a) - mu_a * mu_a
-    var_b = smooth(b * b) - mu_b * mu_b
-    cov = smooth(a * b) - mu_a * mu_b
-    c1, c2 = (0.01 * L) ** 2, (0.03 * L) ** 2
-    s = ((2 * mu_a * mu_b + c1) * (2 * cov + c2)) / ((mu_a ** 2 + mu_b ** 2 + c1) *
-                                                      (var_a + var_b + c2))
-    return float(s.mean())
 
 
 def sigma_workloads(sigmas, noise):
@@ -172,8 +144,7 @@ def run(k_out=10, k_in=30, workloads=None, solvers=SOLVERS, combos=COMBOS, ctx=N
         if not torch.equal(hist[-1], x):
             raise RuntimeError("iterate history does not end at the returned solution")
         rre = (torch.linalg.norm(hist.double() - xt[None, :], dim=1) / nt).tolist()
-        hh = hist.double().cpu().numpy()
-        ssims = [ssim(w.x_true, hh[k].reshape(w.m, w.m, order="F")) for k in range(kf)]
+        ssims = D.dbl_ssim(ctx, xt, [hist[k] for k in range(kf)], w.m, D.DBL_F32).tolist()
         rows.append({"m": w.m, "noise": w.noise_level, "sigma": w.extra.get("sigma"),
                      "solver": solver, "combo": label,
                      "levels": levels, "rre": rre, "ssim": ssims, "iters": rep["iters"][:levels],
