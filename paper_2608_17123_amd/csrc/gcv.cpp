@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstring>
 
+#include "dense.h"
 #include "runtime.h"
 
 namespace dbl {
@@ -102,10 +103,12 @@ int blas_check(dbl_ctx* ctx, rocblas_status st, const char* what) {
 // EXACT tier data of one request (n = m^2 <= DBL_GCV_EXACT_MAX_N), in FP64 on the device:
 //   Ad  = A^(level) applied to every unit vector (the library's own stencil
 //         kernel, FP64 tables) -- the dense level operator;
-//   K   = Ad^T Ad (rocBLAS syrk), M = K + D^T D (D = diag(w) L or L);
+//   K   = Ad^T Ad (lower triangle, the FP64 matrix-core Gram kernel),
+//         M = K + D^T D (D = diag(w) L or L);
 //   (nu, V) = generalised eigenpairs of K v = nu M v with V^T M V = I
 //         (rocSOLVER sygvd, ascending nu);
-//   f = V^T Ad^T b, g = V^T L^T c (0 without a shift), ||b||^2.
+//   f = V^T Ad^T b, g = V^T L^T c (0 without a shift), ||b||^2 (the
+//         column-dot kernel, fixed summation order).
 // Results: nu in r.in, f in r.bh, g in r.e, ||b||^2 in scal[S_G_BB].
 int exact_data(dbl_ctx* ctx, const GcvReq& r, Job& base) {
   const LevelHost& L = r.op->host.levels[r.level];
@@ -144,11 +147,8 @@ int exact_data(dbl_ctx* ctx, const GcvReq& r, Job& base) {
     if ((rc = P.upload(ctx, la))) return rc;
     if ((rc = hip_check(ctx, launch_gcv_prep(la, r.prec), "gcv prep"))) return rc;
   }
-  if ((rc = blas_check(ctx, rocblas_set_pointer_mode(h, rocblas_pointer_mode_device), "mode")))
-    return rc;
-  if ((rc = blas_check(ctx, rocblas_ddot(h, n, r.in, 1, r.in, 1, r.scal + S_G_BB), "ddot")))
-    return rc;
-  if ((rc = blas_check(ctx, rocblas_set_pointer_mode(h, rocblas_pointer_mode_host), "mode")))
+  if ((rc = hip_check(ctx, launch_gemv_t64(r.in, n, n, 1, r.in, r.scal + S_G_BB, ctx->stream),
+                      "||b||^2")))
     return rc;
   // dense operator: Ad = A I, column by column in one launch (one job per column)
   if ((rc = hip_check(ctx, launch_gcv_eye(X1, n, ctx->stream), "gcv eye"))) return rc;
@@ -168,13 +168,12 @@ int exact_data(dbl_ctx* ctx, const GcvReq& r, Job& base) {
     const int sep = L.sep ? 1 : 0, H = L.sep ? L.rb : L.R;
     if ((rc = hip_check(ctx, launch_apply_A(la, 1, sep, L.rb, H), "dense operator"))) return rc;
   }
-  const double one = 1.0, zero = 0.0;
   // A^T b into r.tmp; K = Ad^T Ad (lower triangle)
-  if ((rc = blas_check(ctx, rocblas_dgemv(h, rocblas_operation_transpose, n, n, &one, Ad, n,
-                                          r.in, 1, &zero, r.tmp, 1), "dgemv A^T b")))
+  if ((rc = hip_check(ctx, launch_gemv_t64(Ad, n, n, n, r.in, r.tmp, ctx->stream), "A^T b")))
     return rc;
-  if ((rc = blas_check(ctx, rocblas_dsyrk(h, rocblas_fill_lower, rocblas_operation_transpose, n,
-                                          n, &one, Ad, n, &zero, K, n), "dsyrk")))
+  if ((rc = hip_check(ctx, timed(ctx, "gcv_gram", 1.5 * (double)nn * 8.0,
+                                 [&] { return launch_gram64(Ad, K, n, ctx->stream); }),
+                      "A^T A")))
     return rc;
   // L^T c into r.in (shift), M = K + D^T D
   if (r.c1) {
@@ -205,12 +204,10 @@ int exact_data(dbl_ctx* ctx, const GcvReq& r, Job& base) {
     return set_err(ctx, DBL_ENUMERIC, "generalised eigensolver failed (info " +
                                           std::to_string(hinfo) + ")");
   // f = V^T (A^T b) into r.bh; g = V^T (L^T c) into r.e; nu into r.in
-  if ((rc = blas_check(ctx, rocblas_dgemv(h, rocblas_operation_transpose, n, n, &one, K, n,
-                                          r.tmp, 1, &zero, r.bh, 1), "dgemv f")))
+  if ((rc = hip_check(ctx, launch_gemv_t64(K, n, n, n, r.tmp, r.bh, ctx->stream), "f")))
     return rc;
   if (r.c1) {
-    if ((rc = blas_check(ctx, rocblas_dgemv(h, rocblas_operation_transpose, n, n, &one, K, n,
-                                            r.in, 1, &zero, r.e, 1), "dgemv g")))
+    if ((rc = hip_check(ctx, launch_gemv_t64(K, n, n, n, r.in, r.e, ctx->stream), "g")))
       return rc;
   } else if ((rc = hip_check(ctx, hipMemsetAsync(r.e, 0, (size_t)n * 8, ctx->stream), "g = 0"))) {
     return rc;

@@ -300,8 +300,9 @@ __global__ void __launch_bounds__(NTHREADS) k_gcv_complete(const Job* __restrict
 // as four 16 x 16 accumulators, four k-steps of 4 per slab.  Operand lanes:
 // A fragment a = A[row 16 rb + lane % 16][k 4 q + lane / 16], B fragment
 // b = B[k 4 q + lane / 16][column 16 cb + lane % 16]; result element v of a
-// lane is D[4 (lane / 16) + v][lane % 16] of its 16 x 16 block.  Stores are
-// guarded by the tile size (a grid below 64 is one partial tile).
+// lane is D[lane / 16 + 4 v][lane % 16] of its 16 x 16 block (the FP64
+// instruction interleaves its result rows).  Stores are guarded by the tile
+// size (a grid below 64 is one partial tile).
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 __global__ void __launch_bounds__(NTHREADS) k_gemm64_mfma(const Job* __restrict__ jobs,
@@ -359,7 +360,7 @@ __global__ void __launch_bounds__(NTHREADS) k_gemm64_mfma(const Job* __restrict_
     for (int v = 0; v < 2; ++v)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int r = wr + 16 * u + 4 * fk + e, c = wc + 16 * v + fr;
+        const int r = wr + 16 * u + fk + 4 * e, c = wc + 16 * v + fr;
         if (r < TS && c < TS) C[(i0 + r) + (size_t)(j0 + c) * m] = acc[u][v][e];
       }
 }

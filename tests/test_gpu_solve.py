@@ -464,6 +464,33 @@ def test_gcv_spectral_matches_oracle(ctx, kind, m, level):
     op.close()
 
 
+@pytest.mark.parametrize("m,levels,level", [(8, 1, 0), (16, 2, 1), (16, 1, 0), (32, 2, 1)])
+def test_gcv_spectral_small_grids_match_oracle(ctx, m, levels, level):
+    """Spectral GCV on grids of 8 and 16 pixels per side (8 is the smallest
+    grid an operator may have), where the DCT products are one partial tile
+    of the matrix-core GEMM (at 8, fewer rows than a 16 x 16 result block): a
+    motion kernel, whose symbol is not symmetric, so every coefficient must
+    land in its place; gamma and GCV(gamma) against the oracle."""
+    prec = D.DBL_F64
+    rng = np.random.default_rng(23 + m + level)
+    P = synth.motion_psf(5, 0.6)
+    X = synth.piecewise_constant_image(m, 6, rng)
+    B = ops.blur(X, P)
+    B = rnd(B + 0.01 * np.linalg.norm(B) * rng.standard_normal((m, m)) / m, prec)
+    H = Hierarchy(P, m, levels, "haar")
+    Bi = H.restrict_rhs(B)[level]
+    kern = H.interior_stencil(level)
+    data = ogcv.spectral_data(kern, Bi)
+    g_ref, f_ref, _ = ogcv.choose_gamma(data)
+    op = D.dbl_op_create(ctx, P, m, levels, "haar", prec)
+    g, f = D.dbl_gcv(ctx, op, level, dev(ops.vec(Bi), prec), mode="spectral")
+    print(f"gcv spectral motion m={m} level={level}: gpu {g:.10e} oracle {g_ref:.10e}",
+          flush=True)
+    op.close()
+    assert abs(g - g_ref) <= 1e-3 * g_ref
+    assert abs(f - f_ref) <= 1e-6 * f_ref
+
+
 @pytest.mark.parametrize("m,level", [(128, 0), (256, 1)])
 def test_gcv_spectral_motion_blur_matches_oracle(ctx, m, level):
     """Spectral GCV with a motion kernel: its cosine symbol is not symmetric in
