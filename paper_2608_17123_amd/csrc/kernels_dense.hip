@@ -5,7 +5,7 @@
 // (tiles on and below the diagonal; a diagonal tile is written whole), on the
 // FP64 matrix cores (v_mfma_f64_16x16x4f64).  One block per 128 x 128 tile:
 // each 16-row slab of the two column panels it needs (columns i0.. and j0..
-// of A) is staged in LDS, and wave w computes the 64 x 64 quadrant (rows
+// of A) is staged in LDS (the next one loaded into registers meanwhile), and wave w computes the 64 x 64 quadrant (rows
 // 64 (w % 2), columns 64 (w / 2)) as 4 x 4 accumulators of 16 x 16, four
 // k-steps of 4 per slab.  Operand lanes as for the DCT GEMM: the A fragment of
 // a lane is (row 16 u + lane % 16, k 4 q + lane / 16) of A^T, the B fragment
@@ -38,7 +38,7 @@ __device__ __forceinline__ void gram_tile_of(int t, int& ti, int& tj) {
   tj = t - i * (i + 1) / 2;
 }
 
-__global__ void __launch_bounds__(NTHREADS) k_gram64_mfma(const double* __restrict__ A,
+__global__ void __launch_bounds__(NTHREADS, 2) k_gram64_mfma(const double* __restrict__ A,
                                                           double* __restrict__ K, int n,
                                                           int ntile) {
   __shared__ double As[GR_KS][GR_LD];
@@ -58,16 +58,32 @@ __global__ void __launch_bounds__(NTHREADS) k_gram64_mfma(const double* __restri
   for (int u = 0; u < 4; ++u)
 #pragma unroll
     for (int v = 0; v < 4; ++v) acc[u][v] = dbl4{0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < n; k0 += GR_KS) {
-    // slab rows k0 .. k0 + 15 of the column panels; 16 consecutive rows of a
-    // column are contiguous, so thread idx takes row idx % 16 of column idx / 16
-    for (int idx = threadIdx.x; idx < GR_KS * GR_TS; idx += NTHREADS) {
-      const int k = idx % GR_KS, r = idx / GR_KS, gk = k0 + k;
-      const bool kin = gk < n;
-      As[k][r] = (kin && i0 + r < n) ? A[gk + (size_t)(i0 + r) * n] : 0.0;
-      if (!diag) Bs[k][r] = (kin && j0 + r < n) ? A[gk + (size_t)(j0 + r) * n] : 0.0;
+  // Slab rows k0 .. k0 + 15 of the column panels; 16 consecutive rows of a
+  // column are contiguous, so element p of a thread is row idx % 16 of
+  // column idx / 16, idx = threadIdx.x + p NTHREADS.  The next slab is loaded
+  // into registers while the MFMAs run on the current one (the barriers
+  // around the LDS exchange order LDS only, so those loads stay in flight).
+  constexpr int PER = GR_KS * GR_TS / NTHREADS;
+  double pa[PER], pb[PER];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+      const int idx = threadIdx.x + p * NTHREADS, k = idx % GR_KS, r = idx / GR_KS;
+      const int gk = k0 + k;
+      pa[p] = (gk < n && i0 + r < n) ? A[gk + (size_t)(i0 + r) * n] : 0.0;
+      if (!diag) pb[p] = (gk < n && j0 + r < n) ? A[gk + (size_t)(j0 + r) * n] : 0.0;
     }
-    __syncthreads();
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < n; k0 += GR_KS) {
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+      const int idx = threadIdx.x + p * NTHREADS, k = idx % GR_KS, r = idx / GR_KS;
+      As[k][r] = pa[p];
+      if (!diag) Bs[k][r] = pb[p];
+    }
+    lds_barrier();
+    if (k0 + GR_KS < n) fetch(k0 + GR_KS);
     const double(*Bp)[GR_LD] = diag ? As : Bs;
 #pragma unroll
     for (int s = 0; s < GR_KS / 4; ++s) {
@@ -84,7 +100,7 @@ __global__ void __launch_bounds__(NTHREADS) k_gram64_mfma(const double* __restri
         for (int v = 0; v < 4; ++v)
           acc[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], bb[v], acc[u][v], 0, 0, 0);
     }
-    __syncthreads();
+    lds_barrier();
   }
 #pragma unroll
   for (int u = 0; u < 4; ++u)
