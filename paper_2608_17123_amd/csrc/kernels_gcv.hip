@@ -103,10 +103,13 @@ __global__ void __launch_bounds__(NTHREADS) k_gcv_add_dtd(double* __restrict__ M
 
 // -------------------------------------------------------------- symbol ----
 // a[k0 + k1 m] = sum_{a,b} K[a,b] cos(pi k0 a / m) cos(pi k1 b / m).
-// Job: m, i0 = r0, i1 = r1.
+// Job: m, i0 = r0, i1 = r1.  The inner sums over a, which do not depend on
+// k1, are formed once per tile row and kernel column (T[u, b]), then combined
+// along b for every column of the tile: the same additions in the same order
+// as summing each coefficient on its own.
 __global__ void __launch_bounds__(NTHREADS) k_gcv_symbol(const Job* __restrict__ jobs,
                                                          const uint32_t* __restrict__ tiles) {
-  __shared__ double c0[64 * 33], c1[64 * 33];
+  __shared__ double c0[64 * 33], c1[64 * 33], T[64 * 33];
   const Job* job; int ti, tj, tix;
   decode_tile(jobs, tiles, job, ti, tj, tix);
   const int m = job->m;
@@ -122,14 +125,17 @@ __global__ void __launch_bounds__(NTHREADS) k_gcv_symbol(const Job* __restrict__
   for (int q = threadIdx.x; q < TJ * n1; q += NTHREADS)
     c1[q] = cos(w * (double)(j0 + (q & (TJ - 1))) * (double)((q >> (__ffs(TJ) - 1)) - r1));
   __syncthreads();
+  for (int q = threadIdx.x; q < TI * n1; q += NTHREADS) {
+    const int u = (q & (TI - 1)), b = (q >> (__ffs(TI) - 1));
+    double inner = 0.0;
+    for (int a = 0; a < n0; ++a) inner = fma(K[a + (size_t)b * n0], c0[u + a * TI], inner);
+    T[u + b * TI] = inner;
+  }
+  __syncthreads();
   for (int o = threadIdx.x; o < TI * TJ; o += NTHREADS) {
     const int u = (o & (TI - 1)), v = (o >> (__ffs(TI) - 1));
     double acc = 0.0;
-    for (int b = 0; b < n1; ++b) {
-      double inner = 0.0;
-      for (int a = 0; a < n0; ++a) inner += K[a + (size_t)b * n0] * c0[u + a * TI];
-      acc += inner * c1[v + b * TJ];
-    }
+    for (int b = 0; b < n1; ++b) acc = fma(T[u + b * TI], c1[v + b * TJ], acc);
     sym[(i0 + u) + (size_t)(j0 + v) * m] = acc;
   }
 }
@@ -326,17 +332,31 @@ __global__ void __launch_bounds__(NTHREADS) k_gemm64_mfma(const Job* __restrict_
   for (int u = 0; u < 2; ++u)
 #pragma unroll
     for (int v = 0; v < 2; ++v) acc[u][v] = dbl4{0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < m; k0 += 16) {
+  // The next 16-deep slab is loaded into registers while the MFMAs run on
+  // the current one (LDS-only barriers keep those loads in flight).
+  constexpr int PER = 16 * 64 / NTHREADS;
+  double pa[PER], pb[PER];
+  auto fetch = [&](int k0) {
     const int kk = m - k0 < 16 ? m - k0 : 16;
-    for (int idx = threadIdx.x; idx < 16 * 64; idx += NTHREADS) {
-      const int r = idx % 64, k = idx / 64;
-      As[k][r] = (r < TS && k < kk) ? A[(i0 + r) + (size_t)(k0 + k) * m] : 0.0;
-      double bv = 0.0;
-      if (r < TS && k < kk)
-        bv = tb ? B[(j0 + r) + (size_t)(k0 + k) * m] : B[(k0 + k) + (size_t)(j0 + r) * m];
-      Bs[k][r] = bv;
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+      const int idx = threadIdx.x + p * NTHREADS, r = idx % 64, k = idx / 64;
+      const bool in = r < TS && k < kk;
+      pa[p] = in ? A[(i0 + r) + (size_t)(k0 + k) * m] : 0.0;
+      pb[p] = in ? (tb ? B[(j0 + r) + (size_t)(k0 + k) * m] : B[(k0 + k) + (size_t)(j0 + r) * m])
+                 : 0.0;
     }
-    __syncthreads();
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < m; k0 += 16) {
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+      const int idx = threadIdx.x + p * NTHREADS, r = idx % 64, k = idx / 64;
+      As[k][r] = pa[p];
+      Bs[k][r] = pb[p];
+    }
+    lds_barrier();
+    if (k0 + 16 < m) fetch(k0 + 16);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int k = 4 * q + fk;
@@ -352,7 +372,7 @@ __global__ void __launch_bounds__(NTHREADS) k_gemm64_mfma(const Job* __restrict_
         for (int v = 0; v < 2; ++v)
           acc[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[v], acc[u][v], 0, 0, 0);
     }
-    __syncthreads();
+    lds_barrier();
   }
 #pragma unroll
   for (int u = 0; u < 2; ++u)
