@@ -170,16 +170,33 @@ __device__ __forceinline__ void gen_conv(const T* __restrict__ Xs, const int* __
 #pragma unroll
     for (int u = 0; u < PX; ++u) epi(u, a[u]);
   } else {
-    const T* __restrict__ vals = taps2<T>(tb);
+    // Each pixel's class list is read from global memory (global, not
+    // generic, loads); four taps' entries and values are requested before
+    // any of them is used, and summed in list order.
+    GP<const T> vals = gview(taps2<T>(tb));
+    // an entry (x, y) of 16 bits each as one word, x in the low half
+    GP<const int> te = gview(reinterpret_cast<const int*>(tb.e));
+    GP<const int> toff = gview(tb.off);
+    auto at = [&](int w, int u) { return xo[u] + (int)(short)w * G::LX + (w >> 16); };
 #pragma unroll
     for (int u = 0; u < PX; ++u) {
       const int gj = col0 + 2 * wv + 8 * u + jh;
       const int cls = class_of(row0 + i, m, tb.St0, tb.Sb0) + class_of(gj, m, tb.St1, tb.Sb1) * tb.rows0;
+      const int k1 = toff[cls + 1];
+      int k = toff[cls];
       T a = T(0);
-      for (int k = tb.off[cls]; k < tb.off[cls + 1]; ++k) {
-        const short2 e = tb.e[k];
-        a = fma(vals[k], Xs[xo[u] + e.x * G::LX + e.y], a);
+      for (; k + 4 <= k1; k += 4) {
+        int e[4];
+        T v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          e[q] = te[k + q];
+          v[q] = vals[k + q];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a = fma(v[q], Xs[at(e[q], u)], a);
       }
+      for (; k < k1; ++k) a = fma(vals[k], Xs[at(te[k], u)], a);
       epi(u, a);
     }
   }

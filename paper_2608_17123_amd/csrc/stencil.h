@@ -348,18 +348,35 @@ __device__ __forceinline__ void gen_tile(const T* __restrict__ Xs, int H, const 
       }
     }
   } else {
+    // Each pixel's class list is read from global memory (global, not
+    // generic, loads; an entry (e0, e1) of 16 bits each as one word, e0 in
+    // the low half); four taps are requested before any is used, and summed
+    // in list order.
+    GlobalPtr<const T> gv = gview(vals);
+    GlobalPtr<const int> te = gview(reinterpret_cast<const int*>(tb.e));
+    GlobalPtr<const int> toff = gview(tb.off);
     for (int o = threadIdx.x; o < TI * TJ; o += NT) {
       int i, j;
       tile_ij(o, TI, i, j);
       const int c0 = class_of(i0 + i, m, tb.St0, tb.Sb0);
       const int c1 = class_of(j0 + j, m, tb.St1, tb.Sb1);
       const int cls = c0 + c1 * tb.rows0;
-      const int b = tb.off[cls], e_ = tb.off[cls + 1];
+      const int e_ = toff[cls + 1], p0 = (j + H) * LXC + (i + H);
+      auto at = [&](int w) { return p0 + (w >> 16) * LXC + (int)(short)w; };
+      int k = toff[cls];
       T a = T(0);
-      for (int k = b; k < e_; ++k) {
-        const short2 e = tb.e[k];
-        a = fma(vals[k], Xs[(j + H + e.y) * LXC + (i + H + e.x)], a);
+      for (; k + 4 <= e_; k += 4) {
+        int e[4];
+        T v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          e[q] = te[k + q];
+          v[q] = gv[k + q];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a = fma(v[q], Xs[at(e[q])], a);
       }
+      for (; k < e_; ++k) a = fma(gv[k], Xs[at(te[k])], a);
       epi(i, j, a);
     }
   }
