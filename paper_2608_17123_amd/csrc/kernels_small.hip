@@ -160,14 +160,31 @@ __global__ void __launch_bounds__(small_nt(M, sizeof(T))) k_cgls_small(const Job
 #pragma unroll
         for (int u = 0; u < XPT; ++u) acc[u] = fma(v, X[base[u] + off], acc[u]);
       }
+      // the class lists are read with global (not generic) loads, an entry
+      // (e0, e1) of 16 bits each as one word (e0 in the low half); four taps
+      // are requested before any is used, and summed in list order
+      GlobalPtr<const T> gv = gview(vals);
+      GlobalPtr<const int> te = gview(reinterpret_cast<const int*>(tb.e));
+      GlobalPtr<const int> toff = gview(tb.off);
       for_px([&](int u, int, int i, int j) {
         const int cls = class_of(i, m, tb.St0, tb.Sb0) + class_of(j, m, tb.St1, tb.Sb1) * tb.rows0;
         if (cls != g_cls[t]) {
+          auto px = [&](int wd) { return base[u] + (int)(short)wd * ld + (wd >> 16); };
+          const int k1 = toff[cls + 1];
+          int k = toff[cls];
           T a = T(0);
-          for (int k = tb.off[cls]; k < tb.off[cls + 1]; ++k) {
-            const short2 e = tb.e[k];
-            a = fma(vals[k], X[base[u] + e.x * ld + e.y], a);
+          for (; k + 4 <= k1; k += 4) {
+            int e[4];
+            T v[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              e[q] = te[k + q];
+              v[q] = gv[k + q];
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) a = fma(v[q], X[px(e[q])], a);
           }
+          for (; k < k1; ++k) a = fma(gv[k], X[px(te[k])], a);
           acc[u] = a;
         }
         epi(i, j, acc[u]);
