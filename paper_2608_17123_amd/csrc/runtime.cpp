@@ -735,9 +735,15 @@ Job base_job(const Slot* s, int level) {
   return j;
 }
 
+// A general operator's group is keyed by the radius bucket above its radius:
+// its tile kernels take that bucket as their halo, and the generic kernels
+// lay each job out by the job's own radius (the launch's H only sizes the
+// LDS), so operators of different radii in one bucket share launches and
+// every job computes what it computes alone.
 GroupKey key_of(const Slot* s, int level) {
   const LevelHost& L = s->op->host.levels[level];
-  return GroupKey{s->prec, L.sep ? 1 : 0, L.sep ? L.rb : 0, L.sep ? L.rb : L.R};
+  const int hb = bucket_above(L.R);
+  return GroupKey{s->prec, L.sep ? 1 : 0, L.sep ? L.rb : 0, L.sep ? L.rb : (hb > 0 ? hb : L.R)};
 }
 
 // RC tolerance of the slot's current level (0: fixed outer count).
