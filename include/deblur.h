@@ -230,11 +230,13 @@ typedef enum dbl_option {
   /* Mixed-bucket CGLS launches in batched solves (dbl_deblur_batch, the
    * server).  Jobs whose operators are padded to different radius buckets
    * normally launch apart, one launch per bucket; with this option the
-   * separable levels of at least 32 x 32 on the tile kernels (DBL_OPT_TILE32)
-   * share launches in which every job keeps its own bucket, so results are
-   * identical.  Value < 0: off.  Value >= 0 (default 3072): buckets up to 8
-   * always share one launch, and bucket 12 joins it in a CGLS stage where it
-   * has fewer tiles (32 x 32 each) than the value. */
+   * levels of at least 32 x 32 on the tile kernels (DBL_OPT_TILE32) share
+   * launches in which every job keeps its own bucket, so results are
+   * identical (separable and general operators in launches of their own;
+   * a general operator's bucket is the one above its radius).  Value < 0:
+   * off.  Value >= 0 (default 3072): buckets up to 8 always share one
+   * launch, and bucket 12 joins it in a CGLS stage where it has fewer tiles
+   * (32 x 32 each) than the value. */
   DBL_OPT_MULTI_BUCKET = 4
 } dbl_option;
 /* Set a context option.  Returns DBL_EINVAL for an unknown option or value.

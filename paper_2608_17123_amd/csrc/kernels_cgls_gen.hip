@@ -62,4 +62,79 @@ hipError_t launch_cgls_p2_gen(const LaunchArgs& la, int precision, int rb) {
 #undef DBL_GEN_DISPATCH
 #undef DBL_GEN_CASE
 
+// Launches that mix radius buckets (batched solves): each block runs the body
+// of its own job's bucket, the bucket above the operator's radius (read once
+// per block, so the branch is the same for all its threads), which is the
+// halo the job's own one-bucket launch takes: every job computes what it
+// computes alone, bit for bit.  Buckets up to RBMAX in {4, 8, 12}; the LDS of
+// a launch is that of RBMAX.
+namespace {
+
+template <int PH, typename T, typename S, int RB>
+__device__ __forceinline__ void gen_phase(const Job* __restrict__ jobs,
+                                          const uint32_t* __restrict__ tiles) {
+  if constexpr (PH == 1) p1_sep_body<T, S, RB, true>(jobs, tiles);
+  else p2_sep_body<T, S, RB, true>(jobs, tiles);
+}
+
+template <int PH, typename T, typename S, int RBMAX>
+__device__ __forceinline__ void gen_multi_body(const Job* __restrict__ jobs,
+                                               const uint32_t* __restrict__ tiles) {
+  static_assert(RBMAX == 4 || RBMAX == 8 || RBMAX == 12, "mixed launches cover buckets 2 .. 12");
+  const Job* job = jobs + (tiles[blockIdx.x] >> 16);
+  const int R = __builtin_amdgcn_readfirstlane(gview(job->op)->R);
+  if (R <= 2) {
+    gen_phase<PH, T, S, 2>(jobs, tiles);
+  } else if (RBMAX == 4 || R <= 4) {
+    gen_phase<PH, T, S, 4>(jobs, tiles);
+  } else if constexpr (RBMAX >= 8) {
+    if (RBMAX == 8 || R <= 8) gen_phase<PH, T, S, 8>(jobs, tiles);
+    else if constexpr (RBMAX == 12) gen_phase<PH, T, S, 12>(jobs, tiles);
+  }
+}
+
+}  // namespace
+
+template <typename T, typename S, int RBMAX, int MINW>
+__global__ void __launch_bounds__(NTHREADS, MINW)
+    k_cgls_p1_gmulti(const Job* __restrict__ jobs, const uint32_t* __restrict__ tiles) {
+  gen_multi_body<1, T, S, RBMAX>(jobs, tiles);
+}
+template <typename T, typename S, int RBMAX, int MINW>
+__global__ void __launch_bounds__(NTHREADS, MINW)
+    k_cgls_p2_gmulti(const Job* __restrict__ jobs, const uint32_t* __restrict__ tiles) {
+  gen_multi_body<2, T, S, RBMAX>(jobs, tiles);
+}
+
+bool cgls_gen_multi_bucket(int rbmax) { return rbmax == 4 || rbmax == 8 || rbmax == 12; }
+
+#define DBL_GMULTI_CASE(KERNEL, T, S, R)                                                  \
+  case R:                                                                                 \
+    hipLaunchKernelGGL((KERNEL<T, S, R, waves_per_simd<T, R>()>), dim3(la.ntiles),         \
+                       dim3(NTHREADS), lds, la.stream, la.jobs, la.tiles);                \
+    break;
+#define DBL_GMULTI_DISPATCH(KERNEL, T, S)                                                 \
+  switch (rbmax) {                                                                        \
+    DBL_GMULTI_CASE(KERNEL, T, S, 4)                                                      \
+    DBL_GMULTI_CASE(KERNEL, T, S, 8)                                                      \
+    DBL_GMULTI_CASE(KERNEL, T, S, 12)                                                     \
+    default: return hipErrorInvalidValue;                                                 \
+  }
+
+hipError_t launch_cgls_gen_multi(const LaunchArgs& la, int phase, int precision, int rbmax) {
+  const size_t lds = cgls_gen_lds(phase, precision, rbmax);
+  if (phase == 1) {
+    if (precision == 1) { DBL_GMULTI_DISPATCH(k_cgls_p1_gmulti, double, double) }
+    else if (precision == 2) { DBL_GMULTI_DISPATCH(k_cgls_p1_gmulti, float, bf16s) }
+    else { DBL_GMULTI_DISPATCH(k_cgls_p1_gmulti, float, float) }
+  } else {
+    if (precision == 1) { DBL_GMULTI_DISPATCH(k_cgls_p2_gmulti, double, double) }
+    else if (precision == 2) { DBL_GMULTI_DISPATCH(k_cgls_p2_gmulti, float, bf16s) }
+    else { DBL_GMULTI_DISPATCH(k_cgls_p2_gmulti, float, float) }
+  }
+  return hipGetLastError();
+}
+#undef DBL_GMULTI_DISPATCH
+#undef DBL_GMULTI_CASE
+
 }  // namespace dbl

@@ -767,7 +767,9 @@ int solver_flags(const Slot* s) {
 // mixed launches (kernels_cgls_multi.hip) in which every job keeps its own
 // bucket: buckets up to 8 always (their kernels run at one occupancy), and
 // bucket 12 too when it has fewer than ctx->multi_tiles tiles, too few to
-// keep the chip busy in a launch of its own.
+// keep the chip busy in a launch of its own.  General levels on the tile
+// kernels mix their buckets (the bucket above each operator's radius) by
+// the same rule, in launches of their own.
 struct GroupPlan {
   struct Entry {
     GroupKey key;       // the launch group (rb = the bucket the tables are padded to)
@@ -782,6 +784,14 @@ struct GroupPlan {
 
 constexpr int MERGE_TILES = 256;
 
+// One CGLS phase launch of a group (general operators in mixed-bucket
+// groups take their own kernels).
+hipError_t cgls_phase(const LaunchArgs& la, int phase, const GroupKey& g) {
+  if (g.multi && !g.sep) return launch_cgls_gen_multi(la, phase, g.prec, g.H);
+  return phase == 1 ? launch_cgls_p1(la, g.prec, g.sep, g.rb, g.H)
+                    : launch_cgls_p2(la, g.prec, g.sep, g.rb, g.H);
+}
+
 GroupPlan plan_groups(dbl_ctx* ctx, const std::vector<Slot*>& slots, bool allow_small = true,
                       bool multi = false) {
   GroupPlan P;
@@ -789,7 +799,8 @@ GroupPlan plan_groups(dbl_ctx* ctx, const std::vector<Slot*>& slots, bool allow_
   // member still fits in LDS with it
   std::map<std::tuple<int, int, int>, std::vector<const Slot*>> small;  // (prec, m, sep)
   std::map<GroupKey, std::vector<const Slot*>> tiled;
-  std::map<int, std::vector<const Slot*>> mixed;  // mixed-launch candidates by precision
+  // mixed-launch candidates by (precision, separable)
+  std::map<std::pair<int, int>, std::vector<const Slot*>> mixed;
   multi = multi && ctx->multi_tiles >= 0 && ctx->tile32;
   for (const Slot* s : slots) {
     const int lv = s->level;
@@ -799,14 +810,21 @@ GroupPlan plan_groups(dbl_ctx* ctx, const std::vector<Slot*>& slots, bool allow_
       en.small_lds = small_lds_bytes(ctx, s->op, lv, s->solver == DBL_IRLS, &en.wlds);
     P.e[s] = en;
     if (en.small_lds) small[{s->prec, L.m, L.sep ? 1 : 0}].push_back(s);
-    else if (multi && L.sep && L.m >= 32 && L.rb <= 12) mixed[s->prec].push_back(s);
+    else if (multi && L.sep && L.m >= 32 && L.rb <= 12) mixed[{s->prec, 1}].push_back(s);
+    else if (multi && !L.sep && L.m >= 32 && bucket_above(L.R) > 0 && bucket_above(L.R) <= 12)
+      mixed[{s->prec, 0}].push_back(s);
     else tiled[en.key].push_back(s);
   }
   for (auto& kv : mixed) {
+    const bool sepg = kv.first.second != 0;
+    auto bucket = [&](const Slot* s) {
+      const LevelHost& L = s->op->host.levels[s->level];
+      return sepg ? L.rb : bucket_above(L.R);
+    };
     std::map<int, size_t> per;  // tiles by bucket
     for (const Slot* s : kv.second) {
       const int mi = s->m >> s->level, t = mi / 32;
-      per[s->op->host.levels[s->level].rb] += (size_t)t * t;
+      per[bucket(s)] += (size_t)t * t;
     }
     // the buckets that share the launch
     auto joins = [&](int rb) { return rb <= 8 || per[rb] < (size_t)ctx->multi_tiles; };
@@ -817,16 +835,20 @@ GroupPlan plan_groups(dbl_ctx* ctx, const std::vector<Slot*>& slots, bool allow_
         ++nb;
       }
     for (const Slot* s : kv.second) {
-      const int rb = s->op->host.levels[s->level].rb;
+      const int rb = bucket(s);
       GroupPlan::Entry& en = P.e[s];
-      if (nb < 2 || !joins(rb) || !cgls_multi_bucket(top)) {
+      if (nb < 2 || !joins(rb) || !(sepg ? cgls_multi_bucket(top) : cgls_gen_multi_bucket(top))) {
         tiled[en.key].push_back(s);  // a launch of its own bucket
         continue;
       }
-      en.key.rb = en.key.H = top;
       en.key.t32 = 1;
       en.key.multi = 1;
-      en.tab_rb = rb;
+      if (sepg) {
+        en.key.rb = en.key.H = top;
+        en.tab_rb = rb;
+      } else {
+        en.key.H = top;  // general tables are not padded: rb stays 0
+      }
     }
   }
   for (auto& kv : small) {
@@ -1339,7 +1361,7 @@ int engine_step(dbl_ctx* ctx, std::vector<Slot*>& slots) {
       LaunchArgs la = kv.second;
       if (!g.multi) tune_cgls_launch(ctx, 2, g.prec, g.sep, g.rb, la);
       if ((rc = hip_check(ctx, timed(ctx, "cgls_p2", b, [&] {
-                            return launch_cgls_p2(la, g.prec, g.sep, g.rb, g.H);
+                            return cgls_phase(la, 2, g);
                           }),
                           "cgls p2")))
         return rc;
@@ -1362,7 +1384,7 @@ int engine_step(dbl_ctx* ctx, std::vector<Slot*>& slots) {
         for (int jq = 0; jq < q; ++jq)
           b += job_bytes("cgls_p1", p1[par][g].jobs[jq], g.prec);
         if ((rc = hip_check(ctx, timed(ctx, "cgls_p1", b, [&] {
-                              return launch_cgls_p1(la, g.prec, g.sep, g.rb, g.H);
+                              return cgls_phase(la, 1, g);
                             }),
                             "cgls p1")))
           return rc;
@@ -1380,7 +1402,7 @@ int engine_step(dbl_ctx* ctx, std::vector<Slot*>& slots) {
         for (int jq = 0; jq < q; ++jq)
           b += job_bytes("cgls_p2", p2[par][g].jobs[jq], g.prec);
         if ((rc = hip_check(ctx, timed(ctx, "cgls_p2", b, [&] {
-                              return launch_cgls_p2(la, g.prec, g.sep, g.rb, g.H);
+                              return cgls_phase(la, 2, g);
                             }),
                             "cgls p2")))
           return rc;

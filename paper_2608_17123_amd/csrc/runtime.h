@@ -119,6 +119,11 @@ void pool_trim(dbl_ctx* ctx, size_t keep_bytes);
 int stage(dbl_ctx* ctx, const void* src, size_t bytes, void** dptr);
 int stage_checkpoint(dbl_ctx* ctx);
 
+// CGLS phase launches of general operators that mix radius buckets up to
+// rbmax in {4, 8, 12} (kernels_cgls_gen.hip).
+hipError_t launch_cgls_gen_multi(const LaunchArgs& la, int phase, int precision, int rbmax);
+bool cgls_gen_multi_bucket(int rbmax);
+
 // Per-kernel timing: when profiling is on, `launch` runs between two events on
 // the context stream and the launch is charged `bytes` algorithmic bytes.
 template <class F>

@@ -200,6 +200,19 @@ void check_gen32(const std::string& k, int jb, const Job& j, int rb, size_t esz,
   if (shmem < e) fail(k, jb, "dynamic LDS " + std::to_string(shmem) + " < " + std::to_string(e));
 }
 
+// A general tile kernel of a launch that mixes buckets up to rbmax: the job
+// runs the body of the bucket above its operator's radius, which must be at
+// most rbmax, and is audited as a launch of that bucket (the launch's LDS,
+// sized for rbmax, covers it).
+void check_gmulti(const std::string& k, int jb, const Job& j, int rbmax, size_t esz, int phase,
+                  size_t shmem) {
+  if (!j.op || !owner(j.op, sizeof(dbl::LevelOp))) return;
+  const int R = j.op->R, rb = R <= 2 ? 2 : R <= 4 ? 4 : R <= 8 ? 8 : R <= 12 ? 12 : 16;
+  if (rb > rbmax) fail(k, jb, "job bucket " + std::to_string(rb) + " above the launch's " +
+                                  std::to_string(rbmax));
+  check_gen32(k, jb, j, rb, esz, phase, shmem);
+}
+
 // The one-block CGLS: a separable operator with tables padded to the kernel's
 // halo RB, or (gen) a general operator of radius <= RB whose interior class
 // lists fit the staging area; the dynamic LDS covers the kernel's layout.
@@ -327,13 +340,14 @@ void audit(const void* func, dim3 grid, dim3 block, void** args, size_t shmem) {
         if (irls) need(fam, jb, "V_W", v(dbl::V_W), nl * T);
       }
     } else if (fam == "k_cgls_p1" || fam == "k_cgls_p1_wide" || fam == "k_cgls_p1_sep" ||
-               fam == "k_cgls_p1_multi" || fam == "k_cgls_p1_gen") {
+               fam == "k_cgls_p1_multi" || fam == "k_cgls_p1_gen" || fam == "k_cgls_p1_gmulti") {
       const size_t T = tsize(ta[0]), S = tsize(ta[1]);
       grid_is(m);
       check_op(fam, jb, j, T == 8);
       if (fam == "k_cgls_p1_sep") check_sep32(fam, jb, j, std::atoi(ta[2].c_str()), T, 1, shmem);
       if (fam == "k_cgls_p1_multi") check_multi(fam, jb, j, std::atoi(ta[2].c_str()), T, 1, shmem);
       if (fam == "k_cgls_p1_gen") check_gen32(fam, jb, j, std::atoi(ta[2].c_str()), T, 1, shmem);
+      if (fam == "k_cgls_p1_gmulti") check_gmulti(fam, jb, j, std::atoi(ta[2].c_str()), T, 1, shmem);
       need(fam, jb, "V_S", v(dbl::V_S), n * S);
       need(fam, jb, "V_PA", v(dbl::V_PA), n * S);
       need(fam, jb, "V_PB", v(dbl::V_PB), n * S);
@@ -347,13 +361,14 @@ void audit(const void* func, dim3 grid, dim3 block, void** args, size_t shmem) {
         need(fam, jb, "pr[1]", j.pr[1], (size_t)ntile * 2 * 8);
       }
     } else if (fam == "k_cgls_p2" || fam == "k_cgls_p2_wide" || fam == "k_cgls_p2_sep" ||
-               fam == "k_cgls_p2_multi" || fam == "k_cgls_p2_gen") {
+               fam == "k_cgls_p2_multi" || fam == "k_cgls_p2_gen" || fam == "k_cgls_p2_gmulti") {
       const size_t T = tsize(ta[0]), S = tsize(ta[1]);
       grid_is(m);
       check_op(fam, jb, j, T == 8);
       if (fam == "k_cgls_p2_sep") check_sep32(fam, jb, j, std::atoi(ta[2].c_str()), T, 2, shmem);
       if (fam == "k_cgls_p2_multi") check_multi(fam, jb, j, std::atoi(ta[2].c_str()), T, 2, shmem);
       if (fam == "k_cgls_p2_gen") check_gen32(fam, jb, j, std::atoi(ta[2].c_str()), T, 2, shmem);
+      if (fam == "k_cgls_p2_gmulti") check_gmulti(fam, jb, j, std::atoi(ta[2].c_str()), T, 2, shmem);
       need(fam, jb, "V_R1A", v(dbl::V_R1A), n * S);
       need(fam, jb, "V_R1B", v(dbl::V_R1B), n * S);
       need(fam, jb, "V_R2A", v(dbl::V_R2A), nl * S);

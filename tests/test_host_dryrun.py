@@ -167,3 +167,22 @@ def test_mixed_bucket_launches_are_sound(dryrun, multi, prec):
     assert "launches k_cgls_p1_multi" in r.stdout and "launches k_cgls_p2_multi" in r.stdout
     if multi == "0":  # bucket 12 launches apart when the threshold admits none of it
         assert "launches k_cgls_p2_sep" in r.stdout
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_mixed_bucket_general_launches_are_sound(dryrun, prec):
+    """A batch of motion PSFs whose operators fall in radius buckets 4, 8 and
+    12 at the finest level: the general CGLS phases share mixed-bucket
+    launches, and every job in them passes the general tile kernel's audit
+    for the bucket above its own radius."""
+    exe, out = dryrun
+    kinds = [("m7", synth.motion_psf(7, 0.3)), ("m15", synth.motion_psf(15, 1.1)),
+             ("m21", synth.motion_psf(21, 2.0))]
+    psf = ",".join(psf_file(out, k, P) for k, P in kinds)
+    env = dict(os.environ, DRYRUN_MULTI_TILES="4096")
+    r = subprocess.run([exe, psf, "256", "3", "2", "1", "0", str(PREC[prec]), "2", "4", "0",
+                        "6"], capture_output=True, text=True, timeout=300, env=env)
+    print(r.stdout[-3000:])
+    assert r.returncode == 0, r.stdout[-2000:]
+    assert "violations 0" in r.stdout
+    assert "launches k_cgls_p1_gmulti" in r.stdout and "launches k_cgls_p2_gmulti" in r.stdout
