@@ -260,6 +260,11 @@ void dbl_opts_default(dbl_opts* opts);
 int dbl_profile(dbl_ctx* ctx, int enable);
 int dbl_profile_read(dbl_ctx* ctx, int index, char* name, size_t name_cap, int64_t* launches,
                      double* ms, double* bytes);
+/* Restrict the bracketing of dbl_profile to the launches of one kernel
+ * family (`name` as dbl_profile_read reports it; NULL or "" = every
+ * family), so that one family can be timed inside a run without events
+ * around the others.  Takes effect for work issued afterwards. */
+int dbl_profile_only(dbl_ctx* ctx, const char* name);
 
 /* -------------------------------------------------------------- operators */
 

@@ -44,7 +44,7 @@ EXPORTS = [
     "dbl_opts_default", "dbl_profile", "dbl_profile_read", "dbl_op_create", "dbl_op_destroy", "dbl_apply_A", "dbl_apply_L",
     "dbl_dwt", "dbl_apply_A_batch", "dbl_apply_L_batch", "dbl_dwt_batch", "dbl_dtransfer", "dbl_cgls", "dbl_cgls_noalloc", "dbl_lsqr", "dbl_gcv", "dbl_deblur", "dbl_deblur_batch",
     "dbl_request_bytes", "dbl_server_create", "dbl_server_destroy", "dbl_server_submit",
-    "dbl_server_step", "dbl_server_poll", "dbl_autotune", "dbl_tune_choice", "dbl_ssim",
+    "dbl_server_step", "dbl_server_poll", "dbl_autotune", "dbl_tune_choice", "dbl_ssim", "dbl_profile_only",
 ]
 
 
@@ -131,6 +131,7 @@ def lib():
         "dbl_apply_L_batch": (i, [vp, i, i, i, i, ctypes.POINTER(vp), ctypes.POINTER(vp)]),
         "dbl_dwt_batch": (i, [vp, i, i, i, i, i, i, ctypes.POINTER(vp), ctypes.POINTER(vp)]),
         "dbl_dtransfer": (i, [vp, i, i, i, vp, vp]),
+        "dbl_profile_only": (i, [vp, ctypes.c_char_p]),
         "dbl_ssim": (i, [vp, i, i, i, vp, ctypes.POINTER(vp), ctypes.c_double, i,
                          ctypes.c_double, vp]),
         "dbl_cgls": (i, [vp, vp, i, ctypes.POINTER(dbl_sub), vp, vp, i, vp, dp]),
@@ -294,6 +295,11 @@ def dbl_workspace_bytes(ctx):
 
 def dbl_profile(ctx, enable):
     _check(ctx, lib().dbl_profile(ctx.handle, int(enable)))
+
+
+def dbl_profile_only(ctx, name=None):
+    """Time only the kernel family `name` while profiling (None: all)."""
+    _check(ctx, lib().dbl_profile_only(ctx.handle, name.encode() if name else None))
 
 
 def dbl_profile_read(ctx):

@@ -220,6 +220,13 @@ int dbl_profile(dbl_ctx* ctx, int enable) {
   return DBL_OK;
 }
 
+int dbl_profile_only(dbl_ctx* ctx, const char* name) {
+  if (!ctx) return DBL_EINVAL;
+  if (name && std::strlen(name) >= 64) return set_err(ctx, DBL_EINVAL, "family name too long");
+  ctx->prof_only = name ? name : "";
+  return DBL_OK;
+}
+
 int dbl_profile_read(dbl_ctx* ctx, int index, char* name, size_t name_cap, int64_t* launches,
                      double* ms, double* bytes) {
   if (!ctx || !name || name_cap == 0 || !launches || !ms || !bytes) return DBL_EINVAL;

@@ -41,6 +41,7 @@ struct dbl_ctx {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   // optional per-kernel timing (dbl_profile): event pairs around launches
   bool prof_on = false;
+  std::string prof_only;  // non-empty: time only this kernel family (dbl_profile_only)
   struct ProfPending { int id; hipEvent_t a, b; double bytes; };
   std::vector<ProfPending> prof_pending;
   std::vector<hipEvent_t> prof_pool;
@@ -134,7 +135,7 @@ int prof_id(dbl_ctx* ctx, const char* name);
 
 template <class F>
 hipError_t timed(dbl_ctx* ctx, const char* name, double bytes, F&& launch) {
-  if (!ctx->prof_on) return launch();
+  if (!ctx->prof_on || (!ctx->prof_only.empty() && ctx->prof_only != name)) return launch();
   dbl_ctx::ProfPending p;
   p.id = prof_id(ctx, name);
   p.a = prof_event(ctx);
