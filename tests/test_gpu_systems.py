@@ -70,6 +70,35 @@ def test_batch_equals_plain_bitwise(ctx):
         assert ra["objective"] == rb["objective"]
 
 
+def test_profile_only_times_one_family(ctx):
+    """dbl_profile_only: with a family named, only its launches are timed
+    (the same count as with every family timed); results are unchanged."""
+    items, kw = mixed_requests(count=3)
+
+    def batch():
+        xs = [torch.zeros_like(b) for _, b in items]
+        reqs = [D.make_request(b, x, w.psf, w.m, w.solver, w.wavelet, w.levels, w.transfer,
+                               D.dbl_opts_default(**kw)) for (w, b), x in zip(items, xs)]
+        D.dbl_deblur_batch(ctx, reqs)
+        return [host(x) for x in xs]
+
+    D.dbl_profile(ctx, 1)
+    x_all = batch()
+    every = D.dbl_profile_read(ctx)
+    D.dbl_profile(ctx, 1)
+    D.dbl_profile_only(ctx, "cgls_p2")
+    x_one = batch()
+    one = D.dbl_profile_read(ctx)
+    D.dbl_profile(ctx, 0)
+    D.dbl_profile_only(ctx, None)
+    assert len(every) > 3 and "cgls_p2" in every
+    assert set(one) == {"cgls_p2"} and one["cgls_p2"][0] == every["cgls_p2"][0]
+    assert one["cgls_p2"][2] == every["cgls_p2"][2]  # the same algorithmic bytes
+    assert all(np.array_equal(a, b) for a, b in zip(x_all, x_one))
+    with pytest.raises(D.DeblurError):
+        D.dbl_profile_only(ctx, "x" * 80)
+
+
 def test_deterministic_across_runs(ctx):
     items, kw = mixed_requests(count=4)
     outs = []
