@@ -279,25 +279,43 @@ int gcv_run(dbl_ctx* ctx, std::vector<GcvReq>& reqs) {
     }
     return DBL_OK;
   };
-  // DCT(X) = C X C^T as two GEMMs: tmp = C in, out = tmp C^T.
+  // DCT(X) = C X C^T as two GEMMs: tmp = C in, out = tmp C^T.  The grids of
+  // at least 128 take the 128 x 128 tile kernel when their tiles fill the
+  // chip at least once (256 blocks; the kernel runs two waves per SIMD), else
+  // every grid the 64 x 64 one (both give the same result bit for bit).
   auto dct2 = [&](const std::vector<size_t>& sel, int out_slot) -> int {
-    Launch g1, g2;
+    Launch g1, g2, h1, h2;
+    size_t t128 = 0;
+    for (size_t q : sel)
+      if (base[q].m >= 128) t128 += (size_t)(base[q].m / 128) * (base[q].m / 128);
+    const bool use128 = t128 >= 256;
     for (size_t q : sel) {
       Job a = base[q];
       a.v[0] = base[q].v[G_DCT];
       a.v[1] = base[q].v[G_IN];
       a.v[2] = base[q].v[G_TMP];
       a.i0 = 0;
-      g1.add(a, a.m, 0);
       Job b = base[q];
       b.v[0] = base[q].v[G_TMP];
       b.v[1] = base[q].v[G_DCT];
       b.v[2] = base[q].v[out_slot];
       b.i0 = 1;
-      g2.add(b, b.m, 0);
+      if (use128 && a.m >= 128) {
+        h1.add_grid(a, a.m / 128, a.m / 128);
+        h2.add_grid(b, b.m / 128, b.m / 128);
+      } else {
+        g1.add(a, a.m, 0);
+        g2.add(b, b.m, 0);
+      }
     }
+    auto big = [](int tb) {
+      return tb ? +[](const LaunchArgs& la) { return launch_gemm128(la, 1); }
+                : +[](const LaunchArgs& la) { return launch_gemm128(la, 0); };
+    };
     int r2 = run(launch_gemm64, g1, "gcv_dct_gemm");
+    if (!r2) r2 = run(big(0), h1, "gcv_dct_gemm");
     if (!r2) r2 = run(launch_gemm64, g2, "gcv_dct_gemm");
+    if (!r2) r2 = run(big(1), h2, "gcv_dct_gemm");
     return r2;
   };
   // 1. DCT of the data b (once per level)

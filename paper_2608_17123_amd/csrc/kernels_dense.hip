@@ -125,6 +125,103 @@ __global__ void __launch_bounds__(NTHREADS) k_gemv_t64(const double* __restrict_
   if (threadIdx.x == 0) out[blockIdx.x] = t[0];
 }
 
+// k_gemm128_mfma: the DCT products of the spectral GCV tier on grids of at
+// least 128 (m a multiple of 128): out = A B (i0 = 0) or A B^T (i0 = 1), m x m
+// FP64 column-major, v[0] = A, v[1] = B, v[2] = out (the launch's jobs all
+// take the same form, which is a template parameter); one block per 128 x 128
+// output tile of a job (job and tile tables as for every batched launch).
+// The tile work is the Gram kernel's (slabs of 16 in LDS, the next one
+// prefetched, 4 x 4 accumulators per wave); every output element takes its
+// k terms in the same order as in the 64 x 64 kernel (slabs of 16, four
+// steps of 4), so both give the same result bit for bit.
+template <bool TB>
+__global__ void __launch_bounds__(NTHREADS, 2) k_gemm128_mfma(const Job* __restrict__ jobs,
+                                                             const uint32_t* __restrict__ tiles) {
+  __shared__ double As[GR_KS][GR_LD];
+  __shared__ double Bs[GR_KS][GR_LD];
+  const Job* job; int ti, tj, tix;
+  decode_tile(jobs, tiles, job, ti, tj, tix);
+  const int m = job->m;
+  const int i0 = ti * GR_TS, j0 = tj * GR_TS;
+  const double* __restrict__ A = static_cast<const double*>(job->v[0]);
+  const double* __restrict__ B = static_cast<const double*>(job->v[1]);
+  double* __restrict__ C = static_cast<double*>(job->v[2]);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int wr = 64 * (wid & 1), wc = 64 * (wid >> 1);
+  const int fr = lane & 15, fk = lane >> 4;
+  dbl4 acc[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[u][v] = dbl4{0.0, 0.0, 0.0, 0.0};
+  // element p of a thread: A (and B^T) rows are contiguous along the tile
+  // (row idx % 128 of slab row idx / 128); B columns along k (k idx % 16 of
+  // column idx / 16)
+  constexpr int PER = GR_KS * GR_TS / NTHREADS;
+  double pa[PER], pb[PER];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+      const int idx = threadIdx.x + p * NTHREADS;
+      const int r = idx % GR_TS, k = idx / GR_TS;
+      pa[p] = A[(i0 + r) + (size_t)(k0 + k) * m];
+      if constexpr (TB) {
+        pb[p] = B[(j0 + r) + (size_t)(k0 + k) * m];
+      } else {
+        const int kb = idx % GR_KS, rb = idx / GR_KS;
+        pb[p] = B[(k0 + kb) + (size_t)(j0 + rb) * m];
+      }
+    }
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < m; k0 += GR_KS) {
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+      const int idx = threadIdx.x + p * NTHREADS;
+      As[idx / GR_TS][idx % GR_TS] = pa[p];
+      if constexpr (TB) Bs[idx / GR_TS][idx % GR_TS] = pb[p];
+      else Bs[idx % GR_KS][idx / GR_KS] = pb[p];
+    }
+    lds_barrier();
+    if (k0 + GR_KS < m) fetch(k0 + GR_KS);
+#pragma unroll
+    for (int s = 0; s < GR_KS / 4; ++s) {
+      const int k = 4 * s + fk;
+      double a[4], bb[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        a[u] = As[k][wr + 16 * u + fr];
+        bb[u] = Bs[k][wc + 16 * u + fr];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          acc[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], bb[v], acc[u][v], 0, 0, 0);
+    }
+    lds_barrier();
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = i0 + wr + 16 * u + fk + 4 * e, c = j0 + wc + 16 * v + fr;
+        C[r + (size_t)c * m] = acc[u][v][e];
+      }
+}
+
+hipError_t launch_gemm128(const LaunchArgs& la, int transpose_b) {
+  if (transpose_b)
+    hipLaunchKernelGGL(k_gemm128_mfma<true>, dim3(la.ntiles), dim3(NTHREADS), 0, la.stream,
+                       la.jobs, la.tiles);
+  else
+    hipLaunchKernelGGL(k_gemm128_mfma<false>, dim3(la.ntiles), dim3(NTHREADS), 0, la.stream,
+                       la.jobs, la.tiles);
+  return hipGetLastError();
+}
+
 int gram_tiles(int n) {
   const int t = (n + GR_TS - 1) / GR_TS;
   return t * (t + 1) / 2;
