@@ -736,6 +736,7 @@ __global__ void __launch_bounds__(NTHREADS) k_gcv_grid(const Job* __restrict__ j
 
 // One block per job: grid GCV values from the partials (pr[0], i1 tiles,
 // i0 points), lowest-index minimum, Brent's bracket and start state.
+constexpr int GF_GROUP = 8;  // grid points summed per pass over the partials
 __global__ void __launch_bounds__(NTHREADS) k_gcv_gridfin(const Job* __restrict__ jobs,
                                                           const uint32_t* __restrict__ tiles) {
   const Job* job = jobs + (tiles[blockIdx.x] >> 16);
@@ -743,16 +744,29 @@ __global__ void __launch_bounds__(NTHREADS) k_gcv_gridfin(const Job* __restrict_
   double* sc = job->scal;
   const double tlo = sc[S_G_TLO], thi = sc[S_G_THI];
   __shared__ double vals[DBL_GCV_GRID_MAX_DEV];
-  if (threadIdx.x < npts) {
-    const int p = threadIdx.x;
-    double a = 0.0, b = 0.0;
-    for (int t = 0; t < nt; ++t) {
-      a += job->pr[0][(size_t)t * 2 * npts + 2 * p];
-      b += job->pr[0][(size_t)t * 2 * npts + 2 * p + 1];
+  __shared__ double red[2 * GF_GROUP * (NTHREADS / 64)];
+  // eight points at a time: thread t adds tiles t, t + NTHREADS, ... (their
+  // 16 values are contiguous), then a fixed-order block sum
+  const double* __restrict__ part = job->pr[0];
+  for (int p0 = 0; p0 < npts; p0 += GF_GROUP) {
+    const int np = npts - p0 < GF_GROUP ? npts - p0 : GF_GROUP;
+    double v[2 * GF_GROUP];
+#pragma unroll
+    for (int q = 0; q < 2 * GF_GROUP; ++q) v[q] = 0.0;
+    for (int t = threadIdx.x; t < nt; t += NTHREADS) {
+      const double* row = part + (size_t)t * 2 * npts + 2 * p0;
+#pragma unroll
+      for (int q = 0; q < 2 * GF_GROUP; ++q)
+        if (q < 2 * np) v[q] += row[q];
     }
-    const double t = tlo + (thi - tlo) * p / (npts - 1);
-    vals[p] = gcv_from(job, pow(10.0, t), a, b, n);
-    sc[S_GRID + p] = vals[p];
+    block_sum<2 * GF_GROUP>(v, red);
+    if (threadIdx.x == 0)
+      for (int g = 0; g < np; ++g) {
+        const int p = p0 + g;
+        const double t = tlo + (thi - tlo) * p / (npts - 1);
+        vals[p] = gcv_from(job, pow(10.0, t), v[2 * g], v[2 * g + 1], n);
+        sc[S_GRID + p] = vals[p];
+      }
   }
   __syncthreads();
   if (threadIdx.x != 0) return;
