@@ -467,6 +467,16 @@ void audit(const void* func, dim3 grid, dim3 block, void** args, size_t shmem) {
       grid_is(m);
       need(fam, jb, "v[0]", v(0), (fam == "k_grad" ? n : nl) * T);
       need(fam, jb, "v[1]", v(1), (fam == "k_grad" ? nl : n) * T);
+    } else if (fam == "k_gemm128_mfma") {
+      // the spectral tier's DCT products: one block per 128 x 128 tile of an
+      // m x m FP64 product, m a multiple of 128; A, B and out whole
+      if (m % 128 != 0 || (size_t)j.nti * 128 != m || (size_t)j.ntj * 128 != m)
+        fail(fam, jb, "128 x 128 tile grid " + std::to_string(j.nti) + "x" +
+                          std::to_string(j.ntj) + " does not cover a " + std::to_string(m) +
+                          " grid");
+      for (int s = 0; s < 3; ++s)
+        need(fam, jb, ("v[" + std::to_string(s) + "]").c_str(), v(s), n * 8);
+      if ((ta[0] == "true") != (j.i0 != 0)) fail(fam, jb, "kernel form differs from the job's");
     } else if (fam == "k_cgls_hist") {
       need(fam, jb, "pr[0]", j.pr[0], (size_t)j.i1 * 2 * 8);
       need(fam, jb, "scal", j.scal, dbl::NSCAL * 8);

@@ -129,6 +129,18 @@ def test_spectral_gcv_plan_tables_are_sound(dryrun, solver, prec):
     assert "violations 0" in r.stdout and "launches k_gcv_symbol" in r.stdout
 
 
+def test_spectral_gcv_large_dct_products_are_sound(dryrun):
+    """Sixteen 512 x 512 solves with spectral GCV: on the finest grid the DCT
+    products have 256 tiles of 128 x 128 and take the 128 x 128 tile GEMM,
+    whose launches are audited (tile grid, the three matrices, the kernel's
+    form against each job's)."""
+    psf = psf_file(dryrun[1], "g4", synth.gaussian_psf(1.2, 4))
+    r = run(dryrun, psf, 512, 2, "mm", "haar", "X", "f32", k_out=1, k_in=2, copies=16, gcv=2)
+    assert r.returncode == 0, r.stdout[-2000:]
+    assert "violations 0" in r.stdout
+    assert "launches k_gemm128_mfma" in r.stdout and "launches k_gemm64_mfma" in r.stdout
+
+
 def test_autotune_launches_are_sound(dryrun):
     """The autotuner's synthetic CGLS jobs (every variant of both phases, the
     quick sweep) pass the same audit, before a small solve."""
