@@ -464,6 +464,32 @@ def test_gcv_spectral_matches_oracle(ctx, kind, m, level):
     op.close()
 
 
+@pytest.mark.parametrize("kind", ["motion"])
+def test_gcv_spectral_2048_matches_oracle(ctx, kind):
+    """Spectral GCV on a 2048 x 2048 level: its DCT products have 256 tiles of
+    128 x 128, which take the 128 x 128 tile GEMM; gamma and GCV(gamma) against
+    the oracle (the motion kernel's symbol is not symmetric, so every
+    coefficient must land in place).  The oracle side takes about half a
+    minute."""
+    prec = D.DBL_F64
+    m = 2048
+    rng = np.random.default_rng(29)
+    P = synth.gaussian_psf(3.0, 9) if kind == "gauss" else synth.motion_psf(15, 0.6)
+    X = synth.piecewise_constant_image(m, 64, rng)
+    B = ops.blur(X, P)
+    B = rnd(B + 0.01 * np.linalg.norm(B) * rng.standard_normal((m, m)) / m, prec)
+    H = Hierarchy(P, m, 1, "haar")
+    data = ogcv.spectral_data(H.interior_stencil(0), B)
+    g_ref, f_ref, _ = ogcv.choose_gamma(data)
+    op = D.dbl_op_create(ctx, P, m, 1, "haar", prec)
+    print(f"gcv spectral m=2048 {kind}", flush=True)
+    g, f = D.dbl_gcv(ctx, op, 0, dev(ops.vec(B), prec), mode="spectral")
+    print(f"  gpu {g:.10e} oracle {g_ref:.10e}", flush=True)
+    op.close()
+    assert abs(g - g_ref) <= 1e-3 * g_ref
+    assert abs(f - f_ref) <= 1e-6 * f_ref
+
+
 @pytest.mark.parametrize("m,levels,level", [(8, 1, 0), (16, 2, 1), (16, 1, 0), (32, 2, 1)])
 def test_gcv_spectral_small_grids_match_oracle(ctx, m, levels, level):
     """Spectral GCV on grids of 8 and 16 pixels per side (8 is the smallest
