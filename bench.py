@@ -27,8 +27,8 @@ Printed: one JSON line with
   Cache), batched in one launch each, against the same peak;
 * serving: Poisson arrivals at several rates of requests with m from
   {128, ..., 2048} (weights 4:4:3:2:1) and Gaussian or motion blur into the
-  continuous-batching server, against the plain path fed the same trace:
-  p50 / p99 latency and solves/s;
+  continuous-batching server (on a context of its own), against the plain
+  path fed the same trace: p50 / p99 latency and solves/s;
 * cpu_baseline: the FP64 oracle on a bounded sample of the workload (the
   first 16 solves with m <= 128, full 10 x 30 solves with spectral GCV, data
   built by the oracle's own blur) in a pool of single-threaded workers, and
@@ -528,6 +528,10 @@ def main():
 
     serving = None
     if not args.no_serve:
+        # the server runs on a context of its own, as a service would: none of
+        # the timed batch's operators, workspaces or tuning table carry over
+        ctx.close()
+        ctx = D.dbl_create(0)
         rates = [float(r) for r in args.serve_rates.split(",") if r]
         serving = {"arrivals": "Poisson; m from {128,256,512,1024,2048} (4:4:3:2:1), Gaussian "
                                "or motion blur, random solver/wavelet/transfer, 10x30, "
